@@ -1,0 +1,364 @@
+"""Python face of the FP64 oracle (test infrastructure only).
+
+Wraps liboracle.so (projection, tile binning, per-pixel blending, analytic
+backward, local finite differences) and adds the two steps that are plain
+enough to state in numpy: the L1 term of the photometric loss, eq. (2), and
+the Adam update the paper takes from the default 3DGS optimisation setup
+(Sec. IV-A).
+
+Readings of the paper used here (the paper defers the rasteriser to 3DGS,
+Sec. III-B): see the header of oracle.cpp; every threshold is a field of
+`Options` below, shared with the HIP path by value.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "liboracle.so")
+_lib = None
+
+REC_FIELDS = ("mx", "my", "depth", "ca", "cb", "cc", "opacity", "r", "g", "b")
+GRAD2D_FIELDS = ("mx", "my", "ca", "cb", "cc", "opacity", "r", "g", "b")
+
+# Per-(view, Gaussian) flag bits (same meaning as in oracle.cpp).
+F_CLAMP_RGB = 0x7
+F_GUARD_X, F_GUARD_Y = 1 << 3, 1 << 4
+F_CULL_NEAR, F_CULL_DET, F_CULL_RECT, F_CULL_QUAT = 1 << 8, 1 << 9, 1 << 10, 1 << 11
+F_NEAR_RADIUS, F_NEAR_RECT, F_NEAR_PLANE = 1 << 16, 1 << 17, 1 << 18
+# Per-pixel flag bits.
+P_NEAR_ALPHA_MIN, P_NEAR_T_MIN, P_NEAR_ALPHA_MAX = 1, 2, 4
+
+
+class OrCamera(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class OrOptions(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("reserved", C.c_int32), ("near_plane", C.c_double), ("eps2d", C.c_double),
+                ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
+                ("radius_sigmas", C.c_double), ("guard", C.c_double), ("bg", C.c_double * 3)]
+
+
+@dataclasses.dataclass
+class Options:
+    """Readings of the constants the paper leaves to the 3DGS rasteriser."""
+    tile: int = 16
+    near_plane: float = 0.2
+    eps2d: float = 0.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_min: float = 1e-4
+    radius_sigmas: float = 3.0
+    guard: float = 1.3
+    bg: Sequence[float] = (0.0, 0.0, 0.0)
+
+    def as_c(self) -> OrOptions:
+        # Thresholds are used at their FP32 values so both sides compare against one number.
+        f = lambda x: float(np.float32(x))  # noqa: E731
+        o = OrOptions()
+        o.tile = int(self.tile)
+        o.near_plane, o.eps2d = f(self.near_plane), f(self.eps2d)
+        o.alpha_min, o.alpha_max, o.t_min = f(self.alpha_min), f(self.alpha_max), f(self.t_min)
+        o.radius_sigmas, o.guard = f(self.radius_sigmas), f(self.guard)
+        for i in range(3):
+            o.bg[i] = f(self.bg[i])
+        return o
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing; build it with oracle/build.py")
+        _lib = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        i64, i32 = C.c_int64, C.c_int32
+        _lib.or_project.argtypes = [i64, i32, P, P, P, P, P, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P]
+        _lib.or_bin.argtypes = [i32, i64, P, P, P, P, i32, i64, P, P, P, P]
+        _lib.or_render.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P, P, P]
+        _lib.or_render_backward.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, i64, P, P]
+        _lib.or_project_backward.argtypes = [i64, i32, P, P, P, P, P, C.POINTER(OrCamera), i32,
+                                             C.POINTER(OrOptions), P, P, P, P, P, P]
+        _lib.or_fd_local.argtypes = [i64, i32, P, P, P, P, P, C.POINTER(OrCamera), i32, C.POINTER(OrOptions), P, i64,
+                                     P, P, C.c_double, P, P]
+        _lib.or_sh_basis.argtypes = [i32, i64, P, P, P]
+        _lib.or_quat_to_rot.argtypes = [P, P]
+        for f in ("or_project", "or_bin", "or_render", "or_render_backward", "or_project_backward", "or_fd_local"):
+            getattr(_lib, f).restype = C.c_int
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def cameras_c(cams) -> C.Array:
+    arr = (OrCamera * len(cams))()
+    for k, c in enumerate(cams):
+        R = np.asarray(c.R, np.float64).reshape(9)
+        t = np.asarray(c.t, np.float64).reshape(3)
+        for i in range(9):
+            arr[k].R[i] = float(np.float32(R[i]))
+        for i in range(3):
+            arr[k].t[i] = float(np.float32(t[i]))
+        arr[k].fx, arr[k].fy = float(np.float32(c.fx)), float(np.float32(c.fy))
+        arr[k].cx, arr[k].cy = float(np.float32(c.cx)), float(np.float32(c.cy))
+        arr[k].width, arr[k].height = int(c.width), int(c.height)
+    return arr
+
+
+def tile_grid(cam, tile):
+    return (cam.width + tile - 1) // tile, (cam.height + tile - 1) // tile
+
+
+def total_tiles(cams, tile):
+    return sum(np.prod(tile_grid(c, tile)) for c in cams)
+
+
+# ---------------------------------------------------------------------------
+# Parameters as FP64 arrays.
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Params:
+    means: np.ndarray
+    log_scales: np.ndarray
+    quats: np.ndarray
+    opacity_logits: np.ndarray
+    sh: np.ndarray  # [N,K,3]
+    sh_degree: int
+
+    @property
+    def n(self):
+        return self.means.shape[0]
+
+    @staticmethod
+    def from_scene(scene) -> "Params":
+        return Params(_d(scene.means), _d(scene.log_scales), _d(scene.quats), _d(scene.opacity_logits),
+                      _d(scene.sh_full()), int(scene.sh_degree))
+
+    def copy(self) -> "Params":
+        return Params(self.means.copy(), self.log_scales.copy(), self.quats.copy(), self.opacity_logits.copy(),
+                      self.sh.copy(), self.sh_degree)
+
+
+def project(params: Params, cam, opts: Options):
+    """FP64 projection into one view (see or_project)."""
+    n = params.n
+    rec = np.zeros((n, 10))
+    radius = np.zeros(n, np.int32)
+    rect = np.zeros((n, 4), np.int32)
+    flags = np.zeros(n, np.uint32)
+    cov = np.zeros((n, 3))
+    cc = cameras_c([cam])
+    oc = opts.as_c()
+    rc = lib().or_project(n, params.sh_degree, _p(params.means), _p(params.log_scales), _p(params.quats),
+                          _p(params.opacity_logits), _p(params.sh), cc, C.byref(oc), _p(rec), _p(radius), _p(rect),
+                          _p(flags), _p(cov))
+    assert rc == 0
+    return dict(rec=rec, radius=radius, rect=rect, flags=flags, cov=cov)
+
+
+def project_views(params: Params, cams, opts: Options):
+    outs = [project(params, c, opts) for c in cams]
+    return {k: np.concatenate([o[k] for o in outs]) for k in outs[0]}
+
+
+def bin_sort(mean2d_f32, radius, depth_f32, cams, tile, with_keys=True):
+    """Tile binning + stable key sort on FP32 records (see or_bin)."""
+    n_views = len(cams)
+    vn = radius.shape[0]
+    n = vn // n_views
+    mean2d = np.ascontiguousarray(mean2d_f32, np.float32).reshape(vn, 2)
+    depth = np.ascontiguousarray(depth_f32, np.float32).reshape(vn)
+    radius = np.ascontiguousarray(radius, np.int32).reshape(vn)
+    wh = np.array([[c.width, c.height] for c in cams], np.int32)
+    T = int(total_tiles(cams, tile))
+    npairs = C.c_int64(0)
+    # First call sizes the output.
+    dummy = np.zeros(1, np.uint32)
+    rng = np.zeros(2 * T, np.uint32)
+    lib().or_bin(n_views, n, _p(mean2d), _p(radius), _p(depth), _p(wh), tile, 0, None, _p(dummy), _p(rng),
+                 C.byref(npairs))
+    M = npairs.value
+    keys = np.zeros(max(M, 1), np.uint64)
+    ids = np.zeros(max(M, 1), np.uint32)
+    ranges = np.zeros(2 * T, np.uint32)
+    rc = lib().or_bin(n_views, n, _p(mean2d), _p(radius), _p(depth), _p(wh), tile, M,
+                      _p(keys) if with_keys else None, _p(ids), _p(ranges), C.byref(npairs))
+    assert rc == 0
+    return keys[:M], ids[:M], ranges.reshape(T, 2)
+
+
+def render(cams, opts: Options, rec, ids, ranges):
+    """Per-pixel front-to-back blending (see or_render).  rec: [V*N,10] FP64."""
+    n_views = len(cams)
+    rec = _d(rec)
+    n = rec.shape[0] // n_views
+    P = sum(c.width * c.height for c in cams)
+    image = np.zeros(3 * P)
+    tf = np.zeros(P)
+    nc = np.zeros(P, np.int32)
+    pf = np.zeros(P, np.uint32)
+    ids = np.ascontiguousarray(ids, np.uint32)
+    ranges = np.ascontiguousarray(ranges, np.uint32)
+    oc = opts.as_c()
+    rc = lib().or_render(n_views, n, cameras_c(cams), C.byref(oc), _p(rec), _p(ids), _p(ranges), _p(image), _p(tf),
+                         _p(nc), _p(pf))
+    assert rc == 0
+    return dict(image=image, t_final=tf, n_contrib=nc, pix_flags=pf)
+
+
+def split_views(flat, cams, channels=3):
+    """Split a packed per-view buffer into a list of [channels,H,W] (or [H,W]) arrays."""
+    out, off = [], 0
+    for c in cams:
+        k = channels * c.width * c.height
+        a = flat[off:off + k]
+        out.append(a.reshape(channels, c.height, c.width) if channels > 1 else a.reshape(c.height, c.width))
+        off += k
+    return out
+
+
+def pack_views(arrs) -> np.ndarray:
+    return np.concatenate([np.asarray(a, np.float64).reshape(-1) for a in arrs])
+
+
+def l1_loss(image_flat, targets, cams):
+    """L1 term of eq. (2): sum over views of the per-view mean |I_r - I_gt|.
+
+    Returns (loss, dL/dimage) with the gradient sign(I_r - I_gt)/(3 H W), sign(0) = 0.
+    """
+    tgt = pack_views(targets)
+    d = image_flat - tgt
+    w = np.concatenate([np.full(3 * c.width * c.height, 1.0 / (3.0 * c.width * c.height)) for c in cams])
+    return float(np.sum(w * np.abs(d))), w * np.sign(d)
+
+
+def l1_loss_per_view(image_flat, targets, cams):
+    tgt = pack_views(targets)
+    out, off = [], 0
+    for c in cams:
+        k = 3 * c.width * c.height
+        out.append(float(np.sum(np.abs(image_flat[off:off + k] - tgt[off:off + k])) / k))
+        off += k
+    return out
+
+
+def render_backward(cams, opts: Options, rec, ids, ranges, dl_dimage):
+    n_views = len(cams)
+    rec = _d(rec)
+    n = rec.shape[0] // n_views
+    g2 = np.zeros((n_views * n, 9))
+    ids = np.ascontiguousarray(ids, np.uint32)
+    ranges = np.ascontiguousarray(ranges, np.uint32)
+    dl = _d(dl_dimage)
+    oc = opts.as_c()
+    rc = lib().or_render_backward(n_views, n, cameras_c(cams), C.byref(oc), _p(rec), _p(ids), _p(ranges),
+                                  int(ids.shape[0]), _p(dl), _p(g2))
+    assert rc == 0
+    return g2
+
+
+def project_backward(params: Params, cams, opts: Options, grad2d):
+    n = params.n
+    K = (params.sh_degree + 1) ** 2
+    g = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
+             opacity_logits=np.zeros(n), sh=np.zeros((n, K, 3)))
+    g2 = _d(grad2d)
+    oc = opts.as_c()
+    rc = lib().or_project_backward(n, params.sh_degree, _p(params.means), _p(params.log_scales), _p(params.quats),
+                                   _p(params.opacity_logits), _p(params.sh), cameras_c(cams), len(cams), C.byref(oc),
+                                   _p(g2), _p(g["means"]), _p(g["log_scales"]), _p(g["quats"]),
+                                   _p(g["opacity_logits"]), _p(g["sh"]))
+    assert rc == 0
+    return g
+
+
+def forward(params: Params, cams, opts: Options):
+    """Independent FP64 pipeline: project, bin on the FP32-rounded records, blend."""
+    pr = project_views(params, cams, opts)
+    rec = pr["rec"]
+    keys, ids, ranges = bin_sort(rec[:, 0:2].astype(np.float32), pr["radius"], rec[:, 2].astype(np.float32), cams,
+                                 opts.tile)
+    out = render(cams, opts, rec, ids, ranges)
+    out.update(proj=pr, keys=keys, ids=ids, ranges=ranges)
+    return out
+
+
+def forward_backward_l1(params: Params, cams, targets, opts: Options):
+    """Independent FP64 forward, L1 loss and gradient of every raw parameter."""
+    f = forward(params, cams, opts)
+    loss, dl = l1_loss(f["image"], targets, cams)
+    g2 = render_backward(cams, opts, f["proj"]["rec"], f["ids"], f["ranges"], dl)
+    grads = project_backward(params, cams, opts, g2)
+    f.update(loss=loss, dl_dimage=dl, grad2d=g2, grads=grads)
+    return f
+
+
+PARAM_SLICES = ("means", 0, 3), ("log_scales", 3, 6), ("quats", 6, 10), ("opacity_logits", 10, 11)
+
+
+def param_index_name(p: int):
+    for name, a, b in PARAM_SLICES:
+        if a <= p < b:
+            return name, p - a
+    return "sh", p - 11
+
+
+def fd_local(params: Params, cams, targets, opts: Options, gauss_idx, param_idx, h_rel=1e-6):
+    """Central finite differences of the L1 loss (see or_fd_local)."""
+    g = np.ascontiguousarray(gauss_idx, np.int64)
+    p = np.ascontiguousarray(param_idx, np.int32)
+    out = np.zeros(g.shape[0])
+    st = np.zeros(g.shape[0], np.int32)
+    tgt = pack_views(targets)
+    oc = opts.as_c()
+    rc = lib().or_fd_local(params.n, params.sh_degree, _p(params.means), _p(params.log_scales), _p(params.quats),
+                           _p(params.opacity_logits), _p(params.sh), cameras_c(cams), len(cams), C.byref(oc),
+                           _p(tgt), g.shape[0], _p(g), _p(p), h_rel, _p(out), _p(st))
+    assert rc == 0
+    return out, st
+
+
+def sh_basis(degree, dirs, with_grad=False):
+    dirs = _d(dirs).reshape(-1, 3)
+    n = dirs.shape[0]
+    K = (degree + 1) ** 2
+    Y = np.zeros((n, K))
+    G = np.zeros((n, K, 3)) if with_grad else None
+    lib().or_sh_basis(degree, n, _p(dirs), _p(Y), _p(G) if with_grad else None)
+    return (Y, G) if with_grad else Y
+
+
+def quat_to_rot(q_unit):
+    q = _d(q_unit).reshape(4)
+    R = np.zeros(9)
+    lib().or_quat_to_rot(_p(q), _p(R))
+    return R.reshape(3, 3)
+
+
+# ---------------------------------------------------------------------------
+# Adam (Kingma & Ba), with eps added to the bias-corrected root of the second
+# moment; the 3DGS defaults adopted in Sec. IV-A: beta = (0.9, 0.999),
+# eps = 1e-15, no weight decay, every element stepped.
+# ---------------------------------------------------------------------------
+def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One step in FP64; returns new (p, m, v).  `step` is the 1-based step count."""
+    p, g, m, v = (np.asarray(x, np.float64) for x in (p, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    p = p - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return p, m, v
