@@ -1,0 +1,286 @@
+/*
+ * gs.h -- C ABI of the tile-based differentiable 3D Gaussian splatting
+ * rasteriser and its optimiser step: the data-parallel hot path of the
+ * dense-reconstruction (mapping) module of MGSO (Sec. III-B).
+ *
+ * The mapping module renders RGB images of a set of anisotropic Gaussians,
+ * each with an opacity, a rotation, a location, a scale and a colour, using
+ * tile-based differentiable rasterisation (Sec. III-B), i.e. projecting the
+ * Gaussians onto the camera plane, depth-sorting them and blending them front
+ * to back (Sec. II), and optimises the Gaussian parameters by gradient descent
+ * on a photometric loss against the captured keyframe images (eq. (2)) with
+ * the default 3DGS optimiser configuration (Sec. IV-A).  Several keyframes of
+ * the SLAM window (eight by default, Sec. III-A) can be rendered in one call.
+ *
+ * Conventions shared by every call
+ *  - Every pointer inside the structs below is a DEVICE pointer unless
+ *    stated otherwise.  The caller allocates and owns all device memory,
+ *    workspaces included; the library never allocates, frees or retains it.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Hot-path calls
+ *    only enqueue kernels on it and return; none synchronises, so they may be
+ *    captured into a HIP graph.  No call issues hipMemset: buffers that must
+ *    start at zero are cleared by the library's own fill kernels.
+ *  - Arguments are validated before anything is enqueued; on failure the
+ *    call returns GS_ERR_INVALID_VALUE (or GS_ERR_UNSUPPORTED) and leaves the
+ *    stream untouched.  A failed kernel launch returns GS_ERR_HIP.  The
+ *    detail of the last failure on the calling thread is in gs_last_error().
+ *  - Views: up to GS_MAX_VIEWS cameras per call, passed as a HOST array.
+ *    View v owns the global tiles [tile_off(v), tile_off(v) + TX_v*TY_v) with
+ *    TX_v = ceil(W_v/B), TY_v = ceil(H_v/B), tile_off(v) = sum_{u<v} TX_u*TY_u,
+ *    local tile (tx,ty) -> tile_off(v) + ty*TX_v + tx, and the pixels
+ *    [pix_off(v), pix_off(v) + H_v*W_v), pix_off(v) = sum_{u<v} H_u*W_u.
+ *  - (view, Gaussian) pairs are indexed v*N + i.
+ */
+#ifndef GS_H_
+#define GS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_ABI_VERSION 1
+#define GS_MAX_VIEWS 32
+#define GS_MAX_SH_DEGREE 3
+/* floats per projected record, see gs_projected */
+#define GS_REC_FLOATS 12
+/* floats per image-space gradient row, see gs_render_bwd */
+#define GS_GRAD2D_FLOATS 9
+#define GS_MAX_ADAM_GROUPS 8
+
+typedef enum gs_status {
+  GS_OK = 0,
+  GS_ERR_INVALID_VALUE = 1, /* bad pointer, size or option; nothing enqueued */
+  GS_ERR_UNSUPPORTED = 2,   /* valid but not implemented (e.g. tile size 12) */
+  GS_ERR_CAPACITY = 3,      /* a caller buffer is too small (host-detectable) */
+  GS_ERR_HIP = 4            /* a HIP runtime call failed */
+} gs_status;
+
+const char* gs_status_string(gs_status s);
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* gs_last_error(void);
+int32_t gs_abi_version(void);
+
+/* Pinhole keyframe camera (Sec. III-A keyframe poses).  R (row-major) and t
+ * map world to camera coordinates, p_c = R p_w + t, with x right, y down and
+ * z forward.  Pixel (i, j) is sampled at the point (i, j) of index
+ * coordinates, so a camera-frame point projects to
+ * (fx x/z + cx - 1/2, fy y/z + cy - 1/2). */
+typedef struct gs_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} gs_camera;
+
+/* Gaussian set G of Sec. III-B in optimiser (raw) space, FP32, one row per
+ * Gaussian:
+ *   means          [n,3]     location
+ *   log_scales     [n,3]     scale = exp(log_scales)
+ *   quats          [n,4]     rotation, (w,x,y,z), normalised on use; an all-zero
+ *                            quaternion culls the Gaussian
+ *   opacity_logits [n]       opacity = sigmoid(logit)
+ *   sh_dc          [n,3]     colour, constant spherical-harmonic coefficient
+ *   sh_rest        [n,K-1,3] higher SH bands, K = (sh_degree+1)^2 (NULL when
+ *                            sh_degree == 0)
+ * Colour = max(0, sum_k sh_k Y_k(d) + 1/2) per channel, d the unit direction
+ * from the camera centre to the mean; sh_degree 0 is the plain-RGB colour the
+ * paper adopts (Sec. III-B). */
+typedef struct gs_params {
+  int64_t n;
+  int32_t sh_degree; /* 0..3 */
+  int32_t reserved;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* sh_dc;
+  const float* sh_rest;
+} gs_params;
+
+/* Constants of the rasteriser.  The paper defers them to the original 3DGS
+ * rasteriser (Sec. III-B); gs_default_options() fills the conventional
+ * values noted on the right. */
+typedef struct gs_options {
+  int32_t tile_size;     /* B: 8, 16 or 32 (16) */
+  int32_t checkpoint;    /* 1: forward does not store t_final/n_contrib;
+                            backward recomputes them (0) */
+  float near_plane;      /* cull when camera depth <= near_plane (0.2) */
+  float eps2d;           /* added to the 2D covariance diagonal, px^2 (0.3) */
+  float alpha_min;       /* blend only alpha >= alpha_min (1/255) */
+  float alpha_max;       /* alpha = min(alpha_max, o*G) (0.99) */
+  float t_min;           /* a Gaussian that would take T below t_min ends
+                            the pixel and is not blended (1e-4) */
+  float radius_sigmas;   /* radius = ceil(radius_sigmas*sqrt(lambda_max)) (3) */
+  float frustum_guard;   /* Jacobian uses x/z clamped to +-guard*(W/2)/fx (1.3) */
+  float bg[3];           /* background colour (0,0,0) */
+  uint32_t flags;        /* reserved, must be 0 */
+} gs_options;
+
+void gs_default_options(gs_options* opts);
+
+/* Projected (view, Gaussian) records, FP32, [n_views*n][GS_REC_FLOATS]:
+ *   0 mean_x  1 mean_y  2 conic_a  3 conic_b  4 conic_c  5 opacity
+ *   6 r  7 g  8 b  9 depth  10 radius (int32 bits)  11 flags (uint32 bits)
+ * conic (a,b,c) is the inverse of the dilated 2D covariance [[a,b],[b,c]];
+ * radius 0 marks a culled pair (behind the near plane, degenerate, or no tile
+ * touched).  flags bits 0-2: colour channel clamped at 0; bits 3-4: frustum
+ * guard active in x / y.  tiles_touched [n_views*n] = tile count of the
+ * pair's rect (0 when culled). */
+typedef struct gs_projected {
+  float* rec;
+  int32_t* tiles_touched;
+} gs_projected;
+
+/* Tile bins.  keys [capacity] (may be NULL: not written), ids [capacity],
+ * ranges [total_tiles][2].  After gs_bin_sort the first M entries of ids
+ * hold v*N+i of every (pair, tile) incidence ordered by (global tile,
+ * FP32 bit pattern of the depth, v*N+i); keys[p] = (tile << 32) | depth bits;
+ * ranges[t] = [first, last+1) of tile t, (0,0) for an empty tile.
+ * d_num_pairs (device int64) receives M; d_overflow (device int32) receives
+ * 1 when M > capacity, in which case keys/ids/ranges are undefined and the
+ * caller must grow the buffers and call again (0 otherwise). */
+typedef struct gs_bins {
+  uint64_t* keys;
+  uint32_t* ids;
+  uint32_t* ranges;
+  int64_t capacity;
+  int64_t* d_num_pairs;
+  int32_t* d_overflow;
+} gs_bins;
+
+/* Rendered views.  rgb [sum_v 3*H_v*W_v]: view v at 3*pix_off(v), planar
+ * [3][H_v][W_v]; t_final (final transmittance) and n_contrib (1 + list
+ * position of the last blended Gaussian, 0 if none) [sum_v H_v*W_v]; both
+ * may be NULL when options.checkpoint is set. */
+typedef struct gs_image {
+  float* rgb;
+  float* t_final;
+  int32_t* n_contrib;
+} gs_image;
+
+typedef enum gs_loss_kind {
+  GS_LOSS_NONE = 0,
+  GS_LOSS_L1 = 1,       /* L1 term of eq. (2) against `target` */
+  GS_LOSS_EXTERNAL = 2  /* the caller supplies dL/dimage in `dl_dimage` */
+} gs_loss_kind;
+
+/* Photometric loss.  L1: L = sum_v mean_{c,y,x} |I_r - I_gt| (the L1 term of
+ * eq. (2) summed over the rendered views), dL/dI_r = sign(I_r - I_gt) /
+ * (3 H_v W_v) with sign(0) = 0.  target and dl_dimage use the rgb layout of
+ * gs_image.  loss_out (device, [n_views], may be NULL): gs_render_fwd writes
+ * each view's L1 term there. */
+typedef struct gs_loss {
+  int32_t kind;
+  int32_t reserved;
+  const float* target;
+  const float* dl_dimage;
+  float* loss_out;
+} gs_loss;
+
+/* Gradients of the raw parameters, same shapes as gs_params; gs_render_bwd
+ * ADDS into them (the caller clears them once per iteration), so per-view
+ * calls and one batched call both sum over views. */
+typedef struct gs_grads {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh_dc;
+  float* sh_rest;
+} gs_grads;
+
+/* ---------------------------------------------------------------- queries */
+/* Total tiles / pixels of a set of views at a tile size (host only). */
+gs_status gs_total_tiles(const gs_camera* cams, int32_t n_views, int32_t tile_size, int64_t* out);
+gs_status gs_total_pixels(const gs_camera* cams, int32_t n_views, int64_t* out);
+/* Workspace bytes of gs_bin_sort for n Gaussians, these views and a pair
+ * capacity. */
+gs_status gs_bin_sort_workspace_size(int64_t n, const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                                     int64_t pair_capacity, size_t* bytes);
+/* Workspace bytes of gs_render_fwd (per-tile loss partials) and
+ * gs_render_bwd (the [n_views*n][9] image-space gradient buffer). */
+gs_status gs_render_fwd_workspace_size(const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                                       size_t* bytes);
+gs_status gs_render_bwd_workspace_size(int64_t n, int32_t n_views, size_t* bytes);
+
+/* --------------------------------------------------------------- hot path */
+
+/* Projection (Sec. II "projecting Gaussians onto the camera plane"; Gaussian
+ * parameterisation of Sec. III-B).  For every Gaussian i and view v: camera
+ * point t = R mean + t; cull if t_z <= near_plane; image mean; 2D covariance
+ * J W Sigma W^T J^T + eps2d I with Sigma = R(q) S S^T R(q)^T (local affine
+ * approximation of the perspective map, frustum guard on x/z and y/z);
+ * conic; radius; tile rect; colour; opacity; writes out->rec and
+ * out->tiles_touched for all n_views*n pairs.  Parameters are read once for
+ * all views. */
+gs_status gs_project(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                     const gs_projected* out, void* stream);
+
+/* Tile binning and depth sort (Sec. II "depth-sorting"; tile-based
+ * rasterisation of Sec. III-B).  Every pair with tiles_touched > 0 is
+ * assigned to each tile of its rect [floor((m-r)/B), floor((m+r+B-1)/B))
+ * (computed in FP32, clamped to the view's grid); the (tile, id) incidences
+ * are ordered as documented at gs_bins (a stable LSD radix sort on the
+ * 64-bit key, ties broken by ascending v*N+i).  `workspace` must hold
+ * gs_bin_sort_workspace_size() bytes for the same arguments. */
+gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n_views,
+                      const gs_options* opts, const gs_bins* bins, void* workspace, size_t workspace_bytes,
+                      void* stream);
+
+/* Forward rasterisation (Sec. II "blending them front-to-back").  For every
+ * pixel, over its tile's list in order: power = -(a dx^2 + c dy^2)/2 - b dx dy
+ * with d = pixel - mean (skip if power > 0), alpha = min(alpha_max,
+ * opacity exp(power)) (skip if alpha < alpha_min); stop before a Gaussian
+ * that would take T below t_min; C += colour alpha T; T *= 1 - alpha.
+ * Output C + T bg.  With loss->kind == GS_LOSS_L1 and loss->loss_out set,
+ * also writes the per-view L1 term.  `workspace` must hold
+ * gs_render_fwd_workspace_size() bytes (may be NULL when no loss value is
+ * requested).  Reads the pair count from bins->d_num_pairs. */
+gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
+                        int32_t n_views, const gs_options* opts, const gs_loss* loss, const gs_image* out,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Backward of the rasteriser and the projection (the differentiable part of
+ * Sec. III-B): dL/dimage from `loss` (L1 of eq. (2), or external), then for
+ * every pixel a back-to-front replay of its blended Gaussians giving
+ * d/d(mean2d, conic, opacity, colour), summed per (view, Gaussian) into the
+ * image-space gradient buffer held in `workspace` ([n_views*n][9] floats,
+ * order mean_x, mean_y, conic a, b, c, opacity, r, g, b; readable by the
+ * caller after the call), then chained through the projection to the raw
+ * parameters and added into `grads`.  With options.checkpoint set, t_final
+ * and n_contrib are recomputed by a forward replay instead of read from
+ * `img`.  `workspace` must hold gs_render_bwd_workspace_size() bytes. */
+gs_status gs_render_bwd(const gs_params* params, const gs_projected* proj, const gs_bins* bins,
+                        const gs_image* img, const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                        const gs_loss* loss, const gs_grads* grads, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/* One Adam step over up to GS_MAX_ADAM_GROUPS parameter groups in a single
+ * launch (gradient descent of Sec. III-B with the default 3DGS optimiser of
+ * Sec. IV-A): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), every element
+ * (no visibility mask), t = *d_step + 1.  d_step (device int32) is then
+ * incremented, so graph replays need no host scalars.  With zero_grad != 0
+ * the gradient is cleared after use.  Every pointer of a group is a device
+ * pointer to numel FP32 values. */
+typedef struct gs_adam_group {
+  float* param;
+  float* grad;
+  float* exp_avg;
+  float* exp_avg_sq;
+  int64_t numel;
+  float lr;
+  int32_t reserved;
+} gs_adam_group;
+
+gs_status gs_adam_step(const gs_adam_group* groups /* host array */, int32_t n_groups, float beta1, float beta2,
+                       float eps, int32_t* d_step, int32_t zero_grad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H_ */

@@ -1,0 +1,210 @@
+"""ctypes binding of libgs.so (include/gs.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and raises
+GsError when that call returns a status other than GS_OK.  Importing this
+module fails loudly when the HIP library has not been built: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgs.so")
+
+GS_OK, GS_ERR_INVALID_VALUE, GS_ERR_UNSUPPORTED, GS_ERR_CAPACITY, GS_ERR_HIP = range(5)
+GS_LOSS_NONE, GS_LOSS_L1, GS_LOSS_EXTERNAL = 0, 1, 2
+GS_MAX_VIEWS = 32
+GS_REC_FLOATS = 12
+GS_GRAD2D_FLOATS = 9
+GS_MAX_ADAM_GROUPS = 8
+
+P = C.c_void_p
+
+
+class GsError(RuntimeError):
+    def __init__(self, fn, status, detail):
+        super().__init__(f"{fn} failed: {status} ({detail})")
+        self.status = status
+
+
+class gs_camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class gs_params(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("reserved", C.c_int32), ("means", P),
+                ("log_scales", P), ("quats", P), ("opacity_logits", P), ("sh_dc", P), ("sh_rest", P)]
+
+
+class gs_options(C.Structure):
+    _fields_ = [("tile_size", C.c_int32), ("checkpoint", C.c_int32), ("near_plane", C.c_float),
+                ("eps2d", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
+                ("radius_sigmas", C.c_float), ("frustum_guard", C.c_float), ("bg", C.c_float * 3),
+                ("flags", C.c_uint32)]
+
+
+class gs_projected(C.Structure):
+    _fields_ = [("rec", P), ("tiles_touched", P)]
+
+
+class gs_bins(C.Structure):
+    _fields_ = [("keys", P), ("ids", P), ("ranges", P), ("capacity", C.c_int64), ("d_num_pairs", P),
+                ("d_overflow", P)]
+
+
+class gs_image(C.Structure):
+    _fields_ = [("rgb", P), ("t_final", P), ("n_contrib", P)]
+
+
+class gs_loss(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("target", P), ("dl_dimage", P), ("loss_out", P)]
+
+
+class gs_grads(C.Structure):
+    _fields_ = [("means", P), ("log_scales", P), ("quats", P), ("opacity_logits", P), ("sh_dc", P),
+                ("sh_rest", P)]
+
+
+class gs_adam_group(C.Structure):
+    _fields_ = [("param", P), ("grad", P), ("exp_avg", P), ("exp_avg_sq", P), ("numel", C.c_int64),
+                ("lr", C.c_float), ("reserved", C.c_int32)]
+
+
+EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_options", "gs_total_tiles",
+           "gs_total_pixels", "gs_bin_sort_workspace_size", "gs_render_fwd_workspace_size",
+           "gs_render_bwd_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
+           "gs_adam_step")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgs.so once; raises when it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first "
+                           f"(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = C.CDLL(path)
+    pc, pp, po = C.POINTER(gs_camera), C.POINTER(gs_params), C.POINTER(gs_options)
+    i32, i64, sz = C.c_int32, C.c_int64, C.c_size_t
+    sig = {
+        "gs_status_string": (C.c_char_p, [C.c_int]),
+        "gs_last_error": (C.c_char_p, []),
+        "gs_abi_version": (i32, []),
+        "gs_default_options": (None, [po]),
+        "gs_total_tiles": (C.c_int, [pc, i32, i32, C.POINTER(i64)]),
+        "gs_total_pixels": (C.c_int, [pc, i32, C.POINTER(i64)]),
+        "gs_bin_sort_workspace_size": (C.c_int, [i64, pc, i32, po, i64, C.POINTER(sz)]),
+        "gs_render_fwd_workspace_size": (C.c_int, [pc, i32, po, C.POINTER(sz)]),
+        "gs_render_bwd_workspace_size": (C.c_int, [i64, i32, C.POINTER(sz)]),
+        "gs_project": (C.c_int, [pp, pc, i32, po, C.POINTER(gs_projected), P]),
+        "gs_bin_sort": (C.c_int, [C.POINTER(gs_projected), i64, pc, i32, po, C.POINTER(gs_bins), P, sz, P]),
+        "gs_render_fwd": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), pc, i32, po,
+                                    C.POINTER(gs_loss), C.POINTER(gs_image), P, sz, P]),
+        "gs_render_bwd": (C.c_int, [pp, C.POINTER(gs_projected), C.POINTER(gs_bins), C.POINTER(gs_image), pc, i32,
+                                    po, C.POINTER(gs_loss), C.POINTER(gs_grads), P, sz, P]),
+        "gs_adam_step": (C.c_int, [C.POINTER(gs_adam_group), i32, C.c_float, C.c_float, C.c_float, P, i32, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(fn, status):
+    if status != GS_OK:
+        lib = load()
+        raise GsError(fn, lib.gs_status_string(status).decode(), lib.gs_last_error().decode())
+
+
+def default_options(**overrides) -> gs_options:
+    o = gs_options()
+    load().gs_default_options(C.byref(o))
+    for k, v in overrides.items():
+        if k == "bg":
+            for i in range(3):
+                o.bg[i] = float(v[i])
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def make_cameras(cams) -> C.Array:
+    """Host array of gs_camera from objects with R, t, fx, fy, cx, cy, width, height."""
+    arr = (gs_camera * len(cams))()
+    for k, c in enumerate(cams):
+        R = [float(x) for x in __import__("numpy").asarray(c.R).reshape(9)]
+        t = [float(x) for x in __import__("numpy").asarray(c.t).reshape(3)]
+        for i in range(9):
+            arr[k].R[i] = R[i]
+        for i in range(3):
+            arr[k].t[i] = t[i]
+        arr[k].fx, arr[k].fy, arr[k].cx, arr[k].cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        arr[k].width, arr[k].height = int(c.width), int(c.height)
+    return arr
+
+
+# --------------------------------------------------------------------------- entry points
+def gs_total_tiles(cams, n_views, tile_size) -> int:
+    out = C.c_int64(0)
+    _check("gs_total_tiles", load().gs_total_tiles(cams, n_views, tile_size, C.byref(out)))
+    return out.value
+
+
+def gs_total_pixels(cams, n_views) -> int:
+    out = C.c_int64(0)
+    _check("gs_total_pixels", load().gs_total_pixels(cams, n_views, C.byref(out)))
+    return out.value
+
+
+def gs_bin_sort_workspace_size(n, cams, n_views, opts, pair_capacity) -> int:
+    out = C.c_size_t(0)
+    _check("gs_bin_sort_workspace_size",
+           load().gs_bin_sort_workspace_size(n, cams, n_views, C.byref(opts), pair_capacity, C.byref(out)))
+    return out.value
+
+
+def gs_render_fwd_workspace_size(cams, n_views, opts) -> int:
+    out = C.c_size_t(0)
+    _check("gs_render_fwd_workspace_size", load().gs_render_fwd_workspace_size(cams, n_views, C.byref(opts),
+                                                                              C.byref(out)))
+    return out.value
+
+
+def gs_render_bwd_workspace_size(n, n_views) -> int:
+    out = C.c_size_t(0)
+    _check("gs_render_bwd_workspace_size", load().gs_render_bwd_workspace_size(n, n_views, C.byref(out)))
+    return out.value
+
+
+def gs_project(params, cams, n_views, opts, out, stream):
+    _check("gs_project", load().gs_project(C.byref(params), cams, n_views, C.byref(opts), C.byref(out), stream))
+
+
+def gs_bin_sort(proj, n, cams, n_views, opts, bins, workspace, workspace_bytes, stream):
+    _check("gs_bin_sort", load().gs_bin_sort(C.byref(proj), n, cams, n_views, C.byref(opts), C.byref(bins),
+                                             workspace, workspace_bytes, stream))
+
+
+def gs_render_fwd(proj, n, bins, cams, n_views, opts, loss, out, workspace, workspace_bytes, stream):
+    _check("gs_render_fwd", load().gs_render_fwd(C.byref(proj), n, C.byref(bins), cams, n_views, C.byref(opts),
+                                                 C.byref(loss) if loss is not None else None, C.byref(out),
+                                                 workspace, workspace_bytes, stream))
+
+
+def gs_render_bwd(params, proj, bins, img, cams, n_views, opts, loss, grads, workspace, workspace_bytes, stream):
+    _check("gs_render_bwd", load().gs_render_bwd(C.byref(params), C.byref(proj), C.byref(bins),
+                                                 C.byref(img) if img is not None else None, cams, n_views,
+                                                 C.byref(opts), C.byref(loss), C.byref(grads), workspace,
+                                                 workspace_bytes, stream))
+
+
+def gs_adam_step(groups, n_groups, beta1, beta2, eps, d_step, zero_grad, stream):
+    _check("gs_adam_step", load().gs_adam_step(groups, n_groups, beta1, beta2, eps, d_step, zero_grad, stream))

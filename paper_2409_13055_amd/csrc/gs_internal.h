@@ -1,0 +1,84 @@
+// Internal definitions shared by the HIP kernels and the C-ABI entry points
+// of libgs (gfx950).  Not part of the public interface (include/gs.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "gs.h"
+
+namespace gs {
+
+constexpr int kWave = 64;
+
+// Per-view geometry needed by the binning and raster kernels.
+struct ViewGeom {
+  int32_t W, H, TX, TY;
+  int32_t tile_off, pix_off;
+};
+struct ViewTable {
+  int32_t n_views;
+  int32_t total_tiles;
+  int32_t total_pixels;
+  int32_t tile;
+  ViewGeom v[GS_MAX_VIEWS];
+};
+
+// Camera data needed by the projection kernels (plus derived constants).
+struct CamF {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float centre[3];  // -R^T t
+  float limx, limy; // frustum guard on x/z and y/z
+  int32_t W, H;
+};
+struct CamTable {
+  CamF c[GS_MAX_VIEWS];
+};
+
+// Status plumbing.
+void set_error(const std::string& msg);
+gs_status fail(gs_status s, const std::string& msg);
+gs_status check_launch(const char* what);
+
+gs_status validate_cams(const gs_camera* cams, int32_t n_views);
+gs_status validate_opts(const gs_options* o);
+ViewTable make_view_table(const gs_camera* cams, int32_t n_views, int32_t tile);
+CamTable make_cam_table(const gs_camera* cams, int32_t n_views, const gs_options* o);
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Round up to a multiple of 256 bytes (workspace sub-buffer alignment).
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Projected record field offsets (see gs_projected).
+enum RecField { kMx = 0, kMy, kCa, kCb, kCc, kOp, kR, kG, kB, kDepth, kRadius, kFlags };
+
+// Which view owns global tile `gt` (views are few; linear scan).
+__device__ inline int view_of_tile(const ViewTable& vt, int gt) {
+  int v = 0;
+#pragma unroll 1
+  for (int u = 1; u < vt.n_views; ++u)
+    if (vt.v[u].tile_off <= gt) v = u;
+  return v;
+}
+
+// Tile rectangle of a splat: [x0,x1) x [y0,y1), FP32 arithmetic in exactly
+// this order (the bounds must agree bit for bit wherever they are computed).
+__device__ inline void tile_rect(float mx, float my, int radius, int B, int TX, int TY, int& x0, int& y0, int& x1,
+                                 int& y1) {
+  const float r = (float)radius, fb = (float)B, fb1 = (float)(B - 1);
+  const float ax0 = floorf(__fdiv_rn(__fsub_rn(mx, r), fb));
+  const float ax1 = floorf(__fdiv_rn(__fadd_rn(__fadd_rn(mx, r), fb1), fb));
+  const float ay0 = floorf(__fdiv_rn(__fsub_rn(my, r), fb));
+  const float ay1 = floorf(__fdiv_rn(__fadd_rn(__fadd_rn(my, r), fb1), fb));
+  x0 = (int)fminf(fmaxf(ax0, 0.0f), (float)TX);
+  x1 = (int)fminf(fmaxf(ax1, 0.0f), (float)TX);
+  y0 = (int)fminf(fmaxf(ay0, 0.0f), (float)TY);
+  y1 = (int)fminf(fmaxf(ay1, 0.0f), (float)TY);
+}
+
+}  // namespace gs

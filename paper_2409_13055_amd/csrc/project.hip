@@ -1,0 +1,514 @@
+// Projection of the Gaussian set onto the keyframe image planes and its
+// backward pass (Sec. II "projecting Gaussians onto the camera plane";
+// Gaussian parameterisation of Sec. III-B).
+//
+// One thread per Gaussian loops over every view of the call, so the 236 bytes
+// of parameters of an SH-3 Gaussian are read from HBM once per call however
+// many keyframes are rendered, and the records of view v are written as
+// contiguous 48-byte rows (coalesced across the wavefront).
+#include <cmath>
+#include <cstring>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+struct ProjectArgs {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* logits;
+  const float* sh_dc;
+  const float* sh_rest;
+  int64_t n;
+  int32_t n_views;
+  int32_t tile;
+  float near_plane, eps2d, radius_sigmas;
+};
+
+struct GradPtrs {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* logits;
+  float* sh_dc;
+  float* sh_rest;
+};
+
+// Real spherical harmonics up to degree 3 (Condon-Shortley phase, order
+// l, m = -l..l) at a unit direction.
+__device__ inline void sh_basis(int D, float x, float y, float z, float* Y) {
+  Y[0] = 0.28209479177387814f;
+  if (D < 1) return;
+  Y[1] = -0.4886025119029199f * y;
+  Y[2] = 0.4886025119029199f * z;
+  Y[3] = -0.4886025119029199f * x;
+  if (D < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = 1.0925484305920792f * x * y;
+  Y[5] = -1.0925484305920792f * y * z;
+  Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+  Y[7] = -1.0925484305920792f * x * z;
+  Y[8] = 0.5462742152960396f * (xx - yy);
+  if (D < 3) return;
+  Y[9] = -0.5900435899266435f * y * (3.0f * xx - yy);
+  Y[10] = 2.890611442640554f * x * y * z;
+  Y[11] = -0.4570457994644658f * y * (4.0f * zz - xx - yy);
+  Y[12] = 0.3731763325901154f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[13] = -0.4570457994644658f * x * (4.0f * zz - xx - yy);
+  Y[14] = 1.445305721320277f * z * (xx - yy);
+  Y[15] = -0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+// sum_k a_k grad(Y_k) of the polynomial forms above.
+__device__ inline void sh_grad_dot(int D, float x, float y, float z, const float* a, float& gx, float& gy,
+                                   float& gz) {
+  gx = gy = gz = 0.0f;
+  if (D < 1) return;
+  const float c1 = 0.4886025119029199f;
+  gy -= c1 * a[1];
+  gz += c1 * a[2];
+  gx -= c1 * a[3];
+  if (D < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float c2a = 1.0925484305920792f, c2b = 0.31539156525252005f, c2c = 0.5462742152960396f;
+  gx += c2a * y * a[4];
+  gy += c2a * x * a[4];
+  gy -= c2a * z * a[5];
+  gz -= c2a * y * a[5];
+  gx -= 2.0f * c2b * x * a[6];
+  gy -= 2.0f * c2b * y * a[6];
+  gz += 4.0f * c2b * z * a[6];
+  gx -= c2a * z * a[7];
+  gz -= c2a * x * a[7];
+  gx += 2.0f * c2c * x * a[8];
+  gy -= 2.0f * c2c * y * a[8];
+  if (D < 3) return;
+  const float k0 = -0.5900435899266435f, k1 = 2.890611442640554f, k2 = -0.4570457994644658f,
+              k3 = 0.3731763325901154f, k5 = 1.445305721320277f;
+  gx += k0 * 6.0f * x * y * a[9];
+  gy += k0 * (3.0f * xx - 3.0f * yy) * a[9];
+  gx += k1 * y * z * a[10];
+  gy += k1 * x * z * a[10];
+  gz += k1 * x * y * a[10];
+  gx += k2 * (-2.0f * x * y) * a[11];
+  gy += k2 * (4.0f * zz - xx - 3.0f * yy) * a[11];
+  gz += k2 * 8.0f * y * z * a[11];
+  gx += k3 * (-6.0f * x * z) * a[12];
+  gy += k3 * (-6.0f * y * z) * a[12];
+  gz += k3 * (6.0f * zz - 3.0f * xx - 3.0f * yy) * a[12];
+  gx += k2 * (4.0f * zz - 3.0f * xx - yy) * a[13];
+  gy += k2 * (-2.0f * x * y) * a[13];
+  gz += k2 * 8.0f * x * z * a[13];
+  gx += k5 * 2.0f * x * z * a[14];
+  gy -= k5 * 2.0f * y * z * a[14];
+  gz += k5 * (xx - yy) * a[14];
+  gx += k0 * (3.0f * xx - 3.0f * yy) * a[15];
+  gy += k0 * (-6.0f * x * y) * a[15];
+}
+
+// View-independent part of a Gaussian: normalised quaternion, rotation,
+// scales and the 3D covariance Sigma = (R S)(R S)^T.
+struct Gauss3D {
+  float m[3];
+  float q[4];
+  float qnorm;
+  float R[9];
+  float s[3];
+  float M[9];    // R diag(s)
+  float Sig[6];  // xx xy xz yy yz zz
+  bool ok;
+};
+
+__device__ inline void load_gauss(const ProjectArgs& a, int64_t i, Gauss3D& g) {
+  g.m[0] = a.means[3 * i];
+  g.m[1] = a.means[3 * i + 1];
+  g.m[2] = a.means[3 * i + 2];
+  const float4 q = *reinterpret_cast<const float4*>(a.quats + 4 * i);
+  const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
+  g.ok = qn2 > 0.0f;
+  g.qnorm = sqrtf(qn2);
+  const float inv = g.ok ? 1.0f / g.qnorm : 0.0f;
+  const float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
+  g.q[0] = w; g.q[1] = x; g.q[2] = y; g.q[3] = z;
+  g.R[0] = 1.f - 2.f * (y * y + z * z); g.R[1] = 2.f * (x * y - w * z);       g.R[2] = 2.f * (x * z + w * y);
+  g.R[3] = 2.f * (x * y + w * z);       g.R[4] = 1.f - 2.f * (x * x + z * z); g.R[5] = 2.f * (y * z - w * x);
+  g.R[6] = 2.f * (x * z - w * y);       g.R[7] = 2.f * (y * z + w * x);       g.R[8] = 1.f - 2.f * (x * x + y * y);
+  for (int k = 0; k < 3; ++k) g.s[k] = expf(a.log_scales[3 * i + k]);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) g.M[3 * r + c] = g.R[3 * r + c] * g.s[c];
+  const float* M = g.M;
+  g.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  g.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+  g.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+  g.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+  g.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+  g.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+}
+
+// Per-view projection: camera point, guarded Jacobian J, T = J W, dilated
+// 2D covariance, its inverse (conic) and the image-plane mean.
+struct Proj2D {
+  float t[3];
+  float txc, tyc;
+  float cvx, cvy;   // clamp value of x/z, y/z when the guard is active
+  bool clx, cly;
+  float T[6];
+  float a, b, c;    // dilated covariance
+  float ca, cb, cc; // conic
+  float mx, my;
+};
+
+__device__ inline bool project_view(const Gauss3D& g, const CamF& cam, float near_plane, float eps2d, Proj2D& p) {
+  const float* W = cam.R;
+  for (int r = 0; r < 3; ++r)
+    p.t[r] = W[3 * r] * g.m[0] + W[3 * r + 1] * g.m[1] + W[3 * r + 2] * g.m[2] + cam.t[r];
+  if (!(p.t[2] > near_plane)) return false;
+  const float iz = 1.0f / p.t[2];
+  const float ux = p.t[0] * iz, uy = p.t[1] * iz;
+  p.clx = ux < -cam.limx || ux > cam.limx;
+  p.cly = uy < -cam.limy || uy > cam.limy;
+  p.cvx = fminf(fmaxf(ux, -cam.limx), cam.limx);
+  p.cvy = fminf(fmaxf(uy, -cam.limy), cam.limy);
+  p.txc = p.clx ? p.cvx * p.t[2] : p.t[0];
+  p.tyc = p.cly ? p.cvy * p.t[2] : p.t[1];
+  const float j00 = cam.fx * iz, j02 = -cam.fx * p.txc * iz * iz;
+  const float j11 = cam.fy * iz, j12 = -cam.fy * p.tyc * iz * iz;
+  for (int c = 0; c < 3; ++c) {
+    p.T[c] = j00 * W[c] + j02 * W[6 + c];
+    p.T[3 + c] = j11 * W[3 + c] + j12 * W[6 + c];
+  }
+  const float* S = g.Sig;
+  const float* T = p.T;
+  // (T Sigma) rows
+  const float u0 = T[0] * S[0] + T[1] * S[1] + T[2] * S[2];
+  const float u1 = T[0] * S[1] + T[1] * S[3] + T[2] * S[4];
+  const float u2 = T[0] * S[2] + T[1] * S[4] + T[2] * S[5];
+  const float w0 = T[3] * S[0] + T[4] * S[1] + T[5] * S[2];
+  const float w1 = T[3] * S[1] + T[4] * S[3] + T[5] * S[4];
+  const float w2 = T[3] * S[2] + T[4] * S[4] + T[5] * S[5];
+  p.a = u0 * T[0] + u1 * T[1] + u2 * T[2] + eps2d;
+  p.b = u0 * T[3] + u1 * T[4] + u2 * T[5];
+  p.c = w0 * T[3] + w1 * T[4] + w2 * T[5] + eps2d;
+  const float det = p.a * p.c - p.b * p.b;
+  if (!(det > 0.0f)) return false;
+  const float idet = 1.0f / det;
+  p.ca = p.c * idet;
+  p.cb = -p.b * idet;
+  p.cc = p.a * idet;
+  p.mx = cam.fx * p.t[0] * iz + cam.cx - 0.5f;
+  p.my = cam.fy * p.t[1] * iz + cam.cy - 0.5f;
+  return true;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, float* __restrict__ rec,
+                                                 int32_t* __restrict__ tiles_touched) {
+  constexpr int K = (D + 1) * (D + 1);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  Gauss3D g;
+  load_gauss(a, i, g);
+  float sh[K][3];
+  sh[0][0] = a.sh_dc[3 * i];
+  sh[0][1] = a.sh_dc[3 * i + 1];
+  sh[0][2] = a.sh_dc[3 * i + 2];
+#pragma unroll
+  for (int k = 1; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sh[k][c] = a.sh_rest[(i * (K - 1) + (k - 1)) * 3 + c];
+  const float op = 1.0f / (1.0f + expf(-a.logits[i]));
+  const int B = a.tile;
+#pragma unroll 1
+  for (int v = 0; v < a.n_views; ++v) {
+    const CamF& cam = cams.c[v];
+    Proj2D p;
+    bool ok = g.ok && project_view(g, cam, a.near_plane, a.eps2d, p);
+    int radius = 0, tiles = 0;
+    float rgb[3] = {0.f, 0.f, 0.f};
+    uint32_t flags = 0;
+    if (ok) {
+      const float mid = 0.5f * (p.a + p.c);
+      const float lam = mid + sqrtf(fmaxf(mid * mid - (p.a * p.c - p.b * p.b), 0.0f));
+      radius = (int)ceilf(a.radius_sigmas * sqrtf(lam));
+      const int TX = (cam.W + B - 1) / B, TY = (cam.H + B - 1) / B;
+      int x0, y0, x1, y1;
+      tile_rect(p.mx, p.my, radius, B, TX, TY, x0, y0, x1, y1);
+      tiles = (x1 - x0) * (y1 - y0);
+      if (tiles <= 0) {
+        ok = false;
+        radius = 0;
+        tiles = 0;
+      }
+    }
+    if (ok) {
+      float dx = g.m[0] - cam.centre[0], dy = g.m[1] - cam.centre[1], dz = g.m[2] - cam.centre[2];
+      const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+      dx *= inv; dy *= inv; dz *= inv;
+      float Y[16];
+      sh_basis(D, dx, dy, dz, Y);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float s = 0.5f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) s += sh[k][c] * Y[k];
+        if (s < 0.0f) {
+          flags |= 1u << c;
+          s = 0.0f;
+        }
+        rgb[c] = s;
+      }
+      if (p.clx) flags |= 1u << 3;
+      if (p.cly) flags |= 1u << 4;
+    }
+    const int64_t row = (int64_t)v * a.n + i;
+    float4* out = reinterpret_cast<float4*>(rec + row * GS_REC_FLOATS);
+    if (ok) {
+      out[0] = make_float4(p.mx, p.my, p.ca, p.cb);
+      out[1] = make_float4(p.cc, op, rgb[0], rgb[1]);
+      out[2] = make_float4(rgb[2], p.t[2], __int_as_float(radius), __uint_as_float(flags));
+    } else {
+      out[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+      out[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+      out[2] = make_float4(0.f, 0.f, __int_as_float(0), __uint_as_float(0u));
+    }
+    tiles_touched[row] = tiles;
+  }
+}
+
+// Backward of the projection: one thread per Gaussian sums the image-space
+// gradients of all its views, accumulating the view-independent d/dSigma
+// once, then chains to log-scales and the (unnormalised) quaternion.
+template <int D>
+__global__ __launch_bounds__(128) void k_project_bwd(ProjectArgs a, CamTable cams, const float* __restrict__ rec,
+                                                     const float* __restrict__ grad2d, GradPtrs gp) {
+  constexpr int K = (D + 1) * (D + 1);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  Gauss3D g;
+  load_gauss(a, i, g);
+  if (!g.ok) return;
+  float sh[K][3], gsh[K][3];
+  sh[0][0] = a.sh_dc[3 * i];
+  sh[0][1] = a.sh_dc[3 * i + 1];
+  sh[0][2] = a.sh_dc[3 * i + 2];
+#pragma unroll
+  for (int k = 1; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sh[k][c] = a.sh_rest[(i * (K - 1) + (k - 1)) * 3 + c];
+#pragma unroll
+  for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.0f;
+  float gm[3] = {0.f, 0.f, 0.f};
+  float gS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float gop = 0.0f;
+  bool any = false;
+#pragma unroll 1
+  for (int v = 0; v < a.n_views; ++v) {
+    const int64_t row = (int64_t)v * a.n + i;
+    const float4 r2 = reinterpret_cast<const float4*>(rec + row * GS_REC_FLOATS)[2];
+    if (__float_as_int(r2.z) == 0) continue;
+    const uint32_t flags = __float_as_uint(r2.w);
+    float g2[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g2[k] = grad2d[row * 9 + k];
+    const CamF& cam = cams.c[v];
+    Proj2D p;
+    if (!project_view(g, cam, a.near_plane, a.eps2d, p)) continue;
+    any = true;
+    // conic -> covariance: dL/dcov = -Q GQ Q
+    const float A = p.ca, Bq = p.cb, C = p.cc;
+    const float ga = g2[2], gb = 0.5f * g2[3], gc = g2[4];
+    const float q00 = A * ga + Bq * gb, q01 = A * gb + Bq * gc;
+    const float q10 = Bq * ga + C * gb, q11 = Bq * gb + C * gc;
+    const float G00 = -(q00 * A + q01 * Bq);
+    const float G01 = -(q00 * Bq + q01 * C);
+    const float G11 = -(q10 * Bq + q11 * C);
+    // cov = T Sigma T^T (dilation is additive): dL/dSigma = T^T G T, dL/dT = 2 G T Sigma
+    const float* T = p.T;
+    float u[3], w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      u[k] = G00 * T[k] + G01 * T[3 + k];
+      w[k] = G01 * T[k] + G11 * T[3 + k];
+    }
+    gS[0] += T[0] * u[0] + T[3] * w[0];
+    gS[1] += T[0] * u[1] + T[3] * w[1];
+    gS[2] += T[0] * u[2] + T[3] * w[2];
+    gS[3] += T[1] * u[1] + T[4] * w[1];
+    gS[4] += T[1] * u[2] + T[4] * w[2];
+    gS[5] += T[2] * u[2] + T[5] * w[2];
+    const float* S = g.Sig;
+    const float GT0[3] = {2.f * (u[0] * S[0] + u[1] * S[1] + u[2] * S[2]),
+                          2.f * (u[0] * S[1] + u[1] * S[3] + u[2] * S[4]),
+                          2.f * (u[0] * S[2] + u[1] * S[4] + u[2] * S[5])};
+    const float GT1[3] = {2.f * (w[0] * S[0] + w[1] * S[1] + w[2] * S[2]),
+                          2.f * (w[0] * S[1] + w[1] * S[3] + w[2] * S[4]),
+                          2.f * (w[0] * S[2] + w[1] * S[4] + w[2] * S[5])};
+    const float* Wc = cam.R;
+    // dL/dJ = dL/dT W^T (entries J00, J02, J11, J12)
+    const float gj00 = GT0[0] * Wc[0] + GT0[1] * Wc[1] + GT0[2] * Wc[2];
+    const float gj02 = GT0[0] * Wc[6] + GT0[1] * Wc[7] + GT0[2] * Wc[8];
+    const float gj11 = GT1[0] * Wc[3] + GT1[1] * Wc[4] + GT1[2] * Wc[5];
+    const float gj12 = GT1[0] * Wc[6] + GT1[1] * Wc[7] + GT1[2] * Wc[8];
+    const float tz = p.t[2], iz = 1.0f / tz, iz2 = iz * iz, iz3 = iz2 * iz;
+    float gt0 = 0.f, gt1 = 0.f, gt2 = 0.f;
+    gt2 += gj00 * (-cam.fx * iz2) + gj11 * (-cam.fy * iz2);
+    gt0 += p.clx ? 0.0f : gj02 * (-cam.fx * iz2);
+    gt2 += gj02 * (-cam.fx * iz2 * (p.clx ? p.cvx : 0.0f) + 2.0f * cam.fx * p.txc * iz3);
+    gt1 += p.cly ? 0.0f : gj12 * (-cam.fy * iz2);
+    gt2 += gj12 * (-cam.fy * iz2 * (p.cly ? p.cvy : 0.0f) + 2.0f * cam.fy * p.tyc * iz3);
+    // image-plane mean
+    gt0 += g2[0] * cam.fx * iz;
+    gt1 += g2[1] * cam.fy * iz;
+    gt2 -= (g2[0] * cam.fx * p.t[0] + g2[1] * cam.fy * p.t[1]) * iz2;
+    gm[0] += Wc[0] * gt0 + Wc[3] * gt1 + Wc[6] * gt2;
+    gm[1] += Wc[1] * gt0 + Wc[4] * gt1 + Wc[7] * gt2;
+    gm[2] += Wc[2] * gt0 + Wc[5] * gt1 + Wc[8] * gt2;
+    gop += g2[5];
+    // colour -> SH coefficients and the viewing direction
+    float dx = g.m[0] - cam.centre[0], dy = g.m[1] - cam.centre[1], dz = g.m[2] - cam.centre[2];
+    const float len = sqrtf(dx * dx + dy * dy + dz * dz), il = 1.0f / len;
+    dx *= il; dy *= il; dz *= il;
+    float Y[16], acoef[16];
+    sh_basis(D, dx, dy, dz, Y);
+    const float wr = (flags & 1u) ? 0.f : g2[6], wg = (flags & 2u) ? 0.f : g2[7], wb = (flags & 4u) ? 0.f : g2[8];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      gsh[k][0] += wr * Y[k];
+      gsh[k][1] += wg * Y[k];
+      gsh[k][2] += wb * Y[k];
+      acoef[k] = wr * sh[k][0] + wg * sh[k][1] + wb * sh[k][2];
+    }
+    if (D > 0) {
+      float gdx, gdy, gdz;
+      sh_grad_dot(D, dx, dy, dz, acoef, gdx, gdy, gdz);
+      const float dd = gdx * dx + gdy * dy + gdz * dz;
+      gm[0] += (gdx - dx * dd) * il;
+      gm[1] += (gdy - dy * dd) * il;
+      gm[2] += (gdz - dz * dd) * il;
+    }
+  }
+  if (!any) return;
+  // Sigma = M M^T, M = R diag(s): dL/dM = 2 gS M
+  const float GSm[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
+  float GM[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      GM[3 * r + c] = 2.0f * (GSm[3 * r] * g.M[c] + GSm[3 * r + 1] * g.M[3 + c] + GSm[3 * r + 2] * g.M[6 + c]);
+  float gls[3], GR[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float gsv = GM[c] * g.R[c] + GM[3 + c] * g.R[3 + c] + GM[6 + c] * g.R[6 + c];
+    gls[c] = gsv * g.s[c];
+    GR[c] = GM[c] * g.s[c];
+    GR[3 + c] = GM[3 + c] * g.s[c];
+    GR[6 + c] = GM[6 + c] * g.s[c];
+  }
+  const float w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
+  // d R / d(w,x,y,z) contracted with GR
+  const float gw = 2.f * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+  const float gx = 2.f * (y * GR[1] + z * GR[2] + y * GR[3] - 2.f * x * GR[4] - w * GR[5] + z * GR[6] + w * GR[7] -
+                          2.f * x * GR[8]);
+  const float gy = 2.f * (-2.f * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7] -
+                          2.f * y * GR[8]);
+  const float gz = 2.f * (-2.f * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2.f * z * GR[4] + y * GR[5] +
+                          x * GR[6] + y * GR[7]);
+  const float dotq = w * gw + x * gx + y * gy + z * gz;
+  const float iq = 1.0f / g.qnorm;
+  const float op = 1.0f / (1.0f + expf(-a.logits[i]));
+  gp.means[3 * i] += gm[0];
+  gp.means[3 * i + 1] += gm[1];
+  gp.means[3 * i + 2] += gm[2];
+  gp.log_scales[3 * i] += gls[0];
+  gp.log_scales[3 * i + 1] += gls[1];
+  gp.log_scales[3 * i + 2] += gls[2];
+  float4* gq = reinterpret_cast<float4*>(gp.quats + 4 * i);
+  float4 qv = *gq;
+  qv.x += (gw - w * dotq) * iq;
+  qv.y += (gx - x * dotq) * iq;
+  qv.z += (gy - y * dotq) * iq;
+  qv.w += (gz - z * dotq) * iq;
+  *gq = qv;
+  gp.logits[i] += gop * op * (1.0f - op);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) gp.sh_dc[3 * i + c] += gsh[0][c];
+#pragma unroll
+  for (int k = 1; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gp.sh_rest[(i * (K - 1) + (k - 1)) * 3 + c] += gsh[k][c];
+}
+
+static ProjectArgs make_args(const gs_params* p, int32_t n_views, const gs_options* o) {
+  ProjectArgs a;
+  a.means = p->means;
+  a.log_scales = p->log_scales;
+  a.quats = p->quats;
+  a.logits = p->opacity_logits;
+  a.sh_dc = p->sh_dc;
+  a.sh_rest = p->sh_rest;
+  a.n = p->n;
+  a.n_views = n_views;
+  a.tile = o->tile_size;
+  a.near_plane = o->near_plane;
+  a.eps2d = o->eps2d;
+  a.radius_sigmas = o->radius_sigmas;
+  return a;
+}
+
+gs_status validate_params(const gs_params* p) {
+  if (!p) return fail(GS_ERR_INVALID_VALUE, "params is NULL");
+  if (p->n < 1 || p->n > (int64_t(1) << 31)) return fail(GS_ERR_INVALID_VALUE, "params->n must be in [1, 2^31]");
+  if (p->sh_degree < 0 || p->sh_degree > GS_MAX_SH_DEGREE)
+    return fail(GS_ERR_INVALID_VALUE, "sh_degree must be in [0, 3]");
+  if (!p->means || !p->log_scales || !p->quats || !p->opacity_logits || !p->sh_dc)
+    return fail(GS_ERR_INVALID_VALUE, "a parameter pointer is NULL");
+  if (p->sh_degree > 0 && !p->sh_rest) return fail(GS_ERR_INVALID_VALUE, "sh_rest is NULL with sh_degree > 0");
+  if (reinterpret_cast<uintptr_t>(p->quats) % 16 != 0)
+    return fail(GS_ERR_INVALID_VALUE, "quats must be 16-byte aligned");
+  return GS_OK;
+}
+
+gs_status launch_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                             const float* rec, const float* grad2d, const gs_grads* grads, hipStream_t stream) {
+  const ProjectArgs a = make_args(params, n_views, opts);
+  const CamTable ct = make_cam_table(cams, n_views, opts);
+  GradPtrs gp{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->sh_dc, grads->sh_rest};
+  const int bs = 128;
+  const dim3 grid((unsigned)((params->n + bs - 1) / bs));
+  switch (params->sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(bs), 0, stream, a, ct, rec, grad2d, gp); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(bs), 0, stream, a, ct, rec, grad2d, gp); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(bs), 0, stream, a, ct, rec, grad2d, gp); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(bs), 0, stream, a, ct, rec, grad2d, gp); break;
+  }
+  return check_launch("projection backward");
+}
+
+}  // namespace gs
+
+extern "C" gs_status gs_project(const gs_params* params, const gs_camera* cams, int32_t n_views,
+                                const gs_options* opts, const gs_projected* out, void* stream) {
+  using namespace gs;
+  gs_status s;
+  if ((s = validate_params(params)) != GS_OK) return s;
+  if ((s = validate_cams(cams, n_views)) != GS_OK) return s;
+  if ((s = validate_opts(opts)) != GS_OK) return s;
+  if (!out || !out->rec || !out->tiles_touched) return fail(GS_ERR_INVALID_VALUE, "out/rec/tiles_touched is NULL");
+  if (reinterpret_cast<uintptr_t>(out->rec) % 16 != 0) return fail(GS_ERR_INVALID_VALUE, "rec must be 16-byte aligned");
+  if ((int64_t)n_views * params->n >= (int64_t(1) << 32) - 1)
+    return fail(GS_ERR_INVALID_VALUE, "n_views * n must be < 2^32 - 1");
+  const ProjectArgs a = make_args(params, n_views, opts);
+  const CamTable ct = make_cam_table(cams, n_views, opts);
+  const int bs = 256;
+  const dim3 grid((unsigned)((params->n + bs - 1) / bs));
+  hipStream_t st = as_stream(stream);
+  switch (params->sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched); break;
+    default: hipLaunchKernelGGL(k_project<3>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched); break;
+  }
+  return check_launch("projection");
+}

@@ -1,0 +1,534 @@
+// Tile rasteriser: front-to-back blending (Sec. II) of the depth-ordered
+// splat list of each screen tile, its backward pass, and the L1 term of the
+// photometric loss, eq. (2).
+//
+// Work decomposition (gfx950, wave64): one workgroup per screen tile.  A
+// 16x16 tile is ONE wavefront whose lanes own a column of 4 vertically
+// adjacent pixels each; an 8x8 tile is one wavefront with one pixel per lane;
+// a 32x32 tile is four wavefronts of 4 pixels per lane.  Splat records are
+// staged in LDS in batches of one record per lane and read back as
+// broadcasts (every lane reads the same address: no bank conflicts).  In the
+// backward pass each lane first sums its own pixels, then the wavefront
+// reduces the 9 image-space gradient terms with DPP row operations and the
+// gfx950 permlane16/32 swaps, and 9 lanes issue one hardware FP32 atomic each,
+// so one atomic per term per wavefront per splat reaches L2.
+#include <algorithm>
+#include <string>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+gs_status validate_params(const gs_params* p);
+gs_status launch_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                             const float* rec, const float* grad2d, const gs_grads* grads, hipStream_t stream);
+
+struct RasterConsts {
+  float alpha_min, alpha_max, t_min;
+  float bg0, bg1, bg2;
+};
+
+// power = -(a dx^2 + c dy^2)/2 - b dx dy, with one fixed rounding sequence so
+// that the forward and backward passes take identical skip decisions.
+__device__ __forceinline__ float splat_power(float dx, float dy, float ca, float cb, float cc) {
+#pragma clang fp contract(off)
+  const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
+  return fmaf(-cb * dx, dy, -0.5f * q);
+}
+
+__device__ __forceinline__ float exp_hw(float x) {
+#pragma clang fp contract(off)
+  return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+
+// Sum over the 64 lanes of a wavefront; every lane receives the total.
+__device__ __forceinline__ float wave_sum(float x) {
+  x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp<0x141>(x);  // row_half_mirror
+  x += dpp<0x140>(x);  // row_mirror: each 16-lane row now holds its row sum
+  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  x = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
+}
+
+template <int TILE>
+struct TileShape;
+template <>
+struct TileShape<8> {
+  static constexpr int WAVES = 1, PPL = 1;
+};
+template <>
+struct TileShape<16> {
+  static constexpr int WAVES = 1, PPL = 4;
+};
+template <>
+struct TileShape<32> {
+  static constexpr int WAVES = 4, PPL = 4;
+};
+
+// Pixel placement inside a tile: lane l of wave w owns column l % TILE and
+// PPL consecutive rows starting at w*ROWS + (l / TILE)*PPL.
+template <int TILE>
+struct PixMap {
+  static constexpr int WAVES = TileShape<TILE>::WAVES, PPL = TileShape<TILE>::PPL, NT = 64 * WAVES;
+  static constexpr int ROWS_PER_WAVE = (64 / TILE) * PPL;
+  static_assert(ROWS_PER_WAVE * WAVES == TILE, "tile shape");
+  int v, x, y0, W, H, pix_off, tile;
+  __device__ PixMap(const ViewTable& vt, int gt) {
+    tile = gt;
+    v = view_of_tile(vt, gt);
+    const ViewGeom& g = vt.v[v];
+    W = g.W;
+    H = g.H;
+    pix_off = g.pix_off;
+    const int lt = gt - g.tile_off;
+    const int tx = lt % g.TX, ty = lt / g.TX;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    x = tx * TILE + lane % TILE;
+    y0 = ty * TILE + w * ROWS_PER_WAVE + (lane / TILE) * PPL;
+  }
+  __device__ bool inside(int p) const { return x < W && y0 + p < H; }
+  __device__ int pix(int p) const { return pix_off + (y0 + p) * W + x; }
+  __device__ int chan(int p, int c) const { return 3 * pix_off + c * W * H + (y0 + p) * W + x; }
+};
+
+struct SplatLds {
+  float4 a;  // mx, my, ca, cb
+  float4 b;  // cc, opacity, r, g
+  float c;   // b
+};
+
+// ---------------------------------------------------------------------------
+// Forward.
+// ---------------------------------------------------------------------------
+template <int TILE>
+__global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
+    ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
+    RasterConsts rc, float* __restrict__ img, float* __restrict__ tfin, int32_t* __restrict__ ncon,
+    const float* __restrict__ target, float* __restrict__ tile_loss) {
+  using PM = PixMap<TILE>;
+  constexpr int PPL = PM::PPL, NT = PM::NT;
+  __shared__ float4 s_a[NT];
+  __shared__ float4 s_b[NT];
+  __shared__ float s_c[NT];
+  __shared__ float s_loss[PM::WAVES];
+  const PM pm(vt, blockIdx.x);
+  float T[PPL], C[PPL][3];
+  int last[PPL];
+  bool done[PPL];
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    T[p] = 1.0f;
+    C[p][0] = C[p][1] = C[p][2] = 0.0f;
+    last[p] = 0;
+    done[p] = !pm.inside(p);
+  }
+  const uint2 rg = ranges[blockIdx.x];
+  const int s = (int)rg.x, e = (int)rg.y;
+  const float fx = (float)pm.x;
+  for (int base = s; base < e; base += NT) {
+    int alive = 0;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
+    if (__syncthreads_count(alive) == 0) break;
+    const int idx = base + (int)threadIdx.x;
+    if (idx < e) {
+      const float4* r = reinterpret_cast<const float4*>(rec + (size_t)ids[idx] * GS_REC_FLOATS);
+      s_a[threadIdx.x] = r[0];
+      s_b[threadIdx.x] = r[1];
+      s_c[threadIdx.x] = r[2].x;
+    }
+    __syncthreads();
+    const int cnt = min(NT, e - base);
+    for (int j = 0; j < cnt; ++j) {
+      const float4 A = s_a[j];
+      const float4 Bv = s_b[j];
+      const float cbl = s_c[j];
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        if (done[p]) continue;
+        const float dx = fx - A.x, dy = (float)(pm.y0 + p) - A.y;
+        const float power = splat_power(dx, dy, A.z, A.w, Bv.x);
+        if (power > 0.0f) continue;
+        const float oG = Bv.y * exp_hw(power);
+        const float alpha = fminf(rc.alpha_max, oG);
+        if (alpha < rc.alpha_min) continue;
+        const float test = T[p] * (1.0f - alpha);
+        if (test < rc.t_min) {
+          done[p] = true;
+          continue;
+        }
+        const float wgt = alpha * T[p];
+        C[p][0] += Bv.z * wgt;
+        C[p][1] += Bv.w * wgt;
+        C[p][2] += cbl * wgt;
+        T[p] = test;
+        last[p] = base - s + j + 1;
+      }
+    }
+  }
+  float lsum = 0.0f;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    if (!pm.inside(p)) continue;
+    const float out[3] = {C[p][0] + T[p] * rc.bg0, C[p][1] + T[p] * rc.bg1, C[p][2] + T[p] * rc.bg2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      img[pm.chan(p, c)] = out[c];
+      if (target) lsum += fabsf(out[c] - target[pm.chan(p, c)]);
+    }
+    if (tfin) {
+      tfin[pm.pix(p)] = T[p];
+      ncon[pm.pix(p)] = last[p];
+    }
+  }
+  if (tile_loss) {
+    lsum = wave_sum(lsum);
+    if ((threadIdx.x & 63) == 0) s_loss[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float t = 0.0f;
+      for (int w = 0; w < PM::WAVES; ++w) t += s_loss[w];
+      tile_loss[blockIdx.x] = t;
+    }
+  }
+}
+
+// Per-view L1 term from the per-tile partial sums (fixed order).
+__global__ __launch_bounds__(256) void k_loss_reduce(ViewTable vt, const float* __restrict__ tile_loss,
+                                                     float* __restrict__ loss_out) {
+  __shared__ float s_w[4];
+  const ViewGeom& g = vt.v[blockIdx.x];
+  const int nt = g.TX * g.TY;
+  float acc = 0.0f;
+  for (int t = threadIdx.x; t < nt; t += 256) acc += tile_loss[g.tile_off + t];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) loss_out[blockIdx.x] = (s_w[0] + s_w[1] + s_w[2] + s_w[3]) / (3.0f * (float)g.W * (float)g.H);
+}
+
+// ---------------------------------------------------------------------------
+// Backward.
+// ---------------------------------------------------------------------------
+template <int TILE, bool CKPT>
+__global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
+    ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
+    RasterConsts rc, const float* __restrict__ img, const float* __restrict__ tfin, const int32_t* __restrict__ ncon,
+    int loss_kind, const float* __restrict__ target, const float* __restrict__ dl_dimage,
+    float* __restrict__ grad2d) {
+  using PM = PixMap<TILE>;
+  constexpr int PPL = PM::PPL, NT = PM::NT;
+  __shared__ float4 s_a[NT];
+  __shared__ float4 s_b[NT];
+  __shared__ float s_c[NT];
+  __shared__ uint32_t s_id[NT];
+  __shared__ int s_max[PM::WAVES];
+  const PM pm(vt, blockIdx.x);
+  const uint2 rg = ranges[blockIdx.x];
+  const int s = (int)rg.x, e = (int)rg.y;
+  const float fx = (float)pm.x;
+  const int lane = threadIdx.x & 63;
+  float T[PPL], dl[PPL][3], S[PPL][3];
+  int last[PPL];
+
+  if (CKPT) {
+    // Forward replay: final transmittance and contributor count only.
+    bool done[PPL];
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      T[p] = 1.0f;
+      last[p] = 0;
+      done[p] = !pm.inside(p);
+    }
+    for (int base = s; base < e; base += NT) {
+      int alive = 0;
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
+      if (__syncthreads_count(alive) == 0) break;
+      const int idx = base + (int)threadIdx.x;
+      if (idx < e) {
+        const float4* r = reinterpret_cast<const float4*>(rec + (size_t)ids[idx] * GS_REC_FLOATS);
+        s_a[threadIdx.x] = r[0];
+        s_b[threadIdx.x] = r[1];
+      }
+      __syncthreads();
+      const int cnt = min(NT, e - base);
+      for (int j = 0; j < cnt; ++j) {
+        const float4 A = s_a[j];
+        const float4 Bv = s_b[j];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+          if (done[p]) continue;
+          const float dx = fx - A.x, dy = (float)(pm.y0 + p) - A.y;
+          const float power = splat_power(dx, dy, A.z, A.w, Bv.x);
+          if (power > 0.0f) continue;
+          const float alpha = fminf(rc.alpha_max, Bv.y * exp_hw(power));
+          if (alpha < rc.alpha_min) continue;
+          const float test = T[p] * (1.0f - alpha);
+          if (test < rc.t_min) {
+            done[p] = true;
+            continue;
+          }
+          T[p] = test;
+          last[p] = base - s + j + 1;
+        }
+      }
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      T[p] = pm.inside(p) ? tfin[pm.pix(p)] : 1.0f;
+      // a contributor count never exceeds the tile's list length
+      last[p] = pm.inside(p) ? min(max(ncon[pm.pix(p)], 0), e - s) : 0;
+    }
+  }
+  const float wv = 1.0f / (3.0f * (float)pm.W * (float)pm.H);
+  int mylast = 0;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    if (pm.inside(p)) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float d;
+        if (loss_kind == GS_LOSS_L1) {
+          const float r = img[pm.chan(p, c)] - target[pm.chan(p, c)];
+          d = r > 0.0f ? wv : (r < 0.0f ? -wv : 0.0f);
+        } else {
+          d = dl_dimage[pm.chan(p, c)];
+        }
+        dl[p][c] = d;
+      }
+    } else {
+      dl[p][0] = dl[p][1] = dl[p][2] = 0.0f;
+    }
+    S[p][0] = T[p] * rc.bg0;
+    S[p][1] = T[p] * rc.bg1;
+    S[p][2] = T[p] * rc.bg2;
+    mylast = max(mylast, last[p]);
+  }
+  // Longest blended prefix in the tile.
+  for (int o = 32; o > 0; o >>= 1) mylast = max(mylast, __shfl_xor(mylast, o));
+  if (lane == 0) s_max[threadIdx.x >> 6] = mylast;
+  __syncthreads();
+  int max_last = 0;
+#pragma unroll
+  for (int w = 0; w < PM::WAVES; ++w) max_last = max(max_last, s_max[w]);
+
+  for (int hi = max_last; hi > 0; hi -= NT) {
+    const int lo = max(0, hi - NT);
+    const int idx = s + lo + (int)threadIdx.x;
+    if (idx < s + hi) {
+      const uint32_t id = ids[idx];
+      const float4* r = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS);
+      s_a[threadIdx.x] = r[0];
+      s_b[threadIdx.x] = r[1];
+      s_c[threadIdx.x] = r[2].x;
+      s_id[threadIdx.x] = id;
+    }
+    __syncthreads();
+    for (int k = hi - 1; k >= lo; --k) {
+      const int j = k - lo;
+      const float4 A = s_a[j];
+      const float4 Bv = s_b[j];
+      const float cbl = s_c[j];
+      float g[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) g[c] = 0.0f;
+      bool any = false;
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        if (k >= last[p]) continue;
+        const float dx = fx - A.x, dy = (float)(pm.y0 + p) - A.y;
+        const float power = splat_power(dx, dy, A.z, A.w, Bv.x);
+        if (power > 0.0f) continue;
+        const float G = exp_hw(power);
+        const float oG = Bv.y * G;
+        const float alpha = fminf(rc.alpha_max, oG);
+        if (alpha < rc.alpha_min) continue;
+        any = true;
+        const float inv = 1.0f / (1.0f - alpha);
+        T[p] *= inv;  // transmittance in front of this splat
+        const float wgt = alpha * T[p];
+        g[6] += dl[p][0] * wgt;
+        g[7] += dl[p][1] * wgt;
+        g[8] += dl[p][2] * wgt;
+        const float dLda = dl[p][0] * (Bv.z * T[p] - S[p][0] * inv) + dl[p][1] * (Bv.w * T[p] - S[p][1] * inv) +
+                           dl[p][2] * (cbl * T[p] - S[p][2] * inv);
+        S[p][0] += Bv.z * wgt;
+        S[p][1] += Bv.w * wgt;
+        S[p][2] += cbl * wgt;
+        if (oG <= rc.alpha_max) {
+          const float dLdp = dLda * alpha;
+          g[5] += dLda * G;
+          g[0] += dLdp * (A.z * dx + A.w * dy);
+          g[1] += dLdp * (A.w * dx + Bv.x * dy);
+          g[2] -= 0.5f * dLdp * dx * dx;
+          g[3] -= dLdp * dx * dy;
+          g[4] -= 0.5f * dLdp * dy * dy;
+        }
+      }
+      if (__ballot(any) != 0ull) {
+        float val = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const float t = wave_sum(g[c]);
+          val = (lane == c) ? t : val;
+        }
+        if (lane < 9) atomicAdd(grad2d + (size_t)s_id[j] * 9 + lane, val);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, uint64_t count) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+static RasterConsts consts_of(const gs_options* o) {
+  return RasterConsts{o->alpha_min, o->alpha_max, o->t_min, o->bg[0], o->bg[1], o->bg[2]};
+}
+
+static gs_status validate_raster_common(const gs_projected* proj, const gs_bins* bins, const gs_camera* cams,
+                                        int32_t n_views, const gs_options* opts) {
+  gs_status s;
+  if ((s = validate_cams(cams, n_views)) != GS_OK) return s;
+  if ((s = validate_opts(opts)) != GS_OK) return s;
+  if (!proj || !proj->rec) return fail(GS_ERR_INVALID_VALUE, "proj->rec is NULL");
+  if (!bins || !bins->ids || !bins->ranges) return fail(GS_ERR_INVALID_VALUE, "bins->ids/ranges is NULL");
+  if (reinterpret_cast<uintptr_t>(proj->rec) % 16 != 0) return fail(GS_ERR_INVALID_VALUE, "rec must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(bins->ranges) % 8 != 0)
+    return fail(GS_ERR_INVALID_VALUE, "ranges must be 8-byte aligned");
+  return GS_OK;
+}
+
+}  // namespace gs
+
+extern "C" gs_status gs_render_fwd_workspace_size(const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                                                  size_t* bytes) {
+  using namespace gs;
+  gs_status s;
+  if ((s = validate_cams(cams, n_views)) != GS_OK) return s;
+  if ((s = validate_opts(opts)) != GS_OK) return s;
+  if (!bytes) return fail(GS_ERR_INVALID_VALUE, "bytes is NULL");
+  *bytes = align256(sizeof(float) * (size_t)make_view_table(cams, n_views, opts->tile_size).total_tiles);
+  return GS_OK;
+}
+
+extern "C" gs_status gs_render_bwd_workspace_size(int64_t n, int32_t n_views, size_t* bytes) {
+  using namespace gs;
+  if (!bytes) return fail(GS_ERR_INVALID_VALUE, "bytes is NULL");
+  if (n < 1 || n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_VALUE, "bad n or n_views");
+  *bytes = align256(sizeof(float) * GS_GRAD2D_FLOATS * (size_t)n * (size_t)n_views);
+  return GS_OK;
+}
+
+extern "C" gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
+                                   int32_t n_views, const gs_options* opts, const gs_loss* loss, const gs_image* out,
+                                   void* workspace, size_t workspace_bytes, void* stream) {
+  using namespace gs;
+  gs_status s;
+  if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
+  if (n < 1) return fail(GS_ERR_INVALID_VALUE, "n must be >= 1");
+  if (!out || !out->rgb) return fail(GS_ERR_INVALID_VALUE, "out->rgb is NULL");
+  if (!opts->checkpoint && (!out->t_final || !out->n_contrib))
+    return fail(GS_ERR_INVALID_VALUE, "t_final/n_contrib are required unless checkpoint is set");
+  const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
+  const bool want_loss = loss && loss->kind == GS_LOSS_L1 && loss->loss_out;
+  if (loss && loss->kind != GS_LOSS_NONE && loss->kind != GS_LOSS_L1 && loss->kind != GS_LOSS_EXTERNAL)
+    return fail(GS_ERR_INVALID_VALUE, "unknown loss kind");
+  if (want_loss && !loss->target) return fail(GS_ERR_INVALID_VALUE, "L1 loss needs a target");
+  const size_t need = align256(sizeof(float) * (size_t)vt.total_tiles);
+  if (want_loss && (!workspace || workspace_bytes < need))
+    return fail(GS_ERR_CAPACITY, "workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t st = as_stream(stream);
+  const RasterConsts rc = consts_of(opts);
+  float* tl = want_loss ? static_cast<float*>(workspace) : nullptr;
+  const float* tgt = want_loss ? loss->target : nullptr;
+  float* tf = opts->checkpoint ? nullptr : out->t_final;
+  int32_t* nc = opts->checkpoint ? nullptr : out->n_contrib;
+  const dim3 grid((unsigned)vt.total_tiles);
+  const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
+  switch (opts->tile_size) {
+    case 8:
+      hipLaunchKernelGGL(k_render_fwd<8>, grid, dim3(64), 0, st, vt, proj->rec, bins->ids, rg, rc, out->rgb, tf, nc,
+                         tgt, tl);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_render_fwd<16>, grid, dim3(64), 0, st, vt, proj->rec, bins->ids, rg, rc, out->rgb, tf, nc,
+                         tgt, tl);
+      break;
+    default:
+      hipLaunchKernelGGL(k_render_fwd<32>, grid, dim3(256), 0, st, vt, proj->rec, bins->ids, rg, rc, out->rgb, tf,
+                         nc, tgt, tl);
+      break;
+  }
+  if (want_loss) hipLaunchKernelGGL(k_loss_reduce, dim3(n_views), dim3(256), 0, st, vt, tl, loss->loss_out);
+  return check_launch("render forward");
+}
+
+extern "C" gs_status gs_render_bwd(const gs_params* params, const gs_projected* proj, const gs_bins* bins,
+                                   const gs_image* img, const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                                   const gs_loss* loss, const gs_grads* grads, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
+  using namespace gs;
+  gs_status s;
+  if ((s = validate_params(params)) != GS_OK) return s;
+  if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
+  if (!loss || (loss->kind != GS_LOSS_L1 && loss->kind != GS_LOSS_EXTERNAL))
+    return fail(GS_ERR_INVALID_VALUE, "loss must be GS_LOSS_L1 or GS_LOSS_EXTERNAL");
+  if (loss->kind == GS_LOSS_L1 && (!loss->target || !img || !img->rgb))
+    return fail(GS_ERR_INVALID_VALUE, "L1 loss needs target and img->rgb");
+  if (loss->kind == GS_LOSS_EXTERNAL && !loss->dl_dimage)
+    return fail(GS_ERR_INVALID_VALUE, "external loss needs dl_dimage");
+  if (!opts->checkpoint && (!img || !img->t_final || !img->n_contrib))
+    return fail(GS_ERR_INVALID_VALUE, "img->t_final/n_contrib are required unless checkpoint is set");
+  if (!grads || !grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh_dc ||
+      (params->sh_degree > 0 && !grads->sh_rest))
+    return fail(GS_ERR_INVALID_VALUE, "a gradient pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(grads->quats) % 16 != 0)
+    return fail(GS_ERR_INVALID_VALUE, "grads->quats must be 16-byte aligned");
+  const size_t g2n = (size_t)GS_GRAD2D_FLOATS * (size_t)params->n * (size_t)n_views;
+  if (!workspace || workspace_bytes < sizeof(float) * g2n)
+    return fail(GS_ERR_CAPACITY, "workspace too small: need " + std::to_string(sizeof(float) * g2n) + " bytes");
+  const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
+  hipStream_t st = as_stream(stream);
+  const RasterConsts rc = consts_of(opts);
+  float* g2 = static_cast<float*>(workspace);
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)std::min<size_t>(8192, (g2n + 255) / 256)), dim3(256), 0, st, g2,
+                     (uint64_t)g2n);
+  const dim3 grid((unsigned)vt.total_tiles);
+  const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
+  const float* rgb = img ? img->rgb : nullptr;
+  const float* tf = img ? img->t_final : nullptr;
+  const int32_t* nc = img ? img->n_contrib : nullptr;
+#define GS_BWD(TILE, NT, CK)                                                                                        \
+  hipLaunchKernelGGL((k_render_bwd<TILE, CK>), grid, dim3(NT), 0, st, vt, proj->rec, bins->ids, rg, rc, rgb, tf, nc, \
+                     (int)loss->kind, loss->target, loss->dl_dimage, g2)
+  if (opts->checkpoint) {
+    switch (opts->tile_size) {
+      case 8: GS_BWD(8, 64, true); break;
+      case 16: GS_BWD(16, 64, true); break;
+      default: GS_BWD(32, 256, true); break;
+    }
+  } else {
+    switch (opts->tile_size) {
+      case 8: GS_BWD(8, 64, false); break;
+      case 16: GS_BWD(16, 64, false); break;
+      default: GS_BWD(32, 256, false); break;
+    }
+  }
+#undef GS_BWD
+  if ((s = check_launch("render backward")) != GS_OK) return s;
+  return launch_project_bwd(params, cams, n_views, opts, proj->rec, g2, grads, st);
+}

@@ -1,0 +1,365 @@
+"""Device-side driver of the mapping step built on the libgs C ABI.
+
+PyTorch only provides device memory and the stream; every step of the
+rasteriser and the optimiser runs in the HIP kernels of libgs.so:
+
+  Rasterizer       buffers + the four hot-path calls (project, bin/sort,
+                   forward, backward) for a fixed set of keyframe cameras;
+  render / RasterizeGaussians
+                   torch.autograd.Function around them (dL/dimage from the
+                   caller's loss);
+  FusedAdam        gs_adam_step over the six parameter groups;
+  MappingStep      one full iteration of the mapping module (Sec. III-B:
+                   render, L1 term of eq. (2), backward, Adam) over a batch
+                   of keyframes, runnable eagerly or replayed from a HIP
+                   graph; PerViewMappingStep runs the same kernels one view
+                   at a time.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh_dc", "sh_rest")
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class GaussianParams:
+    """The Gaussian set of Sec. III-B as six FP32 device tensors."""
+
+    def __init__(self, means, log_scales, quats, opacity_logits, sh_dc, sh_rest, sh_degree: int):
+        self.means, self.log_scales, self.quats = means, log_scales, quats
+        self.opacity_logits, self.sh_dc, self.sh_rest = opacity_logits, sh_dc, sh_rest
+        self.sh_degree = int(sh_degree)
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_scene(scene, device="cuda") -> "GaussianParams":
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device).contiguous()  # noqa: E731
+        return GaussianParams(f(scene.means), f(scene.log_scales), f(scene.quats), f(scene.opacity_logits),
+                              f(scene.sh_dc), f(scene.sh_rest), scene.sh_degree)
+
+    def tensors(self) -> List[torch.Tensor]:
+        return [getattr(self, k) for k in PARAM_NAMES]
+
+    def zeros_like(self) -> "GaussianParams":
+        return GaussianParams(*[torch.zeros_like(t) for t in self.tensors()], self.sh_degree)
+
+    def c_params(self) -> L.gs_params:
+        p = L.gs_params()
+        p.n, p.sh_degree = self.n, self.sh_degree
+        p.means, p.log_scales, p.quats = _p(self.means), _p(self.log_scales), _p(self.quats)
+        p.opacity_logits, p.sh_dc = _p(self.opacity_logits), _p(self.sh_dc)
+        p.sh_rest = _p(self.sh_rest) if self.sh_degree > 0 else None
+        return p
+
+    def c_grads(self) -> L.gs_grads:
+        g = L.gs_grads()
+        g.means, g.log_scales, g.quats = _p(self.means), _p(self.log_scales), _p(self.quats)
+        g.opacity_logits, g.sh_dc = _p(self.opacity_logits), _p(self.sh_dc)
+        g.sh_rest = _p(self.sh_rest) if self.sh_degree > 0 else None
+        return g
+
+
+def pack_images(images: Sequence, device="cuda") -> torch.Tensor:
+    """Per-view [3,H,W] images -> one packed FP32 device buffer (view-major, planar)."""
+    parts = [torch.as_tensor(np.ascontiguousarray(a, np.float32)).reshape(-1) for a in images]
+    return torch.cat(parts).to(device).contiguous()
+
+
+def unpack_images(flat: torch.Tensor, cameras, channels=3) -> List[torch.Tensor]:
+    out, off = [], 0
+    for c in cameras:
+        k = channels * c.width * c.height
+        a = flat[off:off + k]
+        out.append(a.view(channels, c.height, c.width) if channels > 1 else a.view(c.height, c.width))
+        off += k
+    return out
+
+
+class Frame:
+    """Buffers of one rendered batch: projected records, bins, image."""
+
+    def __init__(self, rast: "Rasterizer", capacity: int):
+        dev = rast.device
+        VN = rast.n * rast.n_views
+        self.rec = torch.empty(VN * L.GS_REC_FLOATS, dtype=torch.float32, device=dev)
+        self.tiles = torch.empty(VN, dtype=torch.int32, device=dev)
+        self.ranges = torch.empty(2 * rast.total_tiles, dtype=torch.int32, device=dev)
+        self.d_num_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.d_overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.rgb = torch.empty(3 * rast.total_pixels, dtype=torch.float32, device=dev)
+        if rast.checkpoint:
+            self.t_final = self.n_contrib = None
+        else:
+            self.t_final = torch.empty(rast.total_pixels, dtype=torch.float32, device=dev)
+            self.n_contrib = torch.empty(rast.total_pixels, dtype=torch.int32, device=dev)
+        self.keys = None
+        self.set_capacity(capacity, rast.want_keys)
+
+    def set_capacity(self, capacity: int, want_keys: bool):
+        dev = self.rec.device
+        self.capacity = int(capacity)
+        self.ids = torch.empty(max(1, self.capacity), dtype=torch.int32, device=dev)
+        self.keys = torch.empty(max(1, self.capacity), dtype=torch.int64, device=dev) if want_keys else None
+
+    def c_proj(self) -> L.gs_projected:
+        return L.gs_projected(_p(self.rec), _p(self.tiles))
+
+    def c_bins(self) -> L.gs_bins:
+        b = L.gs_bins()
+        b.keys, b.ids, b.ranges = _p(self.keys), _p(self.ids), _p(self.ranges)
+        b.capacity = self.capacity
+        b.d_num_pairs, b.d_overflow = _p(self.d_num_pairs), _p(self.d_overflow)
+        return b
+
+    def c_image(self) -> L.gs_image:
+        return L.gs_image(_p(self.rgb), _p(self.t_final), _p(self.n_contrib))
+
+
+class Rasterizer:
+    """The four rasteriser calls of libgs for a fixed set of keyframe cameras."""
+
+    def __init__(self, cameras, n: int, sh_degree: int, tile_size: int = 16, checkpoint: bool = False,
+                 device="cuda", want_keys: bool = False, growth: float = 1.25, **opt_overrides):
+        L.load()
+        self.cameras = list(cameras)
+        self.n_views = len(self.cameras)
+        self.n = int(n)
+        self.sh_degree = int(sh_degree)
+        self.device = torch.device(device)
+        self.checkpoint = bool(checkpoint)
+        self.want_keys = want_keys
+        self.growth = growth
+        self.opts = L.default_options(tile_size=int(tile_size), checkpoint=int(checkpoint), **opt_overrides)
+        self.cams = L.make_cameras(self.cameras)
+        self.total_tiles = L.gs_total_tiles(self.cams, self.n_views, self.opts.tile_size)
+        self.total_pixels = L.gs_total_pixels(self.cams, self.n_views)
+        self.capacity = 0
+        self.ws_sort = None
+        self.ws_sort_bytes = 0
+        self.ws_fwd_bytes = L.gs_render_fwd_workspace_size(self.cams, self.n_views, self.opts)
+        self.ws_fwd = torch.empty(self.ws_fwd_bytes, dtype=torch.uint8, device=self.device)
+        self.ws_bwd_bytes = L.gs_render_bwd_workspace_size(self.n, self.n_views)
+        self.ws_bwd = torch.empty(self.ws_bwd_bytes, dtype=torch.uint8, device=self.device)
+        self._ensure_sort_ws(0)
+
+    def _ensure_sort_ws(self, capacity: int):
+        need = L.gs_bin_sort_workspace_size(self.n, self.cams, self.n_views, self.opts, capacity)
+        if self.ws_sort is None or need > self.ws_sort_bytes:
+            self.ws_sort = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self.ws_sort_bytes = need
+
+    def reserve(self, capacity: int):
+        """Set the pair capacity used by new frames (and grow the sort workspace)."""
+        self.capacity = int(capacity)
+        self._ensure_sort_ws(self.capacity)
+
+    def new_frame(self) -> Frame:
+        return Frame(self, self.capacity)
+
+    # hot-path calls --------------------------------------------------------
+    def project(self, params: GaussianParams, fr: Frame):
+        L.gs_project(params.c_params(), self.cams, self.n_views, self.opts, fr.c_proj(), _stream())
+
+    def bin_sort(self, fr: Frame):
+        if fr.capacity != self.capacity:
+            fr.set_capacity(self.capacity, self.want_keys)
+        L.gs_bin_sort(fr.c_proj(), self.n, self.cams, self.n_views, self.opts, fr.c_bins(), self.ws_sort.data_ptr(),
+                      self.ws_sort_bytes, _stream())
+
+    def render_fwd(self, fr: Frame, target: Optional[torch.Tensor] = None, loss_out: Optional[torch.Tensor] = None):
+        loss = L.gs_loss()
+        if target is not None and loss_out is not None:
+            loss.kind, loss.target, loss.loss_out = L.GS_LOSS_L1, _p(target), _p(loss_out)
+        L.gs_render_fwd(fr.c_proj(), self.n, fr.c_bins(), self.cams, self.n_views, self.opts, loss, fr.c_image(),
+                        self.ws_fwd.data_ptr(), self.ws_fwd_bytes, _stream())
+
+    def render_bwd(self, params: GaussianParams, fr: Frame, grads: GaussianParams,
+                   target: Optional[torch.Tensor] = None, dl_dimage: Optional[torch.Tensor] = None):
+        loss = L.gs_loss()
+        if dl_dimage is not None:
+            loss.kind, loss.dl_dimage = L.GS_LOSS_EXTERNAL, _p(dl_dimage)
+        else:
+            loss.kind, loss.target = L.GS_LOSS_L1, _p(target)
+        L.gs_render_bwd(params.c_params(), fr.c_proj(), fr.c_bins(), fr.c_image(), self.cams, self.n_views,
+                        self.opts, loss, grads.c_grads(), self.ws_bwd.data_ptr(), self.ws_bwd_bytes, _stream())
+
+    @property
+    def grad2d(self) -> torch.Tensor:
+        """[n_views*n, 9] image-space gradients of the last backward."""
+        return self.ws_bwd.view(torch.float32)[: self.n_views * self.n * 9].view(-1, 9)
+
+    # eager helpers -----------------------------------------------------------
+    def fit_capacity(self, fr: Frame) -> bool:
+        """After bin_sort: if the pairs overflowed, grow the capacity and sort again (syncs)."""
+        if int(fr.d_overflow.item()) == 0:
+            return False
+        m = int(fr.d_num_pairs.item())
+        self.reserve(int(math.ceil(m * self.growth)) + 1024)
+        self.bin_sort(fr)
+        assert int(fr.d_overflow.item()) == 0
+        return True
+
+    def forward(self, params: GaussianParams, fr: Optional[Frame] = None, target=None, loss_out=None) -> Frame:
+        fr = fr or self.new_frame()
+        self.project(params, fr)
+        self.bin_sort(fr)
+        self.fit_capacity(fr)
+        self.render_fwd(fr, target, loss_out)
+        return fr
+
+
+class RasterizeGaussians(torch.autograd.Function):
+    """image = render(Gaussians); backward takes dL/dimage from the caller's loss."""
+
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, means, log_scales, quats, opacity_logits, sh_dc, sh_rest):
+        params = GaussianParams(means.contiguous(), log_scales.contiguous(), quats.contiguous(),
+                                opacity_logits.contiguous(), sh_dc.contiguous(), sh_rest.contiguous(),
+                                rast.sh_degree)
+        fr = rast.forward(params)
+        ctx.rast, ctx.frame, ctx.params = rast, fr, params
+        return fr.rgb.clone()
+
+    @staticmethod
+    def backward(ctx, dl_dimage):
+        grads = ctx.params.zeros_like()
+        ctx.rast.render_bwd(ctx.params, ctx.frame, grads, dl_dimage=dl_dimage.contiguous())
+        return (None, *grads.tensors())
+
+
+def render(rast: Rasterizer, means, log_scales, quats, opacity_logits, sh_dc, sh_rest) -> torch.Tensor:
+    """Differentiable render of all views of `rast`; returns the packed [sum 3HW] image."""
+    return RasterizeGaussians.apply(rast, means, log_scales, quats, opacity_logits, sh_dc, sh_rest)
+
+
+class FusedAdam:
+    """Adam over the six parameter groups in one gs_adam_step launch (step counter on the device)."""
+
+    def __init__(self, params: GaussianParams, grads: GaussianParams, lrs: Dict[str, float],
+                 betas=(0.9, 0.999), eps=1e-15):
+        self.params, self.grads = params, grads
+        self.exp_avg = params.zeros_like()
+        self.exp_avg_sq = params.zeros_like()
+        self.betas, self.eps = betas, eps
+        self.d_step = torch.zeros(1, dtype=torch.int32, device=params.means.device)
+        names = [k for k in PARAM_NAMES if getattr(params, k).numel() > 0]
+        self.groups = (L.gs_adam_group * len(names))()
+        for i, k in enumerate(names):
+            g = self.groups[i]
+            g.param, g.grad = _p(getattr(params, k)), _p(getattr(grads, k))
+            g.exp_avg, g.exp_avg_sq = _p(getattr(self.exp_avg, k)), _p(getattr(self.exp_avg_sq, k))
+            g.numel, g.lr = getattr(params, k).numel(), float(lrs[k])
+        self.n_groups = len(names)
+
+    def step(self, zero_grad: bool = True):
+        L.gs_adam_step(self.groups, self.n_groups, self.betas[0], self.betas[1], self.eps, _p(self.d_step),
+                       1 if zero_grad else 0, _stream())
+
+
+class MappingStep:
+    """One mapping iteration over a batch of keyframes (Sec. III-B): project all
+    views in one pass over the parameters, one bin/sort over every view's
+    tiles, forward with the fused L1 loss, backward, and optionally Adam (which
+    also clears the gradients for the next iteration)."""
+
+    def __init__(self, params: GaussianParams, cameras, targets, lrs=None, tile_size=16, checkpoint=False,
+                 with_adam=True, **opt):
+        self.params = params
+        self.rast = Rasterizer(cameras, params.n, params.sh_degree, tile_size=tile_size, checkpoint=checkpoint,
+                               device=params.means.device, **opt)
+        self.grads = params.zeros_like()
+        self.target = targets if isinstance(targets, torch.Tensor) else pack_images(targets, params.means.device)
+        self.loss = torch.zeros(self.rast.n_views, dtype=torch.float32, device=params.means.device)
+        self.adam = FusedAdam(params, self.grads, lrs) if with_adam else None
+        self.frame = None
+        self.graph = None
+
+    def size(self):
+        """Eager warm-up that sizes the pair capacity (host syncs)."""
+        fr = self.frame or self.rast.new_frame()
+        self.rast.project(self.params, fr)
+        self.rast.bin_sort(fr)
+        self.rast.fit_capacity(fr)
+        self.frame = fr
+
+    def run(self):
+        """Enqueue one iteration (no host synchronisation)."""
+        r, fr = self.rast, self.frame
+        r.project(self.params, fr)
+        r.bin_sort(fr)
+        r.render_fwd(fr, self.target, self.loss)
+        r.render_bwd(self.params, fr, self.grads, target=self.target)
+        if self.adam is not None:
+            self.adam.step(zero_grad=True)
+
+    def overflowed(self) -> bool:
+        return int(self.frame.d_overflow.item()) != 0
+
+    def capture(self):
+        """Record one iteration into a HIP graph (after size())."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()  # one eager iteration on the capture stream before recording
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+
+    def replay(self):
+        self.graph.replay()
+
+
+class PerViewMappingStep:
+    """The same iteration with every keyframe rendered by its own calls
+    (projection re-reads the parameters per view; gradients accumulate)."""
+
+    def __init__(self, params: GaussianParams, cameras, targets, lrs=None, tile_size=16, checkpoint=False,
+                 with_adam=True, **opt):
+        self.params = params
+        dev = params.means.device
+        self.rasts = [Rasterizer([c], params.n, params.sh_degree, tile_size=tile_size, checkpoint=checkpoint,
+                                 device=dev, **opt) for c in cameras]
+        self.grads = params.zeros_like()
+        self.targets = [pack_images([t], dev) for t in targets]
+        self.losses = [torch.zeros(1, dtype=torch.float32, device=dev) for _ in cameras]
+        self.adam = FusedAdam(params, self.grads, lrs) if with_adam else None
+        self.frames = [None] * len(cameras)
+
+    def size(self):
+        for k, r in enumerate(self.rasts):
+            fr = self.frames[k] or r.new_frame()
+            r.project(self.params, fr)
+            r.bin_sort(fr)
+            r.fit_capacity(fr)
+            self.frames[k] = fr
+
+    def run(self):
+        for r, fr, tg, ls in zip(self.rasts, self.frames, self.targets, self.losses):
+            r.project(self.params, fr)
+            r.bin_sort(fr)
+            r.render_fwd(fr, tg, ls)
+            r.render_bwd(self.params, fr, self.grads, target=tg)
+        if self.adam is not None:
+            self.adam.step(zero_grad=True)
+
+    def overflowed(self) -> bool:
+        return any(int(fr.d_overflow.item()) != 0 for fr in self.frames)
