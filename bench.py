@@ -1,0 +1,230 @@
+"""Benchmark of the mapping step: Mpix*iter/s on one MI355X, batched vs per-view.
+
+A step is one mapping iteration over the workload's keyframes: projection,
+tile binning/sort, forward with the fused L1 loss, backward, and Adam when the
+workload includes it.  The batched path replays one HIP graph per step; the
+per-view path launches the same kernels view by view (no graph).  Inputs are
+seeded synthetic scenes already resident in HBM when timing starts.
+
+Prints one JSON line (see the keys below).  Default workload: 2M Gaussians,
+16 keyframes at 1200x680, SH degree 3, fwd+bwd+Adam, transmittance recomputed
+in the backward (checkpoint).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+VALU_PEAK_TOPS = 39.32       # 256 CU * 64 lanes * 2.4 GHz, unpacked FP32 lane-ops/s (x1e12)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=5, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--tile", type=int, default=0, help="tile size (0: autotune over 8/16/32)")
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many eager batched steps (for rocprofv3) and exit")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU design is data-parallel over keyframes, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2409_13055_amd import synthetic as S
+    from paper_2409_13055_amd import rasterizer as R
+    from paper_2409_13055_amd import autotune as A
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    sc = S.make_config(args.workload)
+    log(f"[bench] workload {sc.name}: N={sc.n} views={sc.n_views} px={sc.total_pixels} "
+        f"({time.time() - t0:.1f}s to generate)")
+    params = R.GaussianParams.from_scene(sc, dev)
+    target = R.pack_images(sc.targets, dev)
+    with_adam = "adam" in sc.work
+    lrs = sc.lrs or dict(S.DEFAULT_LRS)
+    tile = args.tile
+    tune = None
+    if tile == 0:
+        tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint)
+        tile = tune["best"]
+        log(f"[bench] autotune: {tune}")
+    step = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
+                         with_adam=with_adam)
+    step.size()
+    torch.cuda.synchronize()
+    log(f"[bench] pairs M={int(step.frame.d_num_pairs.item())} capacity={step.rast.capacity}")
+
+    if args.profile_steps > 0:
+        for _ in range(args.profile_steps):
+            step.run()
+        torch.cuda.synchronize()
+        log("[bench] profile steps done")
+        return
+
+    use_graph = not args.no_graph
+    if use_graph:
+        step.capture()
+    run = step.replay if use_graph else step.run
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    if step.overflowed():
+        raise RuntimeError("pair capacity overflowed during the timed steps")
+    mpix = sc.total_pixels * 1e-6
+    value = mpix / (ms * 1e-3)
+    loss = step.loss.sum().item()
+    log(f"[bench] batched: {ms:.3f} ms/step, {value:.1f} Mpix*iter/s, loss {loss:.5f}")
+
+    # Per-call breakdown (eager, events around each C call) and the dominant kernel.
+    stages = stage_breakdown(step, args.steps)
+    log(f"[bench] stages (ms): {stages}")
+
+    per_view = None
+    if not args.no_per_view:
+        pv = R.PerViewMappingStep(params, sc.cameras, sc.targets, lrs=lrs, tile_size=tile,
+                                  checkpoint=sc.checkpoint, with_adam=with_adam)
+        pv.size()
+        for _ in range(args.warmup):
+            pv.run()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            pv.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_pv = e0.elapsed_time(e1) / args.steps
+        per_view = {"ms_per_step": round(ms_pv, 4), "value": round(mpix / (ms_pv * 1e-3), 2),
+                    "batched_speedup": round(ms_pv / ms, 3)}
+        log(f"[bench] per-view: {ms_pv:.3f} ms/step ({per_view['batched_speedup']}x slower than batched)")
+        del pv
+
+    roof = roofline(step, sc, stages)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(sc, tile)
+    out = {
+        "metric": "3DGS fwd+bwd+Adam Mpix*iter/s at 1 GPU (batched HIP-graph step)",
+        "value": round(value, 2),
+        "unit": "Mpix*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": sc.name, "gaussians": sc.n, "views": sc.n_views, "pixels_per_step": sc.total_pixels,
+                   "sh_degree": sc.sh_degree, "work": sc.work, "checkpoint": sc.checkpoint, "tile": tile,
+                   "graph": use_graph, "pairs": int(step.frame.d_num_pairs.item())},
+        "per_view": per_view,
+        "stages_ms": stages,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if tune is not None:
+        out["autotune"] = tune
+    print(json.dumps(out), flush=True)
+
+
+def stage_breakdown(step, iters):
+    """Average duration of each hot-path call of the batched step (eager launches)."""
+    import torch
+    r, fr, p = step.rast, step.frame, step.params
+    calls = {
+        "project": lambda: r.project(p, fr),
+        "bin_sort": lambda: r.bin_sort(fr),
+        "render_fwd": lambda: r.render_fwd(fr, step.target, step.loss),
+        "render_bwd": lambda: r.render_bwd(p, fr, step.grads, target=step.target),
+    }
+    if step.adam is not None:
+        calls["adam"] = lambda: step.adam.step(zero_grad=True)
+    out = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(iters):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        out[name] = round(ev[0].elapsed_time(ev[1]) / iters, 4)
+    return out
+
+
+def roofline(step, sc, stages):
+    """Roofline entry for the dominant call (by measured duration)."""
+    from paper_2409_13055_amd import roofline as RF
+    return RF.report(step, sc, stages, hbm_peak_gbs=HBM_PEAK_GBS, valu_peak_tops=VALU_PEAK_TOPS)
+
+
+def crop_camera(c, x0, y0, w, h):
+    """The pixels [x0, x0+w) x [y0, y0+h) of camera c as a camera of their own."""
+    from paper_2409_13055_amd import synthetic as S
+    return S.Camera(c.R, c.t, c.fx, c.fy, c.cx - x0, c.cy - y0, w, h)
+
+
+def cpu_baseline(sc, tile):
+    """The FP64 oracle timed on the host cores over a bounded sample of the workload: the central
+    crop (at most half the width and height) of the first keyframe, rendered from all Gaussians
+    (projection, binning, blending, L1, backward), plus Adam over all parameters when the workload
+    steps the optimiser."""
+    import oracle.oracle as O
+    n_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    c = sc.cameras[0]
+    w, h = c.width, c.height
+    if w * h > 200_000:
+        w, h = w // 2, h // 2
+    x0, y0 = (c.width - w) // 2, (c.height - h) // 2
+    cam = crop_camera(c, x0, y0, w, h)
+    tgt = sc.targets[0][:, y0:y0 + h, x0:x0 + w]
+    P = O.Params.from_scene(sc)
+    opts = O.Options(tile=tile)
+    t0 = time.time()
+    fb = O.forward_backward_l1(P, [cam], [tgt], opts)
+    if "adam" in sc.work:
+        lrs = sc.lrs
+        for name, lr in (("means", lrs["means"]), ("log_scales", lrs["log_scales"]), ("quats", lrs["quats"]),
+                         ("opacity_logits", lrs["opacity_logits"]), ("sh", lrs["sh_dc"])):
+            p = getattr(P, name)
+            z = np.zeros_like(p)
+            O.adam_step(p, fb["grads"][name], z, z, 1, lr)
+    dt = time.time() - t0
+    return {"value": round(w * h * 1e-6 / dt, 4), "unit": "Mpix*iter/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"central {w}x{h} crop of keyframe 0 of {sc.n_views}, all {sc.n} Gaussians, fwd+L1+bwd"
+                      + ("+Adam on all parameters" if "adam" in sc.work else "") + f", FP64, {dt:.1f}s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -276,8 +276,8 @@ typedef struct gs_adam_group {
   int32_t reserved;
 } gs_adam_group;
 
-gs_status gs_adam_step(const gs_adam_group* groups /* host array */, int32_t n_groups, float beta1, float beta2,
-                       float eps, int32_t* d_step, int32_t zero_grad, void* stream);
+gs_status gs_adam_step(const gs_adam_group* groups /* host array */, int32_t n_groups, double beta1, double beta2,
+                       double eps, int32_t* d_step, int32_t zero_grad, void* stream);
 
 #ifdef __cplusplus
 }

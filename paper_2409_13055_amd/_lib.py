@@ -108,7 +108,7 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(gs_loss), C.POINTER(gs_image), P, sz, P]),
         "gs_render_bwd": (C.c_int, [pp, C.POINTER(gs_projected), C.POINTER(gs_bins), C.POINTER(gs_image), pc, i32,
                                     po, C.POINTER(gs_loss), C.POINTER(gs_grads), P, sz, P]),
-        "gs_adam_step": (C.c_int, [C.POINTER(gs_adam_group), i32, C.c_float, C.c_float, C.c_float, P, i32, P]),
+        "gs_adam_step": (C.c_int, [C.POINTER(gs_adam_group), i32, C.c_double, C.c_double, C.c_double, P, i32, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

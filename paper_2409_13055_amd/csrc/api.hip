@@ -71,7 +71,7 @@ ViewTable make_view_table(const gs_camera* cams, int32_t n_views, int32_t tile) 
   std::memset(&vt, 0, sizeof vt);
   vt.n_views = n_views;
   vt.tile = tile;
-  int32_t to = 0, po = 0;
+  int32_t to = 0, po = 0, go = 0;
   for (int v = 0; v < n_views; ++v) {
     ViewGeom& g = vt.v[v];
     g.W = cams[v].width;
@@ -80,9 +80,12 @@ ViewTable make_view_table(const gs_camera* cams, int32_t n_views, int32_t tile) 
     g.TY = (g.H + tile - 1) / tile;
     g.tile_off = to;
     g.pix_off = po;
+    g.grid_off = go;
     to += g.TX * g.TY;
     po += g.W * g.H;
+    go += (g.TX + 1) * (g.TY + 1);
   }
+  vt.total_grid = go;
   vt.total_tiles = to;
   vt.total_pixels = po;
   return vt;

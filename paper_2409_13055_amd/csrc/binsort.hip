@@ -36,9 +36,10 @@ __device__ inline Chunk chunk_of(uint64_t count, int nb, int b) {
   return {s, e};
 }
 
-// Exclusive scan of one value per thread over a 256-thread block.
-template <typename T>
-__device__ inline T block_exclusive_scan(T v, T* s_wave /*[4]*/, T& total) {
+// Exclusive scan of one value per thread over an NT-thread block (NT/64
+// wavefronts); `total` receives the block sum.
+template <typename T, int NT = kSortThreads>
+__device__ inline T block_exclusive_scan(T v, T* s_wave /*[NT/64]*/, T& total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   T x = v;
 #pragma unroll
@@ -50,7 +51,7 @@ __device__ inline T block_exclusive_scan(T v, T* s_wave /*[4]*/, T& total) {
   __syncthreads();
   T off = 0, tot = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < NT / 64; ++k) {
     const T t = s_wave[k];
     off += (k < w) ? t : T(0);
     tot += t;
@@ -164,103 +165,334 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scan_digit(uint32_t* __r
   if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
+// Downsweep: a block ranks a tile of kTileKeys keys at a time.  Wave w owns
+// the tile's keys [w*1024, (w+1)*1024) as 16 groups of 64; ballots over the 8
+// digit bits give each key its rank among equal digits of its group, and a
+// per-wave digit counter in LDS carries the rank across groups (a wave's LDS
+// operations execute in program order, so no barrier is needed).  The tile is
+// then reordered by digit in LDS and written out digit run by digit run, so
+// global stores are coalesced.  Order inside a digit follows the input index,
+// which keeps every pass stable.
+constexpr int kItems = 16;
+constexpr int kTileKeys = kSortThreads * kItems;
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_count, int shift, int nb,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_total) {
-  __shared__ uint32_t s_base[kRadixBins];
-  __shared__ uint32_t s_wcnt[4][kRadixBins];
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_total, uint64_t* __restrict__ keys64,
+    const float* __restrict__ rec) {
+  __shared__ uint32_t s_keys[kTileKeys];
+  __shared__ uint32_t s_vals[kTileKeys];
+  __shared__ uint32_t s_wc[4][kRadixBins];
+  __shared__ uint32_t s_start[kRadixBins];
+  __shared__ uint32_t s_glob[kRadixBins];
   __shared__ uint32_t s_w[4];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   {
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan<uint32_t>(digit_total[tid], s_w, tot);
-    s_base[tid] = ex + hist[(size_t)tid * nb + blockIdx.x];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) s_wcnt[k][tid] = 0;
+    s_glob[tid] = ex + hist[(size_t)tid * nb + blockIdx.x];
   }
-  __syncthreads();
   const Chunk c = chunk_of(*d_count, nb, blockIdx.x);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (uint64_t base = c.begin; base < c.end; base += kSortThreads) {
-    const uint64_t i = base + tid;
-    const bool valid = i < c.end;
-    const uint32_t k = valid ? kin[i] : 0u;
-    const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t d = (k >> shift) & (kRadixBins - 1);
-    uint64_t peers = __ballot(valid);
+  for (uint64_t tb = c.begin; tb < c.end; tb += kTileKeys) {
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
+    for (int k = 0; k < 4; ++k) s_wc[k][tid] = 0;
     __syncthreads();
-    if (valid) {
-      uint32_t pos = s_base[d] + rank;
-      for (int k2 = 0; k2 < w; ++k2) pos += s_wcnt[k2][d];
-      kout[pos] = k;
-      vout[pos] = val;
-    }
-    __syncthreads();
-    s_base[tid] += s_wcnt[0][tid] + s_wcnt[1][tid] + s_wcnt[2][tid] + s_wcnt[3][tid];
+    uint32_t key[kItems], val[kItems], rk[kItems];
 #pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) s_wcnt[k2][tid] = 0;
+    for (int k = 0; k < kItems; ++k) {
+      const uint64_t i = tb + (uint64_t)w * (kItems * 64) + k * 64 + lane;
+      const bool valid = i < c.end;
+      key[k] = valid ? kin[i] : 0u;
+      val[k] = valid ? vin[i] : 0u;
+      const uint32_t d = (key[k] >> shift) & (kRadixBins - 1);
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint32_t r = (uint32_t)__popcll(peers & lt);
+      const uint32_t before = s_wc[w][d];
+      if (valid && r == 0) s_wc[w][d] = before + (uint32_t)__popcll(peers);
+      rk[k] = valid ? before + r : 0xffffffffu;
+    }
     __syncthreads();
+    // thread d: wave prefixes of digit d (in place) and the tile's digit starts
+    uint32_t tot_d;
+    {
+      const uint32_t c0 = s_wc[0][tid], c1 = s_wc[1][tid], c2 = s_wc[2][tid], c3 = s_wc[3][tid];
+      tot_d = c0 + c1 + c2 + c3;
+      s_wc[0][tid] = 0;
+      s_wc[1][tid] = c0;
+      s_wc[2][tid] = c0 + c1;
+      s_wc[3][tid] = c0 + c1 + c2;
+      uint32_t all;
+      s_start[tid] = block_exclusive_scan<uint32_t>(tot_d, s_w, all);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (rk[k] != 0xffffffffu) {
+        const uint32_t d = (key[k] >> shift) & (kRadixBins - 1);
+        const uint32_t lp = s_start[d] + s_wc[w][d] + rk[k];
+        s_keys[lp] = key[k];
+        s_vals[lp] = val[k];
+      }
+    }
+    __syncthreads();
+    const uint32_t n_in = (uint32_t)min<uint64_t>(kTileKeys, c.end - tb);
+    for (uint32_t i = tid; i < n_in; i += kSortThreads) {
+      const uint32_t kk = s_keys[i];
+      const uint32_t d = (kk >> shift) & (kRadixBins - 1);
+      const uint32_t g = s_glob[d] + (i - s_start[d]);
+      const uint32_t vv = s_vals[i];
+      if (kout) kout[g] = kk;
+      vout[g] = vv;
+      if (keys64) keys64[g] = ((uint64_t)kk << 32) | depth_key(rec, vv);
+    }
+    __syncthreads();
+    s_glob[tid] += tot_d;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Incidence counting and emission in depth order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSortThreads) void k_count_pairs(const int32_t* __restrict__ tiles,
-                                                              const uint32_t* __restrict__ sorted_val,
-                                                              const uint32_t* __restrict__ d_k, int nb,
-                                                              uint64_t* __restrict__ partial) {
-  __shared__ uint64_t s_w[4];
-  const Chunk c = chunk_of(*d_k, nb, blockIdx.x);
-  uint64_t sum = 0;
-  for (uint64_t j = c.begin + threadIdx.x; j < c.end; j += kSortThreads) sum += (uint64_t)tiles[sorted_val[j]];
-  uint64_t tot;
-  block_exclusive_scan<uint64_t>(sum, s_w, tot);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+// Incidence counts per step of kStep consecutive depth-ordered pairs.
+constexpr int kStep = kSortThreads;
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kSortThreads) void k_step_pair_counts(const int32_t* __restrict__ tiles,
+                                                                   const uint32_t* __restrict__ sorted_val,
+                                                                   const uint32_t* __restrict__ d_k,
+                                                                   uint64_t* __restrict__ step_sums) {
+  __shared__ uint64_t s_w[kSortThreads / 64];
+  const uint32_t K = *d_k, nsteps = (K + kStep - 1) / kStep;
+  for (uint32_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
+    const uint32_t j = st * kStep + threadIdx.x;
+    const uint64_t cnt = j < K ? (uint64_t)tiles[sorted_val[j]] : 0;
+    uint64_t tot;
+    block_exclusive_scan<uint64_t>(cnt, s_w, tot);
+    if (threadIdx.x == 0) step_sums[st] = tot;
+  }
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_emit_pairs(
+// Exclusive scan of the step sums in place (one block); M -> d_num_pairs,
+// overflow flag, and the clamped count for the tile passes (0 on overflow).
+__global__ __launch_bounds__(kScanThreads) void k_scan_steps(uint64_t* __restrict__ step_sums,
+                                                             const uint32_t* __restrict__ d_k,
+                                                             uint32_t* __restrict__ d_m, int64_t* __restrict__ d_pairs,
+                                                             int32_t* __restrict__ d_overflow, uint64_t capacity) {
+  __shared__ uint64_t s_w[kScanThreads / 64];
+  const uint32_t nsteps = (*d_k + kStep - 1) / kStep;
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < nsteps; base += kScanThreads) {
+    const uint32_t i = base + threadIdx.x;
+    const uint64_t v = i < nsteps ? step_sums[i] : 0;
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan<uint64_t, kScanThreads>(v, s_w, tot);
+    if (i < nsteps) step_sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    *d_pairs = (int64_t)carry;
+    *d_overflow = carry > capacity ? 1 : 0;
+    // past the capacity the outputs are undefined; a zero count makes the
+    // remaining kernels of the call no-ops
+    *d_m = carry > capacity ? 0u : (uint32_t)carry;
+  }
+}
+
+// Emission, balanced over the OUTPUT: k_entry_offsets gives every depth-
+// ordered pair its exclusive incidence offset and a compact description of
+// its tile rect, and records which pair holds the first slot of every
+// kChunk-slot output chunk; k_emit_chunks then gives each thread kPerThread
+// consecutive output slots, finds the owning pair once (binary search inside
+// the chunk's pair range) and walks its rect row-major from there.  Work per
+// thread is fixed however skewed the per-pair tile counts are, and the
+// output order is that of a sequential emission (pair order, tiles row-major
+// within a pair).
+constexpr int kPerThread = 8;
+constexpr int kChunk = kSortThreads * kPerThread;
+
+__global__ __launch_bounds__(kSortThreads) void k_entry_offsets(
     const int32_t* __restrict__ tiles, const uint32_t* __restrict__ sorted_val, const float* __restrict__ rec,
-    const uint32_t* __restrict__ d_k, int nb, const uint64_t* __restrict__ partial, ViewTable vt, uint32_t n,
-    uint64_t capacity, uint32_t* __restrict__ p_key, uint32_t* __restrict__ p_val) {
-  __shared__ uint64_t s_w[4];
-  const Chunk c = chunk_of(*d_k, nb, blockIdx.x);
-  uint64_t run = partial[blockIdx.x];
-  for (uint64_t base = c.begin; base < c.end; base += kSortThreads) {
-    const uint64_t j = base + threadIdx.x;
-    uint32_t id = 0;
+    const uint32_t* __restrict__ d_k, const uint64_t* __restrict__ step_off, ViewTable vt, uint32_t n,
+    uint64_t capacity, uint64_t* __restrict__ ent_off, uint32_t* __restrict__ ent_base,
+    uint32_t* __restrict__ ent_txw, uint32_t* __restrict__ chunk_start, int32_t* __restrict__ cover) {
+  __shared__ uint64_t s_w[kSortThreads / 64];
+  const uint32_t K = *d_k, nsteps = (K + kStep - 1) / kStep;
+  for (uint32_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
+    const uint32_t j = st * kStep + threadIdx.x;
     uint64_t cnt = 0;
-    if (j < c.end) {
+    uint32_t id = 0;
+    int corner_view = -1;  // view whose grid origin this pair's rect starts at
+    if (j < K) {
       id = sorted_val[j];
       cnt = (uint64_t)tiles[id];
     }
     uint64_t tot;
-    const uint64_t ex = block_exclusive_scan<uint64_t>(cnt, s_w, tot);
-    uint64_t pos = run + ex;
-    if (cnt > 0 && pos + cnt <= capacity) {
-      const int v = (int)(id / n);
-      const ViewGeom& g = vt.v[v];
+    const uint64_t off = step_off[st] + block_exclusive_scan<uint64_t>(cnt, s_w, tot);
+    if (j < K) {
+      const ViewGeom& g = vt.v[id / n];
       const float4 r0 = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS)[0];
       const float4 r2 = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS)[2];
       int x0, y0, x1, y1;
       tile_rect(r0.x, r0.y, __float_as_int(r2.z), vt.tile, g.TX, g.TY, x0, y0, x1, y1);
-      for (int ty = y0; ty < y1; ++ty)
-        for (int tx = x0; tx < x1; ++tx) {
-          p_key[pos] = (uint32_t)(g.tile_off + ty * g.TX + tx);
-          p_val[pos] = id;
-          ++pos;
-        }
+      ent_off[j] = off;
+      // Corners of the rect in the view's coverage difference grid.  A
+      // corner in column TX or row TY only reaches grid cells outside every
+      // tile's prefix, so it is dropped.
+      int32_t* cg = cover + g.grid_off;
+      const int gw = g.TX + 1;
+      if (x0 != 0 || y0 != 0) atomicAdd(cg + y0 * gw + x0, 1);
+      if (x1 < g.TX) atomicAdd(cg + y0 * gw + x1, -1);
+      if (y1 < g.TY) atomicAdd(cg + y1 * gw + x0, -1);
+      if (x1 < g.TX && y1 < g.TY) atomicAdd(cg + y1 * gw + x1, 1);
+      ent_base[j] = (uint32_t)(g.tile_off + y0 * g.TX + x0);
+      ent_txw[j] = (uint32_t)g.TX | ((uint32_t)(x1 - x0) << 16);
+      corner_view = (x0 == 0 && y0 == 0) ? (int)(id / n) : -1;
+      // chunk boundaries inside [off, off + cnt): this pair holds their first slot
+      if (off + cnt <= capacity)
+        for (uint64_t c = (off + kChunk - 1) / kChunk; c * kChunk < off + cnt; ++c) chunk_start[c] = j;
     }
-    run += tot;
+    // Rects clamped to a view's top-left corner all hit the same grid cell:
+    // one atomic per view per wavefront.
+    uint64_t pending = __ballot(corner_view >= 0);
+    while (pending) {
+      const int lead = __ffsll((unsigned long long)pending) - 1;
+      const int v = __shfl(corner_view, lead);
+      const uint64_t same = __ballot(corner_view == v);
+      if ((threadIdx.x & 63) == lead) atomicAdd(cover + vt.v[v].grid_off, (int)__popcll(same));
+      pending &= ~same;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_emit_chunks(
+    const uint32_t* __restrict__ sorted_val, const uint32_t* __restrict__ d_k, const uint32_t* __restrict__ d_m,
+    const uint64_t* __restrict__ ent_off, const uint32_t* __restrict__ ent_base,
+    const uint32_t* __restrict__ ent_txw, const uint32_t* __restrict__ chunk_start, uint32_t* __restrict__ p_key,
+    uint32_t* __restrict__ p_val) {
+  __shared__ uint4 s_k[kChunk / 4];
+  __shared__ uint4 s_v[kChunk / 4];
+  const uint32_t K = *d_k;
+  const uint64_t M = *d_m;
+  const uint64_t nchunks = (M + kChunk - 1) / kChunk;
+  for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const uint64_t cq = c * kChunk;
+    const uint64_t q0 = cq + (uint64_t)threadIdx.x * kPerThread;
+    uint32_t kk[kPerThread], vv[kPerThread];
+    if (q0 < M) {
+      // last pair whose offset is <= q0, within this chunk's pair range
+      uint32_t lo = chunk_start[c];
+      uint32_t hi = (c + 1 < nchunks) ? chunk_start[c + 1] : K - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (ent_off[mid] <= q0) lo = mid;
+        else hi = mid - 1;
+      }
+      uint32_t j = lo;
+      uint64_t next = (j + 1 < K) ? ent_off[j + 1] : M;
+      uint32_t base = ent_base[j], txw = ent_txw[j], id = sorted_val[j];
+      uint32_t w = txw >> 16, k = (uint32_t)(q0 - ent_off[j]);
+      uint32_t ty = k / w, tx = k - ty * w;
+#pragma unroll
+      for (int e = 0; e < kPerThread; ++e) {
+        const uint64_t q = q0 + e;
+        if (q < M) {
+          while (q >= next) {  // next pair (every listed pair has at least one tile)
+            ++j;
+            next = (j + 1 < K) ? ent_off[j + 1] : M;
+            base = ent_base[j];
+            txw = ent_txw[j];
+            id = sorted_val[j];
+            w = txw >> 16;
+            tx = ty = 0;
+          }
+        }
+        kk[e] = base + ty * (txw & 0xffffu) + tx;
+        vv[e] = id;
+        if (++tx == w) {
+          tx = 0;
+          ++ty;
+        }
+      }
+    }
+    // stage through LDS so the global stores are contiguous across the wavefront
+    s_k[2 * threadIdx.x] = make_uint4(kk[0], kk[1], kk[2], kk[3]);
+    s_k[2 * threadIdx.x + 1] = make_uint4(kk[4], kk[5], kk[6], kk[7]);
+    s_v[2 * threadIdx.x] = make_uint4(vv[0], vv[1], vv[2], vv[3]);
+    s_v[2 * threadIdx.x + 1] = make_uint4(vv[4], vv[5], vv[6], vv[7]);
+    __syncthreads();
+    const uint32_t* lk = reinterpret_cast<const uint32_t*>(s_k);
+    const uint32_t* lv = reinterpret_cast<const uint32_t*>(s_v);
+    for (int e = threadIdx.x; e < kChunk; e += kSortThreads) {
+      const uint64_t q = cq + e;
+      if (q < M) {
+        p_key[q] = lk[e];
+        p_val[q] = lv[e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Per-view 2D inclusive prefix of the coverage difference grid: the number of
+// pair rects covering each tile, i.e. the tile's incidence count.  One block
+// per view (rows, then columns).
+__global__ __launch_bounds__(kSortThreads) void k_tile_counts(ViewTable vt, int32_t* __restrict__ cover) {
+  const ViewGeom& g = vt.v[blockIdx.x];
+  int32_t* cg = cover + g.grid_off;
+  const int gw = g.TX + 1, gh = g.TY + 1;
+  for (int y = threadIdx.x; y < gh; y += kSortThreads) {
+    int32_t acc = 0;
+    for (int x = 0; x < gw; ++x) {
+      acc += cg[y * gw + x];
+      cg[y * gw + x] = acc;
+    }
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < gw; x += kSortThreads) {
+    int32_t acc = 0;
+    for (int y = 0; y < gh; ++y) {
+      acc += cg[y * gw + x];
+      cg[y * gw + x] = acc;
+    }
+  }
+}
+
+// ranges[t] = [start, start + count) with start the exclusive prefix of the
+// tile counts in global tile order, (0,0) for an empty tile.  One block.
+__global__ __launch_bounds__(kScanThreads) void k_ranges_from_counts(ViewTable vt, const int32_t* __restrict__ cover,
+                                                                      const uint32_t* __restrict__ d_m,
+                                                                      uint32_t* __restrict__ ranges) {
+  __shared__ uint64_t s_w[kScanThreads / 64];
+  if (*d_m == 0) {  // no pairs, or the pair capacity overflowed
+    for (int t = threadIdx.x; t < vt.total_tiles; t += kScanThreads) ranges[2 * t] = ranges[2 * t + 1] = 0;
+    return;
+  }
+  uint64_t carry = 0;
+  int v = 0;
+  for (int base = 0; base < vt.total_tiles; base += kScanThreads) {
+    const int t = base + threadIdx.x;
+    uint32_t cnt = 0;
+    if (t < vt.total_tiles) {
+      while (v + 1 < vt.n_views && vt.v[v + 1].tile_off <= t) ++v;
+      const ViewGeom& g = vt.v[v];
+      const int lt = t - g.tile_off, ty = lt / g.TX, tx = lt - ty * g.TX;
+      cnt = (uint32_t)cover[g.grid_off + ty * (g.TX + 1) + tx];
+    }
+    uint64_t tot;
+    const uint64_t ex = carry + block_exclusive_scan<uint64_t, kScanThreads>(cnt, s_w, tot);
+    if (t < vt.total_tiles) {
+      ranges[2 * t] = cnt ? (uint32_t)ex : 0u;
+      ranges[2 * t + 1] = cnt ? (uint32_t)(ex + cnt) : 0u;
+    }
+    carry += tot;
   }
 }
 
@@ -272,19 +504,6 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t va
     p[i] = value;
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ tkey, const uint32_t* __restrict__ ids,
-                         const float* __restrict__ rec, const uint32_t* __restrict__ d_m, uint32_t total_tiles,
-                         uint32_t* __restrict__ ranges, uint64_t* __restrict__ keys64) {
-  const uint32_t m = *d_m;
-  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
-    const uint32_t t = tkey[p];
-    if (t >= total_tiles) continue;
-    if (p == 0 || tkey[p - 1] != t) ranges[2 * (size_t)t] = p;
-    if (p + 1 == m || tkey[p + 1] != t) ranges[2 * (size_t)t + 1] = p + 1;
-    if (keys64) keys64[p] = ((uint64_t)t << 32) | depth_key(rec, ids[p]);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Workspace layout.
 // ---------------------------------------------------------------------------
@@ -293,18 +512,22 @@ struct SortPlan {
   uint64_t cap;      // pair capacity
   int nb_vn;         // blocks over V*N / K entries
   int nb_m;          // blocks over pair entries
+  int n_steps;       // kStep-entry steps over V*N
+  int grid_steps;    // blocks striding over the steps
   int tile_passes;   // 8-bit tile digits
-  size_t off_counters, off_part_a, off_part_b, off_hist, off_dtot;
+  size_t off_counters, off_part_a, off_steps, off_hist, off_dtot, off_eoff, off_ebase, off_etxw, off_chunks, off_cover;
   size_t off_akey, off_aval, off_bkey, off_bval, off_pkey0, off_pkey1, off_pval;
   size_t bytes;
 };
 
-static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64_t capacity) {
+static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64_t total_grid, int64_t capacity) {
   SortPlan p;
   p.vn = (uint64_t)n * (uint64_t)n_views;
   p.cap = (uint64_t)capacity;
-  p.nb_vn = (int)std::min<uint64_t>(1024, std::max<uint64_t>(1, (p.vn + 4095) / 4096));
-  p.nb_m = (int)std::min<uint64_t>(2048, std::max<uint64_t>(1, (p.cap + 8191) / 8192));
+  p.nb_vn = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.vn + 1023) / 1024));
+  p.nb_m = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.cap + 2047) / 2048));
+  p.n_steps = (int)((p.vn + kStep - 1) / kStep);
+  p.grid_steps = std::min(p.n_steps, 8192);
   int bits = 1;
   while ((int64_t(1) << bits) < total_tiles) ++bits;
   p.tile_passes = (bits + kRadixBits - 1) / kRadixBits;
@@ -316,7 +539,12 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   };
   p.off_counters = take(64);
   p.off_part_a = take(sizeof(uint64_t) * p.nb_vn);
-  p.off_part_b = take(sizeof(uint64_t) * p.nb_vn);
+  p.off_steps = take(sizeof(uint64_t) * p.n_steps);
+  p.off_eoff = take(sizeof(uint64_t) * p.vn);
+  p.off_ebase = take(sizeof(uint32_t) * p.vn);
+  p.off_etxw = take(sizeof(uint32_t) * p.vn);
+  p.off_chunks = take(sizeof(uint32_t) * (p.cap / kChunk + 2));
+  p.off_cover = take(sizeof(int32_t) * (size_t)total_grid);
   p.off_hist = take(sizeof(uint32_t) * kRadixBins * std::max(p.nb_vn, p.nb_m));
   p.off_dtot = take(sizeof(uint32_t) * kRadixBins);
   p.off_akey = take(sizeof(uint32_t) * p.vn);
@@ -331,11 +559,12 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
 }
 
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                       const uint32_t* d_count, int shift, int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st) {
+                       const uint32_t* d_count, int shift, int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st,
+                       uint64_t* keys64 = nullptr, const float* rec = nullptr) {
   hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, kin, d_count, shift, nb, hist);
   hipLaunchKernelGGL(k_radix_scan_digit, dim3(kRadixBins), dim3(kSortThreads), 0, st, hist, nb, dtot);
   hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, d_count, shift, nb,
-                     hist, dtot);
+                     hist, dtot, keys64, rec);
 }
 
 }  // namespace gs
@@ -350,7 +579,7 @@ extern "C" gs_status gs_bin_sort_workspace_size(int64_t n, const gs_camera* cams
   if (n < 1 || pair_capacity < 0) return fail(GS_ERR_INVALID_VALUE, "need n >= 1 and pair_capacity >= 0");
   if (pair_capacity >= (int64_t(1) << 32) - 1) return fail(GS_ERR_INVALID_VALUE, "pair_capacity must be < 2^32 - 1");
   const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
-  *bytes = make_plan(n, n_views, vt.total_tiles, pair_capacity).bytes;
+  *bytes = make_plan(n, n_views, vt.total_tiles, vt.total_grid, pair_capacity).bytes;
   return GS_OK;
 }
 
@@ -368,7 +597,7 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   if (bins->capacity < 0 || bins->capacity >= (int64_t(1) << 32) - 1)
     return fail(GS_ERR_INVALID_VALUE, "bins->capacity must be in [0, 2^32 - 1)");
   const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
-  const SortPlan p = make_plan(n, n_views, vt.total_tiles, bins->capacity);
+  const SortPlan p = make_plan(n, n_views, vt.total_tiles, vt.total_grid, bins->capacity);
   if (!workspace || workspace_bytes < p.bytes)
     return fail(GS_ERR_CAPACITY, "workspace too small: need " + std::to_string(p.bytes) + " bytes");
   hipStream_t st = as_stream(stream);
@@ -377,7 +606,12 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   uint32_t* d_k = reinterpret_cast<uint32_t*>(counters + 0);        // visible pair count
   uint32_t* d_m = reinterpret_cast<uint32_t*>(counters + 1);        // min(M, capacity)
   uint64_t* part_a = reinterpret_cast<uint64_t*>(ws + p.off_part_a);
-  uint64_t* part_b = reinterpret_cast<uint64_t*>(ws + p.off_part_b);
+  uint64_t* step_off = reinterpret_cast<uint64_t*>(ws + p.off_steps);
+  uint64_t* ent_off = reinterpret_cast<uint64_t*>(ws + p.off_eoff);
+  uint32_t* ent_base = reinterpret_cast<uint32_t*>(ws + p.off_ebase);
+  uint32_t* ent_txw = reinterpret_cast<uint32_t*>(ws + p.off_etxw);
+  uint32_t* chunk_start = reinterpret_cast<uint32_t*>(ws + p.off_chunks);
+  int32_t* cover = reinterpret_cast<int32_t*>(ws + p.off_cover);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
   uint32_t* dtot = reinterpret_cast<uint32_t*>(ws + p.off_dtot);
   uint32_t* akey = reinterpret_cast<uint32_t*>(ws + p.off_akey);
@@ -400,10 +634,10 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   radix_pass(akey, aval, bkey, bval, d_k, 16, p.nb_vn, hist, dtot, st);
   radix_pass(bkey, bval, akey, aval, d_k, 24, p.nb_vn, hist, dtot, st);
   // 3. incidence count M, overflow check, emission in depth order
-  hipLaunchKernelGGL(k_count_pairs, dim3(p.nb_vn), dim3(kSortThreads), 0, st, proj->tiles_touched, aval, d_k,
-                     p.nb_vn, part_b);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kSortThreads), 0, st, part_b, p.nb_vn, (uint64_t*)nullptr, d_m,
-                     p.cap, bins->d_num_pairs, bins->d_overflow, p.cap);
+  hipLaunchKernelGGL(k_step_pair_counts, dim3(p.grid_steps), dim3(kSortThreads), 0, st, proj->tiles_touched, aval,
+                     d_k, step_off);
+  hipLaunchKernelGGL(k_scan_steps, dim3(1), dim3(kScanThreads), 0, st, step_off, d_k, d_m, bins->d_num_pairs,
+                     bins->d_overflow, p.cap);
   // the last tile pass must land its values in bins->ids
   uint32_t* vbuf[2];
   if (p.tile_passes % 2 == 1) {
@@ -413,18 +647,22 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
     vbuf[0] = bins->ids;
     vbuf[1] = pval_ws;
   }
-  hipLaunchKernelGGL(k_emit_pairs, dim3(p.nb_vn), dim3(kSortThreads), 0, st, proj->tiles_touched, aval, proj->rec,
-                     d_k, p.nb_vn, part_b, vt, (uint32_t)n, p.cap, pkey[0], vbuf[0]);
-  // 4. tile digits
-  for (int k = 0; k < p.tile_passes; ++k)
-    radix_pass(pkey[k % 2], vbuf[k % 2], pkey[(k + 1) % 2], vbuf[(k + 1) % 2], d_m, kRadixBits * k, p.nb_m, hist,
-               dtot, st);
-  // 5. ranges (and the optional 64-bit keys)
-  const uint64_t rcount = 2 * (uint64_t)vt.total_tiles;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>(4096, (rcount + 255) / 256)), dim3(256), 0, st,
-                     bins->ranges, rcount, 0u);
-  const unsigned rg = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(8192, (p.cap + 255) / 256));
-  hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(256), 0, st, pkey[p.tile_passes % 2], bins->ids, proj->rec, d_m,
-                     (uint32_t)vt.total_tiles, bins->ranges, bins->keys);
+  const uint64_t gcount = (uint64_t)vt.total_grid;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>(4096, (gcount + 255) / 256)), dim3(256), 0, st,
+                     reinterpret_cast<uint32_t*>(cover), gcount, 0u);
+  hipLaunchKernelGGL(k_entry_offsets, dim3(p.grid_steps), dim3(kSortThreads), 0, st, proj->tiles_touched, aval,
+                     proj->rec, d_k, step_off, vt, (uint32_t)n, p.cap, ent_off, ent_base, ent_txw, chunk_start, cover);
+  const unsigned emit_grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(16384, (p.cap + kChunk - 1) / kChunk));
+  hipLaunchKernelGGL(k_emit_chunks, dim3(emit_grid), dim3(kSortThreads), 0, st, aval, d_k, d_m, ent_off, ent_base,
+                     ent_txw, chunk_start, pkey[0], vbuf[0]);
+  // 4. tile ranges from the per-tile incidence counts (rect coverage)
+  hipLaunchKernelGGL(k_tile_counts, dim3(n_views), dim3(kSortThreads), 0, st, vt, cover);
+  hipLaunchKernelGGL(k_ranges_from_counts, dim3(1), dim3(kScanThreads), 0, st, vt, cover, d_m, bins->ranges);
+  // 5. tile digits; the last pass writes only the ids (and the optional 64-bit keys)
+  for (int k = 0; k < p.tile_passes; ++k) {
+    const bool last = k + 1 == p.tile_passes;
+    radix_pass(pkey[k % 2], vbuf[k % 2], last ? nullptr : pkey[(k + 1) % 2], vbuf[(k + 1) % 2], d_m, kRadixBits * k,
+               p.nb_m, hist, dtot, st, last ? bins->keys : nullptr, proj->rec);
+  }
   return check_launch("bin/sort");
 }

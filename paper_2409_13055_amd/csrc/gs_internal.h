@@ -17,12 +17,14 @@ constexpr int kWave = 64;
 struct ViewGeom {
   int32_t W, H, TX, TY;
   int32_t tile_off, pix_off;
+  int32_t grid_off;  // offset of the view's (TX+1)x(TY+1) tile-coverage grid
 };
 struct ViewTable {
   int32_t n_views;
   int32_t total_tiles;
   int32_t total_pixels;
   int32_t tile;
+  int32_t total_grid;
   ViewGeom v[GS_MAX_VIEWS];
 };
 

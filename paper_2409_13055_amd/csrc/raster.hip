@@ -26,6 +26,7 @@ gs_status launch_project_bwd(const gs_params* params, const gs_camera* cams, int
 struct RasterConsts {
   float alpha_min, alpha_max, t_min;
   float bg0, bg1, bg2;
+  float radius_sigmas;
 };
 
 // power = -(a dx^2 + c dy^2)/2 - b dx dy, with one fixed rounding sequence so
@@ -99,10 +100,69 @@ struct PixMap {
   __device__ int chan(int p, int c) const { return 3 * pix_off + c * W * H + (y0 + p) * W + x; }
 };
 
-struct SplatLds {
-  float4 a;  // mx, my, ca, cb
-  float4 b;  // cc, opacity, r, g
-  float c;   // b
+// Tile-level cull bound of a splat: the squared distance from its mean beyond
+// which opacity * exp(-q/2) < alpha_min * (1 - 1e-3), using
+// q = d^T Q d >= lambda_min(Q) |d|^2 for the conic Q = [[a,b],[b,c]] the
+// pixels are evaluated with.  lambda_min(Q) = det(Q) / lambda_max(Q), with
+// det(Q) formed in double (products of FP32 values are exact there), so the
+// bound holds for the FP32 conic however elongated the splat.  If no pixel of
+// a tile is that close, every pixel of the tile would skip the splat
+// (alpha < alpha_min), so the whole tile skips it with one wave-uniform test;
+// the margins keep that decision identical to the per-pixel FP32 one.
+// Negative: the splat can never reach alpha_min.
+__device__ __forceinline__ float cull_threshold(float ca, float cb, float cc, float opacity, float alpha_min) {
+  const float amin = alpha_min * 0.999f;
+  if (!(opacity >= amin)) return -1.0f;
+  const double det = (double)ca * (double)cc - (double)cb * (double)cb;
+  const float h = 0.5f * (ca - cc);
+  const float lmax = 0.5f * (ca + cc) + sqrtf(h * h + cb * cb);
+  if (!(det > 0.0) || !(lmax > 0.0f)) return 3.0e38f;  // no usable bound: never cull
+  const float lmin = (float)(det / (double)lmax) * 0.999f;
+  return 2.0f * __logf(opacity / amin) / lmin;
+}
+
+// One splat record staged through registers (prefetch) into LDS.
+struct SplatLoader {
+  float4 a, b, c;  // record words 0-3, 4-7, 8-11
+  uint32_t id;
+  bool valid;
+  __device__ __forceinline__ void fetch(const float* __restrict__ rec, const uint32_t* __restrict__ ids, int idx,
+                                        int lo, int hi) {
+    valid = idx >= lo && idx < hi;
+    if (valid) {
+      id = ids[idx];
+      const float4* r = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS);
+      a = r[0];
+      b = r[1];
+      c = r[2];
+    }
+  }
+  __device__ __forceinline__ void store(float4* s_a, float4* s_b, float2* s_c, uint32_t* s_id, int slot,
+                                        const RasterConsts& rc) const {
+    if (!valid) return;
+    s_a[slot] = a;
+    s_b[slot] = b;
+    s_c[slot] = make_float2(c.x, cull_threshold(a.z, a.w, b.x, b.y, rc.alpha_min));
+    if (s_id) s_id[slot] = id;
+  }
+};
+
+// Pixel rectangle of the tile (pixel centres), for the tile-level cull.
+struct TileBox {
+  float x_lo, x_hi, y_lo, y_hi;
+  template <class PM>
+  __device__ TileBox(const PM& pm, int tile) {
+    const int tx0 = (pm.x / tile) * tile, ty0 = ((pm.y0 - (pm.y0 % tile)) / tile) * tile;
+    x_lo = (float)tx0;
+    x_hi = (float)(min(tx0 + tile, pm.W) - 1);
+    y_lo = (float)ty0;
+    y_hi = (float)(min(ty0 + tile, pm.H) - 1);
+  }
+  __device__ __forceinline__ bool culled(float mx, float my, float thr) const {
+    const float dx = fmaxf(fmaxf(x_lo - mx, mx - x_hi), 0.0f);
+    const float dy = fmaxf(fmaxf(y_lo - my, my - y_hi), 0.0f);
+    return dx * dx + dy * dy > thr;
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -117,9 +177,10 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
   constexpr int PPL = PM::PPL, NT = PM::NT;
   __shared__ float4 s_a[NT];
   __shared__ float4 s_b[NT];
-  __shared__ float s_c[NT];
+  __shared__ float2 s_c[NT];
   __shared__ float s_loss[PM::WAVES];
   const PM pm(vt, blockIdx.x);
+  const TileBox box(pm, TILE);
   float T[PPL], C[PPL][3];
   int last[PPL];
   bool done[PPL];
@@ -133,24 +194,22 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
   const uint2 rg = ranges[blockIdx.x];
   const int s = (int)rg.x, e = (int)rg.y;
   const float fx = (float)pm.x;
+  SplatLoader ld;
+  ld.fetch(rec, ids, s + (int)threadIdx.x, s, e);
   for (int base = s; base < e; base += NT) {
     int alive = 0;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
     if (__syncthreads_count(alive) == 0) break;
-    const int idx = base + (int)threadIdx.x;
-    if (idx < e) {
-      const float4* r = reinterpret_cast<const float4*>(rec + (size_t)ids[idx] * GS_REC_FLOATS);
-      s_a[threadIdx.x] = r[0];
-      s_b[threadIdx.x] = r[1];
-      s_c[threadIdx.x] = r[2].x;
-    }
+    ld.store(s_a, s_b, s_c, nullptr, threadIdx.x, rc);
     __syncthreads();
+    ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);  // next batch, in flight during this one
     const int cnt = min(NT, e - base);
     for (int j = 0; j < cnt; ++j) {
       const float4 A = s_a[j];
+      const float2 Cc = s_c[j];
+      if (box.culled(A.x, A.y, Cc.y)) continue;
       const float4 Bv = s_b[j];
-      const float cbl = s_c[j];
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         if (done[p]) continue;
@@ -168,7 +227,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
         const float wgt = alpha * T[p];
         C[p][0] += Bv.z * wgt;
         C[p][1] += Bv.w * wgt;
-        C[p][2] += cbl * wgt;
+        C[p][2] += Cc.x * wgt;
         T[p] = test;
         last[p] = base - s + j + 1;
       }
@@ -228,16 +287,18 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
   constexpr int PPL = PM::PPL, NT = PM::NT;
   __shared__ float4 s_a[NT];
   __shared__ float4 s_b[NT];
-  __shared__ float s_c[NT];
+  __shared__ float2 s_c[NT];
   __shared__ uint32_t s_id[NT];
   __shared__ int s_max[PM::WAVES];
   const PM pm(vt, blockIdx.x);
+  const TileBox box(pm, TILE);
   const uint2 rg = ranges[blockIdx.x];
   const int s = (int)rg.x, e = (int)rg.y;
   const float fx = (float)pm.x;
   const int lane = threadIdx.x & 63;
   float T[PPL], dl[PPL][3], S[PPL][3];
   int last[PPL];
+  SplatLoader ld;
 
   if (CKPT) {
     // Forward replay: final transmittance and contributor count only.
@@ -248,21 +309,19 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
       last[p] = 0;
       done[p] = !pm.inside(p);
     }
+    ld.fetch(rec, ids, s + (int)threadIdx.x, s, e);
     for (int base = s; base < e; base += NT) {
       int alive = 0;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
       if (__syncthreads_count(alive) == 0) break;
-      const int idx = base + (int)threadIdx.x;
-      if (idx < e) {
-        const float4* r = reinterpret_cast<const float4*>(rec + (size_t)ids[idx] * GS_REC_FLOATS);
-        s_a[threadIdx.x] = r[0];
-        s_b[threadIdx.x] = r[1];
-      }
+      ld.store(s_a, s_b, s_c, nullptr, threadIdx.x, rc);
       __syncthreads();
+      ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);
       const int cnt = min(NT, e - base);
       for (int j = 0; j < cnt; ++j) {
         const float4 A = s_a[j];
+        if (box.culled(A.x, A.y, s_c[j].y)) continue;
         const float4 Bv = s_b[j];
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
@@ -323,23 +382,25 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
 #pragma unroll
   for (int w = 0; w < PM::WAVES; ++w) max_last = max(max_last, s_max[w]);
 
-  for (int hi = max_last; hi > 0; hi -= NT) {
+  // Back to front over [s, s + max_last) in batches of NT, prefetching the
+  // batch in front of the current one.
+  int hi = max_last;
+  ld.fetch(rec, ids, s + max(0, hi - NT) + (int)threadIdx.x, s + max(0, hi - NT), s + hi);
+  for (; hi > 0; hi -= NT) {
     const int lo = max(0, hi - NT);
-    const int idx = s + lo + (int)threadIdx.x;
-    if (idx < s + hi) {
-      const uint32_t id = ids[idx];
-      const float4* r = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS);
-      s_a[threadIdx.x] = r[0];
-      s_b[threadIdx.x] = r[1];
-      s_c[threadIdx.x] = r[2].x;
-      s_id[threadIdx.x] = id;
-    }
+    ld.store(s_a, s_b, s_c, s_id, threadIdx.x, rc);
     __syncthreads();
+    {
+      const int nlo = max(0, lo - NT);
+      ld.fetch(rec, ids, s + nlo + (int)threadIdx.x, s + nlo, s + lo);
+    }
     for (int k = hi - 1; k >= lo; --k) {
       const int j = k - lo;
       const float4 A = s_a[j];
+      const float2 Cc = s_c[j];
+      if (box.culled(A.x, A.y, Cc.y)) continue;
       const float4 Bv = s_b[j];
-      const float cbl = s_c[j];
+      const float cbl = Cc.x;
       float g[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) g[c] = 0.0f;
@@ -396,7 +457,7 @@ __global__ void k_fill_f32(float* __restrict__ p, uint64_t count) {
 }
 
 static RasterConsts consts_of(const gs_options* o) {
-  return RasterConsts{o->alpha_min, o->alpha_max, o->t_min, o->bg[0], o->bg[1], o->bg[2]};
+  return RasterConsts{o->alpha_min, o->alpha_max, o->t_min, o->bg[0], o->bg[1], o->bg[2], o->radius_sigmas};
 }
 
 static gs_status validate_raster_common(const gs_projected* proj, const gs_bins* bins, const gs_camera* cams,
