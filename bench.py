@@ -22,7 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
-VALU_PEAK_TOPS = 39.32       # 256 CU * 64 lanes * 2.4 GHz, unpacked FP32 lane-ops/s (x1e12)
+# FP32 vector peak without packed-FP32 instructions (the build disables them):
+# 256 CU * 4 SIMD * 16 lanes * 2 flop (FMA) * 2.4 GHz = 78.6 TFLOP/s (157.3 with packed FP32).
+VALU_PEAK_TFLOPS = 78.64
 
 
 def log(*a):
@@ -41,6 +43,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many eager batched steps (for rocprofv3) and exit")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="with --profile-steps: also copy a buffer of this many bytes (a plain copy kernel of "
+                         "known size, to calibrate hardware byte counters)")
     return ap.parse_args()
 
 
@@ -81,6 +86,13 @@ def main():
         for _ in range(args.profile_steps):
             step.run()
         torch.cuda.synchronize()
+        if args.copy_probe > 0:
+            src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"[bench] copy probe: {args.copy_probe} bytes")
         log("[bench] profile steps done")
         return
 
@@ -158,13 +170,17 @@ def main():
 
 
 def stage_breakdown(step, iters):
-    """Average duration of each hot-path call of the batched step (eager launches)."""
+    """Average duration of each hot-path call of the batched step (eager launches, HIP events on
+    the stream the kernels are launched on)."""
     import torch
     r, fr, p = step.rast, step.frame, step.params
+    g2 = torch.zeros(r.n_views * r.n * 9, dtype=torch.float32, device=p.means.device)
     calls = {
         "project": lambda: r.project(p, fr),
         "bin_sort": lambda: r.bin_sort(fr),
         "render_fwd": lambda: r.render_fwd(fr, step.target, step.loss),
+        "raster_bwd": lambda: r.raster_bwd(fr, g2, target=step.target),
+        "project_bwd": lambda: r.project_bwd(p, fr, g2, step.grads),
         "render_bwd": lambda: r.render_bwd(p, fr, step.grads, target=step.target),
     }
     if step.adam is not None:
@@ -180,39 +196,49 @@ def stage_breakdown(step, iters):
         ev[1].record()
         torch.cuda.synchronize()
         out[name] = round(ev[0].elapsed_time(ev[1]) / iters, 4)
+    for t in step.grads.tensors():  # the timing launches accumulated into the gradients
+        t.zero_()
     return out
 
 
+def traffic_of(kernel, tile, checkpoint, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, when it was
+    taken on the current kernel source (None otherwise)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_2409_13055_amd", "csrc", rec.get("source", "raster.hip"))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    key = f"{kernel}/{workload}/tile{tile}/ckpt{int(checkpoint)}"
+    e = rec.get("entries", {}).get(key)
+    if not e or e.get("source_sha") != sha:
+        return None
+    return e.get("bytes_per_launch")
+
+
 def roofline(step, sc, stages):
-    """Roofline entry for the dominant call (by measured duration)."""
+    """Roofline entry for the dominant single-kernel call (by measured duration)."""
     from paper_2409_13055_amd import roofline as RF
-    return RF.report(step, sc, stages, hbm_peak_gbs=HBM_PEAK_GBS, valu_peak_tops=VALU_PEAK_TOPS)
-
-
-def crop_camera(c, x0, y0, w, h):
-    """The pixels [x0, x0+w) x [y0, y0+h) of camera c as a camera of their own."""
-    from paper_2409_13055_amd import synthetic as S
-    return S.Camera(c.R, c.t, c.fx, c.fy, c.cx - x0, c.cy - y0, w, h)
+    tr = traffic_of("raster_bwd", step.rast.opts.tile_size, sc.checkpoint, sc.name)
+    return RF.report(step, sc, stages, hbm_peak_gbs=HBM_PEAK_GBS, valu_peak_tflops=VALU_PEAK_TFLOPS, traffic=tr)
 
 
 def cpu_baseline(sc, tile):
-    """The FP64 oracle timed on the host cores over a bounded sample of the workload: the central
-    crop (at most half the width and height) of the first keyframe, rendered from all Gaussians
-    (projection, binning, blending, L1, backward), plus Adam over all parameters when the workload
-    steps the optimiser."""
+    """The FP64 oracle timed on the host cores over a bounded sample of the workload: its first
+    keyframe (the first two for multi-keyframe workloads) rendered from all Gaussians (projection,
+    binning, blending, L1, backward), plus Adam over all parameters when the workload steps the
+    optimiser."""
     import oracle.oracle as O
     n_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    c = sc.cameras[0]
-    w, h = c.width, c.height
-    if w * h > 200_000:
-        w, h = w // 2, h // 2
-    x0, y0 = (c.width - w) // 2, (c.height - h) // 2
-    cam = crop_camera(c, x0, y0, w, h)
-    tgt = sc.targets[0][:, y0:y0 + h, x0:x0 + w]
+    k = 1 if sc.n_views == 1 else 2
+    cams, tgts = sc.cameras[:k], sc.targets[:k]
     P = O.Params.from_scene(sc)
     opts = O.Options(tile=tile)
     t0 = time.time()
-    fb = O.forward_backward_l1(P, [cam], [tgt], opts)
+    fb = O.forward_backward_l1(P, cams, tgts, opts)
     if "adam" in sc.work:
         lrs = sc.lrs
         for name, lr in (("means", lrs["means"]), ("log_scales", lrs["log_scales"]), ("quats", lrs["quats"]),
@@ -221,8 +247,9 @@ def cpu_baseline(sc, tile):
             z = np.zeros_like(p)
             O.adam_step(p, fb["grads"][name], z, z, 1, lr)
     dt = time.time() - t0
-    return {"value": round(w * h * 1e-6 / dt, 4), "unit": "Mpix*iter/s", "cores": n_threads, "kind": "oracle",
-            "sample": f"central {w}x{h} crop of keyframe 0 of {sc.n_views}, all {sc.n} Gaussians, fwd+L1+bwd"
+    px = sum(c.width * c.height for c in cams)
+    return {"value": round(px * 1e-6 / dt, 4), "unit": "Mpix*iter/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"{k} of {sc.n_views} keyframes ({px} px) rendered from all {sc.n} Gaussians, fwd+L1+bwd"
                       + ("+Adam on all parameters" if "adam" in sc.work else "") + f", FP64, {dt:.1f}s"}
 
 

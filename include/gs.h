@@ -258,6 +258,34 @@ gs_status gs_render_bwd(const gs_params* params, const gs_projected* proj, const
                         const gs_loss* loss, const gs_grads* grads, void* workspace, size_t workspace_bytes,
                         void* stream);
 
+/* The two stages of gs_render_bwd, for callers that hold image-space
+ * gradients of their own or time the stages separately.
+ *
+ * gs_raster_bwd: backward of the blending only (Sec. II / III-B): ADDS, for
+ * every (view, Gaussian) pair, d(loss)/d(mean_x, mean_y, conic a, b, c,
+ * opacity, r, g, b) into grad2d ([n_views*n][9] FP32, device; the caller
+ * clears it).  Loss, image and checkpoint semantics as gs_render_bwd.
+ *
+ * gs_project_bwd: backward of the projection: chains grad2d (same layout)
+ * through gs_project's mapping to the raw parameters and ADDS the result into
+ * `grads`, summed over views.  `proj` must hold the records gs_project wrote
+ * for these parameters and cameras (radius 0 pairs are skipped). */
+gs_status gs_raster_bwd(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_image* img,
+                        const gs_camera* cams, int32_t n_views, const gs_options* opts, const gs_loss* loss,
+                        float* grad2d, void* stream);
+gs_status gs_project_bwd(const gs_params* params, const gs_projected* proj, const gs_camera* cams, int32_t n_views,
+                         const gs_options* opts, const float* grad2d, const gs_grads* grads, void* stream);
+
+/* Work counts of the blending as defined per pixel (Sec. II), for roofline
+ * accounting: d_counts (device int64[3], overwritten) receives, summed over
+ * all pixels of all views, [0] the list entries whose alpha is evaluated
+ * until the pixel stops (its list end, or the entry that would take T below
+ * t_min, inclusive), [1] the (pixel, Gaussian) pairs blended, [2] the
+ * contributor counts n_contrib.  Reads the same inputs as gs_render_fwd and
+ * writes nothing else. */
+gs_status gs_render_stats(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
+                          int32_t n_views, const gs_options* opts, int64_t* d_counts, void* stream);
+
 /* One Adam step over up to GS_MAX_ADAM_GROUPS parameter groups in a single
  * launch (gradient descent of Sec. III-B with the default 3DGS optimiser of
  * Sec. IV-A): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;

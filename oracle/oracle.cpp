@@ -340,6 +340,9 @@ void trace_pixel(double px, double py, const uint32_t* list, int64_t len, const 
   tr.n_contrib = 0;
   tr.flags = 0;
   tr.stop_k = -1;
+  // Relative uncertainty of an FP32 evaluation of T so far (for the flags).
+  double t_rel = 0.0;
+  const double u = std::ldexp(1.0, -24);  // FP32 unit roundoff
   for (int64_t k = 0; k < len; ++k) {
     const double* g = (list[k] == ov_id) ? ov_row : rec + (size_t)list[k] * R_STRIDE;
     const double dx = px - g[R_MX], dy = py - g[R_MY];
@@ -347,13 +350,21 @@ void trace_pixel(double px, double py, const uint32_t* list, int64_t len, const 
     if (power > 0) continue;
     const double G = std::exp(power);
     const double oG = g[R_OP] * G;
-    if (std::fabs(oG - o.alpha_max) <= 1e-5 * o.alpha_max) tr.flags |= P_NEAR_ALPHA_MAX;
+    // A decision counts as "near" its threshold when it lies within the
+    // rounding error an FP32 evaluation of the same expression can make:
+    // the quadratic form loses accuracy to cancellation in proportion to the
+    // magnitude of its terms (elongated splats), plus exp and the products.
+    const double terms = std::fabs(g[R_CA] * dx * dx) + std::fabs(g[R_CC] * dy * dy) + 2 * std::fabs(g[R_CB] * dx * dy);
+    const double a_rel = 1e-5 + 8 * u * terms + 2 * u * std::fabs(power);
+    if (std::fabs(oG - o.alpha_max) <= a_rel * o.alpha_max) tr.flags |= P_NEAR_ALPHA_MAX;
     const bool clamped = oG > o.alpha_max;
     const double alpha = clamped ? o.alpha_max : oG;
-    if (std::fabs(alpha - o.alpha_min) <= 1e-5 * o.alpha_min) tr.flags |= P_NEAR_ALPHA_MIN;
+    if (std::fabs(alpha - o.alpha_min) <= a_rel * o.alpha_min) tr.flags |= P_NEAR_ALPHA_MIN;
     if (alpha < o.alpha_min) continue;
     const double nextT = tr.T * (1.0 - alpha);
-    if (std::fabs(nextT - o.t_min) <= 1e-4 * o.t_min) tr.flags |= P_NEAR_T_MIN;
+    const double step_rel = (clamped ? 0.0 : a_rel * alpha / (1.0 - alpha)) + 2 * u;
+    if (std::fabs(nextT - o.t_min) <= (1e-4 + t_rel + step_rel) * o.t_min) tr.flags |= P_NEAR_T_MIN;
+    t_rel += step_rel;
     if (nextT < o.t_min) { tr.stop_k = (int)k; break; }
     for (int ch = 0; ch < 3; ++ch) tr.C[ch] += g[R_R + ch] * alpha * tr.T;
     if (keep) tr.acc.push_back({list[k], (int)k, alpha, G, tr.T, dx, dy, clamped});
@@ -633,18 +644,32 @@ int or_bin(int32_t n_views, int64_t n, const float* mean2d, const int32_t* radiu
   return 0;
 }
 
+int or_render_tiles(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
+                    const uint32_t* ids, const uint32_t* ranges, const int64_t* tiles, int64_t n_tiles, double* image,
+                    double* t_final, int32_t* n_contrib, uint32_t* pix_flags);
+
 // Forward render of all views from records [V*N][10] and sorted tile lists.
 // image is [sum_v 3*H_v*W_v] (view-major, planar channels), t_final and
 // n_contrib [sum_v H_v*W_v]; pix_flags marks near-threshold decisions.
 int or_render(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
               const uint32_t* ids, const uint32_t* ranges, double* image, double* t_final, int32_t* n_contrib,
               uint32_t* pix_flags) {
+  return or_render_tiles(n_views, n, cams, opt, rec, ids, ranges, nullptr, -1, image, t_final, n_contrib, pix_flags);
+}
+
+// As or_render, restricted to the listed global tiles (all tiles when `tiles`
+// is NULL); pixels of other tiles are left untouched.
+int or_render_tiles(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
+                    const uint32_t* ids, const uint32_t* ranges, const int64_t* tiles, int64_t n_tiles, double* image,
+                    double* t_final, int32_t* n_contrib, uint32_t* pix_flags) {
   (void)n;
   const std::vector<ViewInfo> views = make_views(cams, n_views, opt->tile);
   const int64_t T_tot = views.back().tile_off + (int64_t)views.back().grid.tx * views.back().grid.ty;
   const int B = opt->tile;
+  const int64_t count = tiles ? n_tiles : T_tot;
 #pragma omp parallel for schedule(dynamic, 4)
-  for (int64_t gt = 0; gt < T_tot; ++gt) {
+  for (int64_t ti = 0; ti < count; ++ti) {
+    const int64_t gt = tiles ? tiles[ti] : ti;
     const int v = view_of_tile(views, gt);
     const ViewInfo& vw = views[v];
     const int64_t lt = gt - vw.tile_off;
@@ -666,19 +691,26 @@ int or_render(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions*
   return 0;
 }
 
-// Backward of the blending: given dL/dimage (same layout as the image), the
-// 9 image-space gradients per (view, Gaussian) in grad2d [V*N][9], order
-// (mx, my, conic a, b, c, opacity, r, g, b).  Summation over pixels is in a
-// fixed order (tile by tile, pixel by pixel).
-int or_render_backward(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
-                       const uint32_t* ids, const uint32_t* ranges, int64_t n_pairs, const double* dl_dimage,
-                       double* grad2d) {
+// Backward of the blending restricted to the listed global tiles (all when
+// `tiles` is NULL): grad2d [V*N][9] receives the image-space gradients summed
+// over the pixels of those tiles only.
+int or_render_backward_tiles(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt,
+                             const double* rec, const uint32_t* ids, const uint32_t* ranges, const int64_t* tiles,
+                             int64_t n_tiles, const double* dl_dimage, double* grad2d) {
   const std::vector<ViewInfo> views = make_views(cams, n_views, opt->tile);
   const int64_t T_tot = views.back().tile_off + (int64_t)views.back().grid.tx * views.back().grid.ty;
   const int B = opt->tile;
-  std::vector<double> rows((size_t)n_pairs * 9, 0.0);
+  const int64_t count = tiles ? n_tiles : T_tot;
+  // per selected tile, one gradient row per list entry (summed over the tile's pixels)
+  std::vector<int64_t> row_off(count + 1, 0);
+  for (int64_t ti = 0; ti < count; ++ti) {
+    const int64_t gt = tiles ? tiles[ti] : ti;
+    row_off[ti + 1] = row_off[ti] + (int64_t)ranges[2 * gt + 1] - (int64_t)ranges[2 * gt];
+  }
+  std::vector<double> rows((size_t)row_off[count] * 9, 0.0);
 #pragma omp parallel for schedule(dynamic, 4)
-  for (int64_t gt = 0; gt < T_tot; ++gt) {
+  for (int64_t ti = 0; ti < count; ++ti) {
+    const int64_t gt = tiles ? tiles[ti] : ti;
     const int v = view_of_tile(views, gt);
     const ViewInfo& vw = views[v];
     const int64_t lt = gt - vw.tile_off;
@@ -691,13 +723,28 @@ int or_render_backward(int32_t n_views, int64_t n, const OrCamera* cams, const O
         trace_pixel(i, j, ids + s, (int64_t)e - s, rec, *opt, true, tr);
         double dl[3];
         for (int ch = 0; ch < 3; ++ch) dl[ch] = dl_dimage[3 * vw.pix_off + (int64_t)ch * W * H + (int64_t)j * W + i];
-        backward_pixel(tr, dl, rec, *opt, rows.data() + (size_t)s * 9);
+        backward_pixel(tr, dl, rec, *opt, rows.data() + (size_t)row_off[ti] * 9);
       }
   }
   std::memset(grad2d, 0, sizeof(double) * 9 * (size_t)n_views * n);
-  for (int64_t p = 0; p < n_pairs; ++p)
-    for (int c = 0; c < 9; ++c) grad2d[(size_t)ids[p] * 9 + c] += rows[(size_t)p * 9 + c];
+  for (int64_t ti = 0; ti < count; ++ti) {
+    const int64_t gt = tiles ? tiles[ti] : ti;
+    const uint32_t s = ranges[2 * gt];
+    for (int64_t k = 0; k < row_off[ti + 1] - row_off[ti]; ++k)
+      for (int c = 0; c < 9; ++c) grad2d[(size_t)ids[s + k] * 9 + c] += rows[(size_t)(row_off[ti] + k) * 9 + c];
+  }
   return 0;
+}
+
+// Backward of the blending: given dL/dimage (same layout as the image), the
+// 9 image-space gradients per (view, Gaussian) in grad2d [V*N][9], order
+// (mx, my, conic a, b, c, opacity, r, g, b).  Summation over pixels is in a
+// fixed order (tile by tile, pixel by pixel).
+int or_render_backward(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
+                       const uint32_t* ids, const uint32_t* ranges, int64_t n_pairs, const double* dl_dimage,
+                       double* grad2d) {
+  (void)n_pairs;
+  return or_render_backward_tiles(n_views, n, cams, opt, rec, ids, ranges, nullptr, -1, dl_dimage, grad2d);
 }
 
 // Chain image-space gradients [V*N][9] to the raw parameters, summed over
@@ -874,6 +921,35 @@ int or_fd_local(int64_t n, int32_t D, const double* means, const double* log_sca
       st = (sp == sm) ? attempt : 2;
     }
     status[si] = st;
+  }
+  return 0;
+}
+
+// Per-pixel work of the blending: list entries evaluated until the pixel
+// stops (list end, or the entry that would take T below t_min, inclusive)
+// and entries blended.  Same inputs as or_render; outputs [sum_v H_v*W_v].
+int or_pixel_counts(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
+                    const uint32_t* ids, const uint32_t* ranges, int64_t* evaluated, int64_t* blended) {
+  (void)n;
+  const std::vector<ViewInfo> views = make_views(cams, n_views, opt->tile);
+  const int64_t T_tot = views.back().tile_off + (int64_t)views.back().grid.tx * views.back().grid.ty;
+  const int B = opt->tile;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t gt = 0; gt < T_tot; ++gt) {
+    const int v = view_of_tile(views, gt);
+    const ViewInfo& vw = views[v];
+    const int64_t lt = gt - vw.tile_off;
+    const int tx = (int)(lt % vw.grid.tx), ty = (int)(lt / vw.grid.tx);
+    const uint32_t s = ranges[2 * gt], e = ranges[2 * gt + 1];
+    const int W = vw.cam.width, H = vw.cam.height;
+    PixelTrace tr;
+    for (int j = ty * B; j < std::min(H, (ty + 1) * B); ++j)
+      for (int i = tx * B; i < std::min(W, (tx + 1) * B); ++i) {
+        trace_pixel(i, j, ids + s, (int64_t)e - s, rec, *opt, true, tr);
+        const int64_t p = vw.pix_off + (int64_t)j * W + i;
+        evaluated[p] = tr.stop_k >= 0 ? tr.stop_k + 1 : (int64_t)e - s;
+        blended[p] = (int64_t)tr.acc.size();
+      }
   }
   return 0;
 }

@@ -84,13 +84,19 @@ def lib():
         _lib.or_bin.argtypes = [i32, i64, P, P, P, P, i32, i64, P, P, P, P]
         _lib.or_render.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P, P, P]
         _lib.or_render_backward.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, i64, P, P]
+        _lib.or_render_tiles.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, i64, P, P,
+                                         P, P]
+        _lib.or_render_backward_tiles.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P,
+                                                  i64, P, P]
         _lib.or_project_backward.argtypes = [i64, i32, P, P, P, P, P, C.POINTER(OrCamera), i32,
                                              C.POINTER(OrOptions), P, P, P, P, P, P]
         _lib.or_fd_local.argtypes = [i64, i32, P, P, P, P, P, C.POINTER(OrCamera), i32, C.POINTER(OrOptions), P, i64,
                                      P, P, C.c_double, P, P]
+        _lib.or_pixel_counts.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P]
         _lib.or_sh_basis.argtypes = [i32, i64, P, P, P]
         _lib.or_quat_to_rot.argtypes = [P, P]
-        for f in ("or_project", "or_bin", "or_render", "or_render_backward", "or_project_backward", "or_fd_local"):
+        for f in ("or_project", "or_bin", "or_render", "or_render_backward", "or_project_backward", "or_fd_local",
+                  "or_render_tiles", "or_render_backward_tiles"):
             getattr(_lib, f).restype = C.c_int
     return _lib
 
@@ -217,6 +223,57 @@ def render(cams, opts: Options, rec, ids, ranges):
                          _p(nc), _p(pf))
     assert rc == 0
     return dict(image=image, t_final=tf, n_contrib=nc, pix_flags=pf)
+
+
+def render_tiles(cams, opts: Options, rec, ids, ranges, tiles):
+    """or_render restricted to the global tiles listed; other pixels are NaN."""
+    n_views = len(cams)
+    rec = _d(rec)
+    n = rec.shape[0] // n_views
+    P = sum(c.width * c.height for c in cams)
+    image = np.full(3 * P, np.nan)
+    tf = np.full(P, np.nan)
+    nc = np.full(P, -1, np.int32)
+    pf = np.zeros(P, np.uint32)
+    t = np.ascontiguousarray(tiles, np.int64)
+    ids = np.ascontiguousarray(ids, np.uint32)
+    ranges = np.ascontiguousarray(ranges, np.uint32)
+    oc = opts.as_c()
+    rc = lib().or_render_tiles(n_views, n, cameras_c(cams), C.byref(oc), _p(rec), _p(ids), _p(ranges), _p(t),
+                               t.shape[0], _p(image), _p(tf), _p(nc), _p(pf))
+    assert rc == 0
+    return dict(image=image, t_final=tf, n_contrib=nc, pix_flags=pf)
+
+
+def render_backward_tiles(cams, opts: Options, rec, ids, ranges, tiles, dl_dimage):
+    """Image-space gradients summed over the pixels of the listed tiles only."""
+    n_views = len(cams)
+    rec = _d(rec)
+    n = rec.shape[0] // n_views
+    g2 = np.zeros((n_views * n, 9))
+    t = np.ascontiguousarray(tiles, np.int64)
+    oc = opts.as_c()
+    rc = lib().or_render_backward_tiles(n_views, n, cameras_c(cams), C.byref(oc), _p(rec),
+                                        _p(np.ascontiguousarray(ids, np.uint32)),
+                                        _p(np.ascontiguousarray(ranges, np.uint32)), _p(t), t.shape[0],
+                                        _p(_d(dl_dimage)), _p(g2))
+    assert rc == 0
+    return g2
+
+
+def pixel_counts(cams, opts: Options, rec, ids, ranges):
+    """Per pixel: list entries evaluated until the pixel stops, and entries blended."""
+    n_views = len(cams)
+    rec = _d(rec)
+    n = rec.shape[0] // n_views
+    P = sum(c.width * c.height for c in cams)
+    ev = np.zeros(P, np.int64)
+    bl = np.zeros(P, np.int64)
+    oc = opts.as_c()
+    lib().or_pixel_counts(n_views, n, cameras_c(cams), C.byref(oc), _p(rec),
+                          _p(np.ascontiguousarray(ids, np.uint32)), _p(np.ascontiguousarray(ranges, np.uint32)),
+                          _p(ev), _p(bl))
+    return ev, bl
 
 
 def split_views(flat, cams, channels=3):

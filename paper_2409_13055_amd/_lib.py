@@ -76,7 +76,7 @@ class gs_adam_group(C.Structure):
 EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_options", "gs_total_tiles",
            "gs_total_pixels", "gs_bin_sort_workspace_size", "gs_render_fwd_workspace_size",
            "gs_render_bwd_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
-           "gs_adam_step")
+           "gs_raster_bwd", "gs_project_bwd", "gs_render_stats", "gs_adam_step")
 
 _lib = None
 
@@ -108,6 +108,10 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(gs_loss), C.POINTER(gs_image), P, sz, P]),
         "gs_render_bwd": (C.c_int, [pp, C.POINTER(gs_projected), C.POINTER(gs_bins), C.POINTER(gs_image), pc, i32,
                                     po, C.POINTER(gs_loss), C.POINTER(gs_grads), P, sz, P]),
+        "gs_raster_bwd": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), C.POINTER(gs_image), pc, i32,
+                                    po, C.POINTER(gs_loss), P, P]),
+        "gs_project_bwd": (C.c_int, [pp, C.POINTER(gs_projected), pc, i32, po, P, C.POINTER(gs_grads), P]),
+        "gs_render_stats": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), pc, i32, po, P, P]),
         "gs_adam_step": (C.c_int, [C.POINTER(gs_adam_group), i32, C.c_double, C.c_double, C.c_double, P, i32, P]),
     }
     for name, (res, args) in sig.items():
@@ -204,6 +208,22 @@ def gs_render_bwd(params, proj, bins, img, cams, n_views, opts, loss, grads, wor
                                                  C.byref(img) if img is not None else None, cams, n_views,
                                                  C.byref(opts), C.byref(loss), C.byref(grads), workspace,
                                                  workspace_bytes, stream))
+
+
+def gs_raster_bwd(proj, n, bins, img, cams, n_views, opts, loss, grad2d, stream):
+    _check("gs_raster_bwd", load().gs_raster_bwd(C.byref(proj), n, C.byref(bins),
+                                                 C.byref(img) if img is not None else None, cams, n_views,
+                                                 C.byref(opts), C.byref(loss), grad2d, stream))
+
+
+def gs_project_bwd(params, proj, cams, n_views, opts, grad2d, grads, stream):
+    _check("gs_project_bwd", load().gs_project_bwd(C.byref(params), C.byref(proj), cams, n_views, C.byref(opts),
+                                                   grad2d, C.byref(grads), stream))
+
+
+def gs_render_stats(proj, n, bins, cams, n_views, opts, d_counts, stream):
+    _check("gs_render_stats", load().gs_render_stats(C.byref(proj), n, C.byref(bins), cams, n_views, C.byref(opts),
+                                                     d_counts, stream))
 
 
 def gs_adam_step(groups, n_groups, beta1, beta2, eps, d_step, zero_grad, stream):

@@ -107,16 +107,24 @@ __device__ inline void sh_grad_dot(int D, float x, float y, float z, const float
   gy += k0 * (-6.0f * x * y) * a[15];
 }
 
+// Geometry runs in double precision.  Both projection kernels are bound by
+// HBM traffic (parameters in, records or gradients out), and gfx950 issues
+// FP64 vector FMAs at the same rate as unpacked FP32 ones, so the wider type
+// costs little time; it keeps the conic and the covariance chain rule accurate
+// for very elongated or very large splats, where FP32 loses digits to
+// cancellation (det of the 2D covariance, -Q G Q).  Colours stay FP32.
+using real = double;
+
 // View-independent part of a Gaussian: normalised quaternion, rotation,
 // scales and the 3D covariance Sigma = (R S)(R S)^T.
 struct Gauss3D {
-  float m[3];
-  float q[4];
-  float qnorm;
-  float R[9];
-  float s[3];
-  float M[9];    // R diag(s)
-  float Sig[6];  // xx xy xz yy yz zz
+  real m[3];
+  real q[4];
+  real qnorm;
+  real R[9];
+  real s[3];
+  real M[9];    // R diag(s)
+  real Sig[6];  // xx xy xz yy yz zz
   bool ok;
 };
 
@@ -124,20 +132,21 @@ __device__ inline void load_gauss(const ProjectArgs& a, int64_t i, Gauss3D& g) {
   g.m[0] = a.means[3 * i];
   g.m[1] = a.means[3 * i + 1];
   g.m[2] = a.means[3 * i + 2];
-  const float4 q = *reinterpret_cast<const float4*>(a.quats + 4 * i);
-  const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
-  g.ok = qn2 > 0.0f;
-  g.qnorm = sqrtf(qn2);
-  const float inv = g.ok ? 1.0f / g.qnorm : 0.0f;
-  const float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
+  const float4 qf = *reinterpret_cast<const float4*>(a.quats + 4 * i);
+  const real qw = qf.x, qx = qf.y, qy = qf.z, qz = qf.w;
+  const real qn2 = qw * qw + qx * qx + qy * qy + qz * qz;
+  g.ok = qn2 > 0.0;
+  g.qnorm = sqrt(qn2);
+  const real inv = g.ok ? 1.0 / g.qnorm : 0.0;
+  const real w = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
   g.q[0] = w; g.q[1] = x; g.q[2] = y; g.q[3] = z;
-  g.R[0] = 1.f - 2.f * (y * y + z * z); g.R[1] = 2.f * (x * y - w * z);       g.R[2] = 2.f * (x * z + w * y);
-  g.R[3] = 2.f * (x * y + w * z);       g.R[4] = 1.f - 2.f * (x * x + z * z); g.R[5] = 2.f * (y * z - w * x);
-  g.R[6] = 2.f * (x * z - w * y);       g.R[7] = 2.f * (y * z + w * x);       g.R[8] = 1.f - 2.f * (x * x + y * y);
-  for (int k = 0; k < 3; ++k) g.s[k] = expf(a.log_scales[3 * i + k]);
+  g.R[0] = 1 - 2 * (y * y + z * z); g.R[1] = 2 * (x * y - w * z);     g.R[2] = 2 * (x * z + w * y);
+  g.R[3] = 2 * (x * y + w * z);     g.R[4] = 1 - 2 * (x * x + z * z); g.R[5] = 2 * (y * z - w * x);
+  g.R[6] = 2 * (x * z - w * y);     g.R[7] = 2 * (y * z + w * x);     g.R[8] = 1 - 2 * (x * x + y * y);
+  for (int k = 0; k < 3; ++k) g.s[k] = exp((real)a.log_scales[3 * i + k]);
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) g.M[3 * r + c] = g.R[3 * r + c] * g.s[c];
-  const float* M = g.M;
+  const real* M = g.M;
   g.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
   g.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
   g.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
@@ -146,58 +155,74 @@ __device__ inline void load_gauss(const ProjectArgs& a, int64_t i, Gauss3D& g) {
   g.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
 }
 
+// What the per-view projection needs: the mean and the 3D covariance.
+struct GaussCov {
+  real m[3];
+  real Sig[6];
+  bool ok;
+};
+
+__device__ inline void load_cov(const ProjectArgs& a, int64_t i, GaussCov& c) {
+  Gauss3D g;
+  load_gauss(a, i, g);
+  for (int k = 0; k < 3; ++k) c.m[k] = g.m[k];
+  for (int k = 0; k < 6; ++k) c.Sig[k] = g.Sig[k];
+  c.ok = g.ok;
+}
+
 // Per-view projection: camera point, guarded Jacobian J, T = J W, dilated
 // 2D covariance, its inverse (conic) and the image-plane mean.
 struct Proj2D {
-  float t[3];
-  float txc, tyc;
-  float cvx, cvy;   // clamp value of x/z, y/z when the guard is active
+  real t[3];
+  real txc, tyc;
+  real cvx, cvy;   // clamp value of x/z, y/z when the guard is active
   bool clx, cly;
-  float T[6];
-  float a, b, c;    // dilated covariance
-  float ca, cb, cc; // conic
-  float mx, my;
+  real T[6];
+  real a, b, c;    // dilated covariance
+  real ca, cb, cc; // conic
+  real mx, my;
 };
 
-__device__ inline bool project_view(const Gauss3D& g, const CamF& cam, float near_plane, float eps2d, Proj2D& p) {
-  const float* W = cam.R;
+__device__ inline bool project_view(const GaussCov& g, const CamF& cam, real near_plane, real eps2d, Proj2D& p) {
+  const real W[9] = {cam.R[0], cam.R[1], cam.R[2], cam.R[3], cam.R[4], cam.R[5], cam.R[6], cam.R[7], cam.R[8]};
+  const real fx = cam.fx, fy = cam.fy, limx = cam.limx, limy = cam.limy;
   for (int r = 0; r < 3; ++r)
-    p.t[r] = W[3 * r] * g.m[0] + W[3 * r + 1] * g.m[1] + W[3 * r + 2] * g.m[2] + cam.t[r];
+    p.t[r] = W[3 * r] * g.m[0] + W[3 * r + 1] * g.m[1] + W[3 * r + 2] * g.m[2] + (real)cam.t[r];
   if (!(p.t[2] > near_plane)) return false;
-  const float iz = 1.0f / p.t[2];
-  const float ux = p.t[0] * iz, uy = p.t[1] * iz;
-  p.clx = ux < -cam.limx || ux > cam.limx;
-  p.cly = uy < -cam.limy || uy > cam.limy;
-  p.cvx = fminf(fmaxf(ux, -cam.limx), cam.limx);
-  p.cvy = fminf(fmaxf(uy, -cam.limy), cam.limy);
+  const real iz = 1.0 / p.t[2];
+  const real ux = p.t[0] * iz, uy = p.t[1] * iz;
+  p.clx = ux < -limx || ux > limx;
+  p.cly = uy < -limy || uy > limy;
+  p.cvx = fmin(fmax(ux, -limx), limx);
+  p.cvy = fmin(fmax(uy, -limy), limy);
   p.txc = p.clx ? p.cvx * p.t[2] : p.t[0];
   p.tyc = p.cly ? p.cvy * p.t[2] : p.t[1];
-  const float j00 = cam.fx * iz, j02 = -cam.fx * p.txc * iz * iz;
-  const float j11 = cam.fy * iz, j12 = -cam.fy * p.tyc * iz * iz;
+  const real j00 = fx * iz, j02 = -fx * p.txc * iz * iz;
+  const real j11 = fy * iz, j12 = -fy * p.tyc * iz * iz;
   for (int c = 0; c < 3; ++c) {
     p.T[c] = j00 * W[c] + j02 * W[6 + c];
     p.T[3 + c] = j11 * W[3 + c] + j12 * W[6 + c];
   }
-  const float* S = g.Sig;
-  const float* T = p.T;
+  const real* S = g.Sig;
+  const real* T = p.T;
   // (T Sigma) rows
-  const float u0 = T[0] * S[0] + T[1] * S[1] + T[2] * S[2];
-  const float u1 = T[0] * S[1] + T[1] * S[3] + T[2] * S[4];
-  const float u2 = T[0] * S[2] + T[1] * S[4] + T[2] * S[5];
-  const float w0 = T[3] * S[0] + T[4] * S[1] + T[5] * S[2];
-  const float w1 = T[3] * S[1] + T[4] * S[3] + T[5] * S[4];
-  const float w2 = T[3] * S[2] + T[4] * S[4] + T[5] * S[5];
+  const real u0 = T[0] * S[0] + T[1] * S[1] + T[2] * S[2];
+  const real u1 = T[0] * S[1] + T[1] * S[3] + T[2] * S[4];
+  const real u2 = T[0] * S[2] + T[1] * S[4] + T[2] * S[5];
+  const real w0 = T[3] * S[0] + T[4] * S[1] + T[5] * S[2];
+  const real w1 = T[3] * S[1] + T[4] * S[3] + T[5] * S[4];
+  const real w2 = T[3] * S[2] + T[4] * S[4] + T[5] * S[5];
   p.a = u0 * T[0] + u1 * T[1] + u2 * T[2] + eps2d;
   p.b = u0 * T[3] + u1 * T[4] + u2 * T[5];
   p.c = w0 * T[3] + w1 * T[4] + w2 * T[5] + eps2d;
-  const float det = p.a * p.c - p.b * p.b;
-  if (!(det > 0.0f)) return false;
-  const float idet = 1.0f / det;
+  const real det = p.a * p.c - p.b * p.b;
+  if (!(det > 0.0)) return false;
+  const real idet = 1.0 / det;
   p.ca = p.c * idet;
   p.cb = -p.b * idet;
   p.cc = p.a * idet;
-  p.mx = cam.fx * p.t[0] * iz + cam.cx - 0.5f;
-  p.my = cam.fy * p.t[1] * iz + cam.cy - 0.5f;
+  p.mx = fx * p.t[0] * iz + (real)cam.cx - 0.5;
+  p.my = fy * p.t[1] * iz + (real)cam.cy - 0.5;
   return true;
 }
 
@@ -207,8 +232,8 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
   constexpr int K = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  Gauss3D g;
-  load_gauss(a, i, g);
+  GaussCov g;
+  load_cov(a, i, g);
   float sh[K][3];
   sh[0][0] = a.sh_dc[3 * i];
   sh[0][1] = a.sh_dc[3 * i + 1];
@@ -217,7 +242,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
   for (int k = 1; k < K; ++k)
 #pragma unroll
     for (int c = 0; c < 3; ++c) sh[k][c] = a.sh_rest[(i * (K - 1) + (k - 1)) * 3 + c];
-  const float op = 1.0f / (1.0f + expf(-a.logits[i]));
+  const float op = (float)(1.0 / (1.0 + exp(-(real)a.logits[i])));
   const int B = a.tile;
 #pragma unroll 1
   for (int v = 0; v < a.n_views; ++v) {
@@ -227,13 +252,14 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
     int radius = 0, tiles = 0;
     float rgb[3] = {0.f, 0.f, 0.f};
     uint32_t flags = 0;
+    const float fmx = (float)p.mx, fmy = (float)p.my;
     if (ok) {
-      const float mid = 0.5f * (p.a + p.c);
-      const float lam = mid + sqrtf(fmaxf(mid * mid - (p.a * p.c - p.b * p.b), 0.0f));
-      radius = (int)ceilf(a.radius_sigmas * sqrtf(lam));
+      const real mid = 0.5 * (p.a + p.c);
+      const real lam = mid + sqrt(fmax(mid * mid - (p.a * p.c - p.b * p.b), 0.0));
+      radius = (int)ceil((real)a.radius_sigmas * sqrt(lam));
       const int TX = (cam.W + B - 1) / B, TY = (cam.H + B - 1) / B;
       int x0, y0, x1, y1;
-      tile_rect(p.mx, p.my, radius, B, TX, TY, x0, y0, x1, y1);
+      tile_rect(fmx, fmy, radius, B, TX, TY, x0, y0, x1, y1);
       tiles = (x1 - x0) * (y1 - y0);
       if (tiles <= 0) {
         ok = false;
@@ -242,11 +268,10 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
       }
     }
     if (ok) {
-      float dx = g.m[0] - cam.centre[0], dy = g.m[1] - cam.centre[1], dz = g.m[2] - cam.centre[2];
-      const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-      dx *= inv; dy *= inv; dz *= inv;
+      real dx = g.m[0] - cam.centre[0], dy = g.m[1] - cam.centre[1], dz = g.m[2] - cam.centre[2];
+      const real inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
       float Y[16];
-      sh_basis(D, dx, dy, dz, Y);
+      sh_basis(D, (float)(dx * inv), (float)(dy * inv), (float)(dz * inv), Y);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         float s = 0.5f;
@@ -264,9 +289,9 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
     const int64_t row = (int64_t)v * a.n + i;
     float4* out = reinterpret_cast<float4*>(rec + row * GS_REC_FLOATS);
     if (ok) {
-      out[0] = make_float4(p.mx, p.my, p.ca, p.cb);
-      out[1] = make_float4(p.cc, op, rgb[0], rgb[1]);
-      out[2] = make_float4(rgb[2], p.t[2], __int_as_float(radius), __uint_as_float(flags));
+      out[0] = make_float4(fmx, fmy, (float)p.ca, (float)p.cb);
+      out[1] = make_float4((float)p.cc, op, rgb[0], rgb[1]);
+      out[2] = make_float4(rgb[2], (float)p.t[2], __int_as_float(radius), __uint_as_float(flags));
     } else {
       out[0] = make_float4(0.f, 0.f, 0.f, 0.f);
       out[1] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -280,27 +305,24 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
 // gradients of all its views, accumulating the view-independent d/dSigma
 // once, then chains to log-scales and the (unnormalised) quaternion.
 template <int D>
-__global__ __launch_bounds__(128) void k_project_bwd(ProjectArgs a, CamTable cams, const float* __restrict__ rec,
+__global__ __launch_bounds__(256) void k_project_bwd(ProjectArgs a, CamTable cams, const float* __restrict__ rec,
                                                      const float* __restrict__ grad2d, GradPtrs gp) {
   constexpr int K = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  Gauss3D g;
-  load_gauss(a, i, g);
+  GaussCov g;
+  load_cov(a, i, g);
   if (!g.ok) return;
-  float sh[K][3], gsh[K][3];
-  sh[0][0] = a.sh_dc[3 * i];
-  sh[0][1] = a.sh_dc[3 * i + 1];
-  sh[0][2] = a.sh_dc[3 * i + 2];
-#pragma unroll
-  for (int k = 1; k < K; ++k)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) sh[k][c] = a.sh_rest[(i * (K - 1) + (k - 1)) * 3 + c];
+  // SH coefficients are re-read per view (cache hits) instead of held in
+  // registers across the view loop.
+  const float* shd = a.sh_dc + 3 * i;
+  const float* shr = a.sh_rest + i * (K - 1) * 3;
+  float gsh[K][3];
 #pragma unroll
   for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.0f;
-  float gm[3] = {0.f, 0.f, 0.f};
-  float gS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float gop = 0.0f;
+  real gm[3] = {0, 0, 0};
+  real gS[6] = {0, 0, 0, 0, 0, 0};
+  real gop = 0;
   bool any = false;
 #pragma unroll 1
   for (int v = 0; v < a.n_views; ++v) {
@@ -308,7 +330,7 @@ __global__ __launch_bounds__(128) void k_project_bwd(ProjectArgs a, CamTable cam
     const float4 r2 = reinterpret_cast<const float4*>(rec + row * GS_REC_FLOATS)[2];
     if (__float_as_int(r2.z) == 0) continue;
     const uint32_t flags = __float_as_uint(r2.w);
-    float g2[9];
+    real g2[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) g2[k] = grad2d[row * 9 + k];
     const CamF& cam = cams.c[v];
@@ -316,16 +338,16 @@ __global__ __launch_bounds__(128) void k_project_bwd(ProjectArgs a, CamTable cam
     if (!project_view(g, cam, a.near_plane, a.eps2d, p)) continue;
     any = true;
     // conic -> covariance: dL/dcov = -Q GQ Q
-    const float A = p.ca, Bq = p.cb, C = p.cc;
-    const float ga = g2[2], gb = 0.5f * g2[3], gc = g2[4];
-    const float q00 = A * ga + Bq * gb, q01 = A * gb + Bq * gc;
-    const float q10 = Bq * ga + C * gb, q11 = Bq * gb + C * gc;
-    const float G00 = -(q00 * A + q01 * Bq);
-    const float G01 = -(q00 * Bq + q01 * C);
-    const float G11 = -(q10 * Bq + q11 * C);
+    const real A = p.ca, Bq = p.cb, C = p.cc;
+    const real ga = g2[2], gb = 0.5 * g2[3], gc = g2[4];
+    const real q00 = A * ga + Bq * gb, q01 = A * gb + Bq * gc;
+    const real q10 = Bq * ga + C * gb, q11 = Bq * gb + C * gc;
+    const real G00 = -(q00 * A + q01 * Bq);
+    const real G01 = -(q00 * Bq + q01 * C);
+    const real G11 = -(q10 * Bq + q11 * C);
     // cov = T Sigma T^T (dilation is additive): dL/dSigma = T^T G T, dL/dT = 2 G T Sigma
-    const float* T = p.T;
-    float u[3], w[3];
+    const real* T = p.T;
+    real u[3], w[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       u[k] = G00 * T[k] + G01 * T[3 + k];
@@ -337,101 +359,104 @@ __global__ __launch_bounds__(128) void k_project_bwd(ProjectArgs a, CamTable cam
     gS[3] += T[1] * u[1] + T[4] * w[1];
     gS[4] += T[1] * u[2] + T[4] * w[2];
     gS[5] += T[2] * u[2] + T[5] * w[2];
-    const float* S = g.Sig;
-    const float GT0[3] = {2.f * (u[0] * S[0] + u[1] * S[1] + u[2] * S[2]),
-                          2.f * (u[0] * S[1] + u[1] * S[3] + u[2] * S[4]),
-                          2.f * (u[0] * S[2] + u[1] * S[4] + u[2] * S[5])};
-    const float GT1[3] = {2.f * (w[0] * S[0] + w[1] * S[1] + w[2] * S[2]),
-                          2.f * (w[0] * S[1] + w[1] * S[3] + w[2] * S[4]),
-                          2.f * (w[0] * S[2] + w[1] * S[4] + w[2] * S[5])};
-    const float* Wc = cam.R;
+    const real* S = g.Sig;
+    const real GT0[3] = {2 * (u[0] * S[0] + u[1] * S[1] + u[2] * S[2]), 2 * (u[0] * S[1] + u[1] * S[3] + u[2] * S[4]),
+                         2 * (u[0] * S[2] + u[1] * S[4] + u[2] * S[5])};
+    const real GT1[3] = {2 * (w[0] * S[0] + w[1] * S[1] + w[2] * S[2]), 2 * (w[0] * S[1] + w[1] * S[3] + w[2] * S[4]),
+                         2 * (w[0] * S[2] + w[1] * S[4] + w[2] * S[5])};
+    const real Wc[9] = {cam.R[0], cam.R[1], cam.R[2], cam.R[3], cam.R[4], cam.R[5], cam.R[6], cam.R[7], cam.R[8]};
+    const real fx = cam.fx, fy = cam.fy;
     // dL/dJ = dL/dT W^T (entries J00, J02, J11, J12)
-    const float gj00 = GT0[0] * Wc[0] + GT0[1] * Wc[1] + GT0[2] * Wc[2];
-    const float gj02 = GT0[0] * Wc[6] + GT0[1] * Wc[7] + GT0[2] * Wc[8];
-    const float gj11 = GT1[0] * Wc[3] + GT1[1] * Wc[4] + GT1[2] * Wc[5];
-    const float gj12 = GT1[0] * Wc[6] + GT1[1] * Wc[7] + GT1[2] * Wc[8];
-    const float tz = p.t[2], iz = 1.0f / tz, iz2 = iz * iz, iz3 = iz2 * iz;
-    float gt0 = 0.f, gt1 = 0.f, gt2 = 0.f;
-    gt2 += gj00 * (-cam.fx * iz2) + gj11 * (-cam.fy * iz2);
-    gt0 += p.clx ? 0.0f : gj02 * (-cam.fx * iz2);
-    gt2 += gj02 * (-cam.fx * iz2 * (p.clx ? p.cvx : 0.0f) + 2.0f * cam.fx * p.txc * iz3);
-    gt1 += p.cly ? 0.0f : gj12 * (-cam.fy * iz2);
-    gt2 += gj12 * (-cam.fy * iz2 * (p.cly ? p.cvy : 0.0f) + 2.0f * cam.fy * p.tyc * iz3);
+    const real gj00 = GT0[0] * Wc[0] + GT0[1] * Wc[1] + GT0[2] * Wc[2];
+    const real gj02 = GT0[0] * Wc[6] + GT0[1] * Wc[7] + GT0[2] * Wc[8];
+    const real gj11 = GT1[0] * Wc[3] + GT1[1] * Wc[4] + GT1[2] * Wc[5];
+    const real gj12 = GT1[0] * Wc[6] + GT1[1] * Wc[7] + GT1[2] * Wc[8];
+    const real tz = p.t[2], iz = 1.0 / tz, iz2 = iz * iz, iz3 = iz2 * iz;
+    real gt0 = 0, gt1 = 0, gt2 = 0;
+    gt2 += gj00 * (-fx * iz2) + gj11 * (-fy * iz2);
+    gt0 += p.clx ? 0.0 : gj02 * (-fx * iz2);
+    gt2 += gj02 * (-fx * iz2 * (p.clx ? p.cvx : 0.0) + 2.0 * fx * p.txc * iz3);
+    gt1 += p.cly ? 0.0 : gj12 * (-fy * iz2);
+    gt2 += gj12 * (-fy * iz2 * (p.cly ? p.cvy : 0.0) + 2.0 * fy * p.tyc * iz3);
     // image-plane mean
-    gt0 += g2[0] * cam.fx * iz;
-    gt1 += g2[1] * cam.fy * iz;
-    gt2 -= (g2[0] * cam.fx * p.t[0] + g2[1] * cam.fy * p.t[1]) * iz2;
+    gt0 += g2[0] * fx * iz;
+    gt1 += g2[1] * fy * iz;
+    gt2 -= (g2[0] * fx * p.t[0] + g2[1] * fy * p.t[1]) * iz2;
     gm[0] += Wc[0] * gt0 + Wc[3] * gt1 + Wc[6] * gt2;
     gm[1] += Wc[1] * gt0 + Wc[4] * gt1 + Wc[7] * gt2;
     gm[2] += Wc[2] * gt0 + Wc[5] * gt1 + Wc[8] * gt2;
     gop += g2[5];
     // colour -> SH coefficients and the viewing direction
-    float dx = g.m[0] - cam.centre[0], dy = g.m[1] - cam.centre[1], dz = g.m[2] - cam.centre[2];
-    const float len = sqrtf(dx * dx + dy * dy + dz * dz), il = 1.0f / len;
+    real dx = g.m[0] - cam.centre[0], dy = g.m[1] - cam.centre[1], dz = g.m[2] - cam.centre[2];
+    const real len = sqrt(dx * dx + dy * dy + dz * dz), il = 1.0 / len;
     dx *= il; dy *= il; dz *= il;
     float Y[16], acoef[16];
-    sh_basis(D, dx, dy, dz, Y);
-    const float wr = (flags & 1u) ? 0.f : g2[6], wg = (flags & 2u) ? 0.f : g2[7], wb = (flags & 4u) ? 0.f : g2[8];
+    sh_basis(D, (float)dx, (float)dy, (float)dz, Y);
+    const float wr = (flags & 1u) ? 0.f : (float)g2[6], wg = (flags & 2u) ? 0.f : (float)g2[7],
+                wb = (flags & 4u) ? 0.f : (float)g2[8];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       gsh[k][0] += wr * Y[k];
       gsh[k][1] += wg * Y[k];
       gsh[k][2] += wb * Y[k];
-      acoef[k] = wr * sh[k][0] + wg * sh[k][1] + wb * sh[k][2];
+      const float* c3 = k == 0 ? shd : shr + (k - 1) * 3;
+      acoef[k] = wr * c3[0] + wg * c3[1] + wb * c3[2];
     }
     if (D > 0) {
       float gdx, gdy, gdz;
-      sh_grad_dot(D, dx, dy, dz, acoef, gdx, gdy, gdz);
-      const float dd = gdx * dx + gdy * dy + gdz * dz;
+      sh_grad_dot(D, (float)dx, (float)dy, (float)dz, acoef, gdx, gdy, gdz);
+      const real dd = gdx * dx + gdy * dy + gdz * dz;
       gm[0] += (gdx - dx * dd) * il;
       gm[1] += (gdy - dy * dd) * il;
       gm[2] += (gdz - dz * dd) * il;
     }
   }
   if (!any) return;
+  Gauss3D gf;  // rotation, scales and M = R diag(s), recomputed after the view loop
+  load_gauss(a, i, gf);
   // Sigma = M M^T, M = R diag(s): dL/dM = 2 gS M
-  const float GSm[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
-  float GM[9];
+  const real GSm[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
+  real GM[9];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      GM[3 * r + c] = 2.0f * (GSm[3 * r] * g.M[c] + GSm[3 * r + 1] * g.M[3 + c] + GSm[3 * r + 2] * g.M[6 + c]);
-  float gls[3], GR[9];
+      GM[3 * r + c] = 2 * (GSm[3 * r] * gf.M[c] + GSm[3 * r + 1] * gf.M[3 + c] + GSm[3 * r + 2] * gf.M[6 + c]);
+  real gls[3], GR[9];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const float gsv = GM[c] * g.R[c] + GM[3 + c] * g.R[3 + c] + GM[6 + c] * g.R[6 + c];
-    gls[c] = gsv * g.s[c];
-    GR[c] = GM[c] * g.s[c];
-    GR[3 + c] = GM[3 + c] * g.s[c];
-    GR[6 + c] = GM[6 + c] * g.s[c];
+    const real gsv = GM[c] * gf.R[c] + GM[3 + c] * gf.R[3 + c] + GM[6 + c] * gf.R[6 + c];
+    gls[c] = gsv * gf.s[c];
+    GR[c] = GM[c] * gf.s[c];
+    GR[3 + c] = GM[3 + c] * gf.s[c];
+    GR[6 + c] = GM[6 + c] * gf.s[c];
   }
-  const float w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
+  const real w = gf.q[0], x = gf.q[1], y = gf.q[2], z = gf.q[3];
   // d R / d(w,x,y,z) contracted with GR
-  const float gw = 2.f * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
-  const float gx = 2.f * (y * GR[1] + z * GR[2] + y * GR[3] - 2.f * x * GR[4] - w * GR[5] + z * GR[6] + w * GR[7] -
-                          2.f * x * GR[8]);
-  const float gy = 2.f * (-2.f * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7] -
-                          2.f * y * GR[8]);
-  const float gz = 2.f * (-2.f * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2.f * z * GR[4] + y * GR[5] +
-                          x * GR[6] + y * GR[7]);
-  const float dotq = w * gw + x * gx + y * gy + z * gz;
-  const float iq = 1.0f / g.qnorm;
-  const float op = 1.0f / (1.0f + expf(-a.logits[i]));
-  gp.means[3 * i] += gm[0];
-  gp.means[3 * i + 1] += gm[1];
-  gp.means[3 * i + 2] += gm[2];
-  gp.log_scales[3 * i] += gls[0];
-  gp.log_scales[3 * i + 1] += gls[1];
-  gp.log_scales[3 * i + 2] += gls[2];
+  const real gw = 2 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+  const real gx = 2 * (y * GR[1] + z * GR[2] + y * GR[3] - 2 * x * GR[4] - w * GR[5] + z * GR[6] + w * GR[7] -
+                       2 * x * GR[8]);
+  const real gy = 2 * (-2 * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7] -
+                       2 * y * GR[8]);
+  const real gz = 2 * (-2 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2 * z * GR[4] + y * GR[5] +
+                       x * GR[6] + y * GR[7]);
+  const real dotq = w * gw + x * gx + y * gy + z * gz;
+  const real iq = 1.0 / gf.qnorm;
+  const real op = 1.0 / (1.0 + exp(-(real)a.logits[i]));
+  gp.means[3 * i] += (float)gm[0];
+  gp.means[3 * i + 1] += (float)gm[1];
+  gp.means[3 * i + 2] += (float)gm[2];
+  gp.log_scales[3 * i] += (float)gls[0];
+  gp.log_scales[3 * i + 1] += (float)gls[1];
+  gp.log_scales[3 * i + 2] += (float)gls[2];
   float4* gq = reinterpret_cast<float4*>(gp.quats + 4 * i);
   float4 qv = *gq;
-  qv.x += (gw - w * dotq) * iq;
-  qv.y += (gx - x * dotq) * iq;
-  qv.z += (gy - y * dotq) * iq;
-  qv.w += (gz - z * dotq) * iq;
+  qv.x += (float)((gw - w * dotq) * iq);
+  qv.y += (float)((gx - x * dotq) * iq);
+  qv.z += (float)((gy - y * dotq) * iq);
+  qv.w += (float)((gz - z * dotq) * iq);
   *gq = qv;
-  gp.logits[i] += gop * op * (1.0f - op);
+  gp.logits[i] += (float)(gop * op * (1.0 - op));
 #pragma unroll
   for (int c = 0; c < 3; ++c) gp.sh_dc[3 * i + c] += gsh[0][c];
 #pragma unroll
@@ -475,7 +500,7 @@ gs_status launch_project_bwd(const gs_params* params, const gs_camera* cams, int
   const ProjectArgs a = make_args(params, n_views, opts);
   const CamTable ct = make_cam_table(cams, n_views, opts);
   GradPtrs gp{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->sh_dc, grads->sh_rest};
-  const int bs = 128;
+  const int bs = 256;
   const dim3 grid((unsigned)((params->n + bs - 1) / bs));
   switch (params->sh_degree) {
     case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(bs), 0, stream, a, ct, rec, grad2d, gp); break;

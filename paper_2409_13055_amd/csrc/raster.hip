@@ -451,6 +451,90 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
   }
 }
 
+// Work counts of the per-pixel blending as defined (no tile cull): per pixel,
+// the list entries evaluated until it stops (list end, or the entry that would
+// take T below t_min, inclusive), the entries blended, and n_contrib; summed
+// over the image into out[0..2] (one 64-bit atomic per wavefront and count).
+template <int TILE>
+__global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
+    ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
+    RasterConsts rc, unsigned long long* __restrict__ out) {
+  using PM = PixMap<TILE>;
+  constexpr int PPL = PM::PPL, NT = PM::NT;
+  __shared__ float4 s_a[NT];
+  __shared__ float4 s_b[NT];
+  const PM pm(vt, blockIdx.x);
+  float T[PPL];
+  int last[PPL], evals[PPL], blended[PPL];
+  bool done[PPL];
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    T[p] = 1.0f;
+    last[p] = evals[p] = blended[p] = 0;
+    done[p] = !pm.inside(p);
+  }
+  const uint2 rg = ranges[blockIdx.x];
+  const int s = (int)rg.x, e = (int)rg.y;
+  const float fx = (float)pm.x;
+  for (int base = s; base < e; base += NT) {
+    int alive = 0;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
+    if (__syncthreads_count(alive) == 0) break;
+    const int idx = base + (int)threadIdx.x;
+    if (idx < e) {
+      const float4* r = reinterpret_cast<const float4*>(rec + (size_t)ids[idx] * GS_REC_FLOATS);
+      s_a[threadIdx.x] = r[0];
+      s_b[threadIdx.x] = r[1];
+    }
+    __syncthreads();
+    const int cnt = min(NT, e - base);
+    for (int j = 0; j < cnt; ++j) {
+      const float4 A = s_a[j];
+      const float4 Bv = s_b[j];
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        if (done[p]) continue;
+        ++evals[p];
+        const float dx = fx - A.x, dy = (float)(pm.y0 + p) - A.y;
+        const float power = splat_power(dx, dy, A.z, A.w, Bv.x);
+        if (power > 0.0f) continue;
+        const float alpha = fminf(rc.alpha_max, Bv.y * exp_hw(power));
+        if (alpha < rc.alpha_min) continue;
+        const float test = T[p] * (1.0f - alpha);
+        if (test < rc.t_min) {
+          done[p] = true;
+          continue;
+        }
+        T[p] = test;
+        ++blended[p];
+        last[p] = base - s + j + 1;
+      }
+    }
+  }
+  unsigned long long c0 = 0, c1 = 0, c2 = 0;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    c0 += (unsigned long long)evals[p];
+    c1 += (unsigned long long)blended[p];
+    c2 += (unsigned long long)last[p];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    c0 += __shfl_xor(c0, o);
+    c1 += __shfl_xor(c1, o);
+    c2 += __shfl_xor(c2, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(out, c0);
+    atomicAdd(out + 1, c1);
+    atomicAdd(out + 2, c2);
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
 __global__ void k_fill_f32(float* __restrict__ p, uint64_t count) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = 0.0f;
@@ -538,14 +622,9 @@ extern "C" gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs
   return check_launch("render forward");
 }
 
-extern "C" gs_status gs_render_bwd(const gs_params* params, const gs_projected* proj, const gs_bins* bins,
-                                   const gs_image* img, const gs_camera* cams, int32_t n_views, const gs_options* opts,
-                                   const gs_loss* loss, const gs_grads* grads, void* workspace,
-                                   size_t workspace_bytes, void* stream) {
-  using namespace gs;
-  gs_status s;
-  if ((s = validate_params(params)) != GS_OK) return s;
-  if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
+namespace gs {
+
+static gs_status validate_loss_bwd(const gs_loss* loss, const gs_image* img, const gs_options* opts) {
   if (!loss || (loss->kind != GS_LOSS_L1 && loss->kind != GS_LOSS_EXTERNAL))
     return fail(GS_ERR_INVALID_VALUE, "loss must be GS_LOSS_L1 or GS_LOSS_EXTERNAL");
   if (loss->kind == GS_LOSS_L1 && (!loss->target || !img || !img->rgb))
@@ -554,20 +633,21 @@ extern "C" gs_status gs_render_bwd(const gs_params* params, const gs_projected* 
     return fail(GS_ERR_INVALID_VALUE, "external loss needs dl_dimage");
   if (!opts->checkpoint && (!img || !img->t_final || !img->n_contrib))
     return fail(GS_ERR_INVALID_VALUE, "img->t_final/n_contrib are required unless checkpoint is set");
+  return GS_OK;
+}
+
+static gs_status validate_grads(const gs_params* params, const gs_grads* grads) {
   if (!grads || !grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh_dc ||
       (params->sh_degree > 0 && !grads->sh_rest))
     return fail(GS_ERR_INVALID_VALUE, "a gradient pointer is NULL");
   if (reinterpret_cast<uintptr_t>(grads->quats) % 16 != 0)
     return fail(GS_ERR_INVALID_VALUE, "grads->quats must be 16-byte aligned");
-  const size_t g2n = (size_t)GS_GRAD2D_FLOATS * (size_t)params->n * (size_t)n_views;
-  if (!workspace || workspace_bytes < sizeof(float) * g2n)
-    return fail(GS_ERR_CAPACITY, "workspace too small: need " + std::to_string(sizeof(float) * g2n) + " bytes");
-  const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
-  hipStream_t st = as_stream(stream);
+  return GS_OK;
+}
+
+static void launch_raster_bwd(const ViewTable& vt, const gs_projected* proj, const gs_bins* bins, const gs_image* img,
+                              const gs_options* opts, const gs_loss* loss, float* g2, hipStream_t st) {
   const RasterConsts rc = consts_of(opts);
-  float* g2 = static_cast<float*>(workspace);
-  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)std::min<size_t>(8192, (g2n + 255) / 256)), dim3(256), 0, st, g2,
-                     (uint64_t)g2n);
   const dim3 grid((unsigned)vt.total_tiles);
   const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
   const float* rgb = img ? img->rgb : nullptr;
@@ -590,6 +670,79 @@ extern "C" gs_status gs_render_bwd(const gs_params* params, const gs_projected* 
     }
   }
 #undef GS_BWD
+}
+
+}  // namespace gs
+
+extern "C" gs_status gs_raster_bwd(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_image* img,
+                                   const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                                   const gs_loss* loss, float* grad2d, void* stream) {
+  using namespace gs;
+  gs_status s;
+  if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
+  if (n < 1) return fail(GS_ERR_INVALID_VALUE, "n must be >= 1");
+  if ((s = validate_loss_bwd(loss, img, opts)) != GS_OK) return s;
+  if (!grad2d) return fail(GS_ERR_INVALID_VALUE, "grad2d is NULL");
+  const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
+  launch_raster_bwd(vt, proj, bins, img, opts, loss, grad2d, as_stream(stream));
+  return check_launch("raster backward");
+}
+
+extern "C" gs_status gs_project_bwd(const gs_params* params, const gs_projected* proj, const gs_camera* cams,
+                                    int32_t n_views, const gs_options* opts, const float* grad2d,
+                                    const gs_grads* grads, void* stream) {
+  using namespace gs;
+  gs_status s;
+  if ((s = validate_params(params)) != GS_OK) return s;
+  if ((s = validate_cams(cams, n_views)) != GS_OK) return s;
+  if ((s = validate_opts(opts)) != GS_OK) return s;
+  if (!proj || !proj->rec) return fail(GS_ERR_INVALID_VALUE, "proj->rec is NULL");
+  if (!grad2d) return fail(GS_ERR_INVALID_VALUE, "grad2d is NULL");
+  if ((s = validate_grads(params, grads)) != GS_OK) return s;
+  return launch_project_bwd(params, cams, n_views, opts, proj->rec, grad2d, grads, as_stream(stream));
+}
+
+extern "C" gs_status gs_render_bwd(const gs_params* params, const gs_projected* proj, const gs_bins* bins,
+                                   const gs_image* img, const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                                   const gs_loss* loss, const gs_grads* grads, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
+  using namespace gs;
+  gs_status s;
+  if ((s = validate_params(params)) != GS_OK) return s;
+  if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
+  if ((s = validate_loss_bwd(loss, img, opts)) != GS_OK) return s;
+  if ((s = validate_grads(params, grads)) != GS_OK) return s;
+  const size_t g2n = (size_t)GS_GRAD2D_FLOATS * (size_t)params->n * (size_t)n_views;
+  if (!workspace || workspace_bytes < sizeof(float) * g2n)
+    return fail(GS_ERR_CAPACITY, "workspace too small: need " + std::to_string(sizeof(float) * g2n) + " bytes");
+  const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
+  hipStream_t st = as_stream(stream);
+  float* g2 = static_cast<float*>(workspace);
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)std::min<size_t>(8192, (g2n + 255) / 256)), dim3(256), 0, st, g2,
+                     (uint64_t)g2n);
+  launch_raster_bwd(vt, proj, bins, img, opts, loss, g2, st);
   if ((s = check_launch("render backward")) != GS_OK) return s;
   return launch_project_bwd(params, cams, n_views, opts, proj->rec, g2, grads, st);
+}
+
+extern "C" gs_status gs_render_stats(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
+                                     int32_t n_views, const gs_options* opts, int64_t* d_counts, void* stream) {
+  using namespace gs;
+  gs_status s;
+  if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
+  if (n < 1) return fail(GS_ERR_INVALID_VALUE, "n must be >= 1");
+  if (!d_counts) return fail(GS_ERR_INVALID_VALUE, "d_counts is NULL");
+  const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
+  hipStream_t st = as_stream(stream);
+  const RasterConsts rc = consts_of(opts);
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(d_counts);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, out, 3);
+  const dim3 grid((unsigned)vt.total_tiles);
+  const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
+  switch (opts->tile_size) {
+    case 8: hipLaunchKernelGGL(k_render_stats<8>, grid, dim3(64), 0, st, vt, proj->rec, bins->ids, rg, rc, out); break;
+    case 16: hipLaunchKernelGGL(k_render_stats<16>, grid, dim3(64), 0, st, vt, proj->rec, bins->ids, rg, rc, out); break;
+    default: hipLaunchKernelGGL(k_render_stats<32>, grid, dim3(256), 0, st, vt, proj->rec, bins->ids, rg, rc, out); break;
+  }
+  return check_launch("render stats");
 }

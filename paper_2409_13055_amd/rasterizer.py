@@ -201,6 +201,32 @@ class Rasterizer:
         L.gs_render_bwd(params.c_params(), fr.c_proj(), fr.c_bins(), fr.c_image(), self.cams, self.n_views,
                         self.opts, loss, grads.c_grads(), self.ws_bwd.data_ptr(), self.ws_bwd_bytes, _stream())
 
+    def _loss(self, target=None, dl_dimage=None) -> L.gs_loss:
+        loss = L.gs_loss()
+        if dl_dimage is not None:
+            loss.kind, loss.dl_dimage = L.GS_LOSS_EXTERNAL, _p(dl_dimage)
+        else:
+            loss.kind, loss.target = L.GS_LOSS_L1, _p(target)
+        return loss
+
+    def raster_bwd(self, fr: Frame, grad2d: torch.Tensor, target=None, dl_dimage=None):
+        """Adds the image-space gradients of this frame into grad2d ([n_views*n, 9] FP32)."""
+        L.gs_raster_bwd(fr.c_proj(), self.n, fr.c_bins(), fr.c_image(), self.cams, self.n_views, self.opts,
+                        self._loss(target, dl_dimage), grad2d.data_ptr(), _stream())
+
+    def project_bwd(self, params: GaussianParams, fr: Frame, grad2d: torch.Tensor, grads: GaussianParams):
+        """Adds the parameter gradients chained from grad2d into grads."""
+        L.gs_project_bwd(params.c_params(), fr.c_proj(), self.cams, self.n_views, self.opts, grad2d.data_ptr(),
+                         grads.c_grads(), _stream())
+
+    def render_stats(self, fr: Frame) -> Dict[str, int]:
+        """Work counts of the blending of this frame (see gs_render_stats); syncs."""
+        out = torch.zeros(3, dtype=torch.int64, device=self.device)
+        L.gs_render_stats(fr.c_proj(), self.n, fr.c_bins(), self.cams, self.n_views, self.opts, out.data_ptr(),
+                          _stream())
+        e, b, c = (int(x) for x in out.cpu())
+        return {"evaluated": e, "blended": b, "contrib_prefix": c}
+
     @property
     def grad2d(self) -> torch.Tensor:
         """[n_views*n, 9] image-space gradients of the last backward."""

@@ -3,16 +3,17 @@
 Bytes are what the method must move through HBM: each input read once and
 each output written once (not the implementation's extra passes or cache
 re-reads).  For the raster calls the arithmetic is counted too, as FP32
-flops per (pixel, splat) evaluation times a lower bound on the evaluations
-(sum over pixels of the number of list entries up to the last blended one),
-because those kernels are bound by vector ALU issue, not by HBM.
+flops of the per-pixel blending as defined (counted exactly on the GPU by
+gs_render_stats), because those kernels are bound by vector ALU issue, not
+by HBM.
 
 Per-unit figures (P_n = 11 + 3K raw floats per Gaussian, K = (D+1)^2):
   project     N*4*P_n + V*N*(48 + 4)
   bin_sort    V*N*8 + M*(12 + 24 + 8) + T*8
   render_fwd  Nv*36 + M*4 + Px*(12 + 12 [target] + 8 [T_final, n_contrib unless checkpoint])
-  render_bwd  Px*(12 + 12 + 8 [unless checkpoint]) + Nv*36 + M*4 + V*N*36
-              + N*(4*P_n + 8*P_n) + V*N*(36 + 16)
+  raster_bwd  Px*(12 + 12 + 8 [unless checkpoint]) + Nv*36 + M*4 + V*N*36
+  project_bwd N*(4*P_n + 8*P_n) + V*N*(36 + 16)
+  render_bwd  raster_bwd + project_bwd
   adam        N*P_n*32  (read p, g, m, v; write p, m, v, g := 0)
 with N Gaussians, V views, Nv visible (view, Gaussian) pairs, M tile
 incidences, Px pixels and T tiles.
@@ -21,8 +22,24 @@ from __future__ import annotations
 
 import torch
 
-FLOPS_FWD_EVAL = 26   # dx,dy 2; power 10; exp 2; alpha 3; T test 3; weight 1; colour 6 (FMA = 2)
-FLOPS_BWD_EVAL = 66   # recompute 18; T 3; colour grads 7; dL/dalpha 15; S update 6; opacity/power 3; mean/conic 14
+# FP32 operations of the per-pixel blending (an FMA counts 2; a compare, min,
+# exp2 or reciprocal counts 1), per (pixel, list entry):
+#   evaluated entry  17: d = pixel - mean 2; power 9 (3 mul, 2 FMA, 1 scale);
+#                        power > 0 test 1; exp 2; opacity * G 1; min 1;
+#                        alpha test 1
+#   blended, forward +10: 1 - alpha, T (1 - alpha), T test, weight, colour 3 FMA
+#   blended, backward +54: 1/(1 - alpha) 2, T update 1, weight 1, colour grads
+#                        3 FMA, dL/dalpha 15, S update 3 FMA, clamp test 1,
+#                        dL/dpower 1, opacity grad FMA, mean grads 2 x 5,
+#                        conic grads 3 x 3
+#   blended, replay   +4: 1 - alpha, T (1 - alpha), T test, T store
+# The counts come from gs_render_stats (the blending as defined, no tile
+# cull): E_eval entries evaluated until each pixel stops, E_blend blended
+# pairs, E_contrib = sum of n_contrib (the entries the backward revisits).
+FLOPS_EVAL = 17
+FLOPS_FWD_BLEND = 10
+FLOPS_BWD_BLEND = 54
+FLOPS_REPLAY_BLEND = 4
 
 
 def counts(step, sc):
@@ -37,50 +54,56 @@ def counts(step, sc):
 def algorithmic_bytes(c):
     N, V, Pn, M, Nv, Px, T = c["N"], c["V"], c["Pn"], c["M"], c["Nv"], c["Px"], c["T"]
     saved = 0 if c["ckpt"] else 8
+    raster_bwd = Px * (24 + saved) + Nv * 36 + M * 4 + V * N * 36
+    project_bwd = N * 12 * Pn + V * N * 52
     return {
         "project": N * 4 * Pn + V * N * 52,
         "bin_sort": V * N * 8 + M * 44 + T * 8,
         "render_fwd": Nv * 36 + M * 4 + Px * (24 + saved),
-        "render_bwd": Px * (24 + saved) + Nv * 36 + M * 4 + V * N * 36 + N * 12 * Pn + V * N * 52,
+        "raster_bwd": raster_bwd,
+        "project_bwd": project_bwd,
+        "render_bwd": raster_bwd + project_bwd,
         "adam": N * Pn * 32,
     }
 
 
 def evaluations(step):
-    """Lower bound on (pixel, splat) evaluations: sum of contributor counts of a forward render."""
-    from . import rasterizer as R
-    r = step.rast
-    if not r.checkpoint:
-        fr = step.frame
-        r.render_fwd(fr)
-        return int(fr.n_contrib.to(torch.int64).sum().item())
-    probe = R.Rasterizer(r.cameras, r.n, r.sh_degree, tile_size=r.opts.tile_size, checkpoint=False,
-                         device=r.device)
-    probe.reserve(r.capacity)
-    fr = probe.forward(step.params)
-    e = int(fr.n_contrib.to(torch.int64).sum().item())
-    del fr, probe
-    return e
+    """Exact work counts of the blending of the step's frame (gs_render_stats)."""
+    return step.rast.render_stats(step.frame)
 
 
-def report(step, sc, stages_ms, hbm_peak_gbs, valu_peak_tops):
+def alu_flops(kernel, ev, ckpt):
+    if kernel == "render_fwd":
+        return ev["evaluated"] * FLOPS_EVAL + ev["blended"] * FLOPS_FWD_BLEND
+    f = ev["contrib_prefix"] * FLOPS_EVAL + ev["blended"] * FLOPS_BWD_BLEND
+    if ckpt:
+        f += ev["evaluated"] * FLOPS_EVAL + ev["blended"] * FLOPS_REPLAY_BLEND
+    return f
+
+
+SINGLE_KERNEL_CALLS = ("project", "render_fwd", "raster_bwd", "project_bwd", "adam")
+
+
+def report(step, sc, stages_ms, hbm_peak_gbs, valu_peak_tflops, traffic=None):
+    """Roofline of the dominant single-kernel call (by measured duration)."""
     c = counts(step, sc)
     b = algorithmic_bytes(c)
     ev = evaluations(step)
-    dom = max((k for k in stages_ms if k in b), key=lambda k: stages_ms[k])
+    dom = max((k for k in stages_ms if k in SINGLE_KERNEL_CALLS), key=lambda k: stages_ms[k])
     ms = stages_ms[dom]
     per_stage = {k: {"ms": stages_ms[k], "alg_bytes": b[k], "GBps": round(b[k] / (stages_ms[k] * 1e-3) / 1e9, 1)}
                  for k in stages_ms if k in b}
-    if dom in ("render_fwd", "render_bwd"):
-        flops = ev * (FLOPS_FWD_EVAL if dom == "render_fwd" else FLOPS_BWD_EVAL)
+    if dom in ("render_fwd", "raster_bwd"):
+        flops = alu_flops(dom, ev, c["ckpt"])
         achieved = flops / (ms * 1e-3) / 1e12
-        peak = 2 * valu_peak_tops  # FMA counted as 2 flops, no packed FP32
-        out = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": "TFLOP/s",
-               "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom, "evaluations": ev}
+        out = {"bound": "alu", "achieved": round(achieved, 3), "peak": valu_peak_tflops, "unit": "TFLOP/s",
+               "frac": round(achieved / valu_peak_tflops, 4), "traffic": traffic, "kernel": dom,
+               "flops_per_launch": flops, "evaluations": ev, "ms_per_launch": ms}
     else:
         achieved = b[dom] / (ms * 1e-3) / 1e9
         out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": hbm_peak_gbs, "unit": "GB/s",
-               "frac": round(achieved / hbm_peak_gbs, 4), "traffic": None, "kernel": dom}
+               "frac": round(achieved / hbm_peak_gbs, 4), "traffic": traffic, "kernel": dom,
+               "alg_bytes_per_launch": b[dom], "ms_per_launch": ms}
     out["stages"] = per_stage
     out["counts"] = c
     return out

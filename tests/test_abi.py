@@ -1,0 +1,88 @@
+"""The C ABI library on the CPU: it loads, exports every function include/gs.h
+declares, and its host-only entry points (queries, option defaults, argument
+validation) behave as documented.  No call here launches GPU work: validation
+rejects the arguments before anything would be enqueued."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2409_13055_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2409_13055_amd import build
+        build.build()
+    _lib.load()
+    return _lib
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(gs_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 16, names
+    lib = C.CDLL(L.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(L.EXPORTS) == set(names)
+
+
+def test_defaults_and_queries(L):
+    from paper_2409_13055_amd import synthetic as S
+    o = L.default_options()
+    assert o.tile_size == 16 and o.checkpoint == 0 and o.flags == 0
+    assert abs(o.alpha_min - 1 / 255) < 1e-9 and abs(o.alpha_max - 0.99) < 1e-7 and abs(o.t_min - 1e-4) < 1e-10
+    assert abs(o.near_plane - 0.2) < 1e-7 and abs(o.eps2d - 0.3) < 1e-7 and o.radius_sigmas == 3.0
+    cams = [S.pinhole(1200, 680, 600.0), S.pinhole(640, 480, 525.0), S.pinhole(100, 75, 90.0)]
+    cc = L.make_cameras(cams)
+    for B in (8, 16, 32):
+        exp = sum(((c.width + B - 1) // B) * ((c.height + B - 1) // B) for c in cams)
+        assert L.gs_total_tiles(cc, 3, B) == exp
+    assert L.gs_total_pixels(cc, 3) == sum(c.width * c.height for c in cams)
+    assert L.gs_render_bwd_workspace_size(1000, 3) >= 1000 * 3 * 9 * 4
+    assert L.gs_render_fwd_workspace_size(cc, 3, o) >= 4 * L.gs_total_tiles(cc, 3, 16)
+    a = L.gs_bin_sort_workspace_size(1000, cc, 3, o, 10_000)
+    b = L.gs_bin_sort_workspace_size(1000, cc, 3, o, 100_000)
+    assert b > a > 0
+
+
+def test_invalid_arguments_are_rejected_before_any_launch(L):
+    from paper_2409_13055_amd import synthetic as S
+    o = L.default_options()
+    cc = L.make_cameras([S.pinhole(64, 48, 50.0)])
+    with pytest.raises(L.GsError, match="UNSUPPORTED"):
+        L.gs_total_tiles(cc, 1, 12)
+    with pytest.raises(L.GsError, match="n_views"):
+        L.gs_total_pixels(cc, 0)
+    with pytest.raises(L.GsError, match="pair_capacity"):
+        L.gs_bin_sort_workspace_size(10, cc, 1, o, 1 << 33)
+    bad = L.default_options(alpha_min=0.5, alpha_max=0.4)
+    with pytest.raises(L.GsError, match="alpha"):
+        L.gs_render_fwd_workspace_size(cc, 1, bad)
+    # hot-path calls with NULL device pointers fail validation (nothing is enqueued)
+    params = L.gs_params()
+    params.n, params.sh_degree = 10, 0
+    out = L.gs_projected()
+    with pytest.raises(L.GsError, match="INVALID_VALUE"):
+        L.gs_project(params, cc, 1, o, out, None)
+    params.sh_degree = 5
+    with pytest.raises(L.GsError, match="sh_degree"):
+        L.gs_project(params, cc, 1, o, out, None)
+    groups = (L.gs_adam_group * 1)()
+    groups[0].numel = 4
+    with pytest.raises(L.GsError, match="NULL"):
+        L.gs_adam_step(groups, 1, 0.9, 0.999, 1e-15, C.c_void_p(16), 0, None)
+    with pytest.raises(L.GsError, match="beta"):
+        L.gs_adam_step(groups, 1, 1.5, 0.999, 1e-15, C.c_void_p(16), 0, None)
+    lib = L.load()
+    assert lib.gs_status_string(3) == b"GS_ERR_CAPACITY"
+    assert b"beta" in lib.gs_last_error()

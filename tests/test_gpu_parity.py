@@ -248,3 +248,22 @@ def test_bin_sort_bitexact_full_size(workload, tile):
     g = U.run_gpu(sc, tile=tile, backward=False)
     assert g["m"] > 500_000
     check_bins(sc, g, tile)
+
+
+def test_render_stats_counts_match_oracle():
+    """gs_render_stats (work counts used for roofline accounting) against the oracle's per-pixel
+    trace, on the GPU's own lists and records."""
+    sc = small_scene(seed=13, n=3000)
+    g = U.run_gpu(sc, backward=False)
+    rast, fr = g["rast"], g["frame"]
+    st = rast.render_stats(fr)
+    opts = O.Options(tile=16)
+    orec = U.gpu_rec_to_oracle(g["rec"])
+    ev, bl = O.pixel_counts(sc.cameras, opts, orec, g["ids"], g["ranges"])
+    ref = O.render(sc.cameras, opts, orec, g["ids"], g["ranges"])
+    flagged = ref["pix_flags"] != 0
+    assert st["contrib_prefix"] == int(g["n_contrib"].astype(np.int64).sum())
+    # decisions can only differ at flagged pixels
+    assert abs(st["evaluated"] - int(ev.sum())) <= int(ev[flagged].sum())
+    assert abs(st["blended"] - int(bl.sum())) <= int(bl[flagged].sum())
+    assert st["blended"] > 0 and st["evaluated"] >= st["blended"]
