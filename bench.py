@@ -170,34 +170,27 @@ def main():
 
 
 def stage_breakdown(step, iters):
-    """Average duration of each hot-path call of the batched step (eager launches, HIP events on
-    the stream the kernels are launched on)."""
+    """Average duration of each stage of the batched iteration, measured inside
+    `iters` eager iterations (HIP events recorded between the stages on the
+    stream the kernels are launched on).  Every stage is one call; project,
+    render_fwd, raster_bwd, project_bwd and adam each launch one kernel, so
+    their figures are that kernel's launch duration in the iteration."""
     import torch
-    r, fr, p = step.rast, step.frame, step.params
-    g2 = torch.zeros(r.n_views * r.n * 9, dtype=torch.float32, device=p.means.device)
-    calls = {
-        "project": lambda: r.project(p, fr),
-        "bin_sort": lambda: r.bin_sort(fr),
-        "render_fwd": lambda: r.render_fwd(fr, step.target, step.loss),
-        "raster_bwd": lambda: r.raster_bwd(fr, g2, target=step.target),
-        "project_bwd": lambda: r.project_bwd(p, fr, g2, step.grads),
-        "render_bwd": lambda: r.render_bwd(p, fr, step.grads, target=step.target),
-    }
+    names = ["project", "bin_sort", "render_fwd", "clear_grad2d", "raster_bwd", "project_bwd"]
     if step.adam is not None:
-        calls["adam"] = lambda: step.adam.step(zero_grad=True)
+        names.append("adam")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(iters)]
+    torch.cuda.synchronize()
+    for it in range(iters):
+        marks = iter(evs[it][1:])
+        evs[it][0].record()
+        step.run(mark=lambda name: next(marks).record())
+    torch.cuda.synchronize()
     out = {}
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    for name, fn in calls.items():
-        fn()
-        torch.cuda.synchronize()
-        ev[0].record()
-        for _ in range(iters):
-            fn()
-        ev[1].record()
-        torch.cuda.synchronize()
-        out[name] = round(ev[0].elapsed_time(ev[1]) / iters, 4)
-    for t in step.grads.tensors():  # the timing launches accumulated into the gradients
-        t.zero_()
+    for k, name in enumerate(names):
+        out[name] = round(sum(e[k].elapsed_time(e[k + 1]) for e in evs) / iters, 4)
+    out["render_bwd"] = round(out["clear_grad2d"] + out["raster_bwd"] + out["project_bwd"], 4)
+    out["step_eager"] = round(sum(e[0].elapsed_time(e[-1]) for e in evs) / iters, 4)
     return out
 
 

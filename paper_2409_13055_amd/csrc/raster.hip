@@ -29,13 +29,35 @@ struct RasterConsts {
   float radius_sigmas;
 };
 
-// power = -(a dx^2 + c dy^2)/2 - b dx dy, with one fixed rounding sequence so
-// that the forward and backward passes take identical skip decisions.
-__device__ __forceinline__ float splat_power(float dx, float dy, float ca, float cb, float cc) {
+// Per-entry quantities staged in LDS, computed once per batch from the
+// 48-byte record (one record per lane) so the per-pixel loop stays short:
+//   cul = (mean x, mean y, wave-cull bound on |d|^2, power cutoff)
+//   geo = (-a/2, -b, -c/2, opacity) for the conic (a, b, c)
+//   col = (r, g, b, 0)
+// The per-pixel exponent is power = -(a dx^2 + c dy^2)/2 - b dx dy, d = pixel -
+// mean, evaluated with one fixed rounding sequence (the dx terms are shared by
+// the PPL pixels of a lane's column), so that every kernel takes identical
+// decisions for a pixel.
+struct RowTerms {
+  float a2x, nbx;  // -a dx^2 / 2 and -b dx
+};
+__device__ __forceinline__ RowTerms row_terms(float dx, const float4& geo) {
 #pragma clang fp contract(off)
-  const float q = fmaf(ca * dx, dx, (cc * dy) * dy);
-  return fmaf(-cb * dx, dy, -0.5f * q);
+  return RowTerms{(geo.x * dx) * dx, geo.y * dx};
 }
+__device__ __forceinline__ float splat_power(const RowTerms& t, float c2, float dy) {
+#pragma clang fp contract(off)
+  return fmaf(t.nbx, dy, fmaf(c2 * dy, dy, t.a2x));
+}
+
+// Below this exponent opacity * exp(power) < alpha_min is certain: the 1e-3
+// margin in the exponent covers the rounding of the logarithm, of exp and of
+// the product, so skipping such entries before exp changes no decision.
+// Opacity 0 gives +inf (every entry is skipped), NaN skips every pixel.
+__device__ __forceinline__ float power_cutoff(float opacity, float alpha_min) {
+  return __logf(alpha_min / opacity) - 1.0e-3f;
+}
+
 
 __device__ __forceinline__ float exp_hw(float x) {
 #pragma clang fp contract(off)
@@ -74,14 +96,17 @@ struct TileShape<32> {
   static constexpr int WAVES = 4, PPL = 4;
 };
 
-// Pixel placement inside a tile: lane l of wave w owns column l % TILE and
-// PPL consecutive rows starting at w*ROWS + (l / TILE)*PPL.
+// Pixel placement inside a tile.  Each wavefront owns a compact SUBW x SUBH
+// block of the tile (8x8 for tile 8; 16x16 for tiles 16 and 32, the latter as
+// a 2x2 arrangement of four waves); lane l owns column l % SUBW of that block
+// and PPL consecutive rows starting at (l / SUBW) * PPL.
 template <int TILE>
 struct PixMap {
   static constexpr int WAVES = TileShape<TILE>::WAVES, PPL = TileShape<TILE>::PPL, NT = 64 * WAVES;
-  static constexpr int ROWS_PER_WAVE = (64 / TILE) * PPL;
-  static_assert(ROWS_PER_WAVE * WAVES == TILE, "tile shape");
+  static constexpr int SUBW = TILE < 16 ? TILE : 16, SUBH = 64 * PPL / SUBW;
+  static_assert((TILE / SUBW) * (TILE / SUBH) == WAVES && SUBW * SUBH == 64 * PPL, "tile shape");
   int v, x, y0, W, H, pix_off, tile;
+  int wx0, wy0;  // top-left pixel of this wave's block
   __device__ PixMap(const ViewTable& vt, int gt) {
     tile = gt;
     v = view_of_tile(vt, gt);
@@ -92,8 +117,10 @@ struct PixMap {
     const int lt = gt - g.tile_off;
     const int tx = lt % g.TX, ty = lt / g.TX;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    x = tx * TILE + lane % TILE;
-    y0 = ty * TILE + w * ROWS_PER_WAVE + (lane / TILE) * PPL;
+    wx0 = tx * TILE + (w % (TILE / SUBW)) * SUBW;
+    wy0 = ty * TILE + (w / (TILE / SUBW)) * SUBH;
+    x = wx0 + lane % SUBW;
+    y0 = wy0 + (lane / SUBW) * PPL;
   }
   __device__ bool inside(int p) const { return x < W && y0 + p < H; }
   __device__ int pix(int p) const { return pix_off + (y0 + p) * W + x; }
@@ -106,8 +133,8 @@ struct PixMap {
 // pixels are evaluated with.  lambda_min(Q) = det(Q) / lambda_max(Q), with
 // det(Q) formed in double (products of FP32 values are exact there), so the
 // bound holds for the FP32 conic however elongated the splat.  If no pixel of
-// a tile is that close, every pixel of the tile would skip the splat
-// (alpha < alpha_min), so the whole tile skips it with one wave-uniform test;
+// a wavefront's pixel block is that close, every one of its pixels would skip
+// the splat (alpha < alpha_min), so the wave skips it with one uniform test;
 // the margins keep that decision identical to the per-pixel FP32 one.
 // Negative: the splat can never reach alpha_min.
 __device__ __forceinline__ float cull_threshold(float ca, float cb, float cc, float opacity, float alpha_min) {
@@ -137,26 +164,29 @@ struct SplatLoader {
       c = r[2];
     }
   }
-  __device__ __forceinline__ void store(float4* s_a, float4* s_b, float2* s_c, uint32_t* s_id, int slot,
+  // record: a = (mean x, mean y, conic a, conic b), b = (conic c, opacity, r, g), c = (b, ...)
+  __device__ __forceinline__ void store(float4* s_cul, float4* s_geo, float4* s_col, uint32_t* s_id, int slot,
                                         const RasterConsts& rc) const {
     if (!valid) return;
-    s_a[slot] = a;
-    s_b[slot] = b;
-    s_c[slot] = make_float2(c.x, cull_threshold(a.z, a.w, b.x, b.y, rc.alpha_min));
+    s_cul[slot] = make_float4(a.x, a.y, cull_threshold(a.z, a.w, b.x, b.y, rc.alpha_min),
+                              power_cutoff(b.y, rc.alpha_min));
+    s_geo[slot] = make_float4(-0.5f * a.z, -a.w, -0.5f * b.x, b.y);
+    s_col[slot] = make_float4(b.z, b.w, c.x, 0.0f);
     if (s_id) s_id[slot] = id;
   }
 };
 
-// Pixel rectangle of the tile (pixel centres), for the tile-level cull.
-struct TileBox {
+// Pixel rectangle (pixel centres inside the image) of a wavefront's block,
+// for the wave-level cull.  A block entirely outside the image has
+// x_hi < x_lo or y_hi < y_lo; its lanes own no pixel.
+struct WaveBox {
   float x_lo, x_hi, y_lo, y_hi;
   template <class PM>
-  __device__ TileBox(const PM& pm, int tile) {
-    const int tx0 = (pm.x / tile) * tile, ty0 = ((pm.y0 - (pm.y0 % tile)) / tile) * tile;
-    x_lo = (float)tx0;
-    x_hi = (float)(min(tx0 + tile, pm.W) - 1);
-    y_lo = (float)ty0;
-    y_hi = (float)(min(ty0 + tile, pm.H) - 1);
+  __device__ explicit WaveBox(const PM& pm) {
+    x_lo = (float)pm.wx0;
+    x_hi = (float)(min(pm.wx0 + PM::SUBW, pm.W) - 1);
+    y_lo = (float)pm.wy0;
+    y_hi = (float)(min(pm.wy0 + PM::SUBH, pm.H) - 1);
   }
   __device__ __forceinline__ bool culled(float mx, float my, float thr) const {
     const float dx = fmaxf(fmaxf(x_lo - mx, mx - x_hi), 0.0f);
@@ -175,13 +205,14 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
     const float* __restrict__ target, float* __restrict__ tile_loss) {
   using PM = PixMap<TILE>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
-  __shared__ float4 s_a[NT];
-  __shared__ float4 s_b[NT];
-  __shared__ float2 s_c[NT];
+  __shared__ float4 s_cul[NT];
+  __shared__ float4 s_geo[NT];
+  __shared__ float4 s_col[NT];
   __shared__ float s_loss[PM::WAVES];
   const PM pm(vt, blockIdx.x);
-  const TileBox box(pm, TILE);
-  float T[PPL], C[PPL][3];
+  const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
+  const WaveBox box(pm);
+  float T[PPL], C[PPL][3], fy[PPL];
   int last[PPL];
   bool done[PPL];
 #pragma unroll
@@ -190,6 +221,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
     C[p][0] = C[p][1] = C[p][2] = 0.0f;
     last[p] = 0;
     done[p] = !pm.inside(p);
+    fy[p] = (float)(pm.y0 + p);
   }
   const uint2 rg = ranges[blockIdx.x];
   const int s = (int)rg.x, e = (int)rg.y;
@@ -201,23 +233,22 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
 #pragma unroll
     for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
     if (__syncthreads_count(alive) == 0) break;
-    ld.store(s_a, s_b, s_c, nullptr, threadIdx.x, rc);
+    ld.store(s_cul, s_geo, s_col, nullptr, threadIdx.x, rc);
     __syncthreads();
     ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);  // next batch, in flight during this one
-    const int cnt = min(NT, e - base);
+    // a wavefront whose pixels have all stopped only keeps the block's barriers
+    const int cnt = __ballot(alive) != 0ull ? min(NT, e - base) : 0;
     for (int j = 0; j < cnt; ++j) {
-      const float4 A = s_a[j];
-      const float2 Cc = s_c[j];
-      if (box.culled(A.x, A.y, Cc.y)) continue;
-      const float4 Bv = s_b[j];
+      const float4 cu = s_cul[j];
+      if (box.culled(cu.x, cu.y, cu.z)) continue;
+      const float4 geo = s_geo[j];
+      const float4 col = s_col[j];
+      const RowTerms rt = row_terms(fx - cu.x, geo);
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        if (done[p]) continue;
-        const float dx = fx - A.x, dy = (float)(pm.y0 + p) - A.y;
-        const float power = splat_power(dx, dy, A.z, A.w, Bv.x);
-        if (power > 0.0f) continue;
-        const float oG = Bv.y * exp_hw(power);
-        const float alpha = fminf(rc.alpha_max, oG);
+        const float power = splat_power(rt, geo.z, fy[p] - cu.y);
+        if (done[p] || !(power >= cu.w) || power > 0.0f) continue;
+        const float alpha = fminf(amax, geo.w * exp_hw(power));
         if (alpha < rc.alpha_min) continue;
         const float test = T[p] * (1.0f - alpha);
         if (test < rc.t_min) {
@@ -225,9 +256,9 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
           continue;
         }
         const float wgt = alpha * T[p];
-        C[p][0] += Bv.z * wgt;
-        C[p][1] += Bv.w * wgt;
-        C[p][2] += Cc.x * wgt;
+        C[p][0] = fmaf(col.x, wgt, C[p][0]);
+        C[p][1] = fmaf(col.y, wgt, C[p][1]);
+        C[p][2] = fmaf(col.z, wgt, C[p][2]);
         T[p] = test;
         last[p] = base - s + j + 1;
       }
@@ -276,7 +307,72 @@ __global__ __launch_bounds__(256) void k_loss_reduce(ViewTable vt, const float* 
 
 // ---------------------------------------------------------------------------
 // Backward.
+//
+// Per (pixel, entry) the lane accumulates, besides the colour and opacity
+// terms, the moments of u = dL/dpower: sum u dx, sum u dy, sum u dx^2,
+// sum u dx dy, sum u dy^2.  The image-space gradients follow exactly, since
+// the conic is constant per entry: dL/dmean = (a Sx + b Sy, b Sx + c Sy),
+// dL/d(a, b, c) = (-Sxx/2, -Sxy, -Syy/2).  The 9 sums are reduced over the
+// wavefront by a reduce-scatter: each permlane32/permlane16 swap adds two
+// different values at once (one per half of the exchanged lanes), leaving
+// three registers whose 16-lane rows each hold one partial sum, which DPP row
+// operations complete.
 // ---------------------------------------------------------------------------
+struct Acc9 {
+  float sx, sxx, sxy, syy, r, g, b, o, sy;
+};
+struct Red3 {
+  float k0, k1, k2;
+};
+
+__device__ __forceinline__ float swap_add32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_add16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float row_sum(float x) {
+  x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp<0x141>(x);  // row_half_mirror
+  return x + dpp<0x140>(x);  // row_mirror
+}
+// Needs all 64 lanes active.  k0 rows hold {sx, sxx, sxy, syy}, k1 rows
+// {r, g, b, o}, k2 holds sy in every row; which row holds which value is
+// found once per kernel (wave_roles) rather than assumed.
+__device__ __forceinline__ Red3 reduce_scatter(const Acc9& a) {
+  const float h0 = swap_add32(a.sx, a.sxx), h1 = swap_add32(a.sxy, a.syy);
+  const float h2 = swap_add32(a.r, a.g), h3 = swap_add32(a.b, a.o);
+  const float h4 = swap_add32(a.sy, a.sy);
+  return Red3{row_sum(swap_add16(h0, h1)), row_sum(swap_add16(h2, h3)), row_sum(swap_add16(h4, h4))};
+}
+
+// What this lane writes after a reduction: gradient component `comp` (-1:
+// none) = ka * k0 + kc * k2 + k1c * k1, with (ka, kc) = (a, b) for the mean x
+// term, (b, c) for mean y, else (k0c, 0).
+struct LaneRole {
+  int comp;
+  bool mean_x, mean_y;
+  float k0c, k1c;
+};
+__device__ LaneRole wave_roles(int lane) {
+  // one-hot tags 1..9 from lane 0 land, fully reduced, where the values do
+  const float one = lane == 0 ? 1.0f : 0.0f;
+  const Red3 t = reduce_scatter(Acc9{1 * one, 2 * one, 3 * one, 4 * one, 5 * one, 6 * one, 7 * one, 8 * one, 9 * one});
+  const int t0 = (int)(t.k0 + 0.5f), t1 = (int)(t.k1 + 0.5f);
+  const int r16 = lane & 15;
+  LaneRole rl{-1, false, false, 0.0f, 0.0f};
+  if (t0 == 1 && r16 == 0) { rl.comp = 0; rl.mean_x = true; }
+  else if (t0 == 1 && r16 == 1) { rl.comp = 1; rl.mean_y = true; }
+  else if (t0 == 2 && r16 == 0) { rl.comp = 2; rl.k0c = -0.5f; }
+  else if (t0 == 3 && r16 == 0) { rl.comp = 3; rl.k0c = -1.0f; }
+  else if (t0 == 4 && r16 == 0) { rl.comp = 4; rl.k0c = -0.5f; }
+  else if (r16 == 2 && t1 >= 5 && t1 <= 8) { rl.comp = t1 == 8 ? 5 : t1 + 1; rl.k1c = 1.0f; }  // o -> 5, r,g,b -> 6,7,8
+  return rl;
+}
+
 template <int TILE, bool CKPT>
 __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
@@ -285,20 +381,24 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
     float* __restrict__ grad2d) {
   using PM = PixMap<TILE>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
-  __shared__ float4 s_a[NT];
-  __shared__ float4 s_b[NT];
-  __shared__ float2 s_c[NT];
+  __shared__ float4 s_cul[NT];
+  __shared__ float4 s_geo[NT];
+  __shared__ float4 s_col[NT];
   __shared__ uint32_t s_id[NT];
   __shared__ int s_max[PM::WAVES];
   const PM pm(vt, blockIdx.x);
-  const TileBox box(pm, TILE);
+  const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
+  const WaveBox box(pm);
   const uint2 rg = ranges[blockIdx.x];
   const int s = (int)rg.x, e = (int)rg.y;
   const float fx = (float)pm.x;
   const int lane = threadIdx.x & 63;
-  float T[PPL], dl[PPL][3], S[PPL][3];
+  const LaneRole role = wave_roles(lane);
+  float T[PPL], dl[PPL][3], DS[PPL], fy[PPL];
   int last[PPL];
   SplatLoader ld;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) fy[p] = (float)(pm.y0 + p);
 
   if (CKPT) {
     // Forward replay: final transmittance and contributor count only.
@@ -315,21 +415,20 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
 #pragma unroll
       for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
       if (__syncthreads_count(alive) == 0) break;
-      ld.store(s_a, s_b, s_c, nullptr, threadIdx.x, rc);
+      ld.store(s_cul, s_geo, s_col, nullptr, threadIdx.x, rc);
       __syncthreads();
       ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);
-      const int cnt = min(NT, e - base);
+      const int cnt = __ballot(alive) != 0ull ? min(NT, e - base) : 0;
       for (int j = 0; j < cnt; ++j) {
-        const float4 A = s_a[j];
-        if (box.culled(A.x, A.y, s_c[j].y)) continue;
-        const float4 Bv = s_b[j];
+        const float4 cu = s_cul[j];
+        if (box.culled(cu.x, cu.y, cu.z)) continue;
+        const float4 geo = s_geo[j];
+        const RowTerms rt = row_terms(fx - cu.x, geo);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-          if (done[p]) continue;
-          const float dx = fx - A.x, dy = (float)(pm.y0 + p) - A.y;
-          const float power = splat_power(dx, dy, A.z, A.w, Bv.x);
-          if (power > 0.0f) continue;
-          const float alpha = fminf(rc.alpha_max, Bv.y * exp_hw(power));
+          const float power = splat_power(rt, geo.z, fy[p] - cu.y);
+          if (done[p] || !(power >= cu.w) || power > 0.0f) continue;
+          const float alpha = fminf(amax, geo.w * exp_hw(power));
           if (alpha < rc.alpha_min) continue;
           const float test = T[p] * (1.0f - alpha);
           if (test < rc.t_min) {
@@ -369,12 +468,11 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
     } else {
       dl[p][0] = dl[p][1] = dl[p][2] = 0.0f;
     }
-    S[p][0] = T[p] * rc.bg0;
-    S[p][1] = T[p] * rc.bg1;
-    S[p][2] = T[p] * rc.bg2;
+    // dL/dC . S, where S = colour accumulated behind the current entry (the background at first)
+    DS[p] = T[p] * (dl[p][0] * rc.bg0 + dl[p][1] * rc.bg1 + dl[p][2] * rc.bg2);
     mylast = max(mylast, last[p]);
   }
-  // Longest blended prefix in the tile.
+  // Longest blended prefix of the wavefront, then of the tile.
   for (int o = 32; o > 0; o >>= 1) mylast = max(mylast, __shfl_xor(mylast, o));
   if (lane == 0) s_max[threadIdx.x >> 6] = mylast;
   __syncthreads();
@@ -382,89 +480,89 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
 #pragma unroll
   for (int w = 0; w < PM::WAVES; ++w) max_last = max(max_last, s_max[w]);
 
+  Acc9 acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   // Back to front over [s, s + max_last) in batches of NT, prefetching the
   // batch in front of the current one.
   int hi = max_last;
   ld.fetch(rec, ids, s + max(0, hi - NT) + (int)threadIdx.x, s + max(0, hi - NT), s + hi);
   for (; hi > 0; hi -= NT) {
     const int lo = max(0, hi - NT);
-    ld.store(s_a, s_b, s_c, s_id, threadIdx.x, rc);
+    ld.store(s_cul, s_geo, s_col, s_id, threadIdx.x, rc);
     __syncthreads();
     {
       const int nlo = max(0, lo - NT);
       ld.fetch(rec, ids, s + nlo + (int)threadIdx.x, s + nlo, s + lo);
     }
-    for (int k = hi - 1; k >= lo; --k) {
+    // entries at or past the wavefront's longest prefix contribute to none of its pixels
+    for (int k = min(hi, mylast) - 1; k >= lo; --k) {
       const int j = k - lo;
-      const float4 A = s_a[j];
-      const float2 Cc = s_c[j];
-      if (box.culled(A.x, A.y, Cc.y)) continue;
-      const float4 Bv = s_b[j];
-      const float cbl = Cc.x;
-      float g[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) g[c] = 0.0f;
+      const float4 cu = s_cul[j];
+      if (box.culled(cu.x, cu.y, cu.z)) continue;
+      const float4 geo = s_geo[j];
+      const float4 col = s_col[j];
+      const float dx = fx - cu.x;
+      const RowTerms rt = row_terms(dx, geo);
       bool any = false;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        if (k >= last[p]) continue;
-        const float dx = fx - A.x, dy = (float)(pm.y0 + p) - A.y;
-        const float power = splat_power(dx, dy, A.z, A.w, Bv.x);
-        if (power > 0.0f) continue;
+        const float dy = fy[p] - cu.y;
+        const float power = splat_power(rt, geo.z, dy);
+        if (k >= last[p] || !(power >= cu.w) || power > 0.0f) continue;
         const float G = exp_hw(power);
-        const float oG = Bv.y * G;
-        const float alpha = fminf(rc.alpha_max, oG);
+        const float oG = geo.w * G;
+        const float alpha = fminf(amax, oG);
         if (alpha < rc.alpha_min) continue;
         any = true;
-        const float inv = 1.0f / (1.0f - alpha);
-        T[p] *= inv;  // transmittance in front of this splat
+        const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+        T[p] *= inv;  // transmittance in front of this entry
         const float wgt = alpha * T[p];
-        g[6] += dl[p][0] * wgt;
-        g[7] += dl[p][1] * wgt;
-        g[8] += dl[p][2] * wgt;
-        const float dLda = dl[p][0] * (Bv.z * T[p] - S[p][0] * inv) + dl[p][1] * (Bv.w * T[p] - S[p][1] * inv) +
-                           dl[p][2] * (cbl * T[p] - S[p][2] * inv);
-        S[p][0] += Bv.z * wgt;
-        S[p][1] += Bv.w * wgt;
-        S[p][2] += cbl * wgt;
-        if (oG <= rc.alpha_max) {
-          const float dLdp = dLda * alpha;
-          g[5] += dLda * G;
-          g[0] += dLdp * (A.z * dx + A.w * dy);
-          g[1] += dLdp * (A.w * dx + Bv.x * dy);
-          g[2] -= 0.5f * dLdp * dx * dx;
-          g[3] -= dLdp * dx * dy;
-          g[4] -= 0.5f * dLdp * dy * dy;
-        }
+        acc.r = fmaf(dl[p][0], wgt, acc.r);
+        acc.g = fmaf(dl[p][1], wgt, acc.g);
+        acc.b = fmaf(dl[p][2], wgt, acc.b);
+        const float dc = fmaf(dl[p][2], col.z, fmaf(dl[p][1], col.y, dl[p][0] * col.x));
+        const float dLda = fmaf(T[p], dc, -inv * DS[p]);
+        DS[p] = fmaf(dc, wgt, DS[p]);
+        const bool unclamped = oG <= amax;  // d alpha / d(o, power) = 0 where clamped
+        const float dLdp = unclamped ? dLda * alpha : 0.0f;
+        acc.o = fmaf(dLda, unclamped ? G : 0.0f, acc.o);
+        const float ux = dLdp * dx, uy = dLdp * dy;
+        acc.sx += ux;
+        acc.sy += uy;
+        acc.sxx = fmaf(ux, dx, acc.sxx);
+        acc.sxy = fmaf(ux, dy, acc.sxy);
+        acc.syy = fmaf(uy, dy, acc.syy);
       }
       if (__ballot(any) != 0ull) {
-        float val = 0.0f;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          const float t = wave_sum(g[c]);
-          val = (lane == c) ? t : val;
-        }
-        if (lane < 9) atomicAdd(grad2d + (size_t)s_id[j] * 9 + lane, val);
+        const Red3 r = reduce_scatter(acc);
+        const float ca = -2.0f * geo.x, cb = -geo.y, cc = -2.0f * geo.z;
+        const float ka = role.mean_x ? ca : (role.mean_y ? cb : role.k0c);
+        const float kc = role.mean_x ? cb : (role.mean_y ? cc : 0.0f);
+        const float val = fmaf(ka, r.k0, fmaf(kc, r.k2, role.k1c * r.k1));
+        if (role.comp >= 0) atomicAdd(grad2d + (size_t)s_id[j] * GS_GRAD2D_FLOATS + role.comp, val);
+        acc = Acc9{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       }
     }
     __syncthreads();
   }
 }
 
-// Work counts of the per-pixel blending as defined (no tile cull): per pixel,
-// the list entries evaluated until it stops (list end, or the entry that would
-// take T below t_min, inclusive), the entries blended, and n_contrib; summed
-// over the image into out[0..2] (one 64-bit atomic per wavefront and count).
+// Work counts of the per-pixel blending as defined (no cull, no exponent
+// cutoff): per pixel, the list entries evaluated until it stops (list end, or
+// the entry that would take T below t_min, inclusive), the entries blended,
+// and n_contrib; summed over the image into out[0..2] (one 64-bit atomic per
+// wavefront and count).
 template <int TILE>
 __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     RasterConsts rc, unsigned long long* __restrict__ out) {
   using PM = PixMap<TILE>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
-  __shared__ float4 s_a[NT];
-  __shared__ float4 s_b[NT];
+  __shared__ float4 s_cul[NT];
+  __shared__ float4 s_geo[NT];
+  __shared__ float4 s_col[NT];
   const PM pm(vt, blockIdx.x);
-  float T[PPL];
+  const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
+  float T[PPL], fy[PPL];
   int last[PPL], evals[PPL], blended[PPL];
   bool done[PPL];
 #pragma unroll
@@ -472,35 +570,33 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
     T[p] = 1.0f;
     last[p] = evals[p] = blended[p] = 0;
     done[p] = !pm.inside(p);
+    fy[p] = (float)(pm.y0 + p);
   }
   const uint2 rg = ranges[blockIdx.x];
   const int s = (int)rg.x, e = (int)rg.y;
   const float fx = (float)pm.x;
+  SplatLoader ld;
   for (int base = s; base < e; base += NT) {
     int alive = 0;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
     if (__syncthreads_count(alive) == 0) break;
-    const int idx = base + (int)threadIdx.x;
-    if (idx < e) {
-      const float4* r = reinterpret_cast<const float4*>(rec + (size_t)ids[idx] * GS_REC_FLOATS);
-      s_a[threadIdx.x] = r[0];
-      s_b[threadIdx.x] = r[1];
-    }
+    ld.fetch(rec, ids, base + (int)threadIdx.x, s, e);
+    ld.store(s_cul, s_geo, s_col, nullptr, threadIdx.x, rc);
     __syncthreads();
     const int cnt = min(NT, e - base);
     for (int j = 0; j < cnt; ++j) {
-      const float4 A = s_a[j];
-      const float4 Bv = s_b[j];
+      const float4 cu = s_cul[j];
+      const float4 geo = s_geo[j];
+      const RowTerms rt = row_terms(fx - cu.x, geo);
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         if (done[p]) continue;
         ++evals[p];
-        const float dx = fx - A.x, dy = (float)(pm.y0 + p) - A.y;
-        const float power = splat_power(dx, dy, A.z, A.w, Bv.x);
+        const float power = splat_power(rt, geo.z, fy[p] - cu.y);
         if (power > 0.0f) continue;
-        const float alpha = fminf(rc.alpha_max, Bv.y * exp_hw(power));
-        if (alpha < rc.alpha_min) continue;
+        const float alpha = fminf(amax, geo.w * exp_hw(power));
+        if (!(alpha >= rc.alpha_min)) continue;
         const float test = T[p] * (1.0f - alpha);
         if (test < rc.t_min) {
           done[p] = true;
@@ -511,6 +607,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
         last[p] = base - s + j + 1;
       }
     }
+    __syncthreads();
   }
   unsigned long long c0 = 0, c1 = 0, c2 = 0;
 #pragma unroll

@@ -326,15 +326,38 @@ class MappingStep:
         self.rast.fit_capacity(fr)
         self.frame = fr
 
-    def run(self):
-        """Enqueue one iteration (no host synchronisation)."""
+    def run(self, mark=None):
+        """Enqueue one iteration (no host synchronisation).
+
+        With `mark` (a callable taking a stage name), the backward is issued as
+        its two calls (raster backward into the image-space gradient buffer,
+        then the projection backward) and mark(name) is called on the host after
+        each stage is enqueued, so a caller can record stream events between
+        the stages of an iteration."""
         r, fr = self.rast, self.frame
         r.project(self.params, fr)
+        if mark:
+            mark("project")
         r.bin_sort(fr)
+        if mark:
+            mark("bin_sort")
         r.render_fwd(fr, self.target, self.loss)
-        r.render_bwd(self.params, fr, self.grads, target=self.target)
+        if mark:
+            mark("render_fwd")
+        if mark is None:
+            r.render_bwd(self.params, fr, self.grads, target=self.target)
+        else:
+            g2 = r.grad2d
+            g2.zero_()
+            mark("clear_grad2d")
+            r.raster_bwd(fr, g2, target=self.target)
+            mark("raster_bwd")
+            r.project_bwd(self.params, fr, g2, self.grads)
+            mark("project_bwd")
         if self.adam is not None:
             self.adam.step(zero_grad=True)
+            if mark:
+                mark("adam")
 
     def overflowed(self) -> bool:
         return int(self.frame.d_overflow.item()) != 0
