@@ -76,6 +76,8 @@ def main():
         tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint)
         tile = tune["best"]
         log(f"[bench] autotune: {tune}")
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
     step = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
                          with_adam=with_adam)
     step.size()
@@ -111,12 +113,25 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
+    peak_hbm = int(torch.cuda.max_memory_allocated())  # everything the batched iteration holds
     if step.overflowed():
         raise RuntimeError("pair capacity overflowed during the timed steps")
     mpix = sc.total_pixels * 1e-6
     value = mpix / (ms * 1e-3)
     loss = step.loss.sum().item()
     log(f"[bench] batched: {ms:.3f} ms/step, {value:.1f} Mpix*iter/s, loss {loss:.5f}")
+
+    # The same iteration issued eagerly (no graph), for comparison.
+    eager_ms = None
+    if use_graph:
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            step.run()
+        e1.record()
+        torch.cuda.synchronize()
+        eager_ms = e0.elapsed_time(e1) / args.steps
+        log(f"[bench] eager (no graph): {eager_ms:.3f} ms/step")
 
     # Per-call breakdown (eager, events around each C call) and the dominant kernel.
     stages = stage_breakdown(step, args.steps)
@@ -159,6 +174,8 @@ def main():
         "config": {"workload": sc.name, "gaussians": sc.n, "views": sc.n_views, "pixels_per_step": sc.total_pixels,
                    "sh_degree": sc.sh_degree, "work": sc.work, "checkpoint": sc.checkpoint, "tile": tile,
                    "graph": use_graph, "pairs": int(step.frame.d_num_pairs.item())},
+        "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
+        "peak_hbm_bytes": peak_hbm,
         "per_view": per_view,
         "stages_ms": stages,
         "roofline": roof,

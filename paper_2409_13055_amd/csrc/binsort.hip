@@ -166,18 +166,91 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scan_digit(uint32_t* __r
 }
 
 // Downsweep: a block ranks a tile of kTileKeys keys at a time.  Wave w owns
-// the tile's keys [w*1024, (w+1)*1024) as 16 groups of 64; ballots over the 8
+// the tile's keys [w*512, (w+1)*512) as 8 groups of 64; ballots over the 8
 // digit bits give each key its rank among equal digits of its group, and a
 // per-wave digit counter in LDS carries the rank across groups (a wave's LDS
 // operations execute in program order, so no barrier is needed).  The tile is
 // then reordered by digit in LDS and written out digit run by digit run, so
 // global stores are coalesced.  Order inside a digit follows the input index,
 // which keeps every pass stable.
-constexpr int kItems = 16;
+constexpr int kItems = 8;
 constexpr int kTileKeys = kSortThreads * kItems;
 
+// Emission of the (tile, pair) incidences in depth order (pair order, tiles
+// row-major inside each pair's rect), generated on the fly from per-pair
+// offsets: see k_entry_offsets.  The first tile-digit pass reads its input
+// from here instead of from an emitted array.
+constexpr int kChunk = kItems;  // output slots per chunk_start entry: one thread's run
+struct EmitSrc {
+  const uint32_t* d_k;          // number of depth-ordered visible pairs
+  const uint64_t* ent_off;      // exclusive incidence offset per pair
+  const uint4* ent_rec;         // per pair: (global tile of the rect's top-left, TX | width << 16, id, tiles)
+  const uint32_t* chunk_start;  // pair holding slot c * kChunk
+};
+
+// Incidences q0 .. q0 + R - 1 into (kk, vv), q0 a multiple of kChunk; slots
+// at or past `end` (<= M) are left unset.  The owner of slot q0 comes from
+// the chunk table, then the run walks the rects, one pair record ahead.
+template <int R>
+__device__ __forceinline__ void emit_run(const EmitSrc& es, uint32_t K, uint64_t q0, uint64_t end, uint32_t* kk,
+                                         uint32_t* vv) {
+  if (q0 >= end) return;
+  uint32_t j = es.chunk_start[q0 / kChunk];
+  const uint64_t start = es.ent_off[j];
+  uint4 r = es.ent_rec[j];
+  uint4 rn = (j + 1 < K) ? es.ent_rec[j + 1] : r;
+  uint64_t next = start + r.w;
+  uint32_t w = r.y >> 16;
+  const uint32_t k0 = (uint32_t)(q0 - start);
+  uint32_t ty = k0 / w, tx = k0 - ty * w;
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const uint64_t q = q0 + e;
+    if (q < end) {
+      while (q >= next) {  // next pair (every listed pair has at least one tile)
+        ++j;
+        r = rn;
+        next += r.w;
+        rn = (j + 1 < K) ? es.ent_rec[j + 1] : r;
+        w = r.y >> 16;
+        tx = ty = 0;
+      }
+    }
+    kk[e] = r.x + ty * (r.y & 0xffffu) + tx;
+    vv[e] = r.z;
+    if (++tx == w) {
+      tx = 0;
+      ++ty;
+    }
+  }
+}
+
+// Digit histogram of the emitted incidences (the input of the first tile pass).
+__global__ __launch_bounds__(kSortThreads) void k_emit_hist(EmitSrc es, const uint32_t* __restrict__ d_m, int shift,
+                                                            int nb, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kRadixBins];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t K = *es.d_k;
+  const uint64_t M = *d_m;
+  const Chunk c = chunk_of(M, nb, blockIdx.x);
+  for (uint64_t tb = c.begin; tb < c.end; tb += kTileKeys) {
+    uint32_t kk[kItems], vv[kItems];
+    const uint64_t q0 = tb + (uint64_t)threadIdx.x * kItems;
+    emit_run<kItems>(es, K, q0, c.end, kk, vv);
+#pragma unroll
+    for (int e = 0; e < kItems; ++e)
+      if (q0 + e < c.end) atomicAdd(&h[(kk[e] >> shift) & (kRadixBins - 1)], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// EMIT: the input tile is generated by emit_run (natural order, staged in LDS)
+// instead of being read from (kin, vin).
+template <bool EMIT>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, EmitSrc es, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_count, int shift, int nb,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_total, uint64_t* __restrict__ keys64,
     const float* __restrict__ rec) {
@@ -193,19 +266,40 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t ex = block_exclusive_scan<uint32_t>(digit_total[tid], s_w, tot);
     s_glob[tid] = ex + hist[(size_t)tid * nb + blockIdx.x];
   }
-  const Chunk c = chunk_of(*d_count, nb, blockIdx.x);
+  const uint64_t count = *d_count;
+  const uint32_t K = EMIT ? *es.d_k : 0u;
+  const Chunk c = chunk_of(count, nb, blockIdx.x);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // item k of lane `lane` in wave w sits at tile offset w*(kItems*64) + k*64 + lane
+  const uint32_t o0 = (uint32_t)w * (kItems * 64) + (uint32_t)lane;
   for (uint64_t tb = c.begin; tb < c.end; tb += kTileKeys) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_wc[k][tid] = 0;
+    if (EMIT) {
+      uint32_t kk[kItems], vv[kItems];
+      emit_run<kItems>(es, K, tb + (uint64_t)tid * kItems, c.end, kk, vv);
+      uint4* sk = reinterpret_cast<uint4*>(s_keys) + tid * (kItems / 4);
+      uint4* sv = reinterpret_cast<uint4*>(s_vals) + tid * (kItems / 4);
+#pragma unroll
+      for (int q = 0; q < kItems / 4; ++q) {
+        sk[q] = make_uint4(kk[4 * q], kk[4 * q + 1], kk[4 * q + 2], kk[4 * q + 3]);
+        sv[q] = make_uint4(vv[4 * q], vv[4 * q + 1], vv[4 * q + 2], vv[4 * q + 3]);
+      }
+    }
     __syncthreads();
     uint32_t key[kItems], val[kItems], rk[kItems];
+    const uint64_t lim = c.end - tb;  // keys left from this tile's start
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-      const uint64_t i = tb + (uint64_t)w * (kItems * 64) + k * 64 + lane;
-      const bool valid = i < c.end;
-      key[k] = valid ? kin[i] : 0u;
-      val[k] = valid ? vin[i] : 0u;
+      const uint32_t o = o0 + (uint32_t)k * 64;
+      const bool valid = o < lim;
+      if (EMIT) {
+        key[k] = valid ? s_keys[o] : 0u;
+        val[k] = valid ? s_vals[o] : 0u;
+      } else {
+        key[k] = valid ? kin[tb + o] : 0u;
+        val[k] = valid ? vin[tb + o] : 0u;
+      }
       const uint32_t d = (key[k] >> shift) & (kRadixBins - 1);
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -244,14 +338,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
     __syncthreads();
     const uint32_t n_in = (uint32_t)min<uint64_t>(kTileKeys, c.end - tb);
-    for (uint32_t i = tid; i < n_in; i += kSortThreads) {
-      const uint32_t kk = s_keys[i];
-      const uint32_t d = (kk >> shift) & (kRadixBins - 1);
-      const uint32_t g = s_glob[d] + (i - s_start[d]);
-      const uint32_t vv = s_vals[i];
-      if (kout) kout[g] = kk;
-      vout[g] = vv;
-      if (keys64) keys64[g] = ((uint64_t)kk << 32) | depth_key(rec, vv);
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t i = (uint32_t)tid + (uint32_t)k * kSortThreads;
+      if (i < n_in) {
+        const uint32_t kk = s_keys[i];
+        const uint32_t d = (kk >> shift) & (kRadixBins - 1);
+        const uint32_t g = s_glob[d] + (i - s_start[d]);
+        const uint32_t vv = s_vals[i];
+        if (kout) kout[g] = kk;
+        vout[g] = vv;
+        if (keys64) keys64[g] = ((uint64_t)kk << 32) | depth_key(rec, vv);
+      }
     }
     __syncthreads();
     s_glob[tid] += tot_d;
@@ -306,30 +403,24 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_steps(uint64_t* __restric
   }
 }
 
-// Emission, balanced over the OUTPUT: k_entry_offsets gives every depth-
-// ordered pair its exclusive incidence offset and a compact description of
-// its tile rect, and records which pair holds the first slot of every
-// kChunk-slot output chunk; k_emit_chunks then gives each thread kPerThread
-// consecutive output slots, finds the owning pair once (binary search inside
-// the chunk's pair range) and walks its rect row-major from there.  Work per
-// thread is fixed however skewed the per-pair tile counts are, and the
-// output order is that of a sequential emission (pair order, tiles row-major
-// within a pair).
-constexpr int kPerThread = 8;
-constexpr int kChunk = kSortThreads * kPerThread;
-
+// Emission offsets: k_entry_offsets gives every depth-ordered pair its
+// exclusive incidence offset and a compact description of its tile rect, and
+// records which pair holds the first slot of every kChunk-slot run of the
+// output; emit_run then looks up the owner of a run's first slot and walks
+// the rects row-major from there, so the work per output slot is fixed
+// however skewed the per-pair tile counts are, and the order is that of a
+// sequential emission (pair order, tiles row-major within a pair).
 __global__ __launch_bounds__(kSortThreads) void k_entry_offsets(
     const int32_t* __restrict__ tiles, const uint32_t* __restrict__ sorted_val, const float* __restrict__ rec,
     const uint32_t* __restrict__ d_k, const uint64_t* __restrict__ step_off, ViewTable vt, uint32_t n,
-    uint64_t capacity, uint64_t* __restrict__ ent_off, uint32_t* __restrict__ ent_base,
-    uint32_t* __restrict__ ent_txw, uint32_t* __restrict__ chunk_start, int32_t* __restrict__ cover) {
+    uint64_t capacity, uint64_t* __restrict__ ent_off, uint4* __restrict__ ent_rec,
+    uint32_t* __restrict__ chunk_start) {
   __shared__ uint64_t s_w[kSortThreads / 64];
   const uint32_t K = *d_k, nsteps = (K + kStep - 1) / kStep;
   for (uint32_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
     const uint32_t j = st * kStep + threadIdx.x;
     uint64_t cnt = 0;
     uint32_t id = 0;
-    int corner_view = -1;  // view whose grid origin this pair's rect starts at
     if (j < K) {
       id = sorted_val[j];
       cnt = (uint64_t)tiles[id];
@@ -343,101 +434,61 @@ __global__ __launch_bounds__(kSortThreads) void k_entry_offsets(
       int x0, y0, x1, y1;
       tile_rect(r0.x, r0.y, __float_as_int(r2.z), vt.tile, g.TX, g.TY, x0, y0, x1, y1);
       ent_off[j] = off;
-      // Corners of the rect in the view's coverage difference grid.  A
-      // corner in column TX or row TY only reaches grid cells outside every
-      // tile's prefix, so it is dropped.
-      int32_t* cg = cover + g.grid_off;
-      const int gw = g.TX + 1;
-      if (x0 != 0 || y0 != 0) atomicAdd(cg + y0 * gw + x0, 1);
-      if (x1 < g.TX) atomicAdd(cg + y0 * gw + x1, -1);
-      if (y1 < g.TY) atomicAdd(cg + y1 * gw + x0, -1);
-      if (x1 < g.TX && y1 < g.TY) atomicAdd(cg + y1 * gw + x1, 1);
-      ent_base[j] = (uint32_t)(g.tile_off + y0 * g.TX + x0);
-      ent_txw[j] = (uint32_t)g.TX | ((uint32_t)(x1 - x0) << 16);
-      corner_view = (x0 == 0 && y0 == 0) ? (int)(id / n) : -1;
+      ent_rec[j] = make_uint4((uint32_t)(g.tile_off + y0 * g.TX + x0), (uint32_t)g.TX | ((uint32_t)(x1 - x0) << 16),
+                              id, (uint32_t)cnt);
       // chunk boundaries inside [off, off + cnt): this pair holds their first slot
       if (off + cnt <= capacity)
         for (uint64_t c = (off + kChunk - 1) / kChunk; c * kChunk < off + cnt; ++c) chunk_start[c] = j;
     }
-    // Rects clamped to a view's top-left corner all hit the same grid cell:
-    // one atomic per view per wavefront.
-    uint64_t pending = __ballot(corner_view >= 0);
-    while (pending) {
-      const int lead = __ffsll((unsigned long long)pending) - 1;
-      const int v = __shfl(corner_view, lead);
-      const uint64_t same = __ballot(corner_view == v);
-      if ((threadIdx.x & 63) == lead) atomicAdd(cover + vt.v[v].grid_off, (int)__popcll(same));
-      pending &= ~same;
-    }
   }
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_emit_chunks(
-    const uint32_t* __restrict__ sorted_val, const uint32_t* __restrict__ d_k, const uint32_t* __restrict__ d_m,
-    const uint64_t* __restrict__ ent_off, const uint32_t* __restrict__ ent_base,
-    const uint32_t* __restrict__ ent_txw, const uint32_t* __restrict__ chunk_start, uint32_t* __restrict__ p_key,
-    uint32_t* __restrict__ p_val) {
-  __shared__ uint4 s_k[kChunk / 4];
-  __shared__ uint4 s_v[kChunk / 4];
-  const uint32_t K = *d_k;
-  const uint64_t M = *d_m;
-  const uint64_t nchunks = (M + kChunk - 1) / kChunk;
-  for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const uint64_t cq = c * kChunk;
-    const uint64_t q0 = cq + (uint64_t)threadIdx.x * kPerThread;
-    uint32_t kk[kPerThread], vv[kPerThread];
-    if (q0 < M) {
-      // last pair whose offset is <= q0, within this chunk's pair range
-      uint32_t lo = chunk_start[c];
-      uint32_t hi = (c + 1 < nchunks) ? chunk_start[c + 1] : K - 1;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (ent_off[mid] <= q0) lo = mid;
-        else hi = mid - 1;
-      }
-      uint32_t j = lo;
-      uint64_t next = (j + 1 < K) ? ent_off[j + 1] : M;
-      uint32_t base = ent_base[j], txw = ent_txw[j], id = sorted_val[j];
-      uint32_t w = txw >> 16, k = (uint32_t)(q0 - ent_off[j]);
-      uint32_t ty = k / w, tx = k - ty * w;
-#pragma unroll
-      for (int e = 0; e < kPerThread; ++e) {
-        const uint64_t q = q0 + e;
-        if (q < M) {
-          while (q >= next) {  // next pair (every listed pair has at least one tile)
-            ++j;
-            next = (j + 1 < K) ? ent_off[j + 1] : M;
-            base = ent_base[j];
-            txw = ent_txw[j];
-            id = sorted_val[j];
-            w = txw >> 16;
-            tx = ty = 0;
-          }
-        }
-        kk[e] = base + ty * (txw & 0xffffu) + tx;
-        vv[e] = id;
-        if (++tx == w) {
-          tx = 0;
-          ++ty;
-        }
-      }
-    }
-    // stage through LDS so the global stores are contiguous across the wavefront
-    s_k[2 * threadIdx.x] = make_uint4(kk[0], kk[1], kk[2], kk[3]);
-    s_k[2 * threadIdx.x + 1] = make_uint4(kk[4], kk[5], kk[6], kk[7]);
-    s_v[2 * threadIdx.x] = make_uint4(vv[0], vv[1], vv[2], vv[3]);
-    s_v[2 * threadIdx.x + 1] = make_uint4(vv[4], vv[5], vv[6], vv[7]);
+// Tile coverage counts: every visible pair adds +1/-1 at the four corners of
+// its tile rect in its view's (TX+1) x (TY+1) difference grid, whose 2D
+// prefix sum (k_tile_counts) is the number of rects covering each tile.  A
+// corner in column TX or row TY only reaches cells outside every tile's
+// prefix, so it is dropped.  Block (b, v) takes kCoverPairs consecutive pairs
+// of view v and, when `priv` (every view's grid fits the dynamic LDS the
+// launch gives), accumulates in a private LDS copy of the grid, then adds its
+// non-zero cells to the global grid: device-wide atomics are resolved beyond
+// the per-XCD L2, so they are kept few and spread.  Otherwise the corners go
+// to the global grid directly.
+constexpr int kCoverPairs = 8192;
+constexpr int kCoverLdsCells = 16384;
+
+__global__ __launch_bounds__(kSortThreads) void k_cover_counts(const int32_t* __restrict__ tiles,
+                                                               const float* __restrict__ rec, ViewTable vt,
+                                                               uint32_t n, int priv, int32_t* __restrict__ cover) {
+  extern __shared__ int32_t s_grid[];
+  const int v = blockIdx.y;
+  const ViewGeom& g = vt.v[v];
+  const int gw = g.TX + 1, cells = gw * (g.TY + 1);
+  int32_t* cg = cover + g.grid_off;
+  int32_t* grid = priv ? s_grid : cg;
+  if (priv) {
+    for (int c = threadIdx.x; c < cells; c += kSortThreads) s_grid[c] = 0;
     __syncthreads();
-    const uint32_t* lk = reinterpret_cast<const uint32_t*>(s_k);
-    const uint32_t* lv = reinterpret_cast<const uint32_t*>(s_v);
-    for (int e = threadIdx.x; e < kChunk; e += kSortThreads) {
-      const uint64_t q = cq + e;
-      if (q < M) {
-        p_key[q] = lk[e];
-        p_val[q] = lv[e];
-      }
-    }
+  }
+  const uint64_t i0 = (uint64_t)blockIdx.x * kCoverPairs;
+  const uint64_t i1 = min<uint64_t>((uint64_t)n, i0 + kCoverPairs);
+  for (uint64_t i = i0 + threadIdx.x; i < i1; i += kSortThreads) {
+    const size_t id = (size_t)v * n + i;
+    if (tiles[id] <= 0) continue;
+    const float4 r0 = reinterpret_cast<const float4*>(rec + id * GS_REC_FLOATS)[0];
+    const float4 r2 = reinterpret_cast<const float4*>(rec + id * GS_REC_FLOATS)[2];
+    int x0, y0, x1, y1;
+    tile_rect(r0.x, r0.y, __float_as_int(r2.z), vt.tile, g.TX, g.TY, x0, y0, x1, y1);
+    atomicAdd(grid + y0 * gw + x0, 1);
+    if (x1 < g.TX) atomicAdd(grid + y0 * gw + x1, -1);
+    if (y1 < g.TY) atomicAdd(grid + y1 * gw + x0, -1);
+    if (x1 < g.TX && y1 < g.TY) atomicAdd(grid + y1 * gw + x1, 1);
+  }
+  if (priv) {
     __syncthreads();
+    for (int c = threadIdx.x; c < cells; c += kSortThreads) {
+      const int32_t d = s_grid[c];
+      if (d != 0) atomicAdd(cg + c, d);
+    }
   }
 }
 
@@ -515,7 +566,7 @@ struct SortPlan {
   int n_steps;       // kStep-entry steps over V*N
   int grid_steps;    // blocks striding over the steps
   int tile_passes;   // 8-bit tile digits
-  size_t off_counters, off_part_a, off_steps, off_hist, off_dtot, off_eoff, off_ebase, off_etxw, off_chunks, off_cover;
+  size_t off_counters, off_part_a, off_steps, off_hist, off_dtot, off_eoff, off_erec, off_chunks, off_cover;
   size_t off_akey, off_aval, off_bkey, off_bval, off_pkey0, off_pkey1, off_pval;
   size_t bytes;
 };
@@ -541,8 +592,7 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   p.off_part_a = take(sizeof(uint64_t) * p.nb_vn);
   p.off_steps = take(sizeof(uint64_t) * p.n_steps);
   p.off_eoff = take(sizeof(uint64_t) * p.vn);
-  p.off_ebase = take(sizeof(uint32_t) * p.vn);
-  p.off_etxw = take(sizeof(uint32_t) * p.vn);
+  p.off_erec = take(sizeof(uint4) * p.vn);
   p.off_chunks = take(sizeof(uint32_t) * (p.cap / kChunk + 2));
   p.off_cover = take(sizeof(int32_t) * (size_t)total_grid);
   p.off_hist = take(sizeof(uint32_t) * kRadixBins * std::max(p.nb_vn, p.nb_m));
@@ -563,8 +613,18 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                        uint64_t* keys64 = nullptr, const float* rec = nullptr) {
   hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, kin, d_count, shift, nb, hist);
   hipLaunchKernelGGL(k_radix_scan_digit, dim3(kRadixBins), dim3(kSortThreads), 0, st, hist, nb, dtot);
-  hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, d_count, shift, nb,
-                     hist, dtot, keys64, rec);
+  hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, EmitSrc{}, kout, vout,
+                     d_count, shift, nb, hist, dtot, keys64, rec);
+}
+
+// The first tile-digit pass over the incidences generated by emission.
+static void radix_pass_emit(const EmitSrc& es, uint32_t* kout, uint32_t* vout, const uint32_t* d_m, int shift,
+                            int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st, uint64_t* keys64,
+                            const float* rec) {
+  hipLaunchKernelGGL(k_emit_hist, dim3(nb), dim3(kSortThreads), 0, st, es, d_m, shift, nb, hist);
+  hipLaunchKernelGGL(k_radix_scan_digit, dim3(kRadixBins), dim3(kSortThreads), 0, st, hist, nb, dtot);
+  hipLaunchKernelGGL(k_radix_scatter<true>, dim3(nb), dim3(kSortThreads), 0, st, (const uint32_t*)nullptr,
+                     (const uint32_t*)nullptr, es, kout, vout, d_m, shift, nb, hist, dtot, keys64, rec);
 }
 
 }  // namespace gs
@@ -608,8 +668,7 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   uint64_t* part_a = reinterpret_cast<uint64_t*>(ws + p.off_part_a);
   uint64_t* step_off = reinterpret_cast<uint64_t*>(ws + p.off_steps);
   uint64_t* ent_off = reinterpret_cast<uint64_t*>(ws + p.off_eoff);
-  uint32_t* ent_base = reinterpret_cast<uint32_t*>(ws + p.off_ebase);
-  uint32_t* ent_txw = reinterpret_cast<uint32_t*>(ws + p.off_etxw);
+  uint4* ent_rec = reinterpret_cast<uint4*>(ws + p.off_erec);
   uint32_t* chunk_start = reinterpret_cast<uint32_t*>(ws + p.off_chunks);
   int32_t* cover = reinterpret_cast<int32_t*>(ws + p.off_cover);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
@@ -650,19 +709,29 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   const uint64_t gcount = (uint64_t)vt.total_grid;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>(4096, (gcount + 255) / 256)), dim3(256), 0, st,
                      reinterpret_cast<uint32_t*>(cover), gcount, 0u);
+  int max_cells = 0;
+  for (int v = 0; v < n_views; ++v) max_cells = std::max(max_cells, (vt.v[v].TX + 1) * (vt.v[v].TY + 1));
+  const int priv = max_cells <= kCoverLdsCells ? 1 : 0;
+  hipLaunchKernelGGL(k_cover_counts, dim3((unsigned)((n + kCoverPairs - 1) / kCoverPairs), (unsigned)n_views),
+                     dim3(kSortThreads), priv ? sizeof(int32_t) * (size_t)max_cells : 0, st, proj->tiles_touched,
+                     proj->rec, vt, (uint32_t)n, priv, cover);
   hipLaunchKernelGGL(k_entry_offsets, dim3(p.grid_steps), dim3(kSortThreads), 0, st, proj->tiles_touched, aval,
-                     proj->rec, d_k, step_off, vt, (uint32_t)n, p.cap, ent_off, ent_base, ent_txw, chunk_start, cover);
-  const unsigned emit_grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(16384, (p.cap + kChunk - 1) / kChunk));
-  hipLaunchKernelGGL(k_emit_chunks, dim3(emit_grid), dim3(kSortThreads), 0, st, aval, d_k, d_m, ent_off, ent_base,
-                     ent_txw, chunk_start, pkey[0], vbuf[0]);
+                     proj->rec, d_k, step_off, vt, (uint32_t)n, p.cap, ent_off, ent_rec, chunk_start);
   // 4. tile ranges from the per-tile incidence counts (rect coverage)
   hipLaunchKernelGGL(k_tile_counts, dim3(n_views), dim3(kSortThreads), 0, st, vt, cover);
   hipLaunchKernelGGL(k_ranges_from_counts, dim3(1), dim3(kScanThreads), 0, st, vt, cover, d_m, bins->ranges);
-  // 5. tile digits; the last pass writes only the ids (and the optional 64-bit keys)
+  // 5. tile digits, the first pass fed by emission; the last pass writes only the ids (and the optional
+  //    64-bit keys)
+  const EmitSrc es{d_k, ent_off, ent_rec, chunk_start};
   for (int k = 0; k < p.tile_passes; ++k) {
     const bool last = k + 1 == p.tile_passes;
-    radix_pass(pkey[k % 2], vbuf[k % 2], last ? nullptr : pkey[(k + 1) % 2], vbuf[(k + 1) % 2], d_m, kRadixBits * k,
-               p.nb_m, hist, dtot, st, last ? bins->keys : nullptr, proj->rec);
+    uint32_t* kout = last ? nullptr : pkey[(k + 1) % 2];
+    uint64_t* k64 = last ? bins->keys : nullptr;
+    if (k == 0)
+      radix_pass_emit(es, kout, vbuf[(k + 1) % 2], d_m, 0, p.nb_m, hist, dtot, st, k64, proj->rec);
+    else
+      radix_pass(pkey[k % 2], vbuf[k % 2], kout, vbuf[(k + 1) % 2], d_m, kRadixBits * k, p.nb_m, hist, dtot, st, k64,
+                 proj->rec);
   }
   return check_launch("bin/sort");
 }
