@@ -105,8 +105,8 @@ typedef struct gs_params {
  * values noted on the right. */
 typedef struct gs_options {
   int32_t tile_size;     /* B: 8, 16 or 32 (16) */
-  int32_t checkpoint;    /* 1: forward does not store t_final/n_contrib;
-                            backward recomputes them (0) */
+  int32_t checkpoint;    /* 1: forward does not store t_final/n_contrib
+                            (the backward never needs them) (0) */
   float near_plane;      /* cull when camera depth <= near_plane (0.2) */
   float eps2d;           /* added to the 2D covariance diagonal, px^2 (0.3) */
   float alpha_min;       /* blend only alpha >= alpha_min (1/255) */
@@ -154,7 +154,7 @@ typedef struct gs_bins {
 /* Rendered views.  rgb [sum_v 3*H_v*W_v]: view v at 3*pix_off(v), planar
  * [3][H_v][W_v]; t_final (final transmittance) and n_contrib (1 + list
  * position of the last blended Gaussian, 0 if none) [sum_v H_v*W_v]; both
- * may be NULL when options.checkpoint is set. */
+ * may be NULL when options.checkpoint is set.  The backward reads only rgb. */
 typedef struct gs_image {
   float* rgb;
   float* t_final;
@@ -245,14 +245,16 @@ gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs_bins* bins
 
 /* Backward of the rasteriser and the projection (the differentiable part of
  * Sec. III-B): dL/dimage from `loss` (L1 of eq. (2), or external), then for
- * every pixel a back-to-front replay of its blended Gaussians giving
- * d/d(mean2d, conic, opacity, colour), summed per (view, Gaussian) into the
- * image-space gradient buffer held in `workspace` ([n_views*n][9] floats,
- * order mean_x, mean_y, conic a, b, c, opacity, r, g, b; readable by the
- * caller after the call), then chained through the projection to the raw
- * parameters and added into `grads`.  With options.checkpoint set, t_final
- * and n_contrib are recomputed by a forward replay instead of read from
- * `img`.  `workspace` must hold gs_render_bwd_workspace_size() bytes. */
+ * every pixel one front-to-back sweep over its list with the forward's
+ * decisions, giving d/d(mean2d, conic, opacity, colour) of each blended
+ * Gaussian (the colour behind entry k is the rendered value img->rgb minus
+ * the colour blended up to k, so t_final and n_contrib are not read), summed
+ * per (view, Gaussian) into the image-space gradient buffer held in
+ * `workspace` ([n_views*n][9] floats, order mean_x, mean_y, conic a, b, c,
+ * opacity, r, g, b; readable by the caller after the call), then chained
+ * through the projection to the raw parameters and added into `grads`.
+ * img->rgb must be the image gs_render_fwd wrote for these inputs.
+ * `workspace` must hold gs_render_bwd_workspace_size() bytes. */
 gs_status gs_render_bwd(const gs_params* params, const gs_projected* proj, const gs_bins* bins,
                         const gs_image* img, const gs_camera* cams, int32_t n_views, const gs_options* opts,
                         const gs_loss* loss, const gs_grads* grads, void* workspace, size_t workspace_bytes,
@@ -264,7 +266,7 @@ gs_status gs_render_bwd(const gs_params* params, const gs_projected* proj, const
  * gs_raster_bwd: backward of the blending only (Sec. II / III-B): ADDS, for
  * every (view, Gaussian) pair, d(loss)/d(mean_x, mean_y, conic a, b, c,
  * opacity, r, g, b) into grad2d ([n_views*n][9] FP32, device; the caller
- * clears it).  Loss, image and checkpoint semantics as gs_render_bwd.
+ * clears it).  Loss and image semantics as gs_render_bwd.
  *
  * gs_project_bwd: backward of the projection: chains grad2d (same layout)
  * through gs_project's mapping to the raw parameters and ADDS the result into

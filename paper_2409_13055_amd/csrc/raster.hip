@@ -127,25 +127,34 @@ struct PixMap {
   __device__ int chan(int p, int c) const { return 3 * pix_off + c * W * H + (y0 + p) * W + x; }
 };
 
-// Tile-level cull bound of a splat: the squared distance from its mean beyond
-// which opacity * exp(-q/2) < alpha_min * (1 - 1e-3), using
-// q = d^T Q d >= lambda_min(Q) |d|^2 for the conic Q = [[a,b],[b,c]] the
-// pixels are evaluated with.  lambda_min(Q) = det(Q) / lambda_max(Q), with
-// det(Q) formed in double (products of FP32 values are exact there), so the
-// bound holds for the FP32 conic however elongated the splat.  If no pixel of
-// a wavefront's pixel block is that close, every one of its pixels would skip
-// the splat (alpha < alpha_min), so the wave skips it with one uniform test;
-// the margins keep that decision identical to the per-pixel FP32 one.
-// Negative: the splat can never reach alpha_min.
-__device__ __forceinline__ float cull_threshold(float ca, float cb, float cc, float opacity, float alpha_min) {
+// Wave-level cull bounds of a splat.  A pixel can reach
+// opacity * exp(-q/2) >= alpha_min * (1 - 1e-3) only where
+// q = d^T Q d <= thr = 2 ln(opacity / (alpha_min (1 - 1e-3))), for the conic
+// Q = [[a,b],[b,c]] the pixels are evaluated with.  That ellipse lies inside
+// the disc |d|^2 <= thr / lambda_min(Q) (r2) and inside the box
+// |dx| <= sqrt(thr S_xx), |dy| <= sqrt(thr S_yy) with S = Q^-1 (ex, ey; the
+// box is the tighter bound for elongated splats, the disc near the corners of
+// round ones).  det(Q) is formed in double (products of FP32 values are exact
+// there), so the bounds hold for the FP32 conic however elongated the splat;
+// lambda_min and the box carry a further 1e-3 margin.  If a wavefront's pixel
+// block lies outside either bound, every one of its pixels would skip the
+// splat (alpha < alpha_min), so the wave skips it with one uniform test.
+// Negative bounds: the splat can never reach alpha_min.
+struct CullBounds {
+  float r2, ex, ey;
+};
+__device__ __forceinline__ CullBounds cull_bounds(float ca, float cb, float cc, float opacity, float alpha_min) {
   const float amin = alpha_min * 0.999f;
-  if (!(opacity >= amin)) return -1.0f;
+  if (!(opacity >= amin)) return CullBounds{-1.0f, -1.0f, -1.0f};
   const double det = (double)ca * (double)cc - (double)cb * (double)cb;
   const float h = 0.5f * (ca - cc);
   const float lmax = 0.5f * (ca + cc) + sqrtf(h * h + cb * cb);
-  if (!(det > 0.0) || !(lmax > 0.0f)) return 3.0e38f;  // no usable bound: never cull
+  if (!(det > 0.0) || !(lmax > 0.0f)) return CullBounds{3.0e38f, 3.0e38f, 3.0e38f};  // no usable bound
+  const float thr = 2.0f * __logf(opacity / amin);
   const float lmin = (float)(det / (double)lmax) * 0.999f;
-  return 2.0f * __logf(opacity / amin) / lmin;
+  const float ex = sqrtf(thr * (float)((double)cc / det)) * 1.001f;
+  const float ey = sqrtf(thr * (float)((double)ca / det)) * 1.001f;
+  return CullBounds{thr / lmin, ex, ey};
 }
 
 // One splat record staged through registers (prefetch) into LDS.
@@ -165,11 +174,12 @@ struct SplatLoader {
     }
   }
   // record: a = (mean x, mean y, conic a, conic b), b = (conic c, opacity, r, g), c = (b, ...)
-  __device__ __forceinline__ void store(float4* s_cul, float4* s_geo, float4* s_col, uint32_t* s_id, int slot,
-                                        const RasterConsts& rc) const {
+  __device__ __forceinline__ void store(float4* s_cul, float2* s_aux, float4* s_geo, float4* s_col, uint32_t* s_id,
+                                        int slot, const RasterConsts& rc) const {
     if (!valid) return;
-    s_cul[slot] = make_float4(a.x, a.y, cull_threshold(a.z, a.w, b.x, b.y, rc.alpha_min),
-                              power_cutoff(b.y, rc.alpha_min));
+    const CullBounds cb = cull_bounds(a.z, a.w, b.x, b.y, rc.alpha_min);
+    s_cul[slot] = make_float4(a.x, a.y, cb.ex, cb.ey);
+    s_aux[slot] = make_float2(cb.r2, power_cutoff(b.y, rc.alpha_min));
     s_geo[slot] = make_float4(-0.5f * a.z, -a.w, -0.5f * b.x, b.y);
     s_col[slot] = make_float4(b.z, b.w, c.x, 0.0f);
     if (s_id) s_id[slot] = id;
@@ -188,10 +198,11 @@ struct WaveBox {
     y_lo = (float)pm.wy0;
     y_hi = (float)(min(pm.wy0 + PM::SUBH, pm.H) - 1);
   }
-  __device__ __forceinline__ bool culled(float mx, float my, float thr) const {
-    const float dx = fmaxf(fmaxf(x_lo - mx, mx - x_hi), 0.0f);
-    const float dy = fmaxf(fmaxf(y_lo - my, my - y_hi), 0.0f);
-    return dx * dx + dy * dy > thr;
+  // cu = (mean x, mean y, ex, ey), r2: see cull_bounds
+  __device__ __forceinline__ bool culled(const float4& cu, float r2) const {
+    const float ox = fmaxf(x_lo - cu.x, cu.x - x_hi), oy = fmaxf(y_lo - cu.y, cu.y - y_hi);  // > 0: outside
+    const float dx = fmaxf(ox, 0.0f), dy = fmaxf(oy, 0.0f);
+    return ox > cu.z || oy > cu.w || dx * dx + dy * dy > r2;
   }
 };
 
@@ -206,6 +217,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
   using PM = PixMap<TILE>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
   __shared__ float4 s_cul[NT];
+  __shared__ float2 s_aux[NT];
   __shared__ float4 s_geo[NT];
   __shared__ float4 s_col[NT];
   __shared__ float s_loss[PM::WAVES];
@@ -233,21 +245,22 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
 #pragma unroll
     for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
     if (__syncthreads_count(alive) == 0) break;
-    ld.store(s_cul, s_geo, s_col, nullptr, threadIdx.x, rc);
+    ld.store(s_cul, s_aux, s_geo, s_col, nullptr, threadIdx.x, rc);
     __syncthreads();
     ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);  // next batch, in flight during this one
     // a wavefront whose pixels have all stopped only keeps the block's barriers
     const int cnt = __ballot(alive) != 0ull ? min(NT, e - base) : 0;
     for (int j = 0; j < cnt; ++j) {
       const float4 cu = s_cul[j];
-      if (box.culled(cu.x, cu.y, cu.z)) continue;
+      const float2 ax = s_aux[j];
+      if (box.culled(cu, ax.x)) continue;
       const float4 geo = s_geo[j];
       const float4 col = s_col[j];
       const RowTerms rt = row_terms(fx - cu.x, geo);
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         const float power = splat_power(rt, geo.z, fy[p] - cu.y);
-        if (done[p] || !(power >= cu.w) || power > 0.0f) continue;
+        if (done[p] || !(power >= ax.y) || power > 0.0f) continue;
         const float alpha = fminf(amax, geo.w * exp_hw(power));
         if (alpha < rc.alpha_min) continue;
         const float test = T[p] * (1.0f - alpha);
@@ -373,19 +386,22 @@ __device__ LaneRole wave_roles(int lane) {
   return rl;
 }
 
-template <int TILE, bool CKPT>
+// One front-to-back sweep per pixel, with the forward's decisions: the colour
+// behind entry k is S_k = C_pixel - sum_{m<=k} c_m alpha_m T_m (C_pixel the
+// rendered value, background included), so neither the final transmittance
+// nor the contributor count is needed and nothing is replayed or divided.
+template <int TILE>
 __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
-    RasterConsts rc, const float* __restrict__ img, const float* __restrict__ tfin, const int32_t* __restrict__ ncon,
-    int loss_kind, const float* __restrict__ target, const float* __restrict__ dl_dimage,
-    float* __restrict__ grad2d) {
+    RasterConsts rc, const float* __restrict__ img, int loss_kind, const float* __restrict__ target,
+    const float* __restrict__ dl_dimage, float* __restrict__ grad2d) {
   using PM = PixMap<TILE>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
   __shared__ float4 s_cul[NT];
+  __shared__ float2 s_aux[NT];
   __shared__ float4 s_geo[NT];
   __shared__ float4 s_col[NT];
   __shared__ uint32_t s_id[NT];
-  __shared__ int s_max[PM::WAVES];
   const PM pm(vt, blockIdx.x);
   const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
   const WaveBox box(pm);
@@ -394,110 +410,47 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
   const float fx = (float)pm.x;
   const int lane = threadIdx.x & 63;
   const LaneRole role = wave_roles(lane);
-  float T[PPL], dl[PPL][3], DS[PPL], fy[PPL];
-  int last[PPL];
-  SplatLoader ld;
-#pragma unroll
-  for (int p = 0; p < PPL; ++p) fy[p] = (float)(pm.y0 + p);
-
-  if (CKPT) {
-    // Forward replay: final transmittance and contributor count only.
-    bool done[PPL];
-#pragma unroll
-    for (int p = 0; p < PPL; ++p) {
-      T[p] = 1.0f;
-      last[p] = 0;
-      done[p] = !pm.inside(p);
-    }
-    ld.fetch(rec, ids, s + (int)threadIdx.x, s, e);
-    for (int base = s; base < e; base += NT) {
-      int alive = 0;
-#pragma unroll
-      for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
-      if (__syncthreads_count(alive) == 0) break;
-      ld.store(s_cul, s_geo, s_col, nullptr, threadIdx.x, rc);
-      __syncthreads();
-      ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);
-      const int cnt = __ballot(alive) != 0ull ? min(NT, e - base) : 0;
-      for (int j = 0; j < cnt; ++j) {
-        const float4 cu = s_cul[j];
-        if (box.culled(cu.x, cu.y, cu.z)) continue;
-        const float4 geo = s_geo[j];
-        const RowTerms rt = row_terms(fx - cu.x, geo);
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-          const float power = splat_power(rt, geo.z, fy[p] - cu.y);
-          if (done[p] || !(power >= cu.w) || power > 0.0f) continue;
-          const float alpha = fminf(amax, geo.w * exp_hw(power));
-          if (alpha < rc.alpha_min) continue;
-          const float test = T[p] * (1.0f - alpha);
-          if (test < rc.t_min) {
-            done[p] = true;
-            continue;
-          }
-          T[p] = test;
-          last[p] = base - s + j + 1;
-        }
-      }
-    }
-    __syncthreads();
-  } else {
-#pragma unroll
-    for (int p = 0; p < PPL; ++p) {
-      T[p] = pm.inside(p) ? tfin[pm.pix(p)] : 1.0f;
-      // a contributor count never exceeds the tile's list length
-      last[p] = pm.inside(p) ? min(max(ncon[pm.pix(p)], 0), e - s) : 0;
-    }
-  }
+  // per pixel: transmittance in front of the current entry, colour still behind it, dL/dC
+  float T[PPL], S[PPL][3], dl[PPL][3], fy[PPL];
+  bool done[PPL];
   const float wv = 1.0f / (3.0f * (float)pm.W * (float)pm.H);
-  int mylast = 0;
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
-    if (pm.inside(p)) {
+    fy[p] = (float)(pm.y0 + p);
+    T[p] = 1.0f;
+    done[p] = !pm.inside(p);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float d;
+    for (int c = 0; c < 3; ++c) {
+      float d = 0.0f, col = 0.0f;
+      if (pm.inside(p)) {
+        col = img[pm.chan(p, c)];
         if (loss_kind == GS_LOSS_L1) {
-          const float r = img[pm.chan(p, c)] - target[pm.chan(p, c)];
+          const float r = col - target[pm.chan(p, c)];
           d = r > 0.0f ? wv : (r < 0.0f ? -wv : 0.0f);
         } else {
           d = dl_dimage[pm.chan(p, c)];
         }
-        dl[p][c] = d;
       }
-    } else {
-      dl[p][0] = dl[p][1] = dl[p][2] = 0.0f;
+      dl[p][c] = d;
+      S[p][c] = col;
     }
-    // dL/dC . S, where S = colour accumulated behind the current entry (the background at first)
-    DS[p] = T[p] * (dl[p][0] * rc.bg0 + dl[p][1] * rc.bg1 + dl[p][2] * rc.bg2);
-    mylast = max(mylast, last[p]);
   }
-  // Longest blended prefix of the wavefront, then of the tile.
-  for (int o = 32; o > 0; o >>= 1) mylast = max(mylast, __shfl_xor(mylast, o));
-  if (lane == 0) s_max[threadIdx.x >> 6] = mylast;
-  __syncthreads();
-  int max_last = 0;
-#pragma unroll
-  for (int w = 0; w < PM::WAVES; ++w) max_last = max(max_last, s_max[w]);
-
   Acc9 acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  // Back to front over [s, s + max_last) in batches of NT, prefetching the
-  // batch in front of the current one.
-  int hi = max_last;
-  ld.fetch(rec, ids, s + max(0, hi - NT) + (int)threadIdx.x, s + max(0, hi - NT), s + hi);
-  for (; hi > 0; hi -= NT) {
-    const int lo = max(0, hi - NT);
-    ld.store(s_cul, s_geo, s_col, s_id, threadIdx.x, rc);
+  SplatLoader ld;
+  ld.fetch(rec, ids, s + (int)threadIdx.x, s, e);
+  for (int base = s; base < e; base += NT) {
+    int alive = 0;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
+    if (__syncthreads_count(alive) == 0) break;
+    ld.store(s_cul, s_aux, s_geo, s_col, s_id, threadIdx.x, rc);
     __syncthreads();
-    {
-      const int nlo = max(0, lo - NT);
-      ld.fetch(rec, ids, s + nlo + (int)threadIdx.x, s + nlo, s + lo);
-    }
-    // entries at or past the wavefront's longest prefix contribute to none of its pixels
-    for (int k = min(hi, mylast) - 1; k >= lo; --k) {
-      const int j = k - lo;
+    ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);  // next batch, in flight during this one
+    const int cnt = __ballot(alive) != 0ull ? min(NT, e - base) : 0;
+    for (int j = 0; j < cnt; ++j) {
       const float4 cu = s_cul[j];
-      if (box.culled(cu.x, cu.y, cu.z)) continue;
+      const float2 ax = s_aux[j];
+      if (box.culled(cu, ax.x)) continue;
       const float4 geo = s_geo[j];
       const float4 col = s_col[j];
       const float dx = fx - cu.x;
@@ -507,21 +460,29 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
       for (int p = 0; p < PPL; ++p) {
         const float dy = fy[p] - cu.y;
         const float power = splat_power(rt, geo.z, dy);
-        if (k >= last[p] || !(power >= cu.w) || power > 0.0f) continue;
+        if (done[p] || !(power >= ax.y) || power > 0.0f) continue;
         const float G = exp_hw(power);
         const float oG = geo.w * G;
         const float alpha = fminf(amax, oG);
         if (alpha < rc.alpha_min) continue;
+        const float om = 1.0f - alpha;
+        const float test = T[p] * om;
+        if (test < rc.t_min) {
+          done[p] = true;
+          continue;
+        }
         any = true;
-        const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-        T[p] *= inv;  // transmittance in front of this entry
         const float wgt = alpha * T[p];
+        S[p][0] = fmaf(-col.x, wgt, S[p][0]);
+        S[p][1] = fmaf(-col.y, wgt, S[p][1]);
+        S[p][2] = fmaf(-col.z, wgt, S[p][2]);
         acc.r = fmaf(dl[p][0], wgt, acc.r);
         acc.g = fmaf(dl[p][1], wgt, acc.g);
         acc.b = fmaf(dl[p][2], wgt, acc.b);
         const float dc = fmaf(dl[p][2], col.z, fmaf(dl[p][1], col.y, dl[p][0] * col.x));
-        const float dLda = fmaf(T[p], dc, -inv * DS[p]);
-        DS[p] = fmaf(dc, wgt, DS[p]);
+        const float ds = fmaf(dl[p][2], S[p][2], fmaf(dl[p][1], S[p][1], dl[p][0] * S[p][0]));
+        const float dLda = fmaf(T[p], dc, -ds * __builtin_amdgcn_rcpf(om));
+        T[p] = test;
         const bool unclamped = oG <= amax;  // d alpha / d(o, power) = 0 where clamped
         const float dLdp = unclamped ? dLda * alpha : 0.0f;
         acc.o = fmaf(dLda, unclamped ? G : 0.0f, acc.o);
@@ -542,7 +503,6 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
         acc = Acc9{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       }
     }
-    __syncthreads();
   }
 }
 
@@ -558,6 +518,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
   using PM = PixMap<TILE>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
   __shared__ float4 s_cul[NT];
+  __shared__ float2 s_aux[NT];
   __shared__ float4 s_geo[NT];
   __shared__ float4 s_col[NT];
   const PM pm(vt, blockIdx.x);
@@ -582,7 +543,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
     for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
     if (__syncthreads_count(alive) == 0) break;
     ld.fetch(rec, ids, base + (int)threadIdx.x, s, e);
-    ld.store(s_cul, s_geo, s_col, nullptr, threadIdx.x, rc);
+    ld.store(s_cul, s_aux, s_geo, s_col, nullptr, threadIdx.x, rc);
     __syncthreads();
     const int cnt = min(NT, e - base);
     for (int j = 0; j < cnt; ++j) {
@@ -721,15 +682,13 @@ extern "C" gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs
 
 namespace gs {
 
-static gs_status validate_loss_bwd(const gs_loss* loss, const gs_image* img, const gs_options* opts) {
+static gs_status validate_loss_bwd(const gs_loss* loss, const gs_image* img) {
   if (!loss || (loss->kind != GS_LOSS_L1 && loss->kind != GS_LOSS_EXTERNAL))
     return fail(GS_ERR_INVALID_VALUE, "loss must be GS_LOSS_L1 or GS_LOSS_EXTERNAL");
-  if (loss->kind == GS_LOSS_L1 && (!loss->target || !img || !img->rgb))
-    return fail(GS_ERR_INVALID_VALUE, "L1 loss needs target and img->rgb");
+  if (!img || !img->rgb) return fail(GS_ERR_INVALID_VALUE, "img->rgb (the forward's image) is required");
+  if (loss->kind == GS_LOSS_L1 && !loss->target) return fail(GS_ERR_INVALID_VALUE, "L1 loss needs a target");
   if (loss->kind == GS_LOSS_EXTERNAL && !loss->dl_dimage)
     return fail(GS_ERR_INVALID_VALUE, "external loss needs dl_dimage");
-  if (!opts->checkpoint && (!img || !img->t_final || !img->n_contrib))
-    return fail(GS_ERR_INVALID_VALUE, "img->t_final/n_contrib are required unless checkpoint is set");
   return GS_OK;
 }
 
@@ -747,24 +706,13 @@ static void launch_raster_bwd(const ViewTable& vt, const gs_projected* proj, con
   const RasterConsts rc = consts_of(opts);
   const dim3 grid((unsigned)vt.total_tiles);
   const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
-  const float* rgb = img ? img->rgb : nullptr;
-  const float* tf = img ? img->t_final : nullptr;
-  const int32_t* nc = img ? img->n_contrib : nullptr;
-#define GS_BWD(TILE, NT, CK)                                                                                        \
-  hipLaunchKernelGGL((k_render_bwd<TILE, CK>), grid, dim3(NT), 0, st, vt, proj->rec, bins->ids, rg, rc, rgb, tf, nc, \
+#define GS_BWD(TILE, NT)                                                                                      \
+  hipLaunchKernelGGL((k_render_bwd<TILE>), grid, dim3(NT), 0, st, vt, proj->rec, bins->ids, rg, rc, img->rgb, \
                      (int)loss->kind, loss->target, loss->dl_dimage, g2)
-  if (opts->checkpoint) {
-    switch (opts->tile_size) {
-      case 8: GS_BWD(8, 64, true); break;
-      case 16: GS_BWD(16, 64, true); break;
-      default: GS_BWD(32, 256, true); break;
-    }
-  } else {
-    switch (opts->tile_size) {
-      case 8: GS_BWD(8, 64, false); break;
-      case 16: GS_BWD(16, 64, false); break;
-      default: GS_BWD(32, 256, false); break;
-    }
+  switch (opts->tile_size) {
+    case 8: GS_BWD(8, 64); break;
+    case 16: GS_BWD(16, 64); break;
+    default: GS_BWD(32, 256); break;
   }
 #undef GS_BWD
 }
@@ -778,7 +726,7 @@ extern "C" gs_status gs_raster_bwd(const gs_projected* proj, int64_t n, const gs
   gs_status s;
   if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
   if (n < 1) return fail(GS_ERR_INVALID_VALUE, "n must be >= 1");
-  if ((s = validate_loss_bwd(loss, img, opts)) != GS_OK) return s;
+  if ((s = validate_loss_bwd(loss, img)) != GS_OK) return s;
   if (!grad2d) return fail(GS_ERR_INVALID_VALUE, "grad2d is NULL");
   const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
   launch_raster_bwd(vt, proj, bins, img, opts, loss, grad2d, as_stream(stream));
@@ -807,7 +755,7 @@ extern "C" gs_status gs_render_bwd(const gs_params* params, const gs_projected* 
   gs_status s;
   if ((s = validate_params(params)) != GS_OK) return s;
   if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
-  if ((s = validate_loss_bwd(loss, img, opts)) != GS_OK) return s;
+  if ((s = validate_loss_bwd(loss, img)) != GS_OK) return s;
   if ((s = validate_grads(params, grads)) != GS_OK) return s;
   const size_t g2n = (size_t)GS_GRAD2D_FLOATS * (size_t)params->n * (size_t)n_views;
   if (!workspace || workspace_bytes < sizeof(float) * g2n)

@@ -11,7 +11,7 @@ Per-unit figures (P_n = 11 + 3K raw floats per Gaussian, K = (D+1)^2):
   project     N*4*P_n + V*N*(48 + 4)
   bin_sort    V*N*8 + M*(12 + 24 + 8) + T*8
   render_fwd  Nv*36 + M*4 + Px*(12 + 12 [target] + 8 [T_final, n_contrib unless checkpoint])
-  raster_bwd  Px*(12 + 12 + 8 [unless checkpoint]) + Nv*36 + M*4 + V*N*36
+  raster_bwd  Px*(12 [image] + 12 [target]) + Nv*36 + M*4 + V*N*36
   project_bwd N*(4*P_n + 8*P_n) + V*N*(36 + 16)
   render_bwd  raster_bwd + project_bwd
   adam        N*P_n*32  (read p, g, m, v; write p, m, v, g := 0)
@@ -28,18 +28,18 @@ import torch
 #                        power > 0 test 1; exp 2; opacity * G 1; min 1;
 #                        alpha test 1
 #   blended, forward +10: 1 - alpha, T (1 - alpha), T test, weight, colour 3 FMA
-#   blended, backward +54: 1/(1 - alpha) 2, T update 1, weight 1, colour grads
-#                        3 FMA, dL/dalpha 15, S update 3 FMA, clamp test 1,
-#                        dL/dpower 1, opacity grad FMA, mean grads 2 x 5,
-#                        conic grads 3 x 3
-#   blended, replay   +4: 1 - alpha, T (1 - alpha), T test, T store
-# The counts come from gs_render_stats (the blending as defined, no tile
-# cull): E_eval entries evaluated until each pixel stops, E_blend blended
-# pairs, E_contrib = sum of n_contrib (the entries the backward revisits).
+#   blended, backward +44: 1 - alpha, T (1 - alpha), T test, weight, colour
+#                        behind (3 FMA), colour grads (3 FMA), dL/dC . c and
+#                        dL/dC . S (mul + 2 FMA each), reciprocal, dL/dalpha
+#                        (mul + FMA), clamp test, dL/dpower, opacity grad FMA,
+#                        u dx and u dy, moments (2 add + 3 FMA)
+# The backward sweeps each pixel's list front to back with the forward's
+# decisions, so it evaluates the same entries as the forward.  The counts come
+# from gs_render_stats (the blending as defined, no cull): E_eval entries
+# evaluated until each pixel stops, E_blend blended pairs.
 FLOPS_EVAL = 17
 FLOPS_FWD_BLEND = 10
-FLOPS_BWD_BLEND = 54
-FLOPS_REPLAY_BLEND = 4
+FLOPS_BWD_BLEND = 44
 
 
 def counts(step, sc):
@@ -54,7 +54,7 @@ def counts(step, sc):
 def algorithmic_bytes(c):
     N, V, Pn, M, Nv, Px, T = c["N"], c["V"], c["Pn"], c["M"], c["Nv"], c["Px"], c["T"]
     saved = 0 if c["ckpt"] else 8
-    raster_bwd = Px * (24 + saved) + Nv * 36 + M * 4 + V * N * 36
+    raster_bwd = Px * 24 + Nv * 36 + M * 4 + V * N * 36
     project_bwd = N * 12 * Pn + V * N * 52
     return {
         "project": N * 4 * Pn + V * N * 52,
@@ -72,13 +72,9 @@ def evaluations(step):
     return step.rast.render_stats(step.frame)
 
 
-def alu_flops(kernel, ev, ckpt):
-    if kernel == "render_fwd":
-        return ev["evaluated"] * FLOPS_EVAL + ev["blended"] * FLOPS_FWD_BLEND
-    f = ev["contrib_prefix"] * FLOPS_EVAL + ev["blended"] * FLOPS_BWD_BLEND
-    if ckpt:
-        f += ev["evaluated"] * FLOPS_EVAL + ev["blended"] * FLOPS_REPLAY_BLEND
-    return f
+def alu_flops(kernel, ev):
+    blend = FLOPS_FWD_BLEND if kernel == "render_fwd" else FLOPS_BWD_BLEND
+    return ev["evaluated"] * FLOPS_EVAL + ev["blended"] * blend
 
 
 SINGLE_KERNEL_CALLS = ("project", "render_fwd", "raster_bwd", "project_bwd", "adam")
@@ -94,7 +90,7 @@ def report(step, sc, stages_ms, hbm_peak_gbs, valu_peak_tflops, traffic=None):
     per_stage = {k: {"ms": stages_ms[k], "alg_bytes": b[k], "GBps": round(b[k] / (stages_ms[k] * 1e-3) / 1e9, 1)}
                  for k in stages_ms if k in b}
     if dom in ("render_fwd", "raster_bwd"):
-        flops = alu_flops(dom, ev, c["ckpt"])
+        flops = alu_flops(dom, ev)
         achieved = flops / (ms * 1e-3) / 1e12
         out = {"bound": "alu", "achieved": round(achieved, 3), "peak": valu_peak_tflops, "unit": "TFLOP/s",
                "frac": round(achieved / valu_peak_tflops, 4), "traffic": traffic, "kernel": dom,
