@@ -68,6 +68,9 @@ def main():
         f"({time.time() - t0:.1f}s to generate)")
     params = R.GaussianParams.from_scene(sc, dev)
     target = R.pack_images(sc.targets, dev)
+    # Every timed phase starts from these parameters and a fresh optimiser state: the iterations
+    # train the Gaussians, which changes the work per iteration as it goes.
+    initial = [t.detach().cpu() for t in params.tensors()]
     with_adam = "adam" in sc.work
     lrs = sc.lrs or dict(S.DEFAULT_LRS)
     tile = args.tile
@@ -98,10 +101,22 @@ def main():
         log("[bench] profile steps done")
         return
 
+    def reset(st):
+        for t, t0 in zip(params.tensors(), initial):
+            t.copy_(t0)
+        for t in st.grads.tensors():
+            t.zero_()
+        if st.adam is not None:
+            for t in st.adam.exp_avg.tensors() + st.adam.exp_avg_sq.tensors():
+                t.zero_()
+            st.adam.d_step.zero_()
+        torch.cuda.synchronize()
+
     use_graph = not args.no_graph
     if use_graph:
         step.capture()
     run = step.replay if use_graph else step.run
+    reset(step)
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -124,6 +139,9 @@ def main():
     # The same iteration issued eagerly (no graph), for comparison.
     eager_ms = None
     if use_graph:
+        reset(step)
+        for _ in range(args.warmup):
+            step.run()
         torch.cuda.synchronize()
         e0.record()
         for _ in range(args.steps):
@@ -134,7 +152,10 @@ def main():
         log(f"[bench] eager (no graph): {eager_ms:.3f} ms/step")
 
     # Per-call breakdown (eager, events around each C call) and the dominant kernel.
-    stages = stage_breakdown(step, args.steps)
+    reset(step)
+    for _ in range(args.warmup):
+        step.run()
+    stages, work = stage_breakdown(step, args.steps)
     log(f"[bench] stages (ms): {stages}")
 
     per_view = None
@@ -142,6 +163,7 @@ def main():
         pv = R.PerViewMappingStep(params, sc.cameras, sc.targets, lrs=lrs, tile_size=tile,
                                   checkpoint=sc.checkpoint, with_adam=with_adam)
         pv.size()
+        reset(pv)
         for _ in range(args.warmup):
             pv.run()
         torch.cuda.synchronize()
@@ -156,7 +178,7 @@ def main():
         log(f"[bench] per-view: {ms_pv:.3f} ms/step ({per_view['batched_speedup']}x slower than batched)")
         del pv
 
-    roof = roofline(step, sc, stages)
+    roof = roofline(step, sc, stages, work)
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, tile)
     out = {
         "metric": "3DGS fwd+bwd+Adam Mpix*iter/s at 1 GPU (batched HIP-graph step)",
@@ -197,18 +219,23 @@ def stage_breakdown(step, iters):
     if step.adam is not None:
         names.append("adam")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(iters)]
+    counts = torch.zeros(iters, 3, dtype=torch.int64, device=step.params.means.device)
     torch.cuda.synchronize()
     for it in range(iters):
         marks = iter(evs[it][1:])
         evs[it][0].record()
         step.run(mark=lambda name: next(marks).record())
+        # the work counts of this iteration's lists, outside the timed stages
+        step.rast.render_stats(step.frame, out=counts[it])
     torch.cuda.synchronize()
     out = {}
     for k, name in enumerate(names):
         out[name] = round(sum(e[k].elapsed_time(e[k + 1]) for e in evs) / iters, 4)
     out["render_bwd"] = round(out["clear_grad2d"] + out["raster_bwd"] + out["project_bwd"], 4)
     out["step_eager"] = round(sum(e[0].elapsed_time(e[-1]) for e in evs) / iters, 4)
-    return out
+    mean = counts.double().mean(dim=0).tolist()
+    work = {"evaluated": mean[0], "blended": mean[1], "contrib_prefix": mean[2], "iterations": iters}
+    return out, work
 
 
 def traffic_of(kernel, tile, checkpoint, workload):
@@ -229,21 +256,23 @@ def traffic_of(kernel, tile, checkpoint, workload):
     return e.get("bytes_per_launch")
 
 
-def roofline(step, sc, stages):
-    """Roofline entry for the dominant single-kernel call (by measured duration)."""
+def roofline(step, sc, stages, work):
+    """Roofline entry for the dominant single-kernel call (by measured duration); the work counts
+    are the mean over the same iterations the durations are."""
     from paper_2409_13055_amd import roofline as RF
     tr = traffic_of("raster_bwd", step.rast.opts.tile_size, sc.checkpoint, sc.name)
-    return RF.report(step, sc, stages, hbm_peak_gbs=HBM_PEAK_GBS, valu_peak_tflops=VALU_PEAK_TFLOPS, traffic=tr)
+    return RF.report(step, sc, stages, hbm_peak_gbs=HBM_PEAK_GBS, valu_peak_tflops=VALU_PEAK_TFLOPS, traffic=tr,
+                     work=work)
 
 
 def cpu_baseline(sc, tile):
     """The FP64 oracle timed on the host cores over a bounded sample of the workload: its first
-    keyframe (the first two for multi-keyframe workloads) rendered from all Gaussians (projection,
+    keyframe (the first three for multi-keyframe workloads) rendered from all Gaussians (projection,
     binning, blending, L1, backward), plus Adam over all parameters when the workload steps the
     optimiser."""
     import oracle.oracle as O
     n_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    k = 1 if sc.n_views == 1 else 2
+    k = 1 if sc.n_views == 1 else 3
     cams, tgts = sc.cameras[:k], sc.targets[:k]
     P = O.Params.from_scene(sc)
     opts = O.Options(tile=tile)

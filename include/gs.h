@@ -123,12 +123,20 @@ void gs_default_options(gs_options* opts);
 
 /* Projected (view, Gaussian) records, FP32, [n_views*n][GS_REC_FLOATS]:
  *   0 mean_x  1 mean_y  2 conic_a  3 conic_b  4 conic_c  5 opacity
- *   6 r  7 g  8 b  9 depth  10 radius (int32 bits)  11 flags (uint32 bits)
- * conic (a,b,c) is the inverse of the dilated 2D covariance [[a,b],[b,c]];
- * radius 0 marks a culled pair (behind the near plane, degenerate, or no tile
- * touched).  flags bits 0-2: colour channel clamped at 0; bits 3-4: frustum
- * guard active in x / y.  tiles_touched [n_views*n] = tile count of the
- * pair's rect (0 when culled). */
+ *   6 r  7 g  8 b  9 depth  10 extents (int32 bits)  11 flags (uint32 bits)
+ * conic (a,b,c) is the inverse of the dilated 2D covariance S = [[A,B],[B,C]].
+ * extents = rx | ry << 16, the half-extents in pixels of the pair's tile
+ * rect: with r = ceil(radius_sigmas sqrt(lambda_max(S))) and
+ * thr = 2 ln(opacity / (alpha_min (1 - 1e-3))), rx = min(r, ceil(sqrt(thr A)) + 1),
+ * ry = min(r, ceil(sqrt(thr C)) + 1), all at most 32767: the box where the
+ * Gaussian can still reach alpha_min, inside the radius_sigmas square, so the
+ * rect renders like the full square.  The tile rect is
+ * [floor((mean_x - rx)/B), floor((mean_x + rx + B - 1)/B)) (FP32, clamped to
+ * the grid), likewise in y.  extents 0 marks a culled pair (behind the near
+ * plane, degenerate, opacity <= alpha_min (1 - 1e-3), or no tile touched).
+ * flags bits 0-2: colour channel clamped at 0; bits 3-4: frustum guard active
+ * in x / y.  tiles_touched [n_views*n] = tile count of the pair's rect (0 when
+ * culled). */
 typedef struct gs_projected {
   float* rec;
   int32_t* tiles_touched;

@@ -22,8 +22,19 @@
  *   near     a Gaussian with camera depth <= near_plane is culled;
  *   guard    the Jacobian uses x/z clamped to +-guard*(W/2)/fx (same for y);
  *   dilation eps2d * I is added to the 2D covariance (opacity unchanged);
- *   radius   ceil(radius_sigmas * sqrt(largest eigenvalue));
- *   rect     tiles [floor((m-r)/B), floor((m+r+B-1)/B)) in FP32, clamped;
+ *   radius   r = ceil(radius_sigmas * sqrt(largest eigenvalue)), at most 32767;
+ *   extents  the tile rect follows the axis-aligned box of the region where
+ *            opacity * exp(-q/2) can reach alpha' = alpha_min (1 - 1e-3),
+ *            cut to the r square: half-extents rx = min(r, ceil(sqrt(thr
+ *            S_xx)) + 1), ry = min(r, ceil(sqrt(thr S_yy)) + 1), thr =
+ *            2 ln(opacity / alpha'), S the dilated 2D covariance; opacity
+ *            <= alpha' culls.  The rect formula below covers every pixel
+ *            within extent - 1 of the mean (not always the last pixel before
+ *            mean + extent), hence the + 1.  Every tile of the r square left
+ *            out holds no pixel the blending would take, so the image is
+ *            that of the r-square rects;
+ *   rect     tiles [floor((m-rx)/B), floor((m+rx+B-1)/B)) in FP32 (same
+ *            for y), clamped;
  *   alpha    min(alpha_max, o exp(power)); skipped below alpha_min;
  *   stop     a Gaussian that would take transmittance below t_min is not
  *            blended and ends the pixel;
@@ -73,6 +84,7 @@ enum : uint32_t {
   F_CLAMP_R = 1u << 0, F_CLAMP_G = 1u << 1, F_CLAMP_B = 1u << 2,
   F_GUARD_X = 1u << 3, F_GUARD_Y = 1u << 4,
   F_CULL_NEAR = 1u << 8, F_CULL_DET = 1u << 9, F_CULL_RECT = 1u << 10, F_CULL_QUAT = 1u << 11,
+  F_CULL_OPACITY = 1u << 12,
   F_NEAR_RADIUS = 1u << 16, F_NEAR_RECT = 1u << 17, F_NEAR_PLANE = 1u << 18,
 };
 // Per-pixel flag bits: a decision within a relative margin of its threshold.
@@ -158,11 +170,12 @@ struct TileGrid {
 };
 inline TileGrid grid_of(int W, int H, int B) { return {(W + B - 1) / B, (H + B - 1) / B}; }
 
-// Tile rectangle [x0,x1) x [y0,y1) of a splat, defined on FP32 values.
-void tile_rect(float mx, float my, int radius, int B, TileGrid g, int rect[4]) {
-  const float r = (float)radius, fb = (float)B, fb1 = (float)(B - 1);
-  float x0 = std::floor((mx - r) / fb), x1 = std::floor(((mx + r) + fb1) / fb);
-  float y0 = std::floor((my - r) / fb), y1 = std::floor(((my + r) + fb1) / fb);
+// Tile rectangle [x0,x1) x [y0,y1) of a splat with half-extents (rx, ry),
+// defined on FP32 values.
+void tile_rect(float mx, float my, int rx, int ry, int B, TileGrid g, int rect[4]) {
+  const float ex = (float)rx, ey = (float)ry, fb = (float)B, fb1 = (float)(B - 1);
+  float x0 = std::floor((mx - ex) / fb), x1 = std::floor(((mx + ex) + fb1) / fb);
+  float y0 = std::floor((my - ey) / fb), y1 = std::floor(((my + ey) + fb1) / fb);
   auto cl = [](float v, int hi) { return (int)std::min(std::max(v, 0.0f), (float)hi); };
   rect[0] = cl(x0, g.tx); rect[1] = cl(y0, g.ty); rect[2] = cl(x1, g.tx); rect[3] = cl(y1, g.ty);
 }
@@ -179,7 +192,8 @@ inline uint32_t f32_bits(float f) {
 // ---------------------------------------------------------------------------
 struct ProjOut {
   double rec[R_STRIDE];
-  int radius;
+  int radius;   // r, 0 when culled
+  int ext[2];   // (rx, ry), 0 when culled
   int rect[4];
   uint32_t flags;
   double cov[3];  // dilated 2D covariance (a, b, c)
@@ -254,22 +268,38 @@ void project_one(const GaussIn& gi, int D, const OrCamera& cam, const OrOptions&
   const double mid = 0.5 * (a + c);
   const double lam = mid + std::sqrt(std::max(mid * mid - det, 0.0));
   const double rr = o.radius_sigmas * std::sqrt(lam);
-  out.radius = (int)std::ceil(rr);
+  out.radius = (int)std::min(std::ceil(rr), 32767.0);  // extents saturate at 32767 px
   if (near_integer(rr, 1e-5)) out.flags |= F_NEAR_RADIUS;
+
+  // Opacity-aware half-extents of the tile rect (see the header).
+  const double opacity = 1.0 / (1.0 + std::exp(-gi.logit));
+  const double alpha_p = o.alpha_min * (1.0 - 1e-3);
+  if (std::fabs(opacity / alpha_p - 1.0) <= 1e-9) out.flags |= F_NEAR_RADIUS;
+  if (!(opacity > alpha_p)) {
+    out.flags |= F_CULL_OPACITY;
+    out.radius = 0;
+    return;
+  }
+  const double thr = 2.0 * std::log(opacity / alpha_p);
+  const double ex = std::sqrt(thr * a), ey = std::sqrt(thr * c);
+  out.ext[0] = (int)std::min((double)out.radius, std::ceil(ex) + 1.0);
+  out.ext[1] = (int)std::min((double)out.radius, std::ceil(ey) + 1.0);
+  if (near_integer(ex, 1e-5) || near_integer(ey, 1e-5)) out.flags |= F_NEAR_RADIUS;
 
   const int B = o.tile;
   const TileGrid g = grid_of(cam.width, cam.height, B);
-  tile_rect((float)out.rec[R_MX], (float)out.rec[R_MY], out.radius, B, g, out.rect);
+  tile_rect((float)out.rec[R_MX], (float)out.rec[R_MY], out.ext[0], out.ext[1], B, g, out.rect);
   {
-    const double fr = out.radius;
-    const double args[4] = {(out.rec[R_MX] - fr) / B, (out.rec[R_MX] + fr + B - 1) / B,
-                            (out.rec[R_MY] - fr) / B, (out.rec[R_MY] + fr + B - 1) / B};
+    const double fx = out.ext[0], fy = out.ext[1];
+    const double args[4] = {(out.rec[R_MX] - fx) / B, (out.rec[R_MX] + fx + B - 1) / B,
+                            (out.rec[R_MY] - fy) / B, (out.rec[R_MY] + fy + B - 1) / B};
     for (double v : args)
       if (near_integer(v, 1e-5)) out.flags |= F_NEAR_RECT;
   }
   if (out.rect[2] <= out.rect[0] || out.rect[3] <= out.rect[1]) {
     out.flags |= F_CULL_RECT;
     out.radius = 0;
+    out.ext[0] = out.ext[1] = 0;
     std::memset(out.rect, 0, sizeof out.rect);
     return;
   }
@@ -289,7 +319,7 @@ void project_one(const GaussIn& gi, int D, const OrCamera& cam, const OrOptions&
     if (v < 0) { out.flags |= (F_CLAMP_R << ch); v = 0; }
     out.rec[R_R + ch] = v;
   }
-  out.rec[R_OP] = 1.0 / (1.0 + std::exp(-gi.logit));
+  out.rec[R_OP] = opacity;
 }
 
 struct ViewInfo {
@@ -581,11 +611,12 @@ void or_sh_basis(int32_t D, int64_t n, const double* dirs, double* Y, double* gr
 void or_quat_to_rot(const double* q_unit, double* R) { quat_to_rot(q_unit, R); }
 
 // Projection of n Gaussians into one view.  Outputs per Gaussian: the record
-// (mx, my, depth, conic a b c, opacity, r g b), radius (0 = culled), tile
-// rect (x0,y0,x1,y1), flag bits and the dilated 2D covariance (a, b, c).
+// (mx, my, depth, conic a b c, opacity, r g b), radius r (0 = culled), the
+// rect half-extents (rx, ry) (optional), tile rect (x0,y0,x1,y1), flag bits
+// and the dilated 2D covariance (a, b, c) (optional).
 int or_project(int64_t n, int32_t D, const double* means, const double* log_scales, const double* quats,
                const double* logits, const double* sh, const OrCamera* cam, const OrOptions* opt, double* rec,
-               int32_t* radius, int32_t* rect, uint32_t* flags, double* cov) {
+               int32_t* radius, int32_t* ext, int32_t* rect, uint32_t* flags, double* cov) {
   if (D < 0 || D > 3 || n < 0) return 1;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
@@ -593,6 +624,7 @@ int or_project(int64_t n, int32_t D, const double* means, const double* log_scal
     project_one(gauss_at(i, D, means, log_scales, quats, logits, sh), D, *cam, *opt, po);
     std::memcpy(rec + i * R_STRIDE, po.rec, sizeof po.rec);
     radius[i] = po.radius;
+    if (ext) std::memcpy(ext + 2 * i, po.ext, sizeof po.ext);
     std::memcpy(rect + 4 * i, po.rect, sizeof po.rect);
     flags[i] = po.flags;
     if (cov) std::memcpy(cov + 3 * i, po.cov, sizeof po.cov);
@@ -600,13 +632,14 @@ int or_project(int64_t n, int32_t D, const double* means, const double* log_scal
   return 0;
 }
 
-// Tile binning and ordering: every (view, Gaussian) with radius > 0 emits one
-// pair per tile of its rect, in (view, Gaussian, tile) order, keyed by
+// Tile binning and ordering: every (view, Gaussian) with half-extents
+// (rx, ry), rx > 0, emits one pair per tile of its rect, in (view, Gaussian,
+// tile) order, keyed by
 // (global tile << 32) | FP32 bits of the depth; the pairs are stably sorted
 // by key.  Inputs are FP32 records (either side's).  ranges[t] = [first,
 // last+1) of tile t in the sorted arrays, (0,0) when empty.  Returns 2 and
 // sets *n_pairs when the pair count exceeds capacity.
-int or_bin(int32_t n_views, int64_t n, const float* mean2d, const int32_t* radius, const float* depth,
+int or_bin(int32_t n_views, int64_t n, const float* mean2d, const int32_t* ext, const float* depth,
            const int32_t* wh, int32_t tile, int64_t capacity, uint64_t* keys, uint32_t* ids, uint32_t* ranges,
            int64_t* n_pairs) {
   std::vector<std::pair<uint64_t, uint32_t>> pairs;
@@ -615,9 +648,9 @@ int or_bin(int32_t n_views, int64_t n, const float* mean2d, const int32_t* radiu
     const TileGrid g = grid_of(wh[2 * v], wh[2 * v + 1], tile);
     for (int64_t i = 0; i < n; ++i) {
       const int64_t id = (int64_t)v * n + i;
-      if (radius[id] <= 0) continue;
+      if (ext[2 * id] <= 0) continue;
       int r[4];
-      tile_rect(mean2d[2 * id], mean2d[2 * id + 1], radius[id], tile, g, r);
+      tile_rect(mean2d[2 * id], mean2d[2 * id + 1], ext[2 * id], ext[2 * id + 1], tile, g, r);
       const uint32_t db = f32_bits(depth[id]);
       for (int ty = r[1]; ty < r[3]; ++ty)
         for (int tx = r[0]; tx < r[2]; ++tx) {
@@ -791,7 +824,7 @@ int or_fd_local(int64_t n, int32_t D, const double* means, const double* log_sca
   for (int v = 0; v < n_views; ++v) {
     std::vector<uint32_t> fl(n);
     or_project(n, D, means, log_scales, quats, logits, sh, &cams[v], opt, rec.data() + (size_t)v * n * R_STRIDE,
-               rad.data() + (size_t)v * n, rect.data() + (size_t)v * n * 4, fl.data(), nullptr);
+               rad.data() + (size_t)v * n, nullptr, rect.data() + (size_t)v * n * 4, fl.data(), nullptr);
   }
   const int64_t T_tot = views.back().tile_off + (int64_t)views.back().grid.tx * views.back().grid.ty;
   std::vector<std::vector<std::pair<uint32_t, uint32_t>>> lists(T_tot);

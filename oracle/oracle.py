@@ -29,7 +29,7 @@ GRAD2D_FIELDS = ("mx", "my", "ca", "cb", "cc", "opacity", "r", "g", "b")
 # Per-(view, Gaussian) flag bits (same meaning as in oracle.cpp).
 F_CLAMP_RGB = 0x7
 F_GUARD_X, F_GUARD_Y = 1 << 3, 1 << 4
-F_CULL_NEAR, F_CULL_DET, F_CULL_RECT, F_CULL_QUAT = 1 << 8, 1 << 9, 1 << 10, 1 << 11
+F_CULL_NEAR, F_CULL_DET, F_CULL_RECT, F_CULL_QUAT, F_CULL_OPACITY = 1 << 8, 1 << 9, 1 << 10, 1 << 11, 1 << 12
 F_NEAR_RADIUS, F_NEAR_RECT, F_NEAR_PLANE = 1 << 16, 1 << 17, 1 << 18
 # Per-pixel flag bits.
 P_NEAR_ALPHA_MIN, P_NEAR_T_MIN, P_NEAR_ALPHA_MAX = 1, 2, 4
@@ -80,7 +80,7 @@ def lib():
         _lib = C.CDLL(_LIB_PATH)
         P = C.c_void_p
         i64, i32 = C.c_int64, C.c_int32
-        _lib.or_project.argtypes = [i64, i32, P, P, P, P, P, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P]
+        _lib.or_project.argtypes = [i64, i32, P, P, P, P, P, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P, P]
         _lib.or_bin.argtypes = [i32, i64, P, P, P, P, i32, i64, P, P, P, P]
         _lib.or_render.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P, P, P]
         _lib.or_render_backward.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, i64, P, P]
@@ -163,16 +163,17 @@ def project(params: Params, cam, opts: Options):
     n = params.n
     rec = np.zeros((n, 10))
     radius = np.zeros(n, np.int32)
+    ext = np.zeros((n, 2), np.int32)
     rect = np.zeros((n, 4), np.int32)
     flags = np.zeros(n, np.uint32)
     cov = np.zeros((n, 3))
     cc = cameras_c([cam])
     oc = opts.as_c()
     rc = lib().or_project(n, params.sh_degree, _p(params.means), _p(params.log_scales), _p(params.quats),
-                          _p(params.opacity_logits), _p(params.sh), cc, C.byref(oc), _p(rec), _p(radius), _p(rect),
+                          _p(params.opacity_logits), _p(params.sh), cc, C.byref(oc), _p(rec), _p(radius), _p(ext), _p(rect),
                           _p(flags), _p(cov))
     assert rc == 0
-    return dict(rec=rec, radius=radius, rect=rect, flags=flags, cov=cov)
+    return dict(rec=rec, radius=radius, ext=ext, rect=rect, flags=flags, cov=cov)
 
 
 def project_views(params: Params, cams, opts: Options):
@@ -180,27 +181,28 @@ def project_views(params: Params, cams, opts: Options):
     return {k: np.concatenate([o[k] for o in outs]) for k in outs[0]}
 
 
-def bin_sort(mean2d_f32, radius, depth_f32, cams, tile, with_keys=True):
-    """Tile binning + stable key sort on FP32 records (see or_bin)."""
+def bin_sort(mean2d_f32, ext, depth_f32, cams, tile, with_keys=True):
+    """Tile binning + stable key sort on FP32 records (see or_bin).  ext: [V*N, 2] rect
+    half-extents (rx, ry), rx = 0 for culled pairs."""
     n_views = len(cams)
-    vn = radius.shape[0]
+    ext = np.ascontiguousarray(ext, np.int32).reshape(-1, 2)
+    vn = ext.shape[0]
     n = vn // n_views
     mean2d = np.ascontiguousarray(mean2d_f32, np.float32).reshape(vn, 2)
     depth = np.ascontiguousarray(depth_f32, np.float32).reshape(vn)
-    radius = np.ascontiguousarray(radius, np.int32).reshape(vn)
     wh = np.array([[c.width, c.height] for c in cams], np.int32)
     T = int(total_tiles(cams, tile))
     npairs = C.c_int64(0)
     # First call sizes the output.
     dummy = np.zeros(1, np.uint32)
     rng = np.zeros(2 * T, np.uint32)
-    lib().or_bin(n_views, n, _p(mean2d), _p(radius), _p(depth), _p(wh), tile, 0, None, _p(dummy), _p(rng),
+    lib().or_bin(n_views, n, _p(mean2d), _p(ext), _p(depth), _p(wh), tile, 0, None, _p(dummy), _p(rng),
                  C.byref(npairs))
     M = npairs.value
     keys = np.zeros(max(M, 1), np.uint64)
     ids = np.zeros(max(M, 1), np.uint32)
     ranges = np.zeros(2 * T, np.uint32)
-    rc = lib().or_bin(n_views, n, _p(mean2d), _p(radius), _p(depth), _p(wh), tile, M,
+    rc = lib().or_bin(n_views, n, _p(mean2d), _p(ext), _p(depth), _p(wh), tile, M,
                       _p(keys) if with_keys else None, _p(ids), _p(ranges), C.byref(npairs))
     assert rc == 0
     return keys[:M], ids[:M], ranges.reshape(T, 2)
@@ -346,7 +348,7 @@ def forward(params: Params, cams, opts: Options):
     """Independent FP64 pipeline: project, bin on the FP32-rounded records, blend."""
     pr = project_views(params, cams, opts)
     rec = pr["rec"]
-    keys, ids, ranges = bin_sort(rec[:, 0:2].astype(np.float32), pr["radius"], rec[:, 2].astype(np.float32), cams,
+    keys, ids, ranges = bin_sort(rec[:, 0:2].astype(np.float32), pr["ext"], rec[:, 2].astype(np.float32), cams,
                                  opts.tile)
     out = render(cams, opts, rec, ids, ranges)
     out.update(proj=pr, keys=keys, ids=ids, ranges=ranges)

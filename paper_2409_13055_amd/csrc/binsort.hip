@@ -432,7 +432,8 @@ __global__ __launch_bounds__(kSortThreads) void k_entry_offsets(
       const float4 r0 = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS)[0];
       const float4 r2 = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS)[2];
       int x0, y0, x1, y1;
-      tile_rect(r0.x, r0.y, __float_as_int(r2.z), vt.tile, g.TX, g.TY, x0, y0, x1, y1);
+      tile_rect(r0.x, r0.y, ext_x(__float_as_int(r2.z)), ext_y(__float_as_int(r2.z)), vt.tile, g.TX, g.TY, x0, y0,
+              x1, y1);
       ent_off[j] = off;
       ent_rec[j] = make_uint4((uint32_t)(g.tile_off + y0 * g.TX + x0), (uint32_t)g.TX | ((uint32_t)(x1 - x0) << 16),
                               id, (uint32_t)cnt);
@@ -477,7 +478,8 @@ __global__ __launch_bounds__(kSortThreads) void k_cover_counts(const int32_t* __
     const float4 r0 = reinterpret_cast<const float4*>(rec + id * GS_REC_FLOATS)[0];
     const float4 r2 = reinterpret_cast<const float4*>(rec + id * GS_REC_FLOATS)[2];
     int x0, y0, x1, y1;
-    tile_rect(r0.x, r0.y, __float_as_int(r2.z), vt.tile, g.TX, g.TY, x0, y0, x1, y1);
+    tile_rect(r0.x, r0.y, ext_x(__float_as_int(r2.z)), ext_y(__float_as_int(r2.z)), vt.tile, g.TX, g.TY, x0, y0,
+              x1, y1);
     atomicAdd(grid + y0 * gw + x0, 1);
     if (x1 < g.TX) atomicAdd(grid + y0 * gw + x1, -1);
     if (y1 < g.TY) atomicAdd(grid + y1 * gw + x0, -1);

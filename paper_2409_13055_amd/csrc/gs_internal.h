@@ -57,7 +57,13 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Projected record field offsets (see gs_projected).
-enum RecField { kMx = 0, kMy, kCa, kCb, kCc, kOp, kR, kG, kB, kDepth, kRadius, kFlags };
+enum RecField { kMx = 0, kMy, kCa, kCb, kCc, kOp, kR, kG, kB, kDepth, kExtents, kFlags };
+
+// Record word kExtents: the tile rect half-extents rx | ry << 16 (each at most
+// kMaxExtent), 0 for a culled pair.
+constexpr int kMaxExtent = 32767;
+__host__ __device__ inline int ext_x(int packed) { return packed & 0xffff; }
+__host__ __device__ inline int ext_y(int packed) { return packed >> 16; }
 
 // Which view owns global tile `gt` (views are few; linear scan).
 __device__ inline int view_of_tile(const ViewTable& vt, int gt) {
@@ -68,15 +74,17 @@ __device__ inline int view_of_tile(const ViewTable& vt, int gt) {
   return v;
 }
 
-// Tile rectangle of a splat: [x0,x1) x [y0,y1), FP32 arithmetic in exactly
-// this order (the bounds must agree bit for bit wherever they are computed).
-__device__ inline void tile_rect(float mx, float my, int radius, int B, int TX, int TY, int& x0, int& y0, int& x1,
+// Tile rectangle of a splat with half-extents (rx, ry): [x0,x1) x [y0,y1),
+// FP32 arithmetic in exactly this order (the bounds must agree bit for bit
+// wherever they are computed).  It covers every pixel within extent - 1 of
+// the mean.
+__device__ inline void tile_rect(float mx, float my, int rx, int ry, int B, int TX, int TY, int& x0, int& y0, int& x1,
                                  int& y1) {
-  const float r = (float)radius, fb = (float)B, fb1 = (float)(B - 1);
-  const float ax0 = floorf(__fdiv_rn(__fsub_rn(mx, r), fb));
-  const float ax1 = floorf(__fdiv_rn(__fadd_rn(__fadd_rn(mx, r), fb1), fb));
-  const float ay0 = floorf(__fdiv_rn(__fsub_rn(my, r), fb));
-  const float ay1 = floorf(__fdiv_rn(__fadd_rn(__fadd_rn(my, r), fb1), fb));
+  const float ex = (float)rx, ey = (float)ry, fb = (float)B, fb1 = (float)(B - 1);
+  const float ax0 = floorf(__fdiv_rn(__fsub_rn(mx, ex), fb));
+  const float ax1 = floorf(__fdiv_rn(__fadd_rn(__fadd_rn(mx, ex), fb1), fb));
+  const float ay0 = floorf(__fdiv_rn(__fsub_rn(my, ey), fb));
+  const float ay1 = floorf(__fdiv_rn(__fadd_rn(__fadd_rn(my, ey), fb1), fb));
   x0 = (int)fminf(fmaxf(ax0, 0.0f), (float)TX);
   x1 = (int)fminf(fmaxf(ax1, 0.0f), (float)TX);
   y0 = (int)fminf(fmaxf(ay0, 0.0f), (float)TY);

@@ -23,7 +23,7 @@ struct ProjectArgs {
   int64_t n;
   int32_t n_views;
   int32_t tile;
-  float near_plane, eps2d, radius_sigmas;
+  float near_plane, eps2d, radius_sigmas, alpha_min;
 };
 
 struct GradPtrs {
@@ -242,29 +242,40 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
   for (int k = 1; k < K; ++k)
 #pragma unroll
     for (int c = 0; c < 3; ++c) sh[k][c] = a.sh_rest[(i * (K - 1) + (k - 1)) * 3 + c];
-  const float op = (float)(1.0 / (1.0 + exp(-(real)a.logits[i])));
+  const real o64 = 1.0 / (1.0 + exp(-(real)a.logits[i]));
+  const float op = (float)o64;
+  // Tile rect half-extents: the axis-aligned box of the region where opacity * exp(-q/2) can reach
+  // alpha' = alpha_min (1 - 1e-3), cut to the radius_sigmas square, plus one pixel (the rect covers
+  // every pixel within extent - 1 of the mean); opacity <= alpha' never blends and is culled.
+  const real alpha_p = (real)a.alpha_min * (1.0 - 1e-3);
+  const bool opaque_enough = o64 > alpha_p;
+  const real thr = opaque_enough ? 2.0 * log(o64 / alpha_p) : 0.0;
   const int B = a.tile;
 #pragma unroll 1
   for (int v = 0; v < a.n_views; ++v) {
     const CamF& cam = cams.c[v];
     Proj2D p;
     bool ok = g.ok && project_view(g, cam, a.near_plane, a.eps2d, p);
-    int radius = 0, tiles = 0;
+    ok = ok && opaque_enough;
+    int packed = 0, tiles = 0;
     float rgb[3] = {0.f, 0.f, 0.f};
     uint32_t flags = 0;
     const float fmx = (float)p.mx, fmy = (float)p.my;
     if (ok) {
       const real mid = 0.5 * (p.a + p.c);
       const real lam = mid + sqrt(fmax(mid * mid - (p.a * p.c - p.b * p.b), 0.0));
-      radius = (int)ceil((real)a.radius_sigmas * sqrt(lam));
+      const real r = fmin(ceil((real)a.radius_sigmas * sqrt(lam)), (real)kMaxExtent);
+      const int rx = (int)fmin(r, ceil(sqrt(thr * p.a)) + 1.0);
+      const int ry = (int)fmin(r, ceil(sqrt(thr * p.c)) + 1.0);
       const int TX = (cam.W + B - 1) / B, TY = (cam.H + B - 1) / B;
       int x0, y0, x1, y1;
-      tile_rect(fmx, fmy, radius, B, TX, TY, x0, y0, x1, y1);
+      tile_rect(fmx, fmy, rx, ry, B, TX, TY, x0, y0, x1, y1);
       tiles = (x1 - x0) * (y1 - y0);
       if (tiles <= 0) {
         ok = false;
-        radius = 0;
         tiles = 0;
+      } else {
+        packed = rx | (ry << 16);
       }
     }
     if (ok) {
@@ -291,7 +302,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
     if (ok) {
       out[0] = make_float4(fmx, fmy, (float)p.ca, (float)p.cb);
       out[1] = make_float4((float)p.cc, op, rgb[0], rgb[1]);
-      out[2] = make_float4(rgb[2], (float)p.t[2], __int_as_float(radius), __uint_as_float(flags));
+      out[2] = make_float4(rgb[2], (float)p.t[2], __int_as_float(packed), __uint_as_float(flags));
     } else {
       out[0] = make_float4(0.f, 0.f, 0.f, 0.f);
       out[1] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -479,6 +490,7 @@ static ProjectArgs make_args(const gs_params* p, int32_t n_views, const gs_optio
   a.near_plane = o->near_plane;
   a.eps2d = o->eps2d;
   a.radius_sigmas = o->radius_sigmas;
+  a.alpha_min = o->alpha_min;
   return a;
 }
 

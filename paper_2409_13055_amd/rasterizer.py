@@ -219,12 +219,15 @@ class Rasterizer:
         L.gs_project_bwd(params.c_params(), fr.c_proj(), self.cams, self.n_views, self.opts, grad2d.data_ptr(),
                          grads.c_grads(), _stream())
 
-    def render_stats(self, fr: Frame) -> Dict[str, int]:
-        """Work counts of the blending of this frame (see gs_render_stats); syncs."""
-        out = torch.zeros(3, dtype=torch.int64, device=self.device)
-        L.gs_render_stats(fr.c_proj(), self.n, fr.c_bins(), self.cams, self.n_views, self.opts, out.data_ptr(),
+    def render_stats(self, fr: Frame, out: Optional[torch.Tensor] = None) -> Optional[Dict[str, int]]:
+        """Work counts of the blending of this frame (see gs_render_stats).  Without `out` it syncs
+        and returns them; with `out` (3 int64 on the device) it only enqueues the count into it."""
+        dst = torch.zeros(3, dtype=torch.int64, device=self.device) if out is None else out
+        L.gs_render_stats(fr.c_proj(), self.n, fr.c_bins(), self.cams, self.n_views, self.opts, dst.data_ptr(),
                           _stream())
-        e, b, c = (int(x) for x in out.cpu())
+        if out is not None:
+            return None
+        e, b, c = (int(x) for x in dst.cpu())
         return {"evaluated": e, "blended": b, "contrib_prefix": c}
 
     @property

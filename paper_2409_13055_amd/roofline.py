@@ -80,11 +80,12 @@ def alu_flops(kernel, ev):
 SINGLE_KERNEL_CALLS = ("project", "render_fwd", "raster_bwd", "project_bwd", "adam")
 
 
-def report(step, sc, stages_ms, hbm_peak_gbs, valu_peak_tflops, traffic=None):
-    """Roofline of the dominant single-kernel call (by measured duration)."""
+def report(step, sc, stages_ms, hbm_peak_gbs, valu_peak_tflops, traffic=None, work=None):
+    """Roofline of the dominant single-kernel call (by measured duration).  `work`: blending work
+    counts averaged over the timed iterations (default: counted on the step's current lists)."""
     c = counts(step, sc)
     b = algorithmic_bytes(c)
-    ev = evaluations(step)
+    ev = work if work is not None else evaluations(step)
     dom = max((k for k in stages_ms if k in SINGLE_KERNEL_CALLS), key=lambda k: stages_ms[k])
     ms = stages_ms[dom]
     per_stage = {k: {"ms": stages_ms[k], "alg_bytes": b[k], "GBps": round(b[k] / (stages_ms[k] * 1e-3) / 1e9, 1)}

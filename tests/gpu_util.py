@@ -9,8 +9,14 @@ from paper_2409_13055_amd import rasterizer as R
 DEV = "cuda"
 
 
+def gpu_extents(rec):
+    """Tile rect half-extents (rx, ry) [VN,2] from GPU record word 10 (rx | ry << 16; 0 = culled)."""
+    w = np.ascontiguousarray(np.asarray(rec, np.float32)[:, 10]).view(np.int32)
+    return np.stack([w & 0xffff, w >> 16], axis=1).astype(np.int32)
+
+
 def gpu_rec_to_oracle(rec):
-    """GPU record [VN,12] (mx,my,ca,cb,cc,op,r,g,b,depth,radius,flags) -> oracle [VN,10] FP64."""
+    """GPU record [VN,12] (mx,my,ca,cb,cc,op,r,g,b,depth,extents,flags) -> oracle [VN,10] FP64."""
     rec = np.asarray(rec, np.float32)
     return np.concatenate([rec[:, 0:2], rec[:, 9:10], rec[:, 2:9]], axis=1).astype(np.float64)
 

@@ -62,8 +62,8 @@ def test_full_size_sampled_parity(workload, tile):
     assert np.all(np.isfinite(img_g)) and img_g.min() >= 0.0
     # image-space gradients of sampled small splats, exact over the union of their tiles
     n, V = sc.n, len(cams)
-    rad = g["rec"][:, 10].view(np.int32)
-    small = np.nonzero((rad > 0) & (g["tiles"] <= 4))[0]
+    ext = U.gpu_extents(g["rec"])
+    small = np.nonzero((ext[:, 0] > 0) & (g["tiles"] <= 4))[0]
     rows = np.sort(rng.choice(small, min(60, small.shape[0]), replace=False))
     sel = []
     toffs = np.cumsum([0] + [((c.width + tile - 1) // tile) * ((c.height + tile - 1) // tile) for c in cams])
@@ -72,11 +72,11 @@ def test_full_size_sampled_parity(workload, tile):
         c = cams[v]
         TX, TY = (c.width + tile - 1) // tile, (c.height + tile - 1) // tile
         mx, my = g["rec"][r, 0], g["rec"][r, 1]
-        rr = np.float32(rad[r])
-        x0 = int(min(max(np.floor((np.float32(mx) - rr) / np.float32(tile)), 0), TX))
-        x1 = int(min(max(np.floor(((np.float32(mx) + rr) + np.float32(tile - 1)) / np.float32(tile)), 0), TX))
-        y0 = int(min(max(np.floor((np.float32(my) - rr) / np.float32(tile)), 0), TY))
-        y1 = int(min(max(np.floor(((np.float32(my) + rr) + np.float32(tile - 1)) / np.float32(tile)), 0), TY))
+        ex, ey = np.float32(ext[r, 0]), np.float32(ext[r, 1])
+        x0 = int(min(max(np.floor((np.float32(mx) - ex) / np.float32(tile)), 0), TX))
+        x1 = int(min(max(np.floor(((np.float32(mx) + ex) + np.float32(tile - 1)) / np.float32(tile)), 0), TX))
+        y0 = int(min(max(np.floor((np.float32(my) - ey) / np.float32(tile)), 0), TY))
+        y1 = int(min(max(np.floor(((np.float32(my) + ey) + np.float32(tile - 1)) / np.float32(tile)), 0), TY))
         for ty in range(y0, y1):
             for tx in range(x0, x1):
                 sel.append(toffs[v] + ty * TX + tx)

@@ -29,10 +29,10 @@ def check_projection(sc, g, opts):
     P = O.Params.from_scene(sc)
     ref = O.project_views(P, sc.cameras, opts)
     rec = g["rec"].astype(np.float64)
-    rad = g["rec"][:, 10].view(np.int32)
+    ext = U.gpu_extents(g["rec"])
     fl = ref["flags"]
     vis_o = ref["radius"] > 0
-    vis_g = rad > 0
+    vis_g = ext[:, 0] > 0
     boundary = (fl & (O.F_NEAR_RADIUS | O.F_NEAR_RECT | O.F_NEAR_PLANE)) != 0
     assert np.array_equal(vis_o[~boundary], vis_g[~boundary]), "culling differs"
     both = vis_o & vis_g
@@ -46,7 +46,7 @@ def check_projection(sc, g, opts):
     assert (np.abs(rec[both, 5] - r[both, 6]) / r[both, 6]).max() <= 1e-6, "opacity"
     assert np.abs(rec[both, 6:9] - r[both, 7:10]).max() <= 1e-5, "rgb"
     ok = both & ~boundary
-    assert np.array_equal(rad[ok], ref["radius"][ok]), "radius"
+    assert np.array_equal(ext[ok], ref["ext"][ok]), "rect half-extents"
     rect_area = (ref["rect"][:, 2] - ref["rect"][:, 0]) * (ref["rect"][:, 3] - ref["rect"][:, 1])
     assert np.array_equal(g["tiles"][ok], rect_area[ok]), "tiles touched"
     return int(boundary.sum())
@@ -54,8 +54,7 @@ def check_projection(sc, g, opts):
 
 def check_bins(sc, g, tile):
     rec = g["rec"]
-    rad = rec[:, 10].view(np.int32).copy()
-    keys, ids, ranges = O.bin_sort(rec[:, 0:2], rad, rec[:, 9], sc.cameras, tile)
+    keys, ids, ranges = O.bin_sort(rec[:, 0:2], U.gpu_extents(rec), rec[:, 9], sc.cameras, tile)
     assert g["m"] == ids.shape[0]
     assert np.array_equal(g["ids"], ids)
     assert np.array_equal(g["ranges"], ranges)

@@ -202,10 +202,21 @@ def test_quaternion_rotation_matches_library(oracle_lib):
 # ---------------------------------------------------------------------------
 # Tile binning and depth order
 # ---------------------------------------------------------------------------
-def _brute_force_lists(mean2d, radius, depth, cams, B):
-    """Every (tile, Gaussian) pair tested one by one; per tile sorted by (depth bits, id)."""
+def _rect(mx, my, rx, ry, B, TX, TY):
+    """Tile rect of half-extents (rx, ry), in FP32 as the reading defines it."""
+    mx, my, ex, ey, fb = np.float32(mx), np.float32(my), np.float32(rx), np.float32(ry), np.float32(B)
+    x0 = min(max(np.floor((mx - ex) / fb), 0), TX)
+    x1 = min(max(np.floor(((mx + ex) + np.float32(B - 1)) / fb), 0), TX)
+    y0 = min(max(np.floor((my - ey) / fb), 0), TY)
+    y1 = min(max(np.floor(((my + ey) + np.float32(B - 1)) / fb), 0), TY)
+    return int(x0), int(y0), int(x1), int(y1)
+
+
+def _brute_force_lists(mean2d, ext, depth, cams, B):
+    """Every (tile, Gaussian) pair tested one by one; per tile sorted by (depth bits, id).
+    ext: [V*N, 2] rect half-extents, 0 = culled."""
     out = []
-    n = radius.shape[0] // len(cams)
+    n = ext.shape[0] // len(cams)
     for v, c in enumerate(cams):
         TX, TY = (c.width + B - 1) // B, (c.height + B - 1) // B
         for ty in range(TY):
@@ -213,17 +224,22 @@ def _brute_force_lists(mean2d, radius, depth, cams, B):
                 lst = []
                 for i in range(n):
                     g = v * n + i
-                    if radius[g] <= 0:
+                    if ext[g, 0] <= 0:
                         continue
-                    mx, my, r, fb = np.float32(mean2d[g, 0]), np.float32(mean2d[g, 1]), np.float32(radius[g]), np.float32(B)
-                    x0 = min(max(np.floor((mx - r) / fb), 0), TX)
-                    x1 = min(max(np.floor(((mx + r) + np.float32(B - 1)) / fb), 0), TX)
-                    y0 = min(max(np.floor((my - r) / fb), 0), TY)
-                    y1 = min(max(np.floor(((my + r) + np.float32(B - 1)) / fb), 0), TY)
+                    x0, y0, x1, y1 = _rect(mean2d[g, 0], mean2d[g, 1], ext[g, 0], ext[g, 1], B, TX, TY)
                     if x0 <= tx < x1 and y0 <= ty < y1:
                         lst.append((int(np.float32(depth[g]).view(np.uint32)), g))
                 out.append([g for _, g in sorted(lst)])
     return out
+
+
+def _ranges_of(lists):
+    ids, ranges, pos = [], [], 0
+    for lst in lists:
+        ranges.append((pos, pos + len(lst)) if lst else (0, 0))
+        ids += lst
+        pos += len(lst)
+    return np.asarray(ids, np.uint32), np.asarray(ranges, np.uint32).reshape(-1, 2)
 
 
 @pytest.mark.parametrize("B", [8, 16, 32])
@@ -238,9 +254,9 @@ def test_binning_matches_brute_force(oracle_lib, B):
     mean2d = pr["rec"][:, :2].astype(np.float32)
     depth = pr["rec"][:, 2].astype(np.float32)
     depth[5:25] = depth[4]  # injected equal keys: ties must resolve by ascending id
-    radius = pr["radius"]
-    keys, ids, ranges = O.bin_sort(mean2d, radius, depth, cams, B)
-    ref = _brute_force_lists(mean2d, radius, depth, cams, B)
+    ext = pr["ext"]
+    keys, ids, ranges = O.bin_sort(mean2d, ext, depth, cams, B)
+    ref = _brute_force_lists(mean2d, ext, depth, cams, B)
     assert len(ref) == ranges.shape[0]
     for t, lst in enumerate(ref):
         s, e = ranges[t]
@@ -253,28 +269,63 @@ def test_binning_matches_brute_force(oracle_lib, B):
     assert sum(len(l) for l in ref) == ids.shape[0]
 
 
-def test_rect_covers_splat_support(oracle_lib):
-    """Every pixel inside the radius_sigmas ellipse (away from the one-pixel fringe at +r) lies in a
-    tile of the splat's rect."""
+def test_rect_covers_where_alpha_can_reach_threshold(oracle_lib):
+    """Every pixel inside the radius_sigmas square (away from its one-pixel fringe) whose exact alpha
+    reaches alpha_min lies in a tile of the splat's rect, and the rect lies inside the tile rect of
+    that square; low opacities shrink the rects (opacity below alpha_min culls)."""
     O = oracle_lib
-    sc = S.make_config(1, n=300)
+    sc = S.make_config(1, n=400)
     P = O.Params.from_scene(sc)
+    P.opacity_logits[:] = np.random.default_rng(3).normal(-2.0, 2.5, P.n)  # opacities down to ~1e-4
     cam = sc.cameras[0]
     B = 16
-    pr = O.project(P, cam, O.Options(tile=B))
+    opts = O.Options(tile=B)
+    TX, TY = (cam.width + B - 1) // B, (cam.height + B - 1) // B
+    pr = O.project(P, cam, opts)
     ys, xs = np.mgrid[0:cam.height, 0:cam.width]
-    checked = 0
+    tx, ty = xs // B, ys // B
+    checked = shrunk = 0
     for i in np.nonzero(pr["radius"] > 0)[0]:
-        mx, my, _, a, b, c = pr["rec"][i, :6]
+        mx, my, _, a, b, c, o = pr["rec"][i, :7]
         r = pr["radius"][i]
         dx, dy = xs - mx, ys - my
-        inside = (a * dx * dx + 2 * b * dx * dy + c * dy * dy <= 9.0) & (dx <= r - 1) & (dy <= r - 1)
+        alpha = o * np.exp(-0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy)
+        inside = (alpha >= opts.alpha_min) & (np.abs(dx) <= r - 1) & (np.abs(dy) <= r - 1)
         x0, y0, x1, y1 = pr["rect"][i]
-        tx, ty = xs // B, ys // B
         covered = (tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1)
         assert not np.any(inside & ~covered), i
+        sx0, sy0, sx1, sy1 = _rect(mx, my, r, r, B, TX, TY)
+        assert sx0 <= x0 and sy0 <= y0 and x1 <= sx1 and y1 <= sy1, i
+        shrunk += int((x1 - x0) * (y1 - y0) < (sx1 - sx0) * (sy1 - sy0))
         checked += int(inside.sum())
-    assert checked > 10000
+    culled = (pr["flags"] & O.F_CULL_OPACITY) != 0
+    o = 1 / (1 + np.exp(-P.opacity_logits))
+    assert np.array_equal(culled, (o <= opts.alpha_min * (1 - 1e-3)) & ((pr["flags"] & (O.F_CULL_NEAR | O.F_CULL_DET)) == 0))
+    assert checked > 5000 and shrunk > 50 and culled.sum() > 20
+
+
+def test_rects_render_like_radius_squares(oracle_lib):
+    """The tile lists of the opacity-aware rects render exactly the image of the lists of the full
+    radius_sigmas squares: every list entry they leave out is skipped by the alpha test."""
+    O = oracle_lib
+    cams = [S.pinhole(64, 48, 50.0), S.pinhole(48, 40, 40.0, *S.look_at((0.3, 0.0, -0.5), (0.0, 0.0, 3.0)))]
+    n = 220
+    sc = S.make_scene(12, n, 1, cams, "box", log_scale_mu=-2.6, log_scale_sigma=0.7, logit_sigma=1.0, targets=False)
+    P = O.Params.from_scene(sc)
+    P.opacity_logits[:] = np.random.default_rng(4).normal(-1.5, 2.5, n)
+    for B in (8, 16):
+        opts = O.Options(tile=B)
+        pr = O.project_views(P, cams, opts)
+        rec = pr["rec"]
+        mean2d, depth = rec[:, :2].astype(np.float32), rec[:, 2].astype(np.float32)
+        keys, ids, ranges = O.bin_sort(mean2d, pr["ext"], depth, cams, B)
+        square = np.where(pr["radius"][:, None] > 0, pr["radius"][:, None], 0).repeat(2, 1).astype(np.int32)
+        ids_sq, ranges_sq = _ranges_of(_brute_force_lists(mean2d, square, depth, cams, B))
+        assert ids_sq.shape[0] > ids.shape[0] + 100  # the rects leave many entries out
+        a = O.render(cams, opts, rec, ids, ranges)
+        b = O.render(cams, opts, rec, ids_sq, ranges_sq)
+        assert np.abs(a["image"] - b["image"]).max() <= 1e-12
+        assert np.abs(a["t_final"] - b["t_final"]).max() <= 1e-12
 
 
 # ---------------------------------------------------------------------------
