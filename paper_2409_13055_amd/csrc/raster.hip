@@ -29,11 +29,6 @@ struct RasterConsts {
   float radius_sigmas;
 };
 
-// Per-entry quantities staged in LDS, computed once per batch from the
-// 48-byte record (one record per lane) so the per-pixel loop stays short:
-//   cul = (mean x, mean y, wave-cull bound on |d|^2, power cutoff)
-//   geo = (-a/2, -b, -c/2, opacity) for the conic (a, b, c)
-//   col = (r, g, b, 0)
 // The per-pixel exponent is power = -(a dx^2 + c dy^2)/2 - b dx dy, d = pixel -
 // mean, evaluated with one fixed rounding sequence (the dx terms are shared by
 // the PPL pixels of a lane's column), so that every kernel takes identical
@@ -41,9 +36,9 @@ struct RasterConsts {
 struct RowTerms {
   float a2x, nbx;  // -a dx^2 / 2 and -b dx
 };
-__device__ __forceinline__ RowTerms row_terms(float dx, const float4& geo) {
+__device__ __forceinline__ RowTerms row_terms(float dx, float a2, float nb) {
 #pragma clang fp contract(off)
-  return RowTerms{(geo.x * dx) * dx, geo.y * dx};
+  return RowTerms{(a2 * dx) * dx, nb * dx};
 }
 __device__ __forceinline__ float splat_power(const RowTerms& t, float c2, float dy) {
 #pragma clang fp contract(off)
@@ -105,7 +100,9 @@ struct PixMap {
   static constexpr int WAVES = TileShape<TILE>::WAVES, PPL = TileShape<TILE>::PPL, NT = 64 * WAVES;
   static constexpr int SUBW = TILE < 16 ? TILE : 16, SUBH = 64 * PPL / SUBW;
   static_assert((TILE / SUBW) * (TILE / SUBH) == WAVES && SUBW * SUBH == 64 * PPL, "tile shape");
+  static constexpr int WX = TILE / SUBW, WY = TILE / SUBH;  // wave blocks per tile row / column
   int v, x, y0, W, H, pix_off, tile;
+  int tx0, ty0;  // top-left pixel of the tile
   int wx0, wy0;  // top-left pixel of this wave's block
   __device__ PixMap(const ViewTable& vt, int gt) {
     tile = gt;
@@ -117,8 +114,10 @@ struct PixMap {
     const int lt = gt - g.tile_off;
     const int tx = lt % g.TX, ty = lt / g.TX;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    wx0 = tx * TILE + (w % (TILE / SUBW)) * SUBW;
-    wy0 = ty * TILE + (w / (TILE / SUBW)) * SUBH;
+    tx0 = tx * TILE;
+    ty0 = ty * TILE;
+    wx0 = tx0 + (w % WX) * SUBW;
+    wy0 = ty0 + (w / WX) * SUBH;
     x = wx0 + lane % SUBW;
     y0 = wy0 + (lane / SUBW) * PPL;
   }
@@ -157,7 +156,7 @@ __device__ __forceinline__ CullBounds cull_bounds(float ca, float cb, float cc, 
   return CullBounds{thr / lmin, ex, ey};
 }
 
-// One splat record staged through registers (prefetch) into LDS.
+// One splat record loaded into registers ahead of its batch (prefetch).
 struct SplatLoader {
   float4 a, b, c;  // record words 0-3, 4-7, 8-11
   uint32_t id;
@@ -173,42 +172,113 @@ struct SplatLoader {
       c = r[2];
     }
   }
-  // record: a = (mean x, mean y, conic a, conic b), b = (conic c, opacity, r, g), c = (b, ...)
-  __device__ __forceinline__ void store(float4* s_cul, float2* s_aux, float4* s_geo, float4* s_col, uint32_t* s_id,
-                                        int slot, const RasterConsts& rc) const {
-    if (!valid) return;
-    const CullBounds cb = cull_bounds(a.z, a.w, b.x, b.y, rc.alpha_min);
-    s_cul[slot] = make_float4(a.x, a.y, cb.ex, cb.ey);
-    s_aux[slot] = make_float2(cb.r2, power_cutoff(b.y, rc.alpha_min));
-    s_geo[slot] = make_float4(-0.5f * a.z, -a.w, -0.5f * b.x, b.y);
-    s_col[slot] = make_float4(b.z, b.w, c.x, 0.0f);
-    if (s_id) s_id[slot] = id;
+};
+
+// The pixel blocks of a tile's wavefronts (pixel centres inside the image),
+// as WX column ranges and WY row ranges; a block entirely outside the image
+// has hi < lo.
+template <class PM>
+struct BlockBoxes {
+  float x_lo[PM::WX], x_hi[PM::WX], y_lo[PM::WY], y_hi[PM::WY];
+  __device__ explicit BlockBoxes(const PM& pm) {
+#pragma unroll
+    for (int c = 0; c < PM::WX; ++c) {
+      x_lo[c] = (float)(pm.tx0 + c * PM::SUBW);
+      x_hi[c] = (float)(min(pm.tx0 + (c + 1) * PM::SUBW, pm.W) - 1);
+    }
+#pragma unroll
+    for (int r = 0; r < PM::WY; ++r) {
+      y_lo[r] = (float)(pm.ty0 + r * PM::SUBH);
+      y_hi[r] = (float)(min(pm.ty0 + (r + 1) * PM::SUBH, pm.H) - 1);
+    }
+  }
+  // Bit w set: wavefront w's block is inside both cull bounds of a splat at (mx, my).
+  __device__ __forceinline__ int mask(float mx, float my, const CullBounds& cb) const {
+    float dxs[PM::WX], dys[PM::WY];
+    bool okx[PM::WX], oky[PM::WY];
+#pragma unroll
+    for (int c = 0; c < PM::WX; ++c) {
+      const float o = fmaxf(x_lo[c] - mx, mx - x_hi[c]);  // > 0: outside
+      okx[c] = !(o > cb.ex);
+      const float d = fmaxf(o, 0.0f);
+      dxs[c] = d * d;
+    }
+#pragma unroll
+    for (int r = 0; r < PM::WY; ++r) {
+      const float o = fmaxf(y_lo[r] - my, my - y_hi[r]);
+      oky[r] = !(o > cb.ey);
+      const float d = fmaxf(o, 0.0f);
+      dys[r] = d * d;
+    }
+    int m = 0;
+#pragma unroll
+    for (int r = 0; r < PM::WY; ++r)
+#pragma unroll
+      for (int c = 0; c < PM::WX; ++c)
+        if (okx[c] && oky[r] && !(dxs[c] + dys[r] > cb.r2)) m |= 1 << (r * PM::WX + c);
+    return m;
   }
 };
 
-// Pixel rectangle (pixel centres inside the image) of a wavefront's block,
-// for the wave-level cull.  A block entirely outside the image has
-// x_hi < x_lo or y_hi < y_lo; its lanes own no pixel.
-struct WaveBox {
-  float x_lo, x_hi, y_lo, y_hi;
-  template <class PM>
-  __device__ explicit WaveBox(const PM& pm) {
-    x_lo = (float)pm.wx0;
-    x_hi = (float)(min(pm.wx0 + PM::SUBW, pm.W) - 1);
-    y_lo = (float)pm.wy0;
-    y_hi = (float)(min(pm.wy0 + PM::SUBH, pm.H) - 1);
-  }
-  // cu = (mean x, mean y, ex, ey), r2: see cull_bounds
-  __device__ __forceinline__ bool culled(const float4& cu, float r2) const {
-    const float ox = fmaxf(x_lo - cu.x, cu.x - x_hi), oy = fmaxf(y_lo - cu.y, cu.y - y_hi);  // > 0: outside
-    const float dx = fmaxf(ox, 0.0f), dy = fmaxf(oy, 0.0f);
-    return ox > cu.z || oy > cu.w || dx * dx + dy * dy > r2;
-  }
+// LDS of one batch: what the pixel loop reads per entry, and per wavefront
+// the ordered list of the batch entries its pixel block can see.
+template <class PM>
+struct BatchLds {
+  float4 a[PM::NT];  // (mean x, mean y, -a/2, -b) for the conic (a, b, c)
+  float4 b[PM::NT];  // (-c/2, opacity, exponent cutoff, r)
+  float2 c[PM::NT];  // (g, b)
+  uint32_t id[PM::NT];
+  uint16_t list[PM::WAVES][PM::NT];
+  int cnt[PM::WAVES][PM::WAVES];  // [staging wave][listing wave]
 };
+
+// Stages the batch held by `ld` (one entry per thread): entry data into LDS,
+// the cull of every wavefront block done once here per entry, and each
+// wavefront's list built in entry order (ballots, then the staging waves'
+// counts in order).  Ends with a barrier; returns the calling wave's count.
+template <class PM>
+__device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBoxes<PM>& bx, float alpha_min,
+                                           BatchLds<PM>& L, bool with_id) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int mask = 0;
+  if (ld.valid) {
+    const CullBounds cb = cull_bounds(ld.a.z, ld.a.w, ld.b.x, ld.b.y, alpha_min);
+    mask = bx.mask(ld.a.x, ld.a.y, cb);
+    L.a[t] = make_float4(ld.a.x, ld.a.y, -0.5f * ld.a.z, -ld.a.w);
+    L.b[t] = make_float4(-0.5f * ld.b.x, ld.b.y, power_cutoff(ld.b.y, alpha_min), ld.b.z);
+    L.c[t] = make_float2(ld.b.w, ld.c.x);
+    if (with_id) L.id[t] = ld.id;
+  }
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  uint64_t bal[PM::WAVES];
+#pragma unroll
+  for (int q = 0; q < PM::WAVES; ++q) bal[q] = __ballot((mask >> q) & 1);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < PM::WAVES; ++q) L.cnt[w][q] = (int)__popcll(bal[q]);
+  }
+  __syncthreads();
+  int mine = 0;
+#pragma unroll
+  for (int q = 0; q < PM::WAVES; ++q) {
+    int off = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < PM::WAVES; ++w2) {
+      const int c = L.cnt[w2][q];
+      off += w2 < w ? c : 0;
+      mine += q == w ? c : 0;
+    }
+    if ((mask >> q) & 1) L.list[q][off + (int)__popcll(bal[q] & lt)] = (uint16_t)t;
+  }
+  __syncthreads();
+  return mine;
+}
 
 // ---------------------------------------------------------------------------
 // Forward.
 // ---------------------------------------------------------------------------
+// A pixel that has stopped gets row coordinate +inf: its exponent is then
+// -inf or NaN and fails the cutoff test, so no separate flag is tested.
 template <int TILE>
 __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
@@ -216,24 +286,20 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
     const float* __restrict__ target, float* __restrict__ tile_loss) {
   using PM = PixMap<TILE>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
-  __shared__ float4 s_cul[NT];
-  __shared__ float2 s_aux[NT];
-  __shared__ float4 s_geo[NT];
-  __shared__ float4 s_col[NT];
+  __shared__ BatchLds<PM> L;
   __shared__ float s_loss[PM::WAVES];
   const PM pm(vt, blockIdx.x);
   const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
-  const WaveBox box(pm);
+  const BlockBoxes<PM> boxes(pm);
+  const int w = threadIdx.x >> 6;
   float T[PPL], C[PPL][3], fy[PPL];
   int last[PPL];
-  bool done[PPL];
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
     T[p] = 1.0f;
     C[p][0] = C[p][1] = C[p][2] = 0.0f;
     last[p] = 0;
-    done[p] = !pm.inside(p);
-    fy[p] = (float)(pm.y0 + p);
+    fy[p] = pm.inside(p) ? (float)(pm.y0 + p) : INFINITY;
   }
   const uint2 rg = ranges[blockIdx.x];
   const int s = (int)rg.x, e = (int)rg.y;
@@ -243,35 +309,33 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
   for (int base = s; base < e; base += NT) {
     int alive = 0;
 #pragma unroll
-    for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
+    for (int p = 0; p < PPL; ++p) alive |= fy[p] != INFINITY ? 1 : 0;
     if (__syncthreads_count(alive) == 0) break;
-    ld.store(s_cul, s_aux, s_geo, s_col, nullptr, threadIdx.x, rc);
-    __syncthreads();
+    const int n = stage_batch<PM>(ld, boxes, rc.alpha_min, L, false);
     ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);  // next batch, in flight during this one
     // a wavefront whose pixels have all stopped only keeps the block's barriers
-    const int cnt = __ballot(alive) != 0ull ? min(NT, e - base) : 0;
-    for (int j = 0; j < cnt; ++j) {
-      const float4 cu = s_cul[j];
-      const float2 ax = s_aux[j];
-      if (box.culled(cu, ax.x)) continue;
-      const float4 geo = s_geo[j];
-      const float4 col = s_col[j];
-      const RowTerms rt = row_terms(fx - cu.x, geo);
+    const int cnt = __ballot(alive) != 0ull ? n : 0;
+    for (int k = 0; k < cnt; ++k) {
+      const int j = L.list[w][k];
+      const float4 A = L.a[j];
+      const float4 Bv = L.b[j];
+      const float2 Cv = L.c[j];
+      const RowTerms rt = row_terms(fx - A.x, A.z, A.w);
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        const float power = splat_power(rt, geo.z, fy[p] - cu.y);
-        if (done[p] || !(power >= ax.y) || power > 0.0f) continue;
-        const float alpha = fminf(amax, geo.w * exp_hw(power));
+        const float power = splat_power(rt, Bv.x, fy[p] - A.y);
+        if (!(power >= Bv.z) || power > 0.0f) continue;
+        const float alpha = fminf(amax, Bv.y * exp_hw(power));
         if (alpha < rc.alpha_min) continue;
         const float test = T[p] * (1.0f - alpha);
         if (test < rc.t_min) {
-          done[p] = true;
+          fy[p] = INFINITY;
           continue;
         }
         const float wgt = alpha * T[p];
-        C[p][0] = fmaf(col.x, wgt, C[p][0]);
-        C[p][1] = fmaf(col.y, wgt, C[p][1]);
-        C[p][2] = fmaf(col.z, wgt, C[p][2]);
+        C[p][0] = fmaf(Bv.w, wgt, C[p][0]);
+        C[p][1] = fmaf(Cv.x, wgt, C[p][1]);
+        C[p][2] = fmaf(Cv.y, wgt, C[p][2]);
         T[p] = test;
         last[p] = base - s + j + 1;
       }
@@ -298,7 +362,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
     __syncthreads();
     if (threadIdx.x == 0) {
       float t = 0.0f;
-      for (int w = 0; w < PM::WAVES; ++w) t += s_loss[w];
+      for (int q = 0; q < PM::WAVES; ++q) t += s_loss[q];
       tile_loss[blockIdx.x] = t;
     }
   }
@@ -397,28 +461,23 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
     const float* __restrict__ dl_dimage, float* __restrict__ grad2d) {
   using PM = PixMap<TILE>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
-  __shared__ float4 s_cul[NT];
-  __shared__ float2 s_aux[NT];
-  __shared__ float4 s_geo[NT];
-  __shared__ float4 s_col[NT];
-  __shared__ uint32_t s_id[NT];
+  __shared__ BatchLds<PM> L;
   const PM pm(vt, blockIdx.x);
   const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
-  const WaveBox box(pm);
+  const BlockBoxes<PM> boxes(pm);
   const uint2 rg = ranges[blockIdx.x];
   const int s = (int)rg.x, e = (int)rg.y;
   const float fx = (float)pm.x;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const LaneRole role = wave_roles(lane);
-  // per pixel: transmittance in front of the current entry, colour still behind it, dL/dC
+  // per pixel: transmittance in front of the current entry, colour still behind it, dL/dC; a pixel
+  // that has stopped gets row coordinate +inf (see k_render_fwd)
   float T[PPL], S[PPL][3], dl[PPL][3], fy[PPL];
-  bool done[PPL];
   const float wv = 1.0f / (3.0f * (float)pm.W * (float)pm.H);
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
-    fy[p] = (float)(pm.y0 + p);
+    fy[p] = pm.inside(p) ? (float)(pm.y0 + p) : INFINITY;
     T[p] = 1.0f;
-    done[p] = !pm.inside(p);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float d = 0.0f, col = 0.0f;
@@ -441,45 +500,43 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
   for (int base = s; base < e; base += NT) {
     int alive = 0;
 #pragma unroll
-    for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
+    for (int p = 0; p < PPL; ++p) alive |= fy[p] != INFINITY ? 1 : 0;
     if (__syncthreads_count(alive) == 0) break;
-    ld.store(s_cul, s_aux, s_geo, s_col, s_id, threadIdx.x, rc);
-    __syncthreads();
+    const int n = stage_batch<PM>(ld, boxes, rc.alpha_min, L, true);
     ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);  // next batch, in flight during this one
-    const int cnt = __ballot(alive) != 0ull ? min(NT, e - base) : 0;
-    for (int j = 0; j < cnt; ++j) {
-      const float4 cu = s_cul[j];
-      const float2 ax = s_aux[j];
-      if (box.culled(cu, ax.x)) continue;
-      const float4 geo = s_geo[j];
-      const float4 col = s_col[j];
-      const float dx = fx - cu.x;
-      const RowTerms rt = row_terms(dx, geo);
+    const int cnt = __ballot(alive) != 0ull ? n : 0;
+    for (int k = 0; k < cnt; ++k) {
+      const int j = L.list[w][k];
+      const float4 A = L.a[j];
+      const float4 Bv = L.b[j];
+      const float2 Cv = L.c[j];
+      const float dx = fx - A.x;
+      const RowTerms rt = row_terms(dx, A.z, A.w);
       bool any = false;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        const float dy = fy[p] - cu.y;
-        const float power = splat_power(rt, geo.z, dy);
-        if (done[p] || !(power >= ax.y) || power > 0.0f) continue;
+        const float dy = fy[p] - A.y;
+        const float power = splat_power(rt, Bv.x, dy);
+        if (!(power >= Bv.z) || power > 0.0f) continue;
         const float G = exp_hw(power);
-        const float oG = geo.w * G;
+        const float oG = Bv.y * G;
         const float alpha = fminf(amax, oG);
         if (alpha < rc.alpha_min) continue;
         const float om = 1.0f - alpha;
         const float test = T[p] * om;
         if (test < rc.t_min) {
-          done[p] = true;
+          fy[p] = INFINITY;
           continue;
         }
         any = true;
         const float wgt = alpha * T[p];
-        S[p][0] = fmaf(-col.x, wgt, S[p][0]);
-        S[p][1] = fmaf(-col.y, wgt, S[p][1]);
-        S[p][2] = fmaf(-col.z, wgt, S[p][2]);
+        S[p][0] = fmaf(-Bv.w, wgt, S[p][0]);
+        S[p][1] = fmaf(-Cv.x, wgt, S[p][1]);
+        S[p][2] = fmaf(-Cv.y, wgt, S[p][2]);
         acc.r = fmaf(dl[p][0], wgt, acc.r);
         acc.g = fmaf(dl[p][1], wgt, acc.g);
         acc.b = fmaf(dl[p][2], wgt, acc.b);
-        const float dc = fmaf(dl[p][2], col.z, fmaf(dl[p][1], col.y, dl[p][0] * col.x));
+        const float dc = fmaf(dl[p][2], Cv.y, fmaf(dl[p][1], Cv.x, dl[p][0] * Bv.w));
         const float ds = fmaf(dl[p][2], S[p][2], fmaf(dl[p][1], S[p][1], dl[p][0] * S[p][0]));
         const float dLda = fmaf(T[p], dc, -ds * __builtin_amdgcn_rcpf(om));
         T[p] = test;
@@ -495,11 +552,11 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
       }
       if (__ballot(any) != 0ull) {
         const Red3 r = reduce_scatter(acc);
-        const float ca = -2.0f * geo.x, cb = -geo.y, cc = -2.0f * geo.z;
+        const float ca = -2.0f * A.z, cb = -A.w, cc = -2.0f * Bv.x;
         const float ka = role.mean_x ? ca : (role.mean_y ? cb : role.k0c);
         const float kc = role.mean_x ? cb : (role.mean_y ? cc : 0.0f);
         const float val = fmaf(ka, r.k0, fmaf(kc, r.k2, role.k1c * r.k1));
-        if (role.comp >= 0) atomicAdd(grad2d + (size_t)s_id[j] * GS_GRAD2D_FLOATS + role.comp, val);
+        if (role.comp >= 0) atomicAdd(grad2d + (size_t)L.id[j] * GS_GRAD2D_FLOATS + role.comp, val);
         acc = Acc9{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       }
     }
@@ -517,10 +574,8 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
     RasterConsts rc, unsigned long long* __restrict__ out) {
   using PM = PixMap<TILE>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
-  __shared__ float4 s_cul[NT];
-  __shared__ float2 s_aux[NT];
-  __shared__ float4 s_geo[NT];
-  __shared__ float4 s_col[NT];
+  __shared__ float4 s_a[NT];  // (mean x, mean y, -a/2, -b)
+  __shared__ float2 s_b[NT];  // (-c/2, opacity)
   const PM pm(vt, blockIdx.x);
   const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
   float T[PPL], fy[PPL];
@@ -543,20 +598,23 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
     for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
     if (__syncthreads_count(alive) == 0) break;
     ld.fetch(rec, ids, base + (int)threadIdx.x, s, e);
-    ld.store(s_cul, s_aux, s_geo, s_col, nullptr, threadIdx.x, rc);
+    if (ld.valid) {
+      s_a[threadIdx.x] = make_float4(ld.a.x, ld.a.y, -0.5f * ld.a.z, -ld.a.w);
+      s_b[threadIdx.x] = make_float2(-0.5f * ld.b.x, ld.b.y);
+    }
     __syncthreads();
     const int cnt = min(NT, e - base);
     for (int j = 0; j < cnt; ++j) {
-      const float4 cu = s_cul[j];
-      const float4 geo = s_geo[j];
-      const RowTerms rt = row_terms(fx - cu.x, geo);
+      const float4 cu = s_a[j];
+      const float2 geo = s_b[j];
+      const RowTerms rt = row_terms(fx - cu.x, cu.z, cu.w);
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         if (done[p]) continue;
         ++evals[p];
-        const float power = splat_power(rt, geo.z, fy[p] - cu.y);
+        const float power = splat_power(rt, geo.x, fy[p] - cu.y);
         if (power > 0.0f) continue;
-        const float alpha = fminf(amax, geo.w * exp_hw(power));
+        const float alpha = fminf(amax, geo.y * exp_hw(power));
         if (!(alpha >= rc.alpha_min)) continue;
         const float test = T[p] * (1.0f - alpha);
         if (test < rc.t_min) {
