@@ -11,7 +11,7 @@ Per-unit figures (P_n = 11 + 3K raw floats per Gaussian, K = (D+1)^2):
   project     N*4*P_n + V*N*(48 + 4)
   bin_sort    V*N*8 + M*(12 + 24 + 8) + T*8
   render_fwd  Nv*36 + M*4 + Px*(12 + 12 [target] + 8 [T_final, n_contrib unless checkpoint])
-  raster_bwd  Px*(12 [image] + 12 [target]) + Nv*36 + M*4 + V*N*36
+  raster_bwd  Px*(12 [image] + 12 [target]) + Nv*36 [records] + M*4 + Nv*36 [gradients]
   project_bwd N*(4*P_n + 8*P_n) + V*N*(36 + 16)
   render_bwd  raster_bwd + project_bwd
   adam        N*P_n*32  (read p, g, m, v; write p, m, v, g := 0)
@@ -54,7 +54,7 @@ def counts(step, sc):
 def algorithmic_bytes(c):
     N, V, Pn, M, Nv, Px, T = c["N"], c["V"], c["Pn"], c["M"], c["Nv"], c["Px"], c["T"]
     saved = 0 if c["ckpt"] else 8
-    raster_bwd = Px * 24 + Nv * 36 + M * 4 + V * N * 36
+    raster_bwd = Px * 24 + Nv * 36 + M * 4 + Nv * 36
     project_bwd = N * 12 * Pn + V * N * 52
     return {
         "project": N * 4 * Pn + V * N * 52,
