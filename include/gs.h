@@ -278,8 +278,9 @@ gs_status gs_render_bwd(const gs_params* params, const gs_projected* proj, const
  *
  * gs_project_bwd: backward of the projection: chains grad2d (same layout)
  * through gs_project's mapping to the raw parameters and ADDS the result into
- * `grads`, summed over views.  `proj` must hold the records gs_project wrote
- * for these parameters and cameras (radius 0 pairs are skipped). */
+ * `grads`, summed over views.  It reads proj->tiles_touched only (pairs with
+ * 0 are skipped), which must be what gs_project wrote for these parameters,
+ * cameras and options; the rest of the projection is recomputed. */
 gs_status gs_raster_bwd(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_image* img,
                         const gs_camera* cams, int32_t n_views, const gs_options* opts, const gs_loss* loss,
                         float* grad2d, void* stream);

@@ -226,6 +226,27 @@ __device__ inline bool project_view(const GaussCov& g, const CamF& cam, real nea
   return true;
 }
 
+// Unit viewing direction from the camera centre to the mean (d) and
+// 1/|mean - centre| (il).  Shared by the projection and its backward, whose
+// colour-clamp decisions must agree.
+__device__ inline void view_dir(const GaussCov& g, const CamF& cam, real d[3], real& il) {
+  const real dx = g.m[0] - (real)cam.centre[0], dy = g.m[1] - (real)cam.centre[1], dz = g.m[2] - (real)cam.centre[2];
+  il = 1.0 / sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+  d[0] = dx * il;
+  d[1] = dy * il;
+  d[2] = dz * il;
+}
+
+// One colour channel before the clamp at 0: 1/2 + sum_k sh_k Y_k, in one fixed
+// FMA order (coef(k, c) returns coefficient k of channel c).
+template <int K, class Coef>
+__device__ __forceinline__ float sh_channel(const Coef& coef, const float* Y, int c) {
+  float s = 0.5f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) s = fmaf(coef(k, c), Y[k], s);
+  return s;
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, float* __restrict__ rec,
                                                  int32_t* __restrict__ tiles_touched) {
@@ -279,15 +300,13 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
       }
     }
     if (ok) {
-      real dx = g.m[0] - cam.centre[0], dy = g.m[1] - cam.centre[1], dz = g.m[2] - cam.centre[2];
-      const real inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+      real d[3], il;
+      view_dir(g, cam, d, il);
       float Y[16];
-      sh_basis(D, (float)(dx * inv), (float)(dy * inv), (float)(dz * inv), Y);
+      sh_basis(D, (float)d[0], (float)d[1], (float)d[2], Y);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        float s = 0.5f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) s += sh[k][c] * Y[k];
+        float s = sh_channel<K>([&](int k, int ch) { return sh[k][ch]; }, Y, c);
         if (s < 0.0f) {
           flags |= 1u << c;
           s = 0.0f;
@@ -316,7 +335,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
 // gradients of all its views, accumulating the view-independent d/dSigma
 // once, then chains to log-scales and the (unnormalised) quaternion.
 template <int D>
-__global__ __launch_bounds__(256) void k_project_bwd(ProjectArgs a, CamTable cams, const float* __restrict__ rec,
+__global__ __launch_bounds__(256) void k_project_bwd(ProjectArgs a, CamTable cams, const int32_t* __restrict__ tiles,
                                                      const float* __restrict__ grad2d, GradPtrs gp) {
   constexpr int K = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -338,9 +357,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectArgs a, CamTable cam
 #pragma unroll 1
   for (int v = 0; v < a.n_views; ++v) {
     const int64_t row = (int64_t)v * a.n + i;
-    const float4 r2 = reinterpret_cast<const float4*>(rec + row * GS_REC_FLOATS)[2];
-    if (__float_as_int(r2.z) == 0) continue;
-    const uint32_t flags = __float_as_uint(r2.w);
+    if (tiles[row] == 0) continue;  // culled: no image-space gradient
     real g2[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) g2[k] = grad2d[row * 9 + k];
@@ -397,14 +414,17 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectArgs a, CamTable cam
     gm[1] += Wc[1] * gt0 + Wc[4] * gt1 + Wc[7] * gt2;
     gm[2] += Wc[2] * gt0 + Wc[5] * gt1 + Wc[8] * gt2;
     gop += g2[5];
-    // colour -> SH coefficients and the viewing direction
-    real dx = g.m[0] - cam.centre[0], dy = g.m[1] - cam.centre[1], dz = g.m[2] - cam.centre[2];
-    const real len = sqrt(dx * dx + dy * dy + dz * dz), il = 1.0 / len;
-    dx *= il; dy *= il; dz *= il;
+    // colour -> SH coefficients and the viewing direction; a channel clamped at 0 in the
+    // projection (same arithmetic as there) passes no gradient
+    real d[3], il;
+    view_dir(g, cam, d, il);
+    const real dx = d[0], dy = d[1], dz = d[2];
     float Y[16], acoef[16];
     sh_basis(D, (float)dx, (float)dy, (float)dz, Y);
-    const float wr = (flags & 1u) ? 0.f : (float)g2[6], wg = (flags & 2u) ? 0.f : (float)g2[7],
-                wb = (flags & 4u) ? 0.f : (float)g2[8];
+    const auto coef = [&](int k, int ch) { return (k == 0 ? shd : shr + (k - 1) * 3)[ch]; };
+    const float wr = sh_channel<K>(coef, Y, 0) < 0.0f ? 0.f : (float)g2[6];
+    const float wg = sh_channel<K>(coef, Y, 1) < 0.0f ? 0.f : (float)g2[7];
+    const float wb = sh_channel<K>(coef, Y, 2) < 0.0f ? 0.f : (float)g2[8];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       gsh[k][0] += wr * Y[k];
@@ -508,17 +528,17 @@ gs_status validate_params(const gs_params* p) {
 }
 
 gs_status launch_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
-                             const float* rec, const float* grad2d, const gs_grads* grads, hipStream_t stream) {
+                             const int32_t* tiles, const float* grad2d, const gs_grads* grads, hipStream_t stream) {
   const ProjectArgs a = make_args(params, n_views, opts);
   const CamTable ct = make_cam_table(cams, n_views, opts);
   GradPtrs gp{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->sh_dc, grads->sh_rest};
   const int bs = 256;
   const dim3 grid((unsigned)((params->n + bs - 1) / bs));
   switch (params->sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(bs), 0, stream, a, ct, rec, grad2d, gp); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(bs), 0, stream, a, ct, rec, grad2d, gp); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(bs), 0, stream, a, ct, rec, grad2d, gp); break;
-    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(bs), 0, stream, a, ct, rec, grad2d, gp); break;
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp); break;
   }
   return check_launch("projection backward");
 }

@@ -21,7 +21,7 @@ namespace gs {
 
 gs_status validate_params(const gs_params* p);
 gs_status launch_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
-                             const float* rec, const float* grad2d, const gs_grads* grads, hipStream_t stream);
+                             const int32_t* tiles, const float* grad2d, const gs_grads* grads, hipStream_t stream);
 
 struct RasterConsts {
   float alpha_min, alpha_max, t_min;
@@ -799,10 +799,10 @@ extern "C" gs_status gs_project_bwd(const gs_params* params, const gs_projected*
   if ((s = validate_params(params)) != GS_OK) return s;
   if ((s = validate_cams(cams, n_views)) != GS_OK) return s;
   if ((s = validate_opts(opts)) != GS_OK) return s;
-  if (!proj || !proj->rec) return fail(GS_ERR_INVALID_VALUE, "proj->rec is NULL");
+  if (!proj || !proj->tiles_touched) return fail(GS_ERR_INVALID_VALUE, "proj->tiles_touched is NULL");
   if (!grad2d) return fail(GS_ERR_INVALID_VALUE, "grad2d is NULL");
   if ((s = validate_grads(params, grads)) != GS_OK) return s;
-  return launch_project_bwd(params, cams, n_views, opts, proj->rec, grad2d, grads, as_stream(stream));
+  return launch_project_bwd(params, cams, n_views, opts, proj->tiles_touched, grad2d, grads, as_stream(stream));
 }
 
 extern "C" gs_status gs_render_bwd(const gs_params* params, const gs_projected* proj, const gs_bins* bins,
@@ -825,7 +825,7 @@ extern "C" gs_status gs_render_bwd(const gs_params* params, const gs_projected* 
                      (uint64_t)g2n);
   launch_raster_bwd(vt, proj, bins, img, opts, loss, g2, st);
   if ((s = check_launch("render backward")) != GS_OK) return s;
-  return launch_project_bwd(params, cams, n_views, opts, proj->rec, g2, grads, st);
+  return launch_project_bwd(params, cams, n_views, opts, proj->tiles_touched, g2, grads, st);
 }
 
 extern "C" gs_status gs_render_stats(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
