@@ -142,8 +142,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
   h[threadIdx.x] = 0;
   __syncthreads();
   const Chunk c = chunk_of(*d_count, nb, blockIdx.x);
-  for (uint64_t i = c.begin + threadIdx.x; i < c.end; i += kSortThreads)
-    atomicAdd(&h[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
+  // eight loads in flight per thread, then their LDS increments
+  constexpr int U = 8;
+  uint64_t i = c.begin + threadIdx.x;
+  for (; i + (U - 1) * kSortThreads < c.end; i += U * kSortThreads) {
+    uint32_t k[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) k[u] = keys[i + (uint64_t)u * kSortThreads];
+#pragma unroll
+    for (int u = 0; u < U; ++u) atomicAdd(&h[(k[u] >> shift) & (kRadixBins - 1)], 1u);
+  }
+  for (; i < c.end; i += kSortThreads) atomicAdd(&h[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
   __syncthreads();
   hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
@@ -289,6 +298,19 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __syncthreads();
     uint32_t key[kItems], val[kItems], rk[kItems];
     const uint64_t lim = c.end - tb;  // keys left from this tile's start
+    if (!EMIT) {
+      // all of the tile's loads first, unconditionally (indices clamped into the tile), so they are
+      // in flight together rather than one dependent round trip per item
+      const uint32_t* kt = kin + tb;
+      const uint32_t* vt = vin + tb;
+      const uint32_t last = (uint32_t)min<uint64_t>(lim, (uint64_t)kTileKeys) - 1;
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) {
+        const uint32_t o = min(o0 + (uint32_t)k * 64, last);
+        key[k] = kt[o];
+        val[k] = vt[o];
+      }
+    }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
       const uint32_t o = o0 + (uint32_t)k * 64;
@@ -296,9 +318,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       if (EMIT) {
         key[k] = valid ? s_keys[o] : 0u;
         val[k] = valid ? s_vals[o] : 0u;
-      } else {
-        key[k] = valid ? kin[tb + o] : 0u;
-        val[k] = valid ? vin[tb + o] : 0u;
+      } else if (!valid) {
+        key[k] = 0u;
+        val[k] = 0u;
       }
       const uint32_t d = (key[k] >> shift) & (kRadixBins - 1);
       uint64_t peers = __ballot(valid);
