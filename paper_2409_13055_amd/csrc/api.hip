@@ -71,7 +71,7 @@ ViewTable make_view_table(const gs_camera* cams, int32_t n_views, int32_t tile) 
   std::memset(&vt, 0, sizeof vt);
   vt.n_views = n_views;
   vt.tile = tile;
-  int32_t to = 0, po = 0, go = 0;
+  int32_t to = 0, po = 0, wo = 0;
   for (int v = 0; v < n_views; ++v) {
     ViewGeom& g = vt.v[v];
     g.W = cams[v].width;
@@ -80,12 +80,14 @@ ViewTable make_view_table(const gs_camera* cams, int32_t n_views, int32_t tile) 
     g.TY = (g.H + tile - 1) / tile;
     g.tile_off = to;
     g.pix_off = po;
-    g.grid_off = go;
+    g.WX = (g.TX + kWinSide - 1) / kWinSide;
+    g.WY = (g.TY + kWinSide - 1) / kWinSide;
+    g.win_off = wo;
     to += g.TX * g.TY;
     po += g.W * g.H;
-    go += (g.TX + 1) * (g.TY + 1);
+    wo += g.WX * g.WY;
   }
-  vt.total_grid = go;
+  vt.total_windows = wo;
   vt.total_tiles = to;
   vt.total_pixels = po;
   return vt;

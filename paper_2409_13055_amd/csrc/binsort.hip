@@ -3,13 +3,15 @@
 //
 // The required order of the (tile, pair) incidences is that of a stable sort
 // on the 64-bit key (global tile << 32 | FP32 bits of the depth) of the
-// incidences emitted in (v*N+i) order.  An LSD radix sort processes the key
-// from its least significant digit up, and every incidence of one pair shares
-// the low 32 key bits; so the depth digits are sorted first over the visible
-// (view, Gaussian) pairs only (V*N entries instead of M incidences), the
-// incidences are then emitted in that order, and the remaining passes sort
-// the tile digits.  The result is identical to the full 64-bit LSD sort while
-// moving 12*M bytes per depth digit less.
+// incidences emitted in (v*N+i) order: per tile, the pairs covering it in
+// depth order, ties in id order.  The depth digits are sorted once over the
+// visible (view, Gaussian) pairs (a stable LSD radix sort, V*N entries instead
+// of M incidences).  The tiles are then handled by binning windows of 8x8
+// tiles: the depth-ordered pairs are listed in every window their rect meets
+// (a short stable sort on the window index), and one wavefront per chunk of a
+// window's list writes the ids straight into their final slots, one lane per
+// tile, from per-chunk tile counts and the tile ranges.  No pass ever moves
+// the M incidences.
 //
 // Every kernel reads its element count from device memory and uses a grid
 // sized by the capacity, so the whole call can be captured in a HIP graph
@@ -185,84 +187,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scan_digit(uint32_t* __r
 constexpr int kItems = 8;
 constexpr int kTileKeys = kSortThreads * kItems;
 
-// Emission of the (tile, pair) incidences in depth order (pair order, tiles
-// row-major inside each pair's rect), generated on the fly from per-pair
-// offsets: see k_entry_offsets.  The first tile-digit pass reads its input
-// from here instead of from an emitted array.
-constexpr int kChunk = kItems;  // output slots per chunk_start entry: one thread's run
-struct EmitSrc {
-  const uint32_t* d_k;          // number of depth-ordered visible pairs
-  const uint64_t* ent_off;      // exclusive incidence offset per pair
-  const uint4* ent_rec;         // per pair: (global tile of the rect's top-left, TX | width << 16, id, tiles)
-  const uint32_t* chunk_start;  // pair holding slot c * kChunk
-};
-
-// Incidences q0 .. q0 + R - 1 into (kk, vv), q0 a multiple of kChunk; slots
-// at or past `end` (<= M) are left unset.  The owner of slot q0 comes from
-// the chunk table, then the run walks the rects, one pair record ahead.
-template <int R>
-__device__ __forceinline__ void emit_run(const EmitSrc& es, uint32_t K, uint64_t q0, uint64_t end, uint32_t* kk,
-                                         uint32_t* vv) {
-  if (q0 >= end) return;
-  uint32_t j = es.chunk_start[q0 / kChunk];
-  const uint64_t start = es.ent_off[j];
-  uint4 r = es.ent_rec[j];
-  uint4 rn = (j + 1 < K) ? es.ent_rec[j + 1] : r;
-  uint64_t next = start + r.w;
-  uint32_t w = r.y >> 16;
-  const uint32_t k0 = (uint32_t)(q0 - start);
-  uint32_t ty = k0 / w, tx = k0 - ty * w;
-#pragma unroll
-  for (int e = 0; e < R; ++e) {
-    const uint64_t q = q0 + e;
-    if (q < end) {
-      while (q >= next) {  // next pair (every listed pair has at least one tile)
-        ++j;
-        r = rn;
-        next += r.w;
-        rn = (j + 1 < K) ? es.ent_rec[j + 1] : r;
-        w = r.y >> 16;
-        tx = ty = 0;
-      }
-    }
-    kk[e] = r.x + ty * (r.y & 0xffffu) + tx;
-    vv[e] = r.z;
-    if (++tx == w) {
-      tx = 0;
-      ++ty;
-    }
-  }
-}
-
-// Digit histogram of the emitted incidences (the input of the first tile pass).
-__global__ __launch_bounds__(kSortThreads) void k_emit_hist(EmitSrc es, const uint32_t* __restrict__ d_m, int shift,
-                                                            int nb, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kRadixBins];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t K = *es.d_k;
-  const uint64_t M = *d_m;
-  const Chunk c = chunk_of(M, nb, blockIdx.x);
-  for (uint64_t tb = c.begin; tb < c.end; tb += kTileKeys) {
-    uint32_t kk[kItems], vv[kItems];
-    const uint64_t q0 = tb + (uint64_t)threadIdx.x * kItems;
-    emit_run<kItems>(es, K, q0, c.end, kk, vv);
-#pragma unroll
-    for (int e = 0; e < kItems; ++e)
-      if (q0 + e < c.end) atomicAdd(&h[(kk[e] >> shift) & (kRadixBins - 1)], 1u);
-  }
-  __syncthreads();
-  hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
-}
-
-// EMIT: the input tile is generated by emit_run (natural order, staged in LDS)
-// instead of being read from (kin, vin).
-template <bool EMIT>
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, EmitSrc es, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_count, int shift, int nb,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_total, uint64_t* __restrict__ keys64,
-    const float* __restrict__ rec) {
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                                const uint32_t* __restrict__ vin,
+                                                                uint32_t* __restrict__ kout,
+                                                                uint32_t* __restrict__ vout,
+                                                                const uint32_t* __restrict__ d_count, int shift,
+                                                                int nb, const uint32_t* __restrict__ hist,
+                                                                const uint32_t* __restrict__ digit_total) {
   __shared__ uint32_t s_keys[kTileKeys];
   __shared__ uint32_t s_vals[kTileKeys];
   __shared__ uint32_t s_wc[4][kRadixBins];
@@ -276,7 +207,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     s_glob[tid] = ex + hist[(size_t)tid * nb + blockIdx.x];
   }
   const uint64_t count = *d_count;
-  const uint32_t K = EMIT ? *es.d_k : 0u;
   const Chunk c = chunk_of(count, nb, blockIdx.x);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   // item k of lane `lane` in wave w sits at tile offset w*(kItems*64) + k*64 + lane
@@ -284,22 +214,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   for (uint64_t tb = c.begin; tb < c.end; tb += kTileKeys) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_wc[k][tid] = 0;
-    if (EMIT) {
-      uint32_t kk[kItems], vv[kItems];
-      emit_run<kItems>(es, K, tb + (uint64_t)tid * kItems, c.end, kk, vv);
-      uint4* sk = reinterpret_cast<uint4*>(s_keys) + tid * (kItems / 4);
-      uint4* sv = reinterpret_cast<uint4*>(s_vals) + tid * (kItems / 4);
-#pragma unroll
-      for (int q = 0; q < kItems / 4; ++q) {
-        sk[q] = make_uint4(kk[4 * q], kk[4 * q + 1], kk[4 * q + 2], kk[4 * q + 3]);
-        sv[q] = make_uint4(vv[4 * q], vv[4 * q + 1], vv[4 * q + 2], vv[4 * q + 3]);
-      }
-    }
     __syncthreads();
     uint32_t key[kItems], val[kItems], rk[kItems];
     const uint64_t lim = c.end - tb;  // keys left from this tile's start
-    if (!EMIT) {
-      // all of the tile's loads first, unconditionally (indices clamped into the tile), so they are
+    {
+      // all of the tile's loads first, with indices clamped into the tile and no branch, so they are
       // in flight together rather than one dependent round trip per item
       const uint32_t* kt = kin + tb;
       const uint32_t* vt = vin + tb;
@@ -315,10 +234,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     for (int k = 0; k < kItems; ++k) {
       const uint32_t o = o0 + (uint32_t)k * 64;
       const bool valid = o < lim;
-      if (EMIT) {
-        key[k] = valid ? s_keys[o] : 0u;
-        val[k] = valid ? s_vals[o] : 0u;
-      } else if (!valid) {
+      if (!valid) {
         key[k] = 0u;
         val[k] = 0u;
       }
@@ -366,10 +282,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const uint32_t kk = s_keys[i];
         const uint32_t d = (kk >> shift) & (kRadixBins - 1);
         const uint32_t g = s_glob[d] + (i - s_start[d]);
-        const uint32_t vv = s_vals[i];
-        if (kout) kout[g] = kk;
-        vout[g] = vv;
-        if (keys64) keys64[g] = ((uint64_t)kk << 32) | depth_key(rec, vv);
+        kout[g] = kk;
+        vout[g] = s_vals[i];
       }
     }
     __syncthreads();
@@ -378,192 +292,336 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 }
 
 // ---------------------------------------------------------------------------
-// Incidence counting and emission in depth order.
+// Window binning of the depth-ordered pairs.
+//
+// Every tile belongs to one binning window of kWinSide x kWinSide tiles.  A
+// depth-ordered pair is listed once in every window its tile rect meets (a
+// stable LSD radix sort of those (window, pair) items on the window index),
+// so each window's list is in depth order.  A window list is cut into chunks
+// of kChunkEntries entries; one wavefront takes a chunk with one lane per
+// tile of the window, walks the chunk's entries in order and writes the id
+// of every entry that covers its tile to that tile's next output slot.  The
+// slots come from the tile's range start plus the counts of the window's
+// earlier chunks (k_chunk_counts, k_chunk_scan), so each tile's list is the
+// depth order of the pairs covering it, exactly as the stable 64-bit key sort
+// orders it, and the incidences themselves are never sorted.
 // ---------------------------------------------------------------------------
-// Incidence counts per step of kStep consecutive depth-ordered pairs.
-constexpr int kStep = kSortThreads;
+constexpr int kStep = kSortThreads;     // depth-ordered pairs per block step
 constexpr int kScanThreads = 1024;
+constexpr int kChunkEntries = 512;      // window-list entries per chunk (one wavefront)
+constexpr int kChunkWavesPerBlock = kSortThreads / kWave;
 
-__global__ __launch_bounds__(kSortThreads) void k_step_pair_counts(const int32_t* __restrict__ tiles,
-                                                                   const uint32_t* __restrict__ sorted_val,
-                                                                   const uint32_t* __restrict__ d_k,
-                                                                   uint64_t* __restrict__ step_sums) {
+// Entry record of the depth-ordered pair j: x = x0 | x1 << 16 and
+// y = y0 | y1 << 16 (its tile rect [x0,x1) x [y0,y1) in its view's grid),
+// z = v*N+i, w = FP32 bits of its depth.
+__device__ inline uint32_t rect_windows(uint4 e) {
+  const uint32_t x0 = e.x & 0xffffu, x1 = e.x >> 16, y0 = e.y & 0xffffu, y1 = e.y >> 16;
+  if (x1 <= x0 || y1 <= y0) return 0;
+  return (((x1 - 1) >> kWinShift) - (x0 >> kWinShift) + 1) * (((y1 - 1) >> kWinShift) - (y0 >> kWinShift) + 1);
+}
+
+// Entry records of the depth-ordered pairs plus, per step of kStep pairs, the
+// number of (window, pair) items and of (tile, pair) incidences.
+__global__ __launch_bounds__(kSortThreads) void k_entry_records(const uint32_t* __restrict__ sorted_val,
+                                                                const float* __restrict__ rec,
+                                                                const uint32_t* __restrict__ d_k, ViewTable vt,
+                                                                uint32_t n, uint4* __restrict__ ent,
+                                                                uint64_t* __restrict__ step_win,
+                                                                uint64_t* __restrict__ step_tiles) {
   __shared__ uint64_t s_w[kSortThreads / 64];
   const uint32_t K = *d_k, nsteps = (K + kStep - 1) / kStep;
   for (uint32_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
     const uint32_t j = st * kStep + threadIdx.x;
-    const uint64_t cnt = j < K ? (uint64_t)tiles[sorted_val[j]] : 0;
-    uint64_t tot;
-    block_exclusive_scan<uint64_t>(cnt, s_w, tot);
-    if (threadIdx.x == 0) step_sums[st] = tot;
-  }
-}
-
-// Exclusive scan of the step sums in place (one block); M -> d_num_pairs,
-// overflow flag, and the clamped count for the tile passes (0 on overflow).
-__global__ __launch_bounds__(kScanThreads) void k_scan_steps(uint64_t* __restrict__ step_sums,
-                                                             const uint32_t* __restrict__ d_k,
-                                                             uint32_t* __restrict__ d_m, int64_t* __restrict__ d_pairs,
-                                                             int32_t* __restrict__ d_overflow, uint64_t capacity) {
-  __shared__ uint64_t s_w[kScanThreads / 64];
-  const uint32_t nsteps = (*d_k + kStep - 1) / kStep;
-  uint64_t carry = 0;
-  for (uint32_t base = 0; base < nsteps; base += kScanThreads) {
-    const uint32_t i = base + threadIdx.x;
-    const uint64_t v = i < nsteps ? step_sums[i] : 0;
-    uint64_t tot;
-    const uint64_t ex = block_exclusive_scan<uint64_t, kScanThreads>(v, s_w, tot);
-    if (i < nsteps) step_sums[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    *d_pairs = (int64_t)carry;
-    *d_overflow = carry > capacity ? 1 : 0;
-    // past the capacity the outputs are undefined; a zero count makes the
-    // remaining kernels of the call no-ops
-    *d_m = carry > capacity ? 0u : (uint32_t)carry;
-  }
-}
-
-// Emission offsets: k_entry_offsets gives every depth-ordered pair its
-// exclusive incidence offset and a compact description of its tile rect, and
-// records which pair holds the first slot of every kChunk-slot run of the
-// output; emit_run then looks up the owner of a run's first slot and walks
-// the rects row-major from there, so the work per output slot is fixed
-// however skewed the per-pair tile counts are, and the order is that of a
-// sequential emission (pair order, tiles row-major within a pair).
-__global__ __launch_bounds__(kSortThreads) void k_entry_offsets(
-    const int32_t* __restrict__ tiles, const uint32_t* __restrict__ sorted_val, const float* __restrict__ rec,
-    const uint32_t* __restrict__ d_k, const uint64_t* __restrict__ step_off, ViewTable vt, uint32_t n,
-    uint64_t capacity, uint64_t* __restrict__ ent_off, uint4* __restrict__ ent_rec,
-    uint32_t* __restrict__ chunk_start) {
-  __shared__ uint64_t s_w[kSortThreads / 64];
-  const uint32_t K = *d_k, nsteps = (K + kStep - 1) / kStep;
-  for (uint32_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
-    const uint32_t j = st * kStep + threadIdx.x;
-    uint64_t cnt = 0;
-    uint32_t id = 0;
+    // tiles (< 2^23 per pair, so a step's sum stays below 2^31) | windows << 32
+    uint64_t packed = 0;
     if (j < K) {
-      id = sorted_val[j];
-      cnt = (uint64_t)tiles[id];
-    }
-    uint64_t tot;
-    const uint64_t off = step_off[st] + block_exclusive_scan<uint64_t>(cnt, s_w, tot);
-    if (j < K) {
+      const uint32_t id = sorted_val[j];
       const ViewGeom& g = vt.v[id / n];
       const float4 r0 = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS)[0];
       const float4 r2 = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS)[2];
       int x0, y0, x1, y1;
       tile_rect(r0.x, r0.y, ext_x(__float_as_int(r2.z)), ext_y(__float_as_int(r2.z)), vt.tile, g.TX, g.TY, x0, y0,
-              x1, y1);
-      ent_off[j] = off;
-      ent_rec[j] = make_uint4((uint32_t)(g.tile_off + y0 * g.TX + x0), (uint32_t)g.TX | ((uint32_t)(x1 - x0) << 16),
-                              id, (uint32_t)cnt);
-      // chunk boundaries inside [off, off + cnt): this pair holds their first slot
-      if (off + cnt <= capacity)
-        for (uint64_t c = (off + kChunk - 1) / kChunk; c * kChunk < off + cnt; ++c) chunk_start[c] = j;
+                x1, y1);
+      const uint4 e = make_uint4((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16), id,
+                                 __float_as_uint(r2.y));
+      ent[j] = e;
+      const uint32_t nw = rect_windows(e);
+      if (nw) packed = (uint64_t)((x1 - x0) * (y1 - y0)) | ((uint64_t)nw << 32);
+    }
+    uint64_t tot;
+    block_exclusive_scan<uint64_t>(packed, s_w, tot);
+    if (threadIdx.x == 0) {
+      step_tiles[st] = tot & 0xffffffffull;
+      step_win[st] = tot >> 32;
     }
   }
 }
 
-// Tile coverage counts: every visible pair adds +1/-1 at the four corners of
-// its tile rect in its view's (TX+1) x (TY+1) difference grid, whose 2D
-// prefix sum (k_tile_counts) is the number of rects covering each tile.  A
-// corner in column TX or row TY only reaches cells outside every tile's
-// prefix, so it is dropped.  Block (b, v) takes kCoverPairs consecutive pairs
-// of view v and, when `priv` (every view's grid fits the dynamic LDS the
-// launch gives), accumulates in a private LDS copy of the grid, then adds its
-// non-zero cells to the global grid: device-wide atomics are resolved beyond
-// the per-XCD L2, so they are kept few and spread.  Otherwise the corners go
-// to the global grid directly.
-constexpr int kCoverPairs = 8192;
-constexpr int kCoverLdsCells = 16384;
+// Exclusive scans of the per-step item and incidence counts in place (one
+// block).  M -> d_num_pairs and the overflow flag; the clamped counts for the
+// rest of the call are zero on overflow, which makes its kernels no-ops.
+__global__ __launch_bounds__(kScanThreads) void k_scan_step_counts(uint64_t* __restrict__ step_win,
+                                                                   uint64_t* __restrict__ step_tiles,
+                                                                   const uint32_t* __restrict__ d_k,
+                                                                   uint32_t* __restrict__ d_e,
+                                                                   uint32_t* __restrict__ d_m,
+                                                                   int64_t* __restrict__ d_pairs,
+                                                                   int32_t* __restrict__ d_overflow,
+                                                                   uint64_t capacity) {
+  __shared__ uint64_t s_w[kScanThreads / 64];
+  const uint32_t nsteps = (*d_k + kStep - 1) / kStep;
+  uint64_t carry_w = 0, carry_t = 0;
+  for (uint32_t base = 0; base < nsteps; base += kScanThreads) {
+    const uint32_t i = base + threadIdx.x;
+    const uint64_t vw = i < nsteps ? step_win[i] : 0, vtl = i < nsteps ? step_tiles[i] : 0;
+    uint64_t tw, tt;
+    const uint64_t ew = block_exclusive_scan<uint64_t, kScanThreads>(vw, s_w, tw);
+    const uint64_t et = block_exclusive_scan<uint64_t, kScanThreads>(vtl, s_w, tt);
+    if (i < nsteps) {
+      step_win[i] = carry_w + ew;
+      step_tiles[i] = carry_t + et;
+    }
+    carry_w += tw;
+    carry_t += tt;
+  }
+  if (threadIdx.x == 0) {
+    const bool over = carry_t > capacity;
+    *d_pairs = (int64_t)carry_t;
+    *d_overflow = over ? 1 : 0;
+    // every item holds at least one incidence, so the item count fits too
+    *d_m = over ? 0u : (uint32_t)carry_t;
+    *d_e = over ? 0u : (uint32_t)carry_w;
+  }
+}
 
-__global__ __launch_bounds__(kSortThreads) void k_cover_counts(const int32_t* __restrict__ tiles,
-                                                               const float* __restrict__ rec, ViewTable vt,
-                                                               uint32_t n, int priv, int32_t* __restrict__ cover) {
-  extern __shared__ int32_t s_grid[];
-  const int v = blockIdx.y;
+// The (window, pair) items in pair order, windows row-major inside a pair:
+// key = global window index, value = j.
+__global__ __launch_bounds__(kSortThreads) void k_window_items(const uint4* __restrict__ ent,
+                                                               const uint32_t* __restrict__ d_k,
+                                                               const uint32_t* __restrict__ d_e,
+                                                               const uint64_t* __restrict__ step_win, ViewTable vt,
+                                                               uint32_t n, uint32_t* __restrict__ wkey,
+                                                               uint32_t* __restrict__ wval) {
+  __shared__ uint32_t s_w[kSortThreads / 64];
+  if (*d_e == 0) return;
+  const uint32_t K = *d_k, nsteps = (K + kStep - 1) / kStep;
+  for (uint32_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
+    const uint32_t j = st * kStep + threadIdx.x;
+    uint4 e = make_uint4(0, 0, 0, 0);
+    uint32_t nw = 0;
+    if (j < K) {
+      e = ent[j];
+      nw = rect_windows(e);
+    }
+    uint32_t tot;
+    uint64_t o = step_win[st] + block_exclusive_scan<uint32_t>(nw, s_w, tot);
+    if (nw) {
+      const ViewGeom& g = vt.v[e.z / n];
+      const uint32_t wx0 = (e.x & 0xffffu) >> kWinShift, wx1 = (((e.x >> 16) - 1) >> kWinShift) + 1;
+      const uint32_t wy0 = (e.y & 0xffffu) >> kWinShift, wy1 = (((e.y >> 16) - 1) >> kWinShift) + 1;
+      for (uint32_t wy = wy0; wy < wy1; ++wy)
+        for (uint32_t wx = wx0; wx < wx1; ++wx, ++o) {
+          wkey[o] = (uint32_t)g.win_off + wy * (uint32_t)g.WX + wx;
+          wval[o] = j;
+        }
+    }
+  }
+}
+
+// [wbeg[w], wend[w]) = window w's run in the window-sorted items (both
+// pre-filled with 0, so an empty window reads as an empty run).
+__global__ void k_window_bounds(const uint32_t* __restrict__ skey, const uint32_t* __restrict__ d_e,
+                                uint32_t* __restrict__ wbeg, uint32_t* __restrict__ wend) {
+  const uint32_t E = *d_e;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < E; i += gridDim.x * blockDim.x) {
+    const uint32_t k = skey[i];
+    if (i == 0 || skey[i - 1] != k) wbeg[k] = i;
+    if (i + 1 == E || skey[i + 1] != k) wend[k] = i + 1;
+  }
+}
+
+// cfirst[w] = index of window w's first chunk, cfirst[W] = chunk count (one block).
+__global__ __launch_bounds__(kScanThreads) void k_chunk_table(const uint32_t* __restrict__ wbeg,
+                                                              const uint32_t* __restrict__ wend, int n_windows,
+                                                              uint32_t* __restrict__ cfirst,
+                                                              uint32_t* __restrict__ d_nchunks) {
+  __shared__ uint32_t s_w[kScanThreads / 64];
+  uint32_t carry = 0;
+  for (int base = 0; base < n_windows; base += kScanThreads) {
+    const int w = base + threadIdx.x;
+    const uint32_t nch = w < n_windows ? (wend[w] - wbeg[w] + kChunkEntries - 1) / kChunkEntries : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<uint32_t, kScanThreads>(nch, s_w, tot);
+    if (w < n_windows) cfirst[w] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    cfirst[n_windows] = carry;
+    *d_nchunks = carry;
+  }
+}
+
+// Chunk c of the window lists (wave-uniform): its window, its entry run
+// [b, e) and the window's view and tile origin.
+struct ChunkGeom {
+  uint32_t w, b, e;
+  int view, tx0, ty0;
+};
+__device__ inline ChunkGeom chunk_geom(uint32_t c, const uint32_t* __restrict__ cfirst,
+                                       const uint32_t* __restrict__ wbeg, const uint32_t* __restrict__ wend,
+                                       const ViewTable& vt) {
+  // the last window whose first chunk is at or before c (an empty window shares its
+  // first-chunk index with the next one, so the search lands on a non-empty window)
+  uint32_t lo = 0, hi = (uint32_t)vt.total_windows;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (cfirst[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  ChunkGeom cg;
+  cg.w = lo;
+  cg.b = wbeg[lo] + (c - cfirst[lo]) * kChunkEntries;
+  cg.e = min(cg.b + kChunkEntries, wend[lo]);
+  int v = 0;
+  for (int u = 1; u < vt.n_views; ++u)
+    if ((uint32_t)vt.v[u].win_off <= lo) v = u;
   const ViewGeom& g = vt.v[v];
-  const int gw = g.TX + 1, cells = gw * (g.TY + 1);
-  int32_t* cg = cover + g.grid_off;
-  int32_t* grid = priv ? s_grid : cg;
-  if (priv) {
-    for (int c = threadIdx.x; c < cells; c += kSortThreads) s_grid[c] = 0;
-    __syncthreads();
-  }
-  const uint64_t i0 = (uint64_t)blockIdx.x * kCoverPairs;
-  const uint64_t i1 = min<uint64_t>((uint64_t)n, i0 + kCoverPairs);
-  for (uint64_t i = i0 + threadIdx.x; i < i1; i += kSortThreads) {
-    const size_t id = (size_t)v * n + i;
-    if (tiles[id] <= 0) continue;
-    const float4 r0 = reinterpret_cast<const float4*>(rec + id * GS_REC_FLOATS)[0];
-    const float4 r2 = reinterpret_cast<const float4*>(rec + id * GS_REC_FLOATS)[2];
-    int x0, y0, x1, y1;
-    tile_rect(r0.x, r0.y, ext_x(__float_as_int(r2.z)), ext_y(__float_as_int(r2.z)), vt.tile, g.TX, g.TY, x0, y0,
-              x1, y1);
-    atomicAdd(grid + y0 * gw + x0, 1);
-    if (x1 < g.TX) atomicAdd(grid + y0 * gw + x1, -1);
-    if (y1 < g.TY) atomicAdd(grid + y1 * gw + x0, -1);
-    if (x1 < g.TX && y1 < g.TY) atomicAdd(grid + y1 * gw + x1, 1);
-  }
-  if (priv) {
-    __syncthreads();
-    for (int c = threadIdx.x; c < cells; c += kSortThreads) {
-      const int32_t d = s_grid[c];
-      if (d != 0) atomicAdd(cg + c, d);
+  const int lw = (int)lo - g.win_off, wy = lw / g.WX;
+  cg.view = v;
+  cg.tx0 = (lw - wy * g.WX) * kWinSide;
+  cg.ty0 = wy * kWinSide;
+  return cg;
+}
+
+__device__ inline int clamp_win(int x) { return min(max(x, 0), kWinSide); }
+
+// The entry records of a chunk's run [b, e) (at most kChunkEntries) into
+// the wave's LDS slots: all index loads, then all record gathers, with indices
+// clamped into the run and no branch, so each set is in flight at once.
+constexpr int kChunkGroups = kChunkEntries / kWave;
+__device__ inline void stage_chunk(const uint32_t* __restrict__ sval, const uint4* __restrict__ ent, uint32_t b,
+                                   uint32_t e, int lane, uint4* s_ent) {
+  uint32_t jj[kChunkGroups];
+#pragma unroll
+  for (int q = 0; q < kChunkGroups; ++q) jj[q] = sval[min(b + (uint32_t)(q * kWave + lane), e - 1)];
+  uint4 rr[kChunkGroups];
+#pragma unroll
+  for (int q = 0; q < kChunkGroups; ++q) rr[q] = ent[jj[q]];
+#pragma unroll
+  for (int q = 0; q < kChunkGroups; ++q) s_ent[q * kWave + lane] = rr[q];
+}
+
+// Per chunk and tile of its window, the number of the chunk's entries that
+// cover the tile: the entries add +1/-1 at the corners of their rects (clipped
+// to the window) in a per-wave 8x8 difference grid in LDS, whose 2D inclusive
+// prefix is the count; corners in column or row kWinSide lie outside every
+// tile of the window and are dropped.  One wavefront per chunk, lane = tile.
+__global__ __launch_bounds__(kSortThreads) void k_chunk_counts(const uint32_t* __restrict__ sval,
+                                                               const uint4* __restrict__ ent, ViewTable vt,
+                                                               const uint32_t* __restrict__ wbeg,
+                                                               const uint32_t* __restrict__ wend,
+                                                               const uint32_t* __restrict__ cfirst,
+                                                               const uint32_t* __restrict__ d_nchunks,
+                                                               uint32_t* __restrict__ counts) {
+  __shared__ int32_t s_grid[kChunkWavesPerBlock][kWave];
+  __shared__ uint4 s_ent[kChunkWavesPerBlock][kChunkEntries];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int32_t* grid = s_grid[wv];
+  const uint32_t nch = *d_nchunks;
+  for (uint32_t c = blockIdx.x * kChunkWavesPerBlock + wv; c < nch; c += gridDim.x * kChunkWavesPerBlock) {
+    const ChunkGeom cg = chunk_geom(c, cfirst, wbeg, wend, vt);
+    stage_chunk(sval, ent, cg.b, cg.e, lane, s_ent[wv]);
+    grid[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t q = 0; q * kWave < cg.e - cg.b; ++q) {
+      if (cg.b + q * kWave + lane < cg.e) {
+        const uint4 r = s_ent[wv][q * kWave + lane];
+        // the rect meets the window (the entry is listed there), so the clipped rect is not empty
+        const int lx0 = clamp_win((int)(r.x & 0xffffu) - cg.tx0), lx1 = clamp_win((int)(r.x >> 16) - cg.tx0);
+        const int ly0 = clamp_win((int)(r.y & 0xffffu) - cg.ty0), ly1 = clamp_win((int)(r.y >> 16) - cg.ty0);
+        atomicAdd(grid + ly0 * kWinSide + lx0, 1);
+        if (lx1 < kWinSide) atomicAdd(grid + ly0 * kWinSide + lx1, -1);
+        if (ly1 < kWinSide) atomicAdd(grid + ly1 * kWinSide + lx0, -1);
+        if (lx1 < kWinSide && ly1 < kWinSide) atomicAdd(grid + ly1 * kWinSide + lx1, 1);
+      }
     }
+    __builtin_amdgcn_wave_barrier();
+    int32_t d = grid[lane];
+    // lane = ly * 8 + lx: prefix along the row, then down the column
+#pragma unroll
+    for (int o = 1; o < kWinSide; o <<= 1) {
+      const int32_t y = __shfl_up(d, o, kWinSide);
+      if ((lane & (kWinSide - 1)) >= o) d += y;
+    }
+#pragma unroll
+    for (int o = kWinSide; o < kWave; o <<= 1) {
+      const int32_t y = __shfl_up(d, o);
+      if (lane >= o) d += y;
+    }
+    counts[(size_t)c * kWave + lane] = (uint32_t)d;
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
-// Per-view 2D inclusive prefix of the coverage difference grid: the number of
-// pair rects covering each tile, i.e. the tile's incidence count.  One block
-// per view (rows, then columns).
-__global__ __launch_bounds__(kSortThreads) void k_tile_counts(ViewTable vt, int32_t* __restrict__ cover) {
-  const ViewGeom& g = vt.v[blockIdx.x];
-  int32_t* cg = cover + g.grid_off;
-  const int gw = g.TX + 1, gh = g.TY + 1;
-  for (int y = threadIdx.x; y < gh; y += kSortThreads) {
-    int32_t acc = 0;
-    for (int x = 0; x < gw; ++x) {
-      acc += cg[y * gw + x];
-      cg[y * gw + x] = acc;
-    }
-  }
+// One block per window: the counts of the window's chunks become exclusive
+// prefixes over the chunks (per tile), and the window's tiles get their
+// totals (0 for a window no pair meets).
+__global__ __launch_bounds__(kSortThreads) void k_chunk_scan(const uint32_t* __restrict__ cfirst, ViewTable vt,
+                                                             uint32_t* __restrict__ counts,
+                                                             uint32_t* __restrict__ tile_count) {
+  __shared__ uint32_t s_sum[kChunkWavesPerBlock][kWave];
+  const uint32_t w = blockIdx.x;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const uint32_t c0 = cfirst[w], c1 = cfirst[w + 1];
+  const uint32_t per = (c1 - c0 + kChunkWavesPerBlock - 1) / kChunkWavesPerBlock;
+  const uint32_t a = min(c0 + q * per, c1), z = min(a + per, c1);
+  uint32_t sum = 0;
+  for (uint32_t c = a; c < z; ++c) sum += counts[(size_t)c * kWave + lane];
+  s_sum[q][lane] = sum;
   __syncthreads();
-  for (int x = threadIdx.x; x < gw; x += kSortThreads) {
-    int32_t acc = 0;
-    for (int y = 0; y < gh; ++y) {
-      acc += cg[y * gw + x];
-      cg[y * gw + x] = acc;
-    }
+  uint32_t off = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < kChunkWavesPerBlock; ++k) {
+    const uint32_t s = s_sum[k][lane];
+    off += k < q ? s : 0u;
+    total += s;
+  }
+  for (uint32_t c = a; c < z; ++c) {
+    const uint32_t x = counts[(size_t)c * kWave + lane];
+    counts[(size_t)c * kWave + lane] = off;
+    off += x;
+  }
+  if (q == 0) {
+    int v = 0;
+    for (int u = 1; u < vt.n_views; ++u)
+      if ((uint32_t)vt.v[u].win_off <= w) v = u;
+    const ViewGeom& g = vt.v[v];
+    const int lw = (int)w - g.win_off, wy = lw / g.WX;
+    const int tx = (lw - wy * g.WX) * kWinSide + (lane & (kWinSide - 1));
+    const int ty = wy * kWinSide + (lane >> kWinShift);
+    if (tx < g.TX && ty < g.TY) tile_count[g.tile_off + ty * g.TX + tx] = total;
   }
 }
 
 // ranges[t] = [start, start + count) with start the exclusive prefix of the
 // tile counts in global tile order, (0,0) for an empty tile.  One block.
-__global__ __launch_bounds__(kScanThreads) void k_ranges_from_counts(ViewTable vt, const int32_t* __restrict__ cover,
+__global__ __launch_bounds__(kScanThreads) void k_ranges_from_counts(int total_tiles,
+                                                                      const uint32_t* __restrict__ tile_count,
                                                                       const uint32_t* __restrict__ d_m,
                                                                       uint32_t* __restrict__ ranges) {
   __shared__ uint64_t s_w[kScanThreads / 64];
   if (*d_m == 0) {  // no pairs, or the pair capacity overflowed
-    for (int t = threadIdx.x; t < vt.total_tiles; t += kScanThreads) ranges[2 * t] = ranges[2 * t + 1] = 0;
+    for (int t = threadIdx.x; t < total_tiles; t += kScanThreads) ranges[2 * t] = ranges[2 * t + 1] = 0;
     return;
   }
   uint64_t carry = 0;
-  int v = 0;
-  for (int base = 0; base < vt.total_tiles; base += kScanThreads) {
+  for (int base = 0; base < total_tiles; base += kScanThreads) {
     const int t = base + threadIdx.x;
-    uint32_t cnt = 0;
-    if (t < vt.total_tiles) {
-      while (v + 1 < vt.n_views && vt.v[v + 1].tile_off <= t) ++v;
-      const ViewGeom& g = vt.v[v];
-      const int lt = t - g.tile_off, ty = lt / g.TX, tx = lt - ty * g.TX;
-      cnt = (uint32_t)cover[g.grid_off + ty * (g.TX + 1) + tx];
-    }
+    const uint32_t cnt = t < total_tiles ? tile_count[t] : 0u;
     uint64_t tot;
     const uint64_t ex = carry + block_exclusive_scan<uint64_t, kScanThreads>(cnt, s_w, tot);
-    if (t < vt.total_tiles) {
+    if (t < total_tiles) {
       ranges[2 * t] = cnt ? (uint32_t)ex : 0u;
       ranges[2 * t + 1] = cnt ? (uint32_t)(ex + cnt) : 0u;
     }
@@ -571,9 +629,54 @@ __global__ __launch_bounds__(kScanThreads) void k_ranges_from_counts(ViewTable v
   }
 }
 
-// ---------------------------------------------------------------------------
-// Tile ranges (+ optional 64-bit keys) from the tile-sorted incidences.
-// ---------------------------------------------------------------------------
+// The incidences in their final order: one wavefront per chunk, lane = tile
+// of the window.  The chunk's entries are loaded 64 at a time (one per lane)
+// and broadcast in order; every lane whose tile an entry covers writes the
+// entry's id (and, when asked, the 64-bit key) to its tile's next slot.
+__global__ __launch_bounds__(kSortThreads) void k_chunk_emit(const uint32_t* __restrict__ sval,
+                                                             const uint4* __restrict__ ent, ViewTable vt,
+                                                             const uint32_t* __restrict__ wbeg,
+                                                             const uint32_t* __restrict__ wend,
+                                                             const uint32_t* __restrict__ cfirst,
+                                                             const uint32_t* __restrict__ d_nchunks,
+                                                             const uint32_t* __restrict__ counts,
+                                                             const uint32_t* __restrict__ ranges,
+                                                             const uint32_t* __restrict__ d_m,
+                                                             uint32_t* __restrict__ ids, uint64_t* __restrict__ keys) {
+  __shared__ uint4 s_ent[kChunkWavesPerBlock][kChunkEntries];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t nch = *d_nchunks, m = *d_m;
+  for (uint32_t c = blockIdx.x * kChunkWavesPerBlock + wv; c < nch; c += gridDim.x * kChunkWavesPerBlock) {
+    const ChunkGeom cg = chunk_geom(c, cfirst, wbeg, wend, vt);
+    stage_chunk(sval, ent, cg.b, cg.e, lane, s_ent[wv]);
+    const ViewGeom& g = vt.v[cg.view];
+    const uint32_t tx = (uint32_t)(cg.tx0 + (lane & (kWinSide - 1)));
+    const uint32_t ty = (uint32_t)(cg.ty0 + (lane >> kWinShift));
+    // a lane whose tile lies outside the view's grid is never covered (rects are clipped to the grid)
+    const bool in_grid = tx < (uint32_t)g.TX && ty < (uint32_t)g.TY;
+    const uint32_t gt = in_grid ? (uint32_t)g.tile_off + ty * (uint32_t)g.TX + tx : 0u;
+    uint32_t pos = in_grid ? ranges[2 * gt] + counts[(size_t)c * kWave + lane] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t g0 = 0; g0 < cg.e - cg.b; g0 += kWave) {
+      const uint4 r = s_ent[wv][g0 + lane];
+      const int n_in = (int)min<uint32_t>(kWave, cg.e - cg.b - g0);
+      for (int k = 0; k < n_in; ++k) {
+        const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)r.x, k);
+        const uint32_t sy = (uint32_t)__builtin_amdgcn_readlane((int)r.y, k);
+        const uint32_t x0 = sx & 0xffffu, y0 = sy & 0xffffu;
+        // (the slot bound holds by construction; it keeps every store inside the output)
+        if ((tx - x0 < (sx >> 16) - x0) & (ty - y0 < (sy >> 16) - y0) & (pos < m)) {
+          ids[pos] = (uint32_t)__builtin_amdgcn_readlane((int)r.z, k);
+          if (keys) keys[pos] = ((uint64_t)gt << 32) | (uint32_t)__builtin_amdgcn_readlane((int)r.w, k);
+          ++pos;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t value) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = value;
@@ -583,73 +686,74 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t va
 // Workspace layout.
 // ---------------------------------------------------------------------------
 struct SortPlan {
-  uint64_t vn;       // n_views * n
-  uint64_t cap;      // pair capacity
-  int nb_vn;         // blocks over V*N / K entries
-  int nb_m;          // blocks over pair entries
-  int n_steps;       // kStep-entry steps over V*N
-  int grid_steps;    // blocks striding over the steps
-  int tile_passes;   // 8-bit tile digits
-  size_t off_counters, off_part_a, off_steps, off_hist, off_dtot, off_eoff, off_erec, off_chunks, off_cover;
-  size_t off_akey, off_aval, off_bkey, off_bval, off_pkey0, off_pkey1, off_pval;
+  uint64_t vn;        // n_views * n
+  uint64_t cap;       // pair capacity (bounds the window items too: each holds an incidence)
+  int nb_vn;          // radix blocks over the visible pairs
+  int nb_items;       // radix blocks over the window items
+  int n_steps;        // kStep-pair steps over V*N
+  int grid_steps;     // blocks striding over the steps
+  int win_passes;     // 8-bit digits of the window index
+  uint64_t max_chunks;
+  size_t off_counters, off_part_a, off_step_win, off_step_tiles, off_ent, off_hist, off_dtot;
+  size_t off_akey, off_aval, off_bkey, off_bval, off_wkey0, off_wval0, off_wkey1, off_wval1;
+  size_t off_wbeg, off_wend, off_cfirst, off_counts, off_tcount;
   size_t bytes;
 };
 
-static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64_t total_grid, int64_t capacity) {
+static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64_t total_windows,
+                          int64_t capacity) {
   SortPlan p;
   p.vn = (uint64_t)n * (uint64_t)n_views;
   p.cap = (uint64_t)capacity;
   p.nb_vn = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.vn + 1023) / 1024));
-  p.nb_m = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.cap + 2047) / 2048));
+  p.nb_items = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.cap + 2047) / 2048));
   p.n_steps = (int)((p.vn + kStep - 1) / kStep);
   p.grid_steps = std::min(p.n_steps, 8192);
   int bits = 1;
-  while ((int64_t(1) << bits) < total_tiles) ++bits;
-  p.tile_passes = (bits + kRadixBits - 1) / kRadixBits;
+  while ((int64_t(1) << bits) < total_windows) ++bits;
+  p.win_passes = (bits + kRadixBits - 1) / kRadixBits;
+  p.max_chunks = p.cap / kChunkEntries + (uint64_t)total_windows + 1;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
     o += align256(bytes);
     return at;
   };
+  const uint64_t cap1 = std::max<uint64_t>(p.cap, 1);
   p.off_counters = take(64);
   p.off_part_a = take(sizeof(uint64_t) * p.nb_vn);
-  p.off_steps = take(sizeof(uint64_t) * p.n_steps);
-  p.off_eoff = take(sizeof(uint64_t) * p.vn);
-  p.off_erec = take(sizeof(uint4) * p.vn);
-  p.off_chunks = take(sizeof(uint32_t) * (p.cap / kChunk + 2));
-  p.off_cover = take(sizeof(int32_t) * (size_t)total_grid);
-  p.off_hist = take(sizeof(uint32_t) * kRadixBins * std::max(p.nb_vn, p.nb_m));
+  p.off_step_win = take(sizeof(uint64_t) * p.n_steps);
+  p.off_step_tiles = take(sizeof(uint64_t) * p.n_steps);
+  p.off_ent = take(sizeof(uint4) * p.vn);
+  p.off_hist = take(sizeof(uint32_t) * kRadixBins * std::max(p.nb_vn, p.nb_items));
   p.off_dtot = take(sizeof(uint32_t) * kRadixBins);
   p.off_akey = take(sizeof(uint32_t) * p.vn);
   p.off_aval = take(sizeof(uint32_t) * p.vn);
   p.off_bkey = take(sizeof(uint32_t) * p.vn);
   p.off_bval = take(sizeof(uint32_t) * p.vn);
-  p.off_pkey0 = take(sizeof(uint32_t) * std::max<uint64_t>(p.cap, 1));
-  p.off_pkey1 = take(sizeof(uint32_t) * std::max<uint64_t>(p.cap, 1));
-  p.off_pval = take(sizeof(uint32_t) * std::max<uint64_t>(p.cap, 1));
+  p.off_wkey0 = take(sizeof(uint32_t) * cap1);
+  p.off_wval0 = take(sizeof(uint32_t) * cap1);
+  p.off_wkey1 = take(sizeof(uint32_t) * cap1);
+  p.off_wval1 = take(sizeof(uint32_t) * cap1);
+  p.off_wbeg = take(sizeof(uint32_t) * (size_t)total_windows);
+  p.off_wend = take(sizeof(uint32_t) * (size_t)total_windows);
+  p.off_cfirst = take(sizeof(uint32_t) * ((size_t)total_windows + 1));
+  p.off_counts = take(sizeof(uint32_t) * kWave * p.max_chunks);
+  p.off_tcount = take(sizeof(uint32_t) * (size_t)total_tiles);
   p.bytes = o;
   return p;
 }
 
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                       const uint32_t* d_count, int shift, int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st,
-                       uint64_t* keys64 = nullptr, const float* rec = nullptr) {
+                       const uint32_t* d_count, int shift, int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st) {
   hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, kin, d_count, shift, nb, hist);
   hipLaunchKernelGGL(k_radix_scan_digit, dim3(kRadixBins), dim3(kSortThreads), 0, st, hist, nb, dtot);
-  hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, EmitSrc{}, kout, vout,
-                     d_count, shift, nb, hist, dtot, keys64, rec);
+  hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, d_count, shift, nb,
+                     hist, dtot);
 }
 
-// The first tile-digit pass over the incidences generated by emission.
-static void radix_pass_emit(const EmitSrc& es, uint32_t* kout, uint32_t* vout, const uint32_t* d_m, int shift,
-                            int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st, uint64_t* keys64,
-                            const float* rec) {
-  hipLaunchKernelGGL(k_emit_hist, dim3(nb), dim3(kSortThreads), 0, st, es, d_m, shift, nb, hist);
-  hipLaunchKernelGGL(k_radix_scan_digit, dim3(kRadixBins), dim3(kSortThreads), 0, st, hist, nb, dtot);
-  hipLaunchKernelGGL(k_radix_scatter<true>, dim3(nb), dim3(kSortThreads), 0, st, (const uint32_t*)nullptr,
-                     (const uint32_t*)nullptr, es, kout, vout, d_m, shift, nb, hist, dtot, keys64, rec);
-}
+// Blocks striding over the window-list chunks.
+constexpr int kChunkGrid = 2048;
 
 }  // namespace gs
 
@@ -663,7 +767,7 @@ extern "C" gs_status gs_bin_sort_workspace_size(int64_t n, const gs_camera* cams
   if (n < 1 || pair_capacity < 0) return fail(GS_ERR_INVALID_VALUE, "need n >= 1 and pair_capacity >= 0");
   if (pair_capacity >= (int64_t(1) << 32) - 1) return fail(GS_ERR_INVALID_VALUE, "pair_capacity must be < 2^32 - 1");
   const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
-  *bytes = make_plan(n, n_views, vt.total_tiles, vt.total_grid, pair_capacity).bytes;
+  *bytes = make_plan(n, n_views, vt.total_tiles, vt.total_windows, pair_capacity).bytes;
   return GS_OK;
 }
 
@@ -681,28 +785,34 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   if (bins->capacity < 0 || bins->capacity >= (int64_t(1) << 32) - 1)
     return fail(GS_ERR_INVALID_VALUE, "bins->capacity must be in [0, 2^32 - 1)");
   const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
-  const SortPlan p = make_plan(n, n_views, vt.total_tiles, vt.total_grid, bins->capacity);
+  const SortPlan p = make_plan(n, n_views, vt.total_tiles, vt.total_windows, bins->capacity);
   if (!workspace || workspace_bytes < p.bytes)
     return fail(GS_ERR_CAPACITY, "workspace too small: need " + std::to_string(p.bytes) + " bytes");
   hipStream_t st = as_stream(stream);
   char* ws = static_cast<char*>(workspace);
-  uint64_t* counters = reinterpret_cast<uint64_t*>(ws + p.off_counters);
-  uint32_t* d_k = reinterpret_cast<uint32_t*>(counters + 0);        // visible pair count
-  uint32_t* d_m = reinterpret_cast<uint32_t*>(counters + 1);        // min(M, capacity)
+  uint32_t* counters = reinterpret_cast<uint32_t*>(ws + p.off_counters);
+  uint32_t* d_k = counters + 0;        // visible pair count
+  uint32_t* d_e = counters + 1;        // window item count (0 on overflow)
+  uint32_t* d_m = counters + 2;        // incidence count (0 on overflow)
+  uint32_t* d_nchunks = counters + 3;  // window-list chunks
   uint64_t* part_a = reinterpret_cast<uint64_t*>(ws + p.off_part_a);
-  uint64_t* step_off = reinterpret_cast<uint64_t*>(ws + p.off_steps);
-  uint64_t* ent_off = reinterpret_cast<uint64_t*>(ws + p.off_eoff);
-  uint4* ent_rec = reinterpret_cast<uint4*>(ws + p.off_erec);
-  uint32_t* chunk_start = reinterpret_cast<uint32_t*>(ws + p.off_chunks);
-  int32_t* cover = reinterpret_cast<int32_t*>(ws + p.off_cover);
+  uint64_t* step_win = reinterpret_cast<uint64_t*>(ws + p.off_step_win);
+  uint64_t* step_tiles = reinterpret_cast<uint64_t*>(ws + p.off_step_tiles);
+  uint4* ent = reinterpret_cast<uint4*>(ws + p.off_ent);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
   uint32_t* dtot = reinterpret_cast<uint32_t*>(ws + p.off_dtot);
   uint32_t* akey = reinterpret_cast<uint32_t*>(ws + p.off_akey);
   uint32_t* aval = reinterpret_cast<uint32_t*>(ws + p.off_aval);
   uint32_t* bkey = reinterpret_cast<uint32_t*>(ws + p.off_bkey);
   uint32_t* bval = reinterpret_cast<uint32_t*>(ws + p.off_bval);
-  uint32_t* pkey[2] = {reinterpret_cast<uint32_t*>(ws + p.off_pkey0), reinterpret_cast<uint32_t*>(ws + p.off_pkey1)};
-  uint32_t* pval_ws = reinterpret_cast<uint32_t*>(ws + p.off_pval);
+  uint32_t* wkey[2] = {reinterpret_cast<uint32_t*>(ws + p.off_wkey0), reinterpret_cast<uint32_t*>(ws + p.off_wkey1)};
+  uint32_t* wval[2] = {reinterpret_cast<uint32_t*>(ws + p.off_wval0), reinterpret_cast<uint32_t*>(ws + p.off_wval1)};
+  uint32_t* wbeg = reinterpret_cast<uint32_t*>(ws + p.off_wbeg);
+  uint32_t* wend = reinterpret_cast<uint32_t*>(ws + p.off_wend);
+  uint32_t* cfirst = reinterpret_cast<uint32_t*>(ws + p.off_cfirst);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(ws + p.off_counts);
+  uint32_t* tcount = reinterpret_cast<uint32_t*>(ws + p.off_tcount);
+  const int W = vt.total_windows;
 
   // 1. visible (view, Gaussian) pairs, compacted in id order with their depth keys
   hipLaunchKernelGGL(k_count_visible, dim3(p.nb_vn), dim3(kSortThreads), 0, st, proj->tiles_touched, p.vn, p.nb_vn,
@@ -716,46 +826,33 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   radix_pass(bkey, bval, akey, aval, d_k, 8, p.nb_vn, hist, dtot, st);
   radix_pass(akey, aval, bkey, bval, d_k, 16, p.nb_vn, hist, dtot, st);
   radix_pass(bkey, bval, akey, aval, d_k, 24, p.nb_vn, hist, dtot, st);
-  // 3. incidence count M, overflow check, emission in depth order
-  hipLaunchKernelGGL(k_step_pair_counts, dim3(p.grid_steps), dim3(kSortThreads), 0, st, proj->tiles_touched, aval,
-                     d_k, step_off);
-  hipLaunchKernelGGL(k_scan_steps, dim3(1), dim3(kScanThreads), 0, st, step_off, d_k, d_m, bins->d_num_pairs,
-                     bins->d_overflow, p.cap);
-  // the last tile pass must land its values in bins->ids
-  uint32_t* vbuf[2];
-  if (p.tile_passes % 2 == 1) {
-    vbuf[0] = pval_ws;
-    vbuf[1] = bins->ids;
-  } else {
-    vbuf[0] = bins->ids;
-    vbuf[1] = pval_ws;
-  }
-  const uint64_t gcount = (uint64_t)vt.total_grid;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>(4096, (gcount + 255) / 256)), dim3(256), 0, st,
-                     reinterpret_cast<uint32_t*>(cover), gcount, 0u);
-  int max_cells = 0;
-  for (int v = 0; v < n_views; ++v) max_cells = std::max(max_cells, (vt.v[v].TX + 1) * (vt.v[v].TY + 1));
-  const int priv = max_cells <= kCoverLdsCells ? 1 : 0;
-  hipLaunchKernelGGL(k_cover_counts, dim3((unsigned)((n + kCoverPairs - 1) / kCoverPairs), (unsigned)n_views),
-                     dim3(kSortThreads), priv ? sizeof(int32_t) * (size_t)max_cells : 0, st, proj->tiles_touched,
-                     proj->rec, vt, (uint32_t)n, priv, cover);
-  hipLaunchKernelGGL(k_entry_offsets, dim3(p.grid_steps), dim3(kSortThreads), 0, st, proj->tiles_touched, aval,
-                     proj->rec, d_k, step_off, vt, (uint32_t)n, p.cap, ent_off, ent_rec, chunk_start);
-  // 4. tile ranges from the per-tile incidence counts (rect coverage)
-  hipLaunchKernelGGL(k_tile_counts, dim3(n_views), dim3(kSortThreads), 0, st, vt, cover);
-  hipLaunchKernelGGL(k_ranges_from_counts, dim3(1), dim3(kScanThreads), 0, st, vt, cover, d_m, bins->ranges);
-  // 5. tile digits, the first pass fed by emission; the last pass writes only the ids (and the optional
-  //    64-bit keys)
-  const EmitSrc es{d_k, ent_off, ent_rec, chunk_start};
-  for (int k = 0; k < p.tile_passes; ++k) {
-    const bool last = k + 1 == p.tile_passes;
-    uint32_t* kout = last ? nullptr : pkey[(k + 1) % 2];
-    uint64_t* k64 = last ? bins->keys : nullptr;
-    if (k == 0)
-      radix_pass_emit(es, kout, vbuf[(k + 1) % 2], d_m, 0, p.nb_m, hist, dtot, st, k64, proj->rec);
-    else
-      radix_pass(pkey[k % 2], vbuf[k % 2], kout, vbuf[(k + 1) % 2], d_m, kRadixBits * k, p.nb_m, hist, dtot, st, k64,
-                 proj->rec);
-  }
+  // 3. entry records, item and incidence counts, overflow check
+  hipLaunchKernelGGL(k_entry_records, dim3(p.grid_steps), dim3(kSortThreads), 0, st, aval, proj->rec, d_k, vt,
+                     (uint32_t)n, ent, step_win, step_tiles);
+  hipLaunchKernelGGL(k_scan_step_counts, dim3(1), dim3(kScanThreads), 0, st, step_win, step_tiles, d_k, d_e, d_m,
+                     bins->d_num_pairs, bins->d_overflow, p.cap);
+  // 4. (window, pair) items in depth order, stably sorted on the window index
+  hipLaunchKernelGGL(k_window_items, dim3(p.grid_steps), dim3(kSortThreads), 0, st, ent, d_k, d_e, step_win, vt,
+                     (uint32_t)n, wkey[0], wval[0]);
+  for (int k = 0; k < p.win_passes; ++k)
+    radix_pass(wkey[k % 2], wval[k % 2], wkey[(k + 1) % 2], wval[(k + 1) % 2], d_e, kRadixBits * k, p.nb_items, hist,
+               dtot, st);
+  const uint32_t* skey = wkey[p.win_passes % 2];
+  const uint32_t* sval = wval[p.win_passes % 2];
+  // 5. window runs and their chunks
+  const unsigned fill_grid = (unsigned)std::min<int64_t>(4096, (W + 255) / 256);
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, wbeg, (uint64_t)W, 0u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, wend, (uint64_t)W, 0u);
+  hipLaunchKernelGGL(k_window_bounds, dim3(p.nb_items), dim3(kSortThreads), 0, st, skey, d_e, wbeg, wend);
+  hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(kScanThreads), 0, st, wbeg, wend, W, cfirst, d_nchunks);
+  // 6. per-tile counts per chunk, their prefixes over each window's chunks, tile ranges
+  hipLaunchKernelGGL(k_chunk_counts, dim3(kChunkGrid), dim3(kSortThreads), 0, st, sval, ent, vt, wbeg, wend, cfirst,
+                     d_nchunks, counts);
+  hipLaunchKernelGGL(k_chunk_scan, dim3(W), dim3(kSortThreads), 0, st, cfirst, vt, counts, tcount);
+  hipLaunchKernelGGL(k_ranges_from_counts, dim3(1), dim3(kScanThreads), 0, st, vt.total_tiles, tcount, d_m,
+                     bins->ranges);
+  // 7. the incidences, written in place
+  hipLaunchKernelGGL(k_chunk_emit, dim3(kChunkGrid), dim3(kSortThreads), 0, st, sval, ent, vt, wbeg, wend, cfirst,
+                     d_nchunks, counts, bins->ranges, d_m, bins->ids, bins->keys);
   return check_launch("bin/sort");
 }

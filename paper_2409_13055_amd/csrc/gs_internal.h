@@ -13,18 +13,24 @@ namespace gs {
 
 constexpr int kWave = 64;
 
+// Binning windows: kWinSide x kWinSide tiles of one view, one wavefront lane
+// per tile.
+constexpr int kWinSide = 8;
+constexpr int kWinShift = 3;
+
 // Per-view geometry needed by the binning and raster kernels.
 struct ViewGeom {
   int32_t W, H, TX, TY;
   int32_t tile_off, pix_off;
-  int32_t grid_off;  // offset of the view's (TX+1)x(TY+1) tile-coverage grid
+  int32_t WX, WY;    // binning windows per row / column
+  int32_t win_off;   // global index of the view's first window
 };
 struct ViewTable {
   int32_t n_views;
   int32_t total_tiles;
   int32_t total_pixels;
   int32_t tile;
-  int32_t total_grid;
+  int32_t total_windows;
   ViewGeom v[GS_MAX_VIEWS];
 };
 
