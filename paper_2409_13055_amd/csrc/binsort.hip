@@ -26,6 +26,7 @@ namespace gs {
 constexpr int kSortThreads = 256;
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kScanThreads = 1024;
 
 struct Chunk {
   uint64_t begin, end;
@@ -63,32 +64,57 @@ __device__ inline T block_exclusive_scan(T v, T* s_wave /*[NT/64]*/, T& total) {
   return off + x - v;
 }
 
-__device__ inline uint32_t depth_key(const float* rec, uint32_t row) {
-  return __float_as_uint(rec[(size_t)row * GS_REC_FLOATS + kDepth]);
+// Entry record of a visible pair: x = x0 | x1 << 16 and y = y0 | y1 << 16
+// (its tile rect [x0,x1) x [y0,y1) in its view's grid), z = v*N+i,
+// w = FP32 bits of its depth.
+__device__ inline uint32_t rect_windows(uint4 e) {
+  const uint32_t x0 = e.x & 0xffffu, x1 = e.x >> 16, y0 = e.y & 0xffffu, y1 = e.y >> 16;
+  if (x1 <= x0 || y1 <= y0) return 0;
+  return (((x1 - 1) >> kWinShift) - (x0 >> kWinShift) + 1) * (((y1 - 1) >> kWinShift) - (y0 >> kWinShift) + 1);
+}
+__device__ inline uint32_t rect_tiles(uint4 e) {
+  const uint32_t x0 = e.x & 0xffffu, x1 = e.x >> 16, y0 = e.y & 0xffffu, y1 = e.y >> 16;
+  return (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
 }
 
+// Per-view fields indexed by a per-lane view inside a kernel, copied to LDS
+// once per block: a lane-indexed read of the kernel-argument table is a
+// vector memory load, whose wait would also wait for every store issued
+// before it.
+struct ViewLds {
+  int32_t a[GS_MAX_VIEWS], b[GS_MAX_VIEWS];
+};
+
 // ---------------------------------------------------------------------------
-// Visible-pair compaction: A_key/A_val = (depth bits, v*N+i) of every pair
-// with tiles_touched > 0, in (v*N+i) order.
+// Visible-pair compaction: for every pair with tiles_touched > 0, in (v*N+i)
+// order, its compaction index c: a_key[c] = depth bits, a_val[c] = c and
+// entc[c] = its entry record.
 // ---------------------------------------------------------------------------
+constexpr int kCompactItems = 8;  // consecutive pairs per thread
+
 __global__ __launch_bounds__(kSortThreads) void k_count_visible(const int32_t* __restrict__ tiles, uint64_t count,
                                                                 int nb, uint64_t* __restrict__ partial) {
   __shared__ uint64_t s_w[4];
   const Chunk c = chunk_of(count, nb, blockIdx.x);
   uint64_t sum = 0;
-  for (uint64_t i = c.begin + threadIdx.x; i < c.end; i += kSortThreads) sum += tiles[i] > 0 ? 1 : 0;
+  for (uint64_t base = c.begin; base < c.end; base += kSortThreads * kCompactItems) {
+    int32_t t[kCompactItems];
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k)
+      t[k] = tiles[min(base + (uint64_t)(k * kSortThreads + threadIdx.x), c.end - 1)];
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k)
+      sum += (base + (uint64_t)(k * kSortThreads + threadIdx.x) < c.end && t[k] > 0) ? 1 : 0;
+  }
   uint64_t tot;
   block_exclusive_scan<uint64_t>(sum, s_w, tot);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
 // Exclusive scan of the per-block partials in place (single block);
-// total -> *total_u64, *out_i64 and (0 when above cap32) *total_u32.
+// total -> *total_u32 (0 when above cap32).
 __global__ __launch_bounds__(kSortThreads) void k_scan_partials(uint64_t* __restrict__ partial, int nb,
-                                                                uint64_t* __restrict__ total_u64,
-                                                                uint32_t* __restrict__ total_u32, uint64_t cap32,
-                                                                int64_t* __restrict__ out_i64,
-                                                                int32_t* __restrict__ overflow, uint64_t capacity) {
+                                                                uint32_t* __restrict__ total_u32, uint64_t cap32) {
   __shared__ uint64_t s_w[4];
   uint64_t carry = 0;
   for (int base = 0; base < nb; base += kSortThreads) {
@@ -99,33 +125,74 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_partials(uint64_t* __rest
     if (i < nb) partial[i] = carry + ex;
     carry += tot;
   }
-  if (threadIdx.x == 0) {
-    if (total_u64) *total_u64 = carry;
-    // Past the capacity the outputs are undefined; a zero count makes every
-    // later kernel of the call a no-op instead of reading unwritten entries.
-    if (total_u32) *total_u32 = carry > cap32 ? 0u : (uint32_t)carry;
-    if (out_i64) *out_i64 = (int64_t)carry;
-    if (overflow) *overflow = carry > capacity ? 1 : 0;
-  }
+  if (threadIdx.x == 0) *total_u32 = carry > cap32 ? 0u : (uint32_t)carry;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_compact_visible(const int32_t* __restrict__ tiles,
                                                                   const float* __restrict__ rec, uint64_t count,
                                                                   int nb, const uint64_t* __restrict__ partial,
+                                                                  ViewTable vt, uint32_t n,
                                                                   uint32_t* __restrict__ a_key,
-                                                                  uint32_t* __restrict__ a_val) {
-  __shared__ uint64_t s_w[4];
+                                                                  uint32_t* __restrict__ a_val,
+                                                                  uint4* __restrict__ entc) {
+  __shared__ uint32_t s_w[4];
+  __shared__ ViewLds s_g;  // TX, TY
+  // a round's visible pairs, staged so that they leave as coalesced stores
+  __shared__ uint32_t s_key[kSortThreads * kCompactItems];
+  __shared__ uint4 s_rec[kSortThreads * kCompactItems];
+  if (threadIdx.x < vt.n_views) {
+    s_g.a[threadIdx.x] = vt.v[threadIdx.x].TX;
+    s_g.b[threadIdx.x] = vt.v[threadIdx.x].TY;
+  }
+  __syncthreads();
   const Chunk c = chunk_of(count, nb, blockIdx.x);
   uint64_t run = partial[blockIdx.x];
-  for (uint64_t base = c.begin; base < c.end; base += kSortThreads) {
-    const uint64_t i = base + threadIdx.x;
-    const bool vis = i < c.end && tiles[i] > 0;
-    uint64_t tot;
-    const uint64_t ex = block_exclusive_scan<uint64_t>(vis ? 1 : 0, s_w, tot);
-    if (vis) {
-      const uint64_t pos = run + ex;
-      a_key[pos] = depth_key(rec, (uint32_t)i);
-      a_val[pos] = (uint32_t)i;
+  for (uint64_t base = c.begin; base < c.end; base += kSortThreads * kCompactItems) {
+    // thread t takes the kCompactItems consecutive pairs from i0, so its visible
+    // ones are consecutive in the output too
+    const uint64_t i0 = base + (uint64_t)threadIdx.x * kCompactItems;
+    int32_t t[kCompactItems];
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k) t[k] = tiles[min(i0 + k, c.end - 1)];
+    uint32_t vis = 0, cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k)
+      if (i0 + k < c.end && t[k] > 0) {
+        vis |= 1u << k;
+        ++cnt;
+      }
+    // the visible rows' mean, depth and extents, all requested before any is used
+    float4 r0[kCompactItems], r2[kCompactItems];
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k) {
+      const float4* row = reinterpret_cast<const float4*>(rec + (size_t)min(i0 + k, c.end - 1) * GS_REC_FLOATS);
+      if ((vis >> k) & 1u) {
+        r0[k] = row[0];
+        r2[k] = row[2];
+      }
+    }
+    // (the scan's barriers also order this round's staging after the previous round's copy-out)
+    uint32_t tot;
+    uint32_t lp = block_exclusive_scan<uint32_t>(cnt, s_w, tot);
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k) {
+      if ((vis >> k) & 1u) {
+        const uint32_t id = (uint32_t)(i0 + k), v = id / n;
+        int x0, y0, x1, y1;
+        tile_rect(r0[k].x, r0[k].y, ext_x(__float_as_int(r2[k].z)), ext_y(__float_as_int(r2[k].z)), vt.tile,
+                  s_g.a[v], s_g.b[v], x0, y0, x1, y1);
+        const uint32_t d = __float_as_uint(r2[k].y);
+        s_key[lp] = d;
+        s_rec[lp] = make_uint4((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16), id, d);
+        ++lp;
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < tot; i += kSortThreads) {
+      const uint64_t pos = run + i;
+      a_key[pos] = s_key[i];
+      a_val[pos] = (uint32_t)pos;
+      entc[pos] = s_rec[i];
     }
     run += tot;
   }
@@ -183,19 +250,19 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scan_digit(uint32_t* __r
 // operations execute in program order, so no barrier is needed).  The tile is
 // then reordered by digit in LDS and written out digit run by digit run, so
 // global stores are coalesced.  Order inside a digit follows the input index,
-// which keeps every pass stable.
+// which keeps every pass stable.  V is the value type carried with the key.
 constexpr int kItems = 8;
 constexpr int kTileKeys = kSortThreads * kItems;
 
+template <typename V>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
-                                                                const uint32_t* __restrict__ vin,
-                                                                uint32_t* __restrict__ kout,
-                                                                uint32_t* __restrict__ vout,
+                                                                const V* __restrict__ vin,
+                                                                uint32_t* __restrict__ kout, V* __restrict__ vout,
                                                                 const uint32_t* __restrict__ d_count, int shift,
                                                                 int nb, const uint32_t* __restrict__ hist,
                                                                 const uint32_t* __restrict__ digit_total) {
   __shared__ uint32_t s_keys[kTileKeys];
-  __shared__ uint32_t s_vals[kTileKeys];
+  __shared__ V s_vals[kTileKeys];
   __shared__ uint32_t s_wc[4][kRadixBins];
   __shared__ uint32_t s_start[kRadixBins];
   __shared__ uint32_t s_glob[kRadixBins];
@@ -215,13 +282,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_wc[k][tid] = 0;
     __syncthreads();
-    uint32_t key[kItems], val[kItems], rk[kItems];
+    uint32_t key[kItems], rk[kItems];
+    V val[kItems];
     const uint64_t lim = c.end - tb;  // keys left from this tile's start
     {
       // all of the tile's loads first, with indices clamped into the tile and no branch, so they are
       // in flight together rather than one dependent round trip per item
       const uint32_t* kt = kin + tb;
-      const uint32_t* vt = vin + tb;
+      const V* vt = vin + tb;
       const uint32_t last = (uint32_t)min<uint64_t>(lim, (uint64_t)kTileKeys) - 1;
 #pragma unroll
       for (int k = 0; k < kItems; ++k) {
@@ -234,10 +302,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
     for (int k = 0; k < kItems; ++k) {
       const uint32_t o = o0 + (uint32_t)k * 64;
       const bool valid = o < lim;
-      if (!valid) {
-        key[k] = 0u;
-        val[k] = 0u;
-      }
+      if (!valid) key[k] = 0u;
       const uint32_t d = (key[k] >> shift) & (kRadixBins - 1);
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -296,63 +361,57 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
 //
 // Every tile belongs to one binning window of kWinSide x kWinSide tiles.  A
 // depth-ordered pair is listed once in every window its tile rect meets (a
-// stable LSD radix sort of those (window, pair) items on the window index),
-// so each window's list is in depth order.  A window list is cut into chunks
-// of kChunkEntries entries; one wavefront takes a chunk with one lane per
-// tile of the window, walks the chunk's entries in order and writes the id
+// stable LSD radix sort of those (window, entry record) items on the window
+// index), so each window's list is in depth order.  A window list is cut into
+// chunks of kChunkEntries entries; one wavefront takes a chunk with one lane
+// per tile of the window, walks the chunk's entries in order and writes the id
 // of every entry that covers its tile to that tile's next output slot.  The
 // slots come from the tile's range start plus the counts of the window's
 // earlier chunks (k_chunk_counts, k_chunk_scan), so each tile's list is the
 // depth order of the pairs covering it, exactly as the stable 64-bit key sort
 // orders it, and the incidences themselves are never sorted.
 // ---------------------------------------------------------------------------
-constexpr int kStep = kSortThreads;     // depth-ordered pairs per block step
-constexpr int kScanThreads = 1024;
-constexpr int kChunkEntries = 512;      // window-list entries per chunk (one wavefront)
+constexpr int kStepRounds = 8;
+constexpr int kStep = kSortThreads * kStepRounds;  // depth-ordered pairs per block step
+constexpr int kChunkEntries = 512;                 // window-list entries per chunk (one wavefront)
+constexpr int kChunkGroups = kChunkEntries / kWave;
 constexpr int kChunkWavesPerBlock = kSortThreads / kWave;
 
-// Entry record of the depth-ordered pair j: x = x0 | x1 << 16 and
-// y = y0 | y1 << 16 (its tile rect [x0,x1) x [y0,y1) in its view's grid),
-// z = v*N+i, w = FP32 bits of its depth.
-__device__ inline uint32_t rect_windows(uint4 e) {
-  const uint32_t x0 = e.x & 0xffffu, x1 = e.x >> 16, y0 = e.y & 0xffffu, y1 = e.y >> 16;
-  if (x1 <= x0 || y1 <= y0) return 0;
-  return (((x1 - 1) >> kWinShift) - (x0 >> kWinShift) + 1) * (((y1 - 1) >> kWinShift) - (y0 >> kWinShift) + 1);
-}
-
-// Entry records of the depth-ordered pairs plus, per step of kStep pairs, the
-// number of (window, pair) items and of (tile, pair) incidences.
-__global__ __launch_bounds__(kSortThreads) void k_entry_records(const uint32_t* __restrict__ sorted_val,
-                                                                const float* __restrict__ rec,
-                                                                const uint32_t* __restrict__ d_k, ViewTable vt,
-                                                                uint32_t n, uint4* __restrict__ ent,
+// Entry records in depth order (ent[j] = entc[sorted c]) plus, per step of
+// kStep pairs, the number of (window, pair) items and of (tile, pair)
+// incidences.
+__global__ __launch_bounds__(kSortThreads) void k_entry_records(const uint32_t* __restrict__ sorted_c,
+                                                                const uint4* __restrict__ entc,
+                                                                const uint32_t* __restrict__ d_k,
+                                                                uint4* __restrict__ ent,
                                                                 uint64_t* __restrict__ step_win,
                                                                 uint64_t* __restrict__ step_tiles) {
   __shared__ uint64_t s_w[kSortThreads / 64];
   const uint32_t K = *d_k, nsteps = (K + kStep - 1) / kStep;
   for (uint32_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
-    const uint32_t j = st * kStep + threadIdx.x;
-    // tiles (< 2^23 per pair, so a step's sum stays below 2^31) | windows << 32
-    uint64_t packed = 0;
-    if (j < K) {
-      const uint32_t id = sorted_val[j];
-      const ViewGeom& g = vt.v[id / n];
-      const float4 r0 = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS)[0];
-      const float4 r2 = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS)[2];
-      int x0, y0, x1, y1;
-      tile_rect(r0.x, r0.y, ext_x(__float_as_int(r2.z)), ext_y(__float_as_int(r2.z)), vt.tile, g.TX, g.TY, x0, y0,
-                x1, y1);
-      const uint4 e = make_uint4((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16), id,
-                                 __float_as_uint(r2.y));
-      ent[j] = e;
-      const uint32_t nw = rect_windows(e);
-      if (nw) packed = (uint64_t)((x1 - x0) * (y1 - y0)) | ((uint64_t)nw << 32);
+    const uint32_t j0 = st * kStep + threadIdx.x;
+    uint32_t cc[kStepRounds];
+#pragma unroll
+    for (int k = 0; k < kStepRounds; ++k) cc[k] = sorted_c[min(j0 + (uint32_t)(k * kSortThreads), K - 1)];
+    uint4 e[kStepRounds];
+#pragma unroll
+    for (int k = 0; k < kStepRounds; ++k) e[k] = entc[cc[k]];
+    uint64_t nt = 0, nw = 0;
+#pragma unroll
+    for (int k = 0; k < kStepRounds; ++k) {
+      const uint32_t j = j0 + (uint32_t)(k * kSortThreads);
+      if (j < K) {
+        ent[j] = e[k];
+        nt += rect_tiles(e[k]);
+        nw += rect_windows(e[k]);
+      }
     }
-    uint64_t tot;
-    block_exclusive_scan<uint64_t>(packed, s_w, tot);
+    uint64_t tt, tw;
+    block_exclusive_scan<uint64_t>(nt, s_w, tt);
+    block_exclusive_scan<uint64_t>(nw, s_w, tw);
     if (threadIdx.x == 0) {
-      step_tiles[st] = tot & 0xffffffffull;
-      step_win[st] = tot >> 32;
+      step_tiles[st] = tt;
+      step_win[st] = tw;
     }
   }
 }
@@ -394,36 +453,45 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_step_counts(uint64_t* __r
   }
 }
 
-// The (window, pair) items in pair order, windows row-major inside a pair:
-// key = global window index, value = j.
+// The (window, entry record) items in pair order, windows row-major inside a
+// pair: key = global window index.
 __global__ __launch_bounds__(kSortThreads) void k_window_items(const uint4* __restrict__ ent,
                                                                const uint32_t* __restrict__ d_k,
                                                                const uint32_t* __restrict__ d_e,
                                                                const uint64_t* __restrict__ step_win, ViewTable vt,
                                                                uint32_t n, uint32_t* __restrict__ wkey,
-                                                               uint32_t* __restrict__ wval) {
+                                                               uint4* __restrict__ wrec) {
   __shared__ uint32_t s_w[kSortThreads / 64];
+  __shared__ ViewLds s_g;  // win_off, WX
   if (*d_e == 0) return;
+  if (threadIdx.x < vt.n_views) {
+    s_g.a[threadIdx.x] = vt.v[threadIdx.x].win_off;
+    s_g.b[threadIdx.x] = vt.v[threadIdx.x].WX;
+  }
+  __syncthreads();
   const uint32_t K = *d_k, nsteps = (K + kStep - 1) / kStep;
   for (uint32_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
-    const uint32_t j = st * kStep + threadIdx.x;
-    uint4 e = make_uint4(0, 0, 0, 0);
-    uint32_t nw = 0;
-    if (j < K) {
-      e = ent[j];
-      nw = rect_windows(e);
-    }
-    uint32_t tot;
-    uint64_t o = step_win[st] + block_exclusive_scan<uint32_t>(nw, s_w, tot);
-    if (nw) {
-      const ViewGeom& g = vt.v[e.z / n];
-      const uint32_t wx0 = (e.x & 0xffffu) >> kWinShift, wx1 = (((e.x >> 16) - 1) >> kWinShift) + 1;
-      const uint32_t wy0 = (e.y & 0xffffu) >> kWinShift, wy1 = (((e.y >> 16) - 1) >> kWinShift) + 1;
-      for (uint32_t wy = wy0; wy < wy1; ++wy)
-        for (uint32_t wx = wx0; wx < wx1; ++wx, ++o) {
-          wkey[o] = (uint32_t)g.win_off + wy * (uint32_t)g.WX + wx;
-          wval[o] = j;
-        }
+    const uint32_t j0 = st * kStep + threadIdx.x;
+    uint4 e[kStepRounds];
+#pragma unroll
+    for (int k = 0; k < kStepRounds; ++k) e[k] = ent[min(j0 + (uint32_t)(k * kSortThreads), K - 1)];
+    uint64_t o = step_win[st];
+#pragma unroll
+    for (int k = 0; k < kStepRounds; ++k) {
+      const uint32_t nw = (j0 + (uint32_t)(k * kSortThreads) < K) ? rect_windows(e[k]) : 0u;
+      uint32_t tot;
+      uint64_t p = o + block_exclusive_scan<uint32_t>(nw, s_w, tot);
+      o += tot;
+      if (nw) {
+        const uint32_t v = e[k].z / n, win_off = (uint32_t)s_g.a[v], WX = (uint32_t)s_g.b[v];
+        const uint32_t wx0 = (e[k].x & 0xffffu) >> kWinShift, wx1 = (((e[k].x >> 16) - 1) >> kWinShift) + 1;
+        const uint32_t wy0 = (e[k].y & 0xffffu) >> kWinShift, wy1 = (((e[k].y >> 16) - 1) >> kWinShift) + 1;
+        for (uint32_t wy = wy0; wy < wy1; ++wy)
+          for (uint32_t wx = wx0; wx < wx1; ++wx, ++p) {
+            wkey[p] = win_off + wy * WX + wx;
+            wrec[p] = e[k];
+          }
+      }
     }
   }
 }
@@ -493,53 +561,57 @@ __device__ inline ChunkGeom chunk_geom(uint32_t c, const uint32_t* __restrict__ 
   return cg;
 }
 
-__device__ inline int clamp_win(int x) { return min(max(x, 0), kWinSide); }
-
-// The entry records of a chunk's run [b, e) (at most kChunkEntries) into
-// the wave's LDS slots: all index loads, then all record gathers, with indices
-// clamped into the run and no branch, so each set is in flight at once.
-constexpr int kChunkGroups = kChunkEntries / kWave;
-__device__ inline void stage_chunk(const uint32_t* __restrict__ sval, const uint4* __restrict__ ent, uint32_t b,
-                                   uint32_t e, int lane, uint4* s_ent) {
-  uint32_t jj[kChunkGroups];
-#pragma unroll
-  for (int q = 0; q < kChunkGroups; ++q) jj[q] = sval[min(b + (uint32_t)(q * kWave + lane), e - 1)];
-  uint4 rr[kChunkGroups];
-#pragma unroll
-  for (int q = 0; q < kChunkGroups; ++q) rr[q] = ent[jj[q]];
-#pragma unroll
-  for (int q = 0; q < kChunkGroups; ++q) s_ent[q * kWave + lane] = rr[q];
+// Chunk visiting order of the chunk kernels: runs of kXcdRun consecutive
+// chunks (mostly of one window) go to blocks of one XCD (blocks are handed to
+// the kXcds XCDs round robin), so the cache lines shared by neighbouring
+// chunks' slot runs of a tile are written through one XCD's L2.  Visit i of
+// XCD x is chunk ((i / kXcdRun) * kXcds + x) * kXcdRun + i % kXcdRun, which
+// grows with i, and every chunk has exactly one (x, i).
+constexpr uint32_t kXcds = 8;
+constexpr uint32_t kXcdRun = 16;
+__device__ inline uint32_t visited_chunk(uint32_t i, uint32_t xcd) {
+  return ((i / kXcdRun) * kXcds + xcd) * kXcdRun + i % kXcdRun;
 }
+
+// A chunk's entry records (at most kChunkEntries from b, below e), group q in
+// r[q] (lane = entry), loaded with indices clamped into the run and no branch
+// so that all of them are in flight at once.
+__device__ inline void load_chunk(const uint4* __restrict__ srec, uint32_t b, uint32_t e, int lane,
+                                  uint4 (&r)[kChunkGroups]) {
+#pragma unroll
+  for (int q = 0; q < kChunkGroups; ++q) r[q] = srec[min(b + (uint32_t)(q * kWave + lane), e - 1)];
+}
+
+__device__ inline int clamp_win(int x) { return min(max(x, 0), kWinSide); }
 
 // Per chunk and tile of its window, the number of the chunk's entries that
 // cover the tile: the entries add +1/-1 at the corners of their rects (clipped
 // to the window) in a per-wave 8x8 difference grid in LDS, whose 2D inclusive
 // prefix is the count; corners in column or row kWinSide lie outside every
 // tile of the window and are dropped.  One wavefront per chunk, lane = tile.
-__global__ __launch_bounds__(kSortThreads) void k_chunk_counts(const uint32_t* __restrict__ sval,
-                                                               const uint4* __restrict__ ent, ViewTable vt,
+__global__ __launch_bounds__(kSortThreads) void k_chunk_counts(const uint4* __restrict__ srec, ViewTable vt,
                                                                const uint32_t* __restrict__ wbeg,
                                                                const uint32_t* __restrict__ wend,
                                                                const uint32_t* __restrict__ cfirst,
                                                                const uint32_t* __restrict__ d_nchunks,
                                                                uint32_t* __restrict__ counts) {
   __shared__ int32_t s_grid[kChunkWavesPerBlock][kWave];
-  __shared__ uint4 s_ent[kChunkWavesPerBlock][kChunkEntries];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int32_t* grid = s_grid[wv];
   const uint32_t nch = *d_nchunks;
   for (uint32_t c = blockIdx.x * kChunkWavesPerBlock + wv; c < nch; c += gridDim.x * kChunkWavesPerBlock) {
     const ChunkGeom cg = chunk_geom(c, cfirst, wbeg, wend, vt);
-    stage_chunk(sval, ent, cg.b, cg.e, lane, s_ent[wv]);
+    uint4 r[kChunkGroups];
+    load_chunk(srec, cg.b, cg.e, lane, r);
     grid[lane] = 0;
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t q = 0; q * kWave < cg.e - cg.b; ++q) {
-      if (cg.b + q * kWave + lane < cg.e) {
-        const uint4 r = s_ent[wv][q * kWave + lane];
+#pragma unroll
+    for (int q = 0; q < kChunkGroups; ++q) {
+      if (cg.b + (uint32_t)(q * kWave + lane) < cg.e) {
         // the rect meets the window (the entry is listed there), so the clipped rect is not empty
-        const int lx0 = clamp_win((int)(r.x & 0xffffu) - cg.tx0), lx1 = clamp_win((int)(r.x >> 16) - cg.tx0);
-        const int ly0 = clamp_win((int)(r.y & 0xffffu) - cg.ty0), ly1 = clamp_win((int)(r.y >> 16) - cg.ty0);
+        const int lx0 = clamp_win((int)(r[q].x & 0xffffu) - cg.tx0), lx1 = clamp_win((int)(r[q].x >> 16) - cg.tx0);
+        const int ly0 = clamp_win((int)(r[q].y & 0xffffu) - cg.ty0), ly1 = clamp_win((int)(r[q].y >> 16) - cg.ty0);
         atomicAdd(grid + ly0 * kWinSide + lx0, 1);
         if (lx1 < kWinSide) atomicAdd(grid + ly0 * kWinSide + lx1, -1);
         if (ly1 < kWinSide) atomicAdd(grid + ly1 * kWinSide + lx0, -1);
@@ -630,11 +702,29 @@ __global__ __launch_bounds__(kScanThreads) void k_ranges_from_counts(int total_t
 }
 
 // The incidences in their final order: one wavefront per chunk, lane = tile
-// of the window.  The chunk's entries are loaded 64 at a time (one per lane)
-// and broadcast in order; every lane whose tile an entry covers writes the
-// entry's id (and, when asked, the 64-bit key) to its tile's next slot.
-__global__ __launch_bounds__(kSortThreads) void k_chunk_emit(const uint32_t* __restrict__ sval,
-                                                             const uint4* __restrict__ ent, ViewTable vt,
+// of the window, the chunk's entries 64 at a time (group q in r[q], lane =
+// entry).  An entry covers tile (lx, ly) exactly when it covers column lx and
+// row ly of the window, so 16 ballots (a 64-bit entry mask per column and per
+// row) give each tile the mask of the group's entries covering it as
+// col[lx] & row[ly].  Each lane expands its mask, in entry order, into an LDS
+// stage at its exclusive prefix over the tiles, and the stage leaves with
+// consecutive lanes on consecutive slots, so a store instruction writes whole
+// runs of tile slots instead of one scattered slot per covered tile.
+//
+// The grid gives every chunk a wavefront of its own whenever the chunks are
+// at most kEmitGridWaves: the vector memory counter is shared by loads and
+// stores and completes in order, so a wavefront that loaded its next chunk
+// after storing the last one would wait for all of those stores first.
+constexpr int kStageSlots = kWave * kWave;  // one group's incidences at most
+struct EmitLds {
+  uint16_t stage[kStageSlots];  // entry | tile << 6
+  uint64_t mask[2 * kWinSide];  // column masks, then row masks
+  uint32_t id[kWave];           // the group's entry ids
+  uint32_t depth[kWave];        // and depth bits (keys only)
+  uint32_t base[kWave];         // per tile: output slot of stage index 0
+};
+
+__global__ __launch_bounds__(kSortThreads) void k_chunk_emit(const uint4* __restrict__ srec, ViewTable vt,
                                                              const uint32_t* __restrict__ wbeg,
                                                              const uint32_t* __restrict__ wend,
                                                              const uint32_t* __restrict__ cfirst,
@@ -643,37 +733,84 @@ __global__ __launch_bounds__(kSortThreads) void k_chunk_emit(const uint32_t* __r
                                                              const uint32_t* __restrict__ ranges,
                                                              const uint32_t* __restrict__ d_m,
                                                              uint32_t* __restrict__ ids, uint64_t* __restrict__ keys) {
-  __shared__ uint4 s_ent[kChunkWavesPerBlock][kChunkEntries];
+  __shared__ EmitLds s_lds[kChunkWavesPerBlock];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  EmitLds& L = s_lds[wv];
+  const int lx = lane & (kWinSide - 1), ly = lane >> kWinShift;
   const uint32_t nch = *d_nchunks, m = *d_m;
-  for (uint32_t c = blockIdx.x * kChunkWavesPerBlock + wv; c < nch; c += gridDim.x * kChunkWavesPerBlock) {
+  // (the grid is a multiple of kXcds blocks)
+  const uint32_t xcd = blockIdx.x % kXcds, stride = (gridDim.x / kXcds) * kChunkWavesPerBlock;
+  for (uint32_t i = (blockIdx.x / kXcds) * kChunkWavesPerBlock + wv;; i += stride) {
+    const uint32_t c = visited_chunk(i, xcd);
+    if (c >= nch) break;
     const ChunkGeom cg = chunk_geom(c, cfirst, wbeg, wend, vt);
-    stage_chunk(sval, ent, cg.b, cg.e, lane, s_ent[wv]);
+    uint4 r[kChunkGroups];
+    load_chunk(srec, cg.b, cg.e, lane, r);
     const ViewGeom& g = vt.v[cg.view];
-    const uint32_t tx = (uint32_t)(cg.tx0 + (lane & (kWinSide - 1)));
-    const uint32_t ty = (uint32_t)(cg.ty0 + (lane >> kWinShift));
-    // a lane whose tile lies outside the view's grid is never covered (rects are clipped to the grid)
+    const uint32_t tx = (uint32_t)(cg.tx0 + lx), ty = (uint32_t)(cg.ty0 + ly);
+    // a tile outside the view's grid is never covered (rects are clipped to the grid)
     const bool in_grid = tx < (uint32_t)g.TX && ty < (uint32_t)g.TY;
-    const uint32_t gt = in_grid ? (uint32_t)g.tile_off + ty * (uint32_t)g.TX + tx : 0u;
-    uint32_t pos = in_grid ? ranges[2 * gt] + counts[(size_t)c * kWave + lane] : 0u;
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t g0 = 0; g0 < cg.e - cg.b; g0 += kWave) {
-      const uint4 r = s_ent[wv][g0 + lane];
-      const int n_in = (int)min<uint32_t>(kWave, cg.e - cg.b - g0);
-      for (int k = 0; k < n_in; ++k) {
-        const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)r.x, k);
-        const uint32_t sy = (uint32_t)__builtin_amdgcn_readlane((int)r.y, k);
-        const uint32_t x0 = sx & 0xffffu, y0 = sy & 0xffffu;
-        // (the slot bound holds by construction; it keeps every store inside the output)
-        if ((tx - x0 < (sx >> 16) - x0) & (ty - y0 < (sy >> 16) - y0) & (pos < m)) {
-          ids[pos] = (uint32_t)__builtin_amdgcn_readlane((int)r.z, k);
-          if (keys) keys[pos] = ((uint64_t)gt << 32) | (uint32_t)__builtin_amdgcn_readlane((int)r.w, k);
-          ++pos;
+    const uint32_t tile0 = (uint32_t)g.tile_off + (uint32_t)cg.ty0 * (uint32_t)g.TX + (uint32_t)cg.tx0;
+    uint32_t pos = in_grid ? ranges[2 * (tile0 + (uint32_t)ly * (uint32_t)g.TX + (uint32_t)lx)] +
+                                 counts[(size_t)c * kWave + lane]
+                           : 0u;
+    const uint32_t len = cg.e - cg.b;
+#pragma unroll
+    for (int q = 0; q < kChunkGroups; ++q) {
+      if ((uint32_t)(q * kWave) >= len) break;
+      const bool valid = (uint32_t)(q * kWave + lane) < len;
+      const int lx0 = clamp_win((int)(r[q].x & 0xffffu) - cg.tx0), lx1 = clamp_win((int)(r[q].x >> 16) - cg.tx0);
+      const int ly0 = clamp_win((int)(r[q].y & 0xffffu) - cg.ty0), ly1 = clamp_win((int)(r[q].y >> 16) - cg.ty0);
+      uint64_t mine = 0;
+#pragma unroll
+      for (int j = 0; j < kWinSide; ++j) {
+        const uint64_t cm = __ballot(valid && lx0 <= j && j < lx1);
+        const uint64_t rm = __ballot(valid && ly0 <= j && j < ly1);
+        mine = lane == j ? cm : mine;
+        mine = lane == kWinSide + j ? rm : mine;
+      }
+      if (lane < 2 * kWinSide) L.mask[lane] = mine;
+      L.id[lane] = r[q].z;
+      if (keys) L.depth[lane] = r[q].w;
+      __builtin_amdgcn_wave_barrier();
+      const uint64_t tm = in_grid ? (L.mask[lx] & L.mask[kWinSide + ly]) : 0ull;
+      const uint32_t pop = (uint32_t)__popcll(tm);
+      uint32_t incl = pop;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+      }
+      const uint32_t pre = incl - pop;
+      const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+      L.base[lane] = pos - pre;
+      // the mask's halves one after the other, each with 32-bit bit scans
+      uint16_t* dst = L.stage + pre;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint32_t mm = (uint32_t)(tm >> (32 * h));
+        const uint32_t eh = ((uint32_t)lane << 6) | (uint32_t)(32 * h);
+        while (mm) {
+          *dst++ = (uint16_t)(eh | (uint32_t)__builtin_ctz(mm));
+          mm &= mm - 1u;
         }
       }
+      __builtin_amdgcn_wave_barrier();
+      for (uint32_t o = (uint32_t)lane; o < total; o += kWave) {
+        const uint32_t v = L.stage[o], e = v & 63u, t = v >> 6;
+        const uint32_t slot = L.base[t] + o;
+        // (the slot bound holds by construction; it keeps every store inside the output)
+        if (slot < m) {
+          ids[slot] = L.id[e];
+          if (keys)
+            keys[slot] = ((uint64_t)(tile0 + (t >> kWinShift) * (uint32_t)g.TX + (t & (kWinSide - 1))) << 32) |
+                         L.depth[e];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      pos += pop;
     }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -694,8 +831,8 @@ struct SortPlan {
   int grid_steps;     // blocks striding over the steps
   int win_passes;     // 8-bit digits of the window index
   uint64_t max_chunks;
-  size_t off_counters, off_part_a, off_step_win, off_step_tiles, off_ent, off_hist, off_dtot;
-  size_t off_akey, off_aval, off_bkey, off_bval, off_wkey0, off_wval0, off_wkey1, off_wval1;
+  size_t off_counters, off_part_a, off_step_win, off_step_tiles, off_entc, off_ent, off_hist, off_dtot;
+  size_t off_akey, off_aval, off_bkey, off_bval, off_wkey0, off_wrec0, off_wkey1, off_wrec1;
   size_t off_wbeg, off_wend, off_cfirst, off_counts, off_tcount;
   size_t bytes;
 };
@@ -705,10 +842,10 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   SortPlan p;
   p.vn = (uint64_t)n * (uint64_t)n_views;
   p.cap = (uint64_t)capacity;
-  p.nb_vn = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.vn + 1023) / 1024));
+  p.nb_vn = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.vn + 2047) / 2048));
   p.nb_items = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.cap + 2047) / 2048));
   p.n_steps = (int)((p.vn + kStep - 1) / kStep);
-  p.grid_steps = std::min(p.n_steps, 8192);
+  p.grid_steps = std::min(p.n_steps, 4096);
   int bits = 1;
   while ((int64_t(1) << bits) < total_windows) ++bits;
   p.win_passes = (bits + kRadixBits - 1) / kRadixBits;
@@ -724,6 +861,7 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   p.off_part_a = take(sizeof(uint64_t) * p.nb_vn);
   p.off_step_win = take(sizeof(uint64_t) * p.n_steps);
   p.off_step_tiles = take(sizeof(uint64_t) * p.n_steps);
+  p.off_entc = take(sizeof(uint4) * p.vn);
   p.off_ent = take(sizeof(uint4) * p.vn);
   p.off_hist = take(sizeof(uint32_t) * kRadixBins * std::max(p.nb_vn, p.nb_items));
   p.off_dtot = take(sizeof(uint32_t) * kRadixBins);
@@ -732,9 +870,9 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   p.off_bkey = take(sizeof(uint32_t) * p.vn);
   p.off_bval = take(sizeof(uint32_t) * p.vn);
   p.off_wkey0 = take(sizeof(uint32_t) * cap1);
-  p.off_wval0 = take(sizeof(uint32_t) * cap1);
+  p.off_wrec0 = take(sizeof(uint4) * cap1);
   p.off_wkey1 = take(sizeof(uint32_t) * cap1);
-  p.off_wval1 = take(sizeof(uint32_t) * cap1);
+  p.off_wrec1 = take(sizeof(uint4) * cap1);
   p.off_wbeg = take(sizeof(uint32_t) * (size_t)total_windows);
   p.off_wend = take(sizeof(uint32_t) * (size_t)total_windows);
   p.off_cfirst = take(sizeof(uint32_t) * ((size_t)total_windows + 1));
@@ -744,16 +882,21 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   return p;
 }
 
-static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                       const uint32_t* d_count, int shift, int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st) {
+template <typename V>
+static void radix_pass(const uint32_t* kin, const V* vin, uint32_t* kout, V* vout, const uint32_t* d_count,
+                       int shift, int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st) {
   hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, kin, d_count, shift, nb, hist);
   hipLaunchKernelGGL(k_radix_scan_digit, dim3(kRadixBins), dim3(kSortThreads), 0, st, hist, nb, dtot);
-  hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, d_count, shift, nb,
-                     hist, dtot);
+  hipLaunchKernelGGL(k_radix_scatter<V>, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, d_count, shift,
+                     nb, hist, dtot);
 }
 
-// Blocks striding over the window-list chunks.
+// Blocks striding over the window-list chunks (a multiple of kXcds).
 constexpr int kChunkGrid = 2048;
+static_assert(kChunkGrid % kXcds == 0, "chunk grid must split evenly over the XCDs");
+// Wavefronts of the emit kernel (a multiple of kXcds blocks): one per chunk up to this many chunks.
+constexpr int kEmitGridWaves = 65536;
+static_assert((kEmitGridWaves / kChunkWavesPerBlock) % kXcds == 0, "emit grid must split evenly over the XCDs");
 
 }  // namespace gs
 
@@ -798,6 +941,7 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   uint64_t* part_a = reinterpret_cast<uint64_t*>(ws + p.off_part_a);
   uint64_t* step_win = reinterpret_cast<uint64_t*>(ws + p.off_step_win);
   uint64_t* step_tiles = reinterpret_cast<uint64_t*>(ws + p.off_step_tiles);
+  uint4* entc = reinterpret_cast<uint4*>(ws + p.off_entc);
   uint4* ent = reinterpret_cast<uint4*>(ws + p.off_ent);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
   uint32_t* dtot = reinterpret_cast<uint32_t*>(ws + p.off_dtot);
@@ -806,7 +950,7 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   uint32_t* bkey = reinterpret_cast<uint32_t*>(ws + p.off_bkey);
   uint32_t* bval = reinterpret_cast<uint32_t*>(ws + p.off_bval);
   uint32_t* wkey[2] = {reinterpret_cast<uint32_t*>(ws + p.off_wkey0), reinterpret_cast<uint32_t*>(ws + p.off_wkey1)};
-  uint32_t* wval[2] = {reinterpret_cast<uint32_t*>(ws + p.off_wval0), reinterpret_cast<uint32_t*>(ws + p.off_wval1)};
+  uint4* wrec[2] = {reinterpret_cast<uint4*>(ws + p.off_wrec0), reinterpret_cast<uint4*>(ws + p.off_wrec1)};
   uint32_t* wbeg = reinterpret_cast<uint32_t*>(ws + p.off_wbeg);
   uint32_t* wend = reinterpret_cast<uint32_t*>(ws + p.off_wend);
   uint32_t* cfirst = reinterpret_cast<uint32_t*>(ws + p.off_cfirst);
@@ -814,31 +958,31 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   uint32_t* tcount = reinterpret_cast<uint32_t*>(ws + p.off_tcount);
   const int W = vt.total_windows;
 
-  // 1. visible (view, Gaussian) pairs, compacted in id order with their depth keys
+  // 1. visible (view, Gaussian) pairs, compacted in id order with their depth keys and entry records
   hipLaunchKernelGGL(k_count_visible, dim3(p.nb_vn), dim3(kSortThreads), 0, st, proj->tiles_touched, p.vn, p.nb_vn,
                      part_a);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kSortThreads), 0, st, part_a, p.nb_vn, (uint64_t*)nullptr, d_k,
-                     (uint64_t)UINT32_MAX, (int64_t*)nullptr, (int32_t*)nullptr, (uint64_t)UINT64_MAX);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kSortThreads), 0, st, part_a, p.nb_vn, d_k,
+                     (uint64_t)UINT32_MAX);
   hipLaunchKernelGGL(k_compact_visible, dim3(p.nb_vn), dim3(kSortThreads), 0, st, proj->tiles_touched, proj->rec,
-                     p.vn, p.nb_vn, part_a, akey, aval);
+                     p.vn, p.nb_vn, part_a, vt, (uint32_t)n, akey, aval, entc);
   // 2. depth digits (bit 31 of a positive float is 0): four 8-bit passes, ends in (akey, aval)
-  radix_pass(akey, aval, bkey, bval, d_k, 0, p.nb_vn, hist, dtot, st);
-  radix_pass(bkey, bval, akey, aval, d_k, 8, p.nb_vn, hist, dtot, st);
-  radix_pass(akey, aval, bkey, bval, d_k, 16, p.nb_vn, hist, dtot, st);
-  radix_pass(bkey, bval, akey, aval, d_k, 24, p.nb_vn, hist, dtot, st);
-  // 3. entry records, item and incidence counts, overflow check
-  hipLaunchKernelGGL(k_entry_records, dim3(p.grid_steps), dim3(kSortThreads), 0, st, aval, proj->rec, d_k, vt,
-                     (uint32_t)n, ent, step_win, step_tiles);
+  radix_pass<uint32_t>(akey, aval, bkey, bval, d_k, 0, p.nb_vn, hist, dtot, st);
+  radix_pass<uint32_t>(bkey, bval, akey, aval, d_k, 8, p.nb_vn, hist, dtot, st);
+  radix_pass<uint32_t>(akey, aval, bkey, bval, d_k, 16, p.nb_vn, hist, dtot, st);
+  radix_pass<uint32_t>(bkey, bval, akey, aval, d_k, 24, p.nb_vn, hist, dtot, st);
+  // 3. entry records in depth order, item and incidence counts, overflow check
+  hipLaunchKernelGGL(k_entry_records, dim3(p.grid_steps), dim3(kSortThreads), 0, st, aval, entc, d_k, ent, step_win,
+                     step_tiles);
   hipLaunchKernelGGL(k_scan_step_counts, dim3(1), dim3(kScanThreads), 0, st, step_win, step_tiles, d_k, d_e, d_m,
                      bins->d_num_pairs, bins->d_overflow, p.cap);
-  // 4. (window, pair) items in depth order, stably sorted on the window index
+  // 4. (window, entry record) items in depth order, stably sorted on the window index
   hipLaunchKernelGGL(k_window_items, dim3(p.grid_steps), dim3(kSortThreads), 0, st, ent, d_k, d_e, step_win, vt,
-                     (uint32_t)n, wkey[0], wval[0]);
+                     (uint32_t)n, wkey[0], wrec[0]);
   for (int k = 0; k < p.win_passes; ++k)
-    radix_pass(wkey[k % 2], wval[k % 2], wkey[(k + 1) % 2], wval[(k + 1) % 2], d_e, kRadixBits * k, p.nb_items, hist,
-               dtot, st);
+    radix_pass<uint4>(wkey[k % 2], wrec[k % 2], wkey[(k + 1) % 2], wrec[(k + 1) % 2], d_e, kRadixBits * k,
+                      p.nb_items, hist, dtot, st);
   const uint32_t* skey = wkey[p.win_passes % 2];
-  const uint32_t* sval = wval[p.win_passes % 2];
+  const uint4* srec = wrec[p.win_passes % 2];
   // 5. window runs and their chunks
   const unsigned fill_grid = (unsigned)std::min<int64_t>(4096, (W + 255) / 256);
   hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, wbeg, (uint64_t)W, 0u);
@@ -846,13 +990,13 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   hipLaunchKernelGGL(k_window_bounds, dim3(p.nb_items), dim3(kSortThreads), 0, st, skey, d_e, wbeg, wend);
   hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(kScanThreads), 0, st, wbeg, wend, W, cfirst, d_nchunks);
   // 6. per-tile counts per chunk, their prefixes over each window's chunks, tile ranges
-  hipLaunchKernelGGL(k_chunk_counts, dim3(kChunkGrid), dim3(kSortThreads), 0, st, sval, ent, vt, wbeg, wend, cfirst,
+  hipLaunchKernelGGL(k_chunk_counts, dim3(kChunkGrid), dim3(kSortThreads), 0, st, srec, vt, wbeg, wend, cfirst,
                      d_nchunks, counts);
   hipLaunchKernelGGL(k_chunk_scan, dim3(W), dim3(kSortThreads), 0, st, cfirst, vt, counts, tcount);
   hipLaunchKernelGGL(k_ranges_from_counts, dim3(1), dim3(kScanThreads), 0, st, vt.total_tiles, tcount, d_m,
                      bins->ranges);
   // 7. the incidences, written in place
-  hipLaunchKernelGGL(k_chunk_emit, dim3(kChunkGrid), dim3(kSortThreads), 0, st, sval, ent, vt, wbeg, wend, cfirst,
-                     d_nchunks, counts, bins->ranges, d_m, bins->ids, bins->keys);
+  hipLaunchKernelGGL(k_chunk_emit, dim3(kEmitGridWaves / kChunkWavesPerBlock), dim3(kSortThreads), 0, st, srec, vt,
+                     wbeg, wend, cfirst, d_nchunks, counts, bins->ranges, d_m, bins->ids, bins->keys);
   return check_launch("bin/sort");
 }
