@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
 //
 // Every tile belongs to one binning window of kWinSide x kWinSide tiles.  A
 // depth-ordered pair is listed once in every window its tile rect meets (a
-// stable LSD radix sort of those (window, entry record) items on the window
+// stable LSD radix sort of those (window, item) pairs on the window
 // index), so each window's list is in depth order.  A window list is cut into
 // chunks of kChunkEntries entries; one wavefront takes a chunk with one lane
 // per tile of the window, walks the chunk's entries in order and writes the id
@@ -453,14 +453,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_step_counts(uint64_t* __r
   }
 }
 
-// The (window, entry record) items in pair order, windows row-major inside a
-// pair: key = global window index.
+// Window item: x = v*N+i, y = its rect clipped to the window, in window tile
+// coordinates lx0 | lx1 << 4 | ly0 << 8 | ly1 << 12 (each in [0, 8]).
+__device__ inline uint32_t clip_code(uint32_t lo, uint32_t hi, uint32_t w0) {
+  // [lo, hi) meets [w0, w0 + kWinSide); the clipped bounds relative to w0
+  return (uint32_t)(max(lo, w0) - w0) | ((uint32_t)(min(hi, w0 + kWinSide) - w0) << 4);
+}
+
+// The (window, item) pairs in pair order, windows row-major inside a pair:
+// key = global window index.
 __global__ __launch_bounds__(kSortThreads) void k_window_items(const uint4* __restrict__ ent,
                                                                const uint32_t* __restrict__ d_k,
                                                                const uint32_t* __restrict__ d_e,
                                                                const uint64_t* __restrict__ step_win, ViewTable vt,
                                                                uint32_t n, uint32_t* __restrict__ wkey,
-                                                               uint4* __restrict__ wrec) {
+                                                               uint2* __restrict__ witem) {
   __shared__ uint32_t s_w[kSortThreads / 64];
   __shared__ ViewLds s_g;  // win_off, WX
   if (*d_e == 0) return;
@@ -486,11 +493,13 @@ __global__ __launch_bounds__(kSortThreads) void k_window_items(const uint4* __re
         const uint32_t v = e[k].z / n, win_off = (uint32_t)s_g.a[v], WX = (uint32_t)s_g.b[v];
         const uint32_t wx0 = (e[k].x & 0xffffu) >> kWinShift, wx1 = (((e[k].x >> 16) - 1) >> kWinShift) + 1;
         const uint32_t wy0 = (e[k].y & 0xffffu) >> kWinShift, wy1 = (((e[k].y >> 16) - 1) >> kWinShift) + 1;
-        for (uint32_t wy = wy0; wy < wy1; ++wy)
+        for (uint32_t wy = wy0; wy < wy1; ++wy) {
+          const uint32_t cy = clip_code(e[k].y & 0xffffu, e[k].y >> 16, wy * kWinSide) << 8;
           for (uint32_t wx = wx0; wx < wx1; ++wx, ++p) {
             wkey[p] = win_off + wy * WX + wx;
-            wrec[p] = e[k];
+            witem[p] = make_uint2(e[k].z, cy | clip_code(e[k].x & 0xffffu, e[k].x >> 16, wx * kWinSide));
           }
+        }
       }
     }
   }
@@ -576,20 +585,23 @@ __device__ inline uint32_t visited_chunk(uint32_t i, uint32_t xcd) {
 // A chunk's entry records (at most kChunkEntries from b, below e), group q in
 // r[q] (lane = entry), loaded with indices clamped into the run and no branch
 // so that all of them are in flight at once.
-__device__ inline void load_chunk(const uint4* __restrict__ srec, uint32_t b, uint32_t e, int lane,
-                                  uint4 (&r)[kChunkGroups]) {
+__device__ inline void load_chunk(const uint2* __restrict__ srec, uint32_t b, uint32_t e, int lane,
+                                  uint2 (&r)[kChunkGroups]) {
 #pragma unroll
   for (int q = 0; q < kChunkGroups; ++q) r[q] = srec[min(b + (uint32_t)(q * kWave + lane), e - 1)];
 }
 
-__device__ inline int clamp_win(int x) { return min(max(x, 0), kWinSide); }
+__device__ inline int code_x0(uint32_t c) { return (int)(c & 15u); }
+__device__ inline int code_x1(uint32_t c) { return (int)((c >> 4) & 15u); }
+__device__ inline int code_y0(uint32_t c) { return (int)((c >> 8) & 15u); }
+__device__ inline int code_y1(uint32_t c) { return (int)(c >> 12); }
 
 // Per chunk and tile of its window, the number of the chunk's entries that
 // cover the tile: the entries add +1/-1 at the corners of their rects (clipped
 // to the window) in a per-wave 8x8 difference grid in LDS, whose 2D inclusive
 // prefix is the count; corners in column or row kWinSide lie outside every
 // tile of the window and are dropped.  One wavefront per chunk, lane = tile.
-__global__ __launch_bounds__(kSortThreads) void k_chunk_counts(const uint4* __restrict__ srec, ViewTable vt,
+__global__ __launch_bounds__(kSortThreads) void k_chunk_counts(const uint2* __restrict__ srec, ViewTable vt,
                                                                const uint32_t* __restrict__ wbeg,
                                                                const uint32_t* __restrict__ wend,
                                                                const uint32_t* __restrict__ cfirst,
@@ -602,7 +614,7 @@ __global__ __launch_bounds__(kSortThreads) void k_chunk_counts(const uint4* __re
   const uint32_t nch = *d_nchunks;
   for (uint32_t c = blockIdx.x * kChunkWavesPerBlock + wv; c < nch; c += gridDim.x * kChunkWavesPerBlock) {
     const ChunkGeom cg = chunk_geom(c, cfirst, wbeg, wend, vt);
-    uint4 r[kChunkGroups];
+    uint2 r[kChunkGroups];
     load_chunk(srec, cg.b, cg.e, lane, r);
     grid[lane] = 0;
     __builtin_amdgcn_wave_barrier();
@@ -610,8 +622,7 @@ __global__ __launch_bounds__(kSortThreads) void k_chunk_counts(const uint4* __re
     for (int q = 0; q < kChunkGroups; ++q) {
       if (cg.b + (uint32_t)(q * kWave + lane) < cg.e) {
         // the rect meets the window (the entry is listed there), so the clipped rect is not empty
-        const int lx0 = clamp_win((int)(r[q].x & 0xffffu) - cg.tx0), lx1 = clamp_win((int)(r[q].x >> 16) - cg.tx0);
-        const int ly0 = clamp_win((int)(r[q].y & 0xffffu) - cg.ty0), ly1 = clamp_win((int)(r[q].y >> 16) - cg.ty0);
+        const int lx0 = code_x0(r[q].y), lx1 = code_x1(r[q].y), ly0 = code_y0(r[q].y), ly1 = code_y1(r[q].y);
         atomicAdd(grid + ly0 * kWinSide + lx0, 1);
         if (lx1 < kWinSide) atomicAdd(grid + ly0 * kWinSide + lx1, -1);
         if (ly1 < kWinSide) atomicAdd(grid + ly1 * kWinSide + lx0, -1);
@@ -720,11 +731,11 @@ struct EmitLds {
   uint16_t stage[kStageSlots];  // entry | tile << 6
   uint64_t mask[2 * kWinSide];  // column masks, then row masks
   uint32_t id[kWave];           // the group's entry ids
-  uint32_t depth[kWave];        // and depth bits (keys only)
   uint32_t base[kWave];         // per tile: output slot of stage index 0
 };
 
-__global__ __launch_bounds__(kSortThreads) void k_chunk_emit(const uint4* __restrict__ srec, ViewTable vt,
+__global__ __launch_bounds__(kSortThreads) void k_chunk_emit(const uint2* __restrict__ srec,
+                                                             const float* __restrict__ rec, ViewTable vt,
                                                              const uint32_t* __restrict__ wbeg,
                                                              const uint32_t* __restrict__ wend,
                                                              const uint32_t* __restrict__ cfirst,
@@ -745,7 +756,7 @@ __global__ __launch_bounds__(kSortThreads) void k_chunk_emit(const uint4* __rest
     const uint32_t c = visited_chunk(i, xcd);
     if (c >= nch) break;
     const ChunkGeom cg = chunk_geom(c, cfirst, wbeg, wend, vt);
-    uint4 r[kChunkGroups];
+    uint2 r[kChunkGroups];
     load_chunk(srec, cg.b, cg.e, lane, r);
     const ViewGeom& g = vt.v[cg.view];
     const uint32_t tx = (uint32_t)(cg.tx0 + lx), ty = (uint32_t)(cg.ty0 + ly);
@@ -760,8 +771,7 @@ __global__ __launch_bounds__(kSortThreads) void k_chunk_emit(const uint4* __rest
     for (int q = 0; q < kChunkGroups; ++q) {
       if ((uint32_t)(q * kWave) >= len) break;
       const bool valid = (uint32_t)(q * kWave + lane) < len;
-      const int lx0 = clamp_win((int)(r[q].x & 0xffffu) - cg.tx0), lx1 = clamp_win((int)(r[q].x >> 16) - cg.tx0);
-      const int ly0 = clamp_win((int)(r[q].y & 0xffffu) - cg.ty0), ly1 = clamp_win((int)(r[q].y >> 16) - cg.ty0);
+      const int lx0 = code_x0(r[q].y), lx1 = code_x1(r[q].y), ly0 = code_y0(r[q].y), ly1 = code_y1(r[q].y);
       uint64_t mine = 0;
 #pragma unroll
       for (int j = 0; j < kWinSide; ++j) {
@@ -771,8 +781,7 @@ __global__ __launch_bounds__(kSortThreads) void k_chunk_emit(const uint4* __rest
         mine = lane == kWinSide + j ? rm : mine;
       }
       if (lane < 2 * kWinSide) L.mask[lane] = mine;
-      L.id[lane] = r[q].z;
-      if (keys) L.depth[lane] = r[q].w;
+      L.id[lane] = r[q].x;
       __builtin_amdgcn_wave_barrier();
       const uint64_t tm = in_grid ? (L.mask[lx] & L.mask[kWinSide + ly]) : 0ull;
       const uint32_t pop = (uint32_t)__popcll(tm);
@@ -802,10 +811,11 @@ __global__ __launch_bounds__(kSortThreads) void k_chunk_emit(const uint4* __rest
         const uint32_t slot = L.base[t] + o;
         // (the slot bound holds by construction; it keeps every store inside the output)
         if (slot < m) {
-          ids[slot] = L.id[e];
+          const uint32_t id = L.id[e];
+          ids[slot] = id;
           if (keys)
             keys[slot] = ((uint64_t)(tile0 + (t >> kWinShift) * (uint32_t)g.TX + (t & (kWinSide - 1))) << 32) |
-                         L.depth[e];
+                         __float_as_uint(rec[(size_t)id * GS_REC_FLOATS + kDepth]);
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -832,7 +842,7 @@ struct SortPlan {
   int win_passes;     // 8-bit digits of the window index
   uint64_t max_chunks;
   size_t off_counters, off_part_a, off_step_win, off_step_tiles, off_entc, off_ent, off_hist, off_dtot;
-  size_t off_akey, off_aval, off_bkey, off_bval, off_wkey0, off_wrec0, off_wkey1, off_wrec1;
+  size_t off_akey, off_aval, off_bkey, off_bval, off_wkey0, off_witem0, off_wkey1, off_witem1;
   size_t off_wbeg, off_wend, off_cfirst, off_counts, off_tcount;
   size_t bytes;
 };
@@ -870,9 +880,9 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   p.off_bkey = take(sizeof(uint32_t) * p.vn);
   p.off_bval = take(sizeof(uint32_t) * p.vn);
   p.off_wkey0 = take(sizeof(uint32_t) * cap1);
-  p.off_wrec0 = take(sizeof(uint4) * cap1);
+  p.off_witem0 = take(sizeof(uint2) * cap1);
   p.off_wkey1 = take(sizeof(uint32_t) * cap1);
-  p.off_wrec1 = take(sizeof(uint4) * cap1);
+  p.off_witem1 = take(sizeof(uint2) * cap1);
   p.off_wbeg = take(sizeof(uint32_t) * (size_t)total_windows);
   p.off_wend = take(sizeof(uint32_t) * (size_t)total_windows);
   p.off_cfirst = take(sizeof(uint32_t) * ((size_t)total_windows + 1));
@@ -950,7 +960,7 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   uint32_t* bkey = reinterpret_cast<uint32_t*>(ws + p.off_bkey);
   uint32_t* bval = reinterpret_cast<uint32_t*>(ws + p.off_bval);
   uint32_t* wkey[2] = {reinterpret_cast<uint32_t*>(ws + p.off_wkey0), reinterpret_cast<uint32_t*>(ws + p.off_wkey1)};
-  uint4* wrec[2] = {reinterpret_cast<uint4*>(ws + p.off_wrec0), reinterpret_cast<uint4*>(ws + p.off_wrec1)};
+  uint2* witem[2] = {reinterpret_cast<uint2*>(ws + p.off_witem0), reinterpret_cast<uint2*>(ws + p.off_witem1)};
   uint32_t* wbeg = reinterpret_cast<uint32_t*>(ws + p.off_wbeg);
   uint32_t* wend = reinterpret_cast<uint32_t*>(ws + p.off_wend);
   uint32_t* cfirst = reinterpret_cast<uint32_t*>(ws + p.off_cfirst);
@@ -975,14 +985,14 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
                      step_tiles);
   hipLaunchKernelGGL(k_scan_step_counts, dim3(1), dim3(kScanThreads), 0, st, step_win, step_tiles, d_k, d_e, d_m,
                      bins->d_num_pairs, bins->d_overflow, p.cap);
-  // 4. (window, entry record) items in depth order, stably sorted on the window index
+  // 4. (window, item) pairs in depth order, stably sorted on the window index
   hipLaunchKernelGGL(k_window_items, dim3(p.grid_steps), dim3(kSortThreads), 0, st, ent, d_k, d_e, step_win, vt,
-                     (uint32_t)n, wkey[0], wrec[0]);
+                     (uint32_t)n, wkey[0], witem[0]);
   for (int k = 0; k < p.win_passes; ++k)
-    radix_pass<uint4>(wkey[k % 2], wrec[k % 2], wkey[(k + 1) % 2], wrec[(k + 1) % 2], d_e, kRadixBits * k,
+    radix_pass<uint2>(wkey[k % 2], witem[k % 2], wkey[(k + 1) % 2], witem[(k + 1) % 2], d_e, kRadixBits * k,
                       p.nb_items, hist, dtot, st);
   const uint32_t* skey = wkey[p.win_passes % 2];
-  const uint4* srec = wrec[p.win_passes % 2];
+  const uint2* srec = witem[p.win_passes % 2];
   // 5. window runs and their chunks
   const unsigned fill_grid = (unsigned)std::min<int64_t>(4096, (W + 255) / 256);
   hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, wbeg, (uint64_t)W, 0u);
@@ -996,7 +1006,8 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   hipLaunchKernelGGL(k_ranges_from_counts, dim3(1), dim3(kScanThreads), 0, st, vt.total_tiles, tcount, d_m,
                      bins->ranges);
   // 7. the incidences, written in place
-  hipLaunchKernelGGL(k_chunk_emit, dim3(kEmitGridWaves / kChunkWavesPerBlock), dim3(kSortThreads), 0, st, srec, vt,
+  hipLaunchKernelGGL(k_chunk_emit, dim3(kEmitGridWaves / kChunkWavesPerBlock), dim3(kSortThreads), 0, st, srec,
+                     proj->rec, vt,
                      wbeg, wend, cfirst, d_nchunks, counts, bins->ranges, d_m, bins->ids, bins->keys);
   return check_launch("bin/sort");
 }

@@ -9,7 +9,7 @@ by HBM.
 
 Per-unit figures (P_n = 11 + 3K raw floats per Gaussian, K = (D+1)^2):
   project     N*4*P_n + V*N*(48 + 4)
-  bin_sort    V*N*8 + M*(12 + 24 + 8) + T*8
+  bin_sort    V*N*4 [tiles_touched] + Nv*16 [mean, depth, extents] + M*4 [ids] + T*8 [ranges]
   render_fwd  Nv*36 + M*4 + Px*(12 + 12 [target] + 8 [T_final, n_contrib unless checkpoint])
   raster_bwd  Px*(12 [image] + 12 [target]) + Nv*36 [records] + M*4 + Nv*36 [gradients]
   project_bwd N*(4*P_n + 8*P_n) + V*N*(36 + 16)
@@ -58,7 +58,7 @@ def algorithmic_bytes(c):
     project_bwd = N * 12 * Pn + V * N * 52
     return {
         "project": N * 4 * Pn + V * N * 52,
-        "bin_sort": V * N * 8 + M * 44 + T * 8,
+        "bin_sort": V * N * 4 + Nv * 16 + M * 4 + T * 8,
         "render_fwd": Nv * 36 + M * 4 + Px * (24 + saved),
         "raster_bwd": raster_bwd,
         "project_bwd": project_bwd,
