@@ -279,7 +279,8 @@ __device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBox
 // ---------------------------------------------------------------------------
 // A pixel that has stopped gets row coordinate +inf: its exponent is then
 // -inf or NaN and fails the cutoff test, so no separate flag is tested.
-template <int TILE>
+// STATE: the pixel state (T_final, n_contrib) is written (not under the checkpoint flag).
+template <int TILE, bool STATE>
 __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     RasterConsts rc, float* __restrict__ img, float* __restrict__ tfin, int32_t* __restrict__ ncon,
@@ -324,20 +325,21 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         const float power = splat_power(rt, Bv.x, fy[p] - A.y);
-        if (!(power >= Bv.z) || power > 0.0f) continue;
+        // only an exponent in [cutoff, 0] can reach alpha_min; the wave skips a pixel slot no lane reaches
+        if (!(power >= Bv.z && power <= 0.0f)) continue;
+        // the rest is branch-free: a pixel that does not blend gets weight 0, which adds exactly nothing
         const float alpha = fminf(amax, Bv.y * exp_hw(power));
-        if (alpha < rc.alpha_min) continue;
         const float test = T[p] * (1.0f - alpha);
-        if (test < rc.t_min) {
-          fy[p] = INFINITY;
-          continue;
-        }
-        const float wgt = alpha * T[p];
+        const bool keep = alpha >= rc.alpha_min;
+        const bool stop = keep && test < rc.t_min;
+        const bool blend = keep && !stop;
+        fy[p] = stop ? INFINITY : fy[p];
+        const float wgt = blend ? alpha * T[p] : 0.0f;
         C[p][0] = fmaf(Bv.w, wgt, C[p][0]);
         C[p][1] = fmaf(Cv.x, wgt, C[p][1]);
         C[p][2] = fmaf(Cv.y, wgt, C[p][2]);
-        T[p] = test;
-        last[p] = base - s + j + 1;
+        T[p] = blend ? test : T[p];
+        if (STATE) last[p] = blend ? base - s + j + 1 : last[p];
       }
     }
   }
@@ -351,7 +353,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
       img[pm.chan(p, c)] = out[c];
       if (target) lsum += fabsf(out[c] - target[pm.chan(p, c)]);
     }
-    if (tfin) {
+    if (STATE) {
       tfin[pm.pix(p)] = T[p];
       ncon[pm.pix(p)] = last[p];
     }
@@ -517,19 +519,21 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
       for (int p = 0; p < PPL; ++p) {
         const float dy = fy[p] - A.y;
         const float power = splat_power(rt, Bv.x, dy);
-        if (!(power >= Bv.z) || power > 0.0f) continue;
+        // only an exponent in [cutoff, 0] can reach alpha_min; the wave skips a pixel slot no lane reaches
+        if (!(power >= Bv.z && power <= 0.0f)) continue;
+        // the rest is branch-free: a pixel that does not blend gets weight 0 and no exponent
+        // gradient, which add exactly nothing (every factor is finite: 1 - alpha >= 1 - alpha_max)
         const float G = exp_hw(power);
         const float oG = Bv.y * G;
         const float alpha = fminf(amax, oG);
-        if (alpha < rc.alpha_min) continue;
         const float om = 1.0f - alpha;
         const float test = T[p] * om;
-        if (test < rc.t_min) {
-          fy[p] = INFINITY;
-          continue;
-        }
-        any = true;
-        const float wgt = alpha * T[p];
+        const bool keep = alpha >= rc.alpha_min;
+        const bool stop = keep && test < rc.t_min;
+        const bool blend = keep && !stop;
+        fy[p] = stop ? INFINITY : fy[p];
+        any = any || blend;
+        const float wgt = blend ? alpha * T[p] : 0.0f;
         S[p][0] = fmaf(-Bv.w, wgt, S[p][0]);
         S[p][1] = fmaf(-Cv.x, wgt, S[p][1]);
         S[p][2] = fmaf(-Cv.y, wgt, S[p][2]);
@@ -539,8 +543,8 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
         const float dc = fmaf(dl[p][2], Cv.y, fmaf(dl[p][1], Cv.x, dl[p][0] * Bv.w));
         const float ds = fmaf(dl[p][2], S[p][2], fmaf(dl[p][1], S[p][1], dl[p][0] * S[p][0]));
         const float dLda = fmaf(T[p], dc, -ds * __builtin_amdgcn_rcpf(om));
-        T[p] = test;
-        const bool unclamped = oG <= amax;  // d alpha / d(o, power) = 0 where clamped
+        T[p] = blend ? test : T[p];
+        const bool unclamped = blend && oG <= amax;  // d alpha / d(o, power) = 0 where clamped
         const float dLdp = unclamped ? dLda * alpha : 0.0f;
         acc.o = fmaf(dLda, unclamped ? G : 0.0f, acc.o);
         const float ux = dLdp * dx, uy = dLdp * dy;
@@ -720,20 +724,21 @@ extern "C" gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs
   int32_t* nc = opts->checkpoint ? nullptr : out->n_contrib;
   const dim3 grid((unsigned)vt.total_tiles);
   const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
+#define GS_LAUNCH_FWD(TILE_, NT_)                                                                              \
+  do {                                                                                                        \
+    if (tf)                                                                                                   \
+      hipLaunchKernelGGL((k_render_fwd<TILE_, true>), grid, dim3(NT_), 0, st, vt, proj->rec, bins->ids, rg, rc, \
+                         out->rgb, tf, nc, tgt, tl);                                                         \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_render_fwd<TILE_, false>), grid, dim3(NT_), 0, st, vt, proj->rec, bins->ids, rg,   \
+                         rc, out->rgb, tf, nc, tgt, tl);                                                     \
+  } while (0)
   switch (opts->tile_size) {
-    case 8:
-      hipLaunchKernelGGL(k_render_fwd<8>, grid, dim3(64), 0, st, vt, proj->rec, bins->ids, rg, rc, out->rgb, tf, nc,
-                         tgt, tl);
-      break;
-    case 16:
-      hipLaunchKernelGGL(k_render_fwd<16>, grid, dim3(64), 0, st, vt, proj->rec, bins->ids, rg, rc, out->rgb, tf, nc,
-                         tgt, tl);
-      break;
-    default:
-      hipLaunchKernelGGL(k_render_fwd<32>, grid, dim3(256), 0, st, vt, proj->rec, bins->ids, rg, rc, out->rgb, tf,
-                         nc, tgt, tl);
-      break;
+    case 8: GS_LAUNCH_FWD(8, 64); break;
+    case 16: GS_LAUNCH_FWD(16, 64); break;
+    default: GS_LAUNCH_FWD(32, 256); break;
   }
+#undef GS_LAUNCH_FWD
   if (want_loss) hipLaunchKernelGGL(k_loss_reduce, dim3(n_views), dim3(256), 0, st, vt, tl, loss->loss_out);
   return check_launch("render forward");
 }
