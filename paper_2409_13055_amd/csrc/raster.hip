@@ -94,13 +94,16 @@ struct TileShape<32> {
 // Pixel placement inside a tile.  Each wavefront owns a compact SUBW x SUBH
 // block of the tile (8x8 for tile 8; 16x16 for tiles 16 and 32, the latter as
 // a 2x2 arrangement of four waves); lane l owns column l % SUBW of that block
-// and PPL consecutive rows starting at (l / SUBW) * PPL.
+// and rows l / SUBW + p * RS, p < PPL (RS = SUBH / PPL).  Pixel slot p of the
+// wave is then the band of rows [p RS, (p + 1) RS) of the block, so a splat
+// that misses a band is skipped by the whole wave for that slot.
 template <int TILE>
 struct PixMap {
   static constexpr int WAVES = TileShape<TILE>::WAVES, PPL = TileShape<TILE>::PPL, NT = 64 * WAVES;
   static constexpr int SUBW = TILE < 16 ? TILE : 16, SUBH = 64 * PPL / SUBW;
   static_assert((TILE / SUBW) * (TILE / SUBH) == WAVES && SUBW * SUBH == 64 * PPL, "tile shape");
   static constexpr int WX = TILE / SUBW, WY = TILE / SUBH;  // wave blocks per tile row / column
+  static constexpr int RS = SUBH / PPL;                      // row stride between a lane's pixels
   int v, x, y0, W, H, pix_off, tile;
   int tx0, ty0;  // top-left pixel of the tile
   int wx0, wy0;  // top-left pixel of this wave's block
@@ -119,11 +122,12 @@ struct PixMap {
     wx0 = tx0 + (w % WX) * SUBW;
     wy0 = ty0 + (w / WX) * SUBH;
     x = wx0 + lane % SUBW;
-    y0 = wy0 + (lane / SUBW) * PPL;
+    y0 = wy0 + lane / SUBW;
   }
-  __device__ bool inside(int p) const { return x < W && y0 + p < H; }
-  __device__ int pix(int p) const { return pix_off + (y0 + p) * W + x; }
-  __device__ int chan(int p, int c) const { return 3 * pix_off + c * W * H + (y0 + p) * W + x; }
+  __device__ int row(int p) const { return y0 + p * RS; }
+  __device__ bool inside(int p) const { return x < W && row(p) < H; }
+  __device__ int pix(int p) const { return pix_off + row(p) * W + x; }
+  __device__ int chan(int p, int c) const { return 3 * pix_off + c * W * H + row(p) * W + x; }
 };
 
 // Wave-level cull bounds of a splat.  A pixel can reach
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
     T[p] = 1.0f;
     C[p][0] = C[p][1] = C[p][2] = 0.0f;
     last[p] = 0;
-    fy[p] = pm.inside(p) ? (float)(pm.y0 + p) : INFINITY;
+    fy[p] = pm.inside(p) ? (float)pm.row(p) : INFINITY;
   }
   const uint2 rg = ranges[blockIdx.x];
   const int s = (int)rg.x, e = (int)rg.y;
@@ -478,7 +482,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
   const float wv = 1.0f / (3.0f * (float)pm.W * (float)pm.H);
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
-    fy[p] = pm.inside(p) ? (float)(pm.y0 + p) : INFINITY;
+    fy[p] = pm.inside(p) ? (float)pm.row(p) : INFINITY;
     T[p] = 1.0f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -590,7 +594,7 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
     T[p] = 1.0f;
     last[p] = evals[p] = blended[p] = 0;
     done[p] = !pm.inside(p);
-    fy[p] = (float)(pm.y0 + p);
+    fy[p] = (float)pm.row(p);
   }
   const uint2 rg = ranges[blockIdx.x];
   const int s = (int)rg.x, e = (int)rg.y;
