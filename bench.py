@@ -212,12 +212,17 @@ def stage_breakdown(step, iters):
     """Average duration of each stage of the batched iteration, measured inside
     `iters` eager iterations (HIP events recorded between the stages on the
     stream the kernels are launched on).  Every stage is one call; project,
-    render_fwd, raster_bwd, project_bwd and adam each launch one kernel, so
-    their figures are that kernel's launch duration in the iteration."""
+    render_fwd, raster_bwd, project_bwd, adam and project_bwd_adam (the
+    projection backward fused with the Adam step) each launch one kernel (plus
+    the one-thread step increment), so their figures are that kernel's launch
+    duration in the iteration."""
     import torch
-    names = ["project", "bin_sort", "render_fwd", "clear_grad2d", "raster_bwd", "project_bwd"]
-    if step.adam is not None:
-        names.append("adam")
+    if step.fuse_adam:
+        names = ["project", "bin_sort", "render_fwd", "clear_grad2d", "raster_bwd", "project_bwd_adam"]
+    else:
+        names = ["project", "bin_sort", "render_fwd", "clear_grad2d", "raster_bwd", "project_bwd"]
+        if step.adam is not None:
+            names.append("adam")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(iters)]
     counts = torch.zeros(iters, 3, dtype=torch.int64, device=step.params.means.device)
     torch.cuda.synchronize()
@@ -231,7 +236,8 @@ def stage_breakdown(step, iters):
     out = {}
     for k, name in enumerate(names):
         out[name] = round(sum(e[k].elapsed_time(e[k + 1]) for e in evs) / iters, 4)
-    out["render_bwd"] = round(out["clear_grad2d"] + out["raster_bwd"] + out["project_bwd"], 4)
+    if not step.fuse_adam:
+        out["render_bwd"] = round(out["clear_grad2d"] + out["raster_bwd"] + out["project_bwd"], 4)
     out["step_eager"] = round(sum(e[0].elapsed_time(e[-1]) for e in evs) / iters, 4)
     mean = counts.double().mean(dim=0).tolist()
     work = {"evaluated": mean[0], "blended": mean[1], "contrib_prefix": mean[2], "iterations": iters}

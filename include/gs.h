@@ -318,6 +318,25 @@ typedef struct gs_adam_group {
 gs_status gs_adam_step(const gs_adam_group* groups /* host array */, int32_t n_groups, double beta1, double beta2,
                        double eps, int32_t* d_step, int32_t zero_grad, void* stream);
 
+/* Projection backward fused with the Adam step (the backward of Sec. III-B
+ * followed by the optimiser step of Sec. IV-A, without the raw-parameter
+ * gradients going through memory): for every Gaussian the gradient is formed
+ * as by gs_project_bwd from grad2d (summed over views; 0 for a Gaussian no
+ * view sees) and used at once for one Adam step of each of its parameters as
+ * by gs_adam_step (same hyper-parameters, t = *d_step + 1), after which
+ * *d_step is incremented.  The result equals gs_project_bwd into zeroed
+ * gradients followed by gs_adam_step, bit for bit.  `groups` is a host array
+ * of the 6 parameter groups in the order means, log_scales, quats,
+ * opacity_logits, sh_dc, sh_rest: group k's param must be the array `params`
+ * points to for it (read by the projection, then updated in place; a group
+ * with numel 0 may have NULL pointers), numel = n * width (3, 3, 4, 1, 3,
+ * 3 ((D+1)^2 - 1)), exp_avg / exp_avg_sq its moments (updated in place); grad
+ * is not used.  proj->tiles_touched as for gs_project_bwd. */
+gs_status gs_project_bwd_adam(const gs_params* params, const gs_projected* proj, const gs_camera* cams,
+                              int32_t n_views, const gs_options* opts, const float* grad2d,
+                              const gs_adam_group* groups /* host array [6] */, double beta1, double beta2, double eps,
+                              int32_t* d_step, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,7 +76,7 @@ class gs_adam_group(C.Structure):
 EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_options", "gs_total_tiles",
            "gs_total_pixels", "gs_bin_sort_workspace_size", "gs_render_fwd_workspace_size",
            "gs_render_bwd_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
-           "gs_raster_bwd", "gs_project_bwd", "gs_render_stats", "gs_adam_step")
+           "gs_raster_bwd", "gs_project_bwd", "gs_render_stats", "gs_adam_step", "gs_project_bwd_adam")
 
 _lib = None
 
@@ -113,6 +113,8 @@ def load(path: str = LIB_PATH):
         "gs_project_bwd": (C.c_int, [pp, C.POINTER(gs_projected), pc, i32, po, P, C.POINTER(gs_grads), P]),
         "gs_render_stats": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), pc, i32, po, P, P]),
         "gs_adam_step": (C.c_int, [C.POINTER(gs_adam_group), i32, C.c_double, C.c_double, C.c_double, P, i32, P]),
+        "gs_project_bwd_adam": (C.c_int, [pp, C.POINTER(gs_projected), pc, i32, po, P, C.POINTER(gs_adam_group),
+                                          C.c_double, C.c_double, C.c_double, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -228,3 +230,9 @@ def gs_render_stats(proj, n, bins, cams, n_views, opts, d_counts, stream):
 
 def gs_adam_step(groups, n_groups, beta1, beta2, eps, d_step, zero_grad, stream):
     _check("gs_adam_step", load().gs_adam_step(groups, n_groups, beta1, beta2, eps, d_step, zero_grad, stream))
+
+
+def gs_project_bwd_adam(params, proj, cams, n_views, opts, grad2d, groups, beta1, beta2, eps, d_step, stream):
+    _check("gs_project_bwd_adam", load().gs_project_bwd_adam(C.byref(params), C.byref(proj), cams, n_views,
+                                                             C.byref(opts), grad2d, groups, beta1, beta2, eps,
+                                                             d_step, stream))

@@ -25,30 +25,11 @@ struct AdamTable {
   int32_t n_groups;
 };
 
-// Coefficients in FP32; 1 - beta is formed in double on the host (forming it
-// from the FP32 beta would be off by up to 1.3e-5 relative for beta = 0.999).
-struct AdamCoef {
-  double b1d, b2d;
-  float b1, b2, omb1, omb2, eps;
-};
-
-__device__ __forceinline__ void adam_one(float& p, float& g, float& m, float& v, const AdamCoef& c,
-                                         float step_size, float inv_sqrt_bc2) {
-  m = c.b1 * m + c.omb1 * g;
-  v = c.b2 * v + c.omb2 * g * g;
-  p -= step_size * m / (sqrtf(v) * inv_sqrt_bc2 + c.eps);
-}
 
 __global__ __launch_bounds__(kAdamThreads) void k_adam(AdamTable t, AdamCoef c, const int32_t* __restrict__ d_step,
                                                        int zero_grad) {
   __shared__ float s_k[2];
-  if (threadIdx.x == 0) {
-    const double st = (double)(*d_step) + 1.0;
-    const double bc1 = 1.0 - std::pow(c.b1d, st);
-    const double bc2 = 1.0 - std::pow(c.b2d, st);
-    s_k[0] = (float)(1.0 / bc1);
-    s_k[1] = (float)(1.0 / std::sqrt(bc2));
-  }
+  if (threadIdx.x == 0) adam_bias_factors(c, *d_step, s_k[0], s_k[1]);
   __syncthreads();
   const int64_t b = blockIdx.x;
   int gi = 0;
@@ -72,10 +53,10 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam(AdamTable t, AdamCoef c, 
     float4 g = *reinterpret_cast<float4*>(G + e0);
     float4 m = *reinterpret_cast<float4*>(M + e0);
     float4 v = *reinterpret_cast<float4*>(V + e0);
-    adam_one(p.x, g.x, m.x, v.x, c, step_size, isb);
-    adam_one(p.y, g.y, m.y, v.y, c, step_size, isb);
-    adam_one(p.z, g.z, m.z, v.z, c, step_size, isb);
-    adam_one(p.w, g.w, m.w, v.w, c, step_size, isb);
+    adam_update(p.x, g.x, m.x, v.x, c, step_size, isb);
+    adam_update(p.y, g.y, m.y, v.y, c, step_size, isb);
+    adam_update(p.z, g.z, m.z, v.z, c, step_size, isb);
+    adam_update(p.w, g.w, m.w, v.w, c, step_size, isb);
     *reinterpret_cast<float4*>(P + e0) = p;
     *reinterpret_cast<float4*>(M + e0) = m;
     *reinterpret_cast<float4*>(V + e0) = v;
@@ -83,7 +64,7 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam(AdamTable t, AdamCoef c, 
   } else {
     for (int64_t e = e0; e < n && e < e0 + kAdamVec; ++e) {
       float p = P[e], g = G[e], m = M[e], v = V[e];
-      adam_one(p, g, m, v, c, step_size, isb);
+      adam_update(p, g, m, v, c, step_size, isb);
       P[e] = p;
       M[e] = m;
       V[e] = v;
@@ -96,6 +77,21 @@ __global__ void k_step_increment(int32_t* d_step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *d_step += 1;
 }
 
+void launch_step_increment(int32_t* d_step, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(64), 0, st, d_step);
+}
+
+AdamCoef make_adam_coef(double beta1, double beta2, double eps) {
+  return AdamCoef{beta1, beta2, (float)beta1, (float)beta2, (float)(1.0 - beta1), (float)(1.0 - beta2), (float)eps};
+}
+
+gs_status validate_adam_hyper(double beta1, double beta2, double eps, const int32_t* d_step) {
+  if (!d_step) return fail(GS_ERR_INVALID_VALUE, "d_step is NULL");
+  if (!(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0) || !std::isfinite(eps))
+    return fail(GS_ERR_INVALID_VALUE, "need 0 <= beta < 1 and eps >= 0");
+  return GS_OK;
+}
+
 }  // namespace gs
 
 extern "C" gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, double beta1, double beta2,
@@ -103,9 +99,8 @@ extern "C" gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups,
   using namespace gs;
   if (!groups || n_groups < 1 || n_groups > GS_MAX_ADAM_GROUPS)
     return fail(GS_ERR_INVALID_VALUE, "n_groups must be in [1, " + std::to_string(GS_MAX_ADAM_GROUPS) + "]");
-  if (!d_step) return fail(GS_ERR_INVALID_VALUE, "d_step is NULL");
-  if (!(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0) || !std::isfinite(eps))
-    return fail(GS_ERR_INVALID_VALUE, "need 0 <= beta < 1 and eps >= 0");
+  gs_status s;
+  if ((s = validate_adam_hyper(beta1, beta2, eps, d_step)) != GS_OK) return s;
   AdamTable t{};
   t.n_groups = n_groups;
   int64_t blocks = 0;
@@ -125,10 +120,10 @@ extern "C" gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups,
     blocks += (g.numel + (int64_t)kAdamThreads * kAdamVec - 1) / ((int64_t)kAdamThreads * kAdamVec);
   }
   t.blk_off[n_groups] = blocks;
-  const AdamCoef c{beta1, beta2, (float)beta1, (float)beta2, (float)(1.0 - beta1), (float)(1.0 - beta2), (float)eps};
+  const AdamCoef c = make_adam_coef(beta1, beta2, eps);
   hipStream_t st = as_stream(stream);
   if (blocks > 0)
     hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(kAdamThreads), 0, st, t, c, d_step, zero_grad);
-  hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(64), 0, st, d_step);
+  launch_step_increment(d_step, st);
   return check_launch("adam");
 }

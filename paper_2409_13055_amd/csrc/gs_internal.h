@@ -71,6 +71,34 @@ constexpr int kMaxExtent = 32767;
 __host__ __device__ inline int ext_x(int packed) { return packed & 0xffff; }
 __host__ __device__ inline int ext_y(int packed) { return packed >> 16; }
 
+// Adam (the default 3DGS optimiser, Sec. IV-A).  1 - beta is formed in
+// double on the host (forming it from the FP32 beta would be off by up to
+// 1.3e-5 relative for beta = 0.999).  Shared by the standalone step and the
+// projection backward fused with it, so both update a parameter bit for bit
+// identically.
+struct AdamCoef {
+  double b1d, b2d;
+  float b1, b2, omb1, omb2, eps;
+};
+__device__ __forceinline__ void adam_update(float& p, float g, float& m, float& v, const AdamCoef& c,
+                                            float step_size, float inv_sqrt_bc2) {
+  // every operation rounded on its own: where a multiply-add would be fused must not depend on
+  // the kernel the update is inlined into
+#pragma clang fp contract(off)
+  m = c.b1 * m + c.omb1 * g;
+  v = c.b2 * v + c.omb2 * g * g;
+  p -= step_size * m / (sqrtf(v) * inv_sqrt_bc2 + c.eps);
+}
+// 1 / (1 - b1^t) and 1 / sqrt(1 - b2^t) for step t = step + 1, in double.
+__device__ inline void adam_bias_factors(const AdamCoef& c, int32_t step, float& k1, float& k2) {
+  const double st = (double)step + 1.0;
+  k1 = (float)(1.0 / (1.0 - pow(c.b1d, st)));
+  k2 = (float)(1.0 / sqrt(1.0 - pow(c.b2d, st)));
+}
+AdamCoef make_adam_coef(double beta1, double beta2, double eps);
+gs_status validate_adam_hyper(double beta1, double beta2, double eps, const int32_t* d_step);
+void launch_step_increment(int32_t* d_step, hipStream_t st);
+
 // Which view owns global tile `gt` (views are few; linear scan).
 __device__ inline int view_of_tile(const ViewTable& vt, int gt) {
   int v = 0;

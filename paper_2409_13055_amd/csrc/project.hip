@@ -331,169 +331,268 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
   }
 }
 
+// Adam state of the fused projection backward: per parameter group (means,
+// log_scales, quats, opacity logits, sh_dc, sh_rest) the parameters (updated
+// in place), first and second moments and learning rate.
+constexpr int kParamGroups = 6;
+struct AdamPtrs {
+  float* p[kParamGroups];
+  float* m[kParamGroups];
+  float* v[kParamGroups];
+  float lr[kParamGroups];
+  AdamCoef c;
+  const int32_t* d_step;
+};
+
 // Backward of the projection: one thread per Gaussian sums the image-space
 // gradients of all its views, accumulating the view-independent d/dSigma
-// once, then chains to log-scales and the (unnormalised) quaternion.
-template <int D>
-__global__ __launch_bounds__(256) void k_project_bwd(ProjectArgs a, CamTable cams, const int32_t* __restrict__ tiles,
-                                                     const float* __restrict__ grad2d, GradPtrs gp) {
+// once, then chains to log-scales and the (unnormalised) quaternion.  The
+// raw-parameter gradient of a Gaussian some view sees is added into `gp`.
+// With ADAM the gradients of the block's Gaussians (0 where no view sees one)
+// are instead staged in LDS in the parameter arrays' own layout and used at
+// once for the Adam step of every parameter, the same update the standalone
+// step applies, the block streaming each group's contiguous range of p, m and
+// v as float4 with consecutive lanes on consecutive elements.
+constexpr int kBwdThreads = 256;
+template <int D, bool ADAM>
+__global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamTable cams,
+                                                             const int32_t* __restrict__ tiles,
+                                                             const float* __restrict__ grad2d, GradPtrs gp,
+                                                             AdamPtrs ap) {
   constexpr int K = (D + 1) * (D + 1);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  GaussCov g;
-  load_cov(a, i, g);
-  if (!g.ok) return;
-  // SH coefficients are re-read per view (cache hits) instead of held in
-  // registers across the view loop.
-  const float* shd = a.sh_dc + 3 * i;
-  const float* shr = a.sh_rest + i * (K - 1) * 3;
+  constexpr int NPAR = 11 + 3 * K;  // raw floats per Gaussian
+  __shared__ __align__(16) float s_g[ADAM ? kBwdThreads * NPAR : 1];
+  const int64_t i = (int64_t)blockIdx.x * kBwdThreads + threadIdx.x;
+  const bool valid = i < a.n;
+  if (!ADAM && !valid) return;
+  // the raw-parameter gradient of Gaussian i (all 0 when no view sees it)
+  float gmean[3] = {0.f, 0.f, 0.f}, glsc[3] = {0.f, 0.f, 0.f}, gquat[4] = {0.f, 0.f, 0.f, 0.f}, glogit = 0.f;
   float gsh[K][3];
 #pragma unroll
   for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.0f;
-  real gm[3] = {0, 0, 0};
-  real gS[6] = {0, 0, 0, 0, 0, 0};
-  real gop = 0;
-  bool any = false;
-#pragma unroll 1
-  for (int v = 0; v < a.n_views; ++v) {
-    const int64_t row = (int64_t)v * a.n + i;
-    if (tiles[row] == 0) continue;  // culled: no image-space gradient
-    real g2[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) g2[k] = grad2d[row * 9 + k];
-    const CamF& cam = cams.c[v];
-    Proj2D p;
-    if (!project_view(g, cam, a.near_plane, a.eps2d, p)) continue;
-    any = true;
-    // conic -> covariance: dL/dcov = -Q GQ Q
-    const real A = p.ca, Bq = p.cb, C = p.cc;
-    const real ga = g2[2], gb = 0.5 * g2[3], gc = g2[4];
-    const real q00 = A * ga + Bq * gb, q01 = A * gb + Bq * gc;
-    const real q10 = Bq * ga + C * gb, q11 = Bq * gb + C * gc;
-    const real G00 = -(q00 * A + q01 * Bq);
-    const real G01 = -(q00 * Bq + q01 * C);
-    const real G11 = -(q10 * Bq + q11 * C);
-    // cov = T Sigma T^T (dilation is additive): dL/dSigma = T^T G T, dL/dT = 2 G T Sigma
-    const real* T = p.T;
-    real u[3], w[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      u[k] = G00 * T[k] + G01 * T[3 + k];
-      w[k] = G01 * T[k] + G11 * T[3 + k];
+  GaussCov g;
+  g.ok = false;
+  if (valid) load_cov(a, i, g);
+  if (g.ok) {
+    // SH coefficients are re-read per view (cache hits) instead of held in
+    // registers across the view loop.
+    const float* shd = a.sh_dc + 3 * i;
+    const float* shr = a.sh_rest + i * (K - 1) * 3;
+    real gm[3] = {0, 0, 0};
+    real gS[6] = {0, 0, 0, 0, 0, 0};
+    real gop = 0;
+    bool any = false;
+  #pragma unroll 1
+    for (int v = 0; v < a.n_views; ++v) {
+      const int64_t row = (int64_t)v * a.n + i;
+      if (tiles[row] == 0) continue;  // culled: no image-space gradient
+      real g2[9];
+  #pragma unroll
+      for (int k = 0; k < 9; ++k) g2[k] = grad2d[row * 9 + k];
+      const CamF& cam = cams.c[v];
+      Proj2D p;
+      if (!project_view(g, cam, a.near_plane, a.eps2d, p)) continue;
+      any = true;
+      // conic -> covariance: dL/dcov = -Q GQ Q
+      const real A = p.ca, Bq = p.cb, C = p.cc;
+      const real ga = g2[2], gb = 0.5 * g2[3], gc = g2[4];
+      const real q00 = A * ga + Bq * gb, q01 = A * gb + Bq * gc;
+      const real q10 = Bq * ga + C * gb, q11 = Bq * gb + C * gc;
+      const real G00 = -(q00 * A + q01 * Bq);
+      const real G01 = -(q00 * Bq + q01 * C);
+      const real G11 = -(q10 * Bq + q11 * C);
+      // cov = T Sigma T^T (dilation is additive): dL/dSigma = T^T G T, dL/dT = 2 G T Sigma
+      const real* T = p.T;
+      real u[3], w[3];
+  #pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        u[k] = G00 * T[k] + G01 * T[3 + k];
+        w[k] = G01 * T[k] + G11 * T[3 + k];
+      }
+      gS[0] += T[0] * u[0] + T[3] * w[0];
+      gS[1] += T[0] * u[1] + T[3] * w[1];
+      gS[2] += T[0] * u[2] + T[3] * w[2];
+      gS[3] += T[1] * u[1] + T[4] * w[1];
+      gS[4] += T[1] * u[2] + T[4] * w[2];
+      gS[5] += T[2] * u[2] + T[5] * w[2];
+      const real* S = g.Sig;
+      const real GT0[3] = {2 * (u[0] * S[0] + u[1] * S[1] + u[2] * S[2]), 2 * (u[0] * S[1] + u[1] * S[3] + u[2] * S[4]),
+                           2 * (u[0] * S[2] + u[1] * S[4] + u[2] * S[5])};
+      const real GT1[3] = {2 * (w[0] * S[0] + w[1] * S[1] + w[2] * S[2]), 2 * (w[0] * S[1] + w[1] * S[3] + w[2] * S[4]),
+                           2 * (w[0] * S[2] + w[1] * S[4] + w[2] * S[5])};
+      const real Wc[9] = {cam.R[0], cam.R[1], cam.R[2], cam.R[3], cam.R[4], cam.R[5], cam.R[6], cam.R[7], cam.R[8]};
+      const real fx = cam.fx, fy = cam.fy;
+      // dL/dJ = dL/dT W^T (entries J00, J02, J11, J12)
+      const real gj00 = GT0[0] * Wc[0] + GT0[1] * Wc[1] + GT0[2] * Wc[2];
+      const real gj02 = GT0[0] * Wc[6] + GT0[1] * Wc[7] + GT0[2] * Wc[8];
+      const real gj11 = GT1[0] * Wc[3] + GT1[1] * Wc[4] + GT1[2] * Wc[5];
+      const real gj12 = GT1[0] * Wc[6] + GT1[1] * Wc[7] + GT1[2] * Wc[8];
+      const real tz = p.t[2], iz = 1.0 / tz, iz2 = iz * iz, iz3 = iz2 * iz;
+      real gt0 = 0, gt1 = 0, gt2 = 0;
+      gt2 += gj00 * (-fx * iz2) + gj11 * (-fy * iz2);
+      gt0 += p.clx ? 0.0 : gj02 * (-fx * iz2);
+      gt2 += gj02 * (-fx * iz2 * (p.clx ? p.cvx : 0.0) + 2.0 * fx * p.txc * iz3);
+      gt1 += p.cly ? 0.0 : gj12 * (-fy * iz2);
+      gt2 += gj12 * (-fy * iz2 * (p.cly ? p.cvy : 0.0) + 2.0 * fy * p.tyc * iz3);
+      // image-plane mean
+      gt0 += g2[0] * fx * iz;
+      gt1 += g2[1] * fy * iz;
+      gt2 -= (g2[0] * fx * p.t[0] + g2[1] * fy * p.t[1]) * iz2;
+      gm[0] += Wc[0] * gt0 + Wc[3] * gt1 + Wc[6] * gt2;
+      gm[1] += Wc[1] * gt0 + Wc[4] * gt1 + Wc[7] * gt2;
+      gm[2] += Wc[2] * gt0 + Wc[5] * gt1 + Wc[8] * gt2;
+      gop += g2[5];
+      // colour -> SH coefficients and the viewing direction; a channel clamped at 0 in the
+      // projection (same arithmetic as there) passes no gradient
+      real d[3], il;
+      view_dir(g, cam, d, il);
+      const real dx = d[0], dy = d[1], dz = d[2];
+      float Y[16], acoef[16];
+      sh_basis(D, (float)dx, (float)dy, (float)dz, Y);
+      const auto coef = [&](int k, int ch) { return (k == 0 ? shd : shr + (k - 1) * 3)[ch]; };
+      const float wr = sh_channel<K>(coef, Y, 0) < 0.0f ? 0.f : (float)g2[6];
+      const float wg = sh_channel<K>(coef, Y, 1) < 0.0f ? 0.f : (float)g2[7];
+      const float wb = sh_channel<K>(coef, Y, 2) < 0.0f ? 0.f : (float)g2[8];
+  #pragma unroll
+      for (int k = 0; k < K; ++k) {
+        gsh[k][0] += wr * Y[k];
+        gsh[k][1] += wg * Y[k];
+        gsh[k][2] += wb * Y[k];
+        const float* c3 = k == 0 ? shd : shr + (k - 1) * 3;
+        acoef[k] = wr * c3[0] + wg * c3[1] + wb * c3[2];
+      }
+      if (D > 0) {
+        float gdx, gdy, gdz;
+        sh_grad_dot(D, (float)dx, (float)dy, (float)dz, acoef, gdx, gdy, gdz);
+        const real dd = gdx * dx + gdy * dy + gdz * dz;
+        gm[0] += (gdx - dx * dd) * il;
+        gm[1] += (gdy - dy * dd) * il;
+        gm[2] += (gdz - dz * dd) * il;
+      }
     }
-    gS[0] += T[0] * u[0] + T[3] * w[0];
-    gS[1] += T[0] * u[1] + T[3] * w[1];
-    gS[2] += T[0] * u[2] + T[3] * w[2];
-    gS[3] += T[1] * u[1] + T[4] * w[1];
-    gS[4] += T[1] * u[2] + T[4] * w[2];
-    gS[5] += T[2] * u[2] + T[5] * w[2];
-    const real* S = g.Sig;
-    const real GT0[3] = {2 * (u[0] * S[0] + u[1] * S[1] + u[2] * S[2]), 2 * (u[0] * S[1] + u[1] * S[3] + u[2] * S[4]),
-                         2 * (u[0] * S[2] + u[1] * S[4] + u[2] * S[5])};
-    const real GT1[3] = {2 * (w[0] * S[0] + w[1] * S[1] + w[2] * S[2]), 2 * (w[0] * S[1] + w[1] * S[3] + w[2] * S[4]),
-                         2 * (w[0] * S[2] + w[1] * S[4] + w[2] * S[5])};
-    const real Wc[9] = {cam.R[0], cam.R[1], cam.R[2], cam.R[3], cam.R[4], cam.R[5], cam.R[6], cam.R[7], cam.R[8]};
-    const real fx = cam.fx, fy = cam.fy;
-    // dL/dJ = dL/dT W^T (entries J00, J02, J11, J12)
-    const real gj00 = GT0[0] * Wc[0] + GT0[1] * Wc[1] + GT0[2] * Wc[2];
-    const real gj02 = GT0[0] * Wc[6] + GT0[1] * Wc[7] + GT0[2] * Wc[8];
-    const real gj11 = GT1[0] * Wc[3] + GT1[1] * Wc[4] + GT1[2] * Wc[5];
-    const real gj12 = GT1[0] * Wc[6] + GT1[1] * Wc[7] + GT1[2] * Wc[8];
-    const real tz = p.t[2], iz = 1.0 / tz, iz2 = iz * iz, iz3 = iz2 * iz;
-    real gt0 = 0, gt1 = 0, gt2 = 0;
-    gt2 += gj00 * (-fx * iz2) + gj11 * (-fy * iz2);
-    gt0 += p.clx ? 0.0 : gj02 * (-fx * iz2);
-    gt2 += gj02 * (-fx * iz2 * (p.clx ? p.cvx : 0.0) + 2.0 * fx * p.txc * iz3);
-    gt1 += p.cly ? 0.0 : gj12 * (-fy * iz2);
-    gt2 += gj12 * (-fy * iz2 * (p.cly ? p.cvy : 0.0) + 2.0 * fy * p.tyc * iz3);
-    // image-plane mean
-    gt0 += g2[0] * fx * iz;
-    gt1 += g2[1] * fy * iz;
-    gt2 -= (g2[0] * fx * p.t[0] + g2[1] * fy * p.t[1]) * iz2;
-    gm[0] += Wc[0] * gt0 + Wc[3] * gt1 + Wc[6] * gt2;
-    gm[1] += Wc[1] * gt0 + Wc[4] * gt1 + Wc[7] * gt2;
-    gm[2] += Wc[2] * gt0 + Wc[5] * gt1 + Wc[8] * gt2;
-    gop += g2[5];
-    // colour -> SH coefficients and the viewing direction; a channel clamped at 0 in the
-    // projection (same arithmetic as there) passes no gradient
-    real d[3], il;
-    view_dir(g, cam, d, il);
-    const real dx = d[0], dy = d[1], dz = d[2];
-    float Y[16], acoef[16];
-    sh_basis(D, (float)dx, (float)dy, (float)dz, Y);
-    const auto coef = [&](int k, int ch) { return (k == 0 ? shd : shr + (k - 1) * 3)[ch]; };
-    const float wr = sh_channel<K>(coef, Y, 0) < 0.0f ? 0.f : (float)g2[6];
-    const float wg = sh_channel<K>(coef, Y, 1) < 0.0f ? 0.f : (float)g2[7];
-    const float wb = sh_channel<K>(coef, Y, 2) < 0.0f ? 0.f : (float)g2[8];
+    if (any) {
+      Gauss3D gf;  // rotation, scales and M = R diag(s), recomputed after the view loop
+      load_gauss(a, i, gf);
+      // Sigma = M M^T, M = R diag(s): dL/dM = 2 gS M
+      const real GSm[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
+      real GM[9];
+    #pragma unroll
+      for (int r = 0; r < 3; ++r)
+    #pragma unroll
+        for (int c = 0; c < 3; ++c)
+          GM[3 * r + c] = 2 * (GSm[3 * r] * gf.M[c] + GSm[3 * r + 1] * gf.M[3 + c] + GSm[3 * r + 2] * gf.M[6 + c]);
+      real gls[3], GR[9];
+    #pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const real gsv = GM[c] * gf.R[c] + GM[3 + c] * gf.R[3 + c] + GM[6 + c] * gf.R[6 + c];
+        gls[c] = gsv * gf.s[c];
+        GR[c] = GM[c] * gf.s[c];
+        GR[3 + c] = GM[3 + c] * gf.s[c];
+        GR[6 + c] = GM[6 + c] * gf.s[c];
+      }
+      const real w = gf.q[0], x = gf.q[1], y = gf.q[2], z = gf.q[3];
+      // d R / d(w,x,y,z) contracted with GR
+      const real gw = 2 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+      const real gx = 2 * (y * GR[1] + z * GR[2] + y * GR[3] - 2 * x * GR[4] - w * GR[5] + z * GR[6] + w * GR[7] -
+                           2 * x * GR[8]);
+      const real gy = 2 * (-2 * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7] -
+                           2 * y * GR[8]);
+      const real gz = 2 * (-2 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2 * z * GR[4] + y * GR[5] +
+                           x * GR[6] + y * GR[7]);
+      const real dotq = w * gw + x * gx + y * gy + z * gz;
+      const real iq = 1.0 / gf.qnorm;
+      const real op = 1.0 / (1.0 + exp(-(real)a.logits[i]));
+    #pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        gmean[c] = (float)gm[c];
+        glsc[c] = (float)gls[c];
+      }
+      gquat[0] = (float)((gw - w * dotq) * iq);
+      gquat[1] = (float)((gx - x * dotq) * iq);
+      gquat[2] = (float)((gy - y * dotq) * iq);
+      gquat[3] = (float)((gz - z * dotq) * iq);
+      glogit = (float)(gop * op * (1.0 - op));
+      if (!ADAM) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      gsh[k][0] += wr * Y[k];
-      gsh[k][1] += wg * Y[k];
-      gsh[k][2] += wb * Y[k];
-      const float* c3 = k == 0 ? shd : shr + (k - 1) * 3;
-      acoef[k] = wr * c3[0] + wg * c3[1] + wb * c3[2];
-    }
-    if (D > 0) {
-      float gdx, gdy, gdz;
-      sh_grad_dot(D, (float)dx, (float)dy, (float)dz, acoef, gdx, gdy, gdz);
-      const real dd = gdx * dx + gdy * dy + gdz * dz;
-      gm[0] += (gdx - dx * dd) * il;
-      gm[1] += (gdy - dy * dd) * il;
-      gm[2] += (gdz - dz * dd) * il;
-    }
-  }
-  if (!any) return;
-  Gauss3D gf;  // rotation, scales and M = R diag(s), recomputed after the view loop
-  load_gauss(a, i, gf);
-  // Sigma = M M^T, M = R diag(s): dL/dM = 2 gS M
-  const real GSm[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
-  real GM[9];
+        for (int c = 0; c < 3; ++c) {
+          gp.means[3 * i + c] += gmean[c];
+          gp.log_scales[3 * i + c] += glsc[c];
+        }
+        float4* gq = reinterpret_cast<float4*>(gp.quats + 4 * i);
+        float4 qv = *gq;
+        qv.x += gquat[0];
+        qv.y += gquat[1];
+        qv.z += gquat[2];
+        qv.w += gquat[3];
+        *gq = qv;
+        gp.logits[i] += glogit;
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) gp.sh_dc[3 * i + c] += gsh[0][c];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      GM[3 * r + c] = 2 * (GSm[3 * r] * gf.M[c] + GSm[3 * r + 1] * gf.M[3 + c] + GSm[3 * r + 2] * gf.M[6 + c]);
-  real gls[3], GR[9];
+        for (int k = 1; k < K; ++k)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) gp.sh_rest[(i * (K - 1) + (k - 1)) * 3 + c] += gsh[k][c];
+      }
+    }  // any
+  }  // g.ok
+  if (!ADAM) return;
+  // group g's block of gradients sits at s_g[T * off_g + t * width_g + c], as in the group's array
+  constexpr int T = kBwdThreads;
+  const int t = threadIdx.x;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const real gsv = GM[c] * gf.R[c] + GM[3 + c] * gf.R[3 + c] + GM[6 + c] * gf.R[6 + c];
-    gls[c] = gsv * gf.s[c];
-    GR[c] = GM[c] * gf.s[c];
-    GR[3 + c] = GM[3 + c] * gf.s[c];
-    GR[6 + c] = GM[6 + c] * gf.s[c];
+    s_g[0 * T + t * 3 + c] = gmean[c];
+    s_g[3 * T + t * 3 + c] = glsc[c];
+    s_g[11 * T + t * 3 + c] = gsh[0][c];
   }
-  const real w = gf.q[0], x = gf.q[1], y = gf.q[2], z = gf.q[3];
-  // d R / d(w,x,y,z) contracted with GR
-  const real gw = 2 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
-  const real gx = 2 * (y * GR[1] + z * GR[2] + y * GR[3] - 2 * x * GR[4] - w * GR[5] + z * GR[6] + w * GR[7] -
-                       2 * x * GR[8]);
-  const real gy = 2 * (-2 * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7] -
-                       2 * y * GR[8]);
-  const real gz = 2 * (-2 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2 * z * GR[4] + y * GR[5] +
-                       x * GR[6] + y * GR[7]);
-  const real dotq = w * gw + x * gx + y * gy + z * gz;
-  const real iq = 1.0 / gf.qnorm;
-  const real op = 1.0 / (1.0 + exp(-(real)a.logits[i]));
-  gp.means[3 * i] += (float)gm[0];
-  gp.means[3 * i + 1] += (float)gm[1];
-  gp.means[3 * i + 2] += (float)gm[2];
-  gp.log_scales[3 * i] += (float)gls[0];
-  gp.log_scales[3 * i + 1] += (float)gls[1];
-  gp.log_scales[3 * i + 2] += (float)gls[2];
-  float4* gq = reinterpret_cast<float4*>(gp.quats + 4 * i);
-  float4 qv = *gq;
-  qv.x += (float)((gw - w * dotq) * iq);
-  qv.y += (float)((gx - x * dotq) * iq);
-  qv.z += (float)((gy - y * dotq) * iq);
-  qv.w += (float)((gz - z * dotq) * iq);
-  *gq = qv;
-  gp.logits[i] += (float)(gop * op * (1.0 - op));
 #pragma unroll
-  for (int c = 0; c < 3; ++c) gp.sh_dc[3 * i + c] += gsh[0][c];
+  for (int c = 0; c < 4; ++c) s_g[6 * T + t * 4 + c] = gquat[c];
+  s_g[10 * T + t] = glogit;
 #pragma unroll
   for (int k = 1; k < K; ++k)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gp.sh_rest[(i * (K - 1) + (k - 1)) * 3 + c] += gsh[k][c];
+    for (int c = 0; c < 3; ++c) s_g[14 * T + t * 3 * (K - 1) + (k - 1) * 3 + c] = gsh[k][c];
+  __shared__ float s_k[2];
+  if (t == 0) adam_bias_factors(ap.c, *ap.d_step, s_k[0], s_k[1]);
+  __syncthreads();
+  const float k1 = s_k[0], k2 = s_k[1];
+  const int64_t i0 = (int64_t)blockIdx.x * T;
+  const int nb = (int)min<int64_t>(T, a.n - i0);
+  const int width[kParamGroups] = {3, 3, 4, 1, 3, 3 * (K - 1)};
+  const int off[kParamGroups] = {0, 3, 6, 10, 11, 14};
+#pragma unroll
+  for (int grp = 0; grp < kParamGroups; ++grp) {
+    const int w = width[grp];
+    if (w == 0) continue;
+    const float* G = s_g + off[grp] * T;
+    float* __restrict__ P = ap.p[grp] + i0 * w;
+    float* __restrict__ M = ap.m[grp] + i0 * w;
+    float* __restrict__ V = ap.v[grp] + i0 * w;
+    const float step_size = ap.lr[grp] * k1;
+    // float4 over the block's range (it starts 16-byte aligned: i0 is a multiple of 256), the last
+    // block's remainder one by one
+    const int cnt = nb * w, n4 = (((reinterpret_cast<uintptr_t>(P) | reinterpret_cast<uintptr_t>(M) |
+                                    reinterpret_cast<uintptr_t>(V)) & 15) == 0) ? cnt / 4 : 0;
+    for (int q = t; q < n4; q += T) {
+      float4 pv = reinterpret_cast<float4*>(P)[q], mv = reinterpret_cast<float4*>(M)[q];
+      float4 vv = reinterpret_cast<float4*>(V)[q];
+      const float4 gv = reinterpret_cast<const float4*>(G)[q];
+      adam_update(pv.x, gv.x, mv.x, vv.x, ap.c, step_size, k2);
+      adam_update(pv.y, gv.y, mv.y, vv.y, ap.c, step_size, k2);
+      adam_update(pv.z, gv.z, mv.z, vv.z, ap.c, step_size, k2);
+      adam_update(pv.w, gv.w, mv.w, vv.w, ap.c, step_size, k2);
+      reinterpret_cast<float4*>(P)[q] = pv;
+      reinterpret_cast<float4*>(M)[q] = mv;
+      reinterpret_cast<float4*>(V)[q] = vv;
+    }
+    for (int e = 4 * n4 + t; e < cnt; e += T) {
+      float pv = P[e], mv = M[e], vv = V[e];
+      adam_update(pv, G[e], mv, vv, ap.c, step_size, k2);
+      P[e] = pv;
+      M[e] = mv;
+      V[e] = vv;
+    }
+  }
 }
 
 static ProjectArgs make_args(const gs_params* p, int32_t n_views, const gs_options* o) {
@@ -527,23 +626,72 @@ gs_status validate_params(const gs_params* p) {
   return GS_OK;
 }
 
+template <bool ADAM>
+static void launch_project_bwd_kernel(const gs_params* params, const ProjectArgs& a, const CamTable& ct,
+                                      const int32_t* tiles, const float* grad2d, const GradPtrs& gp,
+                                      const AdamPtrs& ap, hipStream_t stream) {
+  const int bs = kBwdThreads;
+  const dim3 grid((unsigned)((params->n + bs - 1) / bs));
+  switch (params->sh_degree) {
+    case 0: hipLaunchKernelGGL((k_project_bwd<0, ADAM>), grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp, ap); break;
+    case 1: hipLaunchKernelGGL((k_project_bwd<1, ADAM>), grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp, ap); break;
+    case 2: hipLaunchKernelGGL((k_project_bwd<2, ADAM>), grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp, ap); break;
+    default:
+      hipLaunchKernelGGL((k_project_bwd<3, ADAM>), grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp, ap);
+      break;
+  }
+}
+
 gs_status launch_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
                              const int32_t* tiles, const float* grad2d, const gs_grads* grads, hipStream_t stream) {
   const ProjectArgs a = make_args(params, n_views, opts);
   const CamTable ct = make_cam_table(cams, n_views, opts);
   GradPtrs gp{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->sh_dc, grads->sh_rest};
-  const int bs = 256;
-  const dim3 grid((unsigned)((params->n + bs - 1) / bs));
-  switch (params->sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp); break;
-    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp); break;
-  }
+  launch_project_bwd_kernel<false>(params, a, ct, tiles, grad2d, gp, AdamPtrs{}, stream);
   return check_launch("projection backward");
 }
 
 }  // namespace gs
+
+extern "C" gs_status gs_project_bwd_adam(const gs_params* params, const gs_projected* proj, const gs_camera* cams,
+                                         int32_t n_views, const gs_options* opts, const float* grad2d,
+                                         const gs_adam_group* groups, double beta1, double beta2, double eps,
+                                         int32_t* d_step, void* stream) {
+  using namespace gs;
+  gs_status s;
+  if ((s = validate_params(params)) != GS_OK) return s;
+  if ((s = validate_cams(cams, n_views)) != GS_OK) return s;
+  if ((s = validate_opts(opts)) != GS_OK) return s;
+  if (!proj || !proj->tiles_touched) return fail(GS_ERR_INVALID_VALUE, "proj->tiles_touched is NULL");
+  if (!grad2d) return fail(GS_ERR_INVALID_VALUE, "grad2d is NULL");
+  if ((s = validate_adam_hyper(beta1, beta2, eps, d_step)) != GS_OK) return s;
+  if (!groups) return fail(GS_ERR_INVALID_VALUE, "groups is NULL");
+  const int K = (params->sh_degree + 1) * (params->sh_degree + 1);
+  const float* owned[kParamGroups] = {params->means, params->log_scales, params->quats, params->opacity_logits,
+                                      params->sh_dc, params->sh_rest};
+  const int64_t width[kParamGroups] = {3, 3, 4, 1, 3, 3 * (K - 1)};
+  AdamPtrs ap{};
+  for (int k = 0; k < kParamGroups; ++k) {
+    const gs_adam_group& gr = groups[k];
+    const std::string which = "group " + std::to_string(k);
+    if (gr.numel != params->n * width[k]) return fail(GS_ERR_INVALID_VALUE, which + ": numel != n * width");
+    if (gr.numel > 0 && (gr.param != owned[k] || !gr.exp_avg || !gr.exp_avg_sq))
+      return fail(GS_ERR_INVALID_VALUE, which + ": param must be the params array, moments non-NULL");
+    if (!std::isfinite(gr.lr)) return fail(GS_ERR_INVALID_VALUE, which + ": lr not finite");
+    ap.p[k] = gr.param;
+    ap.m[k] = gr.exp_avg;
+    ap.v[k] = gr.exp_avg_sq;
+    ap.lr[k] = gr.lr;
+  }
+  ap.c = make_adam_coef(beta1, beta2, eps);
+  ap.d_step = d_step;
+  const ProjectArgs a = make_args(params, n_views, opts);
+  const CamTable ct = make_cam_table(cams, n_views, opts);
+  hipStream_t st = as_stream(stream);
+  launch_project_bwd_kernel<true>(params, a, ct, proj->tiles_touched, grad2d, GradPtrs{}, ap, st);
+  launch_step_increment(d_step, st);
+  return check_launch("projection backward + adam");
+}
 
 extern "C" gs_status gs_project(const gs_params* params, const gs_camera* cams, int32_t n_views,
                                 const gs_options* opts, const gs_projected* out, void* stream) {

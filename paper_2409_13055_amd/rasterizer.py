@@ -219,6 +219,11 @@ class Rasterizer:
         L.gs_project_bwd(params.c_params(), fr.c_proj(), self.cams, self.n_views, self.opts, grad2d.data_ptr(),
                          grads.c_grads(), _stream())
 
+    def project_bwd_adam(self, params: GaussianParams, fr: Frame, grad2d: torch.Tensor, adam: "FusedAdam"):
+        """The projection backward of grad2d fused with adam's step (params and moments updated in place)."""
+        L.gs_project_bwd_adam(params.c_params(), fr.c_proj(), self.cams, self.n_views, self.opts, grad2d.data_ptr(),
+                              adam.all_groups, adam.betas[0], adam.betas[1], adam.eps, _p(adam.d_step), _stream())
+
     def render_stats(self, fr: Frame, out: Optional[torch.Tensor] = None) -> Optional[Dict[str, int]]:
         """Work counts of the blending of this frame (see gs_render_stats).  Without `out` it syncs
         and returns them; with `out` (3 int64 on the device) it only enqueues the count into it."""
@@ -297,6 +302,15 @@ class FusedAdam:
             g.exp_avg, g.exp_avg_sq = _p(getattr(self.exp_avg, k)), _p(getattr(self.exp_avg_sq, k))
             g.numel, g.lr = getattr(params, k).numel(), float(lrs[k])
         self.n_groups = len(names)
+        # all six groups in parameter order, for the projection backward fused with the step
+        self.all_groups = (L.gs_adam_group * len(PARAM_NAMES))()
+        for i, k in enumerate(PARAM_NAMES):
+            g = self.all_groups[i]
+            t = getattr(params, k)
+            if t.numel() > 0:
+                g.param = _p(t)
+                g.exp_avg, g.exp_avg_sq = _p(getattr(self.exp_avg, k)), _p(getattr(self.exp_avg_sq, k))
+            g.numel, g.lr = t.numel(), float(lrs[k])
 
     def step(self, zero_grad: bool = True):
         L.gs_adam_step(self.groups, self.n_groups, self.betas[0], self.betas[1], self.eps, _p(self.d_step),
@@ -306,12 +320,16 @@ class FusedAdam:
 class MappingStep:
     """One mapping iteration over a batch of keyframes (Sec. III-B): project all
     views in one pass over the parameters, one bin/sort over every view's
-    tiles, forward with the fused L1 loss, backward, and optionally Adam (which
-    also clears the gradients for the next iteration)."""
+    tiles, forward with the fused L1 loss, backward, and optionally Adam.  With
+    fuse_adam (the default when Adam is on) the projection backward applies the
+    Adam step itself, so the raw-parameter gradients never reach memory;
+    otherwise the gradients are accumulated into `grads` and Adam (which also
+    clears them) runs as its own call."""
 
     def __init__(self, params: GaussianParams, cameras, targets, lrs=None, tile_size=16, checkpoint=False,
-                 with_adam=True, **opt):
+                 with_adam=True, fuse_adam=True, **opt):
         self.params = params
+        self.fuse_adam = with_adam and fuse_adam
         self.rast = Rasterizer(cameras, params.n, params.sh_degree, tile_size=tile_size, checkpoint=checkpoint,
                                device=params.means.device, **opt)
         self.grads = params.zeros_like()
@@ -347,6 +365,18 @@ class MappingStep:
         r.render_fwd(fr, self.target, self.loss)
         if mark:
             mark("render_fwd")
+        if self.fuse_adam:
+            g2 = r.grad2d
+            g2.zero_()
+            if mark:
+                mark("clear_grad2d")
+            r.raster_bwd(fr, g2, target=self.target)
+            if mark:
+                mark("raster_bwd")
+            r.project_bwd_adam(self.params, fr, g2, self.adam)
+            if mark:
+                mark("project_bwd_adam")
+            return
         if mark is None:
             r.render_bwd(self.params, fr, self.grads, target=self.target)
         else:

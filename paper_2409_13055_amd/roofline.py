@@ -15,6 +15,7 @@ Per-unit figures (P_n = 11 + 3K raw floats per Gaussian, K = (D+1)^2):
   project_bwd N*(4*P_n + 8*P_n) + V*N*(36 + 16)
   render_bwd  raster_bwd + project_bwd
   adam        N*P_n*32  (read p, g, m, v; write p, m, v, g := 0)
+  project_bwd_adam  N*P_n*24 (read p, m, v; write p, m, v) + V*N*52
 with N Gaussians, V views, Nv visible (view, Gaussian) pairs, M tile
 incidences, Px pixels and T tiles.
 """
@@ -64,6 +65,7 @@ def algorithmic_bytes(c):
         "project_bwd": project_bwd,
         "render_bwd": raster_bwd + project_bwd,
         "adam": N * Pn * 32,
+        "project_bwd_adam": N * 24 * Pn + V * N * 52,
     }
 
 
@@ -77,7 +79,7 @@ def alu_flops(kernel, ev):
     return ev["evaluated"] * FLOPS_EVAL + ev["blended"] * blend
 
 
-SINGLE_KERNEL_CALLS = ("project", "render_fwd", "raster_bwd", "project_bwd", "adam")
+SINGLE_KERNEL_CALLS = ("project", "render_fwd", "raster_bwd", "project_bwd", "adam", "project_bwd_adam")
 
 
 def report(step, sc, stages_ms, hbm_peak_gbs, valu_peak_tflops, traffic=None, work=None):

@@ -83,6 +83,25 @@ def test_invalid_arguments_are_rejected_before_any_launch(L):
         L.gs_adam_step(groups, 1, 0.9, 0.999, 1e-15, C.c_void_p(16), 0, None)
     with pytest.raises(L.GsError, match="beta"):
         L.gs_adam_step(groups, 1, 1.5, 0.999, 1e-15, C.c_void_p(16), 0, None)
+    # the fused projection backward + Adam checks its groups against the parameter arrays
+    fp = L.gs_params()
+    fp.n, fp.sh_degree = 10, 0
+    fp.means, fp.log_scales, fp.quats = C.c_void_p(0x1000), C.c_void_p(0x2000), C.c_void_p(0x3000)
+    fp.opacity_logits, fp.sh_dc = C.c_void_p(0x4000), C.c_void_p(0x5000)
+    fproj = L.gs_projected()
+    fproj.tiles_touched = C.c_void_p(0x6000)
+    six = (L.gs_adam_group * 6)()
+    for k, (addr, width) in enumerate([(0x1000, 3), (0x2000, 3), (0x3000, 4), (0x4000, 1), (0x5000, 3), (0, 0)]):
+        six[k].param, six[k].numel, six[k].lr = C.c_void_p(addr or None), 10 * width, 1e-3
+        if width:
+            six[k].exp_avg, six[k].exp_avg_sq = C.c_void_p(0x8000), C.c_void_p(0x9000)
+    six[2].numel = 39
+    with pytest.raises(L.GsError, match="numel"):
+        L.gs_project_bwd_adam(fp, fproj, cc, 1, o, C.c_void_p(0x7000), six, 0.9, 0.999, 1e-15, C.c_void_p(16), None)
+    six[2].numel = 40
+    six[1].param = C.c_void_p(0x2100)
+    with pytest.raises(L.GsError, match="params array"):
+        L.gs_project_bwd_adam(fp, fproj, cc, 1, o, C.c_void_p(0x7000), six, 0.9, 0.999, 1e-15, C.c_void_p(16), None)
     lib = L.load()
     assert lib.gs_status_string(3) == b"GS_ERR_CAPACITY"
-    assert b"beta" in lib.gs_last_error()
+    assert b"params array" in lib.gs_last_error()

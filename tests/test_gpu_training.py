@@ -4,7 +4,8 @@
   the oracle's analytic gradient and central finite differences;
 - the 100k-Gaussian SH-3 workload: the fused L1 gradients of every parameter
   of a 200-Gaussian sample against central finite differences of the oracle;
-- HIP-graph replays of the batched iteration against eager execution.
+- HIP-graph replays of the batched iteration against eager execution;
+- the projection backward fused with Adam against the two separate calls.
 """
 import numpy as np
 import pytest
@@ -149,3 +150,39 @@ def test_graph_replays_with_adam_advance_the_step():
         d = (ta - tb).abs()
         assert (d > 1e-4).float().mean().item() < 0.01
         assert d.median().item() < 1e-6
+
+
+def test_fused_projection_backward_adam_equals_separate_calls():
+    """gs_project_bwd_adam is gs_project_bwd into zeroed gradients then gs_adam_step, bit for bit, fed
+    the same image-space gradients (two steps, so the bias corrections of t = 1 and t = 2 both enter)."""
+    sc = S.make_config(3, n=20_000, res_div=4)
+    p_sep = R.GaussianParams.from_scene(sc, "cuda")
+    p_fus = R.GaussianParams.from_scene(sc, "cuda")
+    lrs = dict(S.DEFAULT_LRS)
+    rast = R.Rasterizer(sc.cameras, p_sep.n, p_sep.sh_degree, tile_size=16, device="cuda")
+    target = R.pack_images(sc.targets, "cuda")
+    grads = p_sep.zeros_like()
+    adam_sep = R.FusedAdam(p_sep, grads, lrs)
+    adam_fus = R.FusedAdam(p_fus, p_fus.zeros_like(), lrs)
+    fr = rast.new_frame()
+    for it in range(2):
+        # one frame of the separate path's parameters; both paths take its image-space gradients
+        rast.project(p_sep, fr)
+        rast.bin_sort(fr)
+        rast.fit_capacity(fr)
+        rast.render_fwd(fr)
+        g2 = torch.zeros(rast.n_views * p_sep.n, 9, device="cuda")
+        rast.raster_bwd(fr, g2, target=target)
+        rast.project_bwd(p_sep, fr, g2, grads)
+        adam_sep.step(zero_grad=True)
+        rast.project_bwd_adam(p_fus, fr, g2, adam_fus)
+        torch.cuda.synchronize()
+        assert g2.abs().sum().item() > 0
+        for name, a, b in zip(R.PARAM_NAMES, p_sep.tensors(), p_fus.tensors()):
+            assert torch.equal(a, b), (it, name)
+        for name, a, b in zip(R.PARAM_NAMES, adam_sep.exp_avg.tensors(), adam_fus.exp_avg.tensors()):
+            assert torch.equal(a, b), (it, "m", name)
+        for name, a, b in zip(R.PARAM_NAMES, adam_sep.exp_avg_sq.tensors(), adam_fus.exp_avg_sq.tensors()):
+            assert torch.equal(a, b), (it, "v", name)
+        assert all(t.abs().sum().item() == 0 for t in grads.tensors())
+    assert int(adam_sep.d_step.item()) == int(adam_fus.d_step.item()) == 2
