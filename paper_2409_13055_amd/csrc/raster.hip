@@ -284,8 +284,9 @@ __device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBox
 // A pixel that has stopped gets row coordinate +inf: its exponent is then
 // -inf or NaN and fails the cutoff test, so no separate flag is tested.
 // STATE: the pixel state (T_final, n_contrib) is written (not under the checkpoint flag).
+// (six wavefronts per SIMD: measured faster than five, despite a few bytes of spill outside the loop)
 template <int TILE, bool STATE>
-__global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_fwd(
+__global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) __attribute__((amdgpu_waves_per_eu(6))) void k_render_fwd(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     RasterConsts rc, float* __restrict__ img, float* __restrict__ tfin, int32_t* __restrict__ ncon,
     const float* __restrict__ target, float* __restrict__ tile_loss) {
@@ -460,8 +461,11 @@ __device__ LaneRole wave_roles(int lane) {
 // behind entry k is S_k = C_pixel - sum_{m<=k} c_m alpha_m T_m (C_pixel the
 // rendered value, background included), so neither the final transmittance
 // nor the contributor count is needed and nothing is replayed or divided.
+// Only its projection on dL/dC enters the gradient, so a pixel carries the
+// scalar D_k = dL/dC . S_k, updated by the entry's dL/dC . c_k.
 template <int TILE>
-__global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
+// (five wavefronts per SIMD: 96 registers, no spill; measured 10% faster than four)
+__global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     RasterConsts rc, const float* __restrict__ img, int loss_kind, const float* __restrict__ target,
     const float* __restrict__ dl_dimage, float* __restrict__ grad2d) {
@@ -476,29 +480,31 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
   const float fx = (float)pm.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const LaneRole role = wave_roles(lane);
-  // per pixel: transmittance in front of the current entry, colour still behind it, dL/dC; a pixel
-  // that has stopped gets row coordinate +inf (see k_render_fwd)
-  float T[PPL], S[PPL][3], dl[PPL][3], fy[PPL];
+  // per pixel: transmittance in front of the current entry, dL/dC . (colour still behind it), dL/dC;
+  // a pixel that has stopped gets row coordinate +inf (see k_render_fwd)
+  float T[PPL], Dp[PPL], dl[PPL][3], fy[PPL];
   const float wv = 1.0f / (3.0f * (float)pm.W * (float)pm.H);
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
     fy[p] = pm.inside(p) ? (float)pm.row(p) : INFINITY;
     T[p] = 1.0f;
+    float col[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float d = 0.0f, col = 0.0f;
+      float d = 0.0f;
+      col[c] = 0.0f;
       if (pm.inside(p)) {
-        col = img[pm.chan(p, c)];
+        col[c] = img[pm.chan(p, c)];
         if (loss_kind == GS_LOSS_L1) {
-          const float r = col - target[pm.chan(p, c)];
+          const float r = col[c] - target[pm.chan(p, c)];
           d = r > 0.0f ? wv : (r < 0.0f ? -wv : 0.0f);
         } else {
           d = dl_dimage[pm.chan(p, c)];
         }
       }
       dl[p][c] = d;
-      S[p][c] = col;
     }
+    Dp[p] = fmaf(dl[p][2], col[2], fmaf(dl[p][1], col[1], dl[p][0] * col[0]));
   }
   Acc9 acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   SplatLoader ld;
@@ -538,15 +544,12 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_bwd(
         fy[p] = stop ? INFINITY : fy[p];
         any = any || blend;
         const float wgt = blend ? alpha * T[p] : 0.0f;
-        S[p][0] = fmaf(-Bv.w, wgt, S[p][0]);
-        S[p][1] = fmaf(-Cv.x, wgt, S[p][1]);
-        S[p][2] = fmaf(-Cv.y, wgt, S[p][2]);
         acc.r = fmaf(dl[p][0], wgt, acc.r);
         acc.g = fmaf(dl[p][1], wgt, acc.g);
         acc.b = fmaf(dl[p][2], wgt, acc.b);
         const float dc = fmaf(dl[p][2], Cv.y, fmaf(dl[p][1], Cv.x, dl[p][0] * Bv.w));
-        const float ds = fmaf(dl[p][2], S[p][2], fmaf(dl[p][1], S[p][1], dl[p][0] * S[p][0]));
-        const float dLda = fmaf(T[p], dc, -ds * __builtin_amdgcn_rcpf(om));
+        Dp[p] = fmaf(-dc, wgt, Dp[p]);  // now dL/dC . S_k, the colour behind this entry
+        const float dLda = fmaf(T[p], dc, -Dp[p] * __builtin_amdgcn_rcpf(om));
         T[p] = blend ? test : T[p];
         const bool unclamped = blend && oG <= amax;  // d alpha / d(o, power) = 0 where clamped
         const float dLdp = unclamped ? dLda * alpha : 0.0f;
