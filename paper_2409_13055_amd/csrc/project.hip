@@ -382,12 +382,12 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
     real gS[6] = {0, 0, 0, 0, 0, 0};
     real gop = 0;
     bool any = false;
-  #pragma unroll 1
+#pragma unroll 1
     for (int v = 0; v < a.n_views; ++v) {
       const int64_t row = (int64_t)v * a.n + i;
       if (tiles[row] == 0) continue;  // culled: no image-space gradient
       real g2[9];
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < 9; ++k) g2[k] = grad2d[row * 9 + k];
       const CamF& cam = cams.c[v];
       Proj2D p;
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
       // cov = T Sigma T^T (dilation is additive): dL/dSigma = T^T G T, dL/dT = 2 G T Sigma
       const real* T = p.T;
       real u[3], w[3];
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < 3; ++k) {
         u[k] = G00 * T[k] + G01 * T[3 + k];
         w[k] = G01 * T[k] + G11 * T[3 + k];
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
       const float wr = sh_channel<K>(coef, Y, 0) < 0.0f ? 0.f : (float)g2[6];
       const float wg = sh_channel<K>(coef, Y, 1) < 0.0f ? 0.f : (float)g2[7];
       const float wb = sh_channel<K>(coef, Y, 2) < 0.0f ? 0.f : (float)g2[8];
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < K; ++k) {
         gsh[k][0] += wr * Y[k];
         gsh[k][1] += wg * Y[k];
@@ -476,13 +476,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
       // Sigma = M M^T, M = R diag(s): dL/dM = 2 gS M
       const real GSm[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
       real GM[9];
-    #pragma unroll
+#pragma unroll
       for (int r = 0; r < 3; ++r)
-    #pragma unroll
+#pragma unroll
         for (int c = 0; c < 3; ++c)
           GM[3 * r + c] = 2 * (GSm[3 * r] * gf.M[c] + GSm[3 * r + 1] * gf.M[3 + c] + GSm[3 * r + 2] * gf.M[6 + c]);
       real gls[3], GR[9];
-    #pragma unroll
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
         const real gsv = GM[c] * gf.R[c] + GM[3 + c] * gf.R[3 + c] + GM[6 + c] * gf.R[6 + c];
         gls[c] = gsv * gf.s[c];
@@ -502,7 +502,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
       const real dotq = w * gw + x * gx + y * gy + z * gz;
       const real iq = 1.0 / gf.qnorm;
       const real op = 1.0 / (1.0 + exp(-(real)a.logits[i]));
-    #pragma unroll
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
         gmean[c] = (float)gm[c];
         glsc[c] = (float)gls[c];
