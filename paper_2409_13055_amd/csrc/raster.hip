@@ -130,34 +130,40 @@ struct PixMap {
   __device__ int chan(int p, int c) const { return 3 * pix_off + c * W * H + row(p) * W + x; }
 };
 
-// Wave-level cull bounds of a splat.  A pixel can reach
-// opacity * exp(-q/2) >= alpha_min * (1 - 1e-3) only where
-// q = d^T Q d <= thr = 2 ln(opacity / (alpha_min (1 - 1e-3))), for the conic
-// Q = [[a,b],[b,c]] the pixels are evaluated with.  That ellipse lies inside
-// the disc |d|^2 <= thr / lambda_min(Q) (r2) and inside the box
-// |dx| <= sqrt(thr S_xx), |dy| <= sqrt(thr S_yy) with S = Q^-1 (ex, ey; the
-// box is the tighter bound for elongated splats, the disc near the corners of
-// round ones).  det(Q) is formed in double (products of FP32 values are exact
-// there), so the bounds hold for the FP32 conic however elongated the splat;
-// lambda_min and the box carry a further 1e-3 margin.  If a wavefront's pixel
-// block lies outside either bound, every one of its pixels would skip the
-// splat (alpha < alpha_min), so the wave skips it with one uniform test.
-// Negative bounds: the splat can never reach alpha_min.
-struct CullBounds {
-  float r2, ex, ey;
+// Wave-level cull of a splat.  A pixel evaluates q = d^T Q d (d = pixel - mean, Q = [[a,b],[b,c]] the conic)
+// in FP32 as -2 power and passes the exponent test only where that value is at most thr = -2 cutoff.  For a
+// positive-definite Q the minimum of q over the rectangle of a wavefront's pixel centres is found exactly with
+// two clamped one-dimensional minimizations: it is 0 when the mean lies inside; otherwise it lies on the
+// rectangle's edge that faces the mean along x or along y (any other boundary point p with q(p) > 0 has t p,
+// t < 1, inside the rectangle and q(t p) = t^2 q(p) < q(p)).  Along the line x = X, q is the parabola
+// c y^2 + 2 b X y + a X^2 with its minimum at y = -b X / c, clamped to the rectangle, and likewise along
+// y = Y.  Evaluating the line x = clamp(0, x0, x1) and the line y = clamp(0, y0, y1) thus gives two values
+// of q on the rectangle whose smaller is its minimum.  The FP32 rounding of this test and of every pixel's
+// own evaluation is below 1e-6 of |a| dx^2 + 2|b dx dy| + |c| dy^2, bounded over the block by
+// (a + |b|) DX^2 + (c + |b|) DY^2 (DX, DY the largest |dx|, |dy|); a block is skipped only when both values
+// exceed thr by 4e-6 of that bound.  Every pixel of a skipped block then computes an exponent below its
+// cutoff, so the cull changes no result.  A splat with opacity below alpha_min (1 - 1e-3) or NaN can never
+// blend (its exponent is at most 0) and is listed nowhere; a conic not shown positive definite is listed for
+// every block.
+constexpr float kQErr = 4.0e-6f;
+struct CullConic {
+  float a, c, b2, nbia, nbic, ka, kc, thr;
+  int mode;  // 0: test the blocks, 1: list nowhere, 2: list everywhere
 };
-__device__ __forceinline__ CullBounds cull_bounds(float ca, float cb, float cc, float opacity, float alpha_min) {
-  const float amin = alpha_min * 0.999f;
-  if (!(opacity >= amin)) return CullBounds{-1.0f, -1.0f, -1.0f};
-  const double det = (double)ca * (double)cc - (double)cb * (double)cb;
-  const float h = 0.5f * (ca - cc);
-  const float lmax = 0.5f * (ca + cc) + sqrtf(h * h + cb * cb);
-  if (!(det > 0.0) || !(lmax > 0.0f)) return CullBounds{3.0e38f, 3.0e38f, 3.0e38f};  // no usable bound
-  const float thr = 2.0f * __logf(opacity / amin);
-  const float lmin = (float)(det / (double)lmax) * 0.999f;
-  const float ex = sqrtf(thr * (float)((double)cc / det)) * 1.001f;
-  const float ey = sqrtf(thr * (float)((double)ca / det)) * 1.001f;
-  return CullBounds{thr / lmin, ex, ey};
+__device__ __forceinline__ CullConic cull_conic(float ca, float cb, float cc, float opacity, float alpha_min,
+                                                float thr) {
+  CullConic k;
+  const bool pd = ca > 0.0f && cc > 0.0f && ca * cc > (cb * cb) * 1.00001f;
+  k.mode = !(opacity >= alpha_min * 0.999f) ? 1 : (pd ? 0 : 2);
+  k.a = ca;
+  k.c = cc;
+  k.b2 = cb + cb;
+  k.nbia = -cb * __builtin_amdgcn_rcpf(ca);
+  k.nbic = -cb * __builtin_amdgcn_rcpf(cc);
+  k.ka = kQErr * (ca + fabsf(cb));
+  k.kc = kQErr * (cc + fabsf(cb));
+  k.thr = thr;
+  return k;
 }
 
 // One splat record loaded into registers ahead of its batch (prefetch).
@@ -184,6 +190,7 @@ struct SplatLoader {
 template <class PM>
 struct BlockBoxes {
   float x_lo[PM::WX], x_hi[PM::WX], y_lo[PM::WY], y_hi[PM::WY];
+  int all;  // bit w: wavefront w's block holds a pixel of the image
   __device__ explicit BlockBoxes(const PM& pm) {
 #pragma unroll
     for (int c = 0; c < PM::WX; ++c) {
@@ -195,32 +202,53 @@ struct BlockBoxes {
       y_lo[r] = (float)(pm.ty0 + r * PM::SUBH);
       y_hi[r] = (float)(min(pm.ty0 + (r + 1) * PM::SUBH, pm.H) - 1);
     }
+    all = 0;
+#pragma unroll
+    for (int r = 0; r < PM::WY; ++r)
+#pragma unroll
+      for (int c = 0; c < PM::WX; ++c)
+        if (x_lo[c] <= x_hi[c] && y_lo[r] <= y_hi[r]) all |= 1 << (r * PM::WX + c);
   }
-  // Bit w set: wavefront w's block is inside both cull bounds of a splat at (mx, my).
-  __device__ __forceinline__ int mask(float mx, float my, const CullBounds& cb) const {
-    float dxs[PM::WX], dys[PM::WY];
-    bool okx[PM::WX], oky[PM::WY];
+  // Bit w set: a pixel of wavefront w's block may pass the exponent test of the splat at (mx, my).
+  __device__ __forceinline__ int mask(float mx, float my, const CullConic& k) const {
+    float x0[PM::WX], x1[PM::WX], axx[PM::WX], bx2[PM::WX], tx[PM::WX], lx[PM::WX];
+    float y0[PM::WY], y1[PM::WY], cyy[PM::WY], by2[PM::WY], ty[PM::WY], ly[PM::WY];
 #pragma unroll
     for (int c = 0; c < PM::WX; ++c) {
-      const float o = fmaxf(x_lo[c] - mx, mx - x_hi[c]);  // > 0: outside
-      okx[c] = !(o > cb.ex);
-      const float d = fmaxf(o, 0.0f);
-      dxs[c] = d * d;
+      x0[c] = x_lo[c] - mx;
+      x1[c] = x_hi[c] - mx;
+      const float xn = __builtin_amdgcn_fmed3f(0.0f, x0[c], x1[c]);
+      axx[c] = (k.a * xn) * xn;
+      bx2[c] = k.b2 * xn;
+      tx[c] = k.nbic * xn;
+      const float dx = fmaxf(fabsf(x0[c]), fabsf(x1[c]));
+      lx[c] = fmaf(k.ka * dx, dx, k.thr);
     }
 #pragma unroll
     for (int r = 0; r < PM::WY; ++r) {
-      const float o = fmaxf(y_lo[r] - my, my - y_hi[r]);
-      oky[r] = !(o > cb.ey);
-      const float d = fmaxf(o, 0.0f);
-      dys[r] = d * d;
+      y0[r] = y_lo[r] - my;
+      y1[r] = y_hi[r] - my;
+      const float yn = __builtin_amdgcn_fmed3f(0.0f, y0[r], y1[r]);
+      cyy[r] = (k.c * yn) * yn;
+      by2[r] = k.b2 * yn;
+      ty[r] = k.nbia * yn;
+      const float dy = fmaxf(fabsf(y0[r]), fabsf(y1[r]));
+      ly[r] = (k.kc * dy) * dy;
     }
     int m = 0;
 #pragma unroll
     for (int r = 0; r < PM::WY; ++r)
 #pragma unroll
-      for (int c = 0; c < PM::WX; ++c)
-        if (okx[c] && oky[r] && !(dxs[c] + dys[r] > cb.r2)) m |= 1 << (r * PM::WX + c);
-    return m;
+      for (int c = 0; c < PM::WX; ++c) {
+        const float ys = __builtin_amdgcn_fmed3f(tx[c], y0[r], y1[r]);
+        const float qv = fmaf(fmaf(k.c, ys, bx2[c]), ys, axx[c]);
+        const float xs = __builtin_amdgcn_fmed3f(ty[r], x0[c], x1[c]);
+        const float qh = fmaf(fmaf(k.a, xs, by2[r]), xs, cyy[r]);
+        const float lim = lx[c] + ly[r];
+        if (!(qv > lim) || !(qh > lim)) m |= 1 << (r * PM::WX + c);
+      }
+    m = k.mode == 0 ? m : (k.mode == 2 ? all : 0);
+    return m & all;
   }
 };
 
@@ -246,10 +274,10 @@ __device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBox
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   int mask = 0;
   if (ld.valid) {
-    const CullBounds cb = cull_bounds(ld.a.z, ld.a.w, ld.b.x, ld.b.y, alpha_min);
-    mask = bx.mask(ld.a.x, ld.a.y, cb);
+    const float cut = power_cutoff(ld.b.y, alpha_min);
+    mask = bx.mask(ld.a.x, ld.a.y, cull_conic(ld.a.z, ld.a.w, ld.b.x, ld.b.y, alpha_min, -2.0f * cut));
     L.a[t] = make_float4(ld.a.x, ld.a.y, -0.5f * ld.a.z, -ld.a.w);
-    L.b[t] = make_float4(-0.5f * ld.b.x, ld.b.y, power_cutoff(ld.b.y, alpha_min), ld.b.z);
+    L.b[t] = make_float4(-0.5f * ld.b.x, ld.b.y, cut, ld.b.z);
     L.c[t] = make_float2(ld.b.w, ld.c.x);
     if (with_id) L.id[t] = ld.id;
   }
