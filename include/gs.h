@@ -136,10 +136,21 @@ void gs_default_options(gs_options* opts);
  * plane, degenerate, opacity <= alpha_min (1 - 1e-3), or no tile touched).
  * flags bits 0-2: colour channel clamped at 0; bits 3-4: frustum guard active
  * in x / y.  tiles_touched [n_views*n] = tile count of the pair's rect (0 when
- * culled). */
+ * culled).
+ * vis, vis_count: the visible pairs (tiles_touched > 0) compacted by blocks of
+ * 64 Gaussians, the hand-off from gs_project to gs_bin_sort.  With
+ * S = ceil(n/64) segments per view, segment s = v*S + b holds the visible
+ * pairs of view v among Gaussians [64 b, 64 b + 64) in ascending i:
+ * vis_count [n_views*S] holds their number and vis [n_views*S*64][4] (uint32,
+ * 16-byte aligned) holds at slots [64 s, 64 s + vis_count[s]) one entry each:
+ * x0 | x1 << 16, y0 | y1 << 16 (the tile rect [x0,x1) x [y0,y1) in the view's
+ * grid, as documented at gs_bin_sort), v*n+i, and the FP32 bits of the depth.
+ * Slots past a segment's count are not written. */
 typedef struct gs_projected {
   float* rec;
   int32_t* tiles_touched;
+  uint32_t* vis;
+  uint32_t* vis_count;
 } gs_projected;
 
 /* Tile bins.  keys [capacity] (may be NULL: not written), ids [capacity],
@@ -222,8 +233,8 @@ gs_status gs_render_bwd_workspace_size(int64_t n, int32_t n_views, size_t* bytes
  * J W Sigma W^T J^T + eps2d I with Sigma = R(q) S S^T R(q)^T (local affine
  * approximation of the perspective map, frustum guard on x/z and y/z);
  * conic; radius; tile rect; colour; opacity; writes out->rec and
- * out->tiles_touched for all n_views*n pairs.  Parameters are read once for
- * all views. */
+ * out->tiles_touched for all n_views*n pairs, and the visible pairs' entries
+ * to out->vis / out->vis_count.  Parameters are read once for all views. */
 gs_status gs_project(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
                      const gs_projected* out, void* stream);
 
@@ -232,7 +243,9 @@ gs_status gs_project(const gs_params* params, const gs_camera* cams, int32_t n_v
  * assigned to each tile of its rect [floor((m-r)/B), floor((m+r+B-1)/B))
  * (computed in FP32, clamped to the view's grid); the (tile, id) incidences
  * are ordered as documented at gs_bins (a stable LSD radix sort on the
- * 64-bit key, ties broken by ascending v*N+i).  `workspace` must hold
+ * 64-bit key, ties broken by ascending v*N+i).  The pairs and their rects are
+ * read from proj->vis / proj->vis_count as gs_project wrote them; proj->rec
+ * is read for the depths of bins->keys.  `workspace` must hold
  * gs_bin_sort_workspace_size() bytes for the same arguments. */
 gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n_views,
                       const gs_options* opts, const gs_bins* bins, void* workspace, size_t workspace_bytes,

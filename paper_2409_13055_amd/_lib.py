@@ -47,7 +47,7 @@ class gs_options(C.Structure):
 
 
 class gs_projected(C.Structure):
-    _fields_ = [("rec", P), ("tiles_touched", P)]
+    _fields_ = [("rec", P), ("tiles_touched", P), ("vis", P), ("vis_count", P)]
 
 
 class gs_bins(C.Structure):

@@ -86,28 +86,19 @@ struct ViewLds {
 };
 
 // ---------------------------------------------------------------------------
-// Visible-pair compaction: for every pair with tiles_touched > 0, in (v*N+i)
-// order, its compaction index c: a_key[c] = depth bits, a_val[c] = c and
-// entc[c] = its entry record.
+// Visible-pair compaction from the projection's segments (64 Gaussians of one
+// view each, in (v*N+i) order): pair c of the concatenation gets a_key[c] =
+// depth bits, a_val[c] = c and entc[c] = its entry record.
 // ---------------------------------------------------------------------------
-constexpr int kCompactItems = 8;  // consecutive pairs per thread
+constexpr int kCopyBatch = 8;  // segments whose entries a wavefront loads before storing any
 
-__global__ __launch_bounds__(kSortThreads) void k_count_visible(const int32_t* __restrict__ tiles, uint64_t count,
-                                                                int nb, uint64_t* __restrict__ partial) {
-  __shared__ uint64_t s_w[4];
-  const Chunk c = chunk_of(count, nb, blockIdx.x);
-  uint64_t sum = 0;
-  for (uint64_t base = c.begin; base < c.end; base += kSortThreads * kCompactItems) {
-    int32_t t[kCompactItems];
-#pragma unroll
-    for (int k = 0; k < kCompactItems; ++k)
-      t[k] = tiles[min(base + (uint64_t)(k * kSortThreads + threadIdx.x), c.end - 1)];
-#pragma unroll
-    for (int k = 0; k < kCompactItems; ++k)
-      sum += (base + (uint64_t)(k * kSortThreads + threadIdx.x) < c.end && t[k] > 0) ? 1 : 0;
-  }
+// Per block of kSortThreads segments: the total of their counts.
+__global__ __launch_bounds__(kSortThreads) void k_segment_totals(const uint32_t* __restrict__ seg_count,
+                                                                 uint32_t n_seg, uint64_t* __restrict__ partial) {
+  __shared__ uint64_t s_w[kSortThreads / 64];
+  const uint32_t sg = blockIdx.x * kSortThreads + threadIdx.x;
   uint64_t tot;
-  block_exclusive_scan<uint64_t>(sum, s_w, tot);
+  block_exclusive_scan<uint64_t>(sg < n_seg ? seg_count[sg] : 0u, s_w, tot);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
@@ -128,73 +119,44 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_partials(uint64_t* __rest
   if (threadIdx.x == 0) *total_u32 = carry > cap32 ? 0u : (uint32_t)carry;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_compact_visible(const int32_t* __restrict__ tiles,
-                                                                  const float* __restrict__ rec, uint64_t count,
-                                                                  int nb, const uint64_t* __restrict__ partial,
-                                                                  ViewTable vt, uint32_t n,
-                                                                  uint32_t* __restrict__ a_key,
-                                                                  uint32_t* __restrict__ a_val,
-                                                                  uint4* __restrict__ entc) {
-  __shared__ uint32_t s_w[4];
-  __shared__ ViewLds s_g;  // TX, TY
-  // a round's visible pairs, staged so that they leave as coalesced stores
-  __shared__ uint32_t s_key[kSortThreads * kCompactItems];
-  __shared__ uint4 s_rec[kSortThreads * kCompactItems];
-  if (threadIdx.x < vt.n_views) {
-    s_g.a[threadIdx.x] = vt.v[threadIdx.x].TX;
-    s_g.b[threadIdx.x] = vt.v[threadIdx.x].TY;
-  }
+// Block b copies segments [b kSortThreads, (b + 1) kSortThreads): their offsets
+// come from a block scan of the counts plus the block's partial; wavefront w
+// copies its 64 segments, lane l taking entry l of each, the entries of
+// kCopyBatch segments loaded before any is stored.
+__global__ __launch_bounds__(kSortThreads) void k_compact_segments(const uint4* __restrict__ seg_ent,
+                                                                   const uint32_t* __restrict__ seg_count,
+                                                                   uint32_t n_seg,
+                                                                   const uint64_t* __restrict__ partial,
+                                                                   uint32_t* __restrict__ a_key,
+                                                                   uint32_t* __restrict__ a_val,
+                                                                   uint4* __restrict__ entc) {
+  __shared__ uint64_t s_w[kSortThreads / 64];
+  __shared__ uint32_t s_off[kSortThreads], s_cnt[kSortThreads];
+  const uint32_t sg0 = blockIdx.x * kSortThreads;
+  const uint32_t c = sg0 + threadIdx.x < n_seg ? seg_count[sg0 + threadIdx.x] : 0u;
+  uint64_t tot;
+  const uint64_t ex = block_exclusive_scan<uint64_t>(c, s_w, tot) + partial[blockIdx.x];
+  s_off[threadIdx.x] = (uint32_t)ex;  // < n_views * n < 2^32
+  s_cnt[threadIdx.x] = c;
   __syncthreads();
-  const Chunk c = chunk_of(count, nb, blockIdx.x);
-  uint64_t run = partial[blockIdx.x];
-  for (uint64_t base = c.begin; base < c.end; base += kSortThreads * kCompactItems) {
-    // thread t takes the kCompactItems consecutive pairs from i0, so its visible
-    // ones are consecutive in the output too
-    const uint64_t i0 = base + (uint64_t)threadIdx.x * kCompactItems;
-    int32_t t[kCompactItems];
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int g = 0; g < 64; g += kCopyBatch) {
+    uint4 e[kCopyBatch];
 #pragma unroll
-    for (int k = 0; k < kCompactItems; ++k) t[k] = tiles[min(i0 + k, c.end - 1)];
-    uint32_t vis = 0, cnt = 0;
+    for (int k = 0; k < kCopyBatch; ++k) {
+      const int q = w * 64 + g + k;
+      if (lane < s_cnt[q]) e[k] = seg_ent[(size_t)(sg0 + q) * 64 + lane];
+    }
 #pragma unroll
-    for (int k = 0; k < kCompactItems; ++k)
-      if (i0 + k < c.end && t[k] > 0) {
-        vis |= 1u << k;
-        ++cnt;
-      }
-    // the visible rows' mean, depth and extents, all requested before any is used
-    float4 r0[kCompactItems], r2[kCompactItems];
-#pragma unroll
-    for (int k = 0; k < kCompactItems; ++k) {
-      const float4* row = reinterpret_cast<const float4*>(rec + (size_t)min(i0 + k, c.end - 1) * GS_REC_FLOATS);
-      if ((vis >> k) & 1u) {
-        r0[k] = row[0];
-        r2[k] = row[2];
+    for (int k = 0; k < kCopyBatch; ++k) {
+      const int q = w * 64 + g + k;
+      if (lane < s_cnt[q]) {
+        const uint32_t pos = s_off[q] + lane;
+        a_key[pos] = e[k].w;
+        a_val[pos] = pos;
+        entc[pos] = e[k];
       }
     }
-    // (the scan's barriers also order this round's staging after the previous round's copy-out)
-    uint32_t tot;
-    uint32_t lp = block_exclusive_scan<uint32_t>(cnt, s_w, tot);
-#pragma unroll
-    for (int k = 0; k < kCompactItems; ++k) {
-      if ((vis >> k) & 1u) {
-        const uint32_t id = (uint32_t)(i0 + k), v = id / n;
-        int x0, y0, x1, y1;
-        tile_rect(r0[k].x, r0[k].y, ext_x(__float_as_int(r2[k].z)), ext_y(__float_as_int(r2[k].z)), vt.tile,
-                  s_g.a[v], s_g.b[v], x0, y0, x1, y1);
-        const uint32_t d = __float_as_uint(r2[k].y);
-        s_key[lp] = d;
-        s_rec[lp] = make_uint4((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16), id, d);
-        ++lp;
-      }
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < tot; i += kSortThreads) {
-      const uint64_t pos = run + i;
-      a_key[pos] = s_key[i];
-      a_val[pos] = (uint32_t)pos;
-      entc[pos] = s_rec[i];
-    }
-    run += tot;
   }
 }
 
@@ -834,6 +796,8 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t va
 // ---------------------------------------------------------------------------
 struct SortPlan {
   uint64_t vn;        // n_views * n
+  uint32_t n_seg;     // projection segments (64 Gaussians of one view)
+  int nb_seg;         // blocks over the segments
   uint64_t cap;       // pair capacity (bounds the window items too: each holds an incidence)
   int nb_vn;          // radix blocks over the visible pairs
   int nb_items;       // radix blocks over the window items
@@ -853,6 +817,8 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   p.vn = (uint64_t)n * (uint64_t)n_views;
   p.cap = (uint64_t)capacity;
   p.nb_vn = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.vn + 2047) / 2048));
+  p.n_seg = (uint32_t)((uint64_t)n_views * (((uint64_t)n + 63) / 64));
+  p.nb_seg = (int)((p.n_seg + kSortThreads - 1) / kSortThreads);
   p.nb_items = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.cap + 2047) / 2048));
   p.n_steps = (int)((p.vn + kStep - 1) / kStep);
   p.grid_steps = std::min(p.n_steps, 4096);
@@ -868,7 +834,7 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   };
   const uint64_t cap1 = std::max<uint64_t>(p.cap, 1);
   p.off_counters = take(64);
-  p.off_part_a = take(sizeof(uint64_t) * p.nb_vn);
+  p.off_part_a = take(sizeof(uint64_t) * p.nb_seg);
   p.off_step_win = take(sizeof(uint64_t) * p.n_steps);
   p.off_step_tiles = take(sizeof(uint64_t) * p.n_steps);
   p.off_entc = take(sizeof(uint4) * p.vn);
@@ -931,7 +897,8 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   gs_status s;
   if ((s = validate_cams(cams, n_views)) != GS_OK) return s;
   if ((s = validate_opts(opts)) != GS_OK) return s;
-  if (!proj || !proj->rec || !proj->tiles_touched) return fail(GS_ERR_INVALID_VALUE, "proj is incomplete");
+  if (!proj || !proj->rec || !proj->vis || !proj->vis_count) return fail(GS_ERR_INVALID_VALUE, "proj is incomplete");
+  if (reinterpret_cast<uintptr_t>(proj->vis) % 16 != 0) return fail(GS_ERR_INVALID_VALUE, "vis must be 16-byte aligned");
   if (!bins || !bins->ids || !bins->ranges || !bins->d_num_pairs || !bins->d_overflow)
     return fail(GS_ERR_INVALID_VALUE, "bins is incomplete");
   if (n < 1 || (int64_t)n_views * n >= (int64_t(1) << 32) - 1) return fail(GS_ERR_INVALID_VALUE, "bad n");
@@ -969,12 +936,12 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   const int W = vt.total_windows;
 
   // 1. visible (view, Gaussian) pairs, compacted in id order with their depth keys and entry records
-  hipLaunchKernelGGL(k_count_visible, dim3(p.nb_vn), dim3(kSortThreads), 0, st, proj->tiles_touched, p.vn, p.nb_vn,
-                     part_a);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kSortThreads), 0, st, part_a, p.nb_vn, d_k,
+  const uint4* seg_ent = reinterpret_cast<const uint4*>(proj->vis);
+  hipLaunchKernelGGL(k_segment_totals, dim3(p.nb_seg), dim3(kSortThreads), 0, st, proj->vis_count, p.n_seg, part_a);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kSortThreads), 0, st, part_a, p.nb_seg, d_k,
                      (uint64_t)UINT32_MAX);
-  hipLaunchKernelGGL(k_compact_visible, dim3(p.nb_vn), dim3(kSortThreads), 0, st, proj->tiles_touched, proj->rec,
-                     p.vn, p.nb_vn, part_a, vt, (uint32_t)n, akey, aval, entc);
+  hipLaunchKernelGGL(k_compact_segments, dim3(p.nb_seg), dim3(kSortThreads), 0, st, seg_ent, proj->vis_count,
+                     p.n_seg, part_a, akey, aval, entc);
   // 2. depth digits (bit 31 of a positive float is 0): four 8-bit passes, ends in (akey, aval)
   radix_pass<uint32_t>(akey, aval, bkey, bval, d_k, 0, p.nb_vn, hist, dtot, st);
   radix_pass<uint32_t>(bkey, bval, akey, aval, d_k, 8, p.nb_vn, hist, dtot, st);

@@ -247,12 +247,19 @@ __device__ __forceinline__ float sh_channel(const Coef& coef, const float* Y, in
   return s;
 }
 
+// Besides the records, each wavefront (64 consecutive Gaussians) lists its
+// visible pairs of every view in ascending i, at their ballot prefix within
+// the segment of (view, wavefront), with the segment's count.
 template <int D>
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, float* __restrict__ rec,
-                                                 int32_t* __restrict__ tiles_touched) {
+                                                 int32_t* __restrict__ tiles_touched, uint4* __restrict__ vis,
+                                                 uint32_t* __restrict__ vis_count) {
   constexpr int K = (D + 1) * (D + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t n_seg = (a.n + 63) >> 6;
   GaussCov g;
   load_cov(a, i, g);
   float sh[K][3];
@@ -279,6 +286,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
     bool ok = g.ok && project_view(g, cam, a.near_plane, a.eps2d, p);
     ok = ok && opaque_enough;
     int packed = 0, tiles = 0;
+    int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
     float rgb[3] = {0.f, 0.f, 0.f};
     uint32_t flags = 0;
     const float fmx = (float)p.mx, fmy = (float)p.my;
@@ -289,7 +297,6 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
       const int rx = (int)fmin(r, ceil(sqrt(thr * p.a)) + 1.0);
       const int ry = (int)fmin(r, ceil(sqrt(thr * p.c)) + 1.0);
       const int TX = (cam.W + B - 1) / B, TY = (cam.H + B - 1) / B;
-      int x0, y0, x1, y1;
       tile_rect(fmx, fmy, rx, ry, B, TX, TY, x0, y0, x1, y1);
       tiles = (x1 - x0) * (y1 - y0);
       if (tiles <= 0) {
@@ -328,6 +335,13 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
       out[2] = make_float4(0.f, 0.f, __int_as_float(0), __uint_as_float(0u));
     }
     tiles_touched[row] = tiles;
+    const uint64_t bal = __ballot(ok);
+    const int64_t seg = (int64_t)v * n_seg + (i >> 6);
+    if (ok)
+      vis[seg * 64 + __popcll(bal & below)] = make_uint4((uint32_t)x0 | ((uint32_t)x1 << 16),
+                                                         (uint32_t)y0 | ((uint32_t)y1 << 16), (uint32_t)row,
+                                                         __float_as_uint((float)p.t[2]));
+    if (lane == 0) vis_count[seg] = (uint32_t)__popcll(bal);
   }
 }
 
@@ -700,8 +714,10 @@ extern "C" gs_status gs_project(const gs_params* params, const gs_camera* cams, 
   if ((s = validate_params(params)) != GS_OK) return s;
   if ((s = validate_cams(cams, n_views)) != GS_OK) return s;
   if ((s = validate_opts(opts)) != GS_OK) return s;
-  if (!out || !out->rec || !out->tiles_touched) return fail(GS_ERR_INVALID_VALUE, "out/rec/tiles_touched is NULL");
+  if (!out || !out->rec || !out->tiles_touched || !out->vis || !out->vis_count)
+    return fail(GS_ERR_INVALID_VALUE, "out/rec/tiles_touched/vis/vis_count is NULL");
   if (reinterpret_cast<uintptr_t>(out->rec) % 16 != 0) return fail(GS_ERR_INVALID_VALUE, "rec must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(out->vis) % 16 != 0) return fail(GS_ERR_INVALID_VALUE, "vis must be 16-byte aligned");
   if ((int64_t)n_views * params->n >= (int64_t(1) << 32) - 1)
     return fail(GS_ERR_INVALID_VALUE, "n_views * n must be < 2^32 - 1");
   const ProjectArgs a = make_args(params, n_views, opts);
@@ -709,11 +725,13 @@ extern "C" gs_status gs_project(const gs_params* params, const gs_camera* cams, 
   const int bs = 256;
   const dim3 grid((unsigned)((params->n + bs - 1) / bs));
   hipStream_t st = as_stream(stream);
+  uint4* vis = reinterpret_cast<uint4*>(out->vis);
+  uint32_t* vc = out->vis_count;
   switch (params->sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched); break;
-    default: hipLaunchKernelGGL(k_project<3>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched); break;
+    case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched, vis, vc); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched, vis, vc); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched, vis, vc); break;
+    default: hipLaunchKernelGGL(k_project<3>, grid, dim3(bs), 0, st, a, ct, out->rec, out->tiles_touched, vis, vc); break;
   }
   return check_launch("projection");
 }

@@ -101,6 +101,9 @@ class Frame:
         VN = rast.n * rast.n_views
         self.rec = torch.empty(VN * L.GS_REC_FLOATS, dtype=torch.float32, device=dev)
         self.tiles = torch.empty(VN, dtype=torch.int32, device=dev)
+        n_seg = rast.n_views * ((rast.n + 63) // 64)  # visible pairs by (view, 64 Gaussians), see gs_projected
+        self.vis = torch.empty(n_seg * 64 * 4, dtype=torch.int32, device=dev)
+        self.vis_count = torch.empty(n_seg, dtype=torch.int32, device=dev)
         self.ranges = torch.empty(2 * rast.total_tiles, dtype=torch.int32, device=dev)
         self.d_num_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
         self.d_overflow = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -120,7 +123,7 @@ class Frame:
         self.keys = torch.empty(max(1, self.capacity), dtype=torch.int64, device=dev) if want_keys else None
 
     def c_proj(self) -> L.gs_projected:
-        return L.gs_projected(_p(self.rec), _p(self.tiles))
+        return L.gs_projected(_p(self.rec), _p(self.tiles), _p(self.vis), _p(self.vis_count))
 
     def c_bins(self) -> L.gs_bins:
         b = L.gs_bins()

@@ -3,21 +3,21 @@
 Bytes are what the method must move through HBM: each input read once and
 each output written once (not the implementation's extra passes or cache
 re-reads).  For the raster calls the arithmetic is counted too, as FP32
-flops of the per-pixel blending as defined (counted exactly on the GPU by
+flops of the (pixel, entry) pairs that blend (counted exactly on the GPU by
 gs_render_stats), because those kernels are bound by vector ALU issue, not
 by HBM.
 
 Per-unit figures (P_n = 11 + 3K raw floats per Gaussian, K = (D+1)^2):
-  project     N*4*P_n + V*N*(48 + 4)
-  bin_sort    V*N*4 [tiles_touched] + Nv*16 [mean, depth, extents] + M*4 [ids] + T*8 [ranges]
+  project     N*4*P_n + V*N*(48 + 4) + Nv*16 + S*4 [visible-pair entries, segment counts]
+  bin_sort    S*4 [segment counts] + Nv*16 [visible-pair entries] + M*4 [ids] + T*8 [ranges]
   render_fwd  Nv*36 + M*4 + Px*(12 + 12 [target] + 8 [T_final, n_contrib unless checkpoint])
   raster_bwd  Px*(12 [image] + 12 [target]) + Nv*36 [records] + M*4 + Nv*36 [gradients]
   project_bwd N*(4*P_n + 8*P_n) + V*N*(36 + 16)
   render_bwd  raster_bwd + project_bwd
   adam        N*P_n*32  (read p, g, m, v; write p, m, v, g := 0)
   project_bwd_adam  N*P_n*24 (read p, m, v; write p, m, v) + V*N*52
-with N Gaussians, V views, Nv visible (view, Gaussian) pairs, M tile
-incidences, Px pixels and T tiles.
+with N Gaussians, V views, Nv visible (view, Gaussian) pairs, S = V*ceil(N/64)
+projection segments, M tile incidences, Px pixels and T tiles.
 """
 from __future__ import annotations
 
@@ -34,10 +34,11 @@ import torch
 #                        dL/dC . S (mul + 2 FMA each), reciprocal, dL/dalpha
 #                        (mul + FMA), clamp test, dL/dpower, opacity grad FMA,
 #                        u dx and u dy, moments (2 add + 3 FMA)
-# The backward sweeps each pixel's list front to back with the forward's
-# decisions, so it evaluates the same entries as the forward.  The counts come
-# from gs_render_stats (the blending as defined, no cull): E_eval entries
-# evaluated until each pixel stops, E_blend blended pairs.
+# Only the blended pairs are counted, each with its evaluation: an evaluation
+# that does not blend is work a cull can avoid (the kernels skip most of them),
+# so counting it would credit work that is not done.  The counts come from
+# gs_render_stats (the blending as defined): E_blend blended pairs; E_eval,
+# the entries evaluated until each pixel stops, is reported beside it.
 FLOPS_EVAL = 17
 FLOPS_FWD_BLEND = 10
 FLOPS_BWD_BLEND = 44
@@ -54,12 +55,13 @@ def counts(step, sc):
 
 def algorithmic_bytes(c):
     N, V, Pn, M, Nv, Px, T = c["N"], c["V"], c["Pn"], c["M"], c["Nv"], c["Px"], c["T"]
+    S = V * ((N + 63) // 64)
     saved = 0 if c["ckpt"] else 8
     raster_bwd = Px * 24 + Nv * 36 + M * 4 + Nv * 36
     project_bwd = N * 12 * Pn + V * N * 52
     return {
-        "project": N * 4 * Pn + V * N * 52,
-        "bin_sort": V * N * 4 + Nv * 16 + M * 4 + T * 8,
+        "project": N * 4 * Pn + V * N * 52 + Nv * 16 + S * 4,
+        "bin_sort": S * 4 + Nv * 16 + M * 4 + T * 8,
         "render_fwd": Nv * 36 + M * 4 + Px * (24 + saved),
         "raster_bwd": raster_bwd,
         "project_bwd": project_bwd,
@@ -76,7 +78,7 @@ def evaluations(step):
 
 def alu_flops(kernel, ev):
     blend = FLOPS_FWD_BLEND if kernel == "render_fwd" else FLOPS_BWD_BLEND
-    return ev["evaluated"] * FLOPS_EVAL + ev["blended"] * blend
+    return ev["blended"] * (FLOPS_EVAL + blend)
 
 
 SINGLE_KERNEL_CALLS = ("project", "render_fwd", "raster_bwd", "project_bwd", "adam", "project_bwd_adam")

@@ -77,6 +77,18 @@ def test_invalid_arguments_are_rejected_before_any_launch(L):
     params.sh_degree = 5
     with pytest.raises(L.GsError, match="sh_degree"):
         L.gs_project(params, cc, 1, o, out, None)
+    # the projection's visible-pair segments are required by the projection and the bin sort
+    params.sh_degree = 0
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh_dc"):
+        setattr(params, k, C.c_void_p(0x1000))
+    out.rec, out.tiles_touched = C.c_void_p(0x1000), C.c_void_p(0x2000)
+    with pytest.raises(L.GsError, match="vis"):
+        L.gs_project(params, cc, 1, o, out, None)
+    with pytest.raises(L.GsError, match="proj is incomplete"):
+        L.gs_bin_sort(out, 10, cc, 1, o, L.gs_bins(), None, 0, None)
+    out.vis, out.vis_count = C.c_void_p(0x3008), C.c_void_p(0x4000)
+    with pytest.raises(L.GsError, match="vis must be 16-byte aligned"):
+        L.gs_bin_sort(out, 10, cc, 1, o, L.gs_bins(), None, 0, None)
     groups = (L.gs_adam_group * 1)()
     groups[0].numel = 4
     with pytest.raises(L.GsError, match="NULL"):

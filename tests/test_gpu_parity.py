@@ -130,6 +130,31 @@ def test_wave_block_cull_on_needles(tile):
         assert U.rel_l2(g["grad2d"][:, c], g2_ref[:, c]) <= 1e-3, (c, U.rel_l2(g["grad2d"][:, c], g2_ref[:, c]))
 
 
+def test_projection_segments_list_the_visible_pairs():
+    """The projection's hand-off to the bin sort: per (view, 64 Gaussians) segment, the visible pairs
+    in ascending id with their depth bits and a tile rect of the pair's tile count; together, in
+    segment order, exactly the pairs with tiles_touched > 0 in (v*N+i) order."""
+    sc = small_scene(seed=5, n=3001)
+    g = U.run_gpu(sc, tile=16, backward=False)
+    fr = g["frame"]
+    n, V = sc.n, len(sc.cameras)
+    S_ = (n + 63) // 64
+    cnt = fr.vis_count.cpu().numpy().astype(np.int64)
+    ent = fr.vis.cpu().numpy().view(np.uint32).reshape(V * S_, 64, 4)
+    assert cnt.shape == (V * S_,) and cnt.min() >= 0 and cnt.max() <= 64
+    got = np.concatenate([ent[s, :cnt[s]] for s in range(V * S_)])
+    tiles = g["tiles"]
+    vis = np.nonzero(tiles > 0)[0]
+    assert np.array_equal(got[:, 2], vis.astype(np.uint32))
+    seg_of = (vis // n) * S_ + (vis % n) // 64
+    assert np.array_equal(np.repeat(np.arange(V * S_), cnt), seg_of)
+    depth_bits = np.ascontiguousarray(g["rec"][vis, 9]).view(np.uint32)
+    assert np.array_equal(got[:, 3], depth_bits)
+    x0, x1, y0, y1 = got[:, 0] & 0xffff, got[:, 0] >> 16, got[:, 1] & 0xffff, got[:, 1] >> 16
+    assert np.all(x1 > x0) and np.all(y1 > y0)
+    assert np.array_equal((x1 - x0) * (y1 - y0), tiles[vis].astype(np.uint32))
+
+
 def test_forward_independent_mode():
     """Whole FP64 pipeline (own projection, binning, sort) vs the GPU: differences are confined to
     rare discrete flips."""
