@@ -18,6 +18,7 @@
 // without a host round trip.
 #include <algorithm>
 #include <string>
+#include <type_traits>
 
 #include "gs_internal.h"
 
@@ -28,12 +29,16 @@ constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kScanThreads = 1024;
 
+// A radix block ranks kRadixTile keys at a time; each block's share of the
+// keys is a whole number of such tiles (a partial tile costs a full one).
+constexpr int kRadixTile = kSortThreads * 8;
+
 struct Chunk {
   uint64_t begin, end;
 };
 __device__ inline Chunk chunk_of(uint64_t count, int nb, int b) {
   uint64_t per = (count + nb - 1) / nb;
-  per = (per + kSortThreads - 1) / kSortThreads * kSortThreads;
+  per = (per + kRadixTile - 1) / kRadixTile * kRadixTile;
   const uint64_t s = std::min<uint64_t>(count, per * (uint64_t)b);
   const uint64_t e = std::min<uint64_t>(count, s + per);
   return {s, e};
@@ -85,6 +90,12 @@ struct ViewLds {
   int32_t a[GS_MAX_VIEWS], b[GS_MAX_VIEWS];
 };
 
+// Sixteen bytes held in registers or LDS (a plain struct: register arrays of
+// HIP's vector types can end up in scratch memory).
+struct alignas(16) Words4 {
+  uint32_t x, y, z, w;
+};
+
 // ---------------------------------------------------------------------------
 // Visible-pair compaction from the projection's segments (64 Gaussians of one
 // view each, in (v*N+i) order): pair c of the concatenation gets a_key[c] =
@@ -119,10 +130,12 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_partials(uint64_t* __rest
   if (threadIdx.x == 0) *total_u32 = carry > cap32 ? 0u : (uint32_t)carry;
 }
 
-// Block b copies segments [b kSortThreads, (b + 1) kSortThreads): their offsets
-// come from a block scan of the counts plus the block's partial; wavefront w
-// copies its 64 segments, lane l taking entry l of each, the entries of
-// kCopyBatch segments loaded before any is stored.
+// Block b copies segments [b kSortThreads, (b + 1) kSortThreads), whose
+// entries are the output positions [partial[b], partial[b] + total): thread t
+// takes positions t, t + kSortThreads, ... of that run, finding each one's
+// segment by a binary search over the block's exclusive count prefixes in LDS,
+// so consecutive lanes store to consecutive positions; kCopyBatch loads are in
+// flight before their stores.
 __global__ __launch_bounds__(kSortThreads) void k_compact_segments(const uint4* __restrict__ seg_ent,
                                                                    const uint32_t* __restrict__ seg_count,
                                                                    uint32_t n_seg,
@@ -130,31 +143,35 @@ __global__ __launch_bounds__(kSortThreads) void k_compact_segments(const uint4* 
                                                                    uint32_t* __restrict__ a_key,
                                                                    uint32_t* __restrict__ a_val,
                                                                    uint4* __restrict__ entc) {
-  __shared__ uint64_t s_w[kSortThreads / 64];
-  __shared__ uint32_t s_off[kSortThreads], s_cnt[kSortThreads];
+  static_assert(kSortThreads == 256, "the binary search covers 256 prefixes");
+  __shared__ uint32_t s_w[kSortThreads / 64];
+  __shared__ uint32_t s_loc[kSortThreads];
   const uint32_t sg0 = blockIdx.x * kSortThreads;
   const uint32_t c = sg0 + threadIdx.x < n_seg ? seg_count[sg0 + threadIdx.x] : 0u;
-  uint64_t tot;
-  const uint64_t ex = block_exclusive_scan<uint64_t>(c, s_w, tot) + partial[blockIdx.x];
-  s_off[threadIdx.x] = (uint32_t)ex;  // < n_views * n < 2^32
-  s_cnt[threadIdx.x] = c;
+  uint32_t tot;
+  s_loc[threadIdx.x] = block_exclusive_scan<uint32_t>(c, s_w, tot);  // at most 256 * 64
+  const uint32_t base = (uint32_t)partial[blockIdx.x];                 // < n_views * n < 2^32
   __syncthreads();
-  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int g = 0; g < 64; g += kCopyBatch) {
-    uint4 e[kCopyBatch];
+  for (uint32_t i0 = threadIdx.x; i0 < tot; i0 += kSortThreads * kCopyBatch) {
+    Words4 e[kCopyBatch];
 #pragma unroll
     for (int k = 0; k < kCopyBatch; ++k) {
-      const int q = w * 64 + g + k;
-      if (lane < s_cnt[q]) e[k] = seg_ent[(size_t)(sg0 + q) * 64 + lane];
+      const uint32_t i = min(i0 + (uint32_t)k * kSortThreads, tot - 1);  // clamped: every load is in bounds
+      uint32_t q = 0;  // the last segment whose prefix is <= i: i lies inside it
+#pragma unroll
+      for (int b = 7; b >= 0; --b)
+        if (s_loc[q + (1u << b)] <= i) q += 1u << b;
+      const uint4 g = seg_ent[(size_t)(sg0 + q) * 64 + (i - s_loc[q])];
+      e[k] = Words4{g.x, g.y, g.z, g.w};
     }
 #pragma unroll
     for (int k = 0; k < kCopyBatch; ++k) {
-      const int q = w * 64 + g + k;
-      if (lane < s_cnt[q]) {
-        const uint32_t pos = s_off[q] + lane;
+      const uint32_t i = i0 + (uint32_t)k * kSortThreads;
+      if (i < tot) {
+        const uint32_t pos = base + i;
         a_key[pos] = e[k].w;
         a_val[pos] = pos;
-        entc[pos] = e[k];
+        entc[pos] = make_uint4(e[k].x, e[k].y, e[k].z, e[k].w);
       }
     }
   }
@@ -213,18 +230,30 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scan_digit(uint32_t* __r
 // then reordered by digit in LDS and written out digit run by digit run, so
 // global stores are coalesced.  Order inside a digit follows the input index,
 // which keeps every pass stable.  V is the value type carried with the key.
+// With a gather source (the last pass over the compaction indices), the value
+// carried out is gather[value in], loaded while the keys are ranked, and only
+// the values are written.
 constexpr int kItems = 8;
 constexpr int kTileKeys = kSortThreads * kItems;
+static_assert(kTileKeys == kRadixTile, "block shares are whole tiles");
 
-template <typename V>
+template <typename V, bool GATHER>
+using CarriedT = typename std::conditional<GATHER, Words4, V>::type;  // in registers and LDS
+template <typename V, bool GATHER>
+using StoredT = typename std::conditional<GATHER, uint4, V>::type;  // in memory
+
+template <typename V, bool GATHER = false>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                                 const V* __restrict__ vin,
-                                                                uint32_t* __restrict__ kout, V* __restrict__ vout,
+                                                                uint32_t* __restrict__ kout,
+                                                                StoredT<V, GATHER>* __restrict__ vout,
                                                                 const uint32_t* __restrict__ d_count, int shift,
                                                                 int nb, const uint32_t* __restrict__ hist,
-                                                                const uint32_t* __restrict__ digit_total) {
+                                                                const uint32_t* __restrict__ digit_total,
+                                                                const uint4* __restrict__ gather) {
+  using VO = CarriedT<V, GATHER>;
   __shared__ uint32_t s_keys[kTileKeys];
-  __shared__ V s_vals[kTileKeys];
+  __shared__ VO s_vals[kTileKeys];
   __shared__ uint32_t s_wc[4][kRadixBins];
   __shared__ uint32_t s_start[kRadixBins];
   __shared__ uint32_t s_glob[kRadixBins];
@@ -246,6 +275,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
     __syncthreads();
     uint32_t key[kItems], rk[kItems];
     V val[kItems];
+    VO out[kItems];
     const uint64_t lim = c.end - tb;  // keys left from this tile's start
     {
       // all of the tile's loads first, with indices clamped into the tile and no branch, so they are
@@ -258,6 +288,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
         const uint32_t o = min(o0 + (uint32_t)k * 64, last);
         key[k] = kt[o];
         val[k] = vt[o];
+      }
+      if constexpr (GATHER) {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+          const uint4 g = gather[val[k]];
+          out[k] = Words4{g.x, g.y, g.z, g.w};
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) out[k] = val[k];
       }
     }
 #pragma unroll
@@ -298,7 +338,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
         const uint32_t d = (key[k] >> shift) & (kRadixBins - 1);
         const uint32_t lp = s_start[d] + s_wc[w][d] + rk[k];
         s_keys[lp] = key[k];
-        s_vals[lp] = val[k];
+        s_vals[lp] = out[k];
       }
     }
     __syncthreads();
@@ -309,8 +349,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
         const uint32_t kk = s_keys[i];
         const uint32_t d = (kk >> shift) & (kRadixBins - 1);
         const uint32_t g = s_glob[d] + (i - s_start[d]);
-        kout[g] = kk;
-        vout[g] = s_vals[i];
+        if constexpr (!GATHER) kout[g] = kk;
+        if constexpr (GATHER) {
+          const Words4 v = s_vals[i];
+          vout[g] = make_uint4(v.x, v.y, v.z, v.w);
+        } else {
+          vout[g] = s_vals[i];
+        }
       }
     }
     __syncthreads();
@@ -339,31 +384,23 @@ constexpr int kChunkEntries = 512;                 // window-list entries per ch
 constexpr int kChunkGroups = kChunkEntries / kWave;
 constexpr int kChunkWavesPerBlock = kSortThreads / kWave;
 
-// Entry records in depth order (ent[j] = entc[sorted c]) plus, per step of
-// kStep pairs, the number of (window, pair) items and of (tile, pair)
-// incidences.
-__global__ __launch_bounds__(kSortThreads) void k_entry_records(const uint32_t* __restrict__ sorted_c,
-                                                                const uint4* __restrict__ entc,
-                                                                const uint32_t* __restrict__ d_k,
-                                                                uint4* __restrict__ ent,
-                                                                uint64_t* __restrict__ step_win,
-                                                                uint64_t* __restrict__ step_tiles) {
+// Per step of kStep depth-ordered entry records: the number of (window, pair)
+// items and of (tile, pair) incidences.
+__global__ __launch_bounds__(kSortThreads) void k_step_counts(const uint4* __restrict__ ent,
+                                                              const uint32_t* __restrict__ d_k,
+                                                              uint64_t* __restrict__ step_win,
+                                                              uint64_t* __restrict__ step_tiles) {
   __shared__ uint64_t s_w[kSortThreads / 64];
   const uint32_t K = *d_k, nsteps = (K + kStep - 1) / kStep;
   for (uint32_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
     const uint32_t j0 = st * kStep + threadIdx.x;
-    uint32_t cc[kStepRounds];
-#pragma unroll
-    for (int k = 0; k < kStepRounds; ++k) cc[k] = sorted_c[min(j0 + (uint32_t)(k * kSortThreads), K - 1)];
     uint4 e[kStepRounds];
 #pragma unroll
-    for (int k = 0; k < kStepRounds; ++k) e[k] = entc[cc[k]];
+    for (int k = 0; k < kStepRounds; ++k) e[k] = ent[min(j0 + (uint32_t)(k * kSortThreads), K - 1)];
     uint64_t nt = 0, nw = 0;
 #pragma unroll
     for (int k = 0; k < kStepRounds; ++k) {
-      const uint32_t j = j0 + (uint32_t)(k * kSortThreads);
-      if (j < K) {
-        ent[j] = e[k];
+      if (j0 + (uint32_t)(k * kSortThreads) < K) {
         nt += rect_tiles(e[k]);
         nw += rect_windows(e[k]);
       }
@@ -858,13 +895,14 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   return p;
 }
 
-template <typename V>
-static void radix_pass(const uint32_t* kin, const V* vin, uint32_t* kout, V* vout, const uint32_t* d_count,
-                       int shift, int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st) {
+template <typename V, bool GATHER = false>
+static void radix_pass(const uint32_t* kin, const V* vin, uint32_t* kout, StoredT<V, GATHER>* vout,
+                       const uint32_t* d_count, int shift, int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st,
+                       const uint4* gather = nullptr) {
   hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, kin, d_count, shift, nb, hist);
   hipLaunchKernelGGL(k_radix_scan_digit, dim3(kRadixBins), dim3(kSortThreads), 0, st, hist, nb, dtot);
-  hipLaunchKernelGGL(k_radix_scatter<V>, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, d_count, shift,
-                     nb, hist, dtot);
+  hipLaunchKernelGGL((k_radix_scatter<V, GATHER>), dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, d_count,
+                     shift, nb, hist, dtot, gather);
 }
 
 // Blocks striding over the window-list chunks (a multiple of kXcds).
@@ -942,14 +980,14 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
                      (uint64_t)UINT32_MAX);
   hipLaunchKernelGGL(k_compact_segments, dim3(p.nb_seg), dim3(kSortThreads), 0, st, seg_ent, proj->vis_count,
                      p.n_seg, part_a, akey, aval, entc);
-  // 2. depth digits (bit 31 of a positive float is 0): four 8-bit passes, ends in (akey, aval)
+  // 2. depth digits (bit 31 of a positive float is 0): four 8-bit passes
   radix_pass<uint32_t>(akey, aval, bkey, bval, d_k, 0, p.nb_vn, hist, dtot, st);
   radix_pass<uint32_t>(bkey, bval, akey, aval, d_k, 8, p.nb_vn, hist, dtot, st);
   radix_pass<uint32_t>(akey, aval, bkey, bval, d_k, 16, p.nb_vn, hist, dtot, st);
-  radix_pass<uint32_t>(bkey, bval, akey, aval, d_k, 24, p.nb_vn, hist, dtot, st);
-  // 3. entry records in depth order, item and incidence counts, overflow check
-  hipLaunchKernelGGL(k_entry_records, dim3(p.grid_steps), dim3(kSortThreads), 0, st, aval, entc, d_k, ent, step_win,
-                     step_tiles);
+  // 3. the last pass carries the entry records (ent[j] = entc[sorted c]); item and incidence counts,
+  //    overflow check
+  radix_pass<uint32_t, true>(bkey, bval, nullptr, ent, d_k, 24, p.nb_vn, hist, dtot, st, entc);
+  hipLaunchKernelGGL(k_step_counts, dim3(p.grid_steps), dim3(kSortThreads), 0, st, ent, d_k, step_win, step_tiles);
   hipLaunchKernelGGL(k_scan_step_counts, dim3(1), dim3(kScanThreads), 0, st, step_win, step_tiles, d_k, d_e, d_m,
                      bins->d_num_pairs, bins->d_overflow, p.cap);
   // 4. (window, item) pairs in depth order, stably sorted on the window index
