@@ -396,10 +396,23 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
     real gS[6] = {0, 0, 0, 0, 0, 0};
     real gop = 0;
     bool any = false;
+    // the views that see the Gaussian (tiles_touched > 0), eight loads in flight at a time
+    uint32_t seen = 0;
+#pragma unroll 1
+    for (int v0 = 0; v0 < a.n_views; v0 += 8) {
+      int32_t t[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t[k] = tiles[(int64_t)min(v0 + k, a.n_views - 1) * a.n + i];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) seen |= (v0 + k < a.n_views && t[k] != 0) ? 1u << (v0 + k) : 0u;
+    }
+    // (the view index stays the same in every lane, so camera data are scalar loads)
 #pragma unroll 1
     for (int v = 0; v < a.n_views; ++v) {
+      const bool sees = (seen >> v) & 1u;
+      if (__ballot(sees) == 0ull) continue;  // no lane's Gaussian is seen by this view
+      if (!sees) continue;                   // culled: no image-space gradient
       const int64_t row = (int64_t)v * a.n + i;
-      if (tiles[row] == 0) continue;  // culled: no image-space gradient
       real g2[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) g2[k] = grad2d[row * 9 + k];

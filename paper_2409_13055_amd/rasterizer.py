@@ -341,6 +341,7 @@ class MappingStep:
         self.adam = FusedAdam(params, self.grads, lrs) if with_adam else None
         self.frame = None
         self.graph = None
+        self._side = None  # stream of the gradient-buffer clear, which overlaps the forward
 
     def size(self):
         """Eager warm-up that sizes the pair capacity (host syncs)."""
@@ -365,6 +366,21 @@ class MappingStep:
         r.bin_sort(fr)
         if mark:
             mark("bin_sort")
+        if self.fuse_adam and mark is None:
+            # The image-space gradient buffer is cleared on a second stream while the forward runs:
+            # the fill is bound by memory bandwidth, the forward by ALU issue.  The previous
+            # iteration's reader of the buffer precedes the fork in stream order.
+            cur = torch.cuda.current_stream()
+            if self._side is None:
+                self._side = torch.cuda.Stream(device=cur.device)
+            self._side.wait_stream(cur)
+            with torch.cuda.stream(self._side):
+                r.grad2d.zero_()
+            r.render_fwd(fr, self.target, self.loss)
+            cur.wait_stream(self._side)
+            r.raster_bwd(fr, r.grad2d, target=self.target)
+            r.project_bwd_adam(self.params, fr, r.grad2d, self.adam)
+            return
         r.render_fwd(fr, self.target, self.loss)
         if mark:
             mark("render_fwd")

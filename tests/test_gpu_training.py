@@ -152,6 +152,32 @@ def test_graph_replays_with_adam_advance_the_step():
         assert d.median().item() < 1e-6
 
 
+def test_gradient_buffer_cleared_on_side_stream_before_the_backward():
+    """The fused step clears the image-space gradient buffer on a second stream while the forward
+    runs.  After every graph replay (and an eager step) the buffer must hold exactly this
+    iteration's raster backward: recomputed from the same frame into a freshly zeroed buffer."""
+    sc = S.make_config(3, n=20_000, res_div=4)
+    p = R.GaussianParams.from_scene(sc, "cuda")
+    step = R.MappingStep(p, sc.cameras, sc.targets, lrs=dict(S.DEFAULT_LRS), tile_size=16)
+    step.size()
+    target = R.pack_images(sc.targets, "cuda")
+    step.capture()
+    for r in range(4):
+        if r == 3:
+            step.run()
+        else:
+            step.replay()
+        x = torch.randn(1 << 20, device="cuda")  # eager work between iterations
+        _ = (x * x).sum().item()
+        torch.cuda.synchronize()
+        got = step.rast.grad2d.clone()
+        ref = torch.zeros_like(got)
+        step.rast.raster_bwd(step.frame, ref, target=target)
+        torch.cuda.synchronize()
+        assert ref.abs().sum().item() > 0
+        assert U.rel_l2(got.cpu().numpy(), ref.cpu().numpy()) <= 1e-5, r
+
+
 def test_fused_projection_backward_adam_equals_separate_calls():
     """gs_project_bwd_adam is gs_project_bwd into zeroed gradients then gs_adam_step, bit for bit, fed
     the same image-space gradients (two steps, so the bias corrections of t = 1 and t = 2 both enter)."""
