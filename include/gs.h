@@ -244,8 +244,10 @@ gs_status gs_project(const gs_params* params, const gs_camera* cams, int32_t n_v
  * (computed in FP32, clamped to the view's grid); the (tile, id) incidences
  * are ordered as documented at gs_bins (a stable LSD radix sort on the
  * 64-bit key, ties broken by ascending v*N+i).  The pairs and their rects are
- * read from proj->vis / proj->vis_count as gs_project wrote them; proj->rec
- * is read for the depths of bins->keys.  `workspace` must hold
+ * read from proj->vis / proj->vis_count as gs_project wrote them, which must
+ * be for the same n, cameras and n_views (their ids number the views of that
+ * call; a sub-batch of views is projected by a call of its own); proj->rec is
+ * read for the depths of bins->keys.  `workspace` must hold
  * gs_bin_sort_workspace_size() bytes for the same arguments. */
 gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n_views,
                       const gs_options* opts, const gs_bins* bins, void* workspace, size_t workspace_bytes,

@@ -111,14 +111,15 @@ __device__ inline int view_of_tile(const ViewTable& vt, int gt) {
 // Tile rectangle of a splat with half-extents (rx, ry): [x0,x1) x [y0,y1),
 // FP32 arithmetic in exactly this order (the bounds must agree bit for bit
 // wherever they are computed).  It covers every pixel within extent - 1 of
-// the mean.
+// the mean.  The tile size B is 8, 16 or 32: 1/B is exact, so multiplying by
+// it rounds exactly as the correctly rounded division by B does.
 __device__ inline void tile_rect(float mx, float my, int rx, int ry, int B, int TX, int TY, int& x0, int& y0, int& x1,
                                  int& y1) {
-  const float ex = (float)rx, ey = (float)ry, fb = (float)B, fb1 = (float)(B - 1);
-  const float ax0 = floorf(__fdiv_rn(__fsub_rn(mx, ex), fb));
-  const float ax1 = floorf(__fdiv_rn(__fadd_rn(__fadd_rn(mx, ex), fb1), fb));
-  const float ay0 = floorf(__fdiv_rn(__fsub_rn(my, ey), fb));
-  const float ay1 = floorf(__fdiv_rn(__fadd_rn(__fadd_rn(my, ey), fb1), fb));
+  const float ex = (float)rx, ey = (float)ry, ib = ldexpf(1.0f, -__builtin_ctz((unsigned)B)), fb1 = (float)(B - 1);
+  const float ax0 = floorf(__fmul_rn(__fsub_rn(mx, ex), ib));
+  const float ax1 = floorf(__fmul_rn(__fadd_rn(__fadd_rn(mx, ex), fb1), ib));
+  const float ay0 = floorf(__fmul_rn(__fsub_rn(my, ey), ib));
+  const float ay1 = floorf(__fmul_rn(__fadd_rn(__fadd_rn(my, ey), fb1), ib));
   x0 = (int)fminf(fmaxf(ax0, 0.0f), (float)TX);
   x1 = (int)fminf(fmaxf(ax1, 0.0f), (float)TX);
   y0 = (int)fminf(fmaxf(ay0, 0.0f), (float)TY);

@@ -30,9 +30,9 @@ struct RasterConsts {
 };
 
 // The per-pixel exponent is power = -(a dx^2 + c dy^2)/2 - b dx dy, d = pixel -
-// mean, evaluated with one fixed rounding sequence (the dx terms are shared by
-// the PPL pixels of a lane's column), so that every kernel takes identical
-// decisions for a pixel.
+// mean, evaluated with one fixed rounding sequence, ((-c/2) dy - b dx) dy +
+// (-a/2) dx^2 (the dx terms are shared by the PPL pixels of a lane's column),
+// so that every kernel takes identical decisions for a pixel.
 struct RowTerms {
   float a2x, nbx;  // -a dx^2 / 2 and -b dx
 };
@@ -42,7 +42,7 @@ __device__ __forceinline__ RowTerms row_terms(float dx, float a2, float nb) {
 }
 __device__ __forceinline__ float splat_power(const RowTerms& t, float c2, float dy) {
 #pragma clang fp contract(off)
-  return fmaf(t.nbx, dy, fmaf(c2 * dy, dy, t.a2x));
+  return fmaf(fmaf(c2, dy, t.nbx), dy, t.a2x);
 }
 
 // Below this exponent opacity * exp(power) < alpha_min is certain: the 1e-3
@@ -192,15 +192,18 @@ struct BlockBoxes {
   float x_lo[PM::WX], x_hi[PM::WX], y_lo[PM::WY], y_hi[PM::WY];
   int all;  // bit w: wavefront w's block holds a pixel of the image
   __device__ explicit BlockBoxes(const PM& pm) {
+    // tile-level values, the same in every lane: scalar registers
+    const int tx0 = __builtin_amdgcn_readfirstlane(pm.tx0), ty0 = __builtin_amdgcn_readfirstlane(pm.ty0);
+    const int W = __builtin_amdgcn_readfirstlane(pm.W), H = __builtin_amdgcn_readfirstlane(pm.H);
 #pragma unroll
     for (int c = 0; c < PM::WX; ++c) {
-      x_lo[c] = (float)(pm.tx0 + c * PM::SUBW);
-      x_hi[c] = (float)(min(pm.tx0 + (c + 1) * PM::SUBW, pm.W) - 1);
+      x_lo[c] = (float)(tx0 + c * PM::SUBW);
+      x_hi[c] = (float)(min(tx0 + (c + 1) * PM::SUBW, W) - 1);
     }
 #pragma unroll
     for (int r = 0; r < PM::WY; ++r) {
-      y_lo[r] = (float)(pm.ty0 + r * PM::SUBH);
-      y_hi[r] = (float)(min(pm.ty0 + (r + 1) * PM::SUBH, pm.H) - 1);
+      y_lo[r] = (float)(ty0 + r * PM::SUBH);
+      y_hi[r] = (float)(min(ty0 + (r + 1) * PM::SUBH, H) - 1);
     }
     all = 0;
 #pragma unroll
@@ -361,7 +364,8 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) __attribute__((amdgpu_
         // only an exponent in [cutoff, 0] can reach alpha_min; the wave skips a pixel slot no lane reaches
         if (!(power >= Bv.z && power <= 0.0f)) continue;
         // the rest is branch-free: a pixel that does not blend gets weight 0, which adds exactly nothing
-        const float alpha = fminf(amax, Bv.y * exp_hw(power));
+        const float oG = Bv.y * exp_hw(power);
+        const float alpha = oG <= amax ? oG : amax;  // min(alpha_max, oG), also for NaN
         const float test = T[p] * (1.0f - alpha);
         const bool keep = alpha >= rc.alpha_min;
         const bool stop = keep && test < rc.t_min;
@@ -463,10 +467,11 @@ __device__ __forceinline__ Red3 reduce_scatter(const Acc9& a) {
 
 // What this lane writes after a reduction: gradient component `comp` (-1:
 // none) = ka * k0 + kc * k2 + k1c * k1, with (ka, kc) = (a, b) for the mean x
-// term, (b, c) for mean y, else (k0c, 0).
+// term, (b, c) for mean y, else (k0c, 0); for the opacity k1c is 1 / opacity
+// (the lanes sum dL/dalpha alpha, which is opacity times dL/dalpha G).
 struct LaneRole {
   int comp;
-  bool mean_x, mean_y;
+  bool mean_x, mean_y, opacity;
   float k0c, k1c;
 };
 __device__ LaneRole wave_roles(int lane) {
@@ -475,13 +480,17 @@ __device__ LaneRole wave_roles(int lane) {
   const Red3 t = reduce_scatter(Acc9{1 * one, 2 * one, 3 * one, 4 * one, 5 * one, 6 * one, 7 * one, 8 * one, 9 * one});
   const int t0 = (int)(t.k0 + 0.5f), t1 = (int)(t.k1 + 0.5f);
   const int r16 = lane & 15;
-  LaneRole rl{-1, false, false, 0.0f, 0.0f};
+  LaneRole rl{-1, false, false, false, 0.0f, 0.0f};
   if (t0 == 1 && r16 == 0) { rl.comp = 0; rl.mean_x = true; }
   else if (t0 == 1 && r16 == 1) { rl.comp = 1; rl.mean_y = true; }
   else if (t0 == 2 && r16 == 0) { rl.comp = 2; rl.k0c = -0.5f; }
   else if (t0 == 3 && r16 == 0) { rl.comp = 3; rl.k0c = -1.0f; }
   else if (t0 == 4 && r16 == 0) { rl.comp = 4; rl.k0c = -0.5f; }
-  else if (r16 == 2 && t1 >= 5 && t1 <= 8) { rl.comp = t1 == 8 ? 5 : t1 + 1; rl.k1c = 1.0f; }  // o -> 5, r,g,b -> 6,7,8
+  else if (r16 == 2 && t1 >= 5 && t1 <= 8) {  // o -> 5, r,g,b -> 6,7,8
+    rl.comp = t1 == 8 ? 5 : t1 + 1;
+    rl.opacity = t1 == 8;
+    rl.k1c = 1.0f;
+  }
   return rl;
 }
 
@@ -561,9 +570,9 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) __attribute__((amdgpu_
         if (!(power >= Bv.z && power <= 0.0f)) continue;
         // the rest is branch-free: a pixel that does not blend gets weight 0 and no exponent
         // gradient, which add exactly nothing (every factor is finite: 1 - alpha >= 1 - alpha_max)
-        const float G = exp_hw(power);
-        const float oG = Bv.y * G;
-        const float alpha = fminf(amax, oG);
+        const float oG = Bv.y * exp_hw(power);
+        const bool below = oG <= amax;
+        const float alpha = below ? oG : amax;  // min(alpha_max, oG), also for NaN
         const float om = 1.0f - alpha;
         const float test = T[p] * om;
         const bool keep = alpha >= rc.alpha_min;
@@ -579,9 +588,9 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) __attribute__((amdgpu_
         Dp[p] = fmaf(-dc, wgt, Dp[p]);  // now dL/dC . S_k, the colour behind this entry
         const float dLda = fmaf(T[p], dc, -Dp[p] * __builtin_amdgcn_rcpf(om));
         T[p] = blend ? test : T[p];
-        const bool unclamped = blend && oG <= amax;  // d alpha / d(o, power) = 0 where clamped
+        const bool unclamped = blend && below;  // d alpha / d(o, power) = 0 where clamped
         const float dLdp = unclamped ? dLda * alpha : 0.0f;
-        acc.o = fmaf(dLda, unclamped ? G : 0.0f, acc.o);
+        acc.o += dLdp;  // dL/do = sum dLda G = (sum dLda alpha) / o
         const float ux = dLdp * dx, uy = dLdp * dy;
         acc.sx += ux;
         acc.sy += uy;
@@ -594,7 +603,8 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) __attribute__((amdgpu_
         const float ca = -2.0f * A.z, cb = -A.w, cc = -2.0f * Bv.x;
         const float ka = role.mean_x ? ca : (role.mean_y ? cb : role.k0c);
         const float kc = role.mean_x ? cb : (role.mean_y ? cc : 0.0f);
-        const float val = fmaf(ka, r.k0, fmaf(kc, r.k2, role.k1c * r.k1));
+        const float k1 = role.opacity ? __builtin_amdgcn_rcpf(Bv.y) : role.k1c;  // a blended entry has opacity >= alpha_min
+        const float val = fmaf(ka, r.k0, fmaf(kc, r.k2, k1 * r.k1));
         if (role.comp >= 0) atomicAdd(grad2d + (size_t)L.id[j] * GS_GRAD2D_FLOATS + role.comp, val);
         acc = Acc9{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       }
@@ -653,7 +663,8 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
         ++evals[p];
         const float power = splat_power(rt, geo.x, fy[p] - cu.y);
         if (power > 0.0f) continue;
-        const float alpha = fminf(amax, geo.y * exp_hw(power));
+        const float oG = geo.y * exp_hw(power);
+        const float alpha = oG <= amax ? oG : amax;  // min(alpha_max, oG), also for NaN
         if (!(alpha >= rc.alpha_min)) continue;
         const float test = T[p] * (1.0f - alpha);
         if (test < rc.t_min) {
