@@ -380,7 +380,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
 // ---------------------------------------------------------------------------
 constexpr int kStepRounds = 8;
 constexpr int kStep = kSortThreads * kStepRounds;  // depth-ordered pairs per block step
-constexpr int kChunkEntries = 512;                 // window-list entries per chunk (one wavefront)
+constexpr int kChunkEntries = 256;                 // window-list entries per chunk (one wavefront)
 constexpr int kChunkGroups = kChunkEntries / kWave;
 constexpr int kChunkWavesPerBlock = kSortThreads / kWave;
 

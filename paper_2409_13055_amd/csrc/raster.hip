@@ -76,30 +76,40 @@ __device__ __forceinline__ float wave_sum(float x) {
   return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
 }
 
+// Wavefront layout of a tile's workgroup: WAVES wavefronts of PPL pixels per lane.
+template <int W, int P>
+struct Shape {
+  static constexpr int WAVES = W, PPL = P, THREADS = 64 * W;
+};
+// Forward and work counts: one 8x8 wave at tile 8, one 16x16 wave of 4 px/lane at tile 16,
+// four 16x16 waves at tile 32.
 template <int TILE>
-struct TileShape;
+struct FwdShape;
 template <>
-struct TileShape<8> {
-  static constexpr int WAVES = 1, PPL = 1;
-};
+struct FwdShape<8> : Shape<1, 1> {};
 template <>
-struct TileShape<16> {
-  static constexpr int WAVES = 1, PPL = 4;
-};
+struct FwdShape<16> : Shape<1, 4> {};
 template <>
-struct TileShape<32> {
-  static constexpr int WAVES = 4, PPL = 4;
-};
+struct FwdShape<32> : Shape<4, 4> {};
+// Backward: at tile 32, two 16x32 waves of 8 px/lane.  A splat that covers the tile is then
+// walked, tested and reduced by two waves instead of four, which halves the per-entry work
+// (about a third of the backward's instructions); the lighter forward loses more to the lower
+// occupancy that eight pixels per lane bring than it gains.  The per-pixel arithmetic does not
+// depend on the layout, so both kernels still decide identically for every pixel.
+template <int TILE>
+struct BwdShape : FwdShape<TILE> {};
+template <>
+struct BwdShape<32> : Shape<2, 8> {};
 
 // Pixel placement inside a tile.  Each wavefront owns a compact SUBW x SUBH
-// block of the tile (8x8 for tile 8; 16x16 for tiles 16 and 32, the latter as
-// a 2x2 arrangement of four waves); lane l owns column l % SUBW of that block
-// and rows l / SUBW + p * RS, p < PPL (RS = SUBH / PPL).  Pixel slot p of the
-// wave is then the band of rows [p RS, (p + 1) RS) of the block, so a splat
-// that misses a band is skipped by the whole wave for that slot.
-template <int TILE>
+// block of the tile (8x8 for tile 8; 16 columns wide otherwise: 16x16 at 4 px/lane,
+// 16x32 at 8 px/lane); lane l owns column l % SUBW of that block and rows
+// l / SUBW + p * RS, p < PPL (RS = SUBH / PPL).  Pixel slot p of the wave is then
+// the band of rows [p RS, (p + 1) RS) of the block, so a splat that misses a band
+// is skipped by the whole wave for that slot.
+template <int TILE, class SHAPE>
 struct PixMap {
-  static constexpr int WAVES = TileShape<TILE>::WAVES, PPL = TileShape<TILE>::PPL, NT = 64 * WAVES;
+  static constexpr int WAVES = SHAPE::WAVES, PPL = SHAPE::PPL, NT = SHAPE::THREADS;
   static constexpr int SUBW = TILE < 16 ? TILE : 16, SUBH = 64 * PPL / SUBW;
   static_assert((TILE / SUBW) * (TILE / SUBH) == WAVES && SUBW * SUBH == 64 * PPL, "tile shape");
   static constexpr int WX = TILE / SUBW, WY = TILE / SUBH;  // wave blocks per tile row / column
@@ -317,11 +327,11 @@ __device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBox
 // STATE: the pixel state (T_final, n_contrib) is written (not under the checkpoint flag).
 // (six wavefronts per SIMD: measured faster than five, despite a few bytes of spill outside the loop)
 template <int TILE, bool STATE>
-__global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) __attribute__((amdgpu_waves_per_eu(6))) void k_render_fwd(
+__global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_render_fwd(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     RasterConsts rc, float* __restrict__ img, float* __restrict__ tfin, int32_t* __restrict__ ncon,
     const float* __restrict__ target, float* __restrict__ tile_loss) {
-  using PM = PixMap<TILE>;
+  using PM = PixMap<TILE, FwdShape<TILE>>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
   __shared__ BatchLds<PM> L;
   __shared__ float s_loss[PM::WAVES];
@@ -502,11 +512,12 @@ __device__ LaneRole wave_roles(int lane) {
 // scalar D_k = dL/dC . S_k, updated by the entry's dL/dC . c_k.
 template <int TILE>
 // (five wavefronts per SIMD: 96 registers, no spill; measured 10% faster than four)
-__global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd(
+__global__ __launch_bounds__(BwdShape<TILE>::THREADS)
+__attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_render_bwd(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     RasterConsts rc, const float* __restrict__ img, int loss_kind, const float* __restrict__ target,
     const float* __restrict__ dl_dimage, float* __restrict__ grad2d) {
-  using PM = PixMap<TILE>;
+  using PM = PixMap<TILE, BwdShape<TILE>>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
   __shared__ BatchLds<PM> L;
   const PM pm(vt, blockIdx.x);
@@ -618,10 +629,10 @@ __global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) __attribute__((amdgpu_
 // and n_contrib; summed over the image into out[0..2] (one 64-bit atomic per
 // wavefront and count).
 template <int TILE>
-__global__ __launch_bounds__(64 * TileShape<TILE>::WAVES) void k_render_stats(
+__global__ __launch_bounds__(FwdShape<TILE>::THREADS) void k_render_stats(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     RasterConsts rc, unsigned long long* __restrict__ out) {
-  using PM = PixMap<TILE>;
+  using PM = PixMap<TILE, FwdShape<TILE>>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
   __shared__ float4 s_a[NT];  // (mean x, mean y, -a/2, -b)
   __shared__ float2 s_b[NT];  // (-c/2, opacity)
@@ -780,9 +791,9 @@ extern "C" gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs
                          rc, out->rgb, tf, nc, tgt, tl);                                                     \
   } while (0)
   switch (opts->tile_size) {
-    case 8: GS_LAUNCH_FWD(8, 64); break;
-    case 16: GS_LAUNCH_FWD(16, 64); break;
-    default: GS_LAUNCH_FWD(32, 256); break;
+    case 8: GS_LAUNCH_FWD(8, FwdShape<8>::THREADS); break;
+    case 16: GS_LAUNCH_FWD(16, FwdShape<16>::THREADS); break;
+    default: GS_LAUNCH_FWD(32, FwdShape<32>::THREADS); break;
   }
 #undef GS_LAUNCH_FWD
   if (want_loss) hipLaunchKernelGGL(k_loss_reduce, dim3(n_views), dim3(256), 0, st, vt, tl, loss->loss_out);
@@ -819,9 +830,9 @@ static void launch_raster_bwd(const ViewTable& vt, const gs_projected* proj, con
   hipLaunchKernelGGL((k_render_bwd<TILE>), grid, dim3(NT), 0, st, vt, proj->rec, bins->ids, rg, rc, img->rgb, \
                      (int)loss->kind, loss->target, loss->dl_dimage, g2)
   switch (opts->tile_size) {
-    case 8: GS_BWD(8, 64); break;
-    case 16: GS_BWD(16, 64); break;
-    default: GS_BWD(32, 256); break;
+    case 8: GS_BWD(8, BwdShape<8>::THREADS); break;
+    case 16: GS_BWD(16, BwdShape<16>::THREADS); break;
+    default: GS_BWD(32, BwdShape<32>::THREADS); break;
   }
 #undef GS_BWD
 }
@@ -894,9 +905,18 @@ extern "C" gs_status gs_render_stats(const gs_projected* proj, int64_t n, const 
   const dim3 grid((unsigned)vt.total_tiles);
   const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
   switch (opts->tile_size) {
-    case 8: hipLaunchKernelGGL(k_render_stats<8>, grid, dim3(64), 0, st, vt, proj->rec, bins->ids, rg, rc, out); break;
-    case 16: hipLaunchKernelGGL(k_render_stats<16>, grid, dim3(64), 0, st, vt, proj->rec, bins->ids, rg, rc, out); break;
-    default: hipLaunchKernelGGL(k_render_stats<32>, grid, dim3(256), 0, st, vt, proj->rec, bins->ids, rg, rc, out); break;
+    case 8:
+      hipLaunchKernelGGL(k_render_stats<8>, grid, dim3(FwdShape<8>::THREADS), 0, st, vt, proj->rec, bins->ids, rg, rc,
+                         out);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_render_stats<16>, grid, dim3(FwdShape<16>::THREADS), 0, st, vt, proj->rec, bins->ids, rg,
+                         rc, out);
+      break;
+    default:
+      hipLaunchKernelGGL(k_render_stats<32>, grid, dim3(FwdShape<32>::THREADS), 0, st, vt, proj->rec, bins->ids, rg,
+                         rc, out);
+      break;
   }
   return check_launch("render stats");
 }
