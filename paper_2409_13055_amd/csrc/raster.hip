@@ -434,11 +434,15 @@ __global__ __launch_bounds__(256) void k_loss_reduce(ViewTable vt, const float* 
 // ---------------------------------------------------------------------------
 // Backward.
 //
-// Per (pixel, entry) the lane accumulates, besides the colour and opacity
-// terms, the moments of u = dL/dpower: sum u dx, sum u dy, sum u dx^2,
-// sum u dx dy, sum u dy^2.  The image-space gradients follow exactly, since
-// the conic is constant per entry: dL/dmean = (a Sx + b Sy, b Sx + c Sy),
-// dL/d(a, b, c) = (-Sxx/2, -Sxy, -Syy/2).  The 9 sums are reduced over the
+// Per entry the wavefront needs, besides the colour terms, the moments of
+// u = dL/dpower over its pixels: Sx = sum u dx, Sy = sum u dy, Sxx = sum u dx^2,
+// Sxy = sum u dx dy, Syy = sum u dy^2.  The image-space gradients follow
+// exactly, since the conic is constant per entry: dL/dmean = (a Sx + b Sy,
+// b Sx + c Sy), dL/d(a, b, c) = (-Sxx/2, -Sxy, -Syy/2).  A lane's pixels share
+// one column, so dx is the same for all of them: the lane sums only U = sum u,
+// Uy = sum u dy and Uyy = sum u dy^2 over its pixels, and its moments are
+// dx U, Uy, dx^2 U, dx Uy, Uyy.  U is also the opacity term: where alpha is not
+// clamped, u = dL/dalpha alpha = o dL/dalpha G, so dL/do = U / o.  The 9 sums are reduced over the
 // wavefront by a reduce-scatter: each permlane32/permlane16 swap adds two
 // different values at once (one per half of the exchanged lanes), leaving
 // three registers whose 16-lane rows each hold one partial sum, which DPP row
@@ -446,6 +450,10 @@ __global__ __launch_bounds__(256) void k_loss_reduce(ViewTable vt, const float* 
 // ---------------------------------------------------------------------------
 struct Acc9 {
   float sx, sxx, sxy, syy, r, g, b, o, sy;
+};
+// A lane's sums over its pixels for the current entry.
+struct Acc6 {
+  float r, g, b, u, uy, uyy;
 };
 struct Red3 {
   float k0, k1, k2;
@@ -554,7 +562,7 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
     }
     Dp[p] = fmaf(dl[p][2], col[2], fmaf(dl[p][1], col[1], dl[p][0] * col[0]));
   }
-  Acc9 acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  Acc6 acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   SplatLoader ld;
   ld.fetch(rec, ids, s + (int)threadIdx.x, s, e);
   for (int base = s; base < e; base += NT) {
@@ -601,23 +609,21 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
         T[p] = blend ? test : T[p];
         const bool unclamped = blend && below;  // d alpha / d(o, power) = 0 where clamped
         const float dLdp = unclamped ? dLda * alpha : 0.0f;
-        acc.o += dLdp;  // dL/do = sum dLda G = (sum dLda alpha) / o
-        const float ux = dLdp * dx, uy = dLdp * dy;
-        acc.sx += ux;
-        acc.sy += uy;
-        acc.sxx = fmaf(ux, dx, acc.sxx);
-        acc.sxy = fmaf(ux, dy, acc.sxy);
-        acc.syy = fmaf(uy, dy, acc.syy);
+        const float uy = dLdp * dy;
+        acc.u += dLdp;
+        acc.uy += uy;
+        acc.uyy = fmaf(uy, dy, acc.uyy);
       }
       if (__ballot(any) != 0ull) {
-        const Red3 r = reduce_scatter(acc);
+        const float sx = dx * acc.u;
+        const Red3 r = reduce_scatter(Acc9{sx, dx * sx, dx * acc.uy, acc.uyy, acc.r, acc.g, acc.b, acc.u, acc.uy});
         const float ca = -2.0f * A.z, cb = -A.w, cc = -2.0f * Bv.x;
         const float ka = role.mean_x ? ca : (role.mean_y ? cb : role.k0c);
         const float kc = role.mean_x ? cb : (role.mean_y ? cc : 0.0f);
         const float k1 = role.opacity ? __builtin_amdgcn_rcpf(Bv.y) : role.k1c;  // a blended entry has opacity >= alpha_min
         const float val = fmaf(ka, r.k0, fmaf(kc, r.k2, k1 * r.k1));
         if (role.comp >= 0) atomicAdd(grad2d + (size_t)L.id[j] * GS_GRAD2D_FLOATS + role.comp, val);
-        acc = Acc9{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        acc = Acc6{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       }
     }
   }
