@@ -29,10 +29,12 @@ struct RasterConsts {
   float radius_sigmas;
 };
 
-// The per-pixel exponent is power = -(a dx^2 + c dy^2)/2 - b dx dy, d = pixel -
-// mean, evaluated with one fixed rounding sequence, ((-c/2) dy - b dx) dy +
-// (-a/2) dx^2 (the dx terms are shared by the PPL pixels of a lane's column),
-// so that every kernel takes identical decisions for a pixel.
+// The per-pixel exponent power = -(a dx^2 + c dy^2)/2 - b dx dy, d = pixel -
+// mean, is evaluated in base 2: the conic is scaled by log2(e) when an entry is
+// staged (kLog2e below), so power2 = log2(e) power and alpha = o exp2(power2)
+// with no multiply per pixel.  One fixed rounding sequence, ((-c'/2) dy - b' dx)
+// dy + (-a'/2) dx^2 with the scaled coefficients (the dx terms shared by the PPL
+// pixels of a lane's column), makes every kernel take identical decisions.
 struct RowTerms {
   float a2x, nbx;  // -a dx^2 / 2 and -b dx
 };
@@ -45,19 +47,17 @@ __device__ __forceinline__ float splat_power(const RowTerms& t, float c2, float 
   return fmaf(fmaf(c2, dy, t.nbx), dy, t.a2x);
 }
 
-// Below this exponent opacity * exp(power) < alpha_min is certain: the 1e-3
-// margin in the exponent covers the rounding of the logarithm, of exp and of
-// the product, so skipping such entries before exp changes no decision.
-// Opacity 0 gives +inf (every entry is skipped), NaN skips every pixel.
+// Below this (natural) exponent opacity * exp(power) < alpha_min is certain:
+// the 1e-3 margin in the exponent covers the rounding of the logarithm, of the
+// base-2 scaling, of exp2 and of the product, so skipping such entries before
+// exp2 changes no decision.  Opacity 0 gives +inf (every entry is skipped), NaN
+// skips every pixel.
 __device__ __forceinline__ float power_cutoff(float opacity, float alpha_min) {
   return __logf(alpha_min / opacity) - 1.0e-3f;
 }
 
-
-__device__ __forceinline__ float exp_hw(float x) {
-#pragma clang fp contract(off)
-  return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
-}
+constexpr float kLog2e = 1.4426950408889634f;  // the staged conic and cutoff are in base 2
+constexpr float kLn2 = 0.6931471805599453f;    // back to natural units (the conic's gradient factors)
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
@@ -148,11 +148,13 @@ struct PixMap {
 // t < 1, inside the rectangle and q(t p) = t^2 q(p) < q(p)).  Along the line x = X, q is the parabola
 // c y^2 + 2 b X y + a X^2 with its minimum at y = -b X / c, clamped to the rectangle, and likewise along
 // y = Y.  Evaluating the line x = clamp(0, x0, x1) and the line y = clamp(0, y0, y1) thus gives two values
-// of q on the rectangle whose smaller is its minimum.  The FP32 rounding of this test and of every pixel's
-// own evaluation is below 1e-6 of |a| dx^2 + 2|b dx dy| + |c| dy^2, bounded over the block by
-// (a + |b|) DX^2 + (c + |b|) DY^2 (DX, DY the largest |dx|, |dy|); a block is skipped only when both values
-// exceed thr by 4e-6 of that bound.  Every pixel of a skipped block then computes an exponent below its
-// cutoff, so the cull changes no result.  A splat with opacity below alpha_min (1 - 1e-3) or NaN can never
+// of q on the rectangle whose smaller is its minimum.  The test is in natural units (thr = -2 cutoff); the
+// pixels evaluate log2(e) times the exponent against log2(e) times the cutoff.  The FP32 rounding of this
+// test and of every pixel's own evaluation, the base-2 scaling included, is below 1e-6 of
+// |a| dx^2 + 2|b dx dy| + |c| dy^2 (which is at least q, so at least thr near the ellipse, and so also covers
+// the rounding of the scaled cutoff), bounded over the block by (a + |b|) DX^2 + (c + |b|) DY^2 (DX, DY the
+// largest |dx|, |dy|); a block is skipped only when both values exceed thr by 4e-6 of that bound.  Every pixel
+// of a skipped block then computes an exponent below its cutoff, so the cull changes no result.  A splat with opacity below alpha_min (1 - 1e-3) or NaN can never
 // blend (its exponent is at most 0) and is listed nowhere; a conic not shown positive definite is listed for
 // every block.
 constexpr float kQErr = 4.0e-6f;
@@ -269,8 +271,8 @@ struct BlockBoxes {
 // the ordered list of the batch entries its pixel block can see.
 template <class PM>
 struct BatchLds {
-  float4 a[PM::NT];  // (mean x, mean y, -a/2, -b) for the conic (a, b, c)
-  float4 b[PM::NT];  // (-c/2, opacity, exponent cutoff, r)
+  float4 a[PM::NT];  // (mean x, mean y, -a'/2, -b') for the conic (a, b, c), ' = times log2(e)
+  float4 b[PM::NT];  // (-c'/2, opacity, exponent cutoff times log2(e), r)
   float2 c[PM::NT];  // (g, b)
   uint32_t id[PM::NT];
   uint16_t list[PM::WAVES][PM::NT];
@@ -289,8 +291,8 @@ __device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBox
   if (ld.valid) {
     const float cut = power_cutoff(ld.b.y, alpha_min);
     mask = bx.mask(ld.a.x, ld.a.y, cull_conic(ld.a.z, ld.a.w, ld.b.x, ld.b.y, alpha_min, -2.0f * cut));
-    L.a[t] = make_float4(ld.a.x, ld.a.y, -0.5f * ld.a.z, -ld.a.w);
-    L.b[t] = make_float4(-0.5f * ld.b.x, ld.b.y, cut, ld.b.z);
+    L.a[t] = make_float4(ld.a.x, ld.a.y, (-0.5f * kLog2e) * ld.a.z, -kLog2e * ld.a.w);
+    L.b[t] = make_float4((-0.5f * kLog2e) * ld.b.x, ld.b.y, kLog2e * cut, ld.b.z);
     L.c[t] = make_float2(ld.b.w, ld.c.x);
     if (with_id) L.id[t] = ld.id;
   }
@@ -374,7 +376,7 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_wave
         // only an exponent in [cutoff, 0] can reach alpha_min; the wave skips a pixel slot no lane reaches
         if (!(power >= Bv.z && power <= 0.0f)) continue;
         // the rest is branch-free: a pixel that does not blend gets weight 0, which adds exactly nothing
-        const float oG = Bv.y * exp_hw(power);
+        const float oG = Bv.y * __builtin_amdgcn_exp2f(power);
         const float alpha = oG <= amax ? oG : amax;  // min(alpha_max, oG), also for NaN
         const float test = T[p] * (1.0f - alpha);
         const bool keep = alpha >= rc.alpha_min;
@@ -589,7 +591,7 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
         if (!(power >= Bv.z && power <= 0.0f)) continue;
         // the rest is branch-free: a pixel that does not blend gets weight 0 and no exponent
         // gradient, which add exactly nothing (every factor is finite: 1 - alpha >= 1 - alpha_max)
-        const float oG = Bv.y * exp_hw(power);
+        const float oG = Bv.y * __builtin_amdgcn_exp2f(power);
         const bool below = oG <= amax;
         const float alpha = below ? oG : amax;  // min(alpha_max, oG), also for NaN
         const float om = 1.0f - alpha;
@@ -617,7 +619,7 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
       if (__ballot(any) != 0ull) {
         const float sx = dx * acc.u;
         const Red3 r = reduce_scatter(Acc9{sx, dx * sx, dx * acc.uy, acc.uyy, acc.r, acc.g, acc.b, acc.u, acc.uy});
-        const float ca = -2.0f * A.z, cb = -A.w, cc = -2.0f * Bv.x;
+        const float ca = (-2.0f * kLn2) * A.z, cb = -kLn2 * A.w, cc = (-2.0f * kLn2) * Bv.x;
         const float ka = role.mean_x ? ca : (role.mean_y ? cb : role.k0c);
         const float kc = role.mean_x ? cb : (role.mean_y ? cc : 0.0f);
         const float k1 = role.opacity ? __builtin_amdgcn_rcpf(Bv.y) : role.k1c;  // a blended entry has opacity >= alpha_min
@@ -640,8 +642,8 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) void k_render_stats(
     RasterConsts rc, unsigned long long* __restrict__ out) {
   using PM = PixMap<TILE, FwdShape<TILE>>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
-  __shared__ float4 s_a[NT];  // (mean x, mean y, -a/2, -b)
-  __shared__ float2 s_b[NT];  // (-c/2, opacity)
+  __shared__ float4 s_a[NT];  // (mean x, mean y, -a'/2, -b'), ' = times log2(e)
+  __shared__ float2 s_b[NT];  // (-c'/2, opacity)
   const PM pm(vt, blockIdx.x);
   const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
   float T[PPL], fy[PPL];
@@ -665,8 +667,8 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) void k_render_stats(
     if (__syncthreads_count(alive) == 0) break;
     ld.fetch(rec, ids, base + (int)threadIdx.x, s, e);
     if (ld.valid) {
-      s_a[threadIdx.x] = make_float4(ld.a.x, ld.a.y, -0.5f * ld.a.z, -ld.a.w);
-      s_b[threadIdx.x] = make_float2(-0.5f * ld.b.x, ld.b.y);
+      s_a[threadIdx.x] = make_float4(ld.a.x, ld.a.y, (-0.5f * kLog2e) * ld.a.z, -kLog2e * ld.a.w);
+      s_b[threadIdx.x] = make_float2((-0.5f * kLog2e) * ld.b.x, ld.b.y);
     }
     __syncthreads();
     const int cnt = min(NT, e - base);
@@ -680,7 +682,7 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) void k_render_stats(
         ++evals[p];
         const float power = splat_power(rt, geo.x, fy[p] - cu.y);
         if (power > 0.0f) continue;
-        const float oG = geo.y * exp_hw(power);
+        const float oG = geo.y * __builtin_amdgcn_exp2f(power);
         const float alpha = oG <= amax ? oG : amax;  // min(alpha_max, oG), also for NaN
         if (!(alpha >= rc.alpha_min)) continue;
         const float test = T[p] * (1.0f - alpha);
