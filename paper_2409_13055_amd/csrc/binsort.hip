@@ -99,7 +99,8 @@ struct alignas(16) Words4 {
 // ---------------------------------------------------------------------------
 // Visible-pair compaction from the projection's segments (64 Gaussians of one
 // view each, in (v*N+i) order): pair c of the concatenation gets a_key[c] =
-// depth bits, a_val[c] = c and entc[c] = its entry record.
+// depth bits and entc[c] = its entry record (the first depth pass takes c itself
+// as the value carried with key c).
 // ---------------------------------------------------------------------------
 constexpr int kCopyBatch = 8;  // segments whose entries a wavefront loads before storing any
 
@@ -141,7 +142,6 @@ __global__ __launch_bounds__(kSortThreads) void k_compact_segments(const uint4* 
                                                                    uint32_t n_seg,
                                                                    const uint64_t* __restrict__ partial,
                                                                    uint32_t* __restrict__ a_key,
-                                                                   uint32_t* __restrict__ a_val,
                                                                    uint4* __restrict__ entc) {
   static_assert(kSortThreads == 256, "the binary search covers 256 prefixes");
   __shared__ uint32_t s_w[kSortThreads / 64];
@@ -170,7 +170,6 @@ __global__ __launch_bounds__(kSortThreads) void k_compact_segments(const uint4* 
       if (i < tot) {
         const uint32_t pos = base + i;
         a_key[pos] = e[k].w;
-        a_val[pos] = pos;
         entc[pos] = make_uint4(e[k].x, e[k].y, e[k].z, e[k].w);
       }
     }
@@ -242,7 +241,8 @@ using CarriedT = typename std::conditional<GATHER, Words4, V>::type;  // in regi
 template <typename V, bool GATHER>
 using StoredT = typename std::conditional<GATHER, uint4, V>::type;  // in memory
 
-template <typename V, bool GATHER = false>
+// IOTA: the values carried in are the keys' own input positions (vin is not read).
+template <typename V, bool GATHER = false, bool IOTA = false>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                                 const V* __restrict__ vin,
                                                                 uint32_t* __restrict__ kout,
@@ -287,7 +287,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
       for (int k = 0; k < kItems; ++k) {
         const uint32_t o = min(o0 + (uint32_t)k * 64, last);
         key[k] = kt[o];
-        val[k] = vt[o];
+        if constexpr (IOTA) {
+          val[k] = (V)(tb + o);
+        } else {
+          val[k] = vt[o];
+        }
       }
       if constexpr (GATHER) {
 #pragma unroll
@@ -517,6 +521,38 @@ __global__ void k_window_bounds(const uint32_t* __restrict__ skey, const uint32_
 }
 
 // cfirst[w] = index of window w's first chunk, cfirst[W] = chunk count (one block).
+// With a single pass over the window index (at most 256 windows) that pass's
+// digit totals are the windows' item counts: their exclusive scan gives every
+// window's run [wbeg, wend) of the sorted items, and a second scan its first
+// chunk, with no pass over the sorted keys (one block).
+__global__ __launch_bounds__(kScanThreads) void k_window_table(const uint32_t* __restrict__ win_count,
+                                                               int n_windows, uint32_t* __restrict__ wbeg,
+                                                               uint32_t* __restrict__ wend,
+                                                               uint32_t* __restrict__ cfirst,
+                                                               uint32_t* __restrict__ d_nchunks) {
+  __shared__ uint32_t s_w[kScanThreads / 64];
+  uint32_t items = 0, chunks = 0;
+  for (int base = 0; base < n_windows; base += kScanThreads) {
+    const int w = base + threadIdx.x;
+    const uint32_t cnt = w < n_windows ? win_count[w] : 0u;
+    const uint32_t nch = (cnt + kChunkEntries - 1) / kChunkEntries;
+    uint32_t ti, tc;
+    const uint32_t ei = block_exclusive_scan<uint32_t, kScanThreads>(cnt, s_w, ti);
+    const uint32_t ec = block_exclusive_scan<uint32_t, kScanThreads>(nch, s_w, tc);
+    if (w < n_windows) {
+      wbeg[w] = items + ei;
+      wend[w] = items + ei + cnt;
+      cfirst[w] = chunks + ec;
+    }
+    items += ti;
+    chunks += tc;
+  }
+  if (threadIdx.x == 0) {
+    cfirst[n_windows] = chunks;
+    *d_nchunks = chunks;
+  }
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_chunk_table(const uint32_t* __restrict__ wbeg,
                                                               const uint32_t* __restrict__ wend, int n_windows,
                                                               uint32_t* __restrict__ cfirst,
@@ -895,13 +931,13 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   return p;
 }
 
-template <typename V, bool GATHER = false>
+template <typename V, bool GATHER = false, bool IOTA = false>
 static void radix_pass(const uint32_t* kin, const V* vin, uint32_t* kout, StoredT<V, GATHER>* vout,
                        const uint32_t* d_count, int shift, int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st,
                        const uint4* gather = nullptr) {
   hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, kin, d_count, shift, nb, hist);
   hipLaunchKernelGGL(k_radix_scan_digit, dim3(kRadixBins), dim3(kSortThreads), 0, st, hist, nb, dtot);
-  hipLaunchKernelGGL((k_radix_scatter<V, GATHER>), dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, d_count,
+  hipLaunchKernelGGL((k_radix_scatter<V, GATHER, IOTA>), dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, d_count,
                      shift, nb, hist, dtot, gather);
 }
 
@@ -979,9 +1015,9 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kSortThreads), 0, st, part_a, p.nb_seg, d_k,
                      (uint64_t)UINT32_MAX);
   hipLaunchKernelGGL(k_compact_segments, dim3(p.nb_seg), dim3(kSortThreads), 0, st, seg_ent, proj->vis_count,
-                     p.n_seg, part_a, akey, aval, entc);
+                     p.n_seg, part_a, akey, entc);
   // 2. depth digits (bit 31 of a positive float is 0): four 8-bit passes
-  radix_pass<uint32_t>(akey, aval, bkey, bval, d_k, 0, p.nb_vn, hist, dtot, st);
+  radix_pass<uint32_t, false, true>(akey, nullptr, bkey, bval, d_k, 0, p.nb_vn, hist, dtot, st);
   radix_pass<uint32_t>(bkey, bval, akey, aval, d_k, 8, p.nb_vn, hist, dtot, st);
   radix_pass<uint32_t>(akey, aval, bkey, bval, d_k, 16, p.nb_vn, hist, dtot, st);
   // 3. the last pass carries the entry records (ent[j] = entc[sorted c]); item and incidence counts,
@@ -999,11 +1035,15 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   const uint32_t* skey = wkey[p.win_passes % 2];
   const uint2* srec = witem[p.win_passes % 2];
   // 5. window runs and their chunks
-  const unsigned fill_grid = (unsigned)std::min<int64_t>(4096, (W + 255) / 256);
-  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, wbeg, (uint64_t)W, 0u);
-  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, wend, (uint64_t)W, 0u);
-  hipLaunchKernelGGL(k_window_bounds, dim3(p.nb_items), dim3(kSortThreads), 0, st, skey, d_e, wbeg, wend);
-  hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(kScanThreads), 0, st, wbeg, wend, W, cfirst, d_nchunks);
+  if (p.win_passes == 1) {
+    hipLaunchKernelGGL(k_window_table, dim3(1), dim3(kScanThreads), 0, st, dtot, W, wbeg, wend, cfirst, d_nchunks);
+  } else {
+    const unsigned fill_grid = (unsigned)std::min<int64_t>(4096, (W + 255) / 256);
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, wbeg, (uint64_t)W, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, wend, (uint64_t)W, 0u);
+    hipLaunchKernelGGL(k_window_bounds, dim3(p.nb_items), dim3(kSortThreads), 0, st, skey, d_e, wbeg, wend);
+    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(kScanThreads), 0, st, wbeg, wend, W, cfirst, d_nchunks);
+  }
   // 6. per-tile counts per chunk, their prefixes over each window's chunks, tile ranges
   hipLaunchKernelGGL(k_chunk_counts, dim3(kChunkGrid), dim3(kSortThreads), 0, st, srec, vt, wbeg, wend, cfirst,
                      d_nchunks, counts);
