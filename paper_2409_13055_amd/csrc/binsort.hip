@@ -685,30 +685,46 @@ __global__ __launch_bounds__(kSortThreads) void k_chunk_counts(const uint2* __re
 // One block per window: the counts of the window's chunks become exclusive
 // prefixes over the chunks (per tile), and the window's tiles get their
 // totals (0 for a window no pair meets).
-__global__ __launch_bounds__(kSortThreads) void k_chunk_scan(const uint32_t* __restrict__ cfirst, ViewTable vt,
-                                                             uint32_t* __restrict__ counts,
-                                                             uint32_t* __restrict__ tile_count) {
-  __shared__ uint32_t s_sum[kChunkWavesPerBlock][kWave];
+constexpr int kChunkScanWaves = 16;  // wavefronts per window in the chunk-count scan
+constexpr int kChunkScanBatch = 8;   // chunks whose counts a wavefront loads before using them
+__global__ __launch_bounds__(kChunkScanWaves * kWave) void k_chunk_scan(const uint32_t* __restrict__ cfirst,
+                                                                       ViewTable vt, uint32_t* __restrict__ counts,
+                                                                       uint32_t* __restrict__ tile_count) {
+  __shared__ uint32_t s_sum[kChunkScanWaves][kWave];
   const uint32_t w = blockIdx.x;
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const uint32_t c0 = cfirst[w], c1 = cfirst[w + 1];
-  const uint32_t per = (c1 - c0 + kChunkWavesPerBlock - 1) / kChunkWavesPerBlock;
+  const uint32_t per = (c1 - c0 + kChunkScanWaves - 1) / kChunkScanWaves;
   const uint32_t a = min(c0 + q * per, c1), z = min(a + per, c1);
+  // (indices clamped into [a, z): every load is in bounds, the extra ones unused)
   uint32_t sum = 0;
-  for (uint32_t c = a; c < z; ++c) sum += counts[(size_t)c * kWave + lane];
+  for (uint32_t cb = a; cb < z; cb += kChunkScanBatch) {
+    uint32_t x[kChunkScanBatch];
+#pragma unroll
+    for (int u = 0; u < kChunkScanBatch; ++u) x[u] = counts[(size_t)min(cb + u, z - 1) * kWave + lane];
+#pragma unroll
+    for (int u = 0; u < kChunkScanBatch; ++u) sum += cb + u < z ? x[u] : 0u;
+  }
   s_sum[q][lane] = sum;
   __syncthreads();
   uint32_t off = 0, total = 0;
 #pragma unroll
-  for (int k = 0; k < kChunkWavesPerBlock; ++k) {
+  for (int k = 0; k < kChunkScanWaves; ++k) {
     const uint32_t s = s_sum[k][lane];
     off += k < q ? s : 0u;
     total += s;
   }
-  for (uint32_t c = a; c < z; ++c) {
-    const uint32_t x = counts[(size_t)c * kWave + lane];
-    counts[(size_t)c * kWave + lane] = off;
-    off += x;
+  for (uint32_t cb = a; cb < z; cb += kChunkScanBatch) {
+    uint32_t x[kChunkScanBatch];
+#pragma unroll
+    for (int u = 0; u < kChunkScanBatch; ++u) x[u] = counts[(size_t)min(cb + u, z - 1) * kWave + lane];
+#pragma unroll
+    for (int u = 0; u < kChunkScanBatch; ++u) {
+      if (cb + u < z) {
+        counts[(size_t)(cb + u) * kWave + lane] = off;
+        off += x[u];
+      }
+    }
   }
   if (q == 0) {
     int v = 0;
@@ -721,9 +737,6 @@ __global__ __launch_bounds__(kSortThreads) void k_chunk_scan(const uint32_t* __r
     if (tx < g.TX && ty < g.TY) tile_count[g.tile_off + ty * g.TX + tx] = total;
   }
 }
-
-// ranges[t] = [start, start + count) with start the exclusive prefix of the
-// tile counts in global tile order, (0,0) for an empty tile.  One block.
 __global__ __launch_bounds__(kScanThreads) void k_ranges_from_counts(int total_tiles,
                                                                       const uint32_t* __restrict__ tile_count,
                                                                       const uint32_t* __restrict__ d_m,
@@ -1047,7 +1060,7 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   // 6. per-tile counts per chunk, their prefixes over each window's chunks, tile ranges
   hipLaunchKernelGGL(k_chunk_counts, dim3(kChunkGrid), dim3(kSortThreads), 0, st, srec, vt, wbeg, wend, cfirst,
                      d_nchunks, counts);
-  hipLaunchKernelGGL(k_chunk_scan, dim3(W), dim3(kSortThreads), 0, st, cfirst, vt, counts, tcount);
+  hipLaunchKernelGGL(k_chunk_scan, dim3(W), dim3(kChunkScanWaves * kWave), 0, st, cfirst, vt, counts, tcount);
   hipLaunchKernelGGL(k_ranges_from_counts, dim3(1), dim3(kScanThreads), 0, st, vt.total_tiles, tcount, d_m,
                      bins->ranges);
   // 7. the incidences, written in place
