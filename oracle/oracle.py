@@ -1,10 +1,10 @@
 """Python face of the FP64 oracle (test infrastructure only).
 
 Wraps liboracle.so (projection, tile binning, per-pixel blending, analytic
-backward, local finite differences) and adds the two steps that are plain
-enough to state in numpy: the L1 term of the photometric loss, eq. (2), and
-the Adam update the paper takes from the default 3DGS optimisation setup
-(Sec. IV-A).
+backward, local finite differences) and adds the steps that are plain enough
+to state in numpy: the photometric loss of eq. (2) (its L1 term, and its SSIM
+term with the analytic gradient), and the Adam update the paper takes from
+the default 3DGS optimisation setup (Sec. IV-A).
 
 Readings of the paper used here (the paper defers the rasteriser to 3DGS,
 Sec. III-B): see the header of oracle.cpp; every threshold is a field of
@@ -312,6 +312,86 @@ def l1_loss_per_view(image_flat, targets, cams):
         out.append(float(np.sum(np.abs(image_flat[off:off + k] - tgt[off:off + k])) / k))
         off += k
     return out
+
+
+# ---------------------------------------------------------------------------
+# The SSIM term of eq. (2).  The paper prints the loss garbled; the reading is
+# (1 - lambda) L1 + lambda (1 - SSIM) with lambda = 0.2 (the 3DGS setup it adopts,
+# Sec. IV-A), SSIM computed as in the 3DGS loss: per channel, an 11 x 11 Gaussian
+# window (sigma 1.5, normalised), zero-padded same-size filtering, C1 = 0.01^2,
+# C2 = 0.03^2, the map averaged over the view's pixels and channels.
+# ---------------------------------------------------------------------------
+SSIM_TAPS = 11
+SSIM_SIGMA = 1.5
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window():
+    """1D Gaussian window: 11 taps, sigma 1.5, normalised to sum 1 (the 2D window is its outer product)."""
+    t = np.arange(SSIM_TAPS, dtype=np.float64) - SSIM_TAPS // 2
+    g = np.exp(-t * t / (2.0 * SSIM_SIGMA * SSIM_SIGMA))
+    return g / g.sum()
+
+
+def ssim_blur(img):
+    """Window-weighted sum around every pixel of img [H, W] (zero outside the image), same size."""
+    g = ssim_window()
+    r = SSIM_TAPS // 2
+    H, W = img.shape
+    pad = np.zeros((H + 2 * r, W + 2 * r))
+    pad[r:r + H, r:r + W] = img
+    rows = sum(g[t] * pad[:, t:t + W] for t in range(SSIM_TAPS))  # along x: [H + 2r, W]
+    return sum(g[t] * rows[t:t + H, :] for t in range(SSIM_TAPS))  # along y: [H, W]
+
+
+def ssim_map(x, y):
+    """SSIM at every pixel of one channel; also returns its partial derivatives with respect to the
+    local statistics of x: A = dS/dmu_x, B = dS/dE[x^2], C = dS/dE[xy] (the y statistics held)."""
+    mx, my = ssim_blur(x), ssim_blur(y)
+    exx, eyy, exy = ssim_blur(x * x), ssim_blur(y * y), ssim_blur(x * y)
+    sxx, syy, sxy = exx - mx * mx, eyy - my * my, exy - mx * my
+    n1, n2 = 2.0 * mx * my + SSIM_C1, 2.0 * sxy + SSIM_C2
+    d1, d2 = mx * mx + my * my + SSIM_C1, sxx + syy + SSIM_C2
+    s = n1 * n2 / (d1 * d2)
+    # chain rule through sxx = E[x^2] - mu_x^2 and sxy = E[xy] - mu_x mu_y
+    a = 2.0 * (my * (n2 - n1) - s * mx * (d2 - d1)) / (d1 * d2)
+    b = -s / d2
+    c = 2.0 * n1 / (d1 * d2)
+    return s, a, b, c
+
+
+def ssim_view(img3, tgt3):
+    """Mean SSIM of one view ([3, H, W] each) and its gradient with respect to img3."""
+    n = img3.size
+    total, grad = 0.0, np.zeros_like(img3, dtype=np.float64)
+    for ch in range(3):
+        x, y = np.asarray(img3[ch], np.float64), np.asarray(tgt3[ch], np.float64)
+        s, a, b, c = ssim_map(x, y)
+        total += s.sum()
+        # mu_x, E[x^2] and E[xy] at pixel p are window sums over x around p: the adjoint of the
+        # zero-padded symmetric window is the same window
+        grad[ch] = (ssim_blur(a) + 2.0 * x * ssim_blur(b) + y * ssim_blur(c)) / n
+    return total / n, grad
+
+
+def photometric_loss(image_flat, targets, cams, lam):
+    """eq. (2) read as (1 - lam) L1 + lam (1 - SSIM) per view, summed over views.
+
+    Returns (per-view losses, dL/dimage) in the packed planar layout of the images."""
+    tgt = pack_views(targets)
+    img = np.asarray(image_flat, np.float64)
+    losses, grad, off = [], np.zeros_like(img), 0
+    for cam in cams:
+        k = 3 * cam.width * cam.height
+        x = img[off:off + k].reshape(3, cam.height, cam.width)
+        y = tgt[off:off + k].reshape(3, cam.height, cam.width)
+        ssim, gs = ssim_view(x, y)
+        d = (x - y).reshape(-1)
+        losses.append((1.0 - lam) * float(np.abs(d).sum()) / k + lam * (1.0 - ssim))
+        grad[off:off + k] = (1.0 - lam) * np.sign(d) / k - lam * gs.reshape(-1)
+        off += k
+    return losses, grad
 
 
 def render_backward(cams, opts: Options, rec, ids, ranges, dl_dimage):

@@ -643,3 +643,96 @@ def test_adam_matches_torch(oracle_lib):
         np.testing.assert_allclose(p, pt.detach().numpy(), rtol=1e-12, atol=1e-15)
         np.testing.assert_allclose(m, st["exp_avg"].numpy(), rtol=1e-12, atol=1e-300)
         np.testing.assert_allclose(v, st["exp_avg_sq"].numpy(), rtol=1e-12, atol=1e-300)
+
+
+# ---------------------------------------------------------------------------
+# SSIM term of eq. (2) (reading: (1 - lambda) L1 + lambda (1 - SSIM), 11 x 11
+# Gaussian window, sigma 1.5, zero padding, C1 = 0.01^2, C2 = 0.03^2)
+# ---------------------------------------------------------------------------
+def brute_window_sums(img, py, px, g):
+    """Explicit 11 x 11 window sum around (py, px), zero outside the image."""
+    H, W = img.shape
+    r = len(g) // 2
+    acc = 0.0
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            y, x = py + dy, px + dx
+            if 0 <= y < H and 0 <= x < W:
+                acc += g[dy + r] * g[dx + r] * img[y, x]
+    return acc
+
+
+def test_ssim_window_closed_form(oracle_lib):
+    O = oracle_lib
+    g = O.ssim_window()
+    assert g.shape == (11,) and abs(g.sum() - 1.0) < 1e-15
+    np.testing.assert_allclose(g, g[::-1], rtol=0, atol=0)
+    # Gaussian: consecutive ratios exp((2k+1)/(2 sigma^2)) away from the centre
+    for k in range(5):
+        assert math.isclose(g[5 - k] / g[4 - k], math.exp((2 * k + 1) / (2 * 1.5 ** 2)), rel_tol=1e-12)
+
+
+def test_ssim_map_matches_brute_force_windows(oracle_lib):
+    O = oracle_lib
+    rng = np.random.default_rng(7)
+    x, y = rng.random((7, 9)), rng.random((7, 9))
+    g = O.ssim_window()
+    s, _, _, _ = O.ssim_map(x, y)
+    for py in range(7):
+        for px in range(9):
+            mx, my = brute_window_sums(x, py, px, g), brute_window_sums(y, py, px, g)
+            sxx = brute_window_sums(x * x, py, px, g) - mx * mx
+            syy = brute_window_sums(y * y, py, px, g) - my * my
+            sxy = brute_window_sums(x * y, py, px, g) - mx * my
+            ref = ((2 * mx * my + 1e-4) * (2 * sxy + 9e-4)) / ((mx * mx + my * my + 1e-4) * (sxx + syy + 9e-4))
+            assert math.isclose(s[py, px], ref, rel_tol=1e-12), (py, px)
+
+
+def test_ssim_identity_symmetry_and_offset_closed_form(oracle_lib):
+    O = oracle_lib
+    rng = np.random.default_rng(3)
+    x, y = rng.random((30, 31)), rng.random((30, 31))
+    s_xx, _, _, _ = O.ssim_map(x, x)
+    np.testing.assert_allclose(s_xx, 1.0, rtol=0, atol=1e-12)
+    s_xy, _, _, _ = O.ssim_map(x, y)
+    s_yx, _, _, _ = O.ssim_map(y, x)
+    np.testing.assert_allclose(s_xy, s_yx, rtol=1e-12)
+    assert s_xy.max() < 1.0
+    # y = x + c: inside the image the two windows see equal variances and covariance, so only the
+    # luminance factor remains, (2 mu (mu + c) + C1) / (mu^2 + (mu + c)^2 + C1)
+    c = 0.3
+    s_off, _, _, _ = O.ssim_map(x, x + c)
+    g = O.ssim_window()
+    for py in range(5, 25, 4):
+        for px in range(5, 26, 5):
+            mu = brute_window_sums(x, py, px, g)
+            ref = (2 * mu * (mu + c) + 1e-4) / (mu * mu + (mu + c) ** 2 + 1e-4)
+            assert math.isclose(s_off[py, px], ref, rel_tol=1e-11), (py, px)
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.2])
+def test_photometric_loss_gradient_matches_central_differences(oracle_lib, lam):
+    O = oracle_lib
+    cams = [S.pinhole(14, 12, 10.0), S.pinhole(9, 8, 7.0)]
+    rng = np.random.default_rng(11)
+    targets = [rng.random((3, c.height, c.width)) for c in cams]
+    img = np.concatenate([rng.random(3 * c.width * c.height) for c in cams])
+    losses, grad = O.photometric_loss(img, targets, cams, lam)
+    h = 1e-6
+    for k in rng.choice(img.size, 40, replace=False):
+        e = np.zeros_like(img)
+        e[k] = h
+        fd = (sum(O.photometric_loss(img + e, targets, cams, lam)[0]) -
+              sum(O.photometric_loss(img - e, targets, cams, lam)[0])) / (2 * h)
+        assert abs(fd - grad[k]) <= 1e-6 * max(1e-3, abs(grad[k])) + 1e-9, (k, fd, grad[k])
+
+
+def test_photometric_loss_without_ssim_is_the_l1_term(oracle_lib):
+    O = oracle_lib
+    cams = [S.pinhole(10, 6, 8.0), S.pinhole(5, 7, 4.0)]
+    rng = np.random.default_rng(2)
+    targets = [rng.random((3, c.height, c.width)) for c in cams]
+    img = np.concatenate([rng.random(3 * c.width * c.height) for c in cams])
+    losses, grad = O.photometric_loss(img, targets, cams, 0.0)
+    np.testing.assert_allclose(losses, O.l1_loss_per_view(img, targets, cams), rtol=1e-14)
+    np.testing.assert_allclose(grad, O.l1_loss(img, targets, cams)[1], rtol=1e-14)
