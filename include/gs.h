@@ -352,6 +352,24 @@ gs_status gs_project_bwd_adam(const gs_params* params, const gs_projected* proj,
                               const gs_adam_group* groups /* host array [6] */, double beta1, double beta2, double eps,
                               int32_t* d_step, void* stream);
 
+/* Photometric loss with its SSIM term (eq. (2); the L1-only loss is
+ * GS_LOSS_L1 inside gs_render_fwd / gs_raster_bwd).  Reading of eq. (2),
+ * printed garbled: per view, loss_v = (1 - lambda) L1_v + lambda (1 - SSIM_v),
+ * L1_v = mean |I - I_gt| and SSIM_v the mean SSIM map over the view's pixels
+ * and 3 channels; SSIM per channel with an 11 x 11 Gaussian window (sigma
+ * 1.5, normalised), zero-padded same-size filtering, C1 = 0.01^2,
+ * C2 = 0.03^2 (3DGS uses lambda = 0.2).  image, target: [sum_v 3 H_v W_v]
+ * FP32, planar per view and packed by view as in gs_image.rgb.  Writes
+ * loss_out[v] (may be NULL) and dl_dimage = d(sum_v loss_v)/d image, same
+ * layout (may be NULL; not both NULL).  dl_dimage feeds gs_raster_bwd /
+ * gs_render_bwd as GS_LOSS_EXTERNAL.  lambda in [0, 1].  `workspace` must
+ * hold gs_photometric_loss_workspace_size() bytes (36 bytes per pixel for the
+ * gradient's intermediate maps). */
+gs_status gs_photometric_loss_workspace_size(const gs_camera* cams, int32_t n_views, size_t* bytes);
+gs_status gs_photometric_loss(const gs_camera* cams, int32_t n_views, const float* image, const float* target,
+                              float lambda, float* loss_out, float* dl_dimage, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,7 +76,8 @@ class gs_adam_group(C.Structure):
 EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_options", "gs_total_tiles",
            "gs_total_pixels", "gs_bin_sort_workspace_size", "gs_render_fwd_workspace_size",
            "gs_render_bwd_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
-           "gs_raster_bwd", "gs_project_bwd", "gs_render_stats", "gs_adam_step", "gs_project_bwd_adam")
+           "gs_raster_bwd", "gs_project_bwd", "gs_render_stats", "gs_adam_step", "gs_project_bwd_adam",
+           "gs_photometric_loss_workspace_size", "gs_photometric_loss")
 
 _lib = None
 
@@ -115,6 +116,8 @@ def load(path: str = LIB_PATH):
         "gs_adam_step": (C.c_int, [C.POINTER(gs_adam_group), i32, C.c_double, C.c_double, C.c_double, P, i32, P]),
         "gs_project_bwd_adam": (C.c_int, [pp, C.POINTER(gs_projected), pc, i32, po, P, C.POINTER(gs_adam_group),
                                           C.c_double, C.c_double, C.c_double, P, P]),
+        "gs_photometric_loss_workspace_size": (C.c_int, [pc, i32, C.POINTER(sz)]),
+        "gs_photometric_loss": (C.c_int, [pc, i32, P, P, C.c_float, P, P, P, sz, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -236,3 +239,15 @@ def gs_project_bwd_adam(params, proj, cams, n_views, opts, grad2d, groups, beta1
     _check("gs_project_bwd_adam", load().gs_project_bwd_adam(C.byref(params), C.byref(proj), cams, n_views,
                                                              C.byref(opts), grad2d, groups, beta1, beta2, eps,
                                                              d_step, stream))
+
+
+def gs_photometric_loss_workspace_size(cams, n_views) -> int:
+    out = C.c_size_t()
+    _check("gs_photometric_loss_workspace_size", load().gs_photometric_loss_workspace_size(cams, n_views,
+                                                                                           C.byref(out)))
+    return out.value
+
+
+def gs_photometric_loss(cams, n_views, image, target, lam, loss_out, dl_dimage, workspace, workspace_bytes, stream):
+    _check("gs_photometric_loss", load().gs_photometric_loss(cams, n_views, image, target, lam, loss_out, dl_dimage,
+                                                             workspace, workspace_bytes, stream))

@@ -287,6 +287,23 @@ def render(rast: Rasterizer, means, log_scales, quats, opacity_logits, sh_dc, sh
     return RasterizeGaussians.apply(rast, means, log_scales, quats, opacity_logits, sh_dc, sh_rest)
 
 
+class PhotometricLoss:
+    """eq. (2) with its SSIM term for a fixed set of keyframes (gs_photometric_loss): per view
+    (1 - lam) L1 + lam (1 - SSIM), and dL/dimage for the raster backward."""
+
+    def __init__(self, cameras, device="cuda"):
+        L.load()
+        self.cams = L.make_cameras(list(cameras))
+        self.n_views = len(cameras)
+        self.ws_bytes = L.gs_photometric_loss_workspace_size(self.cams, self.n_views)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def __call__(self, image: torch.Tensor, target: torch.Tensor, lam: float,
+                 loss_out: Optional[torch.Tensor] = None, dl_dimage: Optional[torch.Tensor] = None):
+        L.gs_photometric_loss(self.cams, self.n_views, _p(image), _p(target), float(lam), _p(loss_out),
+                              _p(dl_dimage), self.ws.data_ptr(), self.ws_bytes, _stream())
+
+
 class FusedAdam:
     """Adam over the six parameter groups in one gs_adam_step launch (step counter on the device)."""
 
@@ -330,8 +347,11 @@ class MappingStep:
     clears them) runs as its own call."""
 
     def __init__(self, params: GaussianParams, cameras, targets, lrs=None, tile_size=16, checkpoint=False,
-                 with_adam=True, fuse_adam=True, **opt):
+                 with_adam=True, fuse_adam=True, ssim_lambda: float = 0.0, **opt):
         self.params = params
+        # eq. (2): with ssim_lambda > 0 the loss is (1 - lambda) L1 + lambda (1 - SSIM) (3DGS: 0.2),
+        # computed by gs_photometric_loss after the forward; 0 keeps the L1 term fused into the forward
+        self.ssim_lambda = float(ssim_lambda)
         self.fuse_adam = with_adam and fuse_adam
         self.rast = Rasterizer(cameras, params.n, params.sh_degree, tile_size=tile_size, checkpoint=checkpoint,
                                device=params.means.device, **opt)
@@ -339,6 +359,11 @@ class MappingStep:
         self.target = targets if isinstance(targets, torch.Tensor) else pack_images(targets, params.means.device)
         self.loss = torch.zeros(self.rast.n_views, dtype=torch.float32, device=params.means.device)
         self.adam = FusedAdam(params, self.grads, lrs) if with_adam else None
+        self.photometric = None
+        self.dl_dimage = None
+        if self.ssim_lambda > 0.0:
+            self.photometric = PhotometricLoss(cameras, device=params.means.device)
+            self.dl_dimage = torch.empty(3 * self.rast.total_pixels, dtype=torch.float32, device=params.means.device)
         self.frame = None
         self.graph = None
         self._side = None  # stream of the gradient-buffer clear, which overlaps the forward
@@ -350,6 +375,24 @@ class MappingStep:
         self.rast.bin_sort(fr)
         self.rast.fit_capacity(fr)
         self.frame = fr
+
+    def _forward(self, fr, mark=None):
+        """Forward raster and the loss: L1 fused into the forward, or eq. (2) with SSIM after it."""
+        r = self.rast
+        if self.photometric is None:
+            r.render_fwd(fr, self.target, self.loss)
+            if mark:
+                mark("render_fwd")
+            return
+        r.render_fwd(fr)
+        if mark:
+            mark("render_fwd")
+        self.photometric(fr.rgb, self.target, self.ssim_lambda, self.loss, self.dl_dimage)
+        if mark:
+            mark("photometric_loss")
+
+    def _loss_args(self):
+        return dict(target=self.target) if self.photometric is None else dict(dl_dimage=self.dl_dimage)
 
     def run(self, mark=None):
         """Enqueue one iteration (no host synchronisation).
@@ -376,20 +419,18 @@ class MappingStep:
             self._side.wait_stream(cur)
             with torch.cuda.stream(self._side):
                 r.grad2d.zero_()
-            r.render_fwd(fr, self.target, self.loss)
+            self._forward(fr)
             cur.wait_stream(self._side)
-            r.raster_bwd(fr, r.grad2d, target=self.target)
+            r.raster_bwd(fr, r.grad2d, **self._loss_args())
             r.project_bwd_adam(self.params, fr, r.grad2d, self.adam)
             return
-        r.render_fwd(fr, self.target, self.loss)
-        if mark:
-            mark("render_fwd")
+        self._forward(fr, mark)
         if self.fuse_adam:
             g2 = r.grad2d
             g2.zero_()
             if mark:
                 mark("clear_grad2d")
-            r.raster_bwd(fr, g2, target=self.target)
+            r.raster_bwd(fr, g2, **self._loss_args())
             if mark:
                 mark("raster_bwd")
             r.project_bwd_adam(self.params, fr, g2, self.adam)
@@ -397,12 +438,12 @@ class MappingStep:
                 mark("project_bwd_adam")
             return
         if mark is None:
-            r.render_bwd(self.params, fr, self.grads, target=self.target)
+            r.render_bwd(self.params, fr, self.grads, **self._loss_args())
         else:
             g2 = r.grad2d
             g2.zero_()
             mark("clear_grad2d")
-            r.raster_bwd(fr, g2, target=self.target)
+            r.raster_bwd(fr, g2, **self._loss_args())
             mark("raster_bwd")
             r.project_bwd(self.params, fr, g2, self.grads)
             mark("project_bwd")

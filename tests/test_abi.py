@@ -114,6 +114,19 @@ def test_invalid_arguments_are_rejected_before_any_launch(L):
     six[1].param = C.c_void_p(0x2100)
     with pytest.raises(L.GsError, match="params array"):
         L.gs_project_bwd_adam(fp, fproj, cc, 1, o, C.c_void_p(0x7000), six, 0.9, 0.999, 1e-15, C.c_void_p(16), None)
+    # the photometric loss validates its arguments before enqueuing anything
+    c2 = L.make_cameras([S.pinhole(64, 48, 50.0), S.pinhole(30, 20, 20.0)])
+    wsb = L.gs_photometric_loss_workspace_size(c2, 2)
+    assert wsb >= 36 * (64 * 48 + 30 * 20)
+    img, tgt, dl, lo = C.c_void_p(0x1000), C.c_void_p(0x2000), C.c_void_p(0x3000), C.c_void_p(0x4000)
+    with pytest.raises(L.GsError, match="image and target"):
+        L.gs_photometric_loss(c2, 2, None, tgt, 0.2, lo, dl, C.c_void_p(0x5000), wsb, None)
+    with pytest.raises(L.GsError, match="lambda"):
+        L.gs_photometric_loss(c2, 2, img, tgt, 1.5, lo, dl, C.c_void_p(0x5000), wsb, None)
+    with pytest.raises(L.GsError, match="nothing to compute"):
+        L.gs_photometric_loss(c2, 2, img, tgt, 0.2, None, None, C.c_void_p(0x5000), wsb, None)
+    with pytest.raises(L.GsError, match="CAPACITY"):
+        L.gs_photometric_loss(c2, 2, img, tgt, 0.2, lo, dl, C.c_void_p(0x5000), wsb - 1, None)
     lib = L.load()
     assert lib.gs_status_string(3) == b"GS_ERR_CAPACITY"
-    assert b"params array" in lib.gs_last_error()
+    assert b"workspace too small" in lib.gs_last_error()
