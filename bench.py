@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-ssim", action="store_true", help="skip the measurement of eq. (2) with its SSIM term")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many eager batched steps (for rocprofv3) and exit")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -178,6 +179,45 @@ def main():
         log(f"[bench] per-view: {ms_pv:.3f} ms/step ({per_view['batched_speedup']}x slower than batched)")
         del pv
 
+    ssim = None
+    if not args.no_ssim:
+        # eq. (2) with its SSIM term (lambda 0.2, the 3DGS setup): the same iteration with
+        # gs_photometric_loss after the forward (not part of `value`: the workload's loss is L1),
+        # and the loss call on its own
+        lam = 0.2
+        st = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
+                           with_adam=with_adam, ssim_lambda=lam)
+        st.size()
+        if use_graph:
+            st.capture()
+        run_s = st.replay if use_graph else st.run
+        reset(st)
+        for _ in range(args.warmup):
+            run_s()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            run_s()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_s = e0.elapsed_time(e1) / args.steps
+        for _ in range(args.warmup):
+            st.photometric(st.frame.rgb, st.target, lam, st.loss, st.dl_dimage)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            st.photometric(st.frame.rgb, st.target, lam, st.loss, st.dl_dimage)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_l = e0.elapsed_time(e1) / args.steps
+        alg = 36 * sc.total_pixels  # image and target read, dL/dimage written: 12 bytes per pixel each
+        gbs = alg / (ms_l * 1e-3) / 1e9
+        ssim = {"lambda": lam, "ms_per_step": round(ms_s, 4), "value": round(mpix / (ms_s * 1e-3), 2),
+                "loss_call_ms": round(ms_l, 4), "loss_alg_bytes": alg, "loss_GBps": round(gbs, 1),
+                "loss_hbm_frac": round(gbs / 8000.0, 4)}
+        log(f"[bench] with SSIM (lambda {lam}): {ms_s:.3f} ms/step; loss call {ms_l:.3f} ms ({gbs:.0f} GB/s alg)")
+        del st
+
     roof = roofline(step, sc, stages, work)
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, tile)
     out = {
@@ -199,6 +239,7 @@ def main():
         "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "peak_hbm_bytes": peak_hbm,
         "per_view": per_view,
+        "ssim": ssim,
         "stages_ms": stages,
         "roofline": roof,
         "cpu_baseline": cpu,

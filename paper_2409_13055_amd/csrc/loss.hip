@@ -97,13 +97,43 @@ __device__ inline LossTile loss_tile(const LossViews& lv, int b) {
   return t;
 }
 
-// The tile's input rectangle of one channel plane (with the halo, zero outside the image) into LDS.
-__device__ inline void load_halo(const float* __restrict__ plane, const LossTile& t, float (*dst)[kLossInW]) {
-  for (int i = threadIdx.x; i < kLossInH * kLossInW; i += kLossThreads) {
-    const int r = i / kLossInW, c = i % kLossInW;
-    const int y = t.y0 + r - kSsimR, x = t.x0 + c - kSsimR;
-    dst[r][c] = (y >= 0 && y < t.H && x >= 0 && x < t.W) ? plane[(size_t)y * t.W + x] : 0.0f;
+// The tile's input rectangle (with the halo, zero outside the image) of NMAP channel planes, read
+// into registers (every load issued before any is used: the next channel's planes are in flight
+// while the current one is filtered) and then stored to LDS.
+constexpr int kHaloPerThread = (kLossInH * kLossInW + kLossThreads - 1) / kLossThreads;
+template <int NMAP>
+struct Halo {
+  float v[NMAP][kHaloPerThread];
+  __device__ inline void fetch(const float* const (&planes)[NMAP], const LossTile& t) {
+    int at[kHaloPerThread];
+#pragma unroll
+    for (int k = 0; k < kHaloPerThread; ++k) {
+      const int i = threadIdx.x + k * kLossThreads;
+      const int r = i / kLossInW, c = i % kLossInW;
+      const int y = t.y0 + r - kSsimR, x = t.x0 + c - kSsimR;
+      const bool in = i < kLossInH * kLossInW && y >= 0 && y < t.H && x >= 0 && x < t.W;
+      at[k] = in ? y * t.W + x : -1;
+    }
+#pragma unroll
+    for (int m = 0; m < NMAP; ++m)
+#pragma unroll
+      for (int k = 0; k < kHaloPerThread; ++k) v[m][k] = at[k] >= 0 ? planes[m][at[k]] : 0.0f;
   }
+  __device__ inline void put(float (*const (&dst)[NMAP])[kLossInW]) const {
+#pragma unroll
+    for (int k = 0; k < kHaloPerThread; ++k) {
+      const int i = threadIdx.x + k * kLossThreads;
+      if (i < kLossInH * kLossInW) {
+        const int r = i / kLossInW, c = i % kLossInW;
+#pragma unroll
+        for (int m = 0; m < NMAP; ++m) dst[m][r][c] = v[m][k];
+      }
+    }
+  }
+};
+
+__device__ inline size_t plane_of(const LossTile& t, int ch) {
+  return (size_t)(3 * t.pix) + (size_t)ch * t.W * t.H;
 }
 
 __device__ inline float block_sum(float x, float* s_w) {
@@ -117,6 +147,37 @@ __device__ inline float block_sum(float x, float* s_w) {
   return t;
 }
 
+// Filtering through LDS: a thread takes two adjacent columns of a row in the row pass (its 12 inputs
+// read once, as 8-byte pairs) and four consecutive rows of a column in the column pass (its 14
+// inputs read once), instead of one LDS read per tap.
+constexpr int kColPairs = kLossTW / 2;
+constexpr int kRowRun = kLossPerThread;  // consecutive output rows per thread
+static_assert(kLossTH == kRowRun * (kLossThreads / kLossTW), "column-pass rows");
+
+__device__ inline void read_run12(const float* row, int c, float (&v)[kSsimTaps + 1]) {
+#pragma unroll
+  for (int m = 0; m < (kSsimTaps + 1) / 2; ++m) {
+    const float2 p = *reinterpret_cast<const float2*>(row + c + 2 * m);
+    v[2 * m] = p.x;
+    v[2 * m + 1] = p.y;
+  }
+}
+
+// Window sum down column `col` at output rows r0 .. r0 + kRowRun - 1 of one row-summed map.
+__device__ inline void column_run(const float (*h)[kLossTW], int r0, int col, const SsimConsts& k,
+                                  float (&out)[kRowRun]) {
+  float v[kRowRun + kSsimTaps - 1];
+#pragma unroll
+  for (int q = 0; q < kRowRun + kSsimTaps - 1; ++q) v[q] = h[r0 + q][col];
+#pragma unroll
+  for (int p = 0; p < kRowRun; ++p) {
+    float a = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kSsimTaps; ++q) a = fmaf(k.g[q], v[p + q], a);
+    out[p] = a;
+  }
+}
+
 // Forward: per tile and channel, the five window sums, the SSIM map and its partials A, B, C
 // (written for the backward), and the tile's sums of S and |x - y| (in a fixed order).
 __global__ __launch_bounds__(kLossThreads) void k_ssim_fwd(LossViews lv, SsimConsts k,
@@ -124,51 +185,63 @@ __global__ __launch_bounds__(kLossThreads) void k_ssim_fwd(LossViews lv, SsimCon
                                                            const float* __restrict__ tgt,
                                                            float* __restrict__ ma, float* __restrict__ mb,
                                                            float* __restrict__ mc, float2* __restrict__ tile_part) {
-  __shared__ float s_x[kLossInH][kLossInW], s_y[kLossInH][kLossInW];
-  __shared__ float s_h[5][kLossInH][kLossTW];  // row sums of x, y, x^2, y^2, xy
+  __shared__ __align__(16) float s_x[kLossInH][kLossInW];
+  __shared__ __align__(16) float s_y[kLossInH][kLossInW];
+  __shared__ __align__(16) float s_h[5][kLossInH][kLossTW];  // row sums of x, y, x^2, y^2, xy
   __shared__ float s_w[kLossThreads / 64];
   const LossTile t = loss_tile(lv, blockIdx.x);
-  const int col = threadIdx.x % kLossTW, row0 = threadIdx.x / kLossTW;
-  constexpr int kRowStep = kLossThreads / kLossTW;
+  const int col = threadIdx.x % kLossTW, row0 = (threadIdx.x / kLossTW) * kRowRun;
   const bool want_grad = ma != nullptr;
   float ssum = 0.0f, l1sum = 0.0f;
+  float (*const dst[2])[kLossInW] = {s_x, s_y};
+  Halo<2> halo;
+  {
+    const float* const src[2] = {img + plane_of(t, 0), tgt + plane_of(t, 0)};
+    halo.fetch(src, t);
+  }
   for (int ch = 0; ch < 3; ++ch) {
-    const size_t plane = (size_t)(3 * t.pix) + (size_t)ch * t.W * t.H;
-    load_halo(img + plane, t, s_x);
-    load_halo(tgt + plane, t, s_y);
+    const size_t plane = plane_of(t, ch);
+    halo.put(dst);
     __syncthreads();
-    for (int i = threadIdx.x; i < kLossInH * kLossTW; i += kLossThreads) {
-      const int r = i / kLossTW, c = i % kLossTW;
-      float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, a4 = 0.0f;
+    if (ch + 1 < 3) {
+      const float* const src[2] = {img + plane_of(t, ch + 1), tgt + plane_of(t, ch + 1)};
+      halo.fetch(src, t);
+    }
+    for (int i = threadIdx.x; i < kLossInH * kColPairs; i += kLossThreads) {
+      const int r = i / kColPairs, c = 2 * (i % kColPairs);
+      float xv[kSsimTaps + 1], yv[kSsimTaps + 1];
+      read_run12(s_x[r], c, xv);
+      read_run12(s_y[r], c, yv);
 #pragma unroll
-      for (int q = 0; q < kSsimTaps; ++q) {
-        const float x = s_x[r][c + q], y = s_y[r][c + q], w = k.g[q];
-        a0 = fmaf(w, x, a0);
-        a1 = fmaf(w, y, a1);
-        a2 = fmaf(w * x, x, a2);
-        a3 = fmaf(w * y, y, a3);
-        a4 = fmaf(w * x, y, a4);
+      for (int u = 0; u < 2; ++u) {
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, a4 = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kSsimTaps; ++q) {
+          const float x = xv[u + q], y = yv[u + q], w = k.g[q], wx = w * x;
+          a0 = fmaf(w, x, a0);
+          a1 = fmaf(w, y, a1);
+          a2 = fmaf(wx, x, a2);
+          a3 = fmaf(w * y, y, a3);
+          a4 = fmaf(wx, y, a4);
+        }
+        s_h[0][r][c + u] = a0;
+        s_h[1][r][c + u] = a1;
+        s_h[2][r][c + u] = a2;
+        s_h[3][r][c + u] = a3;
+        s_h[4][r][c + u] = a4;
       }
-      s_h[0][r][c] = a0;
-      s_h[1][r][c] = a1;
-      s_h[2][r][c] = a2;
-      s_h[3][r][c] = a3;
-      s_h[4][r][c] = a4;
     }
     __syncthreads();
+    float smx[kRowRun], smy[kRowRun], sexx[kRowRun], seyy[kRowRun], sexy[kRowRun];
+    column_run(s_h[0], row0, col, k, smx);
+    column_run(s_h[1], row0, col, k, smy);
+    column_run(s_h[2], row0, col, k, sexx);
+    column_run(s_h[3], row0, col, k, seyy);
+    column_run(s_h[4], row0, col, k, sexy);
 #pragma unroll
-    for (int p = 0; p < kLossPerThread; ++p) {
-      const int r = row0 + p * kRowStep;
-      float mx = 0.0f, my = 0.0f, exx = 0.0f, eyy = 0.0f, exy = 0.0f;
-#pragma unroll
-      for (int q = 0; q < kSsimTaps; ++q) {
-        const float w = k.g[q];
-        mx = fmaf(w, s_h[0][r + q][col], mx);
-        my = fmaf(w, s_h[1][r + q][col], my);
-        exx = fmaf(w, s_h[2][r + q][col], exx);
-        eyy = fmaf(w, s_h[3][r + q][col], eyy);
-        exy = fmaf(w, s_h[4][r + q][col], exy);
-      }
+    for (int p = 0; p < kRowRun; ++p) {
+      const int r = row0 + p;
+      const float mx = smx[p], my = smy[p], exx = sexx[p], eyy = seyy[p], exy = sexy[p];
       const int y = t.y0 + r, x = t.x0 + col;
       if (y >= t.H || x >= t.W) continue;
       const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
@@ -201,45 +274,53 @@ __global__ __launch_bounds__(kLossThreads) void k_ssim_bwd(LossViews lv, SsimCon
                                                            const float* __restrict__ mb,
                                                            const float* __restrict__ mc,
                                                            float* __restrict__ dl) {
-  __shared__ float s_m[3][kLossInH][kLossInW];
-  __shared__ float s_h[3][kLossInH][kLossTW];
+  __shared__ __align__(16) float s_m[3][kLossInH][kLossInW];
+  __shared__ __align__(16) float s_h[3][kLossInH][kLossTW];
   const LossTile t = loss_tile(lv, blockIdx.x);
-  const int col = threadIdx.x % kLossTW, row0 = threadIdx.x / kLossTW;
-  constexpr int kRowStep = kLossThreads / kLossTW;
+  const int col = threadIdx.x % kLossTW, row0 = (threadIdx.x / kLossTW) * kRowRun;
   const float inv_n = 1.0f / (3.0f * (float)t.W * (float)t.H);
   const float w_l1 = (1.0f - k.lam) * inv_n, w_s = k.lam * inv_n;
+  float (*const dst[3])[kLossInW] = {s_m[0], s_m[1], s_m[2]};
+  Halo<3> halo;
+  {
+    const size_t p0 = plane_of(t, 0);
+    const float* const src[3] = {ma + p0, mb + p0, mc + p0};
+    halo.fetch(src, t);
+  }
   for (int ch = 0; ch < 3; ++ch) {
-    const size_t plane = (size_t)(3 * t.pix) + (size_t)ch * t.W * t.H;
-    load_halo(ma + plane, t, s_m[0]);
-    load_halo(mb + plane, t, s_m[1]);
-    load_halo(mc + plane, t, s_m[2]);
+    const size_t plane = plane_of(t, ch);
+    halo.put(dst);
     __syncthreads();
-    for (int i = threadIdx.x; i < kLossInH * kLossTW; i += kLossThreads) {
-      const int r = i / kLossTW, c = i % kLossTW;
-      float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    if (ch + 1 < 3) {
+      const size_t pn = plane_of(t, ch + 1);
+      const float* const src[3] = {ma + pn, mb + pn, mc + pn};
+      halo.fetch(src, t);
+    }
+    for (int i = threadIdx.x; i < kLossInH * kColPairs; i += kLossThreads) {
+      const int r = i / kColPairs, c = 2 * (i % kColPairs);
 #pragma unroll
-      for (int q = 0; q < kSsimTaps; ++q) {
-        const float w = k.g[q];
-        a0 = fmaf(w, s_m[0][r][c + q], a0);
-        a1 = fmaf(w, s_m[1][r][c + q], a1);
-        a2 = fmaf(w, s_m[2][r][c + q], a2);
+      for (int m = 0; m < 3; ++m) {
+        float v[kSsimTaps + 1];
+        read_run12(s_m[m][r], c, v);
+        float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kSsimTaps; ++q) {
+          a0 = fmaf(k.g[q], v[q], a0);
+          a1 = fmaf(k.g[q], v[q + 1], a1);
+        }
+        s_h[m][r][c] = a0;
+        s_h[m][r][c + 1] = a1;
       }
-      s_h[0][r][c] = a0;
-      s_h[1][r][c] = a1;
-      s_h[2][r][c] = a2;
     }
     __syncthreads();
+    float sga[kRowRun], sgb[kRowRun], sgc[kRowRun];
+    column_run(s_h[0], row0, col, k, sga);
+    column_run(s_h[1], row0, col, k, sgb);
+    column_run(s_h[2], row0, col, k, sgc);
 #pragma unroll
-    for (int p = 0; p < kLossPerThread; ++p) {
-      const int r = row0 + p * kRowStep;
-      float ga = 0.0f, gb = 0.0f, gc = 0.0f;
-#pragma unroll
-      for (int q = 0; q < kSsimTaps; ++q) {
-        const float w = k.g[q];
-        ga = fmaf(w, s_h[0][r + q][col], ga);
-        gb = fmaf(w, s_h[1][r + q][col], gb);
-        gc = fmaf(w, s_h[2][r + q][col], gc);
-      }
+    for (int p = 0; p < kRowRun; ++p) {
+      const int r = row0 + p;
+      const float ga = sga[p], gb = sgb[p], gc = sgc[p];
       const int y = t.y0 + r, x = t.x0 + col;
       if (y >= t.H || x >= t.W) continue;
       const size_t o = plane + (size_t)y * t.W + x;
