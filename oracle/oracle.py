@@ -3,8 +3,10 @@
 Wraps liboracle.so (projection, tile binning, per-pixel blending, analytic
 backward, local finite differences) and adds the steps that are plain enough
 to state in numpy: the photometric loss of eq. (2) (its L1 term, and its SSIM
-term with the analytic gradient), and the Adam update the paper takes from
-the default 3DGS optimisation setup (Sec. IV-A).
+term with the analytic gradient), the Adam update the paper takes from
+the default 3DGS optimisation setup (Sec. IV-A), and one level of the
+Gaussian pyramid of ground-truth images used for coarse-to-fine training
+(Sec. IV-A) with the camera that samples it.
 
 Readings of the paper used here (the paper defers the rasteriser to 3DGS,
 Sec. III-B): see the header of oracle.cpp; every threshold is a field of
@@ -392,6 +394,48 @@ def photometric_loss(image_flat, targets, cams, lam):
         grad[off:off + k] = (1.0 - lam) * np.sign(d) / k - lam * gs.reshape(-1)
         off += k
     return losses, grad
+
+
+# ---------------------------------------------------------------------------
+# Gaussian-pyramid training (Sec. IV-A, after Photo-SLAM): the ground-truth image
+# repeatedly smoothed and down-sampled, coarse levels used first.  Reading: one
+# level is the REDUCE step of Burt and Adelson's Gaussian pyramid, the separable
+# binomial window (1, 4, 6, 4, 1)/16 centred on every second pixel, output size
+# ceil(W/2) x ceil(H/2), the border reflected without repeating the edge pixel
+# (index -1 reads 1, index W reads W - 2).  A level's camera samples output pixel
+# x' at input index 2 x', so in index coordinates u' = u / 2: fx' = fx / 2,
+# cx' = cx / 2 + 1/4 (a point projects to fx x/z + cx - 1/2), likewise in y.
+# ---------------------------------------------------------------------------
+PYR_TAPS = np.array([1.0, 4.0, 6.0, 4.0, 1.0]) / 16.0
+
+
+def _reflect(i, n):
+    """Index i reflected into [0, n) without repeating the edge sample."""
+    if n == 1:
+        return 0
+    period = 2 * (n - 1)
+    i = abs(i) % period
+    return period - i if i >= n else i
+
+
+def pyramid_reduce(img):
+    """One pyramid level of img [C, H, W] (FP64): [C, ceil(H/2), ceil(W/2)]."""
+    img = np.asarray(img, np.float64)
+    C, H, W = img.shape
+    H2, W2 = (H + 1) // 2, (W + 1) // 2
+    xs = np.array([[_reflect(2 * x + k - 2, W) for k in range(5)] for x in range(W2)])  # [W2, 5]
+    ys = np.array([[_reflect(2 * y + k - 2, H) for k in range(5)] for y in range(H2)])  # [H2, 5]
+    rows = np.einsum("k,chxk->chx", PYR_TAPS, img[:, :, xs])                            # [C, H, W2]
+    return np.einsum("k,cyxk->cyx", PYR_TAPS, rows[:, ys, :].transpose(0, 1, 3, 2))      # [C, H2, W2]
+
+
+def pyramid_camera(cam, levels=1):
+    """The camera that samples `levels` REDUCE steps of cam's image."""
+    for _ in range(levels):
+        cam = dataclasses.replace(cam, fx=cam.fx / 2.0, fy=cam.fy / 2.0, cx=cam.cx / 2.0 + 0.25,
+                                  cy=cam.cy / 2.0 + 0.25, width=(cam.width + 1) // 2,
+                                  height=(cam.height + 1) // 2)
+    return cam
 
 
 def render_backward(cams, opts: Options, rec, ids, ranges, dl_dimage):

@@ -736,3 +736,97 @@ def test_photometric_loss_without_ssim_is_the_l1_term(oracle_lib):
     losses, grad = O.photometric_loss(img, targets, cams, 0.0)
     np.testing.assert_allclose(losses, O.l1_loss_per_view(img, targets, cams), rtol=1e-14)
     np.testing.assert_allclose(grad, O.l1_loss(img, targets, cams)[1], rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Gaussian pyramid of the ground-truth images (Sec. IV-A): one REDUCE level
+# ---------------------------------------------------------------------------
+def test_pyramid_taps_are_the_binomial_window(oracle_lib):
+    O = oracle_lib
+    # four box filters of width 2 convolved: the binomial (1, 4, 6, 4, 1) / 16
+    w = np.array([1.0])
+    for _ in range(4):
+        w = np.convolve(w, [0.5, 0.5])
+    np.testing.assert_allclose(O.PYR_TAPS, w, rtol=0, atol=0)
+
+
+def test_pyramid_reduce_matches_padded_brute_force(oracle_lib):
+    O = oracle_lib
+    rng = np.random.default_rng(4)
+    w = np.convolve([1.0, 2.0, 1.0], [1.0, 2.0, 1.0]) / 16.0
+    for H, W in [(9, 13), (8, 6), (5, 4), (3, 3), (2, 7), (1, 5)]:
+        img = rng.random((2, H, W))
+        got = O.pyramid_reduce(img)
+        assert got.shape == (2, (H + 1) // 2, (W + 1) // 2)
+        # numpy's "reflect" padding mirrors about the edge sample without repeating it (and keeps a
+        # one-pixel axis constant)
+        pad = np.pad(img, ((0, 0), (2, 2), (2, 2)), mode="reflect")
+        for c in range(2):
+            for y in range(got.shape[1]):
+                for x in range(got.shape[2]):
+                    ref = sum(w[i] * w[j] * pad[c, 2 * y + i, 2 * x + j] for i in range(5) for j in range(5))
+                    assert math.isclose(got[c, y, x], ref, rel_tol=1e-13, abs_tol=1e-15), (H, W, c, y, x)
+
+
+def test_pyramid_reduce_moments(oracle_lib):
+    O = oracle_lib
+    H, W = 23, 30
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    # a constant stays constant everywhere (taps sum to one, reflection keeps constants)
+    np.testing.assert_allclose(O.pyramid_reduce(np.full((1, H, W), 0.7)), 0.7, rtol=1e-15)
+    # an affine image samples at (2x', 2y') away from the border (symmetric window)
+    got = O.pyramid_reduce((0.3 + 0.02 * xx - 0.05 * yy)[None])[0]
+    for y in range(1, got.shape[0] - 1):
+        for x in range(1, got.shape[1] - 1):
+            assert math.isclose(got[y, x], 0.3 + 0.04 * x - 0.1 * y, rel_tol=1e-13, abs_tol=1e-14)
+    # x^2 gains the window's variance: the binomial(4, 1/2) law has variance 1
+    got = O.pyramid_reduce((xx ** 2)[None])[0]
+    for y in range(got.shape[0]):
+        for x in range(1, got.shape[1] - 1):
+            assert math.isclose(got[y, x], 4.0 * x * x + 1.0, rel_tol=1e-13), (y, x)
+    # reflection at the border: the left column sees x^2 mirrored, (4 + 1 + 0 + 1 + 4 weights) ->
+    # (1*4 + 4*1 + 6*0 + 4*1 + 1*4) / 16 = 1
+    assert math.isclose(got[0, 0], 1.0, rel_tol=1e-14)
+    # a row-only image is reduced along rows only
+    row = np.sin(xx / 3.0)
+    got = O.pyramid_reduce(row[None])[0]
+    np.testing.assert_allclose(got, np.broadcast_to(got[0], got.shape), rtol=1e-14)
+
+
+def test_pyramid_camera_halves_index_coordinates(oracle_lib):
+    O = oracle_lib
+    cam = S.pinhole(1200, 680, 600.0, *S.look_at((0.3, -0.2, -0.7), (0.0, 0.1, 2.0)))
+    rng = np.random.default_rng(8)
+    pts = rng.normal(0.0, 0.5, (50, 3)) + np.array([0.0, 0.1, 2.0])
+    for levels in (1, 2, 3):
+        c2 = O.pyramid_camera(cam, levels)
+        assert (c2.width, c2.height) == (
+            [1200, 600, 300, 150][levels], [680, 340, 170, 85][levels])
+        for p in pts:
+            x, y, z = cam.R @ p + cam.t
+            u0 = (cam.fx * x / z + cam.cx - 0.5, cam.fy * y / z + cam.cy - 0.5)
+            u1 = (c2.fx * x / z + c2.cx - 0.5, c2.fy * y / z + c2.cy - 0.5)
+            # level-l pixel x' sits at level-0 index 2^l x' + (2^l - 1) / 2 ... reduced l times from 2 x'
+            assert math.isclose(u1[0] * 2 ** levels, u0[0], rel_tol=1e-12, abs_tol=1e-9)
+            assert math.isclose(u1[1] * 2 ** levels, u0[1], rel_tol=1e-12, abs_tol=1e-9)
+
+
+def test_pyramid_camera_projects_gaussians_at_half_scale(oracle_lib):
+    # through the oracle's own (pinned) EWA projection: means halve, covariances quarter
+    O = oracle_lib
+    rng = np.random.default_rng(12)
+    n = 40
+    means = rng.normal(0.0, 0.4, (n, 3)) + np.array([0.0, 0.0, 3.0])
+    params = make_params(O, means, rng.normal(-3.0, 0.3, (n, 3)), rng.normal(size=(n, 4)),
+                         rng.normal(size=n), rng.normal(size=(n, 1, 3)), 0)
+    cam = S.pinhole(640, 480, 500.0)
+    opts = O.Options(tile=16)
+    a = O.project(params, cam, opts)
+    b = O.project(params, O.pyramid_camera(cam, 1), opts)
+    ok = (a["radius"] > 0) & (b["radius"] > 0)
+    assert ok.sum() > 30
+    np.testing.assert_allclose(b["rec"][ok, :2], a["rec"][ok, :2] / 2.0, rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(b["rec"][ok, 2], a["rec"][ok, 2], rtol=0)
+    # the screen-space dilation (0.3 px^2 on the diagonal) is added after the scaling
+    d = np.array([f32(0.3), 0.0, f32(0.3)])
+    np.testing.assert_allclose(b["cov"][ok] - d, (a["cov"][ok] - d) / 4.0, rtol=1e-10, atol=1e-12)
