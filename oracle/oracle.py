@@ -6,7 +6,7 @@ to state in numpy: the photometric loss of eq. (2) (its L1 term, and its SSIM
 term with the analytic gradient), the Adam update the paper takes from
 the default 3DGS optimisation setup (Sec. IV-A), and one level of the
 Gaussian pyramid of ground-truth images used for coarse-to-fine training
-(Sec. IV-A) with the camera that samples it.
+(Sec. III-B) with the camera that samples it.
 
 Readings of the paper used here (the paper defers the rasteriser to 3DGS,
 Sec. III-B): see the header of oracle.cpp; every threshold is a field of
@@ -397,7 +397,7 @@ def photometric_loss(image_flat, targets, cams, lam):
 
 
 # ---------------------------------------------------------------------------
-# Gaussian-pyramid training (Sec. IV-A, after Photo-SLAM): the ground-truth image
+# Gaussian-pyramid training (Sec. III-B, after Photo-SLAM): the ground-truth image
 # repeatedly smoothed and down-sampled, coarse levels used first.  Reading: one
 # level is the REDUCE step of Burt and Adelson's Gaussian pyramid, the separable
 # binomial window (1, 4, 6, 4, 1)/16 centred on every second pixel, output size

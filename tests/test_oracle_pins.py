@@ -739,7 +739,7 @@ def test_photometric_loss_without_ssim_is_the_l1_term(oracle_lib):
 
 
 # ---------------------------------------------------------------------------
-# Gaussian pyramid of the ground-truth images (Sec. IV-A): one REDUCE level
+# Gaussian pyramid of the ground-truth images (Sec. III-B): one REDUCE level
 # ---------------------------------------------------------------------------
 def test_pyramid_taps_are_the_binomial_window(oracle_lib):
     O = oracle_lib
