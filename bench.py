@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-ssim", action="store_true", help="skip the measurement of eq. (2) with its SSIM term")
+    ap.add_argument("--no-pyramid", action="store_true",
+                    help="skip the measurement of the image pyramid and of the coarse-level iterations")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many eager batched steps (for rocprofv3) and exit")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -218,6 +220,52 @@ def main():
         log(f"[bench] with SSIM (lambda {lam}): {ms_s:.3f} ms/step; loss call {ms_l:.3f} ms ({gbs:.0f} GB/s alg)")
         del st
 
+    pyramid = None
+    if not args.no_pyramid:
+        # the Gaussian pyramid of the targets (Sec. III-B): one reduction of every view (the kernel),
+        # and the same iteration at the coarse levels the first iterations train on
+        pyr = R.ImagePyramid(sc.cameras, target, 2, device=dev)
+        src, dst, cams0 = pyr.images[0], pyr.images[1], pyr.cameras[0]
+        for _ in range(args.warmup):
+            R.ImagePyramid.reduce(cams0, src, dst)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            R.ImagePyramid.reduce(cams0, src, dst)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_r = e0.elapsed_time(e1) / args.steps
+        px1 = sum(c.width * c.height for c in pyr.cameras[1])
+        alg = 12 * (sc.total_pixels + px1)  # three FP32 channels read at level 0, written at level 1
+        gbs = alg / (ms_r * 1e-3) / 1e9
+        pyramid = {"reduce_call_ms": round(ms_r, 4), "reduce_alg_bytes": alg, "reduce_GBps": round(gbs, 1),
+                   "reduce_hbm_frac": round(gbs / 8000.0, 4), "levels": {}}
+        log(f"[bench] pyramid reduce (all views, level 0 -> 1): {ms_r:.4f} ms ({gbs:.0f} GB/s alg)")
+        for lv in (1, 2):
+            st = R.MappingStep(params, pyr.cameras[lv], pyr.images[lv], lrs=lrs, tile_size=tile,
+                               checkpoint=sc.checkpoint, with_adam=with_adam)
+            st.size()
+            if use_graph:
+                st.capture()
+            run_l = st.replay if use_graph else st.run
+            reset(st)
+            for _ in range(args.warmup):
+                run_l()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                run_l()
+            e1.record()
+            torch.cuda.synchronize()
+            ms_lv = e0.elapsed_time(e1) / args.steps
+            pxl = sum(c.width * c.height for c in pyr.cameras[lv])
+            pyramid["levels"][str(lv)] = {"ms_per_step": round(ms_lv, 4), "pixels_per_step": pxl,
+                                          "value": round(pxl * 1e-6 / (ms_lv * 1e-3), 2),
+                                          "speedup_vs_level0": round(ms / ms_lv, 3)}
+            log(f"[bench] level {lv}: {ms_lv:.3f} ms/step ({ms / ms_lv:.2f}x faster than level 0)")
+            del st
+        del pyr
+
     roof = roofline(step, sc, stages, work)
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, tile)
     out = {
@@ -240,6 +288,7 @@ def main():
         "peak_hbm_bytes": peak_hbm,
         "per_view": per_view,
         "ssim": ssim,
+        "pyramid": pyramid,
         "stages_ms": stages,
         "roofline": roof,
         "cpu_baseline": cpu,

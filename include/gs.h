@@ -370,6 +370,29 @@ gs_status gs_photometric_loss(const gs_camera* cams, int32_t n_views, const floa
                               float lambda, float* loss_out, float* dl_dimage, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* Gaussian pyramid of the ground-truth images for coarse-to-fine training
+ * (Sec. III-B, after Photo-SLAM: the images are repeatedly smoothed and
+ * down-sampled, and the loss uses coarse levels first).  Reading (the paper
+ * gives no filter): one level is the REDUCE step of Burt and Adelson's
+ * Gaussian pyramid, the separable binomial window (1, 4, 6, 4, 1) / 16
+ * centred on every second pixel, output ceil(W/2) x ceil(H/2), the border
+ * reflected without repeating the edge pixel (index -1 reads 1, index W reads
+ * W - 2).
+ *
+ * gs_pyramid_camera (host only, no device work): *out = the camera that
+ * samples `levels` reductions of cam's image, each halving fx and fy,
+ * mapping cx -> cx / 2 + 1/4 and cy -> cy / 2 + 1/4 (output pixel x' sits at
+ * input index 2 x') and width, height -> ceil(/2).  levels in [0, 15]; cam
+ * and out are host pointers (may alias).
+ *
+ * gs_pyramid_reduce: one level for every view.  cams (host array, n_views in
+ * [1, GS_MAX_VIEWS]) are the cameras of the src images; src [sum_v 3 H_v W_v]
+ * and dst [sum_v 3 ceil(H_v/2) ceil(W_v/2)] are FP32, planar per view and
+ * packed by view as gs_image.rgb (dst in the layout of the level cameras).
+ * src and dst must not overlap (GS_ERR_INVALID_VALUE). */
+gs_status gs_pyramid_camera(const gs_camera* cam, int32_t levels, gs_camera* out);
+gs_status gs_pyramid_reduce(const gs_camera* cams, int32_t n_views, const float* src, float* dst, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,7 +77,7 @@ EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_op
            "gs_total_pixels", "gs_bin_sort_workspace_size", "gs_render_fwd_workspace_size",
            "gs_render_bwd_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_raster_bwd", "gs_project_bwd", "gs_render_stats", "gs_adam_step", "gs_project_bwd_adam",
-           "gs_photometric_loss_workspace_size", "gs_photometric_loss")
+           "gs_photometric_loss_workspace_size", "gs_photometric_loss", "gs_pyramid_camera", "gs_pyramid_reduce")
 
 _lib = None
 
@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH):
                                           C.c_double, C.c_double, C.c_double, P, P]),
         "gs_photometric_loss_workspace_size": (C.c_int, [pc, i32, C.POINTER(sz)]),
         "gs_photometric_loss": (C.c_int, [pc, i32, P, P, C.c_float, P, P, P, sz, P]),
+        "gs_pyramid_camera": (C.c_int, [pc, i32, pc]),
+        "gs_pyramid_reduce": (C.c_int, [pc, i32, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -251,3 +253,13 @@ def gs_photometric_loss_workspace_size(cams, n_views) -> int:
 def gs_photometric_loss(cams, n_views, image, target, lam, loss_out, dl_dimage, workspace, workspace_bytes, stream):
     _check("gs_photometric_loss", load().gs_photometric_loss(cams, n_views, image, target, lam, loss_out, dl_dimage,
                                                              workspace, workspace_bytes, stream))
+
+
+def gs_pyramid_camera(cam: gs_camera, levels: int) -> gs_camera:
+    out = gs_camera()
+    _check("gs_pyramid_camera", load().gs_pyramid_camera(C.byref(cam), levels, C.byref(out)))
+    return out
+
+
+def gs_pyramid_reduce(cams, n_views, src, dst, stream):
+    _check("gs_pyramid_reduce", load().gs_pyramid_reduce(cams, n_views, src, dst, stream))

@@ -13,11 +13,16 @@ rasteriser and the optimiser runs in the HIP kernels of libgs.so:
                    render, L1 term of eq. (2), backward, Adam) over a batch
                    of keyframes, runnable eagerly or replayed from a HIP
                    graph; PerViewMappingStep runs the same kernels one view
-                   at a time.
+                   at a time;
+  ImagePyramid / PyramidMappingStep
+                   the Gaussian pyramid of the ground-truth images
+                   (gs_pyramid_reduce, Sec. III-B) and coarse-to-fine
+                   mapping over its levels with one shared Adam state.
 """
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import math
 from typing import Dict, List, Optional, Sequence
 
@@ -347,7 +352,9 @@ class MappingStep:
     clears them) runs as its own call."""
 
     def __init__(self, params: GaussianParams, cameras, targets, lrs=None, tile_size=16, checkpoint=False,
-                 with_adam=True, fuse_adam=True, ssim_lambda: float = 0.0, **opt):
+                 with_adam=True, fuse_adam=True, ssim_lambda: float = 0.0, adam: Optional[FusedAdam] = None, **opt):
+        """`adam`: an existing FusedAdam over `params` to step (steps that train the same Gaussians on
+        other views or pyramid levels share its moments and step count); None makes a new one."""
         self.params = params
         # eq. (2): with ssim_lambda > 0 the loss is (1 - lambda) L1 + lambda (1 - SSIM) (3DGS: 0.2),
         # computed by gs_photometric_loss after the forward; 0 keeps the L1 term fused into the forward
@@ -355,10 +362,12 @@ class MappingStep:
         self.fuse_adam = with_adam and fuse_adam
         self.rast = Rasterizer(cameras, params.n, params.sh_degree, tile_size=tile_size, checkpoint=checkpoint,
                                device=params.means.device, **opt)
-        self.grads = params.zeros_like()
+        if adam is not None and (not with_adam or adam.params is not params):
+            raise ValueError("a shared FusedAdam must step the same parameters, with with_adam=True")
+        self.grads = adam.grads if adam is not None else params.zeros_like()
         self.target = targets if isinstance(targets, torch.Tensor) else pack_images(targets, params.means.device)
         self.loss = torch.zeros(self.rast.n_views, dtype=torch.float32, device=params.means.device)
-        self.adam = FusedAdam(params, self.grads, lrs) if with_adam else None
+        self.adam = adam if adam is not None else (FusedAdam(params, self.grads, lrs) if with_adam else None)
         self.photometric = None
         self.dl_dimage = None
         if self.ssim_lambda > 0.0:
@@ -505,3 +514,134 @@ class PerViewMappingStep:
 
     def overflowed(self) -> bool:
         return any(int(fr.d_overflow.item()) != 0 for fr in self.frames)
+
+
+@dataclasses.dataclass
+class LevelCamera:
+    """A keyframe camera as gs_camera holds it (R row-major, world to camera)."""
+    R: np.ndarray
+    t: np.ndarray
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+
+
+def pyramid_camera(cam, levels: int) -> LevelCamera:
+    """The camera that samples `levels` pyramid reductions of cam's image (gs_pyramid_camera)."""
+    c = L.gs_pyramid_camera(L.make_cameras([cam])[0], int(levels))
+    return LevelCamera(np.array(c.R[:], np.float64).reshape(3, 3), np.array(c.t[:], np.float64), c.fx, c.fy, c.cx,
+                       c.cy, c.width, c.height)
+
+
+class ImagePyramid:
+    """Gaussian pyramid of the keyframes' ground-truth images (Sec. III-B): level 0 is the packed
+    input, level l + 1 one gs_pyramid_reduce of level l for all views at once; cameras[l] samples
+    level l."""
+
+    def __init__(self, cameras, images, levels: int, device="cuda"):
+        if levels < 0:
+            raise ValueError("levels must be >= 0")
+        L.load()
+        base = images if isinstance(images, torch.Tensor) else pack_images(images, device)
+        self.cameras = [list(cameras)]
+        self.images = [base]
+        for _ in range(levels):
+            src_cams = self.cameras[-1]
+            dst_cams = [pyramid_camera(c, 1) for c in src_cams]
+            dst = torch.empty(sum(3 * c.width * c.height for c in dst_cams), dtype=torch.float32, device=base.device)
+            self.reduce(src_cams, self.images[-1], dst)
+            self.cameras.append(dst_cams)
+            self.images.append(dst)
+
+    @staticmethod
+    def reduce(cams, src: torch.Tensor, dst: torch.Tensor):
+        """dst = one pyramid level of the packed views src (cameras `cams` of src)."""
+        L.gs_pyramid_reduce(L.make_cameras(list(cams)), len(cams), _p(src), _p(dst), _stream())
+
+    @property
+    def levels(self) -> int:
+        return len(self.images) - 1
+
+    def view(self, level: int, v: int) -> torch.Tensor:
+        """The slice of level `level` holding view v ([3 H W], planar)."""
+        cams = self.cameras[level]
+        off = sum(3 * c.width * c.height for c in cams[:v])
+        return self.images[level][off:off + 3 * cams[v].width * cams[v].height]
+
+    def batch(self, view_levels: Sequence[int]):
+        """Cameras and packed targets of a batch whose view v is taken at level view_levels[v]."""
+        cams = [self.cameras[l][v] for v, l in enumerate(view_levels)]
+        if all(l == view_levels[0] for l in view_levels):
+            return cams, self.images[view_levels[0]]
+        return cams, torch.cat([self.view(l, v) for v, l in enumerate(view_levels)])
+
+
+class PyramidMappingStep:
+    """Coarse-to-fine mapping (Sec. III-B, after Photo-SLAM): the loss of the first iterations uses
+    the coarsest pyramid level of the ground-truth images, later ones finer levels.
+
+    `schedule[k]` iterations run at level levels - k (k = 0 the coarsest), after which every
+    iteration runs at level 0.  Each batch of per-view levels gets its own MappingStep (its own
+    buffers and, after capture(), its own HIP graph); all of them step the same Gaussians with one
+    FusedAdam, so the moments and the step count carry across levels.  run_levels() takes an
+    explicit per-view level tuple: keyframes at different levels share one batch."""
+
+    def __init__(self, params: GaussianParams, cameras, targets, levels: int = 2, schedule=None, lrs=None,
+                 graphs: bool = True, **step_opts):
+        self.params = params
+        self.pyramid = ImagePyramid(cameras, targets, levels, device=params.means.device)
+        self.schedule = list(schedule) if schedule is not None else [100] * levels
+        if len(self.schedule) != levels:
+            raise ValueError("schedule needs one iteration count per coarse level")
+        self.n_views = len(cameras)
+        self.lrs = lrs
+        self.graphs = graphs
+        self.step_opts = step_opts
+        self.adam = FusedAdam(params, params.zeros_like(), lrs)
+        self.steps: Dict[tuple, MappingStep] = {}
+        self._ran_at_capture = set()  # keys whose newest iteration capture() already ran
+        self.iteration = 0
+
+    def level_at(self, iteration: int) -> int:
+        lv = self.pyramid.levels
+        for k, n in enumerate(self.schedule):
+            if iteration < n:
+                return lv - k
+            iteration -= n
+        return 0
+
+    def step_for(self, view_levels: Sequence[int]) -> MappingStep:
+        key = tuple(int(l) for l in view_levels)
+        if len(key) != self.n_views or any(l < 0 or l > self.pyramid.levels for l in key):
+            raise ValueError(f"bad per-view levels {key}")
+        st = self.steps.get(key)
+        if st is None:
+            cams, tgt = self.pyramid.batch(key)
+            st = MappingStep(self.params, cams, tgt, lrs=self.lrs, adam=self.adam, **self.step_opts)
+            st.size()
+            if self.graphs:
+                st.capture()  # runs one iteration eagerly, then records one
+                self._ran_at_capture.add(key)
+            self.steps[key] = st
+        return st
+
+    def run_levels(self, view_levels: Sequence[int]) -> MappingStep:
+        """One iteration with view v at level view_levels[v]."""
+        st = self.step_for(view_levels)
+        key = tuple(int(l) for l in view_levels)
+        if key in self._ran_at_capture:
+            self._ran_at_capture.discard(key)
+        elif st.graph is not None:
+            st.replay()
+        else:
+            st.run()
+        return st
+
+    def run(self) -> MappingStep:
+        """One iteration at the scheduled level (every view at the same level)."""
+        st = self.run_levels([self.level_at(self.iteration)] * self.n_views)
+        self.iteration += 1
+        return st

@@ -130,3 +130,32 @@ def test_invalid_arguments_are_rejected_before_any_launch(L):
     lib = L.load()
     assert lib.gs_status_string(3) == b"GS_ERR_CAPACITY"
     assert b"workspace too small" in lib.gs_last_error()
+
+
+def test_pyramid_camera_host_arithmetic_and_reduce_validation(L, oracle_lib):
+    """gs_pyramid_camera is host arithmetic (no device work): it equals the oracle's level camera.
+    gs_pyramid_reduce rejects bad arguments before enqueuing anything."""
+    from paper_2409_13055_amd import synthetic as S
+    O = oracle_lib
+    cam = S.pinhole(1201, 679, 600.0, *S.look_at((0.3, -0.2, -0.7), (0.0, 0.1, 2.0)))
+    cam.cx, cam.cy = 601.75, 338.5
+    cc = L.make_cameras([cam])
+    for levels in range(5):
+        got = L.gs_pyramid_camera(cc[0], levels)
+        ref = O.pyramid_camera(cam, levels)
+        assert (got.width, got.height) == (ref.width, ref.height)
+        for k in ("fx", "fy", "cx", "cy"):
+            assert abs(getattr(got, k) - getattr(ref, k)) <= 1e-7 * abs(getattr(ref, k)), (levels, k)
+        assert list(got.R) == list(cc[0].R) and list(got.t) == list(cc[0].t)
+    with pytest.raises(L.GsError, match="levels"):
+        L.gs_pyramid_camera(cc[0], -1)
+    with pytest.raises(L.GsError, match="levels"):
+        L.gs_pyramid_camera(cc[0], 16)
+    c2 = L.make_cameras([S.pinhole(64, 48, 50.0), S.pinhole(31, 21, 20.0)])
+    n_src = 3 * (64 * 48 + 31 * 21)
+    with pytest.raises(L.GsError, match="src and dst"):
+        L.gs_pyramid_reduce(c2, 2, None, C.c_void_p(0x100000), None)
+    with pytest.raises(L.GsError, match="overlap"):
+        L.gs_pyramid_reduce(c2, 2, C.c_void_p(0x100000), C.c_void_p(0x100000 + 4 * n_src - 4), None)
+    with pytest.raises(L.GsError, match="n_views"):
+        L.gs_pyramid_reduce(c2, 0, C.c_void_p(0x100000), C.c_void_p(0x900000), None)
