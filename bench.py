@@ -225,13 +225,12 @@ def main():
         # the Gaussian pyramid of the targets (Sec. III-B): one reduction of every view (the kernel),
         # and the same iteration at the coarse levels the first iterations train on
         pyr = R.ImagePyramid(sc.cameras, target, 2, device=dev)
-        src, dst, cams0 = pyr.images[0], pyr.images[1], pyr.cameras[0]
         for _ in range(args.warmup):
-            R.ImagePyramid.reduce(cams0, src, dst)
+            pyr.reduce_level(0)
         torch.cuda.synchronize()
         e0.record()
         for _ in range(args.steps):
-            R.ImagePyramid.reduce(cams0, src, dst)
+            pyr.reduce_level(0)
         e1.record()
         torch.cuda.synchronize()
         ms_r = e0.elapsed_time(e1) / args.steps

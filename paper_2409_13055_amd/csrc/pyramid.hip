@@ -13,7 +13,8 @@
 // The kernel is bound by HBM traffic (one read of the input, a quarter of it
 // written): a block stages the reflected input rectangle of a 16 x 64 output
 // tile in LDS with coalesced loads, filters its rows at the even columns
-// (8-byte LDS reads, conflict-free), then its columns at the even rows.
+// (8-byte LDS reads, conflict-free), then its columns at the even rows, for
+// the three channels in turn with the next channel's loads in flight.
 #include <string>
 
 #include "gs_internal.h"
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(kPyrThreads) void k_pyramid_reduce(PyrViews pv, con
                                                                   float* __restrict__ dst) {
   __shared__ __align__(16) float s_in[kPyrInH][kPyrLd];
   __shared__ float s_row[kPyrInH][kPyrTW];
-  const int b = blockIdx.x, ch = blockIdx.y, tid = threadIdx.x;
+  const int b = blockIdx.x, tid = threadIdx.x;
   int v = 0;
 #pragma unroll 1
   for (int u = 1; u < pv.n_views; ++u)
@@ -87,47 +88,58 @@ __global__ __launch_bounds__(kPyrThreads) void k_pyramid_reduce(PyrViews pv, con
   const int W = pv.W[v], H = pv.H[v], W2 = pv.W2[v], H2 = pv.H2[v];
   const int lt = b - pv.tile_off[v];
   const int ox0 = (lt % pv.TX[v]) * kPyrTW, oy0 = (lt / pv.TX[v]) * kPyrTH;
-  const float* in = src + pv.src_off[v] + (size_t)ch * W * H;
-  float* out = dst + pv.dst_off[v] + (size_t)ch * W2 * H2;
+  const size_t plane = (size_t)W * H, plane2 = (size_t)W2 * H2;
+  const float* in = src + pv.src_off[v];
+  float* out = dst + pv.dst_off[v];
 
-  // the input rectangle rows 2 oy0 - 2 .. 2 oy0 + 2 TH, columns 2 ox0 - 2 .. 2 ox0 + 2 TW: every
-  // load issued before any is stored
-  float val[kPyrLoads];
+  // offsets in a channel plane of the input rectangle, rows 2 oy0 - 2 .. 2 oy0 + 2 TH and columns
+  // 2 ox0 - 2 .. 2 ox0 + 2 TW (reflected); -1 past the rectangle
+  int at[kPyrLoads];
 #pragma unroll
   for (int k = 0; k < kPyrLoads; ++k) {
     const int i = tid + k * kPyrThreads;
     const int r = i / kPyrInW, c = i % kPyrInW;
-    const int y = reflect101(2 * oy0 - 2 + r, H), x = reflect101(2 * ox0 - 2 + c, W);
-    val[k] = i < kPyrInH * kPyrInW ? in[(size_t)y * W + x] : 0.0f;
+    at[k] = i < kPyrInH * kPyrInW ? reflect101(2 * oy0 - 2 + r, H) * W + reflect101(2 * ox0 - 2 + c, W) : -1;
   }
+  // the three channels in turn; the next channel's loads are issued before the current one is filtered
+  float val[kPyrLoads];
 #pragma unroll
-  for (int k = 0; k < kPyrLoads; ++k) {
-    const int i = tid + k * kPyrThreads;
-    if (i < kPyrInH * kPyrInW) s_in[i / kPyrInW][i % kPyrInW] = val[k];
-  }
-  __syncthreads();
-
-  // rows: the window at input column 2 x (LDS column 2 x + 2) for every staged row
-  const int lx = tid % kPyrTW, g = tid / kPyrTW;
+  for (int k = 0; k < kPyrLoads; ++k) val[k] = at[k] >= 0 ? in[at[k]] : 0.0f;
+  const int lx = tid % kPyrTW, g = tid / kPyrTW, ox = ox0 + lx;
+#pragma unroll 1
+  for (int ch = 0; ch < 3; ++ch) {
 #pragma unroll
-  for (int j = 0; j < (kPyrInH + kPyrGroups - 1) / kPyrGroups; ++j) {
-    const int r = g + j * kPyrGroups;
-    if (r >= kPyrInH) break;
-    const float2 p0 = *reinterpret_cast<const float2*>(&s_in[r][2 * lx]);
-    const float2 p1 = *reinterpret_cast<const float2*>(&s_in[r][2 * lx + 2]);
-    const float p2 = s_in[r][2 * lx + 4];
-    s_row[r][lx] = taps5(p0.x, p0.y, p1.x, p1.y, p2);
-  }
-  __syncthreads();
-
-  // columns: the window at input row 2 y (staged row 2 y + 2)
-  const int ox = ox0 + lx;
+    for (int k = 0; k < kPyrLoads; ++k) {
+      const int i = tid + k * kPyrThreads;
+      if (i < kPyrInH * kPyrInW) s_in[i / kPyrInW][i % kPyrInW] = val[k];
+    }
+    __syncthreads();
+    if (ch < 2) {
+      const float* next = in + (ch + 1) * plane;
 #pragma unroll
-  for (int j = 0; j < kPyrTH / kPyrGroups; ++j) {
-    const int y = g + j * kPyrGroups, oy = oy0 + y;
-    const float o = taps5(s_row[2 * y][lx], s_row[2 * y + 1][lx], s_row[2 * y + 2][lx], s_row[2 * y + 3][lx],
-                          s_row[2 * y + 4][lx]);
-    if (ox < W2 && oy < H2) out[(size_t)oy * W2 + ox] = o;
+      for (int k = 0; k < kPyrLoads; ++k) val[k] = at[k] >= 0 ? next[at[k]] : 0.0f;
+    }
+    // rows: the window at input column 2 x (staged column 2 x + 2) for every staged row
+#pragma unroll
+    for (int j = 0; j < (kPyrInH + kPyrGroups - 1) / kPyrGroups; ++j) {
+      const int r = g + j * kPyrGroups;
+      if (r >= kPyrInH) break;
+      const float2 p0 = *reinterpret_cast<const float2*>(&s_in[r][2 * lx]);
+      const float2 p1 = *reinterpret_cast<const float2*>(&s_in[r][2 * lx + 2]);
+      const float p2 = s_in[r][2 * lx + 4];
+      s_row[r][lx] = taps5(p0.x, p0.y, p1.x, p1.y, p2);
+    }
+    __syncthreads();
+    // columns: the window at input row 2 y (staged row 2 y + 2); the next channel's stores to
+    // s_in are ordered after these reads' row pass by the barrier above, and the next row pass
+    // after them by the barrier that follows those stores
+#pragma unroll
+    for (int j = 0; j < kPyrTH / kPyrGroups; ++j) {
+      const int y = g + j * kPyrGroups, oy = oy0 + y;
+      const float o = taps5(s_row[2 * y][lx], s_row[2 * y + 1][lx], s_row[2 * y + 2][lx], s_row[2 * y + 3][lx],
+                            s_row[2 * y + 4][lx]);
+      if (ox < W2 && oy < H2) out[ch * plane2 + (size_t)oy * W2 + ox] = o;
+    }
   }
 }
 
@@ -163,7 +175,7 @@ extern "C" gs_status gs_pyramid_reduce(const gs_camera* cams, int32_t n_views, c
   const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), s1 = s0 + (uintptr_t)ns * sizeof(float);
   const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst), d1 = d0 + (uintptr_t)nd * sizeof(float);
   if (s0 < d1 && d0 < s1) return fail(GS_ERR_INVALID_VALUE, "src and dst overlap");
-  hipLaunchKernelGGL(k_pyramid_reduce, dim3((unsigned)pv.tile_off[n_views], 3), dim3(kPyrThreads), 0,
+  hipLaunchKernelGGL(k_pyramid_reduce, dim3((unsigned)pv.tile_off[n_views]), dim3(kPyrThreads), 0,
                      as_stream(stream), pv, src, dst);
   return check_launch("pyramid reduce");
 }

@@ -548,13 +548,20 @@ class ImagePyramid:
         base = images if isinstance(images, torch.Tensor) else pack_images(images, device)
         self.cameras = [list(cameras)]
         self.images = [base]
+        self._c_cams = []  # host gs_camera arrays of the levels that are reduced
         for _ in range(levels):
             src_cams = self.cameras[-1]
             dst_cams = [pyramid_camera(c, 1) for c in src_cams]
-            dst = torch.empty(sum(3 * c.width * c.height for c in dst_cams), dtype=torch.float32, device=base.device)
-            self.reduce(src_cams, self.images[-1], dst)
+            self._c_cams.append(L.make_cameras(src_cams))
             self.cameras.append(dst_cams)
-            self.images.append(dst)
+            self.images.append(torch.empty(sum(3 * c.width * c.height for c in dst_cams), dtype=torch.float32,
+                                           device=base.device))
+            self.reduce_level(len(self.images) - 2)
+
+    def reduce_level(self, level: int):
+        """Recompute level + 1 from level (one gs_pyramid_reduce over all views)."""
+        src_cams = self._c_cams[level]
+        L.gs_pyramid_reduce(src_cams, len(src_cams), _p(self.images[level]), _p(self.images[level + 1]), _stream())
 
     @staticmethod
     def reduce(cams, src: torch.Tensor, dst: torch.Tensor):
