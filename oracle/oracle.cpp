@@ -404,14 +404,17 @@ void trace_pixel(double px, double py, const uint32_t* list, int64_t len, const 
 }
 
 // Backward of one pixel: adds d(loss)/d(record) of every blended Gaussian.
-// grad row layout: (mx, my, ca, cb, cc, opacity, r, g, b).
+// Row layout: (mx, my, ca, cb, cc, opacity, r, g, b), then the magnitudes of
+// this pixel's two mean components, |dL_pixel/dmx| and |dL_pixel/dmy|, whose
+// sums over pixels are the homodirectional (AbsGS) view-space gradient.
+constexpr int kRowW = 11;
 void backward_pixel(const PixelTrace& tr, const double dl[3], const double* rec, const OrOptions& o,
-                    double* rows /* [len][9], indexed by list position */) {
+                    double* rows /* [len][kRowW], indexed by list position */) {
   double S[3] = {tr.T * o.bg[0], tr.T * o.bg[1], tr.T * o.bg[2]};
   for (size_t a = tr.acc.size(); a-- > 0;) {
     const Accepted& e = tr.acc[a];
     const double* g = rec + (size_t)e.id * R_STRIDE;
-    double* row = rows + (size_t)e.k * 9;
+    double* row = rows + (size_t)e.k * kRowW;
     double dl_dalpha = 0;
     for (int ch = 0; ch < 3; ++ch) {
       row[6 + ch] += dl[ch] * e.alpha * e.T;
@@ -421,8 +424,12 @@ void backward_pixel(const PixelTrace& tr, const double dl[3], const double* rec,
     if (e.clamped) continue;
     const double dl_dpower = dl_dalpha * e.alpha;
     row[5] += dl_dalpha * e.G;
-    row[0] += dl_dpower * (g[R_CA] * e.dx + g[R_CB] * e.dy);
-    row[1] += dl_dpower * (g[R_CB] * e.dx + g[R_CC] * e.dy);
+    const double gmx = dl_dpower * (g[R_CA] * e.dx + g[R_CB] * e.dy);
+    const double gmy = dl_dpower * (g[R_CB] * e.dx + g[R_CC] * e.dy);
+    row[0] += gmx;
+    row[1] += gmy;
+    row[9] += std::fabs(gmx);
+    row[10] += std::fabs(gmy);
     row[2] += dl_dpower * (-0.5 * e.dx * e.dx);
     row[3] += dl_dpower * (-e.dx * e.dy);
     row[4] += dl_dpower * (-0.5 * e.dy * e.dy);
@@ -726,10 +733,11 @@ int or_render_tiles(int32_t n_views, int64_t n, const OrCamera* cams, const OrOp
 
 // Backward of the blending restricted to the listed global tiles (all when
 // `tiles` is NULL): grad2d [V*N][9] receives the image-space gradients summed
-// over the pixels of those tiles only.
-int or_render_backward_tiles(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt,
-                             const double* rec, const uint32_t* ids, const uint32_t* ranges, const int64_t* tiles,
-                             int64_t n_tiles, const double* dl_dimage, double* grad2d) {
+// over the pixels of those tiles only, and abs2d [V*N][2] (when not NULL) the
+// per-pixel magnitudes of the two mean components summed the same way.
+static int render_backward_impl(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt,
+                                const double* rec, const uint32_t* ids, const uint32_t* ranges, const int64_t* tiles,
+                                int64_t n_tiles, const double* dl_dimage, double* grad2d, double* abs2d) {
   const std::vector<ViewInfo> views = make_views(cams, n_views, opt->tile);
   const int64_t T_tot = views.back().tile_off + (int64_t)views.back().grid.tx * views.back().grid.ty;
   const int B = opt->tile;
@@ -740,7 +748,7 @@ int or_render_backward_tiles(int32_t n_views, int64_t n, const OrCamera* cams, c
     const int64_t gt = tiles ? tiles[ti] : ti;
     row_off[ti + 1] = row_off[ti] + (int64_t)ranges[2 * gt + 1] - (int64_t)ranges[2 * gt];
   }
-  std::vector<double> rows((size_t)row_off[count] * 9, 0.0);
+  std::vector<double> rows((size_t)row_off[count] * kRowW, 0.0);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t ti = 0; ti < count; ++ti) {
     const int64_t gt = tiles ? tiles[ti] : ti;
@@ -756,17 +764,39 @@ int or_render_backward_tiles(int32_t n_views, int64_t n, const OrCamera* cams, c
         trace_pixel(i, j, ids + s, (int64_t)e - s, rec, *opt, true, tr);
         double dl[3];
         for (int ch = 0; ch < 3; ++ch) dl[ch] = dl_dimage[3 * vw.pix_off + (int64_t)ch * W * H + (int64_t)j * W + i];
-        backward_pixel(tr, dl, rec, *opt, rows.data() + (size_t)row_off[ti] * 9);
+        backward_pixel(tr, dl, rec, *opt, rows.data() + (size_t)row_off[ti] * kRowW);
       }
   }
   std::memset(grad2d, 0, sizeof(double) * 9 * (size_t)n_views * n);
+  if (abs2d) std::memset(abs2d, 0, sizeof(double) * 2 * (size_t)n_views * n);
   for (int64_t ti = 0; ti < count; ++ti) {
     const int64_t gt = tiles ? tiles[ti] : ti;
     const uint32_t s = ranges[2 * gt];
-    for (int64_t k = 0; k < row_off[ti + 1] - row_off[ti]; ++k)
-      for (int c = 0; c < 9; ++c) grad2d[(size_t)ids[s + k] * 9 + c] += rows[(size_t)(row_off[ti] + k) * 9 + c];
+    for (int64_t k = 0; k < row_off[ti + 1] - row_off[ti]; ++k) {
+      const double* row = rows.data() + (size_t)(row_off[ti] + k) * kRowW;
+      for (int c = 0; c < 9; ++c) grad2d[(size_t)ids[s + k] * 9 + c] += row[c];
+      if (abs2d)
+        for (int c = 0; c < 2; ++c) abs2d[(size_t)ids[s + k] * 2 + c] += row[9 + c];
+    }
   }
   return 0;
+}
+
+int or_render_backward_tiles(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt,
+                             const double* rec, const uint32_t* ids, const uint32_t* ranges, const int64_t* tiles,
+                             int64_t n_tiles, const double* dl_dimage, double* grad2d) {
+  return render_backward_impl(n_views, n, cams, opt, rec, ids, ranges, tiles, n_tiles, dl_dimage, grad2d, nullptr);
+}
+
+// The backward of the blending over all tiles with the homodirectional
+// view-space gradient of AbsGS (Sec. III-B adaptive control): abs2d [V*N][2]
+// = per (view, Gaussian) the sum over pixels of |dL_pixel/dmx| and
+// |dL_pixel/dmy| (pixel units), where dL_pixel is the loss through that
+// pixel's colour alone.
+int or_render_backward_abs(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
+                           const uint32_t* ids, const uint32_t* ranges, const double* dl_dimage, double* grad2d,
+                           double* abs2d) {
+  return render_backward_impl(n_views, n, cams, opt, rec, ids, ranges, nullptr, -1, dl_dimage, grad2d, abs2d);
 }
 
 // Backward of the blending: given dL/dimage (same layout as the image), the

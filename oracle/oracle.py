@@ -4,9 +4,11 @@ Wraps liboracle.so (projection, tile binning, per-pixel blending, analytic
 backward, local finite differences) and adds the steps that are plain enough
 to state in numpy: the photometric loss of eq. (2) (its L1 term, and its SSIM
 term with the analytic gradient), the Adam update the paper takes from
-the default 3DGS optimisation setup (Sec. IV-A), and one level of the
+the default 3DGS optimisation setup (Sec. IV-A), one level of the
 Gaussian pyramid of ground-truth images used for coarse-to-fine training
-(Sec. III-B) with the camera that samples it.
+(Sec. III-B) with the camera that samples it, and the adaptive density
+control of Sec. III-B (AbsGS statistics from the backward's per-pixel
+gradient magnitudes, split / clone / prune with the 3DGS parameters).
 
 Readings of the paper used here (the paper defers the rasteriser to 3DGS,
 Sec. III-B): see the header of oracle.cpp; every threshold is a field of
@@ -16,6 +18,7 @@ from __future__ import annotations
 
 import ctypes as C
 import dataclasses
+import math
 import os
 from typing import List, Optional, Sequence
 
@@ -90,6 +93,8 @@ def lib():
                                          P, P]
         _lib.or_render_backward_tiles.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P,
                                                   i64, P, P]
+        _lib.or_render_backward_abs.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P,
+                                                P]
         _lib.or_project_backward.argtypes = [i64, i32, P, P, P, P, P, C.POINTER(OrCamera), i32,
                                              C.POINTER(OrOptions), P, P, P, P, P, P]
         _lib.or_fd_local.argtypes = [i64, i32, P, P, P, P, P, C.POINTER(OrCamera), i32, C.POINTER(OrOptions), P, i64,
@@ -98,7 +103,7 @@ def lib():
         _lib.or_sh_basis.argtypes = [i32, i64, P, P, P]
         _lib.or_quat_to_rot.argtypes = [P, P]
         for f in ("or_project", "or_bin", "or_render", "or_render_backward", "or_project_backward", "or_fd_local",
-                  "or_render_tiles", "or_render_backward_tiles"):
+                  "or_render_tiles", "or_render_backward_tiles", "or_render_backward_abs"):
             getattr(_lib, f).restype = C.c_int
     return _lib
 
@@ -451,6 +456,123 @@ def render_backward(cams, opts: Options, rec, ids, ranges, dl_dimage):
                                   int(ids.shape[0]), _p(dl), _p(g2))
     assert rc == 0
     return g2
+
+
+def render_backward_abs(cams, opts: Options, rec, ids, ranges, dl_dimage):
+    """render_backward plus the homodirectional view-space gradient of AbsGS: abs2d [V*N][2], per
+    (view, Gaussian) the sums over pixels of |dL_p/dmx| and |dL_p/dmy| (pixel units)."""
+    n_views = len(cams)
+    rec = _d(rec)
+    n = rec.shape[0] // n_views
+    g2 = np.zeros((n_views * n, 9))
+    a2 = np.zeros((n_views * n, 2))
+    oc = opts.as_c()
+    rc = lib().or_render_backward_abs(n_views, n, cameras_c(cams), C.byref(oc), _p(rec),
+                                      _p(np.ascontiguousarray(ids, np.uint32)),
+                                      _p(np.ascontiguousarray(ranges, np.uint32)), _p(_d(dl_dimage)), _p(g2), _p(a2))
+    assert rc == 0
+    return g2, a2
+
+
+# ---------------------------------------------------------------------------
+# Adaptive density control (Sec. III-B): AbsGS densification with the 3DGS
+# split/clone parameters, pruning by opacity.  Readings (the paper names the
+# method and says the 3DGS parameters are kept):
+#  - statistics as in 3DGS, one observation per (view, Gaussian) pair whose
+#    Gaussian touches a tile of the view: the view-space gradient is the mean's
+#    gradient in normalised device units, (W/2) dL/dmx and (H/2) dL/dmy; the
+#    homodirectional one takes AbsGS's per-pixel magnitudes instead; each adds
+#    its Euclidean norm to an accumulator and the pair adds 1 to a count;
+#  - a Gaussian is selected when its mean homodirectional norm reaches tau
+#    (3DGS: 0.0002), decided in FP32 as accum >= tau * count (count > 0);
+#  - selected and max scale > percent_dense * extent (3DGS: 0.01; extent 1.1
+#    times the largest distance of a camera centre from their mean): split into
+#    two, each with mean mu + R (s * eps) (eps a standard normal draw, passed in)
+#    and scales s / 1.6; selected and not larger: cloned (an exact copy); the
+#    scale test is taken in FP32 on log scales against log(percent_dense *
+#    extent);
+#  - opacity below 0.005 (FP32 test on the logit against logit(0.005)): pruned,
+#    with no clone or split (children inherit the opacity, so 3DGS prunes them
+#    too);
+#  - output order: the kept originals, the clones, every split's first child,
+#    every split's second child, each in the original order; Adam moments are
+#    kept for originals and zero for new Gaussians; the statistics restart at 0.
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class DensityConfig:
+    extent: float
+    grad_threshold: float = 0.0002
+    percent_dense: float = 0.01
+    min_opacity: float = 0.005
+    split_scale_div: float = 1.6
+
+
+def scene_extent(cams):
+    """1.1 times the largest distance of a camera centre from the centres' mean."""
+    c = np.array([-np.asarray(cm.R, np.float64).T @ np.asarray(cm.t, np.float64) for cm in cams])
+    return 1.1 * float(np.max(np.linalg.norm(c - c.mean(0), axis=1)))
+
+
+def density_accumulate(grad_acc, abs_acc, count, tiles_touched, grad2d, abs2d, cams):
+    """Adds one iteration's view-space gradient norms to the per-Gaussian statistics (in place)."""
+    n = grad_acc.shape[0]
+    for v, c in enumerate(cams):
+        sl = slice(v * n, (v + 1) * n)
+        vis = np.asarray(tiles_touched[sl]) > 0
+        sx, sy = c.width / 2.0, c.height / 2.0
+        g = np.hypot(sx * grad2d[sl, 0], sy * grad2d[sl, 1])
+        a = np.hypot(sx * abs2d[sl, 0], sy * abs2d[sl, 1])
+        grad_acc[vis] += g[vis]
+        abs_acc[vis] += a[vis]
+        count[vis] += 1
+
+
+def density_classes(params: Params, abs_acc, count, cfg: DensityConfig):
+    """(keep, clone, split) masks; every decision in FP32 as stated in the readings above."""
+    f = np.float32
+    sel = (np.asarray(count) > 0) & (np.asarray(abs_acc, f) >= f(cfg.grad_threshold) * np.asarray(count, f))
+    large = np.asarray(params.log_scales, f).max(axis=1) > f(math.log(cfg.percent_dense * cfg.extent))
+    pruned = np.asarray(params.opacity_logits, f).reshape(-1) < f(math.log(cfg.min_opacity / (1.0 - cfg.min_opacity)))
+    keep = ~pruned & ~(sel & large)
+    return keep, ~pruned & sel & ~large, ~pruned & sel & large
+
+
+def densify_and_prune(params: Params, exp_avg: Params, exp_avg_sq: Params, abs_acc, count, cfg: DensityConfig,
+                      eps):
+    """One density-control step.  eps [n_split, 2, 3]: the standard normal draws of the split
+    children, in split order (first child, second child).  Returns the new parameters and moments
+    (as Params) and the three masks."""
+    keep, clone, split = density_classes(params, abs_acc, count, cfg)
+    ns = int(split.sum())
+    eps = np.asarray(eps, np.float64).reshape(ns, 2, 3)
+    q = params.quats[split]
+    R = np.array([quat_to_rot(qq / np.linalg.norm(qq)) for qq in q]).reshape(ns, 3, 3)
+    s = np.exp(params.log_scales[split])
+
+    def build(arrs, child):
+        return [np.concatenate([a[keep], a[clone]] + [child(a, k) for k in range(2)]) for a in arrs]
+
+    def child_param(name):
+        def f(a, k):
+            if name == "means":
+                return a[split] + np.einsum("nij,nj->ni", R, s * eps[:, k, :])
+            if name == "log_scales":
+                return a[split] - math.log(cfg.split_scale_div)
+            return a[split]
+        return f
+
+    names = ("means", "log_scales", "quats", "opacity_logits", "sh")
+    out = {k: build([getattr(params, k)], child_param(k))[0] for k in names}
+    new_p = Params(out["means"], out["log_scales"], out["quats"], out["opacity_logits"], out["sh"], params.sh_degree)
+
+    def moments(m):
+        o = {}
+        for k in names:
+            a = getattr(m, k)
+            o[k] = np.concatenate([a[keep]] + [np.zeros((int(clone.sum()) + 2 * ns,) + a.shape[1:])])
+        return Params(o["means"], o["log_scales"], o["quats"], o["opacity_logits"], o["sh"], m.sh_degree)
+
+    return new_p, moments(exp_avg), moments(exp_avg_sq), (keep, clone, split)
 
 
 def project_backward(params: Params, cams, opts: Options, grad2d):

@@ -830,3 +830,147 @@ def test_pyramid_camera_projects_gaussians_at_half_scale(oracle_lib):
     # the screen-space dilation (0.3 px^2 on the diagonal) is added after the scaling
     d = np.array([f32(0.3), 0.0, f32(0.3)])
     np.testing.assert_allclose(b["cov"][ok] - d, (a["cov"][ok] - d) / 4.0, rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Adaptive density control (Sec. III-B): AbsGS statistics, split / clone / prune
+# ---------------------------------------------------------------------------
+def test_homodirectional_gradient_matches_per_pixel_differences(oracle_lib):
+    """abs2d of the backward against central differences of every pixel's loss through the
+    oracle's forward render: sum_p |d(dl_p . C_p)/dm| per mean component."""
+    O = oracle_lib
+    cam = S.pinhole(24, 20, 30.0)
+    means = [[0.05, -0.02, 2.0], [-0.1, 0.08, 2.5], [0.12, 0.1, 3.0]]
+    P = make_params(O, means, np.log([[0.05, 0.03, 0.04], [0.06, 0.06, 0.02], [0.08, 0.05, 0.05]]),
+                    [[1.0, 0.1, 0.2, 0.0], [0.9, -0.3, 0.1, 0.2], [1.0, 0.0, 0.0, 0.4]], [0.3, -0.2, 0.8],
+                    rgb_to_dc([[0.9, 0.2, 0.1], [0.1, 0.8, 0.3], [0.2, 0.3, 0.9]])[:, None, :], 0)
+    opts = O.Options(tile=8)
+    f = O.forward(P, [cam], opts)
+    rec, ids, ranges = f["proj"]["rec"], f["ids"], f["ranges"]
+    rng = np.random.default_rng(21)
+    dl = rng.standard_normal(3 * 24 * 20)
+    g2, a2 = O.render_backward_abs([cam], opts, rec, ids, ranges, dl)
+    np.testing.assert_allclose(g2, O.render_backward([cam], opts, rec, ids, ranges, dl), rtol=0, atol=0)
+    h = 1e-6
+    for i in range(3):
+        for comp in range(2):
+            rp, rm = rec.copy(), rec.copy()
+            rp[i, comp] += h
+            rm[i, comp] -= h
+            dC = (O.render([cam], opts, rp, ids, ranges)["image"] - O.render([cam], opts, rm, ids, ranges)["image"]) / (2 * h)
+            per_pixel = (dl * dC).reshape(3, -1).sum(0)
+            assert math.isclose(a2[i, comp], np.abs(per_pixel).sum(), rel_tol=1e-5), (i, comp)
+            assert math.isclose(g2[i, comp], per_pixel.sum(), rel_tol=1e-5, abs_tol=1e-9), (i, comp)
+            assert a2[i, comp] > abs(g2[i, comp]) * 1.01  # signs cancel in the plain gradient
+
+
+def test_density_statistics_closed_form(oracle_lib):
+    O = oracle_lib
+    cams = [S.pinhole(4, 2, 3.0), S.pinhole(10, 6, 3.0)]
+    n = 3
+    tt = np.array([1, 0, 2, 5, 1, 0])
+    g2 = np.zeros((6, 9))
+    a2 = np.zeros((6, 2))
+    g2[0, :2] = [1.5, 4.0]    # view 0 (W/2 = 2, H/2 = 1): (3, 4) -> 5
+    a2[0] = [2.5, 12.0]       # (5, 12) -> 13
+    g2[1, :2] = [9.0, 9.0]    # not visible: ignored
+    g2[2, :2] = [0.0, -0.5]   # -> 0.5
+    a2[2] = [0.0, 0.5]
+    g2[3, :2] = [0.6, 0.0]    # view 1 (W/2 = 5, H/2 = 3): -> 3
+    a2[3] = [1.6, 2.0]        # (8, 6) -> 10
+    g2[4, :2] = [-0.8, 1.0]   # (-4, 3) -> 5
+    a2[4] = [0.8, 1.0]
+    ga, aa, cnt = np.zeros(n), np.zeros(n), np.zeros(n, np.int64)
+    O.density_accumulate(ga, aa, cnt, tt, g2, a2, cams)
+    np.testing.assert_allclose(ga, [5 + 3, 5, 0.5], rtol=1e-15)
+    np.testing.assert_allclose(aa, [13 + 10, 5, 0.5], rtol=1e-15)
+    assert list(cnt) == [2, 1, 1]
+
+
+def test_scene_extent_closed_form(oracle_lib):
+    O = oracle_lib
+    centre = np.array([1.0, 2.0, 3.0])
+    cams = []
+    for k in range(5):
+        th = 2 * math.pi * k / 5
+        c = centre + 2.0 * np.array([math.cos(th), 0.3, math.sin(th)]) / math.hypot(1.0, 0.3)
+        cams.append(S.pinhole(10, 10, 10.0, *S.look_at(c, centre)))
+    # the centres' mean is centre + (0, 0.6, 0)/|.|*..., every centre equally far from it
+    mean = np.mean([-c.R.T @ c.t for c in cams], axis=0)
+    r = np.linalg.norm(-cams[0].R.T @ cams[0].t - mean)
+    assert math.isclose(O.scene_extent(cams), 1.1 * r, rel_tol=1e-12)
+    assert math.isclose(r, 2.0 / math.hypot(1.0, 0.3), rel_tol=1e-12)
+
+
+def density_case(O):
+    """Seven Gaussians, one per case of the rules (extent 10: the split bound is 0.1)."""
+    n = 7
+    log_s = np.log(np.array([[0.01, 0.02, 0.03], [0.5, 0.5, 0.5], [0.05, 0.02, 0.09],
+                             [0.3, 0.01, 0.02], [0.2, 0.2, 0.2], [0.4, 0.4, 0.4], [0.01, 0.01, 0.01]]))
+    logits = np.array([-6.0, 1.0, 0.5, 2.0, 0.0, -5.5, -5.0])  # sigmoid(-6), sigmoid(-5.5) < 0.005 < sigmoid(-5)
+    rng = np.random.default_rng(5)
+    P = make_params(O, rng.normal(size=(n, 3)), log_s, rng.normal(size=(n, 4)), logits,
+                    rng.normal(size=(n, 4, 3)), 1)
+    count = np.array([3, 2, 4, 1, 0, 2, 5])
+    tau = np.float32(0.0002)
+    abs_acc = np.array([1.0, tau * np.float32(2) * np.float32(0.5), tau * np.float32(4), 0.01, 1.0, 1.0,
+                        tau * np.float32(5)], np.float64)
+    abs_acc[1] = float(np.nextafter(np.float32(tau * np.float32(2)), np.float32(0)))  # just below: not selected
+    return P, count, abs_acc
+
+
+def test_density_control_cases_order_and_moments(oracle_lib):
+    from scipy.spatial.transform import Rotation
+    O = oracle_lib
+    P, count, abs_acc = density_case(O)
+    cfg = O.DensityConfig(extent=10.0)
+    keep, clone, split = O.density_classes(P, abs_acc, count, cfg)
+    # 0 pruned (selected, small); 1 below the threshold; 2 cloned (exactly at the threshold);
+    # 3 split; 4 never seen; 5 pruned (selected, large); 6 cloned (at the threshold)
+    assert list(np.nonzero(keep)[0]) == [1, 2, 4, 6]
+    assert list(np.nonzero(clone)[0]) == [2, 6]
+    assert list(np.nonzero(split)[0]) == [3]
+    rng = np.random.default_rng(9)
+    m = O.Params(*[rng.normal(size=a.shape) for a in (P.means, P.log_scales, P.quats, P.opacity_logits, P.sh)], 1)
+    v = O.Params(*[rng.random(a.shape) for a in (P.means, P.log_scales, P.quats, P.opacity_logits, P.sh)], 1)
+    eps = np.array([[[1.0, 0.0, 0.0], [0.0, 0.0, -2.0]]])
+    newp, newm, newv, _ = O.densify_and_prune(P, m, v, abs_acc, count, cfg, eps)
+    order = [1, 2, 4, 6, 2, 6, 3, 3]
+    for name in ("quats", "opacity_logits", "sh"):
+        np.testing.assert_array_equal(getattr(newp, name), getattr(P, name)[order])
+    np.testing.assert_array_equal(newp.means[:6], P.means[order[:6]])
+    np.testing.assert_array_equal(newp.log_scales[:6], P.log_scales[order[:6]])
+    np.testing.assert_allclose(newp.log_scales[6:], P.log_scales[[3, 3]] - math.log(1.6), rtol=0, atol=1e-15)
+    # child k = mean + R (s * eps_k): here s_x times R's first column, -2 s_z times its third
+    q = P.quats[3] / np.linalg.norm(P.quats[3])
+    Rm = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    s = np.exp(P.log_scales[3])
+    np.testing.assert_allclose(newp.means[6], P.means[3] + s[0] * Rm[:, 0], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(newp.means[7], P.means[3] - 2.0 * s[2] * Rm[:, 2], rtol=1e-12, atol=1e-14)
+    for mm, src in ((newm, m), (newv, v)):
+        for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+            a = getattr(mm, name)
+            np.testing.assert_array_equal(a[:4], getattr(src, name)[[1, 2, 4, 6]])
+            assert not np.any(a[4:])
+
+
+def test_split_children_sample_the_parent_gaussian(oracle_lib):
+    """Children drawn with standard normal eps are distributed as N(mu, R S^2 R^T)."""
+    from scipy.spatial.transform import Rotation
+    O = oracle_lib
+    n = 4000
+    q = np.array([0.8, 0.3, -0.4, 0.2])
+    s = np.array([0.3, 0.15, 0.05])
+    P = make_params(O, np.tile([1.0, -2.0, 3.0], (n, 1)), np.tile(np.log(s), (n, 1)), np.tile(q, (n, 1)),
+                    np.zeros(n), np.zeros((n, 1, 3)), 0)
+    z = O.Params(*[np.zeros_like(a) for a in (P.means, P.log_scales, P.quats, P.opacity_logits, P.sh)], 0)
+    eps = np.random.default_rng(2).standard_normal((n, 2, 3))
+    newp, _, _, (keep, clone, split) = O.densify_and_prune(P, z, z, np.ones(n), np.ones(n, np.int64),
+                                                           O.DensityConfig(extent=1.0), eps)
+    assert split.all() and newp.n == 2 * n
+    qn = q / np.linalg.norm(q)
+    Rm = Rotation.from_quat([qn[1], qn[2], qn[3], qn[0]]).as_matrix()
+    cov = Rm @ np.diag(s ** 2) @ Rm.T
+    d = newp.means - np.array([1.0, -2.0, 3.0])
+    np.testing.assert_allclose(d.mean(0), 0.0, atol=4 * 0.3 / math.sqrt(2 * n))
+    np.testing.assert_allclose(np.cov(d.T), cov, atol=0.004)
