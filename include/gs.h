@@ -370,6 +370,78 @@ gs_status gs_photometric_loss(const gs_camera* cams, int32_t n_views, const floa
                               float lambda, float* loss_out, float* dl_dimage, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------- adaptive density control
+ * Sec. III-B: every densification interval (1000 iterations, Sec. IV-A)
+ * Gaussians with a high homodirectional view-space position gradient (AbsGS)
+ * are split when large and cloned when small, with the 3DGS split and clone
+ * parameters, and Gaussians of low opacity are pruned.  Readings (the paper
+ * gives no formulas):
+ *  - gs_raster_bwd_abs: gs_raster_bwd that also ADDS into abs_grad2d
+ *    ([n_views*n][2] FP32, device, caller-cleared) the homodirectional
+ *    gradient of AbsGS, per (view, Gaussian) pair the sums over pixels of
+ *    |dL_p/dmean_x| and |dL_p/dmean_y| (pixel units; dL_p the loss through
+ *    pixel p's colour alone); grad2d as for gs_raster_bwd.
+ *  - gs_density_accumulate: for every pair with tiles_touched > 0, adds the
+ *    Euclidean norm of (W/2 g_x, H/2 g_y) (the gradient in normalised device
+ *    units, as in 3DGS) of grad2d's mean part to stats->grad_accum[i], that of
+ *    abs_grad2d to stats->abs_accum[i], and 1 to stats->count[i].  proj is the
+ *    projection of the iteration that produced the gradients.
+ *  - gs_density_plan: classifies every Gaussian (decisions in FP32; the
+ *    thresholds are formed in double from cfg and rounded to FP32):
+ *    selected = count > 0 and abs_accum >= grad_threshold * count;
+ *    pruned = logit < logit(min_opacity); a pruned Gaussian is dropped;
+ *    otherwise a selected one with max log-scale > log(percent_dense * extent)
+ *    is split (dropped, two children), another selected one is kept and
+ *    cloned, an unselected one kept.  Writes d_counts[0..2] (device) = kept,
+ *    cloned, split, and the classes into `workspace`
+ *    (gs_density_workspace_size(n) bytes), which gs_density_apply reads.
+ *  - gs_density_apply: writes the new set of n_out = kept + cloned + 2 split
+ *    Gaussians (the caller reads d_counts and allocates): the kept originals,
+ *    then the clones (exact copies), then every split's first child, then
+ *    every split's second child, each in the original order.  Child k of the
+ *    q-th split Gaussian has mean mu + R (s * eps[6 q + 3 k .. +3]) (R the
+ *    rotation of the normalised quaternion, s = exp(log_scales), eps standard
+ *    normal draws supplied by the caller, n_eps >= 6 * split floats) and
+ *    log-scales minus log(split_scale_div); its other parameters are the
+ *    parent's.  exp_avg / exp_avg_sq (the Adam moments, same layout as the
+ *    parameters) are copied for kept Gaussians and zero for new ones.  Rows at
+ *    or past n_out, and children whose eps lie past n_eps, are not written.
+ *    The outputs must not overlap the inputs.  The statistics restart at zero
+ *    for the new set (the caller clears new arrays).
+ *  - gs_scene_extent (host only): 1.1 times the largest distance of a camera
+ *    centre from the centres' mean (the 3DGS scene extent).
+ *  - gs_default_density_config: the 3DGS values (grad_threshold 0.0002,
+ *    percent_dense 0.01, min_opacity 0.005, split_scale_div 1.6), extent 1. */
+typedef struct gs_density_config {
+  float grad_threshold;
+  float percent_dense;
+  float min_opacity;
+  float split_scale_div;
+  float extent;
+} gs_density_config;
+
+typedef struct gs_density_stats {
+  float* grad_accum; /* [n] */
+  float* abs_accum;  /* [n] */
+  int32_t* count;    /* [n] */
+} gs_density_stats;
+
+gs_status gs_raster_bwd_abs(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_image* img,
+                            const gs_camera* cams, int32_t n_views, const gs_options* opts, const gs_loss* loss,
+                            float* grad2d, float* abs_grad2d, void* stream);
+void gs_default_density_config(gs_density_config* cfg);
+gs_status gs_scene_extent(const gs_camera* cams, int32_t n_views, float* extent);
+gs_status gs_density_accumulate(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n_views,
+                                const float* grad2d, const float* abs_grad2d, const gs_density_stats* stats,
+                                void* stream);
+gs_status gs_density_workspace_size(int64_t n, size_t* bytes);
+gs_status gs_density_plan(const gs_params* params, const gs_density_stats* stats, const gs_density_config* cfg,
+                          int32_t* d_counts, void* workspace, size_t workspace_bytes, void* stream);
+gs_status gs_density_apply(const gs_params* params, const gs_params* exp_avg, const gs_params* exp_avg_sq,
+                           const gs_density_config* cfg, const float* eps, int64_t n_eps, int64_t n_out,
+                           const gs_grads* out_params, const gs_grads* out_exp_avg, const gs_grads* out_exp_avg_sq,
+                           const void* workspace, size_t workspace_bytes, void* stream);
+
 /* Gaussian pyramid of the ground-truth images for coarse-to-fine training
  * (Sec. III-B, after Photo-SLAM: the images are repeatedly smoothed and
  * down-sampled, and the loss uses coarse levels first).  Reading (the paper

@@ -68,6 +68,15 @@ class gs_grads(C.Structure):
                 ("sh_rest", P)]
 
 
+class gs_density_config(C.Structure):
+    _fields_ = [("grad_threshold", C.c_float), ("percent_dense", C.c_float), ("min_opacity", C.c_float),
+                ("split_scale_div", C.c_float), ("extent", C.c_float)]
+
+
+class gs_density_stats(C.Structure):
+    _fields_ = [("grad_accum", P), ("abs_accum", P), ("count", P)]
+
+
 class gs_adam_group(C.Structure):
     _fields_ = [("param", P), ("grad", P), ("exp_avg", P), ("exp_avg_sq", P), ("numel", C.c_int64),
                 ("lr", C.c_float), ("reserved", C.c_int32)]
@@ -77,7 +86,9 @@ EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_op
            "gs_total_pixels", "gs_bin_sort_workspace_size", "gs_render_fwd_workspace_size",
            "gs_render_bwd_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_raster_bwd", "gs_project_bwd", "gs_render_stats", "gs_adam_step", "gs_project_bwd_adam",
-           "gs_photometric_loss_workspace_size", "gs_photometric_loss", "gs_pyramid_camera", "gs_pyramid_reduce")
+           "gs_photometric_loss_workspace_size", "gs_photometric_loss", "gs_pyramid_camera", "gs_pyramid_reduce",
+           "gs_raster_bwd_abs", "gs_default_density_config", "gs_scene_extent", "gs_density_accumulate",
+           "gs_density_workspace_size", "gs_density_plan", "gs_density_apply")
 
 _lib = None
 
@@ -120,6 +131,16 @@ def load(path: str = LIB_PATH):
         "gs_photometric_loss": (C.c_int, [pc, i32, P, P, C.c_float, P, P, P, sz, P]),
         "gs_pyramid_camera": (C.c_int, [pc, i32, pc]),
         "gs_pyramid_reduce": (C.c_int, [pc, i32, P, P, P]),
+        "gs_raster_bwd_abs": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), C.POINTER(gs_image), pc,
+                                        i32, po, C.POINTER(gs_loss), P, P, P]),
+        "gs_default_density_config": (None, [C.POINTER(gs_density_config)]),
+        "gs_scene_extent": (C.c_int, [pc, i32, C.POINTER(C.c_float)]),
+        "gs_density_accumulate": (C.c_int, [C.POINTER(gs_projected), i64, pc, i32, P, P,
+                                            C.POINTER(gs_density_stats), P]),
+        "gs_density_workspace_size": (C.c_int, [i64, C.POINTER(sz)]),
+        "gs_density_plan": (C.c_int, [pp, C.POINTER(gs_density_stats), C.POINTER(gs_density_config), P, P, sz, P]),
+        "gs_density_apply": (C.c_int, [pp, pp, pp, C.POINTER(gs_density_config), P, i64, i64, C.POINTER(gs_grads),
+                                       C.POINTER(gs_grads), C.POINTER(gs_grads), P, sz, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -263,3 +284,47 @@ def gs_pyramid_camera(cam: gs_camera, levels: int) -> gs_camera:
 
 def gs_pyramid_reduce(cams, n_views, src, dst, stream):
     _check("gs_pyramid_reduce", load().gs_pyramid_reduce(cams, n_views, src, dst, stream))
+
+
+def gs_raster_bwd_abs(proj, n, bins, img, cams, n_views, opts, loss, grad2d, abs_grad2d, stream):
+    _check("gs_raster_bwd_abs", load().gs_raster_bwd_abs(C.byref(proj), n, C.byref(bins),
+                                                         C.byref(img) if img is not None else None, cams, n_views,
+                                                         C.byref(opts), C.byref(loss), grad2d, abs_grad2d, stream))
+
+
+def default_density_config(**overrides) -> gs_density_config:
+    c = gs_density_config()
+    load().gs_default_density_config(C.byref(c))
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c
+
+
+def gs_scene_extent(cams, n_views) -> float:
+    out = C.c_float()
+    _check("gs_scene_extent", load().gs_scene_extent(cams, n_views, C.byref(out)))
+    return out.value
+
+
+def gs_density_accumulate(proj, n, cams, n_views, grad2d, abs_grad2d, stats, stream):
+    _check("gs_density_accumulate", load().gs_density_accumulate(C.byref(proj), n, cams, n_views, grad2d, abs_grad2d,
+                                                                 C.byref(stats), stream))
+
+
+def gs_density_workspace_size(n) -> int:
+    out = C.c_size_t()
+    _check("gs_density_workspace_size", load().gs_density_workspace_size(n, C.byref(out)))
+    return out.value
+
+
+def gs_density_plan(params, stats, cfg, d_counts, workspace, workspace_bytes, stream):
+    _check("gs_density_plan", load().gs_density_plan(C.byref(params), C.byref(stats), C.byref(cfg), d_counts,
+                                                     workspace, workspace_bytes, stream))
+
+
+def gs_density_apply(params, exp_avg, exp_avg_sq, cfg, eps, n_eps, n_out, out_params, out_exp_avg, out_exp_avg_sq,
+                     workspace, workspace_bytes, stream):
+    _check("gs_density_apply", load().gs_density_apply(C.byref(params), C.byref(exp_avg), C.byref(exp_avg_sq),
+                                                       C.byref(cfg), eps, n_eps, n_out, C.byref(out_params),
+                                                       C.byref(out_exp_avg), C.byref(out_exp_avg_sq), workspace,
+                                                       workspace_bytes, stream))

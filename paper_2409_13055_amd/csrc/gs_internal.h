@@ -54,6 +54,7 @@ gs_status check_launch(const char* what);
 
 gs_status validate_cams(const gs_camera* cams, int32_t n_views);
 gs_status validate_opts(const gs_options* o);
+gs_status validate_params(const gs_params* p);
 ViewTable make_view_table(const gs_camera* cams, int32_t n_views, int32_t tile);
 CamTable make_cam_table(const gs_camera* cams, int32_t n_views, const gs_options* o);
 

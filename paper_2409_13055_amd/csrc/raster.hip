@@ -514,19 +514,39 @@ __device__ LaneRole wave_roles(int lane) {
   return rl;
 }
 
+// Per-lane sums of the homodirectional (AbsGS) view-space gradient: the
+// magnitudes of each pixel's two mean components, |u (a dx + b dy)| and
+// |u (b dx + c dy)|, which the moments above cannot give.  Reduced like sy: a
+// swap between the wave halves puts one value's partials in each half, the
+// row swap and row sum complete them; which lane writes which component is
+// found once per kernel from one-hot tags, one lane per component.
+__device__ __forceinline__ float reduce_pair(float a, float b) {
+  return row_sum(swap_add16(swap_add32(a, b), swap_add32(a, b)));
+}
+__device__ int abs_role(int lane) {
+  const float one = lane == 0 ? 1.0f : 0.0f;
+  const int t = (int)(reduce_pair(1.0f * one, 2.0f * one) + 0.5f);
+  const unsigned long long m0 = __ballot(t == 1), m1 = __ballot(t == 2);
+  if (m0 != 0ull && lane == __ffsll((long long)m0) - 1) return 0;
+  if (m1 != 0ull && lane == __ffsll((long long)m1) - 1) return 1;
+  return -1;
+}
+
 // One front-to-back sweep per pixel, with the forward's decisions: the colour
 // behind entry k is S_k = C_pixel - sum_{m<=k} c_m alpha_m T_m (C_pixel the
 // rendered value, background included), so neither the final transmittance
 // nor the contributor count is needed and nothing is replayed or divided.
 // Only its projection on dL/dC enters the gradient, so a pixel carries the
 // scalar D_k = dL/dC . S_k, updated by the entry's dL/dC . c_k.
-template <int TILE>
+// With ABS the kernel also adds the homodirectional view-space gradient of
+// each (view, Gaussian) pair into abs2d [V*N][2].
+template <int TILE, bool ABS>
 // (five wavefronts per SIMD: 96 registers, no spill; measured 10% faster than four)
 __global__ __launch_bounds__(BwdShape<TILE>::THREADS)
 __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_render_bwd(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     RasterConsts rc, const float* __restrict__ img, int loss_kind, const float* __restrict__ target,
-    const float* __restrict__ dl_dimage, float* __restrict__ grad2d) {
+    const float* __restrict__ dl_dimage, float* __restrict__ grad2d, float* __restrict__ abs2d) {
   using PM = PixMap<TILE, BwdShape<TILE>>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
   __shared__ BatchLds<PM> L;
@@ -538,6 +558,7 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
   const float fx = (float)pm.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const LaneRole role = wave_roles(lane);
+  const int arole = ABS ? abs_role(lane) : -1;
   // per pixel: transmittance in front of the current entry, dL/dC . (colour still behind it), dL/dC;
   // a pixel that has stopped gets row coordinate +inf (see k_render_fwd)
   float T[PPL], Dp[PPL], dl[PPL][3], fy[PPL];
@@ -565,6 +586,7 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
     Dp[p] = fmaf(dl[p][2], col[2], fmaf(dl[p][1], col[1], dl[p][0] * col[0]));
   }
   Acc6 acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  float amx = 0.0f, amy = 0.0f;  // ABS: the lane's sums of |dL_p/dmean| for the current entry
   SplatLoader ld;
   ld.fetch(rec, ids, s + (int)threadIdx.x, s, e);
   for (int base = s; base < e; base += NT) {
@@ -582,6 +604,9 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
       const float2 Cv = L.c[j];
       const float dx = fx - A.x;
       const RowTerms rt = row_terms(dx, A.z, A.w);
+      // the natural conic (a, b, c) from the staged base-2 factors
+      const float ca = (-2.0f * kLn2) * A.z, cb = -kLn2 * A.w, cc = (-2.0f * kLn2) * Bv.x;
+      const float tx = ABS ? ca * dx : 0.0f, ty = ABS ? cb * dx : 0.0f;
       bool any = false;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
@@ -615,17 +640,25 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
         acc.u += dLdp;
         acc.uy += uy;
         acc.uyy = fmaf(uy, dy, acc.uyy);
+        if (ABS) {
+          amx += fabsf(dLdp * fmaf(cb, dy, tx));
+          amy += fabsf(dLdp * fmaf(cc, dy, ty));
+        }
       }
       if (__ballot(any) != 0ull) {
         const float sx = dx * acc.u;
         const Red3 r = reduce_scatter(Acc9{sx, dx * sx, dx * acc.uy, acc.uyy, acc.r, acc.g, acc.b, acc.u, acc.uy});
-        const float ca = (-2.0f * kLn2) * A.z, cb = -kLn2 * A.w, cc = (-2.0f * kLn2) * Bv.x;
         const float ka = role.mean_x ? ca : (role.mean_y ? cb : role.k0c);
         const float kc = role.mean_x ? cb : (role.mean_y ? cc : 0.0f);
         const float k1 = role.opacity ? __builtin_amdgcn_rcpf(Bv.y) : role.k1c;  // a blended entry has opacity >= alpha_min
         const float val = fmaf(ka, r.k0, fmaf(kc, r.k2, k1 * r.k1));
         if (role.comp >= 0) atomicAdd(grad2d + (size_t)L.id[j] * GS_GRAD2D_FLOATS + role.comp, val);
         acc = Acc6{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (ABS) {
+          const float t = reduce_pair(amx, amy);
+          if (arole >= 0) atomicAdd(abs2d + (size_t)L.id[j] * 2 + arole, t);
+          amx = amy = 0.0f;
+        }
       }
     }
   }
@@ -830,17 +863,25 @@ static gs_status validate_grads(const gs_params* params, const gs_grads* grads) 
 }
 
 static void launch_raster_bwd(const ViewTable& vt, const gs_projected* proj, const gs_bins* bins, const gs_image* img,
-                              const gs_options* opts, const gs_loss* loss, float* g2, hipStream_t st) {
+                              const gs_options* opts, const gs_loss* loss, float* g2, float* a2, hipStream_t st) {
   const RasterConsts rc = consts_of(opts);
   const dim3 grid((unsigned)vt.total_tiles);
   const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
-#define GS_BWD(TILE, NT)                                                                                      \
-  hipLaunchKernelGGL((k_render_bwd<TILE>), grid, dim3(NT), 0, st, vt, proj->rec, bins->ids, rg, rc, img->rgb, \
-                     (int)loss->kind, loss->target, loss->dl_dimage, g2)
-  switch (opts->tile_size) {
-    case 8: GS_BWD(8, BwdShape<8>::THREADS); break;
-    case 16: GS_BWD(16, BwdShape<16>::THREADS); break;
-    default: GS_BWD(32, BwdShape<32>::THREADS); break;
+#define GS_BWD(TILE, ABS)                                                                                     \
+  hipLaunchKernelGGL((k_render_bwd<TILE, ABS>), grid, dim3(BwdShape<TILE>::THREADS), 0, st, vt, proj->rec,   \
+                     bins->ids, rg, rc, img->rgb, (int)loss->kind, loss->target, loss->dl_dimage, g2, a2)
+  if (a2) {
+    switch (opts->tile_size) {
+      case 8: GS_BWD(8, true); break;
+      case 16: GS_BWD(16, true); break;
+      default: GS_BWD(32, true); break;
+    }
+  } else {
+    switch (opts->tile_size) {
+      case 8: GS_BWD(8, false); break;
+      case 16: GS_BWD(16, false); break;
+      default: GS_BWD(32, false); break;
+    }
   }
 #undef GS_BWD
 }
@@ -857,7 +898,21 @@ extern "C" gs_status gs_raster_bwd(const gs_projected* proj, int64_t n, const gs
   if ((s = validate_loss_bwd(loss, img)) != GS_OK) return s;
   if (!grad2d) return fail(GS_ERR_INVALID_VALUE, "grad2d is NULL");
   const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
-  launch_raster_bwd(vt, proj, bins, img, opts, loss, grad2d, as_stream(stream));
+  launch_raster_bwd(vt, proj, bins, img, opts, loss, grad2d, nullptr, as_stream(stream));
+  return check_launch("raster backward");
+}
+
+extern "C" gs_status gs_raster_bwd_abs(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_image* img,
+                                       const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                                       const gs_loss* loss, float* grad2d, float* abs_grad2d, void* stream) {
+  using namespace gs;
+  gs_status s;
+  if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
+  if (n < 1) return fail(GS_ERR_INVALID_VALUE, "n must be >= 1");
+  if ((s = validate_loss_bwd(loss, img)) != GS_OK) return s;
+  if (!grad2d || !abs_grad2d) return fail(GS_ERR_INVALID_VALUE, "grad2d and abs_grad2d are required");
+  const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
+  launch_raster_bwd(vt, proj, bins, img, opts, loss, grad2d, abs_grad2d, as_stream(stream));
   return check_launch("raster backward");
 }
 
@@ -893,7 +948,7 @@ extern "C" gs_status gs_render_bwd(const gs_params* params, const gs_projected* 
   float* g2 = static_cast<float*>(workspace);
   hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)std::min<size_t>(8192, (g2n + 255) / 256)), dim3(256), 0, st, g2,
                      (uint64_t)g2n);
-  launch_raster_bwd(vt, proj, bins, img, opts, loss, g2, st);
+  launch_raster_bwd(vt, proj, bins, img, opts, loss, g2, nullptr, st);
   if ((s = check_launch("render backward")) != GS_OK) return s;
   return launch_project_bwd(params, cams, n_views, opts, proj->tiles_touched, g2, grads, st);
 }

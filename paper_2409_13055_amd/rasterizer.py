@@ -60,6 +60,12 @@ class GaussianParams:
         return GaussianParams(f(scene.means), f(scene.log_scales), f(scene.quats), f(scene.opacity_logits),
                               f(scene.sh_dc), f(scene.sh_rest), scene.sh_degree)
 
+    @staticmethod
+    def empty(n: int, sh_degree: int, device="cuda") -> "GaussianParams":
+        K = (sh_degree + 1) ** 2
+        e = lambda *shape: torch.empty(*shape, dtype=torch.float32, device=device)  # noqa: E731
+        return GaussianParams(e(n, 3), e(n, 3), e(n, 4), e(n), e(n, 3), e(n, K - 1, 3), sh_degree)
+
     def tensors(self) -> List[torch.Tensor]:
         return [getattr(self, k) for k in PARAM_NAMES]
 
@@ -217,10 +223,16 @@ class Rasterizer:
             loss.kind, loss.target = L.GS_LOSS_L1, _p(target)
         return loss
 
-    def raster_bwd(self, fr: Frame, grad2d: torch.Tensor, target=None, dl_dimage=None):
-        """Adds the image-space gradients of this frame into grad2d ([n_views*n, 9] FP32)."""
-        L.gs_raster_bwd(fr.c_proj(), self.n, fr.c_bins(), fr.c_image(), self.cams, self.n_views, self.opts,
-                        self._loss(target, dl_dimage), grad2d.data_ptr(), _stream())
+    def raster_bwd(self, fr: Frame, grad2d: torch.Tensor, target=None, dl_dimage=None,
+                   abs2d: Optional[torch.Tensor] = None):
+        """Adds the image-space gradients of this frame into grad2d ([n_views*n, 9] FP32), and with
+        abs2d ([n_views*n, 2]) the homodirectional view-space gradient (gs_raster_bwd_abs)."""
+        if abs2d is None:
+            L.gs_raster_bwd(fr.c_proj(), self.n, fr.c_bins(), fr.c_image(), self.cams, self.n_views, self.opts,
+                            self._loss(target, dl_dimage), grad2d.data_ptr(), _stream())
+        else:
+            L.gs_raster_bwd_abs(fr.c_proj(), self.n, fr.c_bins(), fr.c_image(), self.cams, self.n_views, self.opts,
+                                self._loss(target, dl_dimage), grad2d.data_ptr(), abs2d.data_ptr(), _stream())
 
     def project_bwd(self, params: GaussianParams, fr: Frame, grad2d: torch.Tensor, grads: GaussianParams):
         """Adds the parameter gradients chained from grad2d into grads."""
@@ -313,12 +325,16 @@ class FusedAdam:
     """Adam over the six parameter groups in one gs_adam_step launch (step counter on the device)."""
 
     def __init__(self, params: GaussianParams, grads: GaussianParams, lrs: Dict[str, float],
-                 betas=(0.9, 0.999), eps=1e-15):
+                 betas=(0.9, 0.999), eps=1e-15, exp_avg: Optional[GaussianParams] = None,
+                 exp_avg_sq: Optional[GaussianParams] = None, d_step: Optional[torch.Tensor] = None):
+        """exp_avg, exp_avg_sq, d_step: an existing optimiser state to continue (density control
+        hands over the moments of the new Gaussian set); None starts from zero."""
         self.params, self.grads = params, grads
-        self.exp_avg = params.zeros_like()
-        self.exp_avg_sq = params.zeros_like()
+        self.lrs = dict(lrs)
+        self.exp_avg = exp_avg if exp_avg is not None else params.zeros_like()
+        self.exp_avg_sq = exp_avg_sq if exp_avg_sq is not None else params.zeros_like()
         self.betas, self.eps = betas, eps
-        self.d_step = torch.zeros(1, dtype=torch.int32, device=params.means.device)
+        self.d_step = d_step if d_step is not None else torch.zeros(1, dtype=torch.int32, device=params.means.device)
         names = [k for k in PARAM_NAMES if getattr(params, k).numel() > 0]
         self.groups = (L.gs_adam_group * len(names))()
         for i, k in enumerate(names):
@@ -352,10 +368,18 @@ class MappingStep:
     clears them) runs as its own call."""
 
     def __init__(self, params: GaussianParams, cameras, targets, lrs=None, tile_size=16, checkpoint=False,
-                 with_adam=True, fuse_adam=True, ssim_lambda: float = 0.0, adam: Optional[FusedAdam] = None, **opt):
+                 with_adam=True, fuse_adam=True, ssim_lambda: float = 0.0, adam: Optional[FusedAdam] = None,
+                 density: Optional["DensityControl"] = None, **opt):
         """`adam`: an existing FusedAdam over `params` to step (steps that train the same Gaussians on
-        other views or pyramid levels share its moments and step count); None makes a new one."""
+        other views or pyramid levels share its moments and step count); None makes a new one.
+        `density`: a DensityControl whose statistics every iteration adds to (the raster backward then
+        also forms the homodirectional gradient); densify() hands over to a step on the new set."""
         self.params = params
+        self.density = density
+        self._init = dict(cameras=list(cameras), lrs=lrs, tile_size=tile_size, checkpoint=checkpoint,
+                          with_adam=with_adam, fuse_adam=fuse_adam, ssim_lambda=ssim_lambda, opt=dict(opt))
+        if density is not None and not (with_adam and fuse_adam):
+            raise ValueError("density control runs with the fused projection backward and Adam")
         # eq. (2): with ssim_lambda > 0 the loss is (1 - lambda) L1 + lambda (1 - SSIM) (3DGS: 0.2),
         # computed by gs_photometric_loss after the forward; 0 keeps the L1 term fused into the forward
         self.ssim_lambda = float(ssim_lambda)
@@ -376,6 +400,9 @@ class MappingStep:
         self.frame = None
         self.graph = None
         self._side = None  # stream of the gradient-buffer clear, which overlaps the forward
+        self.abs2d = None
+        if density is not None:
+            self.abs2d = torch.empty(self.rast.n_views * params.n, 2, dtype=torch.float32, device=params.means.device)
 
     def size(self):
         """Eager warm-up that sizes the pair capacity (host syncs)."""
@@ -428,23 +455,33 @@ class MappingStep:
             self._side.wait_stream(cur)
             with torch.cuda.stream(self._side):
                 r.grad2d.zero_()
+                if self.abs2d is not None:
+                    self.abs2d.zero_()
             self._forward(fr)
             cur.wait_stream(self._side)
-            r.raster_bwd(fr, r.grad2d, **self._loss_args())
+            r.raster_bwd(fr, r.grad2d, abs2d=self.abs2d, **self._loss_args())
             r.project_bwd_adam(self.params, fr, r.grad2d, self.adam)
+            if self.density is not None:
+                self.density.accumulate(r, fr, r.grad2d, self.abs2d)
             return
         self._forward(fr, mark)
         if self.fuse_adam:
             g2 = r.grad2d
             g2.zero_()
+            if self.abs2d is not None:
+                self.abs2d.zero_()
             if mark:
                 mark("clear_grad2d")
-            r.raster_bwd(fr, g2, **self._loss_args())
+            r.raster_bwd(fr, g2, abs2d=self.abs2d, **self._loss_args())
             if mark:
                 mark("raster_bwd")
             r.project_bwd_adam(self.params, fr, g2, self.adam)
             if mark:
                 mark("project_bwd_adam")
+            if self.density is not None:
+                self.density.accumulate(r, fr, g2, self.abs2d)
+                if mark:
+                    mark("density_accumulate")
             return
         if mark is None:
             r.render_bwd(self.params, fr, self.grads, **self._loss_args())
@@ -463,6 +500,18 @@ class MappingStep:
 
     def overflowed(self) -> bool:
         return int(self.frame.d_overflow.item()) != 0
+
+    def densify(self, generator: Optional[torch.Generator] = None) -> "MappingStep":
+        """One density-control step (Sec. III-B) on this step's Gaussians; returns a MappingStep over
+        the new set, sized, with the optimiser state handed over (a captured graph is not carried:
+        capture() again).  Synchronises with the host (the new size is read back)."""
+        new_params, new_adam = self.density.apply(self.params, self.adam, generator=generator)
+        k = self._init
+        st = MappingStep(new_params, k["cameras"], self.target, lrs=k["lrs"], tile_size=k["tile_size"],
+                         checkpoint=k["checkpoint"], with_adam=k["with_adam"], fuse_adam=k["fuse_adam"],
+                         ssim_lambda=k["ssim_lambda"], adam=new_adam, density=self.density, **k["opt"])
+        st.size()
+        return st
 
     def capture(self):
         """Record one iteration into a HIP graph (after size())."""
@@ -652,3 +701,72 @@ class PyramidMappingStep:
         st = self.run_levels([self.level_at(self.iteration)] * self.n_views)
         self.iteration += 1
         return st
+
+
+class DensityControl:
+    """Adaptive density control of Sec. III-B (AbsGS densification with the 3DGS split and clone
+    parameters, pruning by opacity): per-Gaussian statistics that every iteration adds to
+    (gs_density_accumulate), and the densify-and-prune step (gs_density_plan, then
+    gs_density_apply into new arrays).  The paper runs the step every 1000 iterations (Sec. IV-A).
+
+    `extent` defaults to the 3DGS scene extent of `cameras` (gs_scene_extent); other keyword
+    arguments override gs_default_density_config (grad_threshold, percent_dense, min_opacity,
+    split_scale_div)."""
+
+    def __init__(self, n: int, cameras, device="cuda", extent: Optional[float] = None, **cfg):
+        L.load()
+        self.device = torch.device(device)
+        cams = L.make_cameras(list(cameras))
+        self.cfg = L.default_density_config(**cfg)
+        self.cfg.extent = float(extent) if extent is not None else L.gs_scene_extent(cams, len(cameras))
+        self.d_counts = torch.zeros(3, dtype=torch.int32, device=self.device)
+        self._alloc(n)
+
+    def _alloc(self, n: int):
+        self.n = int(n)
+        self.grad_accum = torch.zeros(self.n, dtype=torch.float32, device=self.device)
+        self.abs_accum = torch.zeros(self.n, dtype=torch.float32, device=self.device)
+        self.count = torch.zeros(self.n, dtype=torch.int32, device=self.device)
+        self.ws_bytes = L.gs_density_workspace_size(self.n)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self._stats = L.gs_density_stats(_p(self.grad_accum), _p(self.abs_accum), _p(self.count))
+
+    def accumulate(self, rast: Rasterizer, fr: Frame, grad2d: torch.Tensor, abs2d: torch.Tensor):
+        L.gs_density_accumulate(fr.c_proj(), rast.n, rast.cams, rast.n_views, _p(grad2d), _p(abs2d), self._stats,
+                                _stream())
+
+    def plan(self, params: GaussianParams):
+        """Classify (device) and return (kept, cloned, split) (host sync)."""
+        if params.n != self.n:
+            raise ValueError("the statistics belong to a Gaussian set of another size")
+        L.gs_density_plan(params.c_params(), self._stats, self.cfg, _p(self.d_counts), self.ws.data_ptr(),
+                          self.ws_bytes, _stream())
+        kept, cloned, split = (int(x) for x in self.d_counts.cpu())
+        return kept, cloned, split
+
+    def apply(self, params: GaussianParams, adam: FusedAdam, generator: Optional[torch.Generator] = None,
+              eps: Optional[torch.Tensor] = None):
+        """plan() then the new Gaussian set: returns (new params, FusedAdam over them continuing the
+        step count).  The split children's standard normal draws are `eps` ([split, 2, 3]) or drawn
+        with `generator`.  The statistics restart at zero for the new set."""
+        kept, cloned, split = self.plan(params)
+        n_out = kept + cloned + 2 * split
+        if eps is None:
+            eps = torch.randn(split, 2, 3, generator=generator, dtype=torch.float32, device=self.device)
+        eps = eps.contiguous()
+        D = params.sh_degree
+        new_p = GaussianParams.empty(n_out, D, self.device)
+        new_m = GaussianParams.empty(n_out, D, self.device)
+        new_v = GaussianParams.empty(n_out, D, self.device)
+
+        def c_of(t: GaussianParams) -> L.gs_params:
+            return t.c_params()
+
+        L.gs_density_apply(params.c_params(), c_of(adam.exp_avg), c_of(adam.exp_avg_sq), self.cfg, _p(eps),
+                           eps.numel(), n_out, new_p.c_grads(), new_m.c_grads(), new_v.c_grads(),
+                           self.ws.data_ptr(), self.ws_bytes, _stream())
+        self._alloc(n_out)
+        new_adam = FusedAdam(new_p, new_p.zeros_like(), adam.lrs, adam.betas, adam.eps, exp_avg=new_m,
+                             exp_avg_sq=new_v, d_step=adam.d_step)
+        self.last_counts = (kept, cloned, split)
+        return new_p, new_adam

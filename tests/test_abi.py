@@ -159,3 +159,49 @@ def test_pyramid_camera_host_arithmetic_and_reduce_validation(L, oracle_lib):
         L.gs_pyramid_reduce(c2, 2, C.c_void_p(0x100000), C.c_void_p(0x100000 + 4 * n_src - 4), None)
     with pytest.raises(L.GsError, match="n_views"):
         L.gs_pyramid_reduce(c2, 0, C.c_void_p(0x100000), C.c_void_p(0x900000), None)
+
+
+def test_density_control_host_entry_points(L, oracle_lib):
+    """Defaults, the scene extent (host arithmetic, against the oracle) and argument validation of
+    the density-control calls; nothing is launched."""
+    from paper_2409_13055_amd import synthetic as S
+    O = oracle_lib
+    c = L.default_density_config()
+    assert (c.grad_threshold, c.percent_dense, c.min_opacity, c.split_scale_div, c.extent) == pytest.approx(
+        (0.0002, 0.01, 0.005, 1.6, 1.0), rel=1e-7)
+    cams = S.make_config(5, n=10).cameras
+    ext = L.gs_scene_extent(L.make_cameras(cams), len(cams))
+    assert ext == pytest.approx(O.scene_extent(cams), rel=1e-6)
+    assert L.gs_density_workspace_size(1000) >= 1000 + 2 * 3 * 4 * 4
+    p = L.gs_params()
+    p.n, p.sh_degree = 1000, 0
+    p.means, p.log_scales, p.quats = C.c_void_p(0x1000), C.c_void_p(0x2000), C.c_void_p(0x3000)
+    p.opacity_logits, p.sh_dc = C.c_void_p(0x4000), C.c_void_p(0x5000)
+    st = L.gs_density_stats(C.c_void_p(0x6000), C.c_void_p(0x7000), C.c_void_p(0x8000))
+    wsb = L.gs_density_workspace_size(1000)
+    ws, cnt = C.c_void_p(0x100000), C.c_void_p(0x9000)
+    with pytest.raises(L.GsError, match="statistics"):
+        L.gs_density_plan(p, L.gs_density_stats(), c, cnt, ws, wsb, None)
+    with pytest.raises(L.GsError, match="min_opacity"):
+        L.gs_density_plan(p, st, L.default_density_config(min_opacity=1.0), cnt, ws, wsb, None)
+    with pytest.raises(L.GsError, match="extent"):
+        L.gs_density_plan(p, st, L.default_density_config(extent=0.0), cnt, ws, wsb, None)
+    with pytest.raises(L.GsError, match="CAPACITY"):
+        L.gs_density_plan(p, st, c, cnt, ws, wsb - 1, None)
+    m = L.gs_params()
+    m.n, m.sh_degree = 999, 0
+    m.means, m.log_scales, m.quats = C.c_void_p(0x1000), C.c_void_p(0x2000), C.c_void_p(0x3000)
+    m.opacity_logits, m.sh_dc = C.c_void_p(0x4000), C.c_void_p(0x5000)
+    out = L.gs_grads()
+    with pytest.raises(L.GsError, match="moments"):
+        L.gs_density_apply(p, m, m, c, None, 0, 10, out, out, out, ws, wsb, None)
+    with pytest.raises(L.GsError, match="n_out"):
+        L.gs_density_apply(p, p, p, c, None, 0, 3001, out, out, out, ws, wsb, None)
+    with pytest.raises(L.GsError, match="eps"):
+        L.gs_density_apply(p, p, p, c, None, 6, 10, out, out, out, ws, wsb, None)
+    with pytest.raises(L.GsError, match="out_params"):
+        L.gs_density_apply(p, p, p, c, None, 0, 10, out, out, out, ws, wsb, None)
+    cc = L.make_cameras([S.pinhole(64, 48, 50.0)])
+    proj = L.gs_projected()
+    with pytest.raises(L.GsError, match="tiles_touched"):
+        L.gs_density_accumulate(proj, 1000, cc, 1, C.c_void_p(0x1000), C.c_void_p(0x2000), st, None)

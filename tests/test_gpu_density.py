@@ -1,0 +1,161 @@
+"""Adaptive density control (Sec. III-B) on the GPU against the FP64 oracle: the homodirectional
+view-space gradient of the raster backward (gs_raster_bwd_abs), the statistics
+(gs_density_accumulate) and the densify-and-prune step (gs_density_plan / gs_density_apply).
+
+Bars: abs2d like the other image-space gradients (relative L2 1e-3 per component, pinned lists:
+FP32 atomics vary the order); statistics relative 1e-5 (FP32 norms and sums of FP32 inputs); the
+classes and the counts exactly (both sides decide in FP32 on the same inputs); copied rows and
+zeroed moments bit-exact; split children's means and log-scales within 2e-6 absolute (FP32
+rotation, exp and sums of values of order 1).
+"""
+import numpy as np
+import pytest
+
+from paper_2409_13055_amd import synthetic as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle.oracle as O  # noqa: E402
+from paper_2409_13055_amd import rasterizer as R  # noqa: E402
+from tests import gpu_util as U  # noqa: E402
+
+DEV = "cuda"
+
+
+def small_scene(seed=3):
+    cams = [S.pinhole(130, 97, 110.0), S.pinhole(100, 76, 90.0, *S.look_at((0.35, -0.1, -0.5), (0.0, 0.0, 3.0)))]
+    return S.make_scene(seed, 3000, 1, cams, "box", log_scale_mu=-3.3, log_scale_sigma=0.6, logit_sigma=1.5)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_homodirectional_gradient_matches_oracle(tile):
+    sc = small_scene()
+    g = U.run_gpu(sc, tile=tile, backward=False)
+    rast, fr = g["rast"], g["frame"]
+    n2 = rast.n_views * rast.n
+    g2 = torch.zeros(n2, 9, device=DEV)
+    a2 = torch.zeros(n2, 2, device=DEV)
+    g2_plain = torch.zeros(n2, 9, device=DEV)
+    target = R.pack_images(sc.targets, DEV)
+    rast.raster_bwd(fr, g2, target=target, abs2d=a2)
+    rast.raster_bwd(fr, g2_plain, target=target)
+    torch.cuda.synchronize()
+    _, dl = O.l1_loss(g["image"], sc.targets, sc.cameras)
+    ref_g2, ref_a2 = O.render_backward_abs(sc.cameras, O.Options(tile=tile), U.gpu_rec_to_oracle(g["rec"]), g["ids"],
+                                           g["ranges"], dl)
+    got_a2 = a2.cpu().numpy().astype(np.float64)
+    got_g2 = g2.cpu().numpy().astype(np.float64)
+    assert np.abs(ref_a2).sum() > 0
+    for c in range(2):
+        assert U.rel_l2(got_a2[:, c], ref_a2[:, c]) <= 1e-3, (c, U.rel_l2(got_a2[:, c], ref_a2[:, c]))
+    # the abs variant's image-space gradients are those of the plain backward (summation order aside)
+    for c in range(9):
+        assert U.rel_l2(got_g2[:, c], g2_plain.cpu().numpy()[:, c]) <= 1e-5
+        assert U.rel_l2(got_g2[:, c], ref_g2[:, c]) <= 1e-3
+    # every pixel magnitude is at least its share of the signed sum
+    assert np.all(got_a2 >= np.abs(got_g2[:, :2]) * (1 - 1e-4) - 1e-9)
+
+
+def test_statistics_match_oracle_over_iterations():
+    sc = small_scene(5)
+    params = R.GaussianParams.from_scene(sc, DEV)
+    dc = R.DensityControl(params.n, sc.cameras, device=DEV)
+    st = R.MappingStep(params, sc.cameras, sc.targets, lrs=dict(S.DEFAULT_LRS), tile_size=16, density=dc)
+    st.size()
+    ga, aa, cnt = np.zeros(params.n), np.zeros(params.n), np.zeros(params.n, np.int64)
+    for _ in range(3):
+        st.run()
+        torch.cuda.synchronize()
+        O.density_accumulate(ga, aa, cnt, st.frame.tiles.cpu().numpy(),
+                             st.rast.grad2d.cpu().numpy().astype(np.float64).reshape(-1, 9),
+                             st.abs2d.cpu().numpy().astype(np.float64), sc.cameras)
+    assert cnt.max() == 3 * len(sc.cameras) and cnt.min() >= 0
+    np.testing.assert_array_equal(dc.count.cpu().numpy(), cnt)
+    np.testing.assert_allclose(dc.grad_accum.cpu().numpy(), ga, rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(dc.abs_accum.cpu().numpy(), aa, rtol=1e-5, atol=1e-12)
+
+
+def gpu_to_oracle_params(p: R.GaussianParams) -> "O.Params":
+    sh = torch.cat([p.sh_dc[:, None, :], p.sh_rest], 1)
+    f = lambda t: t.cpu().numpy().astype(np.float64)  # noqa: E731
+    return O.Params(f(p.means), f(p.log_scales), f(p.quats), f(p.opacity_logits), f(sh), p.sh_degree)
+
+
+def check_density_step(sc, seed, tau=0.0002):
+    params = R.GaussianParams.from_scene(sc, DEV)
+    n = params.n
+    rng = np.random.default_rng(seed)
+    # statistics with every case: about a third selected (a few exactly at the threshold), some never seen
+    count = rng.integers(0, 6, n).astype(np.int32)
+    abs_acc = (rng.random(n) * 3.0 * np.float32(tau) * count).astype(np.float32)
+    at = rng.random(n) < 0.02
+    abs_acc[at] = np.float32(tau) * count[at].astype(np.float32)
+    adam = R.FusedAdam(params, params.zeros_like(), dict(S.DEFAULT_LRS))
+    for t in adam.exp_avg.tensors() + adam.exp_avg_sq.tensors():
+        if t.numel():
+            t.copy_(torch.randn(t.shape, device=DEV))
+    adam.d_step.fill_(7)
+    dc = R.DensityControl(n, sc.cameras, device=DEV, extent=5.0, grad_threshold=tau)
+    dc.abs_accum.copy_(torch.as_tensor(abs_acc, device=DEV))
+    dc.count.copy_(torch.as_tensor(count, device=DEV))
+    P, M, V = gpu_to_oracle_params(params), gpu_to_oracle_params(adam.exp_avg), gpu_to_oracle_params(adam.exp_avg_sq)
+    keep, clone, split = O.density_classes(P, abs_acc, count, O.DensityConfig(extent=5.0, grad_threshold=float(np.float32(tau))))
+    ns = int(split.sum())
+    eps = torch.randn(ns, 2, 3, device=DEV)
+    new_p, new_adam = dc.apply(params, adam, eps=eps)
+    torch.cuda.synchronize()
+    assert dc.last_counts == (int(keep.sum()), int(clone.sum()), ns)
+    assert ns > 0 and clone.sum() > 0 and (~keep & ~split).sum() > 0  # every class is exercised
+    refP, refM, refV, _ = O.densify_and_prune(P, M, V, abs_acc.astype(np.float64), count,
+                                              O.DensityConfig(extent=5.0, grad_threshold=float(np.float32(tau))),
+                                              eps.cpu().numpy().astype(np.float64))
+    got = gpu_to_oracle_params(new_p)
+    nk, nc = int(keep.sum()), int(clone.sum())
+    for name in ("quats", "opacity_logits", "sh"):
+        np.testing.assert_array_equal(getattr(got, name), getattr(refP, name), err_msg=name)
+    np.testing.assert_array_equal(got.means[:nk + nc], refP.means[:nk + nc])
+    np.testing.assert_array_equal(got.log_scales[:nk + nc], refP.log_scales[:nk + nc])
+    np.testing.assert_allclose(got.means[nk + nc:], refP.means[nk + nc:], rtol=0, atol=2e-6)
+    np.testing.assert_allclose(got.log_scales[nk + nc:], refP.log_scales[nk + nc:], rtol=0, atol=2e-6)
+    for gm, rm in ((new_adam.exp_avg, refM), (new_adam.exp_avg_sq, refV)):
+        g = gpu_to_oracle_params(gm)
+        for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+            np.testing.assert_array_equal(getattr(g, name), getattr(rm, name), err_msg=name)
+    assert int(new_adam.d_step.item()) == 7
+    assert dc.n == new_p.n and int(dc.count.sum().item()) == 0
+    return new_p
+
+
+def test_density_step_matches_oracle_small():
+    sc = S.make_scene(2, 5000, 2, [S.pinhole(64, 48, 50.0)], "box", log_scale_mu=-2.0, log_scale_sigma=1.0,
+                      logit_sigma=3.0)
+    check_density_step(sc, 11)
+
+
+def test_density_step_matches_oracle_full_size():
+    # the 2 M Gaussians of the 16-view stress workload (SH degree 3)
+    sc = S.make_config(5)
+    check_density_step(sc, 12)
+
+
+def test_mapping_step_densifies_and_continues():
+    sc = small_scene(9)
+    params = R.GaussianParams.from_scene(sc, DEV)
+    dc = R.DensityControl(params.n, sc.cameras, device=DEV, grad_threshold=1e-6)
+    st = R.MappingStep(params, sc.cameras, sc.targets, lrs=dict(S.DEFAULT_LRS), tile_size=16, density=dc)
+    st.size()
+    for _ in range(2):
+        st.run()
+    st2 = st.densify(generator=torch.Generator(device=DEV).manual_seed(1))
+    kept, cloned, split = dc.last_counts
+    assert st2.params.n == kept + cloned + 2 * split and cloned + split > 0
+    st2.capture()  # one eager iteration, then a recorded one
+    st2.replay()
+    torch.cuda.synchronize()
+    assert int(st2.adam.d_step.item()) == 4
+    assert int(dc.count.max().item()) == 2 * len(sc.cameras)
+    assert np.isfinite(st2.loss.cpu().numpy()).all()
