@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-ssim", action="store_true", help="skip the measurement of eq. (2) with its SSIM term")
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the measurement of adaptive density control (statistics and densify-and-prune)")
     ap.add_argument("--no-pyramid", action="store_true",
                     help="skip the measurement of the image pyramid and of the coarse-level iterations")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -265,6 +267,66 @@ def main():
             del st
         del pyr
 
+    density = None
+    if not args.no_density and with_adam:
+        # adaptive density control (Sec. III-B): the iteration with its statistics (homodirectional
+        # gradient in the raster backward, gs_density_accumulate), then one densify-and-prune step
+        # (plan, apply) on the statistics those iterations gathered
+        dc = R.DensityControl(params.n, sc.cameras, device=dev)
+        st = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
+                           with_adam=with_adam, density=dc)
+        st.size()
+        if use_graph:
+            st.capture()
+        run_d = st.replay if use_graph else st.run
+        reset(st)
+        for t in (dc.grad_accum, dc.abs_accum, dc.count):
+            t.zero_()
+        for _ in range(args.warmup):
+            run_d()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            run_d()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_d = e0.elapsed_time(e1) / args.steps
+        st_stages, _ = stage_breakdown(st, args.steps)
+        kept, cloned, split = dc.plan(params)
+        e0.record()
+        for _ in range(args.steps):
+            dc.plan_launch(params)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_plan = e0.elapsed_time(e1) / args.steps
+        n_out = kept + cloned + 2 * split
+        D = params.sh_degree
+        outs = [R.GaussianParams.empty(n_out, D, dev) for _ in range(3)]
+        eps = torch.randn(split, 2, 3, device=dev)
+        dc.plan_launch(params)
+        e0.record()
+        for _ in range(args.steps):
+            dc.apply_into(params, st.adam, eps, *outs)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_apply = e0.elapsed_time(e1) / args.steps
+        pn = 11 + 3 * (D + 1) ** 2
+        # parameters and both moments: rows read for every surviving source, rows written for the new set
+        alg = 3 * 4 * pn * (kept + cloned + split) + 3 * 4 * pn * n_out
+        gbs = alg / (ms_apply * 1e-3) / 1e9
+        density = {"ms_per_step": round(ms_d, 4), "value": round(mpix / (ms_d * 1e-3), 2),
+                   "overhead_vs_value": round(ms_d / ms - 1.0, 4),
+                   "raster_bwd_abs_ms": st_stages["raster_bwd"],
+                   "accumulate_ms": st_stages["density_accumulate"],
+                   "plan_ms": round(ms_plan, 4), "apply_ms": round(ms_apply, 4), "apply_alg_bytes": alg,
+                   "apply_GBps": round(gbs, 1), "apply_hbm_frac": round(gbs / 8000.0, 4),
+                   "counts": {"kept": kept, "cloned": cloned, "split": split, "n_out": n_out},
+                   "statistics_iterations": args.warmup + 2 * args.steps}
+        log(f"[bench] density tracking: {ms_d:.3f} ms/step (raster_bwd_abs {st_stages['raster_bwd']} ms, "
+            f"accumulate {st_stages['density_accumulate']} ms); plan {ms_plan:.3f} ms, apply {ms_apply:.3f} ms "
+            f"({gbs:.0f} GB/s alg), {kept}+{cloned}+2x{split} -> {n_out}")
+        del st, outs, dc
+
     roof = roofline(step, sc, stages, work)
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, tile)
     out = {
@@ -288,6 +350,7 @@ def main():
         "per_view": per_view,
         "ssim": ssim,
         "pyramid": pyramid,
+        "density": density,
         "stages_ms": stages,
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -308,6 +371,8 @@ def stage_breakdown(step, iters):
     import torch
     if step.fuse_adam:
         names = ["project", "bin_sort", "render_fwd", "clear_grad2d", "raster_bwd", "project_bwd_adam"]
+        if step.density is not None:
+            names.append("density_accumulate")
     else:
         names = ["project", "bin_sort", "render_fwd", "clear_grad2d", "raster_bwd", "project_bwd"]
         if step.adam is not None:

@@ -24,9 +24,10 @@
 // Plan and apply are two calls because the caller allocates the new arrays
 // from the counts the plan writes.  The plan classifies each Gaussian and
 // counts the classes per 256-Gaussian block, one block scans the counts; the
-// apply recomputes each Gaussian's rank inside its block from ballots and
-// writes its rows at the block's offset plus the rank, so every class stays in
-// the original order.  All kernels are bound by HBM traffic.
+// apply recomputes each Gaussian's rank inside its block from ballots, so
+// every class stays in the original order, and copies the block's rows group
+// by group with consecutive threads on consecutive floats.  All kernels are
+// bound by HBM traffic.
 #include <cmath>
 #include <string>
 
@@ -198,83 +199,103 @@ struct DensRows {
   float* om[6];
   float* ov[6];
 };
-constexpr int kWidth[5] = {3, 3, 4, 1, 3};  // floats per Gaussian of the first five groups
 
-__device__ inline int group_width(int g, int rest) { return g < 5 ? kWidth[g] : rest; }
+// Destinations of a block's rows, -1 where a row does not go: kept, clone, first and second child.
+struct DensDst {
+  int64_t keep[kDensThreads], clone[kDensThreads], child1[kDensThreads], child2[kDensThreads];
+};
 
-__device__ inline void copy_row(const float* src, float* dst, int64_t i, int64_t j, int w) {
-  for (int c = 0; c < w; ++c) dst[j * w + c] = src[i * w + c];
+// One parameter group's rows of the block (W floats per Gaussian), copied cooperatively: consecutive
+// threads take consecutive floats of the block's source rows, so the loads are coalesced, and as
+// every class keeps the source order, consecutive rows of a class land on consecutive destination
+// rows, so the stores are too.  New Gaussians get zero moments; CHILD copies the parameter into the
+// split children (the means and log-scales of a child are computed, not copied).
+template <int W, bool CHILD>
+__device__ inline void scatter_group(const float* __restrict__ src, const float* __restrict__ sm,
+                                     const float* __restrict__ sv, float* __restrict__ dp, float* __restrict__ dm,
+                                     float* __restrict__ dv, int64_t i0, int rows, const DensDst& d) {
+  if (W == 0) return;
+  for (int f = threadIdx.x; f < rows * W; f += kDensThreads) {
+    const int r = f / W, col = f - r * W;
+    const int64_t jk = d.keep[r], jc = d.clone[r], j1 = d.child1[r], j2 = d.child2[r];
+    if ((jk & jc & j1 & j2) < 0) continue;  // all -1: a pruned or split-only row with nothing to copy
+    const int64_t si = (i0 + r) * W + col;
+    if (jk >= 0) {
+      dp[jk * W + col] = src[si];
+      dm[jk * W + col] = sm[si];
+      dv[jk * W + col] = sv[si];
+    }
+    if (jc >= 0) {
+      dp[jc * W + col] = src[si];
+      dm[jc * W + col] = 0.0f;
+      dv[jc * W + col] = 0.0f;
+    }
+    if (j1 >= 0) {
+      if (CHILD) dp[j1 * W + col] = src[si];
+      dm[j1 * W + col] = 0.0f;
+      dv[j1 * W + col] = 0.0f;
+    }
+    if (j2 >= 0) {
+      if (CHILD) dp[j2 * W + col] = src[si];
+      dm[j2 * W + col] = 0.0f;
+      dv[j2 * W + col] = 0.0f;
+    }
+  }
 }
-__device__ inline void zero_row(float* dst, int64_t j, int w) {
-  for (int c = 0; c < w; ++c) dst[j * w + c] = 0.0f;
-}
 
-__global__ __launch_bounds__(kDensThreads) void k_density_scatter(int64_t n, int rest, DensRows r, DensCfg k,
+template <int D>
+__global__ __launch_bounds__(kDensThreads) void k_density_scatter(int64_t n, DensRows r, DensCfg k,
                                                                     const uint8_t* __restrict__ cls,
                                                                     const int32_t* __restrict__ block_offs,
                                                                     const int32_t* __restrict__ totals,
                                                                     const float* __restrict__ eps, int64_t n_eps,
                                                                     int64_t n_out) {
-  const int64_t i = (int64_t)blockIdx.x * kDensThreads + threadIdx.x;
+  constexpr int REST = 3 * ((D + 1) * (D + 1) - 1);
+  __shared__ DensDst d;
+  const int64_t i0 = (int64_t)blockIdx.x * kDensThreads, i = i0 + threadIdx.x;
+  const int rows = (int)(n - i0 < kDensThreads ? n - i0 : kDensThreads);
   const uint8_t c = i < n ? cls[i] : (uint8_t)0;
   const BlockRanks br = block_ranks(c);
-  if (c == 0) return;
   const int64_t K = totals[0], C = totals[1], S = totals[2];
   const int32_t* off = block_offs + (int64_t)blockIdx.x * 3;
-  if (c & kKeep) {
-    const int64_t j = off[0] + br.rank[0];
-    if (j < n_out)
-      for (int g = 0; g < 6; ++g) {
-        const int w = group_width(g, rest);
-        if (w == 0) continue;
-        copy_row(r.p[g], r.op[g], i, j, w);
-        copy_row(r.m[g], r.om[g], i, j, w);
-        copy_row(r.v[g], r.ov[g], i, j, w);
-      }
-  }
-  if (c & kClone) {
-    const int64_t j = K + off[1] + br.rank[1];
-    if (j < n_out)
-      for (int g = 0; g < 6; ++g) {
-        const int w = group_width(g, rest);
-        if (w == 0) continue;
-        copy_row(r.p[g], r.op[g], i, j, w);
-        zero_row(r.om[g], j, w);
-        zero_row(r.ov[g], j, w);
-      }
-  }
-  if (c & kSplit) {
-    const int64_t q = off[2] + br.rank[2];
-    // rotation of the normalised quaternion (w, x, y, z) and the scales
-    const float qw = r.p[2][4 * i], qx = r.p[2][4 * i + 1], qy = r.p[2][4 * i + 2], qz = r.p[2][4 * i + 3];
-    const float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-    const float w_ = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
-    const float R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w_ * z),     2 * (x * z + w_ * y),
-                        2 * (x * y + w_ * z),     1 - 2 * (x * x + z * z), 2 * (y * z - w_ * x),
-                        2 * (x * z - w_ * y),     2 * (y * z + w_ * x),     1 - 2 * (x * x + y * y)};
-    float s[3];
-    for (int d = 0; d < 3; ++d) s[d] = expf(r.p[1][3 * i + d]);
-    for (int child = 0; child < 2; ++child) {
-      const int64_t j = K + C + (int64_t)child * S + q;
-      const int64_t e = (q * 2 + child) * 3;
-      if (j >= n_out || e + 3 > n_eps) continue;
-      float lv[3];
-      for (int d = 0; d < 3; ++d) lv[d] = s[d] * eps[e + d];
-      for (int d = 0; d < 3; ++d)
-        r.op[0][3 * j + d] = r.p[0][3 * i + d] + fmaf(R[3 * d], lv[0], fmaf(R[3 * d + 1], lv[1], R[3 * d + 2] * lv[2]));
-      for (int d = 0; d < 3; ++d) r.op[1][3 * j + d] = r.p[1][3 * i + d] - k.log_div;
-      for (int g = 2; g < 6; ++g) {
-        const int w = group_width(g, rest);
-        if (w == 0) continue;
-        copy_row(r.p[g], r.op[g], i, j, w);
-      }
-      for (int g = 0; g < 6; ++g) {
-        const int w = group_width(g, rest);
-        if (w == 0) continue;
-        zero_row(r.om[g], j, w);
-        zero_row(r.ov[g], j, w);
-      }
-    }
+  const int64_t q = off[2] + br.rank[2];  // this row's split rank
+  const bool has_eps = (q * 2 + 2) * 3 <= n_eps;
+  const int64_t jk = (c & kKeep) ? off[0] + br.rank[0] : -1;
+  const int64_t jc = (c & kClone) ? K + off[1] + br.rank[1] : -1;
+  const int64_t j1 = (c & kSplit) && has_eps ? K + C + q : -1;
+  const int64_t j2 = (c & kSplit) && has_eps ? K + C + S + q : -1;
+  d.keep[threadIdx.x] = jk < n_out ? jk : -1;
+  d.clone[threadIdx.x] = jc < n_out ? jc : -1;
+  d.child1[threadIdx.x] = j1 < n_out ? j1 : -1;
+  d.child2[threadIdx.x] = j2 < n_out ? j2 : -1;
+  __syncthreads();
+  scatter_group<3, false>(r.p[0], r.m[0], r.v[0], r.op[0], r.om[0], r.ov[0], i0, rows, d);
+  scatter_group<3, false>(r.p[1], r.m[1], r.v[1], r.op[1], r.om[1], r.ov[1], i0, rows, d);
+  scatter_group<4, true>(r.p[2], r.m[2], r.v[2], r.op[2], r.om[2], r.ov[2], i0, rows, d);
+  scatter_group<1, true>(r.p[3], r.m[3], r.v[3], r.op[3], r.om[3], r.ov[3], i0, rows, d);
+  scatter_group<3, true>(r.p[4], r.m[4], r.v[4], r.op[4], r.om[4], r.ov[4], i0, rows, d);
+  scatter_group<REST, true>(r.p[5], r.m[5], r.v[5], r.op[5], r.om[5], r.ov[5], i0, rows, d);
+  // the split children's means and log-scales
+  const int64_t js[2] = {d.child1[threadIdx.x], d.child2[threadIdx.x]};
+  if (js[0] < 0 && js[1] < 0) return;
+  // rotation of the normalised quaternion (w, x, y, z) and the scales
+  const float qw = r.p[2][4 * i], qx = r.p[2][4 * i + 1], qy = r.p[2][4 * i + 2], qz = r.p[2][4 * i + 3];
+  const float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  const float w_ = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
+  const float R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w_ * z),     2 * (x * z + w_ * y),
+                      2 * (x * y + w_ * z),     1 - 2 * (x * x + z * z), 2 * (y * z - w_ * x),
+                      2 * (x * z - w_ * y),     2 * (y * z + w_ * x),     1 - 2 * (x * x + y * y)};
+  float s[3];
+  for (int t = 0; t < 3; ++t) s[t] = expf(r.p[1][3 * i + t]);
+  for (int child = 0; child < 2; ++child) {
+    const int64_t j = js[child];
+    if (j < 0) continue;
+    const int64_t e = (q * 2 + child) * 3;
+    float lv[3];
+    for (int t = 0; t < 3; ++t) lv[t] = s[t] * eps[e + t];
+    for (int t = 0; t < 3; ++t)
+      r.op[0][3 * j + t] = r.p[0][3 * i + t] + fmaf(R[3 * t], lv[0], fmaf(R[3 * t + 1], lv[1], R[3 * t + 2] * lv[2]));
+    for (int t = 0; t < 3; ++t) r.op[1][3 * j + t] = r.p[1][3 * i + t] - k.log_div;
   }
 }
 
@@ -442,9 +463,16 @@ extern "C" gs_status gs_density_apply(const gs_params* params, const gs_params* 
     return fail(GS_ERR_CAPACITY, "workspace too small: need " + std::to_string(w.bytes) + " bytes");
   if (n_out == 0) return GS_OK;
   const DensCfg k = dens_cfg(cfg);
-  const int rest = 3 * ((D + 1) * (D + 1) - 1);
   const int64_t nb = (n + kDensThreads - 1) / kDensThreads;
-  hipLaunchKernelGGL(k_density_scatter, dim3((unsigned)nb), dim3(kDensThreads), 0, as_stream(stream), n, rest, r, k,
-                     w.cls, w.block_offs, w.totals, eps, n_eps, n_out);
+#define GS_SCATTER(DD)                                                                                         \
+  hipLaunchKernelGGL(k_density_scatter<DD>, dim3((unsigned)nb), dim3(kDensThreads), 0, as_stream(stream), n, r, k, \
+                     w.cls, w.block_offs, w.totals, eps, n_eps, n_out)
+  switch (D) {
+    case 0: GS_SCATTER(0); break;
+    case 1: GS_SCATTER(1); break;
+    case 2: GS_SCATTER(2); break;
+    default: GS_SCATTER(3); break;
+  }
+#undef GS_SCATTER
   return check_launch("density apply");
 }

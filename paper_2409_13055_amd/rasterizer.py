@@ -735,14 +735,25 @@ class DensityControl:
         L.gs_density_accumulate(fr.c_proj(), rast.n, rast.cams, rast.n_views, _p(grad2d), _p(abs2d), self._stats,
                                 _stream())
 
-    def plan(self, params: GaussianParams):
-        """Classify (device) and return (kept, cloned, split) (host sync)."""
+    def plan_launch(self, params: GaussianParams):
+        """Classify every Gaussian into the workspace and write the counts to d_counts (no sync)."""
         if params.n != self.n:
             raise ValueError("the statistics belong to a Gaussian set of another size")
         L.gs_density_plan(params.c_params(), self._stats, self.cfg, _p(self.d_counts), self.ws.data_ptr(),
                           self.ws_bytes, _stream())
+
+    def plan(self, params: GaussianParams):
+        """Classify (device) and return (kept, cloned, split) (host sync)."""
+        self.plan_launch(params)
         kept, cloned, split = (int(x) for x in self.d_counts.cpu())
         return kept, cloned, split
+
+    def apply_into(self, params: GaussianParams, adam: FusedAdam, eps: torch.Tensor, new_p: GaussianParams,
+                   new_m: GaussianParams, new_v: GaussianParams):
+        """gs_density_apply of the last plan into preallocated arrays of the new size."""
+        L.gs_density_apply(params.c_params(), adam.exp_avg.c_params(), adam.exp_avg_sq.c_params(), self.cfg,
+                           _p(eps), eps.numel(), new_p.n, new_p.c_grads(), new_m.c_grads(), new_v.c_grads(),
+                           self.ws.data_ptr(), self.ws_bytes, _stream())
 
     def apply(self, params: GaussianParams, adam: FusedAdam, generator: Optional[torch.Generator] = None,
               eps: Optional[torch.Tensor] = None):
@@ -758,13 +769,7 @@ class DensityControl:
         new_p = GaussianParams.empty(n_out, D, self.device)
         new_m = GaussianParams.empty(n_out, D, self.device)
         new_v = GaussianParams.empty(n_out, D, self.device)
-
-        def c_of(t: GaussianParams) -> L.gs_params:
-            return t.c_params()
-
-        L.gs_density_apply(params.c_params(), c_of(adam.exp_avg), c_of(adam.exp_avg_sq), self.cfg, _p(eps),
-                           eps.numel(), n_out, new_p.c_grads(), new_m.c_grads(), new_v.c_grads(),
-                           self.ws.data_ptr(), self.ws_bytes, _stream())
+        self.apply_into(params, adam, eps, new_p, new_m, new_v)
         self._alloc(n_out)
         new_adam = FusedAdam(new_p, new_p.zeros_like(), adam.lrs, adam.betas, adam.eps, exp_avg=new_m,
                              exp_avg_sq=new_v, d_step=adam.d_step)
