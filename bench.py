@@ -317,13 +317,14 @@ def main():
         density = {"ms_per_step": round(ms_d, 4), "value": round(mpix / (ms_d * 1e-3), 2),
                    "overhead_vs_value": round(ms_d / ms - 1.0, 4),
                    "raster_bwd_abs_ms": st_stages["raster_bwd"],
-                   "accumulate_ms": st_stages["density_accumulate"],
+                   "project_bwd_adam_stats_ms": st_stages["project_bwd_adam"],
                    "plan_ms": round(ms_plan, 4), "apply_ms": round(ms_apply, 4), "apply_alg_bytes": alg,
                    "apply_GBps": round(gbs, 1), "apply_hbm_frac": round(gbs / 8000.0, 4),
                    "counts": {"kept": kept, "cloned": cloned, "split": split, "n_out": n_out},
                    "statistics_iterations": args.warmup + 2 * args.steps}
         log(f"[bench] density tracking: {ms_d:.3f} ms/step (raster_bwd_abs {st_stages['raster_bwd']} ms, "
-            f"accumulate {st_stages['density_accumulate']} ms); plan {ms_plan:.3f} ms, apply {ms_apply:.3f} ms "
+            f"project_bwd_adam with statistics {st_stages['project_bwd_adam']} ms); plan {ms_plan:.3f} ms, "
+            f"apply {ms_apply:.3f} ms "
             f"({gbs:.0f} GB/s alg), {kept}+{cloned}+2x{split} -> {n_out}")
         del st, outs, dc
 
@@ -371,8 +372,6 @@ def stage_breakdown(step, iters):
     import torch
     if step.fuse_adam:
         names = ["project", "bin_sort", "render_fwd", "clear_grad2d", "raster_bwd", "project_bwd_adam"]
-        if step.density is not None:
-            names.append("density_accumulate")
     else:
         names = ["project", "bin_sort", "render_fwd", "clear_grad2d", "raster_bwd", "project_bwd"]
         if step.adam is not None:

@@ -434,6 +434,15 @@ gs_status gs_scene_extent(const gs_camera* cams, int32_t n_views, float* extent)
 gs_status gs_density_accumulate(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n_views,
                                 const float* grad2d, const float* abs_grad2d, const gs_density_stats* stats,
                                 void* stream);
+/* gs_project_bwd_adam followed by gs_density_accumulate of the same grad2d
+ * and abs_grad2d, in one pass over grad2d (the statistics are formed in the
+ * projection backward's view loop); the results equal the two calls', bit
+ * for bit. */
+gs_status gs_project_bwd_adam_stats(const gs_params* params, const gs_projected* proj, const gs_camera* cams,
+                                    int32_t n_views, const gs_options* opts, const float* grad2d,
+                                    const gs_adam_group* groups /* host array [6] */, double beta1, double beta2,
+                                    double eps, int32_t* d_step, const float* abs_grad2d,
+                                    const gs_density_stats* stats, void* stream);
 gs_status gs_density_workspace_size(int64_t n, size_t* bytes);
 gs_status gs_density_plan(const gs_params* params, const gs_density_stats* stats, const gs_density_config* cfg,
                           int32_t* d_counts, void* workspace, size_t workspace_bytes, void* stream);

@@ -87,7 +87,7 @@ EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_op
            "gs_render_bwd_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_raster_bwd", "gs_project_bwd", "gs_render_stats", "gs_adam_step", "gs_project_bwd_adam",
            "gs_photometric_loss_workspace_size", "gs_photometric_loss", "gs_pyramid_camera", "gs_pyramid_reduce",
-           "gs_raster_bwd_abs", "gs_default_density_config", "gs_scene_extent", "gs_density_accumulate",
+           "gs_raster_bwd_abs", "gs_project_bwd_adam_stats", "gs_default_density_config", "gs_scene_extent", "gs_density_accumulate",
            "gs_density_workspace_size", "gs_density_plan", "gs_density_apply")
 
 _lib = None
@@ -133,6 +133,9 @@ def load(path: str = LIB_PATH):
         "gs_pyramid_reduce": (C.c_int, [pc, i32, P, P, P]),
         "gs_raster_bwd_abs": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), C.POINTER(gs_image), pc,
                                         i32, po, C.POINTER(gs_loss), P, P, P]),
+        "gs_project_bwd_adam_stats": (C.c_int, [pp, C.POINTER(gs_projected), pc, i32, po, P,
+                                                C.POINTER(gs_adam_group), C.c_double, C.c_double, C.c_double, P, P,
+                                                C.POINTER(gs_density_stats), P]),
         "gs_default_density_config": (None, [C.POINTER(gs_density_config)]),
         "gs_scene_extent": (C.c_int, [pc, i32, C.POINTER(C.c_float)]),
         "gs_density_accumulate": (C.c_int, [C.POINTER(gs_projected), i64, pc, i32, P, P,
@@ -328,3 +331,10 @@ def gs_density_apply(params, exp_avg, exp_avg_sq, cfg, eps, n_eps, n_out, out_pa
                                                        C.byref(cfg), eps, n_eps, n_out, C.byref(out_params),
                                                        C.byref(out_exp_avg), C.byref(out_exp_avg_sq), workspace,
                                                        workspace_bytes, stream))
+
+
+def gs_project_bwd_adam_stats(params, proj, cams, n_views, opts, grad2d, groups, beta1, beta2, eps, d_step,
+                              abs_grad2d, stats, stream):
+    _check("gs_project_bwd_adam_stats", load().gs_project_bwd_adam_stats(
+        C.byref(params), C.byref(proj), cams, n_views, C.byref(opts), grad2d, groups, beta1, beta2, eps, d_step,
+        abs_grad2d, C.byref(stats), stream))

@@ -367,12 +367,23 @@ struct AdamPtrs {
 // once for the Adam step of every parameter, the same update the standalone
 // step applies, the block streaming each group's contiguous range of p, m and
 // v as float4 with consecutive lanes on consecutive elements.
+// With STATS the thread also adds its Gaussian's density-control statistics
+// of the iteration (the norms of the view-space and homodirectional
+// gradients in normalised device units, and the count of views whose tiles
+// it touches), exactly as the standalone statistics kernel does, so grad2d is
+// read once.
+struct DensAcc {
+  const float* abs2d;
+  float* gacc;
+  float* aacc;
+  int32_t* cnt;
+};
 constexpr int kBwdThreads = 256;
-template <int D, bool ADAM>
+template <int D, bool ADAM, bool STATS>
 __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamTable cams,
                                                              const int32_t* __restrict__ tiles,
                                                              const float* __restrict__ grad2d, GradPtrs gp,
-                                                             AdamPtrs ap) {
+                                                             AdamPtrs ap, DensAcc da) {
   constexpr int K = (D + 1) * (D + 1);
   constexpr int NPAR = 11 + 3 * K;  // raw floats per Gaussian
   __shared__ __align__(16) float s_g[ADAM ? kBwdThreads * NPAR : 1];
@@ -396,6 +407,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
     real gS[6] = {0, 0, 0, 0, 0, 0};
     real gop = 0;
     bool any = false;
+    float sG = 0.0f, sA = 0.0f;  // STATS: this iteration's norms summed over views
+    int sC = 0;
     // the views that see the Gaussian (tiles_touched > 0), eight loads in flight at a time
     uint32_t seen = 0;
 #pragma unroll 1
@@ -417,6 +430,14 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
 #pragma unroll
       for (int k = 0; k < 9; ++k) g2[k] = grad2d[row * 9 + k];
       const CamF& cam = cams.c[v];
+      if (STATS) {
+        const float hx = 0.5f * (float)cam.W, hy = 0.5f * (float)cam.H;
+        const float gx = hx * (float)g2[0], gy = hy * (float)g2[1];
+        const float ax = hx * da.abs2d[row * 2], ay = hy * da.abs2d[row * 2 + 1];
+        sG += sqrtf(fmaf(gx, gx, gy * gy));
+        sA += sqrtf(fmaf(ax, ax, ay * ay));
+        ++sC;
+      }
       Proj2D p;
       if (!project_view(g, cam, a.near_plane, a.eps2d, p)) continue;
       any = true;
@@ -561,6 +582,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
           for (int c = 0; c < 3; ++c) gp.sh_rest[(i * (K - 1) + (k - 1)) * 3 + c] += gsh[k][c];
       }
     }  // any
+    if (STATS && sC > 0) {
+      da.gacc[i] += sG;
+      da.aacc[i] += sA;
+      da.cnt[i] += sC;
+    }
   }  // g.ok
   if (!ADAM) return;
   // group g's block of gradients sits at s_g[T * off_g + t * width_g + c], as in the group's array
@@ -653,20 +679,21 @@ gs_status validate_params(const gs_params* p) {
   return GS_OK;
 }
 
-template <bool ADAM>
+template <bool ADAM, bool STATS = false>
 static void launch_project_bwd_kernel(const gs_params* params, const ProjectArgs& a, const CamTable& ct,
                                       const int32_t* tiles, const float* grad2d, const GradPtrs& gp,
-                                      const AdamPtrs& ap, hipStream_t stream) {
+                                      const AdamPtrs& ap, hipStream_t stream, const DensAcc& da = DensAcc{}) {
   const int bs = kBwdThreads;
   const dim3 grid((unsigned)((params->n + bs - 1) / bs));
+#define GS_PBWD(DD) \
+  hipLaunchKernelGGL((k_project_bwd<DD, ADAM, STATS>), grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp, ap, da)
   switch (params->sh_degree) {
-    case 0: hipLaunchKernelGGL((k_project_bwd<0, ADAM>), grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp, ap); break;
-    case 1: hipLaunchKernelGGL((k_project_bwd<1, ADAM>), grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp, ap); break;
-    case 2: hipLaunchKernelGGL((k_project_bwd<2, ADAM>), grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp, ap); break;
-    default:
-      hipLaunchKernelGGL((k_project_bwd<3, ADAM>), grid, dim3(bs), 0, stream, a, ct, tiles, grad2d, gp, ap);
-      break;
+    case 0: GS_PBWD(0); break;
+    case 1: GS_PBWD(1); break;
+    case 2: GS_PBWD(2); break;
+    default: GS_PBWD(3); break;
   }
+#undef GS_PBWD
 }
 
 gs_status launch_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
@@ -680,11 +707,11 @@ gs_status launch_project_bwd(const gs_params* params, const gs_camera* cams, int
 
 }  // namespace gs
 
-extern "C" gs_status gs_project_bwd_adam(const gs_params* params, const gs_projected* proj, const gs_camera* cams,
-                                         int32_t n_views, const gs_options* opts, const float* grad2d,
-                                         const gs_adam_group* groups, double beta1, double beta2, double eps,
-                                         int32_t* d_step, void* stream) {
-  using namespace gs;
+namespace gs {
+static gs_status project_bwd_adam(const gs_params* params, const gs_projected* proj, const gs_camera* cams,
+                                  int32_t n_views, const gs_options* opts, const float* grad2d,
+                                  const gs_adam_group* groups, double beta1, double beta2, double eps, int32_t* d_step,
+                                  const float* abs_grad2d, const gs_density_stats* stats, void* stream) {
   gs_status s;
   if ((s = validate_params(params)) != GS_OK) return s;
   if ((s = validate_cams(cams, n_views)) != GS_OK) return s;
@@ -715,9 +742,35 @@ extern "C" gs_status gs_project_bwd_adam(const gs_params* params, const gs_proje
   const ProjectArgs a = make_args(params, n_views, opts);
   const CamTable ct = make_cam_table(cams, n_views, opts);
   hipStream_t st = as_stream(stream);
-  launch_project_bwd_kernel<true>(params, a, ct, proj->tiles_touched, grad2d, GradPtrs{}, ap, st);
+  if (stats)
+    launch_project_bwd_kernel<true, true>(params, a, ct, proj->tiles_touched, grad2d, GradPtrs{}, ap, st,
+                                          DensAcc{abs_grad2d, stats->grad_accum, stats->abs_accum, stats->count});
+  else
+    launch_project_bwd_kernel<true>(params, a, ct, proj->tiles_touched, grad2d, GradPtrs{}, ap, st);
   launch_step_increment(d_step, st);
   return check_launch("projection backward + adam");
+}
+}  // namespace gs
+
+extern "C" gs_status gs_project_bwd_adam(const gs_params* params, const gs_projected* proj, const gs_camera* cams,
+                                         int32_t n_views, const gs_options* opts, const float* grad2d,
+                                         const gs_adam_group* groups, double beta1, double beta2, double eps,
+                                         int32_t* d_step, void* stream) {
+  return gs::project_bwd_adam(params, proj, cams, n_views, opts, grad2d, groups, beta1, beta2, eps, d_step, nullptr,
+                              nullptr, stream);
+}
+
+extern "C" gs_status gs_project_bwd_adam_stats(const gs_params* params, const gs_projected* proj,
+                                               const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                                               const float* grad2d, const gs_adam_group* groups, double beta1,
+                                               double beta2, double eps, int32_t* d_step, const float* abs_grad2d,
+                                               const gs_density_stats* stats, void* stream) {
+  using namespace gs;
+  if (!abs_grad2d) return fail(GS_ERR_INVALID_VALUE, "abs_grad2d is NULL");
+  if (!stats || !stats->grad_accum || !stats->abs_accum || !stats->count)
+    return fail(GS_ERR_INVALID_VALUE, "a statistics array is NULL");
+  return project_bwd_adam(params, proj, cams, n_views, opts, grad2d, groups, beta1, beta2, eps, d_step, abs_grad2d,
+                          stats, stream);
 }
 
 extern "C" gs_status gs_project(const gs_params* params, const gs_camera* cams, int32_t n_views,

@@ -239,10 +239,19 @@ class Rasterizer:
         L.gs_project_bwd(params.c_params(), fr.c_proj(), self.cams, self.n_views, self.opts, grad2d.data_ptr(),
                          grads.c_grads(), _stream())
 
-    def project_bwd_adam(self, params: GaussianParams, fr: Frame, grad2d: torch.Tensor, adam: "FusedAdam"):
-        """The projection backward of grad2d fused with adam's step (params and moments updated in place)."""
-        L.gs_project_bwd_adam(params.c_params(), fr.c_proj(), self.cams, self.n_views, self.opts, grad2d.data_ptr(),
-                              adam.all_groups, adam.betas[0], adam.betas[1], adam.eps, _p(adam.d_step), _stream())
+    def project_bwd_adam(self, params: GaussianParams, fr: Frame, grad2d: torch.Tensor, adam: "FusedAdam",
+                         density: Optional["DensityControl"] = None, abs2d: Optional[torch.Tensor] = None):
+        """The projection backward of grad2d fused with adam's step (params and moments updated in place);
+        with `density` and abs2d it also adds the iteration's density-control statistics
+        (gs_project_bwd_adam_stats)."""
+        if density is None:
+            L.gs_project_bwd_adam(params.c_params(), fr.c_proj(), self.cams, self.n_views, self.opts,
+                                  grad2d.data_ptr(), adam.all_groups, adam.betas[0], adam.betas[1], adam.eps,
+                                  _p(adam.d_step), _stream())
+        else:
+            L.gs_project_bwd_adam_stats(params.c_params(), fr.c_proj(), self.cams, self.n_views, self.opts,
+                                        grad2d.data_ptr(), adam.all_groups, adam.betas[0], adam.betas[1], adam.eps,
+                                        _p(adam.d_step), _p(abs2d), density._stats, _stream())
 
     def render_stats(self, fr: Frame, out: Optional[torch.Tensor] = None) -> Optional[Dict[str, int]]:
         """Work counts of the blending of this frame (see gs_render_stats).  Without `out` it syncs
@@ -460,9 +469,7 @@ class MappingStep:
             self._forward(fr)
             cur.wait_stream(self._side)
             r.raster_bwd(fr, r.grad2d, abs2d=self.abs2d, **self._loss_args())
-            r.project_bwd_adam(self.params, fr, r.grad2d, self.adam)
-            if self.density is not None:
-                self.density.accumulate(r, fr, r.grad2d, self.abs2d)
+            r.project_bwd_adam(self.params, fr, r.grad2d, self.adam, density=self.density, abs2d=self.abs2d)
             return
         self._forward(fr, mark)
         if self.fuse_adam:
@@ -475,13 +482,9 @@ class MappingStep:
             r.raster_bwd(fr, g2, abs2d=self.abs2d, **self._loss_args())
             if mark:
                 mark("raster_bwd")
-            r.project_bwd_adam(self.params, fr, g2, self.adam)
+            r.project_bwd_adam(self.params, fr, g2, self.adam, density=self.density, abs2d=self.abs2d)
             if mark:
                 mark("project_bwd_adam")
-            if self.density is not None:
-                self.density.accumulate(r, fr, g2, self.abs2d)
-                if mark:
-                    mark("density_accumulate")
             return
         if mark is None:
             r.render_bwd(self.params, fr, self.grads, **self._loss_args())

@@ -163,3 +163,20 @@ def test_mapping_step_densifies_and_continues():
     assert int(st2.adam.d_step.item()) == 4
     assert int(dc.count.max().item()) == 2 * len(sc.cameras)
     assert np.isfinite(st2.loss.cpu().numpy()).all()
+
+
+def test_fused_statistics_equal_the_standalone_kernel():
+    """gs_project_bwd_adam_stats (what MappingStep uses) against gs_density_accumulate of the same
+    iteration's buffers: bit for bit."""
+    sc = small_scene(6)
+    params = R.GaussianParams.from_scene(sc, DEV)
+    dc = R.DensityControl(params.n, sc.cameras, device=DEV)
+    st = R.MappingStep(params, sc.cameras, sc.targets, lrs=dict(S.DEFAULT_LRS), tile_size=32, density=dc)
+    st.size()
+    st.run()
+    solo = R.DensityControl(params.n, sc.cameras, device=DEV)
+    solo.accumulate(st.rast, st.frame, st.rast.grad2d, st.abs2d)
+    torch.cuda.synchronize()
+    assert int(dc.count.sum().item()) > 0
+    for a, b in ((dc.grad_accum, solo.grad_accum), (dc.abs_accum, solo.abs_accum), (dc.count, solo.count)):
+        assert torch.equal(a, b)
