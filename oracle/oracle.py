@@ -8,7 +8,10 @@ the default 3DGS optimisation setup (Sec. IV-A), one level of the
 Gaussian pyramid of ground-truth images used for coarse-to-fine training
 (Sec. III-B) with the camera that samples it, and the adaptive density
 control of Sec. III-B (AbsGS statistics from the backward's per-pixel
-gradient magnitudes, split / clone / prune with the 3DGS parameters).
+gradient magnitudes, split / clone / prune with the 3DGS parameters), and the
+point-cloud densification of Sec. III-A (Delaunay triangles of the tracked
+pixels through scipy's Qhull, vertex-mean depth in low-gradient regions) with
+the initialisation of new Gaussians from it.
 
 Readings of the paper used here (the paper defers the rasteriser to 3DGS,
 Sec. III-B): see the header of oracle.cpp; every threshold is a field of
@@ -28,6 +31,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "liboracle.so")
 _lib = None
 
+SH_C0 = 0.5 / math.sqrt(math.pi)  # the degree-0 real spherical harmonic
 REC_FIELDS = ("mx", "my", "depth", "ca", "cb", "cc", "opacity", "r", "g", "b")
 GRAD2D_FIELDS = ("mx", "my", "ca", "cb", "cc", "opacity", "r", "g", "b")
 
@@ -573,6 +577,117 @@ def densify_and_prune(params: Params, exp_avg: Params, exp_avg_sq: Params, abs_a
         return Params(o["means"], o["log_scales"], o["quats"], o["opacity_logits"], o["sh"], m.sh_degree)
 
     return new_p, moments(exp_avg), moments(exp_avg_sq), (keep, clone, split)
+
+
+# ---------------------------------------------------------------------------
+# Point-cloud densification and Gaussian initialisation (Sec. III-A, Sec. III-B).
+# The paper triangulates the image with the tracked pixels as vertices
+# (Delaunay), gives each pixel of a low-gradient region the mean depth of its
+# triangle's vertices, and initialises new Gaussians at the points with their
+# colour.  Readings:
+#  - tracked pixels have integer pixel coordinates, distinct, not all
+#    collinear; the triangulation is the Delaunay triangulation of their
+#    convex hull (any one of the valid ones where four are cocircular);
+#  - a pixel belongs to the triangle whose closed interior holds it, edges
+#    shared by two triangles going to one of them: an edge a -> b of a
+#    triangle with positive orientation is its own when b.y > a.y, or b.y ==
+#    a.y and b.x < a.x (exact integer tests); a tracked pixel keeps its own
+#    depth and is never interpolated;
+#  - low gradient: grey = (r + g + b) / 3, central differences (one-sided at
+#    the border) gx, gy, and gx^2 + gy^2 < tau^2, every step in FP32;
+#  - a new Gaussian per pixel with a depth (tracked or interpolated) on the
+#    grid of stride `stride` (x % stride == 0 and y % stride == 0; tracked
+#    pixels always), in row-major pixel order: mean = the pixel's index
+#    coordinate unprojected at its depth, sh_dc = (colour - 1/2) / SH_C0,
+#    identity rotation, opacity 0.1 (the 3DGS initial opacity), isotropic
+#    scale of the pixel footprint, stride * depth / fx, higher SH bands 0.
+# ---------------------------------------------------------------------------
+def delaunay_triangles(pts):
+    """Delaunay triangles of integer points [n, 2] (scipy's Qhull), as sorted index triples."""
+    from scipy.spatial import Delaunay
+    tri = Delaunay(np.asarray(pts, np.float64)).simplices
+    return np.unique(np.sort(tri, axis=1), axis=0)
+
+
+def _orient(a, b, c):
+    return (int(b[0]) - int(a[0])) * (int(c[1]) - int(a[1])) - (int(b[1]) - int(a[1])) * (int(c[0]) - int(a[0]))
+
+
+def pixel_owner(pts, tris, W, H):
+    """Per pixel the index of the triangle that owns it, -1 if none (exact integer edge tests)."""
+    pts = np.asarray(pts, np.int64)
+    owner = np.full((H, W), -1, np.int64)
+    yy, xx = np.mgrid[0:H, 0:W]
+    for t, (i, j, k) in enumerate(tris):
+        a, b, c = pts[i], pts[j], pts[k]
+        if _orient(a, b, c) < 0:
+            b, c = c, b
+        inside = np.ones((H, W), bool)
+        for u, v in ((a, b), (b, c), (c, a)):
+            e = (v[0] - u[0]) * (yy - u[1]) - (v[1] - u[1]) * (xx - u[0])
+            own = v[1] > u[1] or (v[1] == u[1] and v[0] < u[0])
+            inside &= (e > 0) | ((e == 0) & own)
+        assert not np.any(owner[inside] >= 0), "a pixel owned twice"
+        owner[inside] = t
+    return owner
+
+
+def low_gradient_mask(img3, tau):
+    """gx^2 + gy^2 < tau^2 of the grey image, every step in FP32 as stated above."""
+    f = np.float32
+    im = np.asarray(img3, f)
+    grey = (im[0] + im[1] + im[2]) / f(3.0)
+    H, W = grey.shape
+    gx = np.empty_like(grey)
+    gy = np.empty_like(grey)
+    if W > 1:
+        gx[:, 1:-1] = (grey[:, 2:] - grey[:, :-2]) * f(0.5)
+        gx[:, 0] = grey[:, 1] - grey[:, 0]
+        gx[:, -1] = grey[:, -1] - grey[:, -2]
+    else:
+        gx[:] = 0
+    if H > 1:
+        gy[1:-1] = (grey[2:] - grey[:-2]) * f(0.5)
+        gy[0] = grey[1] - grey[0]
+        gy[-1] = grey[-1] - grey[-2]
+    else:
+        gy[:] = 0
+    return gx * gx + gy * gy < f(tau) * f(tau)
+
+
+def interpolate_depth(pts, depths, tris, img3, tau):
+    """Depth map [H, W] (0 where none): tracked pixels their depth, low-gradient pixels the mean
+    depth of the vertices of the triangle that owns them."""
+    H, W = img3.shape[1:]
+    owner = pixel_owner(pts, tris, W, H)
+    mask = low_gradient_mask(img3, tau)
+    d = np.asarray(depths, np.float64)
+    tri_mean = d[np.asarray(tris)].mean(axis=1) if len(tris) else np.zeros(0)
+    out = np.where((owner >= 0) & mask, tri_mean[np.maximum(owner, 0)] if len(tris) else 0.0, 0.0)
+    pts = np.asarray(pts, np.int64)
+    out[pts[:, 1], pts[:, 0]] = d
+    return out, owner
+
+
+def init_gaussians(depth, img3, cam, stride, tracked_mask):
+    """New Gaussians from a depth map (see the readings above): dict of means [m, 3], log_scales
+    [m, 3], quats [m, 4], opacity_logits [m], sh_dc [m, 3], and the pixel indices used."""
+    H, W = depth.shape
+    yy, xx = np.mgrid[0:H, 0:W]
+    grid = (xx % stride == 0) & (yy % stride == 0)
+    use = (depth > 0) & (grid | tracked_mask)
+    idx = np.flatnonzero(use.reshape(-1))
+    x, y = xx.reshape(-1)[idx].astype(np.float64), yy.reshape(-1)[idx].astype(np.float64)
+    z = depth.reshape(-1)[idx]
+    # index coordinate u = fx X/Z + cx - 1/2
+    pc = np.stack([(x - cam.cx + 0.5) / cam.fx * z, (y - cam.cy + 0.5) / cam.fy * z, z], 1)
+    R, t = np.asarray(cam.R, np.float64), np.asarray(cam.t, np.float64)
+    means = (pc - t) @ R
+    col = np.asarray(img3, np.float64).reshape(3, -1)[:, idx].T
+    m = idx.size
+    return dict(means=means, log_scales=np.repeat(np.log(stride * z / cam.fx)[:, None], 3, 1),
+                quats=np.tile([1.0, 0.0, 0.0, 0.0], (m, 1)), opacity_logits=np.full(m, math.log(0.1 / 0.9)),
+                sh_dc=(col - 0.5) / SH_C0, pixels=idx)
 
 
 def project_backward(params: Params, cams, opts: Options, grad2d):

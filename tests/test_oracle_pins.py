@@ -974,3 +974,126 @@ def test_split_children_sample_the_parent_gaussian(oracle_lib):
     d = newp.means - np.array([1.0, -2.0, 3.0])
     np.testing.assert_allclose(d.mean(0), 0.0, atol=4 * 0.3 / math.sqrt(2 * n))
     np.testing.assert_allclose(np.cov(d.T), cov, atol=0.004)
+
+
+# ---------------------------------------------------------------------------
+# Point-cloud densification (Sec. III-A) and Gaussian initialisation (Sec. III-B)
+# ---------------------------------------------------------------------------
+def _incircle(a, b, c, d):
+    """Exact: > 0 when d lies inside the circumcircle of the positively oriented a, b, c."""
+    rows = [(p[0] - d[0], p[1] - d[1]) for p in (a, b, c)]
+    m = [(x, y, x * x + y * y) for x, y in rows]
+    return (m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0])
+            + m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]))
+
+
+def random_pixels(rng, n, W, H):
+    flat = rng.choice(W * H, n, replace=False)
+    return np.stack([flat % W, flat // W], 1).astype(np.int64)
+
+
+def test_delaunay_empty_circles_and_euler(oracle_lib):
+    from scipy.spatial import ConvexHull
+    O = oracle_lib
+    rng = np.random.default_rng(3)
+    pts = random_pixels(rng, 60, 50, 40)
+    tris = O.delaunay_triangles(pts)
+    P = [tuple(int(v) for v in p) for p in pts]
+    for i, j, k in tris:
+        a, b, c = P[i], P[j], P[k]
+        if O._orient(a, b, c) < 0:
+            b, c = c, b
+        assert O._orient(a, b, c) > 0
+        for m in range(len(P)):
+            if m not in (i, j, k):
+                assert _incircle(a, b, c, P[m]) <= 0
+    h = len(ConvexHull(pts.astype(np.float64)).vertices)
+    assert len(tris) == 2 * len(pts) - 2 - h
+
+
+def test_pixel_ownership_partitions_the_hull(oracle_lib):
+    O = oracle_lib
+    # a square split along its diagonal: every pixel of the closed square is owned once, except
+    # those on the two hull edges the rule gives to no triangle
+    pts = np.array([[1, 1], [7, 1], [7, 7], [1, 7]])
+    tris = np.array([[0, 1, 2], [0, 2, 3]])
+    own = O.pixel_owner(pts, tris, 9, 9)
+    for d in range(2, 7):  # the diagonal's interior pixels belong to exactly one triangle
+        assert own[d, d] in (0, 1)
+    assert np.all(own[2:7, 2:7][np.triu_indices(5, 1)] == 0) or np.all(own[2:7, 2:7][np.triu_indices(5, 1)] == 1)
+    # strictly inside each triangle: owned by it (x > y is below the diagonal in image rows: triangle 0)
+    for y in range(2, 7):
+        for x in range(2, 7):
+            if x > y:
+                assert own[y, x] == 0
+            elif x < y:
+                assert own[y, x] == 1
+    assert np.all(own[0] == -1) and np.all(own[:, 8] == -1)
+    # two edges of the square's hull are owned, two are not: 6 + 6 - 1 hull pixels outside the owned set
+    closed = np.zeros((9, 9), bool)
+    closed[1:8, 1:8] = True
+    assert (closed & (own < 0)).sum() == 13
+    # random triangulation: interior pixels owned exactly once, nothing outside the hull
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(8)
+    pts = random_pixels(rng, 40, 30, 24)
+    tris = O.delaunay_triangles(pts)
+    own = O.pixel_owner(pts, tris, 30, 24)
+    hull = Delaunay(pts.astype(np.float64))
+    yy, xx = np.mgrid[0:24, 0:30]
+    q = np.stack([xx.ravel(), yy.ravel()], 1).astype(np.float64)
+    inside = hull.find_simplex(q) >= 0
+    assert np.all(own.ravel()[~inside] == -1)
+    # pixels of the hull's interior that no edge passes through are owned
+    assert (own.ravel()[inside] >= 0).mean() > 0.9
+
+
+def test_low_gradient_mask_closed_forms(oracle_lib):
+    O = oracle_lib
+    H, W = 12, 15
+    assert O.low_gradient_mask(np.full((3, H, W), 0.4), 0.01).all()
+    xx = np.broadcast_to(np.arange(W, dtype=np.float64), (H, W))
+    ramp = np.stack([0.02 * xx] * 3)  # grey gradient 0.02 per pixel in x, 0 in y
+    assert O.low_gradient_mask(ramp, 0.0201).all()
+    assert not O.low_gradient_mask(ramp, 0.0199).any()
+    step = np.zeros((3, H, W))
+    step[:, :, 8:] = 1.0
+    m = O.low_gradient_mask(step, 0.1)
+    assert not m[:, 7:9].any() and m[:, :6].all() and m[:, 10:].all()
+
+
+def test_interpolated_depth_and_initialised_gaussians(oracle_lib):
+    O = oracle_lib
+    rng = np.random.default_rng(4)
+    W, H = 40, 30
+    pts = random_pixels(rng, 25, W, H)
+    depth = rng.uniform(1.0, 3.0, len(pts))
+    tris = O.delaunay_triangles(pts)
+    img = np.full((3, H, W), 0.3)
+    d, own = O.interpolate_depth(pts, depth, tris, img, 0.05)
+    assert np.all(d[pts[:, 1], pts[:, 0]] == depth)
+    ys, xs = np.nonzero((own >= 0) & (d > 0))
+    for y, x in zip(ys[:50], xs[:50]):
+        if not np.any((pts[:, 0] == x) & (pts[:, 1] == y)):
+            assert math.isclose(d[y, x], depth[tris[own[y, x]]].sum() / 3.0, rel_tol=1e-15)
+    # equal vertex depths: every owned pixel gets that depth
+    d2, _ = O.interpolate_depth(pts, np.full(len(pts), 2.5), tris, img, 0.05)
+    assert np.all(d2[own >= 0] == 2.5)
+    # initialisation round trip through the camera
+    cam = S.pinhole(W, H, 35.0, *S.look_at((0.2, -0.1, -1.0), (0.0, 0.0, 2.0)))
+    tracked = np.zeros((H, W), bool)
+    tracked[pts[:, 1], pts[:, 0]] = True
+    img = rng.random((3, H, W))
+    g = O.init_gaussians(d, img, cam, 2, tracked)
+    px = g["pixels"]
+    assert np.all((d.ravel()[px] > 0))
+    pc = g["means"] @ cam.R.T + cam.t
+    np.testing.assert_allclose(cam.fx * pc[:, 0] / pc[:, 2] + cam.cx - 0.5, px % W, atol=1e-9)
+    np.testing.assert_allclose(cam.fy * pc[:, 1] / pc[:, 2] + cam.cy - 0.5, px // W, atol=1e-9)
+    np.testing.assert_allclose(pc[:, 2], d.ravel()[px], rtol=1e-12)
+    np.testing.assert_allclose(g["sh_dc"] * S.SH_C0 + 0.5, img.reshape(3, -1)[:, px].T, rtol=1e-12)
+    np.testing.assert_allclose(np.exp(g["log_scales"][:, 0]), 2 * d.ravel()[px] / cam.fx, rtol=1e-12)
+    assert math.isclose(1.0 / (1.0 + math.exp(-g["opacity_logits"][0])), 0.1, rel_tol=1e-12)
+    # the grid and the tracked pixels, nothing else
+    on_grid = ((px % W) % 2 == 0) & ((px // W) % 2 == 0)
+    assert np.all(on_grid | tracked.ravel()[px])
