@@ -451,6 +451,52 @@ gs_status gs_density_apply(const gs_params* params, const gs_params* exp_avg, co
                            const gs_grads* out_params, const gs_grads* out_exp_avg, const gs_grads* out_exp_avg_sq,
                            const void* workspace, size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------- point-cloud densification
+ * Sec. III-A: the image is triangulated (Delaunay) with the tracked pixels as
+ * vertices and the pixels of low-gradient regions take the mean depth of
+ * their triangle's vertices; Sec. III-B: new Gaussians start at the points
+ * with their colour.  Readings (the paper gives no formulas):
+ *  - gs_delaunay (host only): a Delaunay triangulation of the convex hull of
+ *    n >= 3 distinct, not all collinear points with integer coordinates in
+ *    [0, 32768) (xy host [n][2]), exact (integer predicates; one of the valid
+ *    triangulations where four points are cocircular).  Writes *n_tris and,
+ *    when max_tris suffices (at most 2 n - 5), tris (host [n_tris][3]) with
+ *    every triangle's smallest index first, its orientation kept, the
+ *    triangles in lexicographic order; GS_ERR_CAPACITY otherwise.
+ *  - gs_densify_depth: depth_map [H W] (device) = 0, then the depth of each
+ *    tracked pixel (xy device [n][2], depth device [n], > 0), then for each
+ *    triangle (tris device [n_tris][3]) the mean depth of its vertices on the
+ *    pixels it owns that are not tracked and of low gradient.  A pixel belongs
+ *    to the triangle whose closed interior holds it; an edge shared by two
+ *    triangles goes to one: edge a -> b of a positively oriented triangle is
+ *    its own when b.y > a.y, or b.y == a.y and b.x < a.x.  Low gradient: grey
+ *    = (r + g + b) / 3 of `image` ([3][H][W] FP32, device), central
+ *    differences (one-sided at the border), gx^2 + gy^2 < tau^2, each step an
+ *    FP32 operation.  tracked [H W] (device bytes) = 1 at tracked pixels.
+ *    Points outside the image and triangles with an index outside [0, n) are
+ *    skipped.  The camera gives W and H.
+ *  - gs_init_gaussians_count, then gs_init_gaussians: one new Gaussian per
+ *    pixel with a depth on the grid x % stride == 0, y % stride == 0 (tracked
+ *    pixels always), in row-major order; the count goes to d_count (device),
+ *    the classes to `workspace` (gs_init_gaussians_workspace_size bytes),
+ *    which the second call reads.  Mean: the pixel's index coordinate (x, y)
+ *    unprojected at its depth through `cam`; sh_dc = (colour - 1/2) / SH_C0;
+ *    quaternion (1, 0, 0, 0); opacity logit log(0.1 / 0.9); log-scales
+ *    log(stride * depth / fx) (isotropic: the pixel footprint); sh_rest 0
+ *    (sh_degree gives its width).  out holds n_out rows (the count); rows past
+ *    n_out are not written. */
+gs_status gs_delaunay(const int32_t* xy, int32_t n, int32_t* tris, int32_t max_tris, int32_t* n_tris);
+gs_status gs_densify_depth(const gs_camera* cam, const int32_t* xy, const float* depth, int32_t n,
+                           const int32_t* tris, int32_t n_tris, const float* image, float tau, float* depth_map,
+                           uint8_t* tracked, void* stream);
+gs_status gs_init_gaussians_workspace_size(const gs_camera* cam, size_t* bytes);
+gs_status gs_init_gaussians_count(const gs_camera* cam, const float* depth_map, const uint8_t* tracked,
+                                  int32_t stride, int32_t* d_count, void* workspace, size_t workspace_bytes,
+                                  void* stream);
+gs_status gs_init_gaussians(const gs_camera* cam, const float* depth_map, const uint8_t* tracked,
+                            const float* image, int32_t stride, int32_t sh_degree, int64_t n_out,
+                            const gs_grads* out, const void* workspace, size_t workspace_bytes, void* stream);
+
 /* Gaussian pyramid of the ground-truth images for coarse-to-fine training
  * (Sec. III-B, after Photo-SLAM: the images are repeatedly smoothed and
  * down-sampled, and the loss uses coarse levels first).  Reading (the paper

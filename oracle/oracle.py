@@ -617,18 +617,24 @@ def pixel_owner(pts, tris, W, H):
     """Per pixel the index of the triangle that owns it, -1 if none (exact integer edge tests)."""
     pts = np.asarray(pts, np.int64)
     owner = np.full((H, W), -1, np.int64)
-    yy, xx = np.mgrid[0:H, 0:W]
     for t, (i, j, k) in enumerate(tris):
         a, b, c = pts[i], pts[j], pts[k]
         if _orient(a, b, c) < 0:
             b, c = c, b
-        inside = np.ones((H, W), bool)
+        # only pixels of the triangle's bounding box can be inside it
+        x0, x1 = max(0, min(a[0], b[0], c[0])), min(W - 1, max(a[0], b[0], c[0]))
+        y0, y1 = max(0, min(a[1], b[1], c[1])), min(H - 1, max(a[1], b[1], c[1]))
+        if x1 < x0 or y1 < y0:
+            continue
+        yy, xx = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+        inside = np.ones(yy.shape, bool)
         for u, v in ((a, b), (b, c), (c, a)):
             e = (v[0] - u[0]) * (yy - u[1]) - (v[1] - u[1]) * (xx - u[0])
             own = v[1] > u[1] or (v[1] == u[1] and v[0] < u[0])
             inside &= (e > 0) | ((e == 0) & own)
-        assert not np.any(owner[inside] >= 0), "a pixel owned twice"
-        owner[inside] = t
+        box = owner[y0:y1 + 1, x0:x1 + 1]
+        assert not np.any(box[inside] >= 0), "a pixel owned twice"
+        box[inside] = t
     return owner
 
 

@@ -88,7 +88,8 @@ EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_op
            "gs_raster_bwd", "gs_project_bwd", "gs_render_stats", "gs_adam_step", "gs_project_bwd_adam",
            "gs_photometric_loss_workspace_size", "gs_photometric_loss", "gs_pyramid_camera", "gs_pyramid_reduce",
            "gs_raster_bwd_abs", "gs_project_bwd_adam_stats", "gs_default_density_config", "gs_scene_extent", "gs_density_accumulate",
-           "gs_density_workspace_size", "gs_density_plan", "gs_density_apply")
+           "gs_density_workspace_size", "gs_density_plan", "gs_density_apply", "gs_delaunay", "gs_densify_depth",
+           "gs_init_gaussians_workspace_size", "gs_init_gaussians_count", "gs_init_gaussians")
 
 _lib = None
 
@@ -137,6 +138,11 @@ def load(path: str = LIB_PATH):
                                                 C.POINTER(gs_adam_group), C.c_double, C.c_double, C.c_double, P, P,
                                                 C.POINTER(gs_density_stats), P]),
         "gs_default_density_config": (None, [C.POINTER(gs_density_config)]),
+        "gs_delaunay": (C.c_int, [P, i32, P, i32, C.POINTER(i32)]),
+        "gs_densify_depth": (C.c_int, [pc, P, P, i32, P, i32, P, C.c_float, P, P, P]),
+        "gs_init_gaussians_workspace_size": (C.c_int, [pc, C.POINTER(sz)]),
+        "gs_init_gaussians_count": (C.c_int, [pc, P, P, i32, P, P, sz, P]),
+        "gs_init_gaussians": (C.c_int, [pc, P, P, P, i32, i32, i64, C.POINTER(gs_grads), P, sz, P]),
         "gs_scene_extent": (C.c_int, [pc, i32, C.POINTER(C.c_float)]),
         "gs_density_accumulate": (C.c_int, [C.POINTER(gs_projected), i64, pc, i32, P, P,
                                             C.POINTER(gs_density_stats), P]),
@@ -338,3 +344,38 @@ def gs_project_bwd_adam_stats(params, proj, cams, n_views, opts, grad2d, groups,
     _check("gs_project_bwd_adam_stats", load().gs_project_bwd_adam_stats(
         C.byref(params), C.byref(proj), cams, n_views, C.byref(opts), grad2d, groups, beta1, beta2, eps, d_step,
         abs_grad2d, C.byref(stats), stream))
+
+
+def gs_delaunay(xy) -> "np.ndarray":
+    """Delaunay triangles of integer points xy [n, 2] (host): int32 [n_tris, 3]."""
+    import numpy as np
+    pts = np.ascontiguousarray(xy, np.int32)
+    n = pts.shape[0]
+    cap = max(2 * n, 1)
+    tris = np.zeros((cap, 3), np.int32)
+    nt = C.c_int32()
+    _check("gs_delaunay", load().gs_delaunay(pts.ctypes.data_as(C.c_void_p), n, tris.ctypes.data_as(C.c_void_p), cap,
+                                             C.byref(nt)))
+    return tris[:nt.value].copy()
+
+
+def gs_densify_depth(cam, xy, depth, n, tris, n_tris, image, tau, depth_map, tracked, stream):
+    _check("gs_densify_depth", load().gs_densify_depth(C.byref(cam), xy, depth, n, tris, n_tris, image, tau, depth_map,
+                                                       tracked, stream))
+
+
+def gs_init_gaussians_workspace_size(cam) -> int:
+    out = C.c_size_t()
+    _check("gs_init_gaussians_workspace_size", load().gs_init_gaussians_workspace_size(C.byref(cam), C.byref(out)))
+    return out.value
+
+
+def gs_init_gaussians_count(cam, depth_map, tracked, stride, d_count, workspace, workspace_bytes, stream):
+    _check("gs_init_gaussians_count", load().gs_init_gaussians_count(C.byref(cam), depth_map, tracked, stride, d_count,
+                                                                     workspace, workspace_bytes, stream))
+
+
+def gs_init_gaussians(cam, depth_map, tracked, image, stride, sh_degree, n_out, out, workspace, workspace_bytes,
+                      stream):
+    _check("gs_init_gaussians", load().gs_init_gaussians(C.byref(cam), depth_map, tracked, image, stride, sh_degree,
+                                                         n_out, C.byref(out), workspace, workspace_bytes, stream))

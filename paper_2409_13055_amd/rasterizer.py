@@ -14,6 +14,9 @@ rasteriser and the optimiser runs in the HIP kernels of libgs.so:
                    of keyframes, runnable eagerly or replayed from a HIP
                    graph; PerViewMappingStep runs the same kernels one view
                    at a time;
+  PointCloudInit   a keyframe's tracked pixels triangulated (gs_delaunay),
+                   depth interpolated over low-gradient pixels and new
+                   Gaussians initialised from it (Sec. III-A, III-B);
   ImagePyramid / PyramidMappingStep
                    the Gaussian pyramid of the ground-truth images
                    (gs_pyramid_reduce, Sec. III-B) and coarse-to-fine
@@ -778,3 +781,50 @@ class DensityControl:
                              exp_avg_sq=new_v, d_step=adam.d_step)
         self.last_counts = (kept, cloned, split)
         return new_p, new_adam
+
+
+class PointCloudInit:
+    """New Gaussians for a keyframe (Sec. III-A, III-B): its tracked pixels (integer xy, depth) are
+    triangulated on the host (gs_delaunay), the pixels of low-gradient regions take the mean depth of
+    their triangle's vertices (gs_densify_depth), and one Gaussian starts at every pixel with a depth
+    on the stride grid (gs_init_gaussians)."""
+
+    def __init__(self, cam, device="cuda"):
+        L.load()
+        self.cam = L.make_cameras([cam])[0]
+        self.W, self.H = int(cam.width), int(cam.height)
+        self.device = torch.device(device)
+        self.depth_map = torch.empty(self.W * self.H, dtype=torch.float32, device=self.device)
+        self.tracked = torch.empty(self.W * self.H, dtype=torch.uint8, device=self.device)
+        self.ws_bytes = L.gs_init_gaussians_workspace_size(self.cam)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.d_count = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.tris = None
+
+    def triangulate(self, xy) -> np.ndarray:
+        self.tris = L.gs_delaunay(np.asarray(xy))
+        return self.tris
+
+    def densify(self, xy, depth, image: torch.Tensor, tau: float = 0.02, tris: Optional[np.ndarray] = None):
+        """Depth map of the keyframe ([H W] on the device; 0 where none)."""
+        xy = np.ascontiguousarray(xy, np.int32)
+        tris = self.triangulate(xy) if tris is None else np.ascontiguousarray(tris, np.int32)
+        self.d_xy = torch.as_tensor(xy, device=self.device)
+        self.d_depth = torch.as_tensor(np.ascontiguousarray(depth, np.float32), device=self.device)
+        self.d_tris = torch.as_tensor(tris, device=self.device)
+        L.gs_densify_depth(self.cam, _p(self.d_xy), _p(self.d_depth), int(xy.shape[0]), _p(self.d_tris),
+                           int(tris.shape[0]), _p(image), float(tau), _p(self.depth_map), _p(self.tracked), _stream())
+        return self.depth_map
+
+    def count(self, stride: int) -> int:
+        L.gs_init_gaussians_count(self.cam, _p(self.depth_map), _p(self.tracked), int(stride), _p(self.d_count),
+                                  self.ws.data_ptr(), self.ws_bytes, _stream())
+        return int(self.d_count.item())
+
+    def init(self, image: torch.Tensor, stride: int, sh_degree: int, n_out: Optional[int] = None) -> GaussianParams:
+        """The new Gaussians of the current depth map (count() first, or pass its result as n_out)."""
+        n = self.count(stride) if n_out is None else int(n_out)
+        out = GaussianParams.empty(n, sh_degree, self.device)
+        L.gs_init_gaussians(self.cam, _p(self.depth_map), _p(self.tracked), _p(image), int(stride), int(sh_degree), n,
+                            out.c_grads(), self.ws.data_ptr(), self.ws_bytes, _stream())
+        return out

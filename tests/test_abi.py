@@ -205,3 +205,44 @@ def test_density_control_host_entry_points(L, oracle_lib):
     proj = L.gs_projected()
     with pytest.raises(L.GsError, match="tiles_touched"):
         L.gs_density_accumulate(proj, 1000, cc, 1, C.c_void_p(0x1000), C.c_void_p(0x2000), st, None)
+
+
+def test_delaunay_host_triangulation_matches_qhull(L, oracle_lib):
+    """gs_delaunay is host code: its triangles equal scipy's Qhull on points in general position,
+    and on integer grids (cocircular quadruples) both are valid Delaunay triangulations."""
+    import numpy as np
+    O = oracle_lib
+    rng = np.random.default_rng(17)
+    for n, W, H in [(3, 10, 10), (12, 30, 20), (300, 1200, 680), (2000, 1200, 680)]:
+        flat = rng.choice(W * H, n, replace=False)
+        pts = np.stack([flat % W, flat // W], 1)
+        got = L.gs_delaunay(pts)
+        ref = O.delaunay_triangles(pts)
+        same = np.array_equal(np.unique(np.sort(got, 1), axis=0), ref)
+        if not same:  # a cocircular quadruple: check validity instead
+            assert len(got) == len(ref)
+            P = [tuple(int(v) for v in p) for p in pts]
+            for i, j, k in got:
+                assert O._orient(P[i], P[j], P[k]) > 0
+                for m in rng.choice(n, min(n, 200), replace=False):
+                    if m not in (i, j, k):
+                        assert _incircle_exact(P[i], P[j], P[k], P[m]) <= 0
+        # canonical form: smallest index first, positive orientation, sorted
+        assert np.all(got[:, 0] < got[:, 1]) and np.all(got[:, 0] < got[:, 2])
+        assert [tuple(t) for t in got] == sorted(tuple(t) for t in got)
+    grid = np.array([(x, y) for y in range(0, 20, 4) for x in range(0, 24, 4)])
+    got = L.gs_delaunay(grid)
+    assert len(got) == 2 * (6 - 1) * (5 - 1)  # a grid of squares: two triangles each
+    with pytest.raises(L.GsError, match="distinct"):
+        L.gs_delaunay(np.array([[1, 1], [2, 5], [1, 1], [7, 3]]))
+    with pytest.raises(L.GsError, match="collinear"):
+        L.gs_delaunay(np.array([[0, 0], [1, 1], [2, 2], [5, 5]]))
+    with pytest.raises(L.GsError, match="outside"):
+        L.gs_delaunay(np.array([[0, 0], [40000, 1], [2, 9]]))
+
+
+def _incircle_exact(a, b, c, d):
+    rows = [(p[0] - d[0], p[1] - d[1]) for p in (a, b, c)]
+    m = [(x, y, x * x + y * y) for x, y in rows]
+    return (m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0])
+            + m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]))

@@ -1,0 +1,98 @@
+"""Point-cloud densification (Sec. III-A) and Gaussian initialisation (Sec. III-B) on the GPU
+against the FP64 oracle: the depth map from the triangulated tracked pixels (gs_densify_depth) and
+the new Gaussians (gs_init_gaussians_count / gs_init_gaussians).
+
+Bars: which pixels get a depth, the tracked mask and the count of new Gaussians exactly (integer
+ownership tests; the low-gradient decision is taken in FP32 without contraction on both sides);
+interpolated depths relative 1e-6 (an FP32 sum of three and a division); means relative 1e-5 of
+their distance from the camera (FP32 unprojection and rotation), log-scales 1e-6 absolute, sh_dc
+1e-6 absolute (FP32 (c - 1/2) / SH_C0 of values in [0, 1]).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2409_13055_amd import synthetic as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle.oracle as O  # noqa: E402
+from paper_2409_13055_amd import rasterizer as R  # noqa: E402
+
+DEV = "cuda"
+
+
+def keyframe(seed, W, H, n):
+    """Tracked pixels at random positions with the depths of a tilted plane, and an image that is
+    smooth except for a few vertical edges (so both sides of the gradient test occur)."""
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(W * H, n, replace=False)
+    xy = np.stack([flat % W, flat // W], 1).astype(np.int32)
+    depth = (2.0 + 0.002 * xy[:, 0] - 0.001 * xy[:, 1] + 0.01 * rng.standard_normal(n)).astype(np.float32)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float32)
+    base = 0.5 + 0.1 * np.sin(xx / 37.0) * np.cos(yy / 29.0)
+    img = np.stack([base, base * 0.9, base * 1.1]).astype(np.float32)
+    for x0 in rng.choice(W - 2, 6, replace=False):
+        img[:, :, x0 + 1:] += 0.2
+    img = np.clip(img, 0.0, 1.0).astype(np.float32)
+    return xy, depth, img
+
+
+def check(seed, W, H, n, stride, tau=0.02, sh_degree=3):
+    xy, depth, img = keyframe(seed, W, H, n)
+    cam = S.pinhole(W, H, 0.8 * W, *S.look_at((0.1, -0.2, -0.5), (0.0, 0.0, 2.0)))
+    pc = R.PointCloudInit(cam, device=DEV)
+    image = torch.as_tensor(img.reshape(-1), device=DEV)
+    dm = pc.densify(xy, depth, image, tau=tau)
+    torch.cuda.synchronize()
+    tris = pc.tris
+    ref_d, _ = O.interpolate_depth(xy, depth.astype(np.float64), tris, img, tau)
+    got_d = dm.cpu().numpy().reshape(H, W).astype(np.float64)
+    tracked = np.zeros((H, W), bool)
+    tracked[xy[:, 1], xy[:, 0]] = True
+    np.testing.assert_array_equal(pc.tracked.cpu().numpy().reshape(H, W).astype(bool), tracked)
+    np.testing.assert_array_equal(got_d > 0, ref_d > 0)
+    np.testing.assert_allclose(got_d, ref_d, rtol=1e-6, atol=0)
+    assert (ref_d > 0).sum() > 3 * n and not O.low_gradient_mask(img, tau).all()
+    n_new = pc.count(stride)
+    ref = O.init_gaussians(ref_d, img, cam, stride, tracked)
+    assert n_new == ref["pixels"].size
+    g = pc.init(image, stride, sh_degree, n_out=n_new)
+    torch.cuda.synchronize()
+    dist = np.linalg.norm(ref["means"] - cam.centre, axis=1)[:, None]
+    assert np.all(np.abs(g.means.cpu().numpy() - ref["means"]) <= 1e-5 * dist)
+    np.testing.assert_allclose(g.log_scales.cpu().numpy(), ref["log_scales"], rtol=0, atol=1e-6)
+    np.testing.assert_array_equal(g.quats.cpu().numpy(), ref["quats"])
+    np.testing.assert_allclose(g.opacity_logits.cpu().numpy(), ref["opacity_logits"], rtol=0, atol=1e-6)
+    np.testing.assert_allclose(g.sh_dc.cpu().numpy(), ref["sh_dc"], rtol=0, atol=1e-6)
+    assert not g.sh_rest.cpu().numpy().any()
+    return g
+
+
+def test_small_keyframe_with_ragged_blocks():
+    check(1, 97, 61, 40, 2)
+
+
+def test_full_size_keyframe():
+    # a 1200 x 680 keyframe with 3000 tracked pixels, every fourth pixel initialised
+    check(2, 1200, 680, 3000, 4)
+
+
+def test_degenerate_inputs():
+    # three points (one triangle) and a one-row-high image's neighbours: no interpolation outside it
+    W, H = 16, 9
+    xy = np.array([[1, 1], [12, 2], [5, 7]], np.int32)
+    depth = np.array([1.0, 2.0, 3.0], np.float32)
+    img = np.full((3, H, W), 0.5, np.float32)
+    cam = S.pinhole(W, H, 12.0)
+    pc = R.PointCloudInit(cam, device=DEV)
+    dm = pc.densify(xy, depth, torch.as_tensor(img.reshape(-1), device=DEV), tau=0.01)
+    ref, _ = O.interpolate_depth(xy, depth.astype(np.float64), pc.tris, img, 0.01)
+    np.testing.assert_allclose(dm.cpu().numpy().reshape(H, W), ref, rtol=1e-6)
+    assert math.isclose(float(ref[4, 6]), 2.0, rel_tol=1e-12)
+    assert pc.count(1) == int((ref > 0).sum())
