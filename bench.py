@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-ssim", action="store_true", help="skip the measurement of eq. (2) with its SSIM term")
     ap.add_argument("--no-density", action="store_true",
                     help="skip the measurement of adaptive density control (statistics and densify-and-prune)")
+    ap.add_argument("--no-pointcloud", action="store_true",
+                    help="skip the measurement of point-cloud densification and Gaussian initialisation")
     ap.add_argument("--no-pyramid", action="store_true",
                     help="skip the measurement of the image pyramid and of the coarse-level iterations")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -328,6 +330,47 @@ def main():
             f"({gbs:.0f} GB/s alg), {kept}+{cloned}+2x{split} -> {n_out}")
         del st, outs, dc
 
+    pointcloud = None
+    if not args.no_pointcloud:
+        # one keyframe's densification (Sec. III-A) and the new Gaussians (Sec. III-B): 3000 tracked
+        # pixels of a 1200 x 680 view, every fourth pixel initialised
+        cam0 = sc.cameras[0]
+        xy, dep, img0 = S.tracked_keyframe(7, cam0.width, cam0.height, 3000)
+        pc = R.PointCloudInit(cam0, device=dev)
+        image0 = torch.as_tensor(img0.reshape(-1), device=dev)
+        t_host = time.perf_counter()
+        for _ in range(args.steps):
+            pc.triangulate(xy)
+        ms_tri = (time.perf_counter() - t_host) * 1e3 / args.steps
+        pc.densify(xy, dep, image0, tris=pc.tris)
+        n_new = pc.count(4)
+        out0 = R.GaussianParams.empty(n_new, sc.sh_degree, dev)
+        for _ in range(args.warmup):
+            pc.fill(image0)
+            pc.init_into(image0, 4, out0)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            pc.fill(image0)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_fill = e0.elapsed_time(e1) / args.steps
+        e0.record()
+        for _ in range(args.steps):
+            pc.init_into(image0, 4, out0)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_init = e0.elapsed_time(e1) / args.steps
+        px0 = cam0.width * cam0.height
+        pn = 11 + 3 * (sc.sh_degree + 1) ** 2
+        pointcloud = {"tracked": int(xy.shape[0]), "triangles": int(pc.tris.shape[0]), "new_gaussians": n_new,
+                      "delaunay_host_ms": round(ms_tri, 3), "densify_ms": round(ms_fill, 4),
+                      "init_ms": round(ms_init, 4),
+                      "densify_alg_bytes": px0 * (12 + 4 + 1), "init_alg_bytes": px0 * (4 + 1) + n_new * (4 * pn + 12)}
+        log(f"[bench] point cloud: Delaunay of {xy.shape[0]} points {ms_tri:.2f} ms (host), depth fill "
+            f"{ms_fill:.3f} ms, initialisation of {n_new} Gaussians {ms_init:.3f} ms")
+        del pc, out0
+
     roof = roofline(step, sc, stages, work)
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, tile)
     out = {
@@ -352,6 +395,7 @@ def main():
         "ssim": ssim,
         "pyramid": pyramid,
         "density": density,
+        "pointcloud": pointcloud,
         "stages_ms": stages,
         "roofline": roof,
         "cpu_baseline": cpu,

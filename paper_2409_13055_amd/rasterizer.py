@@ -816,6 +816,19 @@ class PointCloudInit:
                            int(tris.shape[0]), _p(image), float(tau), _p(self.depth_map), _p(self.tracked), _stream())
         return self.depth_map
 
+    def fill(self, image: torch.Tensor, tau: float = 0.02):
+        """gs_densify_depth again on the points and triangles of the last densify() (no host work)."""
+        L.gs_densify_depth(self.cam, _p(self.d_xy), _p(self.d_depth), int(self.d_xy.shape[0]), _p(self.d_tris),
+                           int(self.d_tris.shape[0]), _p(image), float(tau), _p(self.depth_map), _p(self.tracked),
+                           _stream())
+
+    def init_into(self, image: torch.Tensor, stride: int, out: GaussianParams):
+        """gs_init_gaussians_count then gs_init_gaussians into `out` (sized by an earlier count())."""
+        L.gs_init_gaussians_count(self.cam, _p(self.depth_map), _p(self.tracked), int(stride), _p(self.d_count),
+                                  self.ws.data_ptr(), self.ws_bytes, _stream())
+        L.gs_init_gaussians(self.cam, _p(self.depth_map), _p(self.tracked), _p(image), int(stride), out.sh_degree,
+                            out.n, out.c_grads(), self.ws.data_ptr(), self.ws_bytes, _stream())
+
     def count(self, stride: int) -> int:
         L.gs_init_gaussians_count(self.cam, _p(self.depth_map), _p(self.tracked), int(stride), _p(self.d_count),
                                   self.ws.data_ptr(), self.ws_bytes, _stream())

@@ -185,6 +185,23 @@ def arc_cameras(rng, sizes):
     return cams
 
 
+def tracked_keyframe(seed, W, H, n):
+    """A keyframe's tracked pixels and image for point-cloud densification: n distinct pixels at
+    uniform random positions (integer xy) with the depths of a tilted plane plus N(0, 0.01) noise,
+    and an image that is smooth (a product of sines) except for six vertical steps of +0.2, so both
+    outcomes of a gradient test occur.  Returns xy int32 [n, 2], depth f32 [n], image f32 [3, H, W]."""
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(W * H, n, replace=False)
+    xy = np.stack([flat % W, flat // W], 1).astype(np.int32)
+    depth = (2.0 + 0.002 * xy[:, 0] - 0.001 * xy[:, 1] + 0.01 * rng.standard_normal(n)).astype(np.float32)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float32)
+    base = 0.5 + 0.1 * np.sin(xx / 37.0) * np.cos(yy / 29.0)
+    img = np.stack([base, base * 0.9, base * 1.1]).astype(np.float32)
+    for x0 in rng.choice(W - 2, 6, replace=False):
+        img[:, :, x0 + 1:] += 0.2
+    return xy, depth, np.clip(img, 0.0, 1.0).astype(np.float32)
+
+
 def _f32(*arrs):
     return [np.ascontiguousarray(a, dtype=np.float32) for a in arrs]
 

@@ -27,24 +27,8 @@ from paper_2409_13055_amd import rasterizer as R  # noqa: E402
 DEV = "cuda"
 
 
-def keyframe(seed, W, H, n):
-    """Tracked pixels at random positions with the depths of a tilted plane, and an image that is
-    smooth except for a few vertical edges (so both sides of the gradient test occur)."""
-    rng = np.random.default_rng(seed)
-    flat = rng.choice(W * H, n, replace=False)
-    xy = np.stack([flat % W, flat // W], 1).astype(np.int32)
-    depth = (2.0 + 0.002 * xy[:, 0] - 0.001 * xy[:, 1] + 0.01 * rng.standard_normal(n)).astype(np.float32)
-    yy, xx = np.mgrid[0:H, 0:W].astype(np.float32)
-    base = 0.5 + 0.1 * np.sin(xx / 37.0) * np.cos(yy / 29.0)
-    img = np.stack([base, base * 0.9, base * 1.1]).astype(np.float32)
-    for x0 in rng.choice(W - 2, 6, replace=False):
-        img[:, :, x0 + 1:] += 0.2
-    img = np.clip(img, 0.0, 1.0).astype(np.float32)
-    return xy, depth, img
-
-
 def check(seed, W, H, n, stride, tau=0.02, sh_degree=3):
-    xy, depth, img = keyframe(seed, W, H, n)
+    xy, depth, img = S.tracked_keyframe(seed, W, H, n)
     cam = S.pinhole(W, H, 0.8 * W, *S.look_at((0.1, -0.2, -0.5), (0.0, 0.0, 2.0)))
     pc = R.PointCloudInit(cam, device=DEV)
     image = torch.as_tensor(img.reshape(-1), device=DEV)
