@@ -652,9 +652,14 @@ class PyramidMappingStep:
     explicit per-view level tuple: keyframes at different levels share one batch."""
 
     def __init__(self, params: GaussianParams, cameras, targets, levels: int = 2, schedule=None, lrs=None,
-                 graphs: bool = True, **step_opts):
+                 graphs: bool = True, adam: Optional[FusedAdam] = None, pyramid: Optional["ImagePyramid"] = None,
+                 iteration: int = 0, **step_opts):
+        """`adam`, `pyramid`, `iteration`: an optimiser state, a built pyramid of these targets and a
+        position in the schedule to continue from (after density control changed the set)."""
         self.params = params
-        self.pyramid = ImagePyramid(cameras, targets, levels, device=params.means.device)
+        self.pyramid = pyramid if pyramid is not None else ImagePyramid(cameras, targets, levels,
+                                                                        device=params.means.device)
+        levels = self.pyramid.levels
         self.schedule = list(schedule) if schedule is not None else [100] * levels
         if len(self.schedule) != levels:
             raise ValueError("schedule needs one iteration count per coarse level")
@@ -662,10 +667,10 @@ class PyramidMappingStep:
         self.lrs = lrs
         self.graphs = graphs
         self.step_opts = step_opts
-        self.adam = FusedAdam(params, params.zeros_like(), lrs)
+        self.adam = adam if adam is not None else FusedAdam(params, params.zeros_like(), lrs)
         self.steps: Dict[tuple, MappingStep] = {}
         self._ran_at_capture = set()  # keys whose newest iteration capture() already ran
-        self.iteration = 0
+        self.iteration = int(iteration)
 
     def level_at(self, iteration: int) -> int:
         lv = self.pyramid.levels
@@ -841,3 +846,40 @@ class PointCloudInit:
         L.gs_init_gaussians(self.cam, _p(self.depth_map), _p(self.tracked), _p(image), int(stride), int(sh_degree), n,
                             out.c_grads(), self.ws.data_ptr(), self.ws_bytes, _stream())
         return out
+
+
+class MappingLoop:
+    """The mapping iterations of Sec. III-B over a keyframe window: coarse-to-fine over the Gaussian
+    pyramid of the targets, the loss of eq. (2) (ssim_lambda > 0 adds its SSIM term), Adam, and
+    every `densify_every` iterations (1000 in Sec. IV-A) the adaptive density control, after which
+    the iterations continue on the new set with the optimiser state and the schedule position
+    handed over.  Every step runs in libgs kernels; the loop only sequences them."""
+
+    def __init__(self, params: GaussianParams, cameras, targets, lrs=None, levels: int = 2, schedule=None,
+                 ssim_lambda: float = 0.2, densify_every: int = 1000, tile_size: int = 16, graphs: bool = True,
+                 generator: Optional[torch.Generator] = None, **density_cfg):
+        self.cameras, self.lrs = list(cameras), lrs
+        self.densify_every = int(densify_every)
+        self.generator = generator
+        self.density = DensityControl(params.n, cameras, device=params.means.device, **density_cfg)
+        self._opts = dict(schedule=schedule, lrs=lrs, graphs=graphs, ssim_lambda=ssim_lambda, tile_size=tile_size,
+                          density=self.density)
+        self.steps = PyramidMappingStep(params, cameras, targets, levels=levels, **self._opts)
+        self.iteration = 0
+        self.history = []  # (iteration, n) after each density step
+
+    @property
+    def params(self) -> GaussianParams:
+        return self.steps.params
+
+    def run(self, iterations: int) -> MappingStep:
+        st = None
+        for _ in range(int(iterations)):
+            st = self.steps.run()
+            self.iteration += 1
+            if self.densify_every > 0 and self.iteration % self.densify_every == 0:
+                new_p, new_adam = self.density.apply(self.steps.params, self.steps.adam, generator=self.generator)
+                self.steps = PyramidMappingStep(new_p, self.cameras, None, adam=new_adam, pyramid=self.steps.pyramid,
+                                                iteration=self.steps.iteration, **self._opts)
+                self.history.append((self.iteration, new_p.n))
+        return st

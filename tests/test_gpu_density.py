@@ -180,3 +180,26 @@ def test_fused_statistics_equal_the_standalone_kernel():
     assert int(dc.count.sum().item()) > 0
     for a, b in ((dc.grad_accum, solo.grad_accum), (dc.abs_accum, solo.abs_accum), (dc.count, solo.count)):
         assert torch.equal(a, b)
+
+
+def test_mapping_loop_pyramid_ssim_and_density_control():
+    """The mapping loop end to end: coarse-to-fine levels, eq. (2) with its SSIM term, Adam, and
+    density control every four iterations with the state handed over."""
+    sc = small_scene(10)
+    params = R.GaussianParams.from_scene(sc, DEV)
+    n0 = params.n
+    loop = R.MappingLoop(params, sc.cameras, sc.targets, lrs=dict(S.DEFAULT_LRS), levels=1, schedule=[3],
+                         ssim_lambda=0.2, densify_every=4, generator=torch.Generator(device=DEV).manual_seed(3),
+                         grad_threshold=1e-7)
+    st = loop.run(10)
+    torch.cuda.synchronize()
+    assert [h[0] for h in loop.history] == [4, 8]
+    assert loop.history[0][1] > n0 and loop.params.n == loop.history[-1][1]
+    assert int(loop.steps.adam.d_step.item()) == 10
+    assert loop.steps.iteration == 10 and loop.steps.level_at(9) == 0 and loop.steps.level_at(0) == 1
+    assert st.rast.cameras[0].width == sc.cameras[0].width  # the last iterations ran at full resolution
+    assert np.isfinite(st.loss.cpu().numpy()).all() and float(st.loss.sum()) > 0
+    # the statistics of the two iterations since the last density step
+    assert int(loop.density.count.max().item()) == 2 * len(sc.cameras)
+    for t in loop.params.tensors():
+        assert torch.isfinite(t).all()
