@@ -10,7 +10,8 @@
 //    hull, built on the host by Bowyer-Watson insertion with exact integer
 //    predicates (64-bit orientation, 128-bit in-circle) and ghost triangles
 //    for the hull, so it is exact; where four points are cocircular it is one
-//    of the valid triangulations;
+//    of the valid triangulations (conflicts are looked up in a bucket grid of
+//    circumcircles);
 //  - a pixel belongs to the triangle whose closed interior holds it, an edge
 //    shared by two triangles going to one of them: edge a -> b of a triangle
 //    of positive orientation is its own when b.y > a.y, or b.y == a.y and
@@ -110,19 +111,65 @@ static gs_status delaunay(const int32_t* xy, int n, std::vector<DTri>& out) {
   if (i2 < 0) return fail(GS_ERR_INVALID_VALUE, "the points are collinear");
   int a = 0, b = 1, c = i2;
   if (orient2(P[a], P[b], P[c]) < 0) std::swap(b, c);
+  // Triangles live in slots that are never reused.  A bucket grid over the points' bounding box
+  // lists, per cell, the real triangles whose (filtered) circumcircle's box meets the cell; ghost
+  // triangles, slivers and circles spanning much of the grid sit in one global list.  A point's
+  // conflicts are then among its cell's list and the global list; dead slots are dropped from the
+  // lists as they are scanned.
+  int64_t bx0 = P[0].x, bx1 = P[0].x, by0 = P[0].y, by1 = P[0].y;
+  for (const IPt& q : P) {
+    bx0 = std::min(bx0, q.x);
+    bx1 = std::max(bx1, q.x);
+    by0 = std::min(by0, q.y);
+    by1 = std::max(by1, q.y);
+  }
+  const int G = std::max(1, (int)std::sqrt((double)n / 2.0));
+  const double cw = std::max(1.0, (double)(bx1 - bx0 + 1) / G), ch = std::max(1.0, (double)(by1 - by0 + 1) / G);
+  std::vector<std::vector<int>> cells((size_t)G * G);
+  std::vector<int> global;
   std::vector<DTri> T;
-  T.push_back(make_tri(a, b, c, P));
-  T.push_back(make_tri(b, a, -1, P));
-  T.push_back(make_tri(c, b, -1, P));
-  T.push_back(make_tri(a, c, -1, P));
+  std::vector<char> alive;
+  auto cell_x = [&](double x) { return std::min(G - 1, std::max(0, (int)std::floor((x - (double)bx0) / cw))); };
+  auto cell_y = [&](double y) { return std::min(G - 1, std::max(0, (int)std::floor((y - (double)by0) / ch))); };
+  auto add = [&](const DTri& t) {
+    const int id = (int)T.size();
+    T.push_back(t);
+    alive.push_back(1);
+    if (t.v[2] < 0 || !t.filter) {
+      global.push_back(id);
+      return;
+    }
+    const double r = std::sqrt(t.r2) + 1.0;  // the filter's margin is far below a pixel
+    const int cx0 = cell_x(t.cx - r), cx1 = cell_x(t.cx + r), cy0 = cell_y(t.cy - r), cy1 = cell_y(t.cy + r);
+    if ((int64_t)(cx1 - cx0 + 1) * (cy1 - cy0 + 1) * 4 > (int64_t)G * G) {
+      global.push_back(id);
+      return;
+    }
+    for (int yy = cy0; yy <= cy1; ++yy)
+      for (int xx = cx0; xx <= cx1; ++xx) cells[(size_t)yy * G + xx].push_back(id);
+  };
+  add(make_tri(a, b, c, P));
+  add(make_tri(b, a, -1, P));
+  add(make_tri(c, b, -1, P));
+  add(make_tri(a, c, -1, P));
   std::vector<int> bad;
   std::vector<std::pair<int, int>> edges, boundary;
+  auto scan = [&](std::vector<int>& list, const IPt& p) {
+    size_t w = 0;
+    for (size_t k = 0; k < list.size(); ++k) {
+      const int id = list[k];
+      if (!alive[id]) continue;
+      list[w++] = id;
+      if (in_conflict(T[id], P, p)) bad.push_back(id);
+    }
+    list.resize(w);
+  };
   for (int ip = 2; ip < n; ++ip) {
     if (ip == i2) continue;
     const IPt& p = P[ip];
     bad.clear();
-    for (int t = 0; t < (int)T.size(); ++t)
-      if (in_conflict(T[t], P, p)) bad.push_back(t);
+    scan(cells[(size_t)cell_y((double)p.y) * G + cell_x((double)p.x)], p);
+    scan(global, p);
     if (bad.empty()) return fail(GS_ERR_INVALID_VALUE, "delaunay: a point in no triangle's circle");
     edges.clear();
     for (int t : bad)
@@ -137,26 +184,21 @@ static gs_status delaunay(const int32_t* xy, int n, std::vector<DTri>& out) {
         }
       if (!shared) boundary.push_back(e);
     }
-    // remove the cavity (highest index first, swapping the last triangle in)
-    std::sort(bad.begin(), bad.end());
-    for (int k = (int)bad.size() - 1; k >= 0; --k) {
-      T[bad[k]] = T.back();
-      T.pop_back();
-    }
+    for (int t : bad) alive[t] = 0;
     for (const auto& e : boundary) {
       if (e.first == -1) {
-        T.push_back(make_tri(e.second, ip, -1, P));
+        add(make_tri(e.second, ip, -1, P));
       } else if (e.second == -1) {
-        T.push_back(make_tri(ip, e.first, -1, P));
+        add(make_tri(ip, e.first, -1, P));
       } else {
         if (orient2(P[e.first], P[e.second], p) <= 0) return fail(GS_ERR_INVALID_VALUE, "delaunay: degenerate cavity");
-        T.push_back(make_tri(e.first, e.second, ip, P));
+        add(make_tri(e.first, e.second, ip, P));
       }
     }
   }
   out.clear();
-  for (const DTri& t : T)
-    if (t.v[2] >= 0) out.push_back(t);
+  for (size_t t = 0; t < T.size(); ++t)
+    if (alive[t] && T[t].v[2] >= 0) out.push_back(T[t]);
   return GS_OK;
 }
 
