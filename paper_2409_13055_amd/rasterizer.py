@@ -738,7 +738,8 @@ class DensityControl:
         self.grad_accum = torch.zeros(self.n, dtype=torch.float32, device=self.device)
         self.abs_accum = torch.zeros(self.n, dtype=torch.float32, device=self.device)
         self.count = torch.zeros(self.n, dtype=torch.int32, device=self.device)
-        self.ws_bytes = L.gs_density_workspace_size(self.n)
+        # an empty set (everything pruned) has no plan to hold
+        self.ws_bytes = L.gs_density_workspace_size(self.n) if self.n > 0 else 0
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self._stats = L.gs_density_stats(_p(self.grad_accum), _p(self.abs_accum), _p(self.count))
 

@@ -203,3 +203,27 @@ def test_mapping_loop_pyramid_ssim_and_density_control():
     assert int(loop.density.count.max().item()) == 2 * len(sc.cameras)
     for t in loop.params.tensors():
         assert torch.isfinite(t).all()
+
+
+def test_density_step_edge_cases():
+    """No Gaussian selected (nothing split or cloned, eps empty) and every Gaussian pruned
+    (an empty new set, no launch)."""
+    sc = S.make_scene(4, 700, 1, [S.pinhole(64, 48, 50.0)], "box", log_scale_mu=-2.0, log_scale_sigma=1.0)
+    params = R.GaussianParams.from_scene(sc, DEV)
+    adam = R.FusedAdam(params, params.zeros_like(), dict(S.DEFAULT_LRS))
+    dc = R.DensityControl(params.n, sc.cameras, device=DEV, extent=5.0)
+    new_p, new_adam = dc.apply(params, adam)  # zero statistics: nothing selected
+    torch.cuda.synchronize()
+    kept, cloned, split = dc.last_counts
+    pruned = int((params.opacity_logits.cpu().numpy() < np.float32(np.log(0.005 / 0.995))).sum())
+    assert (cloned, split) == (0, 0) and kept == params.n - pruned and new_p.n == kept
+    keep = params.opacity_logits.cpu().numpy() >= np.float32(np.log(0.005 / 0.995))
+    np.testing.assert_array_equal(new_p.means.cpu().numpy(), params.means.cpu().numpy()[keep])
+    np.testing.assert_array_equal(new_adam.exp_avg.means.cpu().numpy(), adam.exp_avg.means.cpu().numpy()[keep])
+    params.opacity_logits.fill_(-10.0)  # every Gaussian below the opacity bound
+    dc2 = R.DensityControl(params.n, sc.cameras, device=DEV, extent=5.0)
+    dc2.count.fill_(3)
+    dc2.abs_accum.fill_(1.0)
+    empty, _ = dc2.apply(params, adam)
+    torch.cuda.synchronize()
+    assert dc2.last_counts == (0, 0, 0) and empty.n == 0

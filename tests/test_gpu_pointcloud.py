@@ -80,3 +80,26 @@ def test_degenerate_inputs():
     np.testing.assert_allclose(dm.cpu().numpy().reshape(H, W), ref, rtol=1e-6)
     assert math.isclose(float(ref[4, 6]), 2.0, rel_tol=1e-12)
     assert pc.count(1) == int((ref > 0).sum())
+
+
+def test_border_points_and_zero_threshold():
+    # tracked pixels on all four borders (one-sided gradients there) and tau = 0: nothing is of
+    # low gradient, so only the tracked pixels have a depth
+    W, H = 50, 31
+    rng = np.random.default_rng(6)
+    xy = np.array([[0, 0], [W - 1, 0], [0, H - 1], [W - 1, H - 1], [0, 15], [W - 1, 9], [20, 0], [33, H - 1],
+                   [25, 15], [10, 20]], np.int32)
+    depth = rng.uniform(1.0, 3.0, len(xy)).astype(np.float32)
+    _, _, img = S.tracked_keyframe(3, W, H, 5)
+    cam = S.pinhole(W, H, 40.0)
+    pc = R.PointCloudInit(cam, device=DEV)
+    image = torch.as_tensor(img.reshape(-1), device=DEV)
+    for tau in (0.0, 0.05):
+        dm = pc.densify(xy, depth, image, tau=tau).cpu().numpy().reshape(H, W).astype(np.float64)
+        ref, _ = O.interpolate_depth(xy, depth.astype(np.float64), pc.tris, img, tau)
+        np.testing.assert_array_equal(dm > 0, ref > 0)
+        np.testing.assert_allclose(dm, ref, rtol=1e-6)
+        if tau == 0.0:
+            assert int((dm > 0).sum()) == len(xy)
+        else:
+            assert int((dm > 0).sum()) > 10 * len(xy)  # the hull covers the image
