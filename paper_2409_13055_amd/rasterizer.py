@@ -851,21 +851,29 @@ class PointCloudInit:
 
 class MappingLoop:
     """The mapping iterations of Sec. III-B over a keyframe window: coarse-to-fine over the Gaussian
-    pyramid of the targets, the loss of eq. (2) (ssim_lambda > 0 adds its SSIM term), Adam, and
-    every `densify_every` iterations (1000 in Sec. IV-A) the adaptive density control, after which
-    the iterations continue on the new set with the optimiser state and the schedule position
-    handed over.  Every step runs in libgs kernels; the loop only sequences them."""
+    pyramid of the targets, each keyframe on its own schedule (a keyframe added later starts at the
+    coarsest level while the others train at full resolution, in one batch of mixed view sizes),
+    the loss of eq. (2) (ssim_lambda > 0 adds its SSIM term), Adam, and every `densify_every`
+    iterations (1000 in Sec. IV-A) the adaptive density control, after which the iterations
+    continue on the new set with the optimiser state handed over.  add_keyframe() initialises the
+    new keyframe's Gaussians from its tracked pixels (Sec. III-A) and appends them (zero moments).
+    Every step of the method runs in libgs kernels; the loop sequences them, and appending
+    Gaussians is a device copy."""
 
     def __init__(self, params: GaussianParams, cameras, targets, lrs=None, levels: int = 2, schedule=None,
                  ssim_lambda: float = 0.2, densify_every: int = 1000, tile_size: int = 16, graphs: bool = True,
                  generator: Optional[torch.Generator] = None, **density_cfg):
-        self.cameras, self.lrs = list(cameras), lrs
+        self.cameras, self.lrs, self.levels = list(cameras), lrs, int(levels)
+        self.targets = [t if isinstance(t, torch.Tensor) else pack_images([t], params.means.device)
+                        for t in targets]
         self.densify_every = int(densify_every)
         self.generator = generator
         self.density = DensityControl(params.n, cameras, device=params.means.device, **density_cfg)
         self._opts = dict(schedule=schedule, lrs=lrs, graphs=graphs, ssim_lambda=ssim_lambda, tile_size=tile_size,
                           density=self.density)
-        self.steps = PyramidMappingStep(params, cameras, targets, levels=levels, **self._opts)
+        self.steps = PyramidMappingStep(params, self.cameras, torch.cat(self.targets), levels=self.levels,
+                                        **self._opts)
+        self.kf_iters = [0] * len(self.cameras)  # iterations each keyframe has trained
         self.iteration = 0
         self.history = []  # (iteration, n) after each density step
 
@@ -873,14 +881,48 @@ class MappingLoop:
     def params(self) -> GaussianParams:
         return self.steps.params
 
+    def _rebuild(self, params: GaussianParams, adam: FusedAdam, rebuild_pyramid: bool = False):
+        pyr = None if rebuild_pyramid else self.steps.pyramid
+        self.steps = PyramidMappingStep(params, self.cameras, torch.cat(self.targets), levels=self.levels,
+                                        adam=adam, pyramid=pyr, **self._opts)
+
     def run(self, iterations: int) -> MappingStep:
         st = None
         for _ in range(int(iterations)):
-            st = self.steps.run()
+            st = self.steps.run_levels([self.steps.level_at(k) for k in self.kf_iters])
+            self.kf_iters = [k + 1 for k in self.kf_iters]
             self.iteration += 1
             if self.densify_every > 0 and self.iteration % self.densify_every == 0:
                 new_p, new_adam = self.density.apply(self.steps.params, self.steps.adam, generator=self.generator)
-                self.steps = PyramidMappingStep(new_p, self.cameras, None, adam=new_adam, pyramid=self.steps.pyramid,
-                                                iteration=self.steps.iteration, **self._opts)
+                self._rebuild(new_p, new_adam)
                 self.history.append((self.iteration, new_p.n))
         return st
+
+    def add_keyframe(self, cam, target, xy, depth, stride: int = 4, tau: float = 0.02) -> int:
+        """Appends keyframe `cam` with its image `target` ([3, H, W]) and the Gaussians initialised
+        from its tracked pixels (integer xy, depth); returns how many were added."""
+        dev = self.params.means.device
+        image = target if isinstance(target, torch.Tensor) else pack_images([target], dev)
+        pc = PointCloudInit(cam, device=dev)
+        pc.densify(xy, depth, image, tau=tau)
+        new = pc.init(image, stride, self.params.sh_degree)
+        old, adam = self.params, self.steps.adam
+        cat = lambda a, b: torch.cat([a, b]).contiguous()  # noqa: E731
+        params = GaussianParams(*[cat(getattr(old, k), getattr(new, k)) for k in PARAM_NAMES], old.sh_degree)
+        zeros = new.zeros_like()
+        m = GaussianParams(*[cat(getattr(adam.exp_avg, k), getattr(zeros, k)) for k in PARAM_NAMES], old.sh_degree)
+        v = GaussianParams(*[cat(getattr(adam.exp_avg_sq, k), getattr(zeros, k)) for k in PARAM_NAMES],
+                           old.sh_degree)
+        new_adam = FusedAdam(params, params.zeros_like(), adam.lrs, adam.betas, adam.eps, exp_avg=m, exp_avg_sq=v,
+                             d_step=adam.d_step)
+        # the statistics of the existing Gaussians carry on; the new ones start at zero
+        g, a, c = self.density.grad_accum, self.density.abs_accum, self.density.count
+        self.density._alloc(params.n)
+        self.density.grad_accum[:old.n].copy_(g)
+        self.density.abs_accum[:old.n].copy_(a)
+        self.density.count[:old.n].copy_(c)
+        self.cameras.append(cam)
+        self.targets.append(image)
+        self.kf_iters.append(0)
+        self._rebuild(params, new_adam, rebuild_pyramid=True)
+        return new.n

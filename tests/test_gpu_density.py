@@ -196,7 +196,7 @@ def test_mapping_loop_pyramid_ssim_and_density_control():
     assert [h[0] for h in loop.history] == [4, 8]
     assert loop.history[0][1] > n0 and loop.params.n == loop.history[-1][1]
     assert int(loop.steps.adam.d_step.item()) == 10
-    assert loop.steps.iteration == 10 and loop.steps.level_at(9) == 0 and loop.steps.level_at(0) == 1
+    assert loop.kf_iters == [10, 10] and loop.steps.level_at(9) == 0 and loop.steps.level_at(0) == 1
     assert st.rast.cameras[0].width == sc.cameras[0].width  # the last iterations ran at full resolution
     assert np.isfinite(st.loss.cpu().numpy()).all() and float(st.loss.sum()) > 0
     # the statistics of the two iterations since the last density step
@@ -227,3 +227,30 @@ def test_density_step_edge_cases():
     empty, _ = dc2.apply(params, adam)
     torch.cuda.synchronize()
     assert dc2.last_counts == (0, 0, 0) and empty.n == 0
+
+
+def test_mapping_loop_adds_a_keyframe_at_the_coarsest_level():
+    """A keyframe added to the window: its Gaussians come from its tracked pixels, it trains from
+    the coarsest level in the same batch as the others at full resolution, and the optimiser and
+    density state carry over."""
+    sc = small_scene(11)
+    params = R.GaussianParams.from_scene(sc, DEV)
+    loop = R.MappingLoop(params, sc.cameras, sc.targets, lrs=dict(S.DEFAULT_LRS), levels=1, schedule=[2],
+                         ssim_lambda=0.2, densify_every=0)
+    loop.run(3)
+    n_before = loop.params.n
+    cam = S.pinhole(120, 90, 100.0, *S.look_at((0.2, 0.2, -0.4), (0.0, 0.0, 3.0)))
+    xy, depth, img = S.tracked_keyframe(5, 120, 90, 60)
+    depth = depth + 1.5  # in front of the scene box
+    added = loop.add_keyframe(cam, img, xy, depth, stride=3)
+    assert added > 60 and loop.params.n == n_before + added
+    assert int(loop.density.count[n_before:].sum().item()) == 0
+    st = loop.run(1)
+    torch.cuda.synchronize()
+    # the first two keyframes at full resolution, the new one at level 1
+    assert [c.width for c in st.rast.cameras] == [sc.cameras[0].width, sc.cameras[1].width, 60]
+    assert int(loop.steps.adam.d_step.item()) == 4
+    assert np.isfinite(st.loss.cpu().numpy()).all()
+    loop.run(2)
+    torch.cuda.synchronize()
+    assert loop.kf_iters == [6, 6, 3] and int(loop.steps.adam.d_step.item()) == 6
