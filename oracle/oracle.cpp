@@ -88,7 +88,7 @@ enum : uint32_t {
   F_NEAR_RADIUS = 1u << 16, F_NEAR_RECT = 1u << 17, F_NEAR_PLANE = 1u << 18,
 };
 // Per-pixel flag bits: a decision within a relative margin of its threshold.
-enum : uint32_t { P_NEAR_ALPHA_MIN = 1u, P_NEAR_T_MIN = 2u, P_NEAR_ALPHA_MAX = 4u };
+enum : uint32_t { P_NEAR_ALPHA_MIN = 1u, P_NEAR_T_MIN = 2u, P_NEAR_ALPHA_MAX = 4u, P_NEAR_POWER0 = 8u };
 
 inline int sh_count(int D) { return (D + 1) * (D + 1); }
 
@@ -353,6 +353,14 @@ struct Accepted {
   bool clamped;  // o*G exceeded alpha_max
 };
 
+// A decision of the blending at one list entry that lies within the FP32
+// rounding bound of its threshold: `kind` is the P_NEAR_* bit of the test.
+struct FlaggedDecision {
+  int k;
+  uint32_t kind;
+};
+constexpr int kMaxFlagged = 8;
+
 struct PixelTrace {
   std::vector<Accepted> acc;
   double C[3];
@@ -360,16 +368,41 @@ struct PixelTrace {
   int n_contrib;
   uint32_t flags;
   int stop_k;  // list position of the Gaussian that ended the pixel, or -1
+  // the first kMaxFlagged near-threshold decisions in list order, and their number
+  FlaggedDecision flagged[kMaxFlagged];
+  int n_flagged;
+  // smallest relative distance of an evaluated entry's alpha from alpha_min, and of
+  // a blended or stopping entry's transmittance from t_min
+  double margin_alpha, margin_t;
+};
+
+// The decision at list position flip.k of kind flip.kind is taken the other
+// way (for the alternatives an FP32 evaluation may produce at a flagged
+// decision); flip.k < 0 takes every decision as the definition says.
+struct Flip {
+  int k = -1;
+  uint32_t kind = 0;
 };
 
 void trace_pixel(double px, double py, const uint32_t* list, int64_t len, const double* rec, const OrOptions& o,
-                 bool keep, PixelTrace& tr, uint32_t ov_id = 0xffffffffu, const double* ov_row = nullptr) {
+                 bool keep, PixelTrace& tr, uint32_t ov_id = 0xffffffffu, const double* ov_row = nullptr,
+                 Flip flip = Flip()) {
   tr.acc.clear();
   tr.C[0] = tr.C[1] = tr.C[2] = 0;
   tr.T = 1.0;
   tr.n_contrib = 0;
   tr.flags = 0;
   tr.stop_k = -1;
+  tr.n_flagged = 0;
+  tr.margin_alpha = tr.margin_t = INFINITY;
+  auto flag = [&](int64_t k, uint32_t kind) {
+    tr.flags |= kind;
+    if (tr.n_flagged < kMaxFlagged) tr.flagged[tr.n_flagged] = {(int)k, kind};
+    ++tr.n_flagged;
+  };
+  auto flipped = [&](int64_t k, uint32_t kind, bool decision) {
+    return (k == flip.k && kind == flip.kind) ? !decision : decision;
+  };
   // Relative uncertainty of an FP32 evaluation of T so far (for the flags).
   double t_rel = 0.0;
   const double u = std::ldexp(1.0, -24);  // FP32 unit roundoff
@@ -377,25 +410,29 @@ void trace_pixel(double px, double py, const uint32_t* list, int64_t len, const 
     const double* g = (list[k] == ov_id) ? ov_row : rec + (size_t)list[k] * R_STRIDE;
     const double dx = px - g[R_MX], dy = py - g[R_MY];
     const double power = -0.5 * (g[R_CA] * dx * dx + g[R_CC] * dy * dy) - g[R_CB] * dx * dy;
-    if (power > 0) continue;
-    const double G = std::exp(power);
-    const double oG = g[R_OP] * G;
     // A decision counts as "near" its threshold when it lies within the
     // rounding error an FP32 evaluation of the same expression can make:
     // the quadratic form loses accuracy to cancellation in proportion to the
     // magnitude of its terms (elongated splats), plus exp and the products.
     const double terms = std::fabs(g[R_CA] * dx * dx) + std::fabs(g[R_CC] * dy * dy) + 2 * std::fabs(g[R_CB] * dx * dy);
+    // the sign of the exponent: its absolute FP32 error is that of the quadratic form
+    if (std::fabs(power) < 8 * u * terms) flag(k, P_NEAR_POWER0);
+    if (flipped(k, P_NEAR_POWER0, power > 0)) continue;
+    const double G = std::exp(power);
+    const double oG = g[R_OP] * G;
     const double a_rel = 1e-5 + 8 * u * terms + 2 * u * std::fabs(power);
-    if (std::fabs(oG - o.alpha_max) <= a_rel * o.alpha_max) tr.flags |= P_NEAR_ALPHA_MAX;
-    const bool clamped = oG > o.alpha_max;
+    if (std::fabs(oG - o.alpha_max) <= a_rel * o.alpha_max) flag(k, P_NEAR_ALPHA_MAX);
+    const bool clamped = flipped(k, P_NEAR_ALPHA_MAX, oG > o.alpha_max);
     const double alpha = clamped ? o.alpha_max : oG;
-    if (std::fabs(alpha - o.alpha_min) <= a_rel * o.alpha_min) tr.flags |= P_NEAR_ALPHA_MIN;
-    if (alpha < o.alpha_min) continue;
+    if (std::fabs(alpha - o.alpha_min) <= a_rel * o.alpha_min) flag(k, P_NEAR_ALPHA_MIN);
+    tr.margin_alpha = std::min(tr.margin_alpha, std::fabs(alpha - o.alpha_min) / o.alpha_min);
+    if (flipped(k, P_NEAR_ALPHA_MIN, alpha < o.alpha_min)) continue;
     const double nextT = tr.T * (1.0 - alpha);
+    tr.margin_t = std::min(tr.margin_t, std::fabs(nextT - o.t_min) / o.t_min);
     const double step_rel = (clamped ? 0.0 : a_rel * alpha / (1.0 - alpha)) + 2 * u;
-    if (std::fabs(nextT - o.t_min) <= (1e-4 + t_rel + step_rel) * o.t_min) tr.flags |= P_NEAR_T_MIN;
+    if (std::fabs(nextT - o.t_min) <= (1e-4 + t_rel + step_rel) * o.t_min) flag(k, P_NEAR_T_MIN);
     t_rel += step_rel;
-    if (nextT < o.t_min) { tr.stop_k = (int)k; break; }
+    if (flipped(k, P_NEAR_T_MIN, nextT < o.t_min)) { tr.stop_k = (int)k; break; }
     for (int ch = 0; ch < 3; ++ch) tr.C[ch] += g[R_R + ch] * alpha * tr.T;
     if (keep) tr.acc.push_back({list[k], (int)k, alpha, G, tr.T, dx, dy, clamped});
     tr.T = nextT;
@@ -1012,6 +1049,150 @@ int or_pixel_counts(int32_t n_views, int64_t n, const OrCamera* cams, const OrOp
         const int64_t p = vw.pix_off + (int64_t)j * W + i;
         evaluated[p] = tr.stop_k >= 0 ? tr.stop_k + 1 : (int64_t)e - s;
         blended[p] = (int64_t)tr.acc.size();
+      }
+  }
+  return 0;
+}
+
+
+// Tile binning of a sample of tiles, by the same brute force as or_bin: every
+// pair with rx > 0 is tested against the tiles of its rect, in (view,
+// Gaussian) order.  tile_count [T_tot] receives the number of incidences of
+// every tile; for the listed tiles (ascending, distinct) the ids covering
+// each, stably sorted by the FP32 bits of their depth (so ties stay in id
+// order), are concatenated in list order into out_ids (capacity out_cap) and
+// out_len [n_tiles] receives each list's length.  Returns 2 when out_cap is
+// too small.  For workloads whose full binning does not fit in memory.
+int or_bin_sampled(int32_t n_views, int64_t n, const float* mean2d, const int32_t* ext, const float* depth,
+                   const int32_t* wh, int32_t tile, const int64_t* tiles, int64_t n_tiles, int64_t* tile_count,
+                   uint32_t* out_ids, int64_t out_cap, int64_t* out_len) {
+  int64_t T_tot = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const TileGrid g = grid_of(wh[2 * v], wh[2 * v + 1], tile);
+    T_tot += (int64_t)g.tx * g.ty;
+  }
+  std::vector<int64_t> slot(T_tot, -1);  // sample index of a global tile
+  for (int64_t k = 0; k < n_tiles; ++k) slot[tiles[k]] = k;
+  std::vector<std::vector<std::pair<uint32_t, uint32_t>>> lists(n_tiles);  // (depth bits, id)
+  std::memset(tile_count, 0, sizeof(int64_t) * (size_t)T_tot);
+  int64_t toff = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const TileGrid g = grid_of(wh[2 * v], wh[2 * v + 1], tile);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t id = (int64_t)v * n + i;
+      if (ext[2 * id] <= 0) continue;
+      int r[4];
+      tile_rect(mean2d[2 * id], mean2d[2 * id + 1], ext[2 * id], ext[2 * id + 1], tile, g, r);
+      for (int ty = r[1]; ty < r[3]; ++ty)
+        for (int tx = r[0]; tx < r[2]; ++tx) {
+          const int64_t gt = toff + (int64_t)ty * g.tx + tx;
+          ++tile_count[gt];
+          if (slot[gt] >= 0) lists[slot[gt]].push_back({f32_bits(depth[id]), (uint32_t)id});
+        }
+    }
+    toff += (int64_t)g.tx * g.ty;
+  }
+  int64_t o = 0;
+  for (int64_t k = 0; k < n_tiles; ++k) {
+    auto& l = lists[k];
+    std::stable_sort(l.begin(), l.end(), [](const std::pair<uint32_t, uint32_t>& a,
+                                            const std::pair<uint32_t, uint32_t>& b) { return a.first < b.first; });
+    out_len[k] = (int64_t)l.size();
+    if (o + (int64_t)l.size() > out_cap) return 2;
+    for (const auto& e : l) out_ids[o++] = e.second;
+  }
+  return 0;
+}
+
+// Locate pixel p (global index over the packed views) in the views.
+static void locate_pixel(const std::vector<ViewInfo>& views, int B, int64_t p, int* v_out, int* i_out, int* j_out,
+                         int64_t* gt_out) {
+  int v = 0;
+  while (v + 1 < (int)views.size() && views[v + 1].pix_off <= p) ++v;
+  const ViewInfo& vw = views[v];
+  const int64_t lp = p - vw.pix_off;
+  const int W = vw.cam.width;
+  const int i = (int)(lp % W), j = (int)(lp / W);
+  *v_out = v;
+  *i_out = i;
+  *j_out = j;
+  *gt_out = vw.tile_off + (int64_t)(j / B) * vw.grid.tx + i / B;
+}
+
+// One-flip alternatives of listed pixels: for pixel pixels[q] (global index),
+// n_alt[q] receives the number of its near-threshold decisions (or -1 when
+// there are more than max_alt, or more than the trace keeps), and alt
+// [n_pix][max_alt][3] the colour (background included) the pixel takes when
+// exactly the a-th of them goes the other way, every other decision as
+// defined; kinds [n_pix][max_alt] the P_NEAR_* bit of each.  A value computed
+// with FP32 arithmetic near such a threshold may take either side of it.
+int or_render_flips(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
+                    const uint32_t* ids, const uint32_t* ranges, const int64_t* pixels, int64_t n_pix, int32_t max_alt,
+                    int32_t* n_alt, double* alt, uint32_t* kinds) {
+  (void)n;
+  const std::vector<ViewInfo> views = make_views(cams, n_views, opt->tile);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < n_pix; ++q) {
+    int v, i, j;
+    int64_t gt;
+    locate_pixel(views, opt->tile, pixels[q], &v, &i, &j, &gt);
+    const uint32_t s = ranges[2 * gt], e = ranges[2 * gt + 1];
+    PixelTrace tr, tf;
+    trace_pixel(i, j, ids + s, (int64_t)e - s, rec, *opt, false, tr);
+    const int nf = tr.n_flagged;
+    n_alt[q] = (nf > max_alt || nf > kMaxFlagged) ? -1 : nf;
+    for (int a = 0; a < std::min(nf, std::min<int>(max_alt, kMaxFlagged)); ++a) {
+      Flip f;
+      f.k = tr.flagged[a].k;
+      f.kind = tr.flagged[a].kind;
+      trace_pixel(i, j, ids + s, (int64_t)e - s, rec, *opt, false, tf, 0xffffffffu, nullptr, f);
+      for (int ch = 0; ch < 3; ++ch) alt[(q * max_alt + a) * 3 + ch] = tf.C[ch] + tf.T * opt->bg[ch];
+      kinds[q * max_alt + a] = f.kind;
+    }
+  }
+  return 0;
+}
+
+// Discrete decisions of every pixel, for comparing two renders of the same
+// scene whose records or lists come from different projections: per pixel
+// the number of blended entries, an order-independent hash of their ids
+// (sum of a 64-bit mix of each id), the id that ended the pixel (0xffffffff
+// when none), and the smallest relative distance of any evaluated entry's
+// alpha from alpha_min and of any blended or stopping entry's transmittance
+// from t_min (how far the closest threshold decision was).
+int or_pixel_decisions(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
+                       const uint32_t* ids, const uint32_t* ranges, int32_t* n_blended, uint64_t* blend_hash,
+                       uint32_t* stop_id, double* margin_alpha, double* margin_t) {
+  (void)n;
+  const std::vector<ViewInfo> views = make_views(cams, n_views, opt->tile);
+  const int64_t T_tot = views.back().tile_off + (int64_t)views.back().grid.tx * views.back().grid.ty;
+  const int B = opt->tile;
+  auto mix = [](uint64_t x) {  // splitmix64 finaliser
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+  };
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t gt = 0; gt < T_tot; ++gt) {
+    const int v = view_of_tile(views, gt);
+    const ViewInfo& vw = views[v];
+    const int64_t lt = gt - vw.tile_off;
+    const int tx = (int)(lt % vw.grid.tx), ty = (int)(lt / vw.grid.tx);
+    const uint32_t s = ranges[2 * gt], e = ranges[2 * gt + 1];
+    const int W = vw.cam.width, H = vw.cam.height;
+    PixelTrace tr;
+    for (int j = ty * B; j < std::min(H, (ty + 1) * B); ++j)
+      for (int i = tx * B; i < std::min(W, (tx + 1) * B); ++i) {
+        trace_pixel(i, j, ids + s, (int64_t)e - s, rec, *opt, true, tr);
+        const int64_t p = vw.pix_off + (int64_t)j * W + i;
+        uint64_t h = 0;
+        for (const Accepted& a : tr.acc) h += mix(a.id);
+        n_blended[p] = (int32_t)tr.acc.size();
+        blend_hash[p] = h;
+        stop_id[p] = tr.stop_k >= 0 ? ids[s + tr.stop_k] : 0xffffffffu;
+        margin_alpha[p] = tr.margin_alpha;
+        margin_t[p] = tr.margin_t;
       }
   }
   return 0;

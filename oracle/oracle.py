@@ -41,7 +41,7 @@ F_GUARD_X, F_GUARD_Y = 1 << 3, 1 << 4
 F_CULL_NEAR, F_CULL_DET, F_CULL_RECT, F_CULL_QUAT, F_CULL_OPACITY = 1 << 8, 1 << 9, 1 << 10, 1 << 11, 1 << 12
 F_NEAR_RADIUS, F_NEAR_RECT, F_NEAR_PLANE = 1 << 16, 1 << 17, 1 << 18
 # Per-pixel flag bits.
-P_NEAR_ALPHA_MIN, P_NEAR_T_MIN, P_NEAR_ALPHA_MAX = 1, 2, 4
+P_NEAR_ALPHA_MIN, P_NEAR_T_MIN, P_NEAR_ALPHA_MAX, P_NEAR_POWER0 = 1, 2, 4, 8
 
 
 class OrCamera(C.Structure):
@@ -104,10 +104,16 @@ def lib():
         _lib.or_fd_local.argtypes = [i64, i32, P, P, P, P, P, C.POINTER(OrCamera), i32, C.POINTER(OrOptions), P, i64,
                                      P, P, C.c_double, P, P]
         _lib.or_pixel_counts.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P]
+        _lib.or_bin_sampled.argtypes = [i32, i64, P, P, P, P, i32, P, i64, P, P, i64, P]
+        _lib.or_render_flips.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, i64, i32,
+                                         P, P, P]
+        _lib.or_pixel_decisions.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P, P,
+                                            P, P]
         _lib.or_sh_basis.argtypes = [i32, i64, P, P, P]
         _lib.or_quat_to_rot.argtypes = [P, P]
         for f in ("or_project", "or_bin", "or_render", "or_render_backward", "or_project_backward", "or_fd_local",
-                  "or_render_tiles", "or_render_backward_tiles", "or_render_backward_abs"):
+                  "or_render_tiles", "or_render_backward_tiles", "or_render_backward_abs", "or_bin_sampled",
+                  "or_render_flips", "or_pixel_decisions"):
             getattr(_lib, f).restype = C.c_int
     return _lib
 
@@ -217,6 +223,84 @@ def bin_sort(mean2d_f32, ext, depth_f32, cams, tile, with_keys=True):
                       _p(keys) if with_keys else None, _p(ids), _p(ranges), C.byref(npairs))
     assert rc == 0
     return keys[:M], ids[:M], ranges.reshape(T, 2)
+
+
+def bin_sampled(mean2d_f32, ext, depth_f32, cams, tile, tiles):
+    """Brute-force binning of a sample of tiles (see or_bin_sampled): returns the incidence count
+    of every tile [T] and, per listed tile (ascending global ids), its ids in the stable
+    (depth bits, id) order."""
+    n_views = len(cams)
+    ext = np.ascontiguousarray(ext, np.int32).reshape(-1, 2)
+    vn = ext.shape[0]
+    n = vn // n_views
+    mean2d = np.ascontiguousarray(mean2d_f32, np.float32).reshape(vn, 2)
+    depth = np.ascontiguousarray(depth_f32, np.float32).reshape(vn)
+    wh = np.array([[c.width, c.height] for c in cams], np.int32)
+    T = int(total_tiles(cams, tile))
+    tiles = np.ascontiguousarray(tiles, np.int64)
+    assert np.all(np.diff(tiles) > 0) and tiles[0] >= 0 and tiles[-1] < T
+    counts = np.zeros(T, np.int64)
+    lens = np.zeros(tiles.shape[0], np.int64)
+    cap = 1 << 20
+    while True:
+        out = np.zeros(cap, np.uint32)
+        rc = lib().or_bin_sampled(n_views, n, _p(mean2d), _p(ext), _p(depth), _p(wh), tile, _p(tiles),
+                                  tiles.shape[0], _p(counts), _p(out), cap, _p(lens))
+        if rc == 0:
+            break
+        assert rc == 2
+        cap *= 4
+    offs = np.concatenate([[0], np.cumsum(lens)])
+    return counts, [out[offs[k]:offs[k + 1]] for k in range(tiles.shape[0])]
+
+
+def ranges_from_counts(counts):
+    """Tile ranges [first, last + 1) of tiles laid out in order with these incidence counts, (0, 0)
+    for an empty tile (the layout of the sorted incidence array)."""
+    counts = np.asarray(counts, np.int64)
+    start = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    r = np.stack([start, start + counts], axis=1)
+    r[counts == 0] = 0
+    return r
+
+
+def render_flips(cams, opts: Options, rec, ids, ranges, pixels, max_alt=8):
+    """One-flip alternatives of the listed pixels (see or_render_flips): n_alt [P] (-1: too many
+    near-threshold decisions), alt [P, max_alt, 3] colours, kinds [P, max_alt] P_NEAR_* bits."""
+    n_views = len(cams)
+    rec = _d(rec)
+    n = rec.shape[0] // n_views
+    px = np.ascontiguousarray(pixels, np.int64)
+    n_alt = np.zeros(px.shape[0], np.int32)
+    alt = np.full((px.shape[0], max_alt, 3), np.nan)
+    kinds = np.zeros((px.shape[0], max_alt), np.uint32)
+    oc = opts.as_c()
+    rc = lib().or_render_flips(n_views, n, cameras_c(cams), C.byref(oc), _p(rec),
+                               _p(np.ascontiguousarray(ids, np.uint32)), _p(np.ascontiguousarray(ranges, np.uint32)),
+                               _p(px), px.shape[0], max_alt, _p(n_alt), _p(alt), _p(kinds))
+    assert rc == 0
+    return n_alt, alt, kinds
+
+
+def pixel_decisions(cams, opts: Options, rec, ids, ranges):
+    """Per pixel: blended count, order-independent hash of the blended ids, the id that ended the
+    pixel (0xffffffff: none), and the smallest relative distances of an alpha from alpha_min and of
+    a transmittance from t_min (see or_pixel_decisions)."""
+    n_views = len(cams)
+    rec = _d(rec)
+    n = rec.shape[0] // n_views
+    P = sum(c.width * c.height for c in cams)
+    nb = np.zeros(P, np.int32)
+    h = np.zeros(P, np.uint64)
+    stop = np.zeros(P, np.uint32)
+    ma = np.zeros(P)
+    mt = np.zeros(P)
+    oc = opts.as_c()
+    rc = lib().or_pixel_decisions(n_views, n, cameras_c(cams), C.byref(oc), _p(rec),
+                                  _p(np.ascontiguousarray(ids, np.uint32)),
+                                  _p(np.ascontiguousarray(ranges, np.uint32)), _p(nb), _p(h), _p(stop), _p(ma), _p(mt))
+    assert rc == 0
+    return dict(n_blended=nb, blend_hash=h, stop_id=stop, margin_alpha=ma, margin_t=mt)
 
 
 def render(cams, opts: Options, rec, ids, ranges):

@@ -267,6 +267,14 @@ def test_binning_matches_brute_force(oracle_lib, B):
             assert np.all((keys[s:e] >> np.uint64(32)) == t)
             assert np.array_equal(keys[s:e] & np.uint64(0xffffffff), depth[ids[s:e]].view(np.uint32).astype(np.uint64))
     assert sum(len(l) for l in ref) == ids.shape[0]
+    # the sampled binning (for workloads too large to bin whole): counts of every tile and the
+    # lists of a sample of tiles, against the same brute force
+    sample = np.sort(rng.choice(len(ref), max(1, len(ref) // 3), replace=False))
+    counts, lists = O.bin_sampled(mean2d, ext, depth, cams, B, sample)
+    assert counts.tolist() == [len(l) for l in ref]
+    np.testing.assert_array_equal(O.ranges_from_counts(counts), ranges)
+    for t, lst in zip(sample, lists):
+        assert lst.tolist() == ref[t]
 
 
 def test_rect_covers_where_alpha_can_reach_threshold(oracle_lib):
@@ -394,6 +402,174 @@ def test_blending_invariants(oracle_lib):
     assert np.all(f0["t_final"] == 1.0) and np.all(f0["n_contrib"] == 0)
     for ch in range(3):
         assert np.all(f0["image"].reshape(3, -1)[ch] == f32(bg[ch]))
+
+
+def _flat_record(op, rgb, depth, mean=(3.5, 3.5), conic=(0.0, 0.0, 0.0)):
+    """Pinned-lists record (mx, my, depth, conic a, b, c, opacity, r, g, b).  A zero conic gives
+    power = 0 at every pixel, so alpha = min(0.99, opacity) exactly."""
+    return [mean[0], mean[1], depth, conic[0], conic[1], conic[2], op, rgb[0], rgb[1], rgb[2]]
+
+
+def _one_tile(O, recs):
+    """An 8x8 view with one tile whose list is the records in the given order."""
+    cam = S.pinhole(8, 8, 10.0)
+    rec = np.array(recs, np.float64)
+    ids = np.arange(rec.shape[0], dtype=np.uint32)
+    ranges = np.array([[0, rec.shape[0]]], np.uint32)
+    return [cam], O.Options(tile=8), rec, ids, ranges
+
+
+@pytest.mark.parametrize("k_skip,k_after", [(0, 0), (5, 0), (7, 3)])
+def test_contributor_count_is_list_position(oracle_lib, k_skip, k_after):
+    """n_contrib is one plus the list position of the last blended entry, skipped entries included:
+    one blending Gaussian behind k_skip transparent ones (opacity below alpha_min) gives k_skip + 1,
+    whatever follows it.  Counting blended entries instead would give 1.  The work counts: every
+    list entry is evaluated (the pixel never stops), one is blended."""
+    O = oracle_lib
+    skip = [_flat_record(0.002, (1.0, 1.0, 1.0), 1.0 + 0.1 * i) for i in range(k_skip)]
+    after = [_flat_record(0.003, (1.0, 1.0, 1.0), 5.0 + 0.1 * i) for i in range(k_after)]
+    blend = _flat_record(0.5, (0.2, 0.4, 0.8), 3.0)
+    cams, opts, rec, ids, ranges = _one_tile(O, skip + [blend] + after)
+    r = O.render(cams, opts, rec, ids, ranges)
+    assert np.all(r["n_contrib"] == k_skip + 1)
+    np.testing.assert_array_equal(r["t_final"], 0.5)
+    img = r["image"].reshape(3, -1)
+    for ch, c in enumerate((0.2, 0.4, 0.8)):
+        np.testing.assert_array_equal(img[ch], c * 0.5)
+    ev, bl = O.pixel_counts(cams, opts, rec, ids, ranges)
+    assert np.all(ev == k_skip + 1 + k_after) and np.all(bl == 1)
+
+
+@pytest.mark.parametrize("k_skip", [0, 4])
+def test_opaque_walls_stop_at_the_known_entry(oracle_lib, k_skip):
+    """Walls of alpha 0.95 behind k_skip transparent entries: T goes 1, 0.05, 2.5e-3, 1.25e-4, and
+    the fourth wall would take it to 6.25e-6 < t_min, so it ends the pixel unblended.  Closed forms:
+    n_contrib = k_skip + 3, T_final = 0.05^3, C = c (1 - 0.05^3); the work counts evaluate up to and
+    including the fourth wall (k_skip + 4 entries) and blend 3, however long the list goes on."""
+    O = oracle_lib
+    skip = [_flat_record(0.001, (1.0, 1.0, 1.0), 0.5 + 0.1 * i) for i in range(k_skip)]
+    walls = [_flat_record(0.95, (0.3, 0.6, 0.9), 2.0 + i) for i in range(6)]
+    cams, opts, rec, ids, ranges = _one_tile(O, skip + walls)
+    r = O.render(cams, opts, rec, ids, ranges)
+    assert np.all(r["n_contrib"] == k_skip + 3)
+    np.testing.assert_allclose(r["t_final"], 0.05 ** 3, rtol=1e-13)
+    img = r["image"].reshape(3, -1)
+    for ch, c in enumerate((0.3, 0.6, 0.9)):
+        np.testing.assert_allclose(img[ch], c * (1 - 0.05 ** 3), rtol=1e-13)
+    ev, bl = O.pixel_counts(cams, opts, rec, ids, ranges)
+    assert np.all(ev == k_skip + 4) and np.all(bl == 3)
+
+
+def test_pixel_counts_of_a_partial_splat(oracle_lib):
+    """A small Gaussian over part of the tile in front of one wall of alpha 0.5: where it blends
+    (alpha >= 1/255 by the closed form of the exponent) two entries are blended, elsewhere one;
+    every pixel evaluates both entries and n_contrib is 2 everywhere (the wall is second)."""
+    O = oracle_lib
+    a, b, c = 1.1, 0.35, 0.7
+    small = _flat_record(0.8, (1.0, 0.0, 0.0), 1.0, mean=(2.2, 4.7), conic=(a, b, c))
+    wall = _flat_record(0.5, (0.0, 1.0, 0.0), 2.0)
+    cams, opts, rec, ids, ranges = _one_tile(O, [small, wall])
+    ev, bl = O.pixel_counts(cams, opts, rec, ids, ranges)
+    ys, xs = np.mgrid[0:8, 0:8].astype(np.float64)
+    dx, dy = xs - 2.2, ys - 4.7
+    alpha = np.minimum(0.99, 0.8 * np.exp(-0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy))
+    hit = (alpha >= f32(1 / 255)).reshape(-1)
+    assert 0 < hit.sum() < 64
+    np.testing.assert_array_equal(bl, np.where(hit, 2, 1))
+    assert np.all(ev == 2)
+    r = O.render(cams, opts, rec, ids, ranges)
+    assert np.all(r["n_contrib"] == 2)
+
+
+def test_one_flip_alternatives_of_near_threshold_decisions(oracle_lib):
+    """A decision within the FP32 rounding bound of its threshold is flagged, and its one-flip
+    alternative is the pixel with that decision taken the other way, in closed form:
+    - alpha 1e-7 relatively above alpha_min (zero conic, so alpha = opacity exactly): blended by
+      definition, C = c1 a1 + c2 a2 (1 - a1); the alternative skips it, C = c2 a2;
+    - walls of alpha 0.99 then one taking T to 1e-4 (1 + 1e-9): blended by definition; the
+      alternative stops there;
+    - a needle whose exponent at a pixel is a tiny residue of cancelling terms: flagged for its
+      sign, and the alternative is the other side of the sign test.
+    Unflagged pixels have no alternative."""
+    O = oracle_lib
+    amin = float(np.float32(1 / 255))
+    c1, c2 = (0.9, 0.2, 0.1), (0.1, 0.5, 0.7)
+    a1 = amin * (1 + 1e-7)
+    cams, opts, rec, ids, ranges = _one_tile(O, [_flat_record(a1, c1, 1.0), _flat_record(0.3, c2, 2.0)])
+    r = O.render(cams, opts, rec, ids, ranges)
+    assert np.all(r["pix_flags"] == O.P_NEAR_ALPHA_MIN)
+    img = r["image"].reshape(3, -1)
+    for ch in range(3):
+        np.testing.assert_allclose(img[ch], c1[ch] * a1 + c2[ch] * 0.3 * (1 - a1), rtol=1e-14)
+    n_alt, alt, kinds = O.render_flips(cams, opts, rec, ids, ranges, np.arange(64))
+    assert np.all(n_alt == 1) and np.all(kinds[:, 0] == O.P_NEAR_ALPHA_MIN)
+    for ch in range(3):
+        np.testing.assert_allclose(alt[:, 0, ch], c2[ch] * 0.3, rtol=1e-14)
+    # transmittance: 1e-3 after three walls of alpha 0.9; the fourth entry's alpha (about 0.9, below
+    # alpha_max) takes it to t_min (1 + 1e-9), so it is blended by definition, and the fifth (alpha 0.5)
+    # stops the pixel
+    tmin = float(np.float32(1e-4))
+    T3 = 1.0 * (1 - 0.9) * (1 - 0.9) * (1 - 0.9)
+    a4 = 1 - tmin * (1 + 1e-9) / T3
+    walls = [_flat_record(0.9, c1, 1.0 + i) for i in range(3)]
+    cams, opts, rec, ids, ranges = _one_tile(O, walls + [_flat_record(a4, c2, 4.0), _flat_record(0.5, c1, 5.0)])
+    r = O.render(cams, opts, rec, ids, ranges)
+    assert np.all(r["pix_flags"] == O.P_NEAR_T_MIN) and np.all(r["n_contrib"] == 4)
+    n_alt, alt, kinds = O.render_flips(cams, opts, rec, ids, ranges, np.arange(64))
+    assert np.all(n_alt == 1) and np.all(kinds[:, 0] == O.P_NEAR_T_MIN)
+    for ch in range(3):
+        walls_c = c1[ch] * (1 - T3)
+        np.testing.assert_allclose(r["image"].reshape(3, -1)[ch], walls_c + c2[ch] * a4 * T3, rtol=1e-13)
+        np.testing.assert_allclose(alt[:, 0, ch], walls_c, rtol=1e-13)
+    # the sign of the exponent: a needle conic (a c - b^2 tiny against a c) whose quadratic form at a
+    # pixel on its long axis is the difference of two large terms
+    a, c = 4e4, 1e-2
+    b = -math.sqrt(a * c) * (1 - 1e-12)
+    mean = (3.0 - 2.5e-4, 3.5)  # pixel (3, 4): dy = 0.5 and dx = dy sqrt(c / a), on the long axis
+    cams, opts, rec, ids, ranges = _one_tile(O, [_flat_record(0.6, c1, 1.0, mean=mean, conic=(a, b, c))])
+    r = O.render(cams, opts, rec, ids, ranges)
+    flagged = np.nonzero(r["pix_flags"] & O.P_NEAR_POWER0)[0]
+    assert flagged.shape[0] > 0
+    n_alt, alt, kinds = O.render_flips(cams, opts, rec, ids, ranges, flagged)
+    assert np.all(n_alt >= 1)
+    img = r["image"].reshape(3, -1)
+    for q, p in enumerate(flagged):
+        a0 = np.nonzero(kinds[q, :n_alt[q]] == O.P_NEAR_POWER0)[0][0]
+        # one side blends alpha ~ opacity (exponent ~ 0), the other skips the entry
+        pair = sorted([img[0, p], alt[q, a0, 0]])
+        assert pair[0] == 0.0 and abs(pair[1] - 0.9 * 0.6) < 1e-6
+    # a pixel with no near-threshold decision has no alternative
+    cams, opts, rec, ids, ranges = _one_tile(O, [_flat_record(0.5, c1, 1.0)])
+    n_alt, _, _ = O.render_flips(cams, opts, rec, ids, ranges, np.arange(64))
+    assert np.all(n_alt == 0)
+
+
+def test_pixel_decisions_summarise_the_trace(oracle_lib):
+    """Decision summaries on the walls scene (closed form: 3 blended, the fourth wall stops the pixel,
+    alpha margins |0.95 - 1/255| / (1/255) and the smallest transmittance margin at the stopping wall),
+    the hash equal to the mix of the blended ids, and a renumbering of the entries changing it."""
+    O = oracle_lib
+    walls = [_flat_record(0.95, (0.3, 0.6, 0.9), 2.0 + i) for i in range(6)]
+    cams, opts, rec, ids, ranges = _one_tile(O, walls)
+    d = O.pixel_decisions(cams, opts, rec, ids, ranges)
+    assert np.all(d["n_blended"] == 3) and np.all(d["stop_id"] == 3)
+    amin = float(np.float32(1 / 255))
+    np.testing.assert_allclose(d["margin_alpha"], (0.95 - amin) / amin, rtol=1e-12)
+    tmin = float(np.float32(1e-4))
+    T = [1.0, 0.05, 0.05 ** 2, 0.05 ** 3, 0.05 ** 4]
+    np.testing.assert_allclose(d["margin_t"], min(abs(t - tmin) / tmin for t in T[1:]), rtol=1e-12)
+
+    def mix(x):
+        m = (1 << 64) - 1
+        x = (x + 0x9e3779b97f4a7c15) & m
+        x = ((x ^ (x >> 30)) * 0xbf58476d1ce4e5b9) & m
+        x = ((x ^ (x >> 27)) * 0x94d049bb133111eb) & m
+        return x ^ (x >> 31)
+    assert np.all(d["blend_hash"] == np.uint64((mix(0) + mix(1) + mix(2)) % (1 << 64)))
+    d2 = O.pixel_decisions(cams, opts, rec[[1, 0, 2, 3, 4, 5]], np.array([1, 0, 2, 3, 4, 5], np.uint32), ranges)
+    assert np.all(d2["blend_hash"] == d["blend_hash"])  # same blended set in another order
+    d3 = O.pixel_decisions(cams, opts, rec, np.arange(1, 7, dtype=np.uint32) % 6, ranges)
+    assert np.all(d3["blend_hash"] != d["blend_hash"]) and np.all(d3["stop_id"] == 4)
 
 
 def test_back_to_front_over_recurrence(oracle_lib):
