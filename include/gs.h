@@ -15,7 +15,8 @@
  * Conventions shared by every call
  *  - Every pointer inside the structs below is a DEVICE pointer unless
  *    stated otherwise.  The caller allocates and owns all device memory,
- *    workspaces included; the library never allocates, frees or retains it.
+ *    workspaces included; the library never allocates, frees or retains it
+ *    (gs_render_fwd_noalloc's static per-GPU scratch aside).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Hot-path calls
  *    only enqueue kernels on it and return; none synchronises, so they may be
  *    captured into a HIP graph.  No call issues hipMemset: buffers that must
@@ -265,6 +266,22 @@ gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_camera* cams
 gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
                         int32_t n_views, const gs_options* opts, const gs_loss* loss, const gs_image* out,
                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* gs_render_fwd without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as gs_render_fwd;
+ * the per-tile L1 partial sums live in a static array of the library, one per
+ * GPU, held until the process ends (GS_NOALLOC_MAX_TILES floats, 4 MiB).  A
+ * call that requests the loss value with more than GS_NOALLOC_MAX_TILES tiles
+ * returns GS_ERR_CAPACITY and enqueues nothing.  No call allocates or frees
+ * memory; its first call on a device looks up that device's array.  Calls
+ * that overlap on one GPU (other streams, other threads) share the array and
+ * race: serialise them.  Every tile's partial sum is written before it is
+ * read, so nothing needs clearing between calls. */
+#define GS_NOALLOC_MAX_TILES (1 << 20)
+gs_status gs_render_fwd_noalloc(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
+                                int32_t n_views, const gs_options* opts, const gs_loss* loss, const gs_image* out,
+                                void* stream);
 
 /* Backward of the rasteriser and the projection (the differentiable part of
  * Sec. III-B): dL/dimage from `loss` (L1 of eq. (2), or external), then for

@@ -17,6 +17,7 @@ GS_OK, GS_ERR_INVALID_VALUE, GS_ERR_UNSUPPORTED, GS_ERR_CAPACITY, GS_ERR_HIP = r
 GS_LOSS_NONE, GS_LOSS_L1, GS_LOSS_EXTERNAL = 0, 1, 2
 GS_MAX_VIEWS = 32
 GS_REC_FLOATS = 12
+GS_NOALLOC_MAX_TILES = 1 << 20  # tiles of gs_render_fwd_noalloc's static per-tile loss scratch
 GS_GRAD2D_FLOATS = 9
 GS_MAX_ADAM_GROUPS = 8
 
@@ -89,7 +90,8 @@ EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_op
            "gs_photometric_loss_workspace_size", "gs_photometric_loss", "gs_pyramid_camera", "gs_pyramid_reduce",
            "gs_raster_bwd_abs", "gs_project_bwd_adam_stats", "gs_default_density_config", "gs_scene_extent", "gs_density_accumulate",
            "gs_density_workspace_size", "gs_density_plan", "gs_density_apply", "gs_delaunay", "gs_densify_depth",
-           "gs_init_gaussians_workspace_size", "gs_init_gaussians_count", "gs_init_gaussians")
+           "gs_init_gaussians_workspace_size", "gs_init_gaussians_count", "gs_init_gaussians",
+           "gs_render_fwd_noalloc")
 
 _lib = None
 
@@ -119,6 +121,8 @@ def load(path: str = LIB_PATH):
         "gs_bin_sort": (C.c_int, [C.POINTER(gs_projected), i64, pc, i32, po, C.POINTER(gs_bins), P, sz, P]),
         "gs_render_fwd": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), pc, i32, po,
                                     C.POINTER(gs_loss), C.POINTER(gs_image), P, sz, P]),
+        "gs_render_fwd_noalloc": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), pc, i32, po,
+                                            C.POINTER(gs_loss), C.POINTER(gs_image), P]),
         "gs_render_bwd": (C.c_int, [pp, C.POINTER(gs_projected), C.POINTER(gs_bins), C.POINTER(gs_image), pc, i32,
                                     po, C.POINTER(gs_loss), C.POINTER(gs_grads), P, sz, P]),
         "gs_raster_bwd": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), C.POINTER(gs_image), pc, i32,
@@ -238,6 +242,13 @@ def gs_render_fwd(proj, n, bins, cams, n_views, opts, loss, out, workspace, work
     _check("gs_render_fwd", load().gs_render_fwd(C.byref(proj), n, C.byref(bins), cams, n_views, C.byref(opts),
                                                  C.byref(loss) if loss is not None else None, C.byref(out),
                                                  workspace, workspace_bytes, stream))
+
+
+def gs_render_fwd_noalloc(proj, n, bins, cams, n_views, opts, loss, out, stream):
+    _check("gs_render_fwd_noalloc", load().gs_render_fwd_noalloc(C.byref(proj), n, C.byref(bins), cams, n_views,
+                                                                 C.byref(opts),
+                                                                 C.byref(loss) if loss is not None else None,
+                                                                 C.byref(out), stream))
 
 
 def gs_render_bwd(params, proj, bins, img, cams, n_views, opts, loss, grads, workspace, workspace_bytes, stream):

@@ -13,6 +13,7 @@
 // gfx950 permlane16/32 swaps, and 9 lanes issue one hardware FP32 atomic each,
 // so one atomic per term per wavefront per splat reaches L2.
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "gs_internal.h"
@@ -796,40 +797,29 @@ extern "C" gs_status gs_render_bwd_workspace_size(int64_t n, int32_t n_views, si
   return GS_OK;
 }
 
-extern "C" gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
-                                   int32_t n_views, const gs_options* opts, const gs_loss* loss, const gs_image* out,
-                                   void* workspace, size_t workspace_bytes, void* stream) {
-  using namespace gs;
-  gs_status s;
-  if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
-  if (n < 1) return fail(GS_ERR_INVALID_VALUE, "n must be >= 1");
-  if (!out || !out->rgb) return fail(GS_ERR_INVALID_VALUE, "out->rgb is NULL");
-  if (!opts->checkpoint && (!out->t_final || !out->n_contrib))
-    return fail(GS_ERR_INVALID_VALUE, "t_final/n_contrib are required unless checkpoint is set");
-  const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
-  const bool want_loss = loss && loss->kind == GS_LOSS_L1 && loss->loss_out;
-  if (loss && loss->kind != GS_LOSS_NONE && loss->kind != GS_LOSS_L1 && loss->kind != GS_LOSS_EXTERNAL)
-    return fail(GS_ERR_INVALID_VALUE, "unknown loss kind");
-  if (want_loss && !loss->target) return fail(GS_ERR_INVALID_VALUE, "L1 loss needs a target");
-  const size_t need = align256(sizeof(float) * (size_t)vt.total_tiles);
-  if (want_loss && (!workspace || workspace_bytes < need))
-    return fail(GS_ERR_CAPACITY, "workspace too small: need " + std::to_string(need) + " bytes");
-  hipStream_t st = as_stream(stream);
+namespace gs {
+
+// The forward behind gs_render_fwd and gs_render_fwd_noalloc: `tile_loss` (total_tiles floats, or
+// NULL when no loss value is requested) receives the per-tile L1 partial sums.
+static gs_status render_fwd_impl(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
+                                 int32_t n_views, const gs_options* opts, const gs_loss* loss, const gs_image* out,
+                                 const ViewTable& vt, float* tile_loss, hipStream_t st) {
+  const bool want_loss = tile_loss != nullptr;
   const RasterConsts rc = consts_of(opts);
-  float* tl = want_loss ? static_cast<float*>(workspace) : nullptr;
   const float* tgt = want_loss ? loss->target : nullptr;
   float* tf = opts->checkpoint ? nullptr : out->t_final;
   int32_t* nc = opts->checkpoint ? nullptr : out->n_contrib;
   const dim3 grid((unsigned)vt.total_tiles);
   const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
+  (void)n;
 #define GS_LAUNCH_FWD(TILE_, NT_)                                                                              \
   do {                                                                                                        \
     if (tf)                                                                                                   \
       hipLaunchKernelGGL((k_render_fwd<TILE_, true>), grid, dim3(NT_), 0, st, vt, proj->rec, bins->ids, rg, rc, \
-                         out->rgb, tf, nc, tgt, tl);                                                         \
+                         out->rgb, tf, nc, tgt, tile_loss);                                                  \
     else                                                                                                      \
       hipLaunchKernelGGL((k_render_fwd<TILE_, false>), grid, dim3(NT_), 0, st, vt, proj->rec, bins->ids, rg,   \
-                         rc, out->rgb, tf, nc, tgt, tl);                                                     \
+                         rc, out->rgb, tf, nc, tgt, tile_loss);                                              \
   } while (0)
   switch (opts->tile_size) {
     case 8: GS_LAUNCH_FWD(8, FwdShape<8>::THREADS); break;
@@ -837,9 +827,87 @@ extern "C" gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs
     default: GS_LAUNCH_FWD(32, FwdShape<32>::THREADS); break;
   }
 #undef GS_LAUNCH_FWD
-  if (want_loss) hipLaunchKernelGGL(k_loss_reduce, dim3(n_views), dim3(256), 0, st, vt, tl, loss->loss_out);
+  if (want_loss) hipLaunchKernelGGL(k_loss_reduce, dim3(n_views), dim3(256), 0, st, vt, tile_loss, loss->loss_out);
   return check_launch("render forward");
 }
+
+// Validation shared by both forward entry points; *want_loss tells whether a loss value is requested.
+static gs_status validate_render_fwd(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
+                                     int32_t n_views, const gs_options* opts, const gs_loss* loss,
+                                     const gs_image* out, bool* want_loss) {
+  gs_status s;
+  if ((s = validate_raster_common(proj, bins, cams, n_views, opts)) != GS_OK) return s;
+  if (n < 1) return fail(GS_ERR_INVALID_VALUE, "n must be >= 1");
+  if (!out || !out->rgb) return fail(GS_ERR_INVALID_VALUE, "out->rgb is NULL");
+  if (!opts->checkpoint && (!out->t_final || !out->n_contrib))
+    return fail(GS_ERR_INVALID_VALUE, "t_final/n_contrib are required unless checkpoint is set");
+  if (loss && loss->kind != GS_LOSS_NONE && loss->kind != GS_LOSS_L1 && loss->kind != GS_LOSS_EXTERNAL)
+    return fail(GS_ERR_INVALID_VALUE, "unknown loss kind");
+  *want_loss = loss && loss->kind == GS_LOSS_L1 && loss->loss_out;
+  if (*want_loss && !loss->target) return fail(GS_ERR_INVALID_VALUE, "L1 loss needs a target");
+  return GS_OK;
+}
+
+// Per-tile L1 partial sums of gs_render_fwd_noalloc: one array per GPU, held until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is not a device address): it
+// takes the address hipGetSymbolAddress gives for the current device, once per device.
+constexpr int64_t kNoAllocTiles = GS_NOALLOC_MAX_TILES;
+static __device__ __align__(256) float scratch[kNoAllocTiles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[kMaxDevices];
+
+static gs_status noalloc_scratch(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GS_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
+}
+
+}  // namespace gs
+
+extern "C" gs_status gs_render_fwd(const gs_projected* proj, int64_t n, const gs_bins* bins, const gs_camera* cams,
+                                   int32_t n_views, const gs_options* opts, const gs_loss* loss, const gs_image* out,
+                                   void* workspace, size_t workspace_bytes, void* stream) {
+  using namespace gs;
+  gs_status s;
+  bool want_loss = false;
+  if ((s = validate_render_fwd(proj, n, bins, cams, n_views, opts, loss, out, &want_loss)) != GS_OK) return s;
+  const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
+  const size_t need = align256(sizeof(float) * (size_t)vt.total_tiles);
+  if (want_loss && (!workspace || workspace_bytes < need))
+    return fail(GS_ERR_CAPACITY, "workspace too small: need " + std::to_string(need) + " bytes");
+  return render_fwd_impl(proj, n, bins, cams, n_views, opts, loss, out, vt,
+                         want_loss ? static_cast<float*>(workspace) : nullptr, as_stream(stream));
+}
+
+extern "C" gs_status gs_render_fwd_noalloc(const gs_projected* proj, int64_t n, const gs_bins* bins,
+                                           const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                                           const gs_loss* loss, const gs_image* out, void* stream) {
+  using namespace gs;
+  gs_status s;
+  bool want_loss = false;
+  if ((s = validate_render_fwd(proj, n, bins, cams, n_views, opts, loss, out, &want_loss)) != GS_OK) return s;
+  const ViewTable vt = make_view_table(cams, n_views, opts->tile_size);
+  if (want_loss && (int64_t)vt.total_tiles > kNoAllocTiles)
+    return fail(GS_ERR_CAPACITY, "gs_render_fwd_noalloc: " + std::to_string(vt.total_tiles) +
+                                     " tiles exceed the static scratch of " + std::to_string(kNoAllocTiles) +
+                                     " tiles (use gs_render_fwd with a workspace)");
+  float* tl = nullptr;
+  if (want_loss && (s = noalloc_scratch(&tl)) != GS_OK) return s;
+  return render_fwd_impl(proj, n, bins, cams, n_views, opts, loss, out, vt, tl, as_stream(stream));
+}
+
 
 namespace gs {
 

@@ -246,3 +246,14 @@ def _incircle_exact(a, b, c, d):
     m = [(x, y, x * x + y * y) for x, y in rows]
     return (m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0])
             + m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]))
+
+
+def test_noalloc_forward_validates_before_any_launch(L):
+    """gs_render_fwd_noalloc rejects bad arguments before touching the device, as gs_render_fwd does."""
+    from paper_2409_13055_amd import synthetic as S
+    o = L.default_options()
+    cc = L.make_cameras([S.pinhole(64, 48, 50.0)])
+    proj = L.gs_projected()
+    with pytest.raises(L.GsError, match="rec"):
+        L.gs_render_fwd_noalloc(proj, 10, L.gs_bins(), cc, 1, o, None, L.gs_image(), None)
+    assert L.GS_NOALLOC_MAX_TILES == 1 << 20
