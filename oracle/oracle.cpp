@@ -443,33 +443,49 @@ void trace_pixel(double px, double py, const uint32_t* list, int64_t len, const 
 // Backward of one pixel: adds d(loss)/d(record) of every blended Gaussian.
 // Row layout: (mx, my, ca, cb, cc, opacity, r, g, b), then the magnitudes of
 // this pixel's two mean components, |dL_pixel/dmx| and |dL_pixel/dmy|, whose
-// sums over pixels are the homodirectional (AbsGS) view-space gradient.
-constexpr int kRowW = 11;
+// sums over pixels are the homodirectional (AbsGS) view-space gradient, then
+// for each of the nine terms the magnitude of the parts it is formed from
+// (their sums over pixels scale the rounding error of any evaluation of the
+// gradient): dL/dalpha = sum_c dl_c (col_c T - S_c / (1 - alpha)) is taken
+// with |col_c| T + (|S_c| + C_c) / (1 - alpha), C the pixel's colour, because
+// an evaluation that recovers the colour behind an entry by subtracting the
+// colour in front of it from C carries an error relative to C, not to S.
+constexpr int kRowW = 20;
 void backward_pixel(const PixelTrace& tr, const double dl[3], const double* rec, const OrOptions& o,
                     double* rows /* [len][kRowW], indexed by list position */) {
   double S[3] = {tr.T * o.bg[0], tr.T * o.bg[1], tr.T * o.bg[2]};
+  const double Cpix[3] = {tr.C[0] + S[0], tr.C[1] + S[1], tr.C[2] + S[2]};
   for (size_t a = tr.acc.size(); a-- > 0;) {
     const Accepted& e = tr.acc[a];
     const double* g = rec + (size_t)e.id * R_STRIDE;
     double* row = rows + (size_t)e.k * kRowW;
-    double dl_dalpha = 0;
+    double t[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double dl_dalpha = 0, dl_dalpha_mag = 0;
     for (int ch = 0; ch < 3; ++ch) {
-      row[6 + ch] += dl[ch] * e.alpha * e.T;
+      t[6 + ch] = dl[ch] * e.alpha * e.T;
+      m[6 + ch] = std::fabs(t[6 + ch]);
       dl_dalpha += dl[ch] * (g[R_R + ch] * e.T - S[ch] / (1.0 - e.alpha));
+      dl_dalpha_mag += std::fabs(dl[ch]) * (std::fabs(g[R_R + ch]) * e.T +
+                                            (std::fabs(S[ch]) + std::fabs(Cpix[ch])) / (1.0 - e.alpha));
       S[ch] += g[R_R + ch] * e.alpha * e.T;
     }
-    if (e.clamped) continue;
-    const double dl_dpower = dl_dalpha * e.alpha;
-    row[5] += dl_dalpha * e.G;
-    const double gmx = dl_dpower * (g[R_CA] * e.dx + g[R_CB] * e.dy);
-    const double gmy = dl_dpower * (g[R_CB] * e.dx + g[R_CC] * e.dy);
-    row[0] += gmx;
-    row[1] += gmy;
-    row[9] += std::fabs(gmx);
-    row[10] += std::fabs(gmy);
-    row[2] += dl_dpower * (-0.5 * e.dx * e.dx);
-    row[3] += dl_dpower * (-e.dx * e.dy);
-    row[4] += dl_dpower * (-0.5 * e.dy * e.dy);
+    if (!e.clamped) {
+      const double dl_dpower = dl_dalpha * e.alpha, mp = dl_dalpha_mag * e.alpha;
+      const double geo[5] = {g[R_CA] * e.dx + g[R_CB] * e.dy, g[R_CB] * e.dx + g[R_CC] * e.dy, -0.5 * e.dx * e.dx,
+                             -e.dx * e.dy, -0.5 * e.dy * e.dy};
+      t[5] = dl_dalpha * e.G;
+      m[5] = dl_dalpha_mag * e.G;
+      for (int c = 0; c < 5; ++c) {
+        t[c] = dl_dpower * geo[c];
+        m[c] = mp * std::fabs(geo[c]);
+      }
+      row[9] += std::fabs(t[0]);
+      row[10] += std::fabs(t[1]);
+    }
+    for (int c = 0; c < 9; ++c) {
+      row[c] += t[c];
+      row[11 + c] += m[c];
+    }
   }
 }
 
@@ -772,9 +788,16 @@ int or_render_tiles(int32_t n_views, int64_t n, const OrCamera* cams, const OrOp
 // `tiles` is NULL): grad2d [V*N][9] receives the image-space gradients summed
 // over the pixels of those tiles only, and abs2d [V*N][2] (when not NULL) the
 // per-pixel magnitudes of the two mean components summed the same way.
+// A decision of one pixel taken the other way (see Flip): pixel = global pixel index.
+struct PixelFlip {
+  int64_t pixel;
+  Flip flip;
+};
+
 static int render_backward_impl(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt,
                                 const double* rec, const uint32_t* ids, const uint32_t* ranges, const int64_t* tiles,
-                                int64_t n_tiles, const double* dl_dimage, double* grad2d, double* abs2d) {
+                                int64_t n_tiles, const double* dl_dimage, double* grad2d, double* abs2d,
+                                const std::vector<PixelFlip>* flips = nullptr, double* mag9 = nullptr) {
   const std::vector<ViewInfo> views = make_views(cams, n_views, opt->tile);
   const int64_t T_tot = views.back().tile_off + (int64_t)views.back().grid.tx * views.back().grid.ty;
   const int B = opt->tile;
@@ -798,7 +821,14 @@ static int render_backward_impl(int32_t n_views, int64_t n, const OrCamera* cams
     PixelTrace tr;
     for (int j = ty * B; j < std::min(H, (ty + 1) * B); ++j)
       for (int i = tx * B; i < std::min(W, (tx + 1) * B); ++i) {
-        trace_pixel(i, j, ids + s, (int64_t)e - s, rec, *opt, true, tr);
+        Flip f;
+        if (flips && !flips->empty()) {
+          const int64_t p = vw.pix_off + (int64_t)j * W + i;
+          auto it = std::lower_bound(flips->begin(), flips->end(), p,
+                                     [](const PixelFlip& a, int64_t q) { return a.pixel < q; });
+          if (it != flips->end() && it->pixel == p) f = it->flip;
+        }
+        trace_pixel(i, j, ids + s, (int64_t)e - s, rec, *opt, true, tr, 0xffffffffu, nullptr, f);
         double dl[3];
         for (int ch = 0; ch < 3; ++ch) dl[ch] = dl_dimage[3 * vw.pix_off + (int64_t)ch * W * H + (int64_t)j * W + i];
         backward_pixel(tr, dl, rec, *opt, rows.data() + (size_t)row_off[ti] * kRowW);
@@ -806,6 +836,7 @@ static int render_backward_impl(int32_t n_views, int64_t n, const OrCamera* cams
   }
   std::memset(grad2d, 0, sizeof(double) * 9 * (size_t)n_views * n);
   if (abs2d) std::memset(abs2d, 0, sizeof(double) * 2 * (size_t)n_views * n);
+  if (mag9) std::memset(mag9, 0, sizeof(double) * 9 * (size_t)n_views * n);
   for (int64_t ti = 0; ti < count; ++ti) {
     const int64_t gt = tiles ? tiles[ti] : ti;
     const uint32_t s = ranges[2 * gt];
@@ -814,6 +845,8 @@ static int render_backward_impl(int32_t n_views, int64_t n, const OrCamera* cams
       for (int c = 0; c < 9; ++c) grad2d[(size_t)ids[s + k] * 9 + c] += row[c];
       if (abs2d)
         for (int c = 0; c < 2; ++c) abs2d[(size_t)ids[s + k] * 2 + c] += row[9 + c];
+      if (mag9)
+        for (int c = 0; c < 9; ++c) mag9[(size_t)ids[s + k] * 9 + c] += row[11 + c];
     }
   }
   return 0;
@@ -823,6 +856,29 @@ int or_render_backward_tiles(int32_t n_views, int64_t n, const OrCamera* cams, c
                              const double* rec, const uint32_t* ids, const uint32_t* ranges, const int64_t* tiles,
                              int64_t n_tiles, const double* dl_dimage, double* grad2d) {
   return render_backward_impl(n_views, n, cams, opt, rec, ids, ranges, tiles, n_tiles, dl_dimage, grad2d, nullptr);
+}
+
+// As or_render_backward_tiles, with one decision of each listed pixel taken
+// the other way: pixel flip_px[q] (global index, ascending, distinct) takes
+// the decision of kind flip_kind[q] (a P_NEAR_* bit) at list position
+// flip_k[q] the other way.  For comparing with an FP32 evaluation that went
+// the other way at near-threshold decisions.  mag9 [V*N][9] (may be NULL)
+// receives, per row and component, the sum over pixels of the magnitudes of
+// the parts of the per-pixel terms that grad2d adds up (see backward_pixel).
+int or_render_backward_tiles_flips(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt,
+                                   const double* rec, const uint32_t* ids, const uint32_t* ranges,
+                                   const int64_t* tiles, int64_t n_tiles, const double* dl_dimage, double* grad2d,
+                                   int64_t n_flips, const int64_t* flip_px, const int32_t* flip_k,
+                                   const uint32_t* flip_kind, double* mag9) {
+  std::vector<PixelFlip> flips((size_t)n_flips);
+  for (int64_t q = 0; q < n_flips; ++q) {
+    if (q > 0 && flip_px[q] <= flip_px[q - 1]) return 1;
+    flips[q].pixel = flip_px[q];
+    flips[q].flip.k = flip_k[q];
+    flips[q].flip.kind = flip_kind[q];
+  }
+  return render_backward_impl(n_views, n, cams, opt, rec, ids, ranges, tiles, n_tiles, dl_dimage, grad2d, nullptr,
+                              &flips, mag9);
 }
 
 // The backward of the blending over all tiles with the homodirectional
@@ -1124,11 +1180,12 @@ static void locate_pixel(const std::vector<ViewInfo>& views, int B, int64_t p, i
 // there are more than max_alt, or more than the trace keeps), and alt
 // [n_pix][max_alt][3] the colour (background included) the pixel takes when
 // exactly the a-th of them goes the other way, every other decision as
-// defined; kinds [n_pix][max_alt] the P_NEAR_* bit of each.  A value computed
+// defined; kinds [n_pix][max_alt] the P_NEAR_* bit of each and ks its list
+// position.  A value computed
 // with FP32 arithmetic near such a threshold may take either side of it.
 int or_render_flips(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
                     const uint32_t* ids, const uint32_t* ranges, const int64_t* pixels, int64_t n_pix, int32_t max_alt,
-                    int32_t* n_alt, double* alt, uint32_t* kinds) {
+                    int32_t* n_alt, double* alt, uint32_t* kinds, int32_t* ks) {
   (void)n;
   const std::vector<ViewInfo> views = make_views(cams, n_views, opt->tile);
 #pragma omp parallel for schedule(dynamic, 16)
@@ -1148,6 +1205,7 @@ int or_render_flips(int32_t n_views, int64_t n, const OrCamera* cams, const OrOp
       trace_pixel(i, j, ids + s, (int64_t)e - s, rec, *opt, false, tf, 0xffffffffu, nullptr, f);
       for (int ch = 0; ch < 3; ++ch) alt[(q * max_alt + a) * 3 + ch] = tf.C[ch] + tf.T * opt->bg[ch];
       kinds[q * max_alt + a] = f.kind;
+      ks[q * max_alt + a] = f.k;
     }
   }
   return 0;
@@ -1193,6 +1251,62 @@ int or_pixel_decisions(int32_t n_views, int64_t n, const OrCamera* cams, const O
         stop_id[p] = tr.stop_k >= 0 ? ids[s + tr.stop_k] : 0xffffffffu;
         margin_alpha[p] = tr.margin_alpha;
         margin_t[p] = tr.margin_t;
+      }
+  }
+  return 0;
+}
+
+
+// The single decision, taken the other way, that gives listed pixel q the
+// contributor count target_nc[q] and the final transmittance target_T[q]
+// (within 1e-3 relative; an FP32 evaluation that went the other way at some
+// threshold shows in both: a blended entry scales T by 1 - alpha, at least
+// 1/255 away from 1): candidates are the four threshold tests at every list
+// position up to two past the larger of the defined and target counts and of
+// the stop position; among those reaching both targets, the one whose colour
+// is nearest target_rgb[q] (3 per pixel).  found[q] = 0 when the defined
+// decisions already give both targets, 1 with (flip_k[q], flip_kind[q]) set,
+// -1 when no single flip does.
+int or_find_flips(int32_t n_views, int64_t n, const OrCamera* cams, const OrOptions* opt, const double* rec,
+                  const uint32_t* ids, const uint32_t* ranges, const int64_t* pixels, int64_t n_pix,
+                  const int32_t* target_nc, const double* target_T, const double* target_rgb, int32_t* found,
+                  int32_t* flip_k, uint32_t* flip_kind) {
+  (void)n;
+  const std::vector<ViewInfo> views = make_views(cams, n_views, opt->tile);
+  const uint32_t kinds[4] = {P_NEAR_ALPHA_MIN, P_NEAR_T_MIN, P_NEAR_POWER0, P_NEAR_ALPHA_MAX};
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t q = 0; q < n_pix; ++q) {
+    int v, i, j;
+    int64_t gt;
+    locate_pixel(views, opt->tile, pixels[q], &v, &i, &j, &gt);
+    const uint32_t s = ranges[2 * gt], e = ranges[2 * gt + 1];
+    const int64_t len = (int64_t)e - s;
+    PixelTrace tr, tf;
+    trace_pixel(i, j, ids + s, len, rec, *opt, false, tr);
+    found[q] = 0;
+    flip_k[q] = -1;
+    flip_kind[q] = 0;
+    auto same_T = [&](double T) { return std::fabs(T - target_T[q]) <= 1e-3 * target_T[q]; };
+    if (tr.n_contrib == target_nc[q] && same_T(tr.T)) continue;
+    const int64_t hi = std::min<int64_t>(len - 1, (int64_t)std::max({tr.n_contrib, target_nc[q], tr.stop_k}) + 2);
+    double best = INFINITY;
+    found[q] = -1;
+    for (int64_t k = 0; k <= hi; ++k)
+      for (uint32_t kind : kinds) {
+        Flip f;
+        f.k = (int)k;
+        f.kind = kind;
+        trace_pixel(i, j, ids + s, len, rec, *opt, false, tf, 0xffffffffu, nullptr, f);
+        if (tf.n_contrib != target_nc[q] || !same_T(tf.T)) continue;
+        double d = std::fabs(tf.T - target_T[q]) / target_T[q];
+        for (int ch = 0; ch < 3; ++ch)
+          d = std::max(d, std::fabs(tf.C[ch] + tf.T * opt->bg[ch] - target_rgb[3 * q + ch]));
+        if (d < best) {
+          best = d;
+          found[q] = 1;
+          flip_k[q] = (int)k;
+          flip_kind[q] = kind;
+        }
       }
   }
   return 0;

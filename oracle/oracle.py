@@ -106,14 +106,18 @@ def lib():
         _lib.or_pixel_counts.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P]
         _lib.or_bin_sampled.argtypes = [i32, i64, P, P, P, P, i32, P, i64, P, P, i64, P]
         _lib.or_render_flips.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, i64, i32,
-                                         P, P, P]
+                                         P, P, P, P]
+        _lib.or_render_backward_tiles_flips.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P,
+                                                        P, P, i64, P, P, i64, P, P, P, P]
         _lib.or_pixel_decisions.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, P, P,
                                             P, P]
+        _lib.or_find_flips.argtypes = [i32, i64, C.POINTER(OrCamera), C.POINTER(OrOptions), P, P, P, P, i64, P, P,
+                                       P, P, P, P]
         _lib.or_sh_basis.argtypes = [i32, i64, P, P, P]
         _lib.or_quat_to_rot.argtypes = [P, P]
         for f in ("or_project", "or_bin", "or_render", "or_render_backward", "or_project_backward", "or_fd_local",
                   "or_render_tiles", "or_render_backward_tiles", "or_render_backward_abs", "or_bin_sampled",
-                  "or_render_flips", "or_pixel_decisions"):
+                  "or_render_flips", "or_pixel_decisions", "or_render_backward_tiles_flips", "or_find_flips"):
             getattr(_lib, f).restype = C.c_int
     return _lib
 
@@ -264,9 +268,10 @@ def ranges_from_counts(counts):
     return r
 
 
-def render_flips(cams, opts: Options, rec, ids, ranges, pixels, max_alt=8):
+def render_flips(cams, opts: Options, rec, ids, ranges, pixels, max_alt=8, with_positions=False):
     """One-flip alternatives of the listed pixels (see or_render_flips): n_alt [P] (-1: too many
-    near-threshold decisions), alt [P, max_alt, 3] colours, kinds [P, max_alt] P_NEAR_* bits."""
+    near-threshold decisions), alt [P, max_alt, 3] colours, kinds [P, max_alt] P_NEAR_* bits (and
+    with_positions: ks [P, max_alt], the list position of each)."""
     n_views = len(cams)
     rec = _d(rec)
     n = rec.shape[0] // n_views
@@ -274,12 +279,35 @@ def render_flips(cams, opts: Options, rec, ids, ranges, pixels, max_alt=8):
     n_alt = np.zeros(px.shape[0], np.int32)
     alt = np.full((px.shape[0], max_alt, 3), np.nan)
     kinds = np.zeros((px.shape[0], max_alt), np.uint32)
+    ks = np.full((px.shape[0], max_alt), -1, np.int32)
     oc = opts.as_c()
     rc = lib().or_render_flips(n_views, n, cameras_c(cams), C.byref(oc), _p(rec),
                                _p(np.ascontiguousarray(ids, np.uint32)), _p(np.ascontiguousarray(ranges, np.uint32)),
-                               _p(px), px.shape[0], max_alt, _p(n_alt), _p(alt), _p(kinds))
+                               _p(px), px.shape[0], max_alt, _p(n_alt), _p(alt), _p(kinds), _p(ks))
     assert rc == 0
-    return n_alt, alt, kinds
+    return (n_alt, alt, kinds, ks) if with_positions else (n_alt, alt, kinds)
+
+
+def find_flips(cams, opts: Options, rec, ids, ranges, pixels, target_nc, target_T, target_rgb):
+    """Per listed pixel, the single decision taken the other way that gives it the contributor count
+    target_nc and the final transmittance target_T (see or_find_flips): (found [P] 0/1/-1, positions
+    [P], kinds [P])."""
+    n_views = len(cams)
+    rec = _d(rec)
+    n = rec.shape[0] // n_views
+    px = np.ascontiguousarray(pixels, np.int64)
+    tnc = np.ascontiguousarray(target_nc, np.int32)
+    tT = np.ascontiguousarray(target_T, np.float64)
+    trgb = np.ascontiguousarray(np.asarray(target_rgb, np.float64).reshape(-1, 3))
+    found = np.zeros(px.shape[0], np.int32)
+    ks = np.zeros(px.shape[0], np.int32)
+    kinds = np.zeros(px.shape[0], np.uint32)
+    oc = opts.as_c()
+    rc = lib().or_find_flips(n_views, n, cameras_c(cams), C.byref(oc), _p(rec),
+                             _p(np.ascontiguousarray(ids, np.uint32)), _p(np.ascontiguousarray(ranges, np.uint32)),
+                             _p(px), px.shape[0], _p(tnc), _p(tT), _p(trgb), _p(found), _p(ks), _p(kinds))
+    assert rc == 0
+    return found, ks, kinds
 
 
 def pixel_decisions(cams, opts: Options, rec, ids, ranges):
@@ -342,20 +370,38 @@ def render_tiles(cams, opts: Options, rec, ids, ranges, tiles):
     return dict(image=image, t_final=tf, n_contrib=nc, pix_flags=pf)
 
 
-def render_backward_tiles(cams, opts: Options, rec, ids, ranges, tiles, dl_dimage):
-    """Image-space gradients summed over the pixels of the listed tiles only."""
+def render_backward_tiles(cams, opts: Options, rec, ids, ranges, tiles, dl_dimage, flips=None, with_mag=False):
+    """Image-space gradients summed over the pixels of the listed tiles only.  flips: optional
+    (pixels, positions, kinds) arrays, one decision per listed pixel taken the other way (see
+    or_render_backward_tiles_flips).  with_mag: also return, per row and component, the sum of the
+    magnitudes of the per-pixel terms (the scale of the rounding error of any summation of them)."""
     n_views = len(cams)
     rec = _d(rec)
     n = rec.shape[0] // n_views
     g2 = np.zeros((n_views * n, 9))
+    mag = np.zeros((n_views * n, 9))
     t = np.ascontiguousarray(tiles, np.int64)
     oc = opts.as_c()
-    rc = lib().or_render_backward_tiles(n_views, n, cameras_c(cams), C.byref(oc), _p(rec),
-                                        _p(np.ascontiguousarray(ids, np.uint32)),
-                                        _p(np.ascontiguousarray(ranges, np.uint32)), _p(t), t.shape[0],
-                                        _p(_d(dl_dimage)), _p(g2))
+    ids = np.ascontiguousarray(ids, np.uint32)
+    ranges = np.ascontiguousarray(ranges, np.uint32)
+    if flips is None:
+        flips = (np.zeros(0, np.int64), np.zeros(0, np.int32), np.zeros(0, np.uint32))
+    order = np.argsort(np.asarray(flips[0], np.int64), kind="stable")
+    fp = np.ascontiguousarray(np.asarray(flips[0], np.int64)[order])
+    fk = np.ascontiguousarray(np.asarray(flips[1], np.int32)[order])
+    fkind = np.ascontiguousarray(np.asarray(flips[2], np.uint32)[order])
+    rc = lib().or_render_backward_tiles_flips(n_views, n, cameras_c(cams), C.byref(oc), _p(rec), _p(ids),
+                                              _p(ranges), _p(t), t.shape[0], _p(_d(dl_dimage)), _p(g2),
+                                              fp.shape[0], _p(fp), _p(fk), _p(fkind), _p(mag))
     assert rc == 0
-    return g2
+    return (g2, mag) if with_mag else g2
+
+
+def render_backward_mag(cams, opts: Options, rec, ids, ranges, dl_dimage):
+    """render_backward over every tile with the per-row, per-component sums of the magnitudes of the
+    per-pixel terms (see render_backward_tiles)."""
+    T = int(total_tiles(cams, opts.tile))
+    return render_backward_tiles(cams, opts, rec, ids, ranges, np.arange(T), dl_dimage, with_mag=True)
 
 
 def pixel_counts(cams, opts: Options, rec, ids, ranges):

@@ -521,6 +521,18 @@ def test_one_flip_alternatives_of_near_threshold_decisions(oracle_lib):
         walls_c = c1[ch] * (1 - T3)
         np.testing.assert_allclose(r["image"].reshape(3, -1)[ch], walls_c + c2[ch] * a4 * T3, rtol=1e-13)
         np.testing.assert_allclose(alt[:, 0, ch], walls_c, rtol=1e-13)
+    # the flip that gives a pixel a given contributor count: 3 (stopped at the fourth entry) is the
+    # transmittance test at position 3; 4 needs none; 6 is beyond the five-entry list
+    px = np.arange(4)
+    rgb_stop = np.tile(np.array(c1) * (1 - T3), (4, 1))
+    T4 = T3 * (1 - a4)
+    found, ks, kinds = O.find_flips(cams, opts, rec, ids, ranges, px, [3, 4, 6, 3], [T3, T4, T3, T3], rgb_stop)
+    assert found.tolist() == [1, 0, -1, 1]
+    assert ks[0] == 3 and kinds[0] == O.P_NEAR_T_MIN
+    # the same count with another transmittance: the fourth entry skipped by its alpha test instead
+    # (T stays T3 and the fifth entry, alpha 0.5, is blended: count 5)
+    found, ks, kinds = O.find_flips(cams, opts, rec, ids, ranges, [0], [5], [T3 * 0.5], rgb_stop[:1])
+    assert found[0] == 1 and ks[0] == 3 and kinds[0] == O.P_NEAR_ALPHA_MIN
     # the sign of the exponent: a needle conic (a c - b^2 tiny against a c) whose quadratic form at a
     # pixel on its long axis is the difference of two large terms
     a, c = 4e4, 1e-2
@@ -542,6 +554,103 @@ def test_one_flip_alternatives_of_near_threshold_decisions(oracle_lib):
     cams, opts, rec, ids, ranges = _one_tile(O, [_flat_record(0.5, c1, 1.0)])
     n_alt, _, _ = O.render_flips(cams, opts, rec, ids, ranges, np.arange(64))
     assert np.all(n_alt == 0)
+
+
+def test_backward_with_a_flipped_decision_equals_the_shortened_list(oracle_lib):
+    """The backward with one near-threshold decision taken the other way at chosen pixels equals the
+    backward of the list without the entries that decision removes: skipping an entry just above
+    alpha_min is that entry left out; stopping at an entry whose transmittance lands just above t_min
+    is the list cut before it.  Pixels without a flip keep the full list's gradient."""
+    O = oracle_lib
+    amin = float(np.float32(1 / 255))
+    c1, c2 = (0.9, 0.2, 0.1), (0.1, 0.5, 0.7)
+    rng = np.random.default_rng(5)
+    dl = rng.standard_normal(3 * 64)
+    flipped = np.array([3, 17, 40])
+
+    def grads(rec, ids, ranges, flips=None):
+        cams = [S.pinhole(8, 8, 10.0)]
+        return O.render_backward_tiles(cams, O.Options(tile=8), rec, ids, ranges, [0], dl, flips)
+
+    # a small conic so the gradients of the means and conic are not zero
+    rec_a = [_flat_record(amin * (1 + 1e-7), c1, 1.0, conic=(1e-9, 0.0, 1e-9)),
+             _flat_record(0.3, c2, 2.0, mean=(2.5, 4.0), conic=(0.02, 0.01, 0.03))]
+    cams, opts, rec, ids, ranges = _one_tile(O, rec_a)
+    n_alt, alt, kinds, ks = O.render_flips(cams, opts, rec, ids, ranges, flipped, with_positions=True)
+    assert np.all(kinds[:, 0] == O.P_NEAR_ALPHA_MIN) and np.all(ks[:, 0] == 0)
+    g_flip = grads(rec, ids, ranges, (flipped, ks[:, 0], kinds[:, 0]))
+    g_full = grads(rec, ids, ranges)
+    # the flipped pixels' share equals that of the list without entry 0
+    only = np.zeros(3 * 64)
+    for ch in range(3):
+        only[ch * 64 + flipped] = dl[ch * 64 + flipped]
+    rest = dl - only
+    cams1, opts1, rec1, ids1, ranges1 = _one_tile(O, rec_a[1:])
+    g_short = O.render_backward_tiles(cams1, opts1, rec1, ids1, ranges1, [0], only)
+    g_full_rest = O.render_backward_tiles(cams, opts, rec, ids, ranges, [0], rest)
+    np.testing.assert_allclose(g_flip[1], g_short[0] + g_full_rest[1], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(g_flip[0], g_full_rest[0], rtol=1e-12, atol=1e-15)
+    assert not np.allclose(g_flip, g_full)
+    # transmittance: the flip stops the pixel at the fourth entry, as the list cut before it does
+    tmin = float(np.float32(1e-4))
+    T3 = 1.0 * (1 - 0.9) * (1 - 0.9) * (1 - 0.9)
+    a4 = 1 - tmin * (1 + 1e-9) / T3
+    walls = [_flat_record(0.9, c1, 1.0 + i) for i in range(3)]  # zero conic: alpha 0.9 at every pixel
+    recs = walls + [_flat_record(a4, c2, 4.0), _flat_record(0.5, c1, 5.0)]
+    cams, opts, rec, ids, ranges = _one_tile(O, recs)
+    r = O.render(cams, opts, rec, ids, ranges)
+    tflag = np.nonzero(r["pix_flags"] & O.P_NEAR_T_MIN)[0]
+    assert tflag.shape[0] > 0
+    n_alt, alt, kinds, ks = O.render_flips(cams, opts, rec, ids, ranges, tflag, with_positions=True)
+    a = np.array([np.nonzero(kinds[q, :n_alt[q]] == O.P_NEAR_T_MIN)[0][0] for q in range(tflag.shape[0])])
+    assert np.all(ks[np.arange(tflag.shape[0]), a] == 3)
+    g_flip = O.render_backward_tiles(cams, opts, rec, ids, ranges, [0], dl,
+                                     (tflag, ks[np.arange(tflag.shape[0]), a], kinds[np.arange(tflag.shape[0]), a]))
+    only = np.zeros(3 * 64)
+    for ch in range(3):
+        only[ch * 64 + tflag] = dl[ch * 64 + tflag]
+    cams3, opts3, rec3, ids3, ranges3 = _one_tile(O, walls)
+    g_cut = O.render_backward_tiles(cams3, opts3, rec3, ids3, ranges3, [0], only)
+    g_rest = O.render_backward_tiles(cams, opts, rec, ids, ranges, [0], dl - only)
+    np.testing.assert_allclose(g_flip[:3], g_cut[:3] + g_rest[:3], rtol=1e-11, atol=1e-15)
+    np.testing.assert_allclose(g_flip[3:], g_rest[3:], rtol=1e-11, atol=1e-15)
+
+
+def test_backward_term_magnitudes(oracle_lib):
+    """The per-row magnitudes of the parts of the per-pixel terms: for the colour components they are
+    the sums over pixels of |the gradient of the loss restricted to that pixel| (the backward is linear
+    in dL/dimage); for the others they bound those sums; and for one Gaussian alone (nothing behind
+    it, background 0) the opacity component has the closed form
+    sum_p G_p sum_c |dl_pc| (|col_c| + col_c alpha_p / (1 - alpha_p))."""
+    O = oracle_lib
+    cams = [S.pinhole(16, 16, 20.0)]
+    sc = S.make_scene(7, 12, 1, cams, "box", log_scale_mu=-1.7, log_scale_sigma=0.3, logit_sigma=1.0)
+    opts = O.Options(tile=16)
+    f = O.forward(O.Params.from_scene(sc), cams, opts)
+    rng = np.random.default_rng(1)
+    dl = rng.standard_normal(3 * 256)
+    g, mag = O.render_backward_tiles(cams, opts, f["proj"]["rec"], f["ids"], f["ranges"], [0], dl, with_mag=True)
+    acc = np.zeros_like(g)
+    for p in range(256):
+        one = np.zeros_like(dl)
+        one[p::256] = dl[p::256]
+        acc += np.abs(O.render_backward_tiles(cams, opts, f["proj"]["rec"], f["ids"], f["ranges"], [0], one))
+    np.testing.assert_allclose(mag[:, 6:], acc[:, 6:], rtol=1e-12, atol=1e-300)
+    assert np.all(mag[:, :6] >= acc[:, :6] * (1 - 1e-12)) and mag.max() > 0
+    assert np.all(mag >= np.abs(g) * (1 - 1e-12))
+    # one Gaussian: closed form of the opacity component's magnitude
+    rec = np.array([_flat_record(0.7, (0.3, 0.8, 0.5), 1.0, mean=(3.2, 4.1), conic=(0.3, 0.05, 0.2))])
+    cams1, opts1, rec1, ids1, ranges1 = _one_tile(O, rec.tolist())
+    dl1 = rng.standard_normal(3 * 64)
+    g1, mag1 = O.render_backward_tiles(cams1, opts1, rec1, ids1, ranges1, [0], dl1, with_mag=True)
+    ys, xs = np.mgrid[0:8, 0:8].astype(np.float64)
+    dx, dy = (xs - 3.2).reshape(-1), (ys - 4.1).reshape(-1)
+    G = np.exp(-0.5 * (0.3 * dx * dx + 0.2 * dy * dy) - 0.05 * dx * dy)
+    al = 0.7 * G
+    on = al >= f32(1 / 255)
+    col = np.array([0.3, 0.8, 0.5])
+    per = sum(np.abs(dl1[ch * 64:(ch + 1) * 64]) * (col[ch] + col[ch] * al / (1 - al)) for ch in range(3))
+    np.testing.assert_allclose(mag1[0, 5], np.sum((G * per)[on]), rtol=1e-12)
 
 
 def test_pixel_decisions_summarise_the_trace(oracle_lib):
