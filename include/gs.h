@@ -16,7 +16,8 @@
  *  - Every pointer inside the structs below is a DEVICE pointer unless
  *    stated otherwise.  The caller allocates and owns all device memory,
  *    workspaces included; the library never allocates, frees or retains it
- *    (gs_render_fwd_noalloc's static per-GPU scratch aside).
+ *    (gs_render_fwd_noalloc's static per-GPU scratch and gs_autotune's own
+ *    temporary buffers aside).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Hot-path calls
  *    only enqueue kernels on it and return; none synchronises, so they may be
  *    captured into a HIP graph.  No call issues hipMemset: buffers that must
@@ -386,6 +387,35 @@ gs_status gs_photometric_loss_workspace_size(const gs_camera* cams, int32_t n_vi
 gs_status gs_photometric_loss(const gs_camera* cams, int32_t n_views, const float* image, const float* target,
                               float lambda, float* loss_out, float* dl_dimage, void* workspace,
                               size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------- autotuning
+ * The tile size of the tile-based rasterisation (Sec. III-B) is a free
+ * parameter; gs_autotune picks it by timing the actual problem: for each
+ * candidate (bits of candidate_mask: 1 = tile 8, 2 = 16, 4 = 32; 0 = all)
+ * one warm-up and `iters` timed iterations of gs_project, gs_bin_sort,
+ * gs_render_fwd with the L1 term against `target` (rgb layout of gs_image,
+ * device), gs_raster_bwd and gs_project_bwd on `stream`, at opts with its
+ * tile_size replaced (the LDS batch is one record per lane of the tile's
+ * workgroup, so the tile also fixes it).  Host-side and synchronising, NOT
+ * for graph capture; the only call that allocates device memory (its own
+ * buffers per candidate, all freed before it returns).  A candidate that does
+ * not fit in device memory or whose pair count exceeds the 32-bit index space
+ * is skipped (ms -1); GS_ERR_CAPACITY when none fits.  Results are cached for
+ * the life of the process by (floor(log2 n), the multiset of view
+ * resolutions, sh_degree, checkpoint, candidate mask); refresh != 0 times
+ * again.  The parameters are not modified. */
+typedef struct gs_autotune_result {
+  int32_t tile_size;     /* the fastest candidate */
+  int32_t from_cache;    /* 1: taken from the cache, nothing timed */
+  int32_t n_candidates;  /* candidates timed, ascending in candidates[] */
+  int32_t candidates[3];
+  float ms[3];           /* mean milliseconds of one iteration at each (-1: skipped) */
+  int64_t pairs[3];      /* (tile, Gaussian) incidences at each (-1: not reached) */
+} gs_autotune_result;
+
+gs_status gs_autotune(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
+                      const float* target, int32_t iters, int32_t candidate_mask, int32_t refresh,
+                      gs_autotune_result* out, void* stream);
 
 /* ------------------------------------------------- adaptive density control
  * Sec. III-B: every densification interval (1000 iterations, Sec. IV-A)

@@ -83,6 +83,11 @@ class gs_adam_group(C.Structure):
                 ("lr", C.c_float), ("reserved", C.c_int32)]
 
 
+class gs_autotune_result(C.Structure):
+    _fields_ = [("tile_size", C.c_int32), ("from_cache", C.c_int32), ("n_candidates", C.c_int32),
+                ("candidates", C.c_int32 * 3), ("ms", C.c_float * 3), ("pairs", C.c_int64 * 3)]
+
+
 EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_options", "gs_total_tiles",
            "gs_total_pixels", "gs_bin_sort_workspace_size", "gs_render_fwd_workspace_size",
            "gs_render_bwd_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
@@ -91,7 +96,7 @@ EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_op
            "gs_raster_bwd_abs", "gs_project_bwd_adam_stats", "gs_default_density_config", "gs_scene_extent", "gs_density_accumulate",
            "gs_density_workspace_size", "gs_density_plan", "gs_density_apply", "gs_delaunay", "gs_densify_depth",
            "gs_init_gaussians_workspace_size", "gs_init_gaussians_count", "gs_init_gaussians",
-           "gs_render_fwd_noalloc")
+           "gs_render_fwd_noalloc", "gs_autotune")
 
 _lib = None
 
@@ -121,6 +126,7 @@ def load(path: str = LIB_PATH):
         "gs_bin_sort": (C.c_int, [C.POINTER(gs_projected), i64, pc, i32, po, C.POINTER(gs_bins), P, sz, P]),
         "gs_render_fwd": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), pc, i32, po,
                                     C.POINTER(gs_loss), C.POINTER(gs_image), P, sz, P]),
+        "gs_autotune": (C.c_int, [pp, pc, i32, po, P, i32, i32, i32, C.POINTER(gs_autotune_result), P]),
         "gs_render_fwd_noalloc": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), pc, i32, po,
                                             C.POINTER(gs_loss), C.POINTER(gs_image), P]),
         "gs_render_bwd": (C.c_int, [pp, C.POINTER(gs_projected), C.POINTER(gs_bins), C.POINTER(gs_image), pc, i32,
@@ -242,6 +248,13 @@ def gs_render_fwd(proj, n, bins, cams, n_views, opts, loss, out, workspace, work
     _check("gs_render_fwd", load().gs_render_fwd(C.byref(proj), n, C.byref(bins), cams, n_views, C.byref(opts),
                                                  C.byref(loss) if loss is not None else None, C.byref(out),
                                                  workspace, workspace_bytes, stream))
+
+
+def gs_autotune(params, cams, n_views, opts, target, iters, candidate_mask, refresh, stream):
+    out = gs_autotune_result()
+    _check("gs_autotune", load().gs_autotune(C.byref(params), cams, n_views, C.byref(opts), target, iters,
+                                             candidate_mask, refresh, C.byref(out), stream))
+    return out
 
 
 def gs_render_fwd_noalloc(proj, n, bins, cams, n_views, opts, loss, out, stream):

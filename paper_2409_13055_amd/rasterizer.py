@@ -370,6 +370,10 @@ class FusedAdam:
                        1 if zero_grad else 0, _stream())
 
 
+class CapacityOverflow(RuntimeError):
+    """The pair capacity of a captured or repeated iteration was exceeded."""
+
+
 class MappingStep:
     """One mapping iteration over a batch of keyframes (Sec. III-B): project all
     views in one pass over the parameters, one bin/sort over every view's
@@ -412,6 +416,10 @@ class MappingStep:
         self.frame = None
         self.graph = None
         self._side = None  # stream of the gradient-buffer clear, which overlaps the forward
+        # 1 once any iteration since the last check_overflow() overflowed the pair capacity (that
+        # iteration rendered nothing: gs_bin_sort leaves every tile empty); set on the device, so
+        # graph replays keep it too
+        self.overflow_seen = torch.zeros(1, dtype=torch.int32, device=params.means.device)
         self.abs2d = None
         if density is not None:
             self.abs2d = torch.empty(self.rast.n_views * params.n, 2, dtype=torch.float32, device=params.means.device)
@@ -443,6 +451,12 @@ class MappingStep:
         return dict(target=self.target) if self.photometric is None else dict(dl_dimage=self.dl_dimage)
 
     def run(self, mark=None):
+        """Enqueue one iteration (no host synchronisation); see _run.  The iteration's overflow flag
+        is folded into overflow_seen after its last stage."""
+        self._run(mark)
+        torch.maximum(self.overflow_seen, self.frame.d_overflow, out=self.overflow_seen)
+
+    def _run(self, mark=None):
         """Enqueue one iteration (no host synchronisation).
 
         With `mark` (a callable taking a stage name), the backward is issued as
@@ -506,6 +520,15 @@ class MappingStep:
 
     def overflowed(self) -> bool:
         return int(self.frame.d_overflow.item()) != 0
+
+    def check_overflow(self):
+        """Raises CapacityOverflow when an iteration since the last check overflowed the pair capacity
+        (synchronises with the host); the flag is cleared."""
+        if int(self.overflow_seen.item()) != 0:
+            self.overflow_seen.zero_()
+            raise CapacityOverflow(f"the (tile, Gaussian) pair count exceeded the capacity {self.rast.capacity}: "
+                                   f"those iterations rendered empty tiles and stepped Adam on zero gradients; "
+                                   f"size() again (and capture()) before continuing")
 
     def densify(self, generator: Optional[torch.Generator] = None) -> "MappingStep":
         """One density-control step (Sec. III-B) on this step's Gaussians; returns a MappingStep over
@@ -713,6 +736,11 @@ class PyramidMappingStep:
         self.iteration += 1
         return st
 
+    def check_overflow(self):
+        """MappingStep.check_overflow of every level batch (synchronises)."""
+        for st in self.steps.values():
+            st.check_overflow()
+
 
 class DensityControl:
     """Adaptive density control of Sec. III-B (AbsGS densification with the 3DGS split and clone
@@ -862,11 +890,14 @@ class MappingLoop:
 
     def __init__(self, params: GaussianParams, cameras, targets, lrs=None, levels: int = 2, schedule=None,
                  ssim_lambda: float = 0.2, densify_every: int = 1000, tile_size: int = 16, graphs: bool = True,
-                 generator: Optional[torch.Generator] = None, **density_cfg):
+                 generator: Optional[torch.Generator] = None, check_every: int = 100, **density_cfg):
+        """check_every: iterations between host checks of the pair-capacity overflow flag (also checked
+        before every density step); an overflow raises CapacityOverflow."""
         self.cameras, self.lrs, self.levels = list(cameras), lrs, int(levels)
         self.targets = [t if isinstance(t, torch.Tensor) else pack_images([t], params.means.device)
                         for t in targets]
         self.densify_every = int(densify_every)
+        self.check_every = max(1, int(check_every))
         self.generator = generator
         self.density = DensityControl(params.n, cameras, device=params.means.device, **density_cfg)
         self._opts = dict(schedule=schedule, lrs=lrs, graphs=graphs, ssim_lambda=ssim_lambda, tile_size=tile_size,
@@ -892,7 +923,10 @@ class MappingLoop:
             st = self.steps.run_levels([self.steps.level_at(k) for k in self.kf_iters])
             self.kf_iters = [k + 1 for k in self.kf_iters]
             self.iteration += 1
-            if self.densify_every > 0 and self.iteration % self.densify_every == 0:
+            densify = self.densify_every > 0 and self.iteration % self.densify_every == 0
+            if densify or self.iteration % self.check_every == 0:
+                self.steps.check_overflow()
+            if densify:
                 new_p, new_adam = self.density.apply(self.steps.params, self.steps.adam, generator=self.generator)
                 self._rebuild(new_p, new_adam)
                 self.history.append((self.iteration, new_p.n))

@@ -72,7 +72,30 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def compare_grads(gpu_grads, ref, tol, msg=""):
+# Element-wise gradient bound: |gpu - oracle| <= REL |oracle| + KAPPA mag + FLOOR max|oracle|, where mag
+# is the sum over pixels of the magnitudes of the per-pixel terms the gradient adds up (the oracle gives
+# it).  A sum of terms that cancel can only be as accurate as the terms: an FP32 term carries a relative
+# error of order 1e-6 (1e-5 for elongated splats, whose exponent is a difference of large quantities),
+# so KAPPA = 1e-4 leaves a factor of ten over the worst of them.
+REL, KAPPA, FLOOR = 1e-3, 1e-4, 1e-6
+
+
+def elementwise_frac(a, b, rel=REL, floor=FLOOR, mag=None, kappa=KAPPA):
+    """Fraction of elements with |a - b| <= rel |b| + kappa mag + floor max|b| (b the oracle's value;
+    mag as above, or none)."""
+    a = np.asarray(a, np.float64).reshape(-1)
+    b = np.asarray(b, np.float64).reshape(-1)
+    if b.size == 0:
+        return 1.0
+    bound = rel * np.abs(b) + floor * np.abs(b).max()
+    if mag is not None:
+        bound = bound + kappa * np.asarray(mag, np.float64).reshape(-1)
+    return float(np.mean(np.abs(a - b) <= bound))
+
+
+def compare_grads(gpu_grads, ref, tol, msg="", min_frac=0.999):
+    """Per tensor: relative L2 error <= tol, and the element-wise bound (elementwise_frac) met by at
+    least min_frac of the elements.  Returns {name: (rel_l2, frac)}."""
     dc, rest = oracle_grads_sh(ref)
     pairs = [("means", ref["means"]), ("log_scales", ref["log_scales"]), ("quats", ref["quats"]),
              ("opacity_logits", ref["opacity_logits"]), ("sh_dc", dc)]
@@ -80,7 +103,114 @@ def compare_grads(gpu_grads, ref, tol, msg=""):
         pairs.append(("sh_rest", rest))
     out = {}
     for k, r in pairs:
-        out[k] = rel_l2(gpu_grads[k], r)
-    bad = {k: v for k, v in out.items() if not v <= tol}
-    assert not bad, f"{msg} gradient rel-L2 above {tol}: {bad} (all: {out})"
+        out[k] = (rel_l2(gpu_grads[k], r), elementwise_frac(gpu_grads[k], r))
+    print(f"[grads] {msg}: " + ", ".join(f"{k} rel {v[0]:.2e} elem {v[1]:.5f}" for k, v in out.items()), flush=True)
+    bad = {k: v for k, v in out.items() if not (v[0] <= tol and v[1] >= min_frac)}
+    assert not bad, f"{msg} gradient above rel-L2 {tol} or element-wise fraction below {min_frac}: {bad} (all: {out})"
     return out
+
+
+def compare_grad2d(got, ref, tol=1e-3, msg="", min_frac=0.999, mag=None):
+    """Image-space gradients [rows, C] per component: relative L2 <= tol and the element-wise bound
+    (elementwise_frac, with the oracle's per-term magnitudes when given) for at least min_frac of the
+    rows."""
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    out = [(rel_l2(got[:, c], ref[:, c]),
+            elementwise_frac(got[:, c], ref[:, c], mag=None if mag is None else mag[:, c]))
+           for c in range(ref.shape[1])]
+    print(f"[grad2d] {msg}: rel " + " ".join(f"{r:.1e}" for r, _ in out) + " | elem "
+          + " ".join(f"{f:.5f}" for _, f in out) + ("" if mag is None else " (with term magnitudes)"), flush=True)
+    bad = [(c, v) for c, v in enumerate(out) if not (v[0] <= tol and v[1] >= min_frac)]
+    for c, _ in bad:  # the worst elements of a failing component
+        b = np.abs(ref[:, c])
+        bound = REL * b + FLOOR * b.max() + (0.0 if mag is None else KAPPA * mag[:, c])
+        r = np.abs(got[:, c] - ref[:, c]) / np.maximum(bound, 1e-300)
+        for k in np.argsort(-r)[:4]:
+            print(f"  component {c} row {k}: gpu {got[k, c]:.6e} oracle {ref[k, c]:.6e} "
+                  f"mag {(0.0 if mag is None else mag[k, c]):.3e} |d|/bound {r[k]:.2f}", flush=True)
+    assert not bad, f"{msg} image-space gradient components above rel-L2 {tol} / below {min_frac}: {bad}"
+    return out
+
+
+def pixel_channel_index(cams):
+    """[P, 3] index of each pixel's three channels in the packed planar image (views packed)."""
+    parts, off = [], 0
+    for c in cams:
+        hw = c.width * c.height
+        base = off + np.arange(hw)
+        parts.append(np.stack([base, base + hw, base + 2 * hw], axis=1))
+        off += 3 * hw
+    return np.concatenate(parts)
+
+
+def check_image_one_flip(cams, opts, orec, ids, ranges, img_gpu, ref, pixels=None, tol=1e-4, msg=""):
+    """Every pixel (or every listed pixel) of the GPU image within tol of the oracle's render on the same
+    lists and records, or, where a decision lies within the FP32 rounding bound of its threshold
+    (flagged), within tol of that render with one such decision taken the other way.  Returns counts."""
+    idx = pixel_channel_index(cams)
+    P = idx.shape[0]
+    sel = np.arange(P) if pixels is None else np.asarray(pixels, np.int64)
+    d = np.abs(np.asarray(img_gpu, np.float64)[idx[sel]] - ref["image"][idx[sel]]).max(axis=1)
+    flagged = ref["pix_flags"][sel] != 0
+    bad = ~(d <= tol)
+    unflagged_bad = bad & ~flagged
+    assert not unflagged_bad.any(), (f"{msg}: {int(unflagged_bad.sum())} unflagged pixels differ by more than {tol} "
+                                     f"(max {d[unflagged_bad].max():.3e})")
+    fb = sel[bad]
+    explained = 0
+    if fb.shape[0]:
+        n_alt, alt, _ = O.render_flips(cams, opts, orec, ids, ranges, fb)
+        g = np.asarray(img_gpu, np.float64)[idx[fb]]
+        da = np.abs(alt - g[:, None, :]).max(axis=2)  # [pixels, alternatives]
+        ok = np.array([(n_alt[q] > 0) and bool(np.any(da[q, :n_alt[q]] <= tol)) for q in range(fb.shape[0])])
+        explained = int(ok.sum())
+        assert ok.all(), (f"{msg}: {int((~ok).sum())} flagged pixels differ by more than {tol} from the oracle and from "
+                          f"every one-flip alternative")
+    st = dict(pixels=int(sel.shape[0]), flagged=int(flagged.sum()), flagged_frac=float(flagged.mean()),
+              differing=int(bad.sum()), explained_by_one_flip=explained, max_abs_unflagged=float(d[~flagged].max(initial=0)))
+    print(f"[image] {msg}: {st}", flush=True)
+    return st
+
+
+def gpu_flips(cams, opts, orec, ids, ranges, img_gpu, ref, pixels, nc_gpu=None, tf_gpu=None):
+    """The decisions the GPU took the other way, for the oracle's backward to take them the GPU's way:
+    - where the GPU's contributor count or final transmittance (nc_gpu, tf_gpu, per pixel; optional)
+      differs from the oracle's (the transmittance by more than 1e-3 relative: a blended entry changes
+      it by at least 1/255), the single decision that gives the oracle both (or_find_flips), nearest
+      the GPU's colour;
+    - at other flagged pixels, the one-flip alternative closest to the GPU's colour, when the GPU's
+      colour is off the oracle's own by more than FP32 noise (1e-6) and at most half as far from the
+      alternative.
+    Returns ((pixels, list positions, kinds), number of pixels whose count no single flip explains)."""
+    idx = pixel_channel_index(cams)
+    pixels = np.asarray(pixels, np.int64)
+    img_gpu = np.asarray(img_gpu, np.float64)
+    chosen = {}
+    unexplained = 0
+    if nc_gpu is not None:
+        nc_gpu, tf_gpu = np.asarray(nc_gpu), np.asarray(tf_gpu, np.float64)
+        differ = (nc_gpu[pixels] != ref["n_contrib"][pixels]) | \
+                 (np.abs(tf_gpu[pixels] - ref["t_final"][pixels]) > 1e-3 * ref["t_final"][pixels])
+        mism = pixels[differ]
+        if mism.shape[0]:
+            found, ks, kinds = O.find_flips(cams, opts, orec, ids, ranges, mism, nc_gpu[mism], tf_gpu[mism],
+                                            img_gpu[idx[mism]])
+            for q, p in enumerate(mism):
+                if found[q] == 1:
+                    chosen[int(p)] = (int(ks[q]), int(kinds[q]))
+            unexplained = int((found < 0).sum())
+    fl = np.array([p for p in pixels[ref["pix_flags"][pixels] != 0] if int(p) not in chosen], np.int64)
+    if fl.shape[0]:
+        n_alt, alt, kinds, ks = O.render_flips(cams, opts, orec, ids, ranges, fl, with_positions=True)
+        g = img_gpu[idx[fl]]
+        d0 = np.abs(g - ref["image"][idx[fl]]).max(axis=1)
+        da = np.abs(alt - g[:, None, :]).max(axis=2)
+        for q in range(fl.shape[0]):
+            if n_alt[q] <= 0:
+                continue
+            a = int(np.argmin(da[q, :n_alt[q]]))
+            if d0[q] > 1e-6 and da[q, a] < 0.5 * d0[q]:
+                chosen[int(fl[q])] = (int(ks[q, a]), int(kinds[q, a]))
+    px = np.array(sorted(chosen), np.int64)
+    out = (px, np.array([chosen[int(p)][0] for p in px], np.int32), np.array([chosen[int(p)][1] for p in px], np.uint32))
+    return out, unexplained

@@ -248,6 +248,29 @@ def _incircle_exact(a, b, c, d):
             + m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]))
 
 
+def test_autotune_validates_before_any_launch(L):
+    """gs_autotune (host-side, synchronising) rejects bad arguments before touching the device."""
+    from paper_2409_13055_amd import synthetic as S
+    o = L.default_options()
+    cc = L.make_cameras([S.pinhole(64, 48, 50.0)])
+    params = L.gs_params()
+    params.n, params.sh_degree = 10, 0
+    for k, a in zip(("means", "log_scales", "quats", "opacity_logits", "sh_dc"), (0x1000, 0x2000, 0x3000, 0x4000,
+                                                                                 0x5000)):
+        setattr(params, k, C.c_void_p(a))
+    with pytest.raises(L.GsError, match="target is required"):
+        L.gs_autotune(params, cc, 1, o, None, 3, 0, 0, None)
+    with pytest.raises(L.GsError, match="iters"):
+        L.gs_autotune(params, cc, 1, o, C.c_void_p(0x6000), 0, 0, 0, None)
+    with pytest.raises(L.GsError, match="candidate_mask"):
+        L.gs_autotune(params, cc, 1, o, C.c_void_p(0x6000), 3, 8, 0, None)
+    params.sh_degree = 4
+    with pytest.raises(L.GsError, match="sh_degree"):
+        L.gs_autotune(params, cc, 1, o, C.c_void_p(0x6000), 3, 0, 0, None)
+    r = L.gs_autotune_result()
+    assert C.sizeof(r) == 64  # int32 x 6, float x 3, padding, int64 x 3: the layout gs.h declares
+
+
 def test_noalloc_forward_validates_before_any_launch(L):
     """gs_render_fwd_noalloc rejects bad arguments before touching the device, as gs_render_fwd does."""
     from paper_2409_13055_amd import synthetic as S

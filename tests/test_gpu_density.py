@@ -50,12 +50,11 @@ def test_homodirectional_gradient_matches_oracle(tile):
     got_a2 = a2.cpu().numpy().astype(np.float64)
     got_g2 = g2.cpu().numpy().astype(np.float64)
     assert np.abs(ref_a2).sum() > 0
-    for c in range(2):
-        assert U.rel_l2(got_a2[:, c], ref_a2[:, c]) <= 1e-3, (c, U.rel_l2(got_a2[:, c], ref_a2[:, c]))
+    U.compare_grad2d(got_a2, ref_a2, msg=f"homodirectional, tile {tile}")
     # the abs variant's image-space gradients are those of the plain backward (summation order aside)
     for c in range(9):
         assert U.rel_l2(got_g2[:, c], g2_plain.cpu().numpy()[:, c]) <= 1e-5
-        assert U.rel_l2(got_g2[:, c], ref_g2[:, c]) <= 1e-3
+    U.compare_grad2d(got_g2, ref_g2, msg=f"abs variant, tile {tile}")
     # every pixel magnitude is at least its share of the signed sum
     assert np.all(got_a2 >= np.abs(got_g2[:, :2]) * (1 - 1e-4) - 1e-9)
 
@@ -254,3 +253,22 @@ def test_mapping_loop_adds_a_keyframe_at_the_coarsest_level():
     loop.run(2)
     torch.cuda.synchronize()
     assert loop.kf_iters == [6, 6, 3] and int(loop.steps.adam.d_step.item()) == 6
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_mapping_loop_detects_pair_capacity_overflow(graphs):
+    """A capacity too small for the pairs (forced here) makes gs_bin_sort leave every tile empty; the
+    loop's periodic check raises instead of training on empty renders, eager or graph-replayed."""
+    sc = small_scene(10)
+    params = R.GaussianParams.from_scene(sc, DEV)
+    loop = R.MappingLoop(params, sc.cameras, sc.targets, lrs=dict(S.DEFAULT_LRS), levels=1, schedule=[0],
+                         ssim_lambda=0.0, densify_every=0, graphs=graphs, check_every=3)
+    loop.run(3)  # sized correctly: no overflow
+    st = loop.steps.step_for([0] * len(sc.cameras))
+    st.rast.reserve(64)
+    st.frame.set_capacity(64, st.rast.want_keys)
+    if graphs:
+        st.capture()  # records the small capacity (and runs one iteration)
+    with pytest.raises(R.CapacityOverflow):
+        loop.run(3)
+    assert loop.iteration <= 6

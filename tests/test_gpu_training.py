@@ -37,7 +37,7 @@ def gpu_grad_at(grads, g, p, K):
     return grads["sh_rest"][g, k - 1, ch]
 
 
-def fd_compare(sc, gpu_grads, gidx, tol):
+def fd_compare(sc, gpu_grads, gidx, tol, msg=""):
     """Central FD of the oracle's L1 loss vs the GPU gradient, per parameter group (rel L2)."""
     P = O.Params.from_scene(sc)
     K = (sc.sh_degree + 1) ** 2
@@ -53,6 +53,7 @@ def fd_compare(sc, gpu_grads, gidx, tol):
     for name, (a, b) in groups.items():
         m = ok & (pp >= a) & (pp < b)
         out[name] = U.rel_l2(got[m], fd[m])
+    print(f"[fd] {msg}: kept {ok.mean():.3f} of {ok.shape[0]} samples; rel-L2 per group {out}", flush=True)
     bad = {k: v for k, v in out.items() if not v <= tol}
     assert not bad, out
     return out
@@ -78,10 +79,10 @@ def test_autograd_function_matches_oracle_and_fd():
     P = O.Params.from_scene(sc)
     ref = O.forward_backward_l1(P, cams, sc.targets, O.Options(tile=16))
     assert abs(loss.item() - ref["loss"]) <= 1e-5 * ref["loss"]
-    U.compare_grads(grads, ref["grads"], 2e-3, "autograd vs oracle")
+    U.compare_grads(grads, ref["grads"], 1e-3, "autograd vs oracle")
     vis = np.nonzero(ref["proj"]["radius"].reshape(len(cams), -1).max(axis=0) > 0)[0]
     gidx = np.random.default_rng(0).choice(vis, 25, replace=False)
-    fd_compare(sc, grads, gidx, 2e-3)
+    fd_compare(sc, grads, gidx, 1e-3, "autograd")
 
 
 @pytest.mark.slow
@@ -92,7 +93,7 @@ def test_fused_l1_gradients_match_fd_on_200_gaussians_100k():
     g = U.run_gpu(sc)
     vis = np.nonzero(U.gpu_extents(g["rec"])[:, 0] > 0)[0]
     gidx = np.random.default_rng(200).choice(vis, 200, replace=False)
-    fd_compare(sc, g["grads"], gidx, 2e-3)
+    fd_compare(sc, g["grads"], gidx, 1e-3, "100k SH3, 200 Gaussians")
 
 
 def test_graph_replays_match_eager():
