@@ -22,9 +22,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
-# FP32 vector peak without packed-FP32 instructions (the build disables them):
-# 256 CU * 4 SIMD * 16 lanes * 2 flop (FMA) * 2.4 GHz = 78.6 TFLOP/s (157.3 with packed FP32).
-VALU_PEAK_TFLOPS = 78.64
+# FP32 vector peak: 256 CU * 4 SIMD * 16 lanes * 2 flop (FMA) * 2 (packed FP32) * 2.4 GHz = 157.3
+# TFLOP/s published; the build disables packed-FP32 instructions, which halves the rate it can reach.
+VALU_PEAK_TFLOPS = 157.29
+VALU_UNPACKED_TFLOPS = 78.64
 
 
 def log(*a):
@@ -39,6 +40,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=5, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--tile", type=int, default=0, help="tile size (0: autotune over 8/16/32)")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--configs", default="1,2,3,4",
+                    help="comma-separated other workloads (1-4) timed after the main one ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-ssim", action="store_true", help="skip the measurement of eq. (2) with its SSIM term")
@@ -171,18 +174,17 @@ def main():
                                   checkpoint=sc.checkpoint, with_adam=with_adam)
         pv.size()
         reset(pv)
-        for _ in range(args.warmup):
-            pv.run()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            pv.run()
-        e1.record()
-        torch.cuda.synchronize()
-        ms_pv = e0.elapsed_time(e1) / args.steps
+        ms_pv_eager = time_graph(pv.run, args.steps, args.warmup)
+        pv.capture()
+        reset(pv)
+        ms_pv = time_graph(pv.replay, args.steps, args.warmup)
+        if pv.overflowed():
+            raise RuntimeError("per-view pair capacity overflowed during the timed steps")
         per_view = {"ms_per_step": round(ms_pv, 4), "value": round(mpix / (ms_pv * 1e-3), 2),
-                    "batched_speedup": round(ms_pv / ms, 3)}
-        log(f"[bench] per-view: {ms_pv:.3f} ms/step ({per_view['batched_speedup']}x slower than batched)")
+                    "batched_speedup": round(ms_pv / ms, 3), "eager_ms_per_step": round(ms_pv_eager, 4),
+                    "batched_speedup_vs_eager": round(ms_pv_eager / ms, 3)}
+        log(f"[bench] per-view: graph {ms_pv:.3f} ms/step ({per_view['batched_speedup']}x slower than batched), "
+            f"eager {ms_pv_eager:.3f} ms/step")
         del pv
 
     ssim = None
@@ -371,7 +373,11 @@ def main():
             f"{ms_fill:.3f} ms, initialisation of {n_new} Gaussians {ms_init:.3f} ms")
         del pc, out0
 
-    roof = roofline(step, sc, stages, work)
+    roof = roofline(step, sc, stages, work, ms)
+    others = {}
+    for idx in [int(x) for x in args.configs.split(",") if x.strip()]:
+        if idx != args.workload:
+            others[str(idx)] = bench_config(idx, args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, tile)
     out = {
         "metric": "3DGS fwd+bwd+Adam Mpix*iter/s at 1 GPU (batched HIP-graph step)",
@@ -399,10 +405,112 @@ def main():
         "stages_ms": stages,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "configs": others,
     }
     if tune is not None:
         out["autotune"] = tune
     print(json.dumps(out), flush=True)
+
+
+def time_graph(run, steps, warmup):
+    """Average ms of `run` over `steps` calls after `warmup` (HIP events on the current stream)."""
+    import torch
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_config(idx, args):
+    """One of the other workloads in its own configuration: the whole iteration its work names
+    (forward only; forward and backward; or forward, backward and Adam) replayed as one HIP graph,
+    ms/step and Mpix*iter/s; for several views also the same iteration issued view by view (as a
+    graph of per-view calls, and eagerly).  Algorithmic bytes per step as in the main workload's
+    roofline entry."""
+    import torch
+    from paper_2409_13055_amd import synthetic as S
+    from paper_2409_13055_amd import rasterizer as R
+    from paper_2409_13055_amd import autotune as A
+    from paper_2409_13055_amd import roofline as RF
+    dev = torch.device("cuda:0")
+    sc = S.make_config(idx)
+    params = R.GaussianParams.from_scene(sc, dev)
+    tune = None
+    if sc.work == "fwd":
+        tile = 16  # the forward-only workload names 16 x 16 tiles
+        target = None
+    else:
+        target = R.pack_images(sc.targets, dev)
+        tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint)
+        tile = tune["best"]
+    lrs = sc.lrs or dict(S.DEFAULT_LRS)
+    mpix = sc.total_pixels * 1e-6
+    if sc.work == "fwd":
+        rast = R.Rasterizer(sc.cameras, params.n, params.sh_degree, tile_size=tile, checkpoint=sc.checkpoint,
+                            device=dev)
+        fr = rast.forward(params)
+
+        def run_eager():
+            rast.project(params, fr)
+            rast.bin_sort(fr)
+            rast.render_fwd(fr)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            run_eager()
+        torch.cuda.current_stream().wait_stream(s)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            run_eager()
+        ms = time_graph(graph.replay, args.steps, args.warmup)
+        overflow = int(fr.d_overflow.item()) != 0
+        holder = type("H", (), {})()
+        holder.frame, holder.rast, holder.params = fr, rast, params
+        c = RF.counts(holder, sc)
+        stages = ("project", "bin_sort", "render_fwd")
+    else:
+        step = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
+                             with_adam="adam" in sc.work)
+        step.size()
+        step.capture()
+        ms = time_graph(step.replay, args.steps, args.warmup)
+        overflow = step.overflowed()
+        c = RF.counts(step, sc)
+        stages = ("project", "bin_sort", "render_fwd", "raster_bwd") + \
+            (("project_bwd_adam",) if step.fuse_adam else ("project_bwd",))
+    if overflow:
+        raise RuntimeError(f"workload {idx}: pair capacity overflowed during the timed steps")
+    b = RF.algorithmic_bytes(c)
+    alg = sum(b[k] for k in stages)
+    gbs = alg / (ms * 1e-3) / 1e9
+    out = {"workload": sc.name, "work": sc.work, "gaussians": sc.n, "views": sc.n_views,
+           "pixels_per_step": sc.total_pixels, "tile": tile, "pairs": c["M"], "ms_per_step": round(ms, 4),
+           "value": round(mpix / (ms * 1e-3), 2), "unit": "Mpix*iter/s", "step_alg_bytes": alg,
+           "step_GBps": round(gbs, 1), "step_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if tune is not None:
+        out["autotune"] = tune
+    log(f"[bench] workload {sc.name}: {ms:.4f} ms/step, {out['value']} Mpix*iter/s (tile {tile})")
+    if sc.n_views > 1 and sc.work != "fwd" and not args.no_per_view:
+        pv = R.PerViewMappingStep(params, sc.cameras, sc.targets, lrs=lrs, tile_size=tile,
+                                  checkpoint=sc.checkpoint, with_adam="adam" in sc.work)
+        pv.size()
+        ms_eager = time_graph(pv.run, args.steps, args.warmup)
+        pv.capture()
+        ms_pv = time_graph(pv.replay, args.steps, args.warmup)
+        if pv.overflowed():
+            raise RuntimeError(f"workload {idx}: per-view pair capacity overflowed")
+        out["per_view"] = {"ms_per_step": round(ms_pv, 4), "value": round(mpix / (ms_pv * 1e-3), 2),
+                           "batched_speedup": round(ms_pv / ms, 3), "eager_ms_per_step": round(ms_eager, 4),
+                           "batched_speedup_vs_eager": round(ms_eager / ms, 3)}
+        log(f"[bench]   per-view: graph {ms_pv:.4f} ms/step, eager {ms_eager:.4f} ms/step")
+        del pv
+    return out
 
 
 def stage_breakdown(step, iters):
@@ -459,40 +567,80 @@ def traffic_of(kernel, tile, checkpoint, workload):
     return e.get("bytes_per_launch")
 
 
-def roofline(step, sc, stages, work):
-    """Roofline entry for the dominant single-kernel call (by measured duration); the work counts
-    are the mean over the same iterations the durations are."""
+def roofline(step, sc, stages, work, step_ms):
+    """Roofline entry for the dominant single-kernel call (by measured duration) and for the whole
+    step; the work counts are the mean over the same iterations the durations are."""
     from paper_2409_13055_amd import roofline as RF
     tr = traffic_of("raster_bwd", step.rast.opts.tile_size, sc.checkpoint, sc.name)
-    return RF.report(step, sc, stages, hbm_peak_gbs=HBM_PEAK_GBS, valu_peak_tflops=VALU_PEAK_TFLOPS, traffic=tr,
-                     work=work)
+    return RF.report(step, sc, stages, hbm_peak_gbs=HBM_PEAK_GBS, valu_peak_tflops=VALU_PEAK_TFLOPS,
+                     valu_unpacked_tflops=VALU_UNPACKED_TFLOPS, traffic=tr, work=work, step_ms=step_ms)
 
 
-def cpu_baseline(sc, tile):
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(sc, tile, repeats=3):
     """The FP64 oracle timed on the host cores over a bounded sample of the workload: its first
-    keyframe (the first three for multi-keyframe workloads) rendered from all Gaussians (projection,
-    binning, blending, L1, backward), plus Adam over all parameters when the workload steps the
-    optimiser."""
+    keyframe rendered from all Gaussians (projection, binning, blending, L1, backward), plus Adam
+    over all parameters when the workload steps the optimiser.  Median of `repeats` runs with every
+    core of the process's CPU set, and median of `repeats` runs on one thread."""
     import oracle.oracle as O
-    n_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    k = 1 if sc.n_views == 1 else 3
-    cams, tgts = sc.cameras[:k], sc.targets[:k]
+    cams, tgts = sc.cameras[:1], sc.targets[:1]
     P = O.Params.from_scene(sc)
     opts = O.Options(tile=tile)
-    t0 = time.time()
-    fb = O.forward_backward_l1(P, cams, tgts, opts)
-    if "adam" in sc.work:
-        lrs = sc.lrs
-        for name, lr in (("means", lrs["means"]), ("log_scales", lrs["log_scales"]), ("quats", lrs["quats"]),
-                         ("opacity_logits", lrs["opacity_logits"]), ("sh", lrs["sh_dc"])):
-            p = getattr(P, name)
-            z = np.zeros_like(p)
-            O.adam_step(p, fb["grads"][name], z, z, 1, lr)
-    dt = time.time() - t0
     px = sum(c.width * c.height for c in cams)
-    return {"value": round(px * 1e-6 / dt, 4), "unit": "Mpix*iter/s", "cores": n_threads, "kind": "oracle",
-            "sample": f"{k} of {sc.n_views} keyframes ({px} px) rendered from all {sc.n} Gaussians, fwd+L1+bwd"
-                      + ("+Adam on all parameters" if "adam" in sc.work else "") + f", FP64, {dt:.1f}s"}
+
+    lrs = sc.lrs or {}
+    groups = (("means", lrs.get("means")), ("log_scales", lrs.get("log_scales")), ("quats", lrs.get("quats")),
+              ("opacity_logits", lrs.get("opacity_logits")), ("sh", lrs.get("sh_dc")))
+
+    def once():
+        # the optimiser's first step from zero moments (allocated outside the timed region); its
+        # results are dropped, so every run repeats the same iteration
+        moments = {name: (np.zeros_like(getattr(P, name)), np.zeros_like(getattr(P, name))) for name, _ in groups} \
+            if "adam" in sc.work else {}
+        t0 = time.perf_counter()
+        fb = O.forward_backward_l1(P, cams, tgts, opts)
+        for name, lr in groups:
+            if name in moments:
+                O.adam_step(getattr(P, name), fb["grads"][name], moments[name][0], moments[name][1], 1, lr)
+        return time.perf_counter() - t0
+
+    try:
+        all_cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        all_cores = os.cpu_count() or 1
+    legs = {}
+    for cores in (all_cores, 1):
+        got = O.set_threads(cores)
+        runs = [once() for _ in range(repeats)]
+        dt = float(np.median(runs))
+        legs[cores] = {"value": round(px * 1e-6 / dt, 4), "cores": got, "seconds": [round(r, 2) for r in runs]}
+        log(f"[bench] cpu baseline at {got} threads: runs {legs[cores]['seconds']} s")
+    O.set_threads(all_cores)
+    a, one = legs[all_cores], legs[1]
+    return {"value": a["value"], "unit": "Mpix*iter/s", "cores": a["cores"], "kind": "oracle",
+            "sample": f"keyframe 0 of {sc.n_views} ({px} px) rendered from all {sc.n} Gaussians, fwd+L1+bwd"
+                      + ("+Adam on all parameters" if "adam" in sc.work else "") + f", FP64, median of {repeats} "
+                      f"runs ({a['seconds']} s)",
+            "single_thread": {"value": one["value"], "cores": 1, "seconds": one["seconds"]},
+            "cpu_model": cpu_model()}
 
 
 if __name__ == "__main__":

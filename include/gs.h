@@ -3,13 +3,15 @@
  * rasteriser and its optimiser step: the data-parallel hot path of the
  * dense-reconstruction (mapping) module of MGSO (Sec. III-B).
  *
- * The mapping module renders RGB images of a set of anisotropic Gaussians,
- * each with an opacity, a rotation, a location, a scale and a colour, using
- * tile-based differentiable rasterisation (Sec. III-B), i.e. projecting the
- * Gaussians onto the camera plane, depth-sorting them and blending them front
- * to back (Sec. II), and optimises the Gaussian parameters by gradient descent
- * on a photometric loss against the captured keyframe images (eq. (2)) with
- * the default 3DGS optimiser configuration (Sec. IV-A).  Several keyframes of
+ * The mapping module renders keyframe images of a 3D Gaussian map (each
+ * Gaussian carries a position, an orientation quaternion, per-axis scales,
+ * an opacity and a colour) with the tile-based differentiable rasteriser of
+ * Sec. III-B, whose three stages (Sec. II) are a perspective projection of
+ * every Gaussian to a 2D splat, an ordering of the splats of each screen tile
+ * by depth, and front-to-back alpha compositing of each pixel.  It optimises
+ * the Gaussian parameters by gradient descent on a photometric loss against
+ * the captured keyframe images (eq. (2)) with the default 3DGS optimiser
+ * configuration (Sec. IV-A).  Several keyframes of
  * the SLAM window (eight by default, Sec. III-A) can be rendered in one call.
  *
  * Conventions shared by every call
@@ -229,7 +231,7 @@ gs_status gs_render_bwd_workspace_size(int64_t n, int32_t n_views, size_t* bytes
 
 /* --------------------------------------------------------------- hot path */
 
-/* Projection (Sec. II "projecting Gaussians onto the camera plane"; Gaussian
+/* Projection (Sec. II, first stage of the rasteriser; Gaussian
  * parameterisation of Sec. III-B).  For every Gaussian i and view v: camera
  * point t = R mean + t; cull if t_z <= near_plane; image mean; 2D covariance
  * J W Sigma W^T J^T + eps2d I with Sigma = R(q) S S^T R(q)^T (local affine
@@ -240,7 +242,7 @@ gs_status gs_render_bwd_workspace_size(int64_t n, int32_t n_views, size_t* bytes
 gs_status gs_project(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
                      const gs_projected* out, void* stream);
 
-/* Tile binning and depth sort (Sec. II "depth-sorting"; tile-based
+/* Tile binning and depth sort (Sec. II, second stage; tile-based
  * rasterisation of Sec. III-B).  Every pair with tiles_touched > 0 is
  * assigned to each tile of its rect [floor((m-r)/B), floor((m+r+B-1)/B))
  * (computed in FP32, clamped to the view's grid); the (tile, id) incidences
@@ -255,7 +257,7 @@ gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_camera* cams
                       const gs_options* opts, const gs_bins* bins, void* workspace, size_t workspace_bytes,
                       void* stream);
 
-/* Forward rasterisation (Sec. II "blending them front-to-back").  For every
+/* Forward rasterisation (Sec. II, third stage).  For every
  * pixel, over its tile's list in order: power = -(a dx^2 + c dy^2)/2 - b dx dy
  * with d = pixel - mean (skip if power > 0), alpha = min(alpha_max,
  * opacity exp(power)) (skip if alpha < alpha_min); stop before a Gaussian

@@ -1,8 +1,9 @@
 /*
  * FP64 CPU oracle for the tile-based differentiable 3D Gaussian splatting
  * rasteriser of the dense-reconstruction module (Sec. III-B) and its
- * gradient.  Rendering follows the outline of Sec. II: project every Gaussian
- * onto the camera plane, sort by depth (per screen tile), blend front to back.
+ * gradient.  Rendering takes the three stages of Sec. II: a perspective
+ * projection of each Gaussian to a 2D splat, a depth order per screen tile,
+ * and front-to-back compositing per pixel.
  * The gradient is that of the L1 term of the photometric loss, eq. (2), with
  * respect to the five per-Gaussian quantities of Sec. III-B (opacity,
  * rotation, location, scale, colour).
@@ -1310,6 +1311,18 @@ int or_find_flips(int32_t n_views, int64_t n, const OrCamera* cams, const OrOpti
       }
   }
   return 0;
+}
+
+// Thread count of the OpenMP loops (the CPU-baseline leg times the oracle at
+// one thread and at all cores); returns the count in force afterwards.
+int32_t or_set_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 }  // extern "C"

@@ -28,7 +28,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(HERE, "liboracle.so")
+# GS_ORACLE_LIB points the checker at another build of the same source (the sanitizer test's)
+_LIB_PATH = os.environ.get("GS_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 _lib = None
 
 SH_C0 = 0.5 / math.sqrt(math.pi)  # the degree-0 real spherical harmonic
@@ -115,11 +116,18 @@ def lib():
                                        P, P, P, P]
         _lib.or_sh_basis.argtypes = [i32, i64, P, P, P]
         _lib.or_quat_to_rot.argtypes = [P, P]
+        _lib.or_set_threads.argtypes = [i32]
+        _lib.or_set_threads.restype = i32
         for f in ("or_project", "or_bin", "or_render", "or_render_backward", "or_project_backward", "or_fd_local",
                   "or_render_tiles", "or_render_backward_tiles", "or_render_backward_abs", "or_bin_sampled",
                   "or_render_flips", "or_pixel_decisions", "or_render_backward_tiles_flips", "or_find_flips"):
             getattr(_lib, f).restype = C.c_int
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the oracle's OpenMP loops (n <= 0 leaves it); returns the count in force."""
+    return int(lib().or_set_threads(int(n)))
 
 
 def _p(a: np.ndarray):

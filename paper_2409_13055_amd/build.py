@@ -10,7 +10,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgs.so")
-SOURCES = ["api.hip", "project.hip", "binsort.hip", "raster.hip", "adam.hip", "loss.hip", "pyramid.hip", "density.hip", "pointcloud.hip", "autotune.hip"]
+SOURCES = ["api.hip", "project.hip", "binsort.hip", "raster.hip", "adam.hip", "loss.hip", "pyramid.hip", "density.hip", "pointcloud.hip", "autotune.hip",
+           "delaunay.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

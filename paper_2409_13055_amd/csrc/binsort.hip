@@ -1,5 +1,5 @@
-// Tile binning and depth ordering (Sec. II "depth-sorting"; the tile-based
-// rasterisation of Sec. III-B).
+// Tile binning and depth ordering (Sec. II, second stage of the rasteriser;
+// the tile-based rasterisation of Sec. III-B).
 //
 // The required order of the (tile, pair) incidences is that of a stable sort
 // on the 64-bit key (global tile << 32 | FP32 bits of the depth) of the

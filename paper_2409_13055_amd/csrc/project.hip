@@ -1,6 +1,6 @@
 // Projection of the Gaussian set onto the keyframe image planes and its
-// backward pass (Sec. II "projecting Gaussians onto the camera plane";
-// Gaussian parameterisation of Sec. III-B).
+// backward pass (Sec. II, first stage of the rasteriser; Gaussian
+// parameterisation of Sec. III-B).
 //
 // One thread per Gaussian loops over every view of the call, so the 236 bytes
 // of parameters of an SH-3 Gaussian are read from HBM once per call however

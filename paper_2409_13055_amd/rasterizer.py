@@ -572,6 +572,7 @@ class PerViewMappingStep:
         self.losses = [torch.zeros(1, dtype=torch.float32, device=dev) for _ in cameras]
         self.adam = FusedAdam(params, self.grads, lrs) if with_adam else None
         self.frames = [None] * len(cameras)
+        self.graph = None
 
     def size(self):
         for k, r in enumerate(self.rasts):
@@ -592,6 +593,20 @@ class PerViewMappingStep:
 
     def overflowed(self) -> bool:
         return any(int(fr.d_overflow.item()) != 0 for fr in self.frames)
+
+    def capture(self):
+        """Record one iteration (every view's calls, then Adam) into a HIP graph (after size())."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+
+    def replay(self):
+        self.graph.replay()
 
 
 @dataclasses.dataclass

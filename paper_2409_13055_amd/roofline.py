@@ -84,27 +84,54 @@ def alu_flops(kernel, ev):
 SINGLE_KERNEL_CALLS = ("project", "render_fwd", "raster_bwd", "project_bwd", "adam", "project_bwd_adam")
 
 
-def report(step, sc, stages_ms, hbm_peak_gbs, valu_peak_tflops, traffic=None, work=None):
-    """Roofline of the dominant single-kernel call (by measured duration).  `work`: blending work
-    counts averaged over the timed iterations (default: counted on the step's current lists)."""
+def step_bytes(b, stages):
+    """Algorithmic bytes of one iteration made of the given single-call stages."""
+    return sum(b[k] for k in stages if k in b)
+
+
+def report(step, sc, stages_ms, hbm_peak_gbs, valu_peak_tflops, valu_unpacked_tflops, traffic=None, work=None,
+           step_ms=None):
+    """Roofline of the dominant single-kernel call (by measured duration), and of the whole step.
+    `work`: blending work counts averaged over the timed iterations (default: counted on the step's
+    current lists).  The raster calls are priced against FP32 vector issue, both at the published
+    peak (which needs packed FP32 instructions) and at the rate without them; their HBM bytes are
+    listed but given no bandwidth fraction, since they stop reading a tile's list where its pixels
+    terminate.  `step_ms`: the measured time of the whole iteration (graph replay)."""
     c = counts(step, sc)
     b = algorithmic_bytes(c)
     ev = work if work is not None else evaluations(step)
     dom = max((k for k in stages_ms if k in SINGLE_KERNEL_CALLS), key=lambda k: stages_ms[k])
     ms = stages_ms[dom]
-    per_stage = {k: {"ms": stages_ms[k], "alg_bytes": b[k], "GBps": round(b[k] / (stages_ms[k] * 1e-3) / 1e9, 1)}
-                 for k in stages_ms if k in b}
+    per_stage = {}
+    for k in stages_ms:
+        if k not in b:
+            continue
+        e = {"ms": stages_ms[k], "alg_bytes": b[k]}
+        if k in ("render_fwd", "raster_bwd"):
+            e["TFLOPs"] = round(alu_flops(k, ev) / (stages_ms[k] * 1e-3) / 1e12, 3)
+        else:
+            e["GBps"] = round(b[k] / (stages_ms[k] * 1e-3) / 1e9, 1)
+            e["hbm_frac"] = round(e["GBps"] / hbm_peak_gbs, 4)
+        per_stage[k] = e
     if dom in ("render_fwd", "raster_bwd"):
         flops = alu_flops(dom, ev)
         achieved = flops / (ms * 1e-3) / 1e12
         out = {"bound": "alu", "achieved": round(achieved, 3), "peak": valu_peak_tflops, "unit": "TFLOP/s",
                "frac": round(achieved / valu_peak_tflops, 4), "traffic": traffic, "kernel": dom,
+               "peak_without_packed_fp32": valu_unpacked_tflops,
+               "frac_without_packed_fp32": round(achieved / valu_unpacked_tflops, 4),
                "flops_per_launch": flops, "evaluations": ev, "ms_per_launch": ms}
     else:
         achieved = b[dom] / (ms * 1e-3) / 1e9
         out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": hbm_peak_gbs, "unit": "GB/s",
                "frac": round(achieved / hbm_peak_gbs, 4), "traffic": traffic, "kernel": dom,
                "alg_bytes_per_launch": b[dom], "ms_per_launch": ms}
+    stages = [k for k in stages_ms if k in SINGLE_KERNEL_CALLS or k == "bin_sort"]
+    alg = step_bytes(b, stages)
+    t = step_ms if step_ms is not None else stages_ms.get("step_eager")
+    gbs = alg / (t * 1e-3) / 1e9
+    out["step"] = {"stages": stages, "alg_bytes": alg, "ms": round(t, 4), "GBps": round(gbs, 1),
+                   "hbm_frac": round(gbs / hbm_peak_gbs, 4)}
     out["stages"] = per_stage
     out["counts"] = c
     return out
