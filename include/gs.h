@@ -140,7 +140,9 @@ void gs_default_options(gs_options* opts);
  * plane, degenerate, opacity <= alpha_min (1 - 1e-3), or no tile touched).
  * flags bits 0-2: colour channel clamped at 0; bits 3-4: frustum guard active
  * in x / y.  tiles_touched [n_views*n] = tile count of the pair's rect (0 when
- * culled).
+ * culled).  gs_project writes the record of a visible pair (tiles_touched > 0)
+ * only: the row of a culled pair keeps whatever it held, and no call reads it
+ * (every later stage reaches records through the tile lists).
  * vis, vis_count: the visible pairs (tiles_touched > 0) compacted by blocks of
  * 64 Gaussians, the hand-off from gs_project to gs_bin_sort.  With
  * S = ceil(n/64) segments per view, segment s = v*S + b holds the visible
@@ -236,9 +238,9 @@ gs_status gs_render_bwd_workspace_size(int64_t n, int32_t n_views, size_t* bytes
  * point t = R mean + t; cull if t_z <= near_plane; image mean; 2D covariance
  * J W Sigma W^T J^T + eps2d I with Sigma = R(q) S S^T R(q)^T (local affine
  * approximation of the perspective map, frustum guard on x/z and y/z);
- * conic; radius; tile rect; colour; opacity; writes out->rec and
- * out->tiles_touched for all n_views*n pairs, and the visible pairs' entries
- * to out->vis / out->vis_count.  Parameters are read once for all views. */
+ * conic; radius; tile rect; colour; opacity; writes out->tiles_touched for
+ * all n_views*n pairs, out->rec for the visible ones (tiles_touched > 0), and
+ * the visible pairs' entries to out->vis / out->vis_count.  Parameters are read once for all views. */
 gs_status gs_project(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,
                      const gs_projected* out, void* stream);
 

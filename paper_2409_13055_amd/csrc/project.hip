@@ -283,13 +283,13 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
   for (int v = 0; v < a.n_views; ++v) {
     const CamF& cam = cams.c[v];
     Proj2D p;
-    bool ok = g.ok && project_view(g, cam, a.near_plane, a.eps2d, p);
-    ok = ok && opaque_enough;
+    // a Gaussian too transparent to ever blend is culled before its projection is computed
+    bool ok = g.ok && opaque_enough && project_view(g, cam, a.near_plane, a.eps2d, p);
     int packed = 0, tiles = 0;
     int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
     float rgb[3] = {0.f, 0.f, 0.f};
     uint32_t flags = 0;
-    const float fmx = (float)p.mx, fmy = (float)p.my;
+    const float fmx = ok ? (float)p.mx : 0.f, fmy = ok ? (float)p.my : 0.f;
     if (ok) {
       const real mid = 0.5 * (p.a + p.c);
       const real lam = mid + sqrt(fmax(mid * mid - (p.a * p.c - p.b * p.b), 0.0));
@@ -324,15 +324,14 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
       if (p.cly) flags |= 1u << 4;
     }
     const int64_t row = (int64_t)v * a.n + i;
-    float4* out = reinterpret_cast<float4*>(rec + row * GS_REC_FLOATS);
+    // only a visible pair's record is written: every later stage reads records through the tile
+    // lists, and most pairs of a multi-view batch are culled, so their 48 bytes would be write
+    // traffic nobody reads
     if (ok) {
+      float4* out = reinterpret_cast<float4*>(rec + row * GS_REC_FLOATS);
       out[0] = make_float4(fmx, fmy, (float)p.ca, (float)p.cb);
       out[1] = make_float4((float)p.cc, op, rgb[0], rgb[1]);
       out[2] = make_float4(rgb[2], (float)p.t[2], __int_as_float(packed), __uint_as_float(flags));
-    } else {
-      out[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-      out[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-      out[2] = make_float4(0.f, 0.f, __int_as_float(0), __uint_as_float(0u));
     }
     tiles_touched[row] = tiles;
     const uint64_t bal = __ballot(ok);

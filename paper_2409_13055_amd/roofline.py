@@ -8,7 +8,7 @@ gs_render_stats), because those kernels are bound by vector ALU issue, not
 by HBM.
 
 Per-unit figures (P_n = 11 + 3K raw floats per Gaussian, K = (D+1)^2):
-  project     N*4*P_n + V*N*(48 + 4) + Nv*16 + S*4 [visible-pair entries, segment counts]
+  project     N*4*P_n + V*N*4 [tiles_touched] + Nv*(48 + 16) [visible records and entries] + S*4 [segment counts]
   bin_sort    S*4 [segment counts] + Nv*16 [visible-pair entries] + M*4 [ids] + T*8 [ranges]
   render_fwd  Nv*36 + M*4 + Px*(12 + 12 [target] + 8 [T_final, n_contrib unless checkpoint])
   raster_bwd  Px*(12 [image] + 12 [target]) + Nv*36 [records] + M*4 + Nv*36 [gradients]
@@ -60,7 +60,7 @@ def algorithmic_bytes(c):
     raster_bwd = Px * 24 + Nv * 36 + M * 4 + Nv * 36
     project_bwd = N * 12 * Pn + V * N * 52
     return {
-        "project": N * 4 * Pn + V * N * 52 + Nv * 16 + S * 4,
+        "project": N * 4 * Pn + V * N * 4 + Nv * (48 + 16) + S * 4,
         "bin_sort": S * 4 + Nv * 16 + M * 4 + T * 8,
         "render_fwd": Nv * 36 + M * 4 + Px * (24 + saved),
         "raster_bwd": raster_bwd,

@@ -32,7 +32,11 @@ def run_gpu(sc, tile=16, checkpoint=False, backward=True, want_keys=True, capaci
         rast.reserve(capacity)
     target = R.pack_images(sc.targets, DEV) if sc.targets is not None else None
     loss = torch.zeros(len(cams), device=DEV)
-    fr = rast.forward(params, target=target, loss_out=loss if target is not None else None)
+    # gs_project leaves the records of culled pairs unwritten and nothing may read them: NaN there
+    # would reach every output that did
+    fr = rast.new_frame()
+    fr.rec.fill_(float("nan"))
+    fr = rast.forward(params, fr, target=target, loss_out=loss if target is not None else None)
     out = dict(params=params, rast=rast, frame=fr)
     if backward:
         grads = params.zeros_like()
@@ -47,8 +51,10 @@ def run_gpu(sc, tile=16, checkpoint=False, backward=True, want_keys=True, capaci
     torch.cuda.synchronize()
     m = int(fr.d_num_pairs.item())
     out["m"] = m
-    out["rec"] = fr.rec.view(-1, 12).cpu().numpy()
     out["tiles"] = fr.tiles.cpu().numpy()
+    rec = fr.rec.view(-1, 12).cpu().numpy()
+    rec[out["tiles"] == 0] = 0.0  # culled pairs' rows are unwritten: read them as zero (extents 0)
+    out["rec"] = rec
     out["ids"] = fr.ids[:m].cpu().numpy().view(np.uint32)
     out["keys"] = fr.keys[:m].cpu().numpy().view(np.uint64) if fr.keys is not None else None
     out["ranges"] = fr.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
