@@ -496,6 +496,24 @@ def bench_config(idx, args):
     if tune is not None:
         out["autotune"] = tune
     log(f"[bench] workload {sc.name}: {ms:.4f} ms/step, {out['value']} Mpix*iter/s (tile {tile})")
+    if not args.no_cpu_baseline:
+        # the oracle on the whole workload (every view), one run with every core of the process
+        import oracle.oracle as O
+        P = O.Params.from_scene(sc)
+        opts = O.Options(tile=tile)
+        t0 = time.perf_counter()
+        if sc.work == "fwd":
+            O.forward(P, sc.cameras, opts)
+        else:
+            fb = O.forward_backward_l1(P, sc.cameras, sc.targets, opts)
+            if "adam" in sc.work:
+                for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+                    z = np.zeros_like(getattr(P, name))
+                    O.adam_step(getattr(P, name), fb["grads"][name], z, z, 1, 1e-3)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": round(mpix / dt, 4), "unit": "Mpix*iter/s", "seconds": round(dt, 2),
+                             "cores": O.set_threads(0), "kind": "oracle", "sample": "the whole workload, one run"}
+        log(f"[bench]   oracle: {dt:.2f} s ({out['cpu_oracle']['value']} Mpix*iter/s)")
     if sc.n_views > 1 and sc.work != "fwd" and not args.no_per_view:
         pv = R.PerViewMappingStep(params, sc.cameras, sc.targets, lrs=lrs, tile_size=tile,
                                   checkpoint=sc.checkpoint, with_adam="adam" in sc.work)
