@@ -31,28 +31,39 @@ struct RasterConsts {
 };
 
 // The per-pixel exponent power = -(a dx^2 + c dy^2)/2 - b dx dy, d = pixel -
-// mean, is evaluated in base 2: the conic is scaled by log2(e) when an entry is
-// staged (kLog2e below), so power2 = log2(e) power and alpha = o exp2(power2)
-// with no multiply per pixel.  One fixed rounding sequence, ((-c'/2) dy - b' dx)
-// dy + (-a'/2) dx^2 with the scaled coefficients (the dx terms shared by the PPL
-// pixels of a lane's column), makes every kernel take identical decisions.
+// mean, is evaluated in base 2 and with the opposite sign: the conic is scaled
+// by log2(e) when an entry is staged (kLog2e below), and the kernels form
+// q = -log2(e) power >= 0, so alpha = o exp2(-q) with no multiply per pixel.
+// One fixed rounding sequence, ((c'/2) dy + b' dx) dy + (a'/2) dx^2 with the
+// scaled coefficients (the dx terms shared by the PPL pixels of a lane's
+// column), makes every kernel take identical decisions.  Rounding is symmetric,
+// so q is exactly -log2(e) power as the opposite signs would give it, except
+// that an exact zero comes out as +0.  With q >= 0 the test "power in
+// [cutoff, 0]" is one unsigned comparison of bit patterns: bits(q) <=
+// bits(qmax) for a staged qmax >= 0 holds exactly for +0 <= q <= qmax, and
+// fails for a negative q (power > 0), +inf and NaN.
 struct RowTerms {
-  float a2x, nbx;  // -a dx^2 / 2 and -b dx
+  float a2x, bx;  // a dx^2 / 2 and b dx (scaled)
 };
-__device__ __forceinline__ RowTerms row_terms(float dx, float a2, float nb) {
+__device__ __forceinline__ RowTerms row_terms(float dx, float a2, float b) {
 #pragma clang fp contract(off)
-  return RowTerms{(a2 * dx) * dx, nb * dx};
+  return RowTerms{(a2 * dx) * dx, b * dx};
 }
-__device__ __forceinline__ float splat_power(const RowTerms& t, float c2, float dy) {
+__device__ __forceinline__ float splat_q(const RowTerms& t, float c2, float dy) {
 #pragma clang fp contract(off)
-  return fmaf(fmaf(c2, dy, t.nbx), dy, t.a2x);
+  return fmaf(fmaf(c2, dy, t.bx), dy, t.a2x);
+}
+__device__ __forceinline__ bool q_in_range(float q, float qmax) {
+  return __float_as_uint(q) <= __float_as_uint(qmax);
 }
 
 // Below this (natural) exponent opacity * exp(power) < alpha_min is certain:
 // the 1e-3 margin in the exponent covers the rounding of the logarithm, of the
 // base-2 scaling, of exp2 and of the product, so skipping such entries before
-// exp2 changes no decision.  Opacity 0 gives +inf (every entry is skipped), NaN
-// skips every pixel.
+// exp2 changes no decision.  The staged bound is qmax = max(0, -log2(e)
+// cutoff): an entry whose opacity is below alpha_min, or NaN, keeps only q = +0,
+// where alpha = opacity fails the alpha_min test (and the wave-level cull has
+// already dropped it).
 __device__ __forceinline__ float power_cutoff(float opacity, float alpha_min) {
   return __logf(alpha_min / opacity) - 1.0e-3f;
 }
@@ -272,8 +283,8 @@ struct BlockBoxes {
 // the ordered list of the batch entries its pixel block can see.
 template <class PM>
 struct BatchLds {
-  float4 a[PM::NT];  // (mean x, mean y, -a'/2, -b') for the conic (a, b, c), ' = times log2(e)
-  float4 b[PM::NT];  // (-c'/2, opacity, exponent cutoff times log2(e), r)
+  float4 a[PM::NT];  // (mean x, mean y, a'/2, b') for the conic (a, b, c), ' = times log2(e)
+  float4 b[PM::NT];  // (c'/2, opacity, qmax (the exponent cutoff as a bound on q), r)
   float2 c[PM::NT];  // (g, b)
   uint32_t id[PM::NT];
   uint16_t list[PM::WAVES][PM::NT];
@@ -292,8 +303,8 @@ __device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBox
   if (ld.valid) {
     const float cut = power_cutoff(ld.b.y, alpha_min);
     mask = bx.mask(ld.a.x, ld.a.y, cull_conic(ld.a.z, ld.a.w, ld.b.x, ld.b.y, alpha_min, -2.0f * cut));
-    L.a[t] = make_float4(ld.a.x, ld.a.y, (-0.5f * kLog2e) * ld.a.z, -kLog2e * ld.a.w);
-    L.b[t] = make_float4((-0.5f * kLog2e) * ld.b.x, ld.b.y, kLog2e * cut, ld.b.z);
+    L.a[t] = make_float4(ld.a.x, ld.a.y, (0.5f * kLog2e) * ld.a.z, kLog2e * ld.a.w);
+    L.b[t] = make_float4((0.5f * kLog2e) * ld.b.x, ld.b.y, fmaxf(-kLog2e * cut, 0.0f), ld.b.z);
     L.c[t] = make_float2(ld.b.w, ld.c.x);
     if (with_id) L.id[t] = ld.id;
   }
@@ -325,8 +336,8 @@ __device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBox
 // ---------------------------------------------------------------------------
 // Forward.
 // ---------------------------------------------------------------------------
-// A pixel that has stopped gets row coordinate +inf: its exponent is then
-// -inf or NaN and fails the cutoff test, so no separate flag is tested.
+// A pixel that has stopped gets row coordinate +inf: its q is then +inf or
+// NaN and fails the range test, so no separate flag is tested.
 // STATE: the pixel state (T_final, n_contrib) is written (not under the checkpoint flag).
 // (six wavefronts per SIMD: measured faster than five, despite a few bytes of spill outside the loop)
 template <int TILE, bool STATE>
@@ -373,11 +384,11 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_wave
       const RowTerms rt = row_terms(fx - A.x, A.z, A.w);
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        const float power = splat_power(rt, Bv.x, fy[p] - A.y);
+        const float q = splat_q(rt, Bv.x, fy[p] - A.y);
         // only an exponent in [cutoff, 0] can reach alpha_min; the wave skips a pixel slot no lane reaches
-        if (!(power >= Bv.z && power <= 0.0f)) continue;
+        if (!q_in_range(q, Bv.z)) continue;
         // the rest is branch-free: a pixel that does not blend gets weight 0, which adds exactly nothing
-        const float oG = Bv.y * __builtin_amdgcn_exp2f(power);
+        const float oG = Bv.y * __builtin_amdgcn_exp2f(-q);
         const float alpha = oG <= amax ? oG : amax;  // min(alpha_max, oG), also for NaN
         const float test = T[p] * (1.0f - alpha);
         const bool keep = alpha >= rc.alpha_min;
@@ -606,18 +617,18 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
       const float dx = fx - A.x;
       const RowTerms rt = row_terms(dx, A.z, A.w);
       // the natural conic (a, b, c) from the staged base-2 factors
-      const float ca = (-2.0f * kLn2) * A.z, cb = -kLn2 * A.w, cc = (-2.0f * kLn2) * Bv.x;
+      const float ca = (2.0f * kLn2) * A.z, cb = kLn2 * A.w, cc = (2.0f * kLn2) * Bv.x;
       const float tx = ABS ? ca * dx : 0.0f, ty = ABS ? cb * dx : 0.0f;
       bool any = false;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         const float dy = fy[p] - A.y;
-        const float power = splat_power(rt, Bv.x, dy);
+        const float q = splat_q(rt, Bv.x, dy);
         // only an exponent in [cutoff, 0] can reach alpha_min; the wave skips a pixel slot no lane reaches
-        if (!(power >= Bv.z && power <= 0.0f)) continue;
+        if (!q_in_range(q, Bv.z)) continue;
         // the rest is branch-free: a pixel that does not blend gets weight 0 and no exponent
         // gradient, which add exactly nothing (every factor is finite: 1 - alpha >= 1 - alpha_max)
-        const float oG = Bv.y * __builtin_amdgcn_exp2f(power);
+        const float oG = Bv.y * __builtin_amdgcn_exp2f(-q);
         const bool below = oG <= amax;
         const float alpha = below ? oG : amax;  // min(alpha_max, oG), also for NaN
         const float om = 1.0f - alpha;
@@ -701,8 +712,8 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) void k_render_stats(
     if (__syncthreads_count(alive) == 0) break;
     ld.fetch(rec, ids, base + (int)threadIdx.x, s, e);
     if (ld.valid) {
-      s_a[threadIdx.x] = make_float4(ld.a.x, ld.a.y, (-0.5f * kLog2e) * ld.a.z, -kLog2e * ld.a.w);
-      s_b[threadIdx.x] = make_float2((-0.5f * kLog2e) * ld.b.x, ld.b.y);
+      s_a[threadIdx.x] = make_float4(ld.a.x, ld.a.y, (0.5f * kLog2e) * ld.a.z, kLog2e * ld.a.w);
+      s_b[threadIdx.x] = make_float2((0.5f * kLog2e) * ld.b.x, ld.b.y);
     }
     __syncthreads();
     const int cnt = min(NT, e - base);
@@ -714,9 +725,9 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) void k_render_stats(
       for (int p = 0; p < PPL; ++p) {
         if (done[p]) continue;
         ++evals[p];
-        const float power = splat_power(rt, geo.x, fy[p] - cu.y);
-        if (power > 0.0f) continue;
-        const float oG = geo.y * __builtin_amdgcn_exp2f(power);
+        const float q = splat_q(rt, geo.x, fy[p] - cu.y);
+        if (q < 0.0f) continue;  // power > 0
+        const float oG = geo.y * __builtin_amdgcn_exp2f(-q);
         const float alpha = oG <= amax ? oG : amax;  // min(alpha_max, oG), also for NaN
         if (!(alpha >= rc.alpha_min)) continue;
         const float test = T[p] * (1.0f - alpha);
