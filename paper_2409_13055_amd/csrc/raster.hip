@@ -285,7 +285,7 @@ template <class PM>
 struct BatchLds {
   float4 a[PM::NT];  // (mean x, mean y, a'/2, b') for the conic (a, b, c), ' = times log2(e)
   float4 b[PM::NT];  // (c'/2, opacity, qmax (the exponent cutoff as a bound on q), r)
-  float2 c[PM::NT];  // (g, b)
+  float4 c[PM::NT];  // (g, b, unused, unused): 16-byte rows, so one index scale serves all three arrays
   uint32_t id[PM::NT];
   uint16_t list[PM::WAVES][PM::NT];
   int cnt[PM::WAVES][PM::WAVES];  // [staging wave][listing wave]
@@ -305,7 +305,7 @@ __device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBox
     mask = bx.mask(ld.a.x, ld.a.y, cull_conic(ld.a.z, ld.a.w, ld.b.x, ld.b.y, alpha_min, -2.0f * cut));
     L.a[t] = make_float4(ld.a.x, ld.a.y, (0.5f * kLog2e) * ld.a.z, kLog2e * ld.a.w);
     L.b[t] = make_float4((0.5f * kLog2e) * ld.b.x, ld.b.y, fmaxf(-kLog2e * cut, 0.0f), ld.b.z);
-    L.c[t] = make_float2(ld.b.w, ld.c.x);
+    L.c[t] = make_float4(ld.b.w, ld.c.x, 0.0f, 0.0f);
     if (with_id) L.id[t] = ld.id;
   }
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -375,12 +375,13 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_wave
     const int n = stage_batch<PM>(ld, boxes, rc.alpha_min, L, false);
     ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);  // next batch, in flight during this one
     // a wavefront whose pixels have all stopped only keeps the block's barriers
-    const int cnt = __ballot(alive) != 0ull ? n : 0;
+    // (wave-uniform: kept in a scalar register, so the walk's loop control is scalar)
+    const int cnt = __builtin_amdgcn_readfirstlane(__ballot(alive) != 0ull ? n : 0);
     for (int k = 0; k < cnt; ++k) {
       const int j = L.list[w][k];
       const float4 A = L.a[j];
       const float4 Bv = L.b[j];
-      const float2 Cv = L.c[j];
+      const float2 Cv = make_float2(L.c[j].x, L.c[j].y);
       const RowTerms rt = row_terms(fx - A.x, A.z, A.w);
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
@@ -608,12 +609,13 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
     if (__syncthreads_count(alive) == 0) break;
     const int n = stage_batch<PM>(ld, boxes, rc.alpha_min, L, true);
     ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);  // next batch, in flight during this one
-    const int cnt = __ballot(alive) != 0ull ? n : 0;
+    // (wave-uniform: kept in a scalar register, so the walk's loop control is scalar)
+    const int cnt = __builtin_amdgcn_readfirstlane(__ballot(alive) != 0ull ? n : 0);
     for (int k = 0; k < cnt; ++k) {
       const int j = L.list[w][k];
       const float4 A = L.a[j];
       const float4 Bv = L.b[j];
-      const float2 Cv = L.c[j];
+      const float2 Cv = make_float2(L.c[j].x, L.c[j].y);
       const float dx = fx - A.x;
       const RowTerms rt = row_terms(dx, A.z, A.w);
       // the natural conic (a, b, c) from the staged base-2 factors
