@@ -511,7 +511,7 @@ def bench_config(idx, args):
                     z = np.zeros_like(getattr(P, name))
                     O.adam_step(getattr(P, name), fb["grads"][name], z, z, 1, 1e-3)
         dt = time.perf_counter() - t0
-        out["cpu_oracle"] = {"value": round(mpix / dt, 4), "unit": "Mpix*iter/s", "seconds": round(dt, 2),
+        out["cpu_oracle"] = {"value": round(mpix / dt, 4), "unit": "Mpix*iter/s", "seconds": round(dt, 4),
                              "cores": O.set_threads(0), "kind": "oracle", "sample": "the whole workload, one run"}
         log(f"[bench]   oracle: {dt:.2f} s ({out['cpu_oracle']['value']} Mpix*iter/s)")
     if sc.n_views > 1 and sc.work != "fwd" and not args.no_per_view:
