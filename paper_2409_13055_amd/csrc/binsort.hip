@@ -115,17 +115,29 @@ __global__ __launch_bounds__(kSortThreads) void k_segment_totals(const uint32_t*
 }
 
 // Exclusive scan of the per-block partials in place (single block);
-// total -> *total_u32 (0 when above cap32).
+// total -> *total_u32 (0 when above cap32).  Each thread takes kScanItems
+// consecutive values per round, so a round covers kScanItems blocks' worth of
+// values with one block-wide scan.
+constexpr int kScanItems = 8;
 __global__ __launch_bounds__(kSortThreads) void k_scan_partials(uint64_t* __restrict__ partial, int nb,
                                                                 uint32_t* __restrict__ total_u32, uint64_t cap32) {
   __shared__ uint64_t s_w[4];
   uint64_t carry = 0;
-  for (int base = 0; base < nb; base += kSortThreads) {
-    const int i = base + threadIdx.x;
-    const uint64_t v = i < nb ? partial[i] : 0;
+  for (int base = 0; base < nb; base += kSortThreads * kScanItems) {
+    const int i0 = base + (int)threadIdx.x * kScanItems;
+    uint64_t v[kScanItems], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      v[k] = i0 + k < nb ? partial[i0 + k] : 0;
+      sum += v[k];
+    }
     uint64_t tot;
-    const uint64_t ex = block_exclusive_scan<uint64_t>(v, s_w, tot);
-    if (i < nb) partial[i] = carry + ex;
+    uint64_t run = carry + block_exclusive_scan<uint64_t>(sum, s_w, tot);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (i0 + k < nb) partial[i0 + k] = run;
+      run += v[k];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) *total_u32 = carry > cap32 ? 0u : (uint32_t)carry;
@@ -182,6 +194,21 @@ __global__ __launch_bounds__(kSortThreads) void k_compact_segments(const uint4* 
 // stable block-local ranking (wavefront ballots + per-wave digit counts in
 // LDS) and scatter.
 // ---------------------------------------------------------------------------
+// One count of digit d into the block histogram h.  When every active lane of
+// the wavefront holds the same digit (the top digit of depths spanning a
+// narrow range, for instance), the first of them adds them all with one
+// atomic: 64 lanes on one LDS word would otherwise serialise.
+__device__ __forceinline__ void hist_add(uint32_t* h, uint32_t d) {
+  const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+  const uint64_t active = __ballot(1);
+  if (__ballot(d != d0) == 0ull) {
+    if ((int)(threadIdx.x & 63) == __ffsll((unsigned long long)active) - 1)
+      atomicAdd(&h[d0], (uint32_t)__popcll(active));
+  } else {
+    atomicAdd(&h[d], 1u);
+  }
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ d_count, int shift, int nb,
                                                              uint32_t* __restrict__ hist) {
@@ -197,9 +224,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
 #pragma unroll
     for (int u = 0; u < U; ++u) k[u] = keys[i + (uint64_t)u * kSortThreads];
 #pragma unroll
-    for (int u = 0; u < U; ++u) atomicAdd(&h[(k[u] >> shift) & (kRadixBins - 1)], 1u);
+    for (int u = 0; u < U; ++u) hist_add(h, (k[u] >> shift) & (kRadixBins - 1));
   }
-  for (; i < c.end; i += kSortThreads) atomicAdd(&h[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
+  for (; i < c.end; i += kSortThreads) hist_add(h, (keys[i] >> shift) & (kRadixBins - 1));
   __syncthreads();
   hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
@@ -433,15 +460,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_step_counts(uint64_t* __r
   __shared__ uint64_t s_w[kScanThreads / 64];
   const uint32_t nsteps = (*d_k + kStep - 1) / kStep;
   uint64_t carry_w = 0, carry_t = 0;
-  for (uint32_t base = 0; base < nsteps; base += kScanThreads) {
-    const uint32_t i = base + threadIdx.x;
-    const uint64_t vw = i < nsteps ? step_win[i] : 0, vtl = i < nsteps ? step_tiles[i] : 0;
+  for (uint32_t base = 0; base < nsteps; base += kScanThreads * kScanItems) {
+    const uint32_t i0 = base + threadIdx.x * kScanItems;
+    uint64_t vw[kScanItems], vtl[kScanItems], sw = 0, stl = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      vw[k] = i0 + k < nsteps ? step_win[i0 + k] : 0;
+      vtl[k] = i0 + k < nsteps ? step_tiles[i0 + k] : 0;
+      sw += vw[k];
+      stl += vtl[k];
+    }
     uint64_t tw, tt;
-    const uint64_t ew = block_exclusive_scan<uint64_t, kScanThreads>(vw, s_w, tw);
-    const uint64_t et = block_exclusive_scan<uint64_t, kScanThreads>(vtl, s_w, tt);
-    if (i < nsteps) {
-      step_win[i] = carry_w + ew;
-      step_tiles[i] = carry_t + et;
+    uint64_t rw = carry_w + block_exclusive_scan<uint64_t, kScanThreads>(sw, s_w, tw);
+    uint64_t rt = carry_t + block_exclusive_scan<uint64_t, kScanThreads>(stl, s_w, tt);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (i0 + k < nsteps) {
+        step_win[i0 + k] = rw;
+        step_tiles[i0 + k] = rt;
+      }
+      rw += vw[k];
+      rt += vtl[k];
     }
     carry_w += tw;
     carry_t += tt;
@@ -747,14 +786,25 @@ __global__ __launch_bounds__(kScanThreads) void k_ranges_from_counts(int total_t
     return;
   }
   uint64_t carry = 0;
-  for (int base = 0; base < total_tiles; base += kScanThreads) {
-    const int t = base + threadIdx.x;
-    const uint32_t cnt = t < total_tiles ? tile_count[t] : 0u;
+  for (int base = 0; base < total_tiles; base += kScanThreads * kScanItems) {
+    const int t0 = base + (int)threadIdx.x * kScanItems;
+    uint32_t cnt[kScanItems];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      cnt[k] = t0 + k < total_tiles ? tile_count[t0 + k] : 0u;
+      sum += cnt[k];
+    }
     uint64_t tot;
-    const uint64_t ex = carry + block_exclusive_scan<uint64_t, kScanThreads>(cnt, s_w, tot);
-    if (t < total_tiles) {
-      ranges[2 * t] = cnt ? (uint32_t)ex : 0u;
-      ranges[2 * t + 1] = cnt ? (uint32_t)(ex + cnt) : 0u;
+    uint64_t ex = carry + block_exclusive_scan<uint64_t, kScanThreads>(sum, s_w, tot);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int t = t0 + k;
+      if (t < total_tiles) {
+        ranges[2 * t] = cnt[k] ? (uint32_t)ex : 0u;
+        ranges[2 * t + 1] = cnt[k] ? (uint32_t)(ex + cnt[k]) : 0u;
+      }
+      ex += cnt[k];
     }
     carry += tot;
   }
