@@ -220,9 +220,16 @@ def main():
         ms_l = e0.elapsed_time(e1) / args.steps
         alg = 36 * sc.total_pixels  # image and target read, dL/dimage written: 12 bytes per pixel each
         gbs = alg / (ms_l * 1e-3) / 1e9
+        # FP32 arithmetic of the separable 11-tap window per pixel and channel (an FMA counts 2; the
+        # halo rows the tiles recompute are not counted): forward 5 maps x (11 + 11) FMA + 3 products
+        # + ~22 for S and its partials; backward 3 maps x (11 + 11) FMA + ~8 to combine them
+        flops = (5 * 22 * 2 + 3 + 22 + 3 * 22 * 2 + 8) * 3 * sc.total_pixels
+        tfs = flops / (ms_l * 1e-3) / 1e12
         ssim = {"lambda": lam, "ms_per_step": round(ms_s, 4), "value": round(mpix / (ms_s * 1e-3), 2),
                 "loss_call_ms": round(ms_l, 4), "loss_alg_bytes": alg, "loss_GBps": round(gbs, 1),
-                "loss_hbm_frac": round(gbs / 8000.0, 4)}
+                "loss_hbm_frac": round(gbs / 8000.0, 4), "loss_flops": flops, "loss_TFLOPs": round(tfs, 2),
+                "loss_alu_frac": round(tfs / VALU_PEAK_TFLOPS, 4),
+                "loss_alu_frac_without_packed_fp32": round(tfs / VALU_UNPACKED_TFLOPS, 4)}
         log(f"[bench] with SSIM (lambda {lam}): {ms_s:.3f} ms/step; loss call {ms_l:.3f} ms ({gbs:.0f} GB/s alg)")
         del st
 
