@@ -228,10 +228,14 @@ __device__ inline bool project_view(const GaussCov& g, const CamF& cam, real nea
 
 // Unit viewing direction from the camera centre to the mean (d) and
 // 1/|mean - centre| (il).  Shared by the projection and its backward, whose
-// colour-clamp decisions must agree.
-__device__ inline void view_dir(const GaussCov& g, const CamF& cam, real d[3], real& il) {
-  const real dx = g.m[0] - (real)cam.centre[0], dy = g.m[1] - (real)cam.centre[1], dz = g.m[2] - (real)cam.centre[2];
-  il = 1.0 / sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+// colour-clamp decisions must agree.  The offset is formed in FP64 (a camera
+// far from the scene keeps its digits) and normalised in FP32: the direction
+// only feeds the FP32 colour evaluation and the colour's share of the mean
+// gradient.
+__device__ inline void view_dir(const GaussCov& g, const CamF& cam, float d[3], float& il) {
+  const float dx = (float)(g.m[0] - (real)cam.centre[0]), dy = (float)(g.m[1] - (real)cam.centre[1]),
+              dz = (float)(g.m[2] - (real)cam.centre[2]);
+  il = rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
   d[0] = dx * il;
   d[1] = dy * il;
   d[2] = dz * il;
@@ -307,10 +311,10 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
       }
     }
     if (ok) {
-      real d[3], il;
+      float d[3], il;
       view_dir(g, cam, d, il);
       float Y[16];
-      sh_basis(D, (float)d[0], (float)d[1], (float)d[2], Y);
+      sh_basis(D, d[0], d[1], d[2], Y);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         float s = sh_channel<K>([&](int k, int ch) { return sh[k][ch]; }, Y, c);
@@ -491,11 +495,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
       gop += g2[5];
       // colour -> SH coefficients and the viewing direction; a channel clamped at 0 in the
       // projection (same arithmetic as there) passes no gradient
-      real d[3], il;
+      float d[3], il;
       view_dir(g, cam, d, il);
-      const real dx = d[0], dy = d[1], dz = d[2];
+      const float dx = d[0], dy = d[1], dz = d[2];
       float Y[16], acoef[16];
-      sh_basis(D, (float)dx, (float)dy, (float)dz, Y);
+      sh_basis(D, dx, dy, dz, Y);
       const auto coef = [&](int k, int ch) { return (k == 0 ? shd : shr + (k - 1) * 3)[ch]; };
       const float wr = sh_channel<K>(coef, Y, 0) < 0.0f ? 0.f : (float)g2[6];
       const float wg = sh_channel<K>(coef, Y, 1) < 0.0f ? 0.f : (float)g2[7];
@@ -510,8 +514,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
       }
       if (D > 0) {
         float gdx, gdy, gdz;
-        sh_grad_dot(D, (float)dx, (float)dy, (float)dz, acoef, gdx, gdy, gdz);
-        const real dd = gdx * dx + gdy * dy + gdz * dz;
+        sh_grad_dot(D, dx, dy, dz, acoef, gdx, gdy, gdz);
+        const float dd = gdx * dx + gdy * dy + gdz * dz;
         gm[0] += (gdx - dx * dd) * il;
         gm[1] += (gdy - dy * dd) * il;
         gm[2] += (gdz - dz * dd) * il;
