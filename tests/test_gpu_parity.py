@@ -97,6 +97,35 @@ def test_forward_backward_parity_two_views(tile):
     U.compare_grads(g["grads"], O.project_backward(P, sc.cameras, opts, g2_ref), 1e-3, "end-to-end")
 
 
+@pytest.mark.parametrize("tile", [8, 32])
+def test_the_most_views_of_ragged_sizes(tile):
+    """GS_MAX_VIEWS (32) views in one call, every one of another size that is not a multiple of the tile
+    or of the 8-tile binning window (one pixel wide and tall among them), from scattered camera centres:
+    projection, bins (bit-exact), image and image-space gradients against the oracle."""
+    from paper_2409_13055_amd import _lib as L
+    rng = np.random.default_rng(41)
+    sizes = [(1, 1), (1, 37), (29, 1)] + [(int(rng.integers(3, 150)), int(rng.integers(3, 120)))
+                                          for _ in range(L.GS_MAX_VIEWS - 3)]
+    cams = []
+    for w, h in sizes:
+        eye = (rng.uniform(-0.4, 0.4), rng.uniform(-0.4, 0.4), rng.uniform(-0.8, -0.2))
+        cams.append(S.pinhole(w, h, max(0.9 * max(w, h), 1.0), *S.look_at(eye, (0.0, 0.0, 3.0))))
+    sc = S.make_scene(43 + tile, 1500, 1, cams, "box", log_scale_mu=-3.0, log_scale_sigma=0.8, logit_sigma=1.5)
+    opts = O.Options(tile=tile)
+    g = U.run_gpu(sc, tile=tile)
+    assert g["m"] > 0
+    check_projection(sc, g, opts)
+    check_bins(sc, g, tile)
+    check_image_pinned(sc, g, opts)
+    np.testing.assert_allclose(g["loss"], O.l1_loss_per_view(g["image"], sc.targets, sc.cameras), rtol=1e-5)
+    orec = U.gpu_rec_to_oracle(g["rec"])
+    _, dl = O.l1_loss(g["image"], sc.targets, sc.cameras)
+    g2_ref, mag = O.render_backward_mag(sc.cameras, opts, orec, g["ids"], g["ranges"], dl)
+    U.compare_grad2d(g["grad2d"], g2_ref, msg=f"{L.GS_MAX_VIEWS} views, tile {tile}", mag=mag)
+    P = O.Params.from_scene(sc)
+    U.compare_grads(g["grads"], O.project_backward(P, sc.cameras, opts, g["grad2d"]), 1e-3, "chain")
+
+
 @pytest.mark.parametrize("tile", [16, 32])
 def test_wave_block_cull_on_needles(tile):
     """Strongly anisotropic splats at random orientations (log-scales N(-2.8, 1.3) per axis, so long
