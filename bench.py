@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=5, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--tile", type=int, default=0, help="tile size (0: autotune over 8/16/32)")
+    ap.add_argument("--lds-batch", type=int, default=0, choices=[0, 1, 2],
+                    help="splat records per lane per LDS batch (0: autotuned with the tile, or 1 at a fixed tile)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--configs", default="1,2,3,4",
                     help="comma-separated other workloads (1-4) timed after the main one ('' for none)")
@@ -84,18 +86,23 @@ def main():
     with_adam = "adam" in sc.work
     lrs = sc.lrs or dict(S.DEFAULT_LRS)
     tile = args.tile
+    lds_batch = args.lds_batch
     tune = None
     if tile == 0:
-        tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint)
-        tile = tune["best"]
+        tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint,
+                               batches=(1, 2) if lds_batch == 0 else (lds_batch,))
+        tile, lds_batch = tune["best"], tune["lds_batch"]
         log(f"[bench] autotune: {tune}")
+    elif lds_batch == 0:
+        lds_batch = 1
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
     step = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                         with_adam=with_adam)
+                         with_adam=with_adam, lds_batch=lds_batch)
     step.size()
     torch.cuda.synchronize()
-    log(f"[bench] pairs M={int(step.frame.d_num_pairs.item())} capacity={step.rast.capacity}")
+    log(f"[bench] pairs M={int(step.frame.d_num_pairs.item())} capacity={step.rast.capacity} "
+        f"tile {tile} lds_batch {lds_batch}")
 
     if args.profile_steps > 0:
         for _ in range(args.profile_steps):
@@ -171,7 +178,7 @@ def main():
     per_view = None
     if not args.no_per_view:
         pv = R.PerViewMappingStep(params, sc.cameras, sc.targets, lrs=lrs, tile_size=tile,
-                                  checkpoint=sc.checkpoint, with_adam=with_adam)
+                                  checkpoint=sc.checkpoint, with_adam=with_adam, lds_batch=lds_batch)
         pv.size()
         reset(pv)
         ms_pv_eager = time_graph(pv.run, args.steps, args.warmup)
@@ -194,7 +201,7 @@ def main():
         # and the loss call on its own
         lam = 0.2
         st = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                           with_adam=with_adam, ssim_lambda=lam)
+                           with_adam=with_adam, ssim_lambda=lam, lds_batch=lds_batch)
         st.size()
         if use_graph:
             st.capture()
@@ -255,7 +262,7 @@ def main():
         log(f"[bench] pyramid reduce (all views, level 0 -> 1): {ms_r:.4f} ms ({gbs:.0f} GB/s alg)")
         for lv in (1, 2):
             st = R.MappingStep(params, pyr.cameras[lv], pyr.images[lv], lrs=lrs, tile_size=tile,
-                               checkpoint=sc.checkpoint, with_adam=with_adam)
+                               checkpoint=sc.checkpoint, with_adam=with_adam, lds_batch=lds_batch)
             st.size()
             if use_graph:
                 st.capture()
@@ -285,7 +292,7 @@ def main():
         # (plan, apply) on the statistics those iterations gathered
         dc = R.DensityControl(params.n, sc.cameras, device=dev)
         st = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                           with_adam=with_adam, density=dc)
+                           with_adam=with_adam, density=dc, lds_batch=lds_batch)
         st.size()
         if use_graph:
             st.capture()
@@ -401,7 +408,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "gaussians": sc.n, "views": sc.n_views, "pixels_per_step": sc.total_pixels,
                    "sh_degree": sc.sh_degree, "work": sc.work, "checkpoint": sc.checkpoint, "tile": tile,
-                   "graph": use_graph, "pairs": int(step.frame.d_num_pairs.item())},
+                   "lds_batch": lds_batch, "graph": use_graph, "pairs": int(step.frame.d_num_pairs.item())},
         "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "peak_hbm_bytes": peak_hbm,
         "per_view": per_view,
@@ -450,17 +457,17 @@ def bench_config(idx, args):
     params = R.GaussianParams.from_scene(sc, dev)
     tune = None
     if sc.work == "fwd":
-        tile = 16  # the forward-only workload names 16 x 16 tiles
+        tile, lds_batch = 16, 1  # the forward-only workload names 16 x 16 tiles
         target = None
     else:
         target = R.pack_images(sc.targets, dev)
         tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint)
-        tile = tune["best"]
+        tile, lds_batch = tune["best"], tune["lds_batch"]
     lrs = sc.lrs or dict(S.DEFAULT_LRS)
     mpix = sc.total_pixels * 1e-6
     if sc.work == "fwd":
         rast = R.Rasterizer(sc.cameras, params.n, params.sh_degree, tile_size=tile, checkpoint=sc.checkpoint,
-                            device=dev)
+                            device=dev, lds_batch=lds_batch)
         fr = rast.forward(params)
 
         def run_eager():
@@ -483,7 +490,7 @@ def bench_config(idx, args):
         stages = ("project", "bin_sort", "render_fwd")
     else:
         step = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                             with_adam="adam" in sc.work)
+                             with_adam="adam" in sc.work, lds_batch=lds_batch)
         step.size()
         step.capture()
         ms = time_graph(step.replay, args.steps, args.warmup)
@@ -497,7 +504,8 @@ def bench_config(idx, args):
     alg = sum(b[k] for k in stages)
     gbs = alg / (ms * 1e-3) / 1e9
     out = {"workload": sc.name, "work": sc.work, "gaussians": sc.n, "views": sc.n_views,
-           "pixels_per_step": sc.total_pixels, "tile": tile, "pairs": c["M"], "ms_per_step": round(ms, 4),
+           "pixels_per_step": sc.total_pixels, "tile": tile, "lds_batch": lds_batch, "pairs": c["M"],
+           "ms_per_step": round(ms, 4),
            "value": round(mpix / (ms * 1e-3), 2), "unit": "Mpix*iter/s", "step_alg_bytes": alg,
            "step_GBps": round(gbs, 1), "step_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     if tune is not None:
@@ -523,7 +531,7 @@ def bench_config(idx, args):
         log(f"[bench]   oracle: {dt:.2f} s ({out['cpu_oracle']['value']} Mpix*iter/s)")
     if sc.n_views > 1 and sc.work != "fwd" and not args.no_per_view:
         pv = R.PerViewMappingStep(params, sc.cameras, sc.targets, lrs=lrs, tile_size=tile,
-                                  checkpoint=sc.checkpoint, with_adam="adam" in sc.work)
+                                  checkpoint=sc.checkpoint, with_adam="adam" in sc.work, lds_batch=lds_batch)
         pv.size()
         ms_eager = time_graph(pv.run, args.steps, args.warmup)
         pv.capture()

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 1
+#define GS_ABI_VERSION 2
 #define GS_MAX_VIEWS 32
 #define GS_MAX_SH_DEGREE 3
 /* floats per projected record, see gs_projected */
@@ -121,6 +121,10 @@ typedef struct gs_options {
   float frustum_guard;   /* Jacobian uses x/z clamped to +-guard*(W/2)/fx (1.3) */
   float bg[3];           /* background colour (0,0,0) */
   uint32_t flags;        /* reserved, must be 0 */
+  int32_t lds_batch;     /* splat records each lane of a raster workgroup
+                            stages into LDS per batch: 1 or 2 (1); the
+                            batch is lds_batch x the workgroup's threads.
+                            Every output is the same for either value. */
 } gs_options;
 
 void gs_default_options(gs_options* opts);
@@ -393,28 +397,31 @@ gs_status gs_photometric_loss(const gs_camera* cams, int32_t n_views, const floa
                               size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------- autotuning
- * The tile size of the tile-based rasterisation (Sec. III-B) is a free
- * parameter; gs_autotune picks it by timing the actual problem: for each
- * candidate (bits of candidate_mask: 1 = tile 8, 2 = 16, 4 = 32; 0 = all)
- * one warm-up and `iters` timed iterations of gs_project, gs_bin_sort,
- * gs_render_fwd with the L1 term against `target` (rgb layout of gs_image,
- * device), gs_raster_bwd and gs_project_bwd on `stream`, at opts with its
- * tile_size replaced (the LDS batch is one record per lane of the tile's
- * workgroup, so the tile also fixes it).  Host-side and synchronising, NOT
- * for graph capture; the only call that allocates device memory (its own
- * buffers per candidate, all freed before it returns).  A candidate that does
- * not fit in device memory or whose pair count exceeds the 32-bit index space
- * is skipped (ms -1); GS_ERR_CAPACITY when none fits.  Results are cached for
- * the life of the process by (floor(log2 n), the multiset of view
- * resolutions, sh_degree, checkpoint, candidate mask); refresh != 0 times
- * again.  The parameters are not modified. */
+ * The tile size of the tile-based rasterisation (Sec. III-B) and the LDS
+ * batch of the raster kernels (gs_options.lds_batch) are free parameters;
+ * gs_autotune picks both by timing the actual problem: for each candidate
+ * pair (bits 0-2 of candidate_mask: tile 8, 16, 32; bits 3-4: LDS batch 1,
+ * 2; a group with no bit set means all of it) one warm-up and `iters` timed
+ * iterations of gs_project, gs_bin_sort, gs_render_fwd with the L1 term
+ * against `target` (rgb layout of gs_image, device), gs_raster_bwd and
+ * gs_project_bwd on `stream`, at opts with tile_size and lds_batch replaced.
+ * Host-side and synchronising, NOT for graph capture; the only call that
+ * allocates device memory (its own buffers per tile size, all freed before it
+ * returns).  A candidate that does not fit in device memory or whose pair
+ * count exceeds the 32-bit index space is skipped (ms -1); GS_ERR_CAPACITY
+ * when none fits.  Results are cached for the life of the process by
+ * (floor(log2 n), the multiset of view resolutions, sh_degree, checkpoint,
+ * candidate mask); refresh != 0 times again.  The parameters are not
+ * modified. */
 typedef struct gs_autotune_result {
-  int32_t tile_size;     /* the fastest candidate */
+  int32_t tile_size;     /* the fastest candidate's tile size */
+  int32_t lds_batch;     /* and its LDS batch */
   int32_t from_cache;    /* 1: taken from the cache, nothing timed */
-  int32_t n_candidates;  /* candidates timed, ascending in candidates[] */
-  int32_t candidates[3];
-  float ms[3];           /* mean milliseconds of one iteration at each (-1: skipped) */
-  int64_t pairs[3];      /* (tile, Gaussian) incidences at each (-1: not reached) */
+  int32_t n_candidates;  /* candidates timed, in the order of the arrays */
+  int32_t cand_tile[6];
+  int32_t cand_batch[6];
+  float ms[6];           /* mean milliseconds of one iteration at each (-1: skipped) */
+  int64_t pairs[6];      /* (tile, Gaussian) incidences at each (-1: not reached) */
 } gs_autotune_result;
 
 gs_status gs_autotune(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,

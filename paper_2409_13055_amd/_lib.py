@@ -44,7 +44,7 @@ class gs_options(C.Structure):
     _fields_ = [("tile_size", C.c_int32), ("checkpoint", C.c_int32), ("near_plane", C.c_float),
                 ("eps2d", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("radius_sigmas", C.c_float), ("frustum_guard", C.c_float), ("bg", C.c_float * 3),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("lds_batch", C.c_int32)]
 
 
 class gs_projected(C.Structure):
@@ -84,8 +84,9 @@ class gs_adam_group(C.Structure):
 
 
 class gs_autotune_result(C.Structure):
-    _fields_ = [("tile_size", C.c_int32), ("from_cache", C.c_int32), ("n_candidates", C.c_int32),
-                ("candidates", C.c_int32 * 3), ("ms", C.c_float * 3), ("pairs", C.c_int64 * 3)]
+    _fields_ = [("tile_size", C.c_int32), ("lds_batch", C.c_int32), ("from_cache", C.c_int32),
+                ("n_candidates", C.c_int32), ("cand_tile", C.c_int32 * 6), ("cand_batch", C.c_int32 * 6),
+                ("ms", C.c_float * 6), ("pairs", C.c_int64 * 6)]
 
 
 EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_options", "gs_total_tiles",
@@ -98,6 +99,7 @@ EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_op
            "gs_init_gaussians_workspace_size", "gs_init_gaussians_count", "gs_init_gaussians",
            "gs_render_fwd_noalloc", "gs_autotune")
 
+GS_ABI_VERSION = 2  # include/gs.h
 _lib = None
 
 
@@ -165,6 +167,9 @@ def load(path: str = LIB_PATH):
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
+    if lib.gs_abi_version() != GS_ABI_VERSION:
+        raise RuntimeError(f"{path} implements ABI version {lib.gs_abi_version()}, these bindings version "
+                           f"{GS_ABI_VERSION}: rebuild the HIP library")
     _lib = lib
     return lib
 

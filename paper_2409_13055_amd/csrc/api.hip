@@ -63,6 +63,7 @@ gs_status validate_opts(const gs_options* o) {
   for (int k = 0; k < 3; ++k)
     if (!finite(o->bg[k])) return fail(GS_ERR_INVALID_VALUE, "bg must be finite");
   if (o->flags != 0) return fail(GS_ERR_INVALID_VALUE, "flags must be 0");
+  if (o->lds_batch != 1 && o->lds_batch != 2) return fail(GS_ERR_UNSUPPORTED, "lds_batch must be 1 or 2");
   return GS_OK;
 }
 
@@ -146,6 +147,7 @@ void gs_default_options(gs_options* o) {
   o->t_min = 1e-4f;
   o->radius_sigmas = 3.0f;
   o->frustum_guard = 1.3f;
+  o->lds_batch = 1;
 }
 
 gs_status gs_total_tiles(const gs_camera* cams, int32_t n_views, int32_t tile_size, int64_t* out) {

@@ -4,8 +4,9 @@
 // fastest depends on the splats' footprints and on the views, so the
 // candidates are timed on the actual problem: one iteration of projection,
 // bin/sort, forward with the L1 term, raster backward and projection
-// backward, through the library's own entry points.  The LDS batch is one
-// record per lane of the tile's workgroup, so the tile size also fixes it.
+// backward, through the library's own entry points.  The LDS batch of the
+// raster kernels (one or two splat records per lane) is timed with each tile
+// size on the same buffers.
 //
 // This is the one call that allocates device memory (its own buffers for each
 // candidate, freed before it returns) and the one that synchronises: it is not
@@ -56,11 +57,16 @@ std::vector<int64_t> cache_key(const gs_params* p, const gs_camera* cams, int32_
 
 // Times `iters` iterations at one tile size; *ms < 0 when the candidate cannot run (memory, or a pair
 // count beyond the 32-bit index space).  Returns an error only for failures that are not about size.
+// Times `iters` iterations at one tile size for each LDS batch of `batches` (n_b of them, into ms[b]
+// and pairs[b]); the buffers are allocated once for the tile size.
 gs_status time_candidate(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* base,
-                         int32_t tile, const float* target, int32_t iters, hipStream_t st, float* ms,
-                         int64_t* pairs) {
-  *ms = -1.0f;
-  *pairs = -1;
+                         int32_t tile, const int32_t* batches, int n_b, const float* target, int32_t iters,
+                         hipStream_t st, float* ms_out, int64_t* pairs_out) {
+  for (int b = 0; b < n_b; ++b) {
+    ms_out[b] = -1.0f;
+    pairs_out[b] = -1;
+  }
+  int64_t* pairs = pairs_out;  // the pair count is the same for every batch
   gs_options o = *base;
   o.tile_size = tile;
   const ViewTable vt = make_view_table(cams, n_views, tile);
@@ -152,25 +158,29 @@ gs_status time_candidate(const gs_params* params, const gs_camera* cams, int32_t
       return r;
     return gs_project_bwd(params, &proj, cams, n_views, &o, static_cast<float*>(g2), &grads, st);
   };
-  if ((s = iteration()) != GS_OK) return s;  // warm-up
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  e = hipEventCreate(&e0);
-  if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e == hipSuccess) e = hipEventRecord(e0, st);
-  for (int it = 0; e == hipSuccess && s == GS_OK && it < iters; ++it) s = iteration();
-  if (e == hipSuccess) e = hipEventRecord(e1, st);
-  if (e == hipSuccess) e = hipEventSynchronize(e1);
-  float total = 0.0f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&total, e0, e1);
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  if (s != GS_OK) return s;
-  if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("gs_autotune: events: ") + hipGetErrorString(e));
-  int32_t over = 0;
-  e = hipMemcpy(&over, ovf, sizeof over, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("gs_autotune: ") + hipGetErrorString(e));
-  if (over) return fail(GS_ERR_CAPACITY, "gs_autotune: the pair count grew past its capacity while timing");
-  *ms = total / (float)iters;
+  for (int bi = 0; bi < n_b; ++bi) {
+    o.lds_batch = batches[bi];
+    pairs_out[bi] = *pairs;
+    if ((s = iteration()) != GS_OK) return s;  // warm-up
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int it = 0; e == hipSuccess && s == GS_OK && it < iters; ++it) s = iteration();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float total = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&total, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s != GS_OK) return s;
+    if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("gs_autotune: events: ") + hipGetErrorString(e));
+    int32_t over = 0;
+    e = hipMemcpy(&over, ovf, sizeof over, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("gs_autotune: ") + hipGetErrorString(e));
+    if (over) return fail(GS_ERR_CAPACITY, "gs_autotune: the pair count grew past its capacity while timing");
+    ms_out[bi] = total / (float)iters;
+  }
   return GS_OK;
 }
 
@@ -189,8 +199,11 @@ extern "C" gs_status gs_autotune(const gs_params* params, const gs_camera* cams,
   if (!target) return fail(GS_ERR_INVALID_VALUE, "gs_autotune times the L1 iteration: target is required");
   if (!out) return fail(GS_ERR_INVALID_VALUE, "out is NULL");
   if (iters < 1 || iters > 1000) return fail(GS_ERR_INVALID_VALUE, "iters must be in [1, 1000]");
-  const int32_t mask = candidate_mask == 0 ? 7 : candidate_mask;
-  if (mask < 0 || mask > 7) return fail(GS_ERR_INVALID_VALUE, "candidate_mask uses bits 0-2 (tiles 8, 16, 32)");
+  if (candidate_mask < 0 || candidate_mask > 31)
+    return fail(GS_ERR_INVALID_VALUE, "candidate_mask uses bits 0-2 (tiles 8, 16, 32) and 3-4 (LDS batch 1, 2)");
+  const int32_t tmask = (candidate_mask & 7) == 0 ? 7 : (candidate_mask & 7);
+  const int32_t bmask = ((candidate_mask >> 3) & 3) == 0 ? 3 : ((candidate_mask >> 3) & 3);
+  const int32_t mask = tmask | (bmask << 3);
   if ((int64_t)n_views * params->n >= (int64_t(1) << 32) - 1) return fail(GS_ERR_INVALID_VALUE, "bad n");
   const std::vector<int64_t> key = cache_key(params, cams, n_views, opts, mask);
   if (!refresh) {
@@ -206,17 +219,28 @@ extern "C" gs_status gs_autotune(const gs_params* params, const gs_camera* cams,
   gs_autotune_result r{};
   r.tile_size = 0;
   const int32_t tiles[3] = {8, 16, 32};
+  int32_t batches[2];
+  int n_b = 0;
+  for (int b = 0; b < 2; ++b)
+    if ((bmask >> b) & 1) batches[n_b++] = b + 1;
   float best = 0.0f;
   for (int k = 0; k < 3; ++k) {
-    if (!((mask >> k) & 1)) continue;
-    const int c = r.n_candidates++;
-    r.candidates[c] = tiles[k];
-    if ((s = time_candidate(params, cams, n_views, opts, tiles[k], target, iters, st, &r.ms[c], &r.pairs[c])) !=
-        GS_OK)
+    if (!((tmask >> k) & 1)) continue;
+    const int c = r.n_candidates;
+    r.n_candidates += n_b;
+    for (int b = 0; b < n_b; ++b) {
+      r.cand_tile[c + b] = tiles[k];
+      r.cand_batch[c + b] = batches[b];
+    }
+    if ((s = time_candidate(params, cams, n_views, opts, tiles[k], batches, n_b, target, iters, st, &r.ms[c],
+                            &r.pairs[c])) != GS_OK)
       return s;
-    if (r.ms[c] > 0.0f && (r.tile_size == 0 || r.ms[c] < best)) {
-      best = r.ms[c];
-      r.tile_size = tiles[k];
+    for (int b = 0; b < n_b; ++b) {
+      if (r.ms[c + b] > 0.0f && (r.tile_size == 0 || r.ms[c + b] < best)) {
+        best = r.ms[c + b];
+        r.tile_size = tiles[k];
+        r.lds_batch = batches[b];
+      }
     }
   }
   if (r.tile_size == 0) return fail(GS_ERR_CAPACITY, "gs_autotune: no candidate tile size fits in device memory");

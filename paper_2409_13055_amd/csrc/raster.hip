@@ -279,55 +279,69 @@ struct BlockBoxes {
   }
 };
 
-// LDS of one batch: what the pixel loop reads per entry, and per wavefront
-// the ordered list of the batch entries its pixel block can see.
-template <class PM>
+// LDS of one batch of RPL records per lane (RPL x NT entries): what the pixel
+// loop reads per entry, and per wavefront the ordered list of the batch entries
+// its pixel block can see.  Entry r NT + t of the batch is record r of thread t.
+template <class PM, int RPL>
 struct BatchLds {
-  float4 a[PM::NT];  // (mean x, mean y, a'/2, b') for the conic (a, b, c), ' = times log2(e)
-  float4 b[PM::NT];  // (c'/2, opacity, qmax (the exponent cutoff as a bound on q), r)
-  float4 c[PM::NT];  // (g, b, unused, unused): 16-byte rows, so one index scale serves all three arrays
-  uint32_t id[PM::NT];
-  uint16_t list[PM::WAVES][PM::NT];
-  int cnt[PM::WAVES][PM::WAVES];  // [staging wave][listing wave]
+  static constexpr int NB = RPL * PM::NT;
+  float4 a[NB];  // (mean x, mean y, a'/2, b') for the conic (a, b, c), ' = times log2(e)
+  float4 b[NB];  // (c'/2, opacity, qmax (the exponent cutoff as a bound on q), r)
+  float4 c[NB];  // (g, b, unused, unused): 16-byte rows, so one index scale serves all three arrays
+  uint32_t id[NB];
+  uint16_t list[PM::WAVES][NB];
+  int cnt[RPL][PM::WAVES][PM::WAVES];  // [record][staging wave][listing wave]
 };
 
-// Stages the batch held by `ld` (one entry per thread): entry data into LDS,
+// Stages the batch held by `ld` (RPL entries per thread): entry data into LDS,
 // the cull of every wavefront block done once here per entry, and each
 // wavefront's list built in entry order (ballots, then the staging waves'
-// counts in order).  Ends with a barrier; returns the calling wave's count.
-template <class PM>
-__device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBoxes<PM>& bx, float alpha_min,
-                                           BatchLds<PM>& L, bool with_id) {
+// counts in order, record by record).  Ends with a barrier; returns the
+// calling wave's count.
+template <class PM, int RPL>
+__device__ __forceinline__ int stage_batch(const SplatLoader (&ld)[RPL], const BlockBoxes<PM>& bx, float alpha_min,
+                                           BatchLds<PM, RPL>& L, bool with_id) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  int mask = 0;
-  if (ld.valid) {
-    const float cut = power_cutoff(ld.b.y, alpha_min);
-    mask = bx.mask(ld.a.x, ld.a.y, cull_conic(ld.a.z, ld.a.w, ld.b.x, ld.b.y, alpha_min, -2.0f * cut));
-    L.a[t] = make_float4(ld.a.x, ld.a.y, (0.5f * kLog2e) * ld.a.z, kLog2e * ld.a.w);
-    L.b[t] = make_float4((0.5f * kLog2e) * ld.b.x, ld.b.y, fmaxf(-kLog2e * cut, 0.0f), ld.b.z);
-    L.c[t] = make_float4(ld.b.w, ld.c.x, 0.0f, 0.0f);
-    if (with_id) L.id[t] = ld.id;
-  }
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  uint64_t bal[PM::WAVES];
+  int mask[RPL];
+  uint64_t bal[RPL][PM::WAVES];
 #pragma unroll
-  for (int q = 0; q < PM::WAVES; ++q) bal[q] = __ballot((mask >> q) & 1);
-  if (lane == 0) {
+  for (int r = 0; r < RPL; ++r) {
+    const int slot = r * PM::NT + t;
+    mask[r] = 0;
+    if (ld[r].valid) {
+      const SplatLoader& d = ld[r];
+      const float cut = power_cutoff(d.b.y, alpha_min);
+      mask[r] = bx.mask(d.a.x, d.a.y, cull_conic(d.a.z, d.a.w, d.b.x, d.b.y, alpha_min, -2.0f * cut));
+      L.a[slot] = make_float4(d.a.x, d.a.y, (0.5f * kLog2e) * d.a.z, kLog2e * d.a.w);
+      L.b[slot] = make_float4((0.5f * kLog2e) * d.b.x, d.b.y, fmaxf(-kLog2e * cut, 0.0f), d.b.z);
+      L.c[slot] = make_float4(d.b.w, d.c.x, 0.0f, 0.0f);
+      if (with_id) L.id[slot] = d.id;
+    }
 #pragma unroll
-    for (int q = 0; q < PM::WAVES; ++q) L.cnt[w][q] = (int)__popcll(bal[q]);
+    for (int q = 0; q < PM::WAVES; ++q) bal[r][q] = __ballot((mask[r] >> q) & 1);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < PM::WAVES; ++q) L.cnt[r][w][q] = (int)__popcll(bal[r][q]);
+    }
   }
   __syncthreads();
   int mine = 0;
 #pragma unroll
   for (int q = 0; q < PM::WAVES; ++q) {
-    int off = 0;
+    int off = 0;  // the entries of earlier records, then of earlier staging waves of this record
 #pragma unroll
-    for (int w2 = 0; w2 < PM::WAVES; ++w2) {
-      const int c = L.cnt[w2][q];
-      off += w2 < w ? c : 0;
-      mine += q == w ? c : 0;
+    for (int r = 0; r < RPL; ++r) {
+      int here = off;
+#pragma unroll
+      for (int w2 = 0; w2 < PM::WAVES; ++w2) {
+        const int c = L.cnt[r][w2][q];
+        here += w2 < w ? c : 0;
+        off += c;
+      }
+      if ((mask[r] >> q) & 1) L.list[q][here + (int)__popcll(bal[r][q] & lt)] = (uint16_t)(r * PM::NT + t);
     }
-    if ((mask >> q) & 1) L.list[q][off + (int)__popcll(bal[q] & lt)] = (uint16_t)t;
+    mine = q == w ? off : mine;
   }
   __syncthreads();
   return mine;
@@ -340,14 +354,16 @@ __device__ __forceinline__ int stage_batch(const SplatLoader& ld, const BlockBox
 // NaN and fails the range test, so no separate flag is tested.
 // STATE: the pixel state (T_final, n_contrib) is written (not under the checkpoint flag).
 // (six wavefronts per SIMD: measured faster than five, despite a few bytes of spill outside the loop)
-template <int TILE, bool STATE>
+// RPL: splat records each lane stages per LDS batch.
+template <int TILE, bool STATE, int RPL>
 __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_render_fwd(
     ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     RasterConsts rc, float* __restrict__ img, float* __restrict__ tfin, int32_t* __restrict__ ncon,
     const float* __restrict__ target, float* __restrict__ tile_loss) {
   using PM = PixMap<TILE, FwdShape<TILE>>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
-  __shared__ BatchLds<PM> L;
+  constexpr int NB = RPL * NT;  // entries per batch
+  __shared__ BatchLds<PM, RPL> L;
   __shared__ float s_loss[PM::WAVES];
   const PM pm(vt, blockIdx.x);
   const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
@@ -365,15 +381,18 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_wave
   const uint2 rg = ranges[blockIdx.x];
   const int s = (int)rg.x, e = (int)rg.y;
   const float fx = (float)pm.x;
-  SplatLoader ld;
-  ld.fetch(rec, ids, s + (int)threadIdx.x, s, e);
-  for (int base = s; base < e; base += NT) {
+  SplatLoader ld[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) ld[r].fetch(rec, ids, s + r * NT + (int)threadIdx.x, s, e);
+  for (int base = s; base < e; base += NB) {
     int alive = 0;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) alive |= fy[p] != INFINITY ? 1 : 0;
     if (__syncthreads_count(alive) == 0) break;
-    const int n = stage_batch<PM>(ld, boxes, rc.alpha_min, L, false);
-    ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);  // next batch, in flight during this one
+    const int n = stage_batch<PM, RPL>(ld, boxes, rc.alpha_min, L, false);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)  // next batch, in flight during this one
+      ld[r].fetch(rec, ids, base + NB + r * NT + (int)threadIdx.x, s, e);
     // a wavefront whose pixels have all stopped only keeps the block's barriers
     // (wave-uniform: kept in a scalar register, so the walk's loop control is scalar)
     const int cnt = __builtin_amdgcn_readfirstlane(__ballot(alive) != 0ull ? n : 0);
@@ -553,7 +572,7 @@ __device__ int abs_role(int lane) {
 // scalar D_k = dL/dC . S_k, updated by the entry's dL/dC . c_k.
 // With ABS the kernel also adds the homodirectional view-space gradient of
 // each (view, Gaussian) pair into abs2d [V*N][2].
-template <int TILE, bool ABS>
+template <int TILE, bool ABS, int RPL>
 // (five wavefronts per SIMD: 96 registers, no spill; measured 10% faster than four)
 __global__ __launch_bounds__(BwdShape<TILE>::THREADS)
 __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_render_bwd(
@@ -562,7 +581,8 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
     const float* __restrict__ dl_dimage, float* __restrict__ grad2d, float* __restrict__ abs2d) {
   using PM = PixMap<TILE, BwdShape<TILE>>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
-  __shared__ BatchLds<PM> L;
+  constexpr int NB = RPL * NT;  // entries per batch
+  __shared__ BatchLds<PM, RPL> L;
   const PM pm(vt, blockIdx.x);
   const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
   const BlockBoxes<PM> boxes(pm);
@@ -600,15 +620,18 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
   }
   Acc6 acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   float amx = 0.0f, amy = 0.0f;  // ABS: the lane's sums of |dL_p/dmean| for the current entry
-  SplatLoader ld;
-  ld.fetch(rec, ids, s + (int)threadIdx.x, s, e);
-  for (int base = s; base < e; base += NT) {
+  SplatLoader ld[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) ld[r].fetch(rec, ids, s + r * NT + (int)threadIdx.x, s, e);
+  for (int base = s; base < e; base += NB) {
     int alive = 0;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) alive |= fy[p] != INFINITY ? 1 : 0;
     if (__syncthreads_count(alive) == 0) break;
-    const int n = stage_batch<PM>(ld, boxes, rc.alpha_min, L, true);
-    ld.fetch(rec, ids, base + NT + (int)threadIdx.x, s, e);  // next batch, in flight during this one
+    const int n = stage_batch<PM, RPL>(ld, boxes, rc.alpha_min, L, true);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)  // next batch, in flight during this one
+      ld[r].fetch(rec, ids, base + NB + r * NT + (int)threadIdx.x, s, e);
     // (wave-uniform: kept in a scalar register, so the walk's loop control is scalar)
     const int cnt = __builtin_amdgcn_readfirstlane(__ballot(alive) != 0ull ? n : 0);
     for (int k = 0; k < cnt; ++k) {
@@ -825,20 +848,28 @@ static gs_status render_fwd_impl(const gs_projected* proj, int64_t n, const gs_b
   const dim3 grid((unsigned)vt.total_tiles);
   const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
   (void)n;
-#define GS_LAUNCH_FWD(TILE_, NT_)                                                                              \
+#define GS_LAUNCH_FWD_R(TILE_, NT_, RPL_)                                                                      \
   do {                                                                                                        \
     if (tf)                                                                                                   \
-      hipLaunchKernelGGL((k_render_fwd<TILE_, true>), grid, dim3(NT_), 0, st, vt, proj->rec, bins->ids, rg, rc, \
-                         out->rgb, tf, nc, tgt, tile_loss);                                                  \
+      hipLaunchKernelGGL((k_render_fwd<TILE_, true, RPL_>), grid, dim3(NT_), 0, st, vt, proj->rec, bins->ids, \
+                         rg, rc, out->rgb, tf, nc, tgt, tile_loss);                                          \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_render_fwd<TILE_, false>), grid, dim3(NT_), 0, st, vt, proj->rec, bins->ids, rg,   \
-                         rc, out->rgb, tf, nc, tgt, tile_loss);                                              \
+      hipLaunchKernelGGL((k_render_fwd<TILE_, false, RPL_>), grid, dim3(NT_), 0, st, vt, proj->rec, bins->ids,\
+                         rg, rc, out->rgb, tf, nc, tgt, tile_loss);                                          \
+  } while (0)
+#define GS_LAUNCH_FWD(TILE_, NT_)                  \
+  do {                                            \
+    if (opts->lds_batch == 2)                     \
+      GS_LAUNCH_FWD_R(TILE_, NT_, 2);             \
+    else                                          \
+      GS_LAUNCH_FWD_R(TILE_, NT_, 1);             \
   } while (0)
   switch (opts->tile_size) {
     case 8: GS_LAUNCH_FWD(8, FwdShape<8>::THREADS); break;
     case 16: GS_LAUNCH_FWD(16, FwdShape<16>::THREADS); break;
     default: GS_LAUNCH_FWD(32, FwdShape<32>::THREADS); break;
   }
+#undef GS_LAUNCH_FWD_R
 #undef GS_LAUNCH_FWD
   if (want_loss) hipLaunchKernelGGL(k_loss_reduce, dim3(n_views), dim3(256), 0, st, vt, tile_loss, loss->loss_out);
   return check_launch("render forward");
@@ -948,9 +979,16 @@ static void launch_raster_bwd(const ViewTable& vt, const gs_projected* proj, con
   const RasterConsts rc = consts_of(opts);
   const dim3 grid((unsigned)vt.total_tiles);
   const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
-#define GS_BWD(TILE, ABS)                                                                                     \
-  hipLaunchKernelGGL((k_render_bwd<TILE, ABS>), grid, dim3(BwdShape<TILE>::THREADS), 0, st, vt, proj->rec,   \
+#define GS_BWD_R(TILE, ABS, RPL)                                                                              \
+  hipLaunchKernelGGL((k_render_bwd<TILE, ABS, RPL>), grid, dim3(BwdShape<TILE>::THREADS), 0, st, vt, proj->rec, \
                      bins->ids, rg, rc, img->rgb, (int)loss->kind, loss->target, loss->dl_dimage, g2, a2)
+#define GS_BWD(TILE, ABS)          \
+  do {                             \
+    if (opts->lds_batch == 2)      \
+      GS_BWD_R(TILE, ABS, 2);      \
+    else                           \
+      GS_BWD_R(TILE, ABS, 1);      \
+  } while (0)
   if (a2) {
     switch (opts->tile_size) {
       case 8: GS_BWD(8, true); break;
@@ -964,6 +1002,7 @@ static void launch_raster_bwd(const ViewTable& vt, const gs_projected* proj, con
       default: GS_BWD(32, false); break;
     }
   }
+#undef GS_BWD_R
 #undef GS_BWD
 }
 

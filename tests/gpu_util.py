@@ -22,12 +22,13 @@ def gpu_rec_to_oracle(rec):
 
 
 def run_gpu(sc, tile=16, checkpoint=False, backward=True, want_keys=True, capacity=None, cams=None,
-            external_dl=None):
-    """Forward (+ L1 backward) of `sc` on the GPU; returns numpy outputs."""
+            external_dl=None, lds_batch=1, with_abs=False):
+    """Forward (+ L1 backward) of `sc` on the GPU; returns numpy outputs.  with_abs: also the raster
+    backward with the homodirectional gradient (gs_raster_bwd_abs) into out["abs2d"]."""
     cams = sc.cameras if cams is None else cams
     params = R.GaussianParams.from_scene(sc, DEV)
     rast = R.Rasterizer(cams, params.n, params.sh_degree, tile_size=tile, checkpoint=checkpoint, device=DEV,
-                        want_keys=want_keys)
+                        want_keys=want_keys, lds_batch=lds_batch)
     if capacity is not None:
         rast.reserve(capacity)
     target = R.pack_images(sc.targets, DEV) if sc.targets is not None else None
@@ -48,6 +49,12 @@ def run_gpu(sc, tile=16, checkpoint=False, backward=True, want_keys=True, capaci
         torch.cuda.synchronize()
         out["grad2d"] = rast.grad2d.cpu().numpy().astype(np.float64)
         out["grads"] = {k: getattr(grads, k).cpu().numpy().astype(np.float64) for k in R.PARAM_NAMES}
+        if with_abs:
+            g2 = torch.zeros(len(cams) * params.n, 9, dtype=torch.float32, device=DEV)
+            a2 = torch.zeros(len(cams) * params.n, 2, dtype=torch.float32, device=DEV)
+            rast.raster_bwd(fr, g2, target=target, abs2d=a2)
+            torch.cuda.synchronize()
+            out["abs2d"] = a2.cpu().numpy().astype(np.float64)
     torch.cuda.synchronize()
     m = int(fr.d_num_pairs.item())
     out["m"] = m

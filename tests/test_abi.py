@@ -39,7 +39,8 @@ def test_every_declared_symbol_is_exported(L):
 def test_defaults_and_queries(L):
     from paper_2409_13055_amd import synthetic as S
     o = L.default_options()
-    assert o.tile_size == 16 and o.checkpoint == 0 and o.flags == 0
+    assert o.tile_size == 16 and o.checkpoint == 0 and o.flags == 0 and o.lds_batch == 1
+    assert L.load().gs_abi_version() == L.GS_ABI_VERSION == 2
     assert abs(o.alpha_min - 1 / 255) < 1e-9 and abs(o.alpha_max - 0.99) < 1e-7 and abs(o.t_min - 1e-4) < 1e-10
     assert abs(o.near_plane - 0.2) < 1e-7 and abs(o.eps2d - 0.3) < 1e-7 and o.radius_sigmas == 3.0
     cams = [S.pinhole(1200, 680, 600.0), S.pinhole(640, 480, 525.0), S.pinhole(100, 75, 90.0)]
@@ -68,6 +69,9 @@ def test_invalid_arguments_are_rejected_before_any_launch(L):
     bad = L.default_options(alpha_min=0.5, alpha_max=0.4)
     with pytest.raises(L.GsError, match="alpha"):
         L.gs_render_fwd_workspace_size(cc, 1, bad)
+    for batch in (0, 3):
+        with pytest.raises(L.GsError, match="lds_batch"):
+            L.gs_render_fwd_workspace_size(cc, 1, L.default_options(lds_batch=batch))
     # hot-path calls with NULL device pointers fail validation (nothing is enqueued)
     params = L.gs_params()
     params.n, params.sh_degree = 10, 0
@@ -262,13 +266,14 @@ def test_autotune_validates_before_any_launch(L):
         L.gs_autotune(params, cc, 1, o, None, 3, 0, 0, None)
     with pytest.raises(L.GsError, match="iters"):
         L.gs_autotune(params, cc, 1, o, C.c_void_p(0x6000), 0, 0, 0, None)
-    with pytest.raises(L.GsError, match="candidate_mask"):
-        L.gs_autotune(params, cc, 1, o, C.c_void_p(0x6000), 3, 8, 0, None)
+    for mask in (32, -1):
+        with pytest.raises(L.GsError, match="candidate_mask"):
+            L.gs_autotune(params, cc, 1, o, C.c_void_p(0x6000), 3, mask, 0, None)
     params.sh_degree = 4
     with pytest.raises(L.GsError, match="sh_degree"):
         L.gs_autotune(params, cc, 1, o, C.c_void_p(0x6000), 3, 0, 0, None)
     r = L.gs_autotune_result()
-    assert C.sizeof(r) == 64  # int32 x 6, float x 3, padding, int64 x 3: the layout gs.h declares
+    assert C.sizeof(r) == 136  # int32 x 16, float x 6, int64 x 6: the layout gs.h declares
 
 
 def test_noalloc_forward_validates_before_any_launch(L):

@@ -353,6 +353,23 @@ def test_batched_equals_per_view():
     assert npx[0] > 0
 
 
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_lds_batch_changes_no_output(tile):
+    """Two splat records per lane per LDS batch (gs_options.lds_batch = 2) against one: images, final
+    transmittance, contributor counts and losses bit-identical; image-space gradients, the homodirectional
+    ones and the parameter gradients equal up to the order of the FP32 atomics."""
+    sc = small_scene(seed=21, n=2500)
+    a = U.run_gpu(sc, tile=tile, lds_batch=1, with_abs=True)
+    b = U.run_gpu(sc, tile=tile, lds_batch=2, with_abs=True)
+    assert a["m"] == b["m"] > 0
+    for k in ("image", "t_final", "n_contrib", "loss", "ids", "ranges"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    for k in ("grad2d", "abs2d"):
+        assert U.rel_l2(b[k], a[k]) <= 1e-5, k
+    for k in a["grads"]:
+        assert U.rel_l2(b["grads"][k], a["grads"][k]) <= 1e-5, k
+
+
 def test_empty_and_degenerate_inputs():
     sc = small_scene(seed=4, n=64, D=0)
     sc.means[:, 2] = -5.0  # all behind the camera
@@ -487,16 +504,19 @@ def test_autotune_times_every_tile_and_parity_holds_at_its_choice():
     target = R.pack_images(sc.targets, "cuda")
     res = A.autotune_tile(params, sc.cameras, target, refresh=True)
     ms, pairs = res["ms_fwd_bwd"], res["pairs"]
-    assert not res["from_cache"] and set(ms) == {8, 16, 32} and all(v > 0 for v in ms.values()), res
-    assert res["best"] == min(ms, key=ms.get)
+    assert not res["from_cache"] and all(v > 0 for v in ms.values()), res
+    assert set(ms) == {f"{t}/{b}" for t in (8, 16, 32) for b in (1, 2)}, res
+    assert f"{res['best']}/{res['lds_batch']}" == min(ms, key=ms.get)
     assert pairs[8] >= pairs[16] >= pairs[32] > 0  # a finer grid lists a splat in at least as many tiles
     for a, b in zip(before, params.tensors()):
         assert torch.equal(a, b)
     again = A.autotune_tile(params, sc.cameras, target)
-    assert again["from_cache"] and again["best"] == res["best"]
+    assert again["from_cache"] and (again["best"], again["lds_batch"]) == (res["best"], res["lds_batch"])
+    only = A.autotune_tile(params, sc.cameras, target, candidates=(16,), batches=(2,), refresh=True)
+    assert set(only["ms_fwd_bwd"]) == {"16/2"} and (only["best"], only["lds_batch"]) == (16, 2)
     tile = res["best"]
     opts = O.Options(tile=tile)
-    g = U.run_gpu(sc, tile=tile)
+    g = U.run_gpu(sc, tile=tile, lds_batch=res["lds_batch"])
     check_bins(sc, g, tile)
     check_image_pinned(sc, g, opts)
     orec = U.gpu_rec_to_oracle(g["rec"])
