@@ -194,21 +194,38 @@ __global__ __launch_bounds__(kSortThreads) void k_compact_segments(const uint4* 
 // stable block-local ranking (wavefront ballots + per-wave digit counts in
 // LDS) and scatter.
 // ---------------------------------------------------------------------------
-// One count of digit d into the block histogram h.  When every active lane of
-// the wavefront holds the same digit (the top digit of depths spanning a
-// narrow range, for instance), the first of them adds them all with one
-// atomic: 64 lanes on one LDS word would otherwise serialise.
+// One count of digit d into the block histogram h.  PEERS: the lanes of the
+// wavefront holding the same digit (found by ballots over its bits) are added
+// by the first of them with one atomic, for a digit with few distinct values
+// across the keys (the top digit of depths spanning a narrow range), where
+// many lanes would otherwise serialise on a few LDS words.  Otherwise one
+// atomic per lane, except that a wavefront whose active lanes all share one
+// digit adds them at once.
+template <bool PEERS>
 __device__ __forceinline__ void hist_add(uint32_t* h, uint32_t d) {
-  const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-  const uint64_t active = __ballot(1);
-  if (__ballot(d != d0) == 0ull) {
-    if ((int)(threadIdx.x & 63) == __ffsll((unsigned long long)active) - 1)
-      atomicAdd(&h[d0], (uint32_t)__popcll(active));
+  const int lane = (int)(threadIdx.x & 63);
+  if constexpr (PEERS) {
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint64_t peers = __ballot(1);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    if ((peers & lt) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(peers));
   } else {
-    atomicAdd(&h[d], 1u);
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    const uint64_t active = __ballot(1);
+    if (__ballot(d != d0) == 0ull) {
+      if (lane == __ffsll((unsigned long long)active) - 1) atomicAdd(&h[d0], (uint32_t)__popcll(active));
+    } else {
+      atomicAdd(&h[d], 1u);
+    }
   }
 }
 
+template <bool PEERS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ d_count, int shift, int nb,
                                                              uint32_t* __restrict__ hist) {
@@ -224,9 +241,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
 #pragma unroll
     for (int u = 0; u < U; ++u) k[u] = keys[i + (uint64_t)u * kSortThreads];
 #pragma unroll
-    for (int u = 0; u < U; ++u) hist_add(h, (k[u] >> shift) & (kRadixBins - 1));
+    for (int u = 0; u < U; ++u) hist_add<PEERS>(h, (k[u] >> shift) & (kRadixBins - 1));
   }
-  for (; i < c.end; i += kSortThreads) hist_add(h, (keys[i] >> shift) & (kRadixBins - 1));
+  for (; i < c.end; i += kSortThreads) hist_add<PEERS>(h, (keys[i] >> shift) & (kRadixBins - 1));
   __syncthreads();
   hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
@@ -998,7 +1015,11 @@ template <typename V, bool GATHER = false, bool IOTA = false>
 static void radix_pass(const uint32_t* kin, const V* vin, uint32_t* kout, StoredT<V, GATHER>* vout,
                        const uint32_t* d_count, int shift, int nb, uint32_t* hist, uint32_t* dtot, hipStream_t st,
                        const uint4* gather = nullptr) {
-  hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, kin, d_count, shift, nb, hist);
+  // the top digit of the FP32 depth (sign and high exponent bits) takes few distinct values
+  if (shift == 24)
+    hipLaunchKernelGGL(k_radix_hist<true>, dim3(nb), dim3(kSortThreads), 0, st, kin, d_count, shift, nb, hist);
+  else
+    hipLaunchKernelGGL(k_radix_hist<false>, dim3(nb), dim3(kSortThreads), 0, st, kin, d_count, shift, nb, hist);
   hipLaunchKernelGGL(k_radix_scan_digit, dim3(kRadixBins), dim3(kSortThreads), 0, st, hist, nb, dtot);
   hipLaunchKernelGGL((k_radix_scatter<V, GATHER, IOTA>), dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, d_count,
                      shift, nb, hist, dtot, gather);
