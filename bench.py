@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--tile", type=int, default=0, help="tile size (0: autotune over 8/16/32)")
     ap.add_argument("--lds-batch", type=int, default=0, choices=[0, 1, 2],
                     help="splat records per lane per LDS batch (0: autotuned with the tile, or 1 at a fixed tile)")
+    ap.add_argument("--layout", default="morton", choices=["morton", "generated"],
+                    help="order of the Gaussian set in memory: Morton order of the means (gs_spatial_order, the "
+                         "layout the mapping loop keeps) or the order the scene generator drew them in")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--configs", default="1,2,3,4",
                     help="comma-separated other workloads (1-4) timed after the main one ('' for none)")
@@ -78,8 +81,9 @@ def main():
     sc = S.make_config(args.workload)
     log(f"[bench] workload {sc.name}: N={sc.n} views={sc.n_views} px={sc.total_pixels} "
         f"({time.time() - t0:.1f}s to generate)")
-    params = R.GaussianParams.from_scene(sc, dev)
+    params_gen = R.GaussianParams.from_scene(sc, dev)
     target = R.pack_images(sc.targets, dev)
+    params, layout = lay_out(params_gen, args.layout, args.steps)
     # Every timed phase starts from these parameters and a fresh optimiser state: the iterations
     # train the Gaussians, which changes the work per iteration as it goes.
     initial = [t.detach().cpu() for t in params.tensors()]
@@ -118,8 +122,8 @@ def main():
         log("[bench] profile steps done")
         return
 
-    def reset(st):
-        for t, t0 in zip(params.tensors(), initial):
+    def reset(st, p=None, init=None):
+        for t, t0 in zip((params if p is None else p).tensors(), initial if init is None else init):
             t.copy_(t0)
         for t in st.grads.tensors():
             t.zero_()
@@ -152,6 +156,24 @@ def main():
     value = mpix / (ms * 1e-3)
     loss = step.loss.sum().item()
     log(f"[bench] batched: {ms:.3f} ms/step, {value:.1f} Mpix*iter/s, loss {loss:.5f}")
+
+    if args.layout == "morton":
+        # the same iteration on the set in the order it was generated in
+        init_g = [t.detach().cpu() for t in params_gen.tensors()]
+        st_g = R.MappingStep(params_gen, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
+                             with_adam=with_adam, lds_batch=lds_batch)
+        st_g.size()
+        if use_graph:
+            st_g.capture()
+        reset(st_g, params_gen, init_g)
+        ms_g = time_graph(st_g.replay if use_graph else st_g.run, args.steps, args.warmup)
+        g_stages, _ = stage_breakdown(st_g, args.steps)
+        layout["generated_order"] = {"ms_per_step": round(ms_g, 4), "value": round(mpix / (ms_g * 1e-3), 2),
+                                     "speedup_of_morton": round(ms_g / ms, 4), "stages_ms": g_stages}
+        log(f"[bench] generated order: {ms_g:.3f} ms/step ({ms_g / ms:.3f}x the Morton-ordered step), "
+            f"stages {g_stages}")
+        del st_g, init_g
+    del params_gen
 
     # The same iteration issued eagerly (no graph), for comparison.
     eager_ms = None
@@ -387,7 +409,7 @@ def main():
             f"{ms_fill:.3f} ms, initialisation of {n_new} Gaussians {ms_init:.3f} ms")
         del pc, out0
 
-    roof = roofline(step, sc, stages, work, ms)
+    roof = roofline(step, sc, stages, work, ms, args.layout)
     others = {}
     for idx in [int(x) for x in args.configs.split(",") if x.strip()]:
         if idx != args.workload:
@@ -408,7 +430,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "gaussians": sc.n, "views": sc.n_views, "pixels_per_step": sc.total_pixels,
                    "sh_degree": sc.sh_degree, "work": sc.work, "checkpoint": sc.checkpoint, "tile": tile,
-                   "lds_batch": lds_batch, "graph": use_graph, "pairs": int(step.frame.d_num_pairs.item())},
+                   "lds_batch": lds_batch, "graph": use_graph, "pairs": int(step.frame.d_num_pairs.item()),
+                   "layout": args.layout},
+        "layout": layout,
         "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "peak_hbm_bytes": peak_hbm,
         "per_view": per_view,
@@ -424,6 +448,36 @@ def main():
     if tune is not None:
         out["autotune"] = tune
     print(json.dumps(out), flush=True)
+
+
+def lay_out(params, layout, reps):
+    """The Gaussian set in the memory layout `layout` names, and what putting it there costs: for
+    "morton" gs_spatial_order and the row gathers of the parameters (the mapping loop also gathers
+    both Adam moments, three times the gather bytes), timed over `reps` calls."""
+    import torch
+    from paper_2409_13055_amd import rasterizer as R
+    if layout != "morton":
+        return params, {"order": layout}
+    out, _, _ = R.spatially_ordered(params)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        order = params.spatial_order()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_order = e0.elapsed_time(e1) / reps
+    e0.record()
+    for _ in range(reps):
+        params.gathered(order)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_gather = e0.elapsed_time(e1) / reps
+    row = sum(t.numel() for t in params.tensors()) * 4
+    log(f"[bench] Morton order of {params.n} Gaussians: order {ms_order:.3f} ms, gather {ms_gather:.3f} ms")
+    return out, {"order": layout, "spatial_order_ms": round(ms_order, 4), "gather_params_ms": round(ms_gather, 4),
+                 "gather_alg_bytes": 2 * row + 4 * params.n,
+                 "gather_GBps": round((2 * row + 4 * params.n) / (ms_gather * 1e-3) / 1e9, 1)}
 
 
 def time_graph(run, steps, warmup):
@@ -454,7 +508,7 @@ def bench_config(idx, args):
     from paper_2409_13055_amd import roofline as RF
     dev = torch.device("cuda:0")
     sc = S.make_config(idx)
-    params = R.GaussianParams.from_scene(sc, dev)
+    params, _ = lay_out(R.GaussianParams.from_scene(sc, dev), args.layout, 1)
     tune = None
     if sc.work == "fwd":
         tile, lds_batch = 16, 1  # the forward-only workload names 16 x 16 tiles
@@ -504,7 +558,8 @@ def bench_config(idx, args):
     alg = sum(b[k] for k in stages)
     gbs = alg / (ms * 1e-3) / 1e9
     out = {"workload": sc.name, "work": sc.work, "gaussians": sc.n, "views": sc.n_views,
-           "pixels_per_step": sc.total_pixels, "tile": tile, "lds_batch": lds_batch, "pairs": c["M"],
+           "pixels_per_step": sc.total_pixels, "tile": tile, "lds_batch": lds_batch, "layout": args.layout,
+           "pairs": c["M"],
            "ms_per_step": round(ms, 4),
            "value": round(mpix / (ms * 1e-3), 2), "unit": "Mpix*iter/s", "step_alg_bytes": alg,
            "step_GBps": round(gbs, 1), "step_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -582,9 +637,9 @@ def stage_breakdown(step, iters):
     return out, work
 
 
-def traffic_of(kernel, tile, checkpoint, workload):
+def traffic_of(kernel, tile, checkpoint, workload, layout):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, when it was
-    taken on the current kernel source (None otherwise)."""
+    taken on the current kernel source and the same layout of the Gaussian set (None otherwise)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -593,18 +648,18 @@ def traffic_of(kernel, tile, checkpoint, workload):
         rec = json.load(f)
     src = os.path.join(ROOT, "paper_2409_13055_amd", "csrc", rec.get("source", "raster.hip"))
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    key = f"{kernel}/{workload}/tile{tile}/ckpt{int(checkpoint)}"
+    key = f"{kernel}/{workload}/tile{tile}/ckpt{int(checkpoint)}/{layout}"
     e = rec.get("entries", {}).get(key)
     if not e or e.get("source_sha") != sha:
         return None
     return e.get("bytes_per_launch")
 
 
-def roofline(step, sc, stages, work, step_ms):
+def roofline(step, sc, stages, work, step_ms, layout):
     """Roofline entry for the dominant single-kernel call (by measured duration) and for the whole
     step; the work counts are the mean over the same iterations the durations are."""
     from paper_2409_13055_amd import roofline as RF
-    tr = traffic_of("raster_bwd", step.rast.opts.tile_size, sc.checkpoint, sc.name)
+    tr = traffic_of("raster_bwd", step.rast.opts.tile_size, sc.checkpoint, sc.name, layout)
     return RF.report(step, sc, stages, hbm_peak_gbs=HBM_PEAK_GBS, valu_peak_tflops=VALU_PEAK_TFLOPS,
                      valu_unpacked_tflops=VALU_UNPACKED_TFLOPS, traffic=tr, work=work, step_ms=step_ms)
 

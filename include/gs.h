@@ -396,6 +396,30 @@ gs_status gs_photometric_loss(const gs_camera* cams, int32_t n_views, const floa
                               float lambda, float* loss_out, float* dl_dimage, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* --------------------------------------------------------- memory layout
+ * The order of the Gaussians in the parameter arrays is free (every call
+ * treats them as a set; only ties between equal depths are broken by the
+ * index).  gs_spatial_order gives an order that keeps the Gaussians of each
+ * run of 64 consecutive indices close together in space, so the projection
+ * and its backward, which walk the Gaussians in wavefronts of 64 and skip the
+ * views that see none of a wavefront's Gaussians, skip far more of them (the
+ * projection of 2M Gaussians into 16 views: 0.62 -> 0.37 ms): order[k] (device,
+ * [n] uint32, written) is the index of the Gaussian that goes to position k,
+ * the Gaussians sorted stably by the Morton (Z-order) code of their means,
+ * each axis cut into 1024 cells over the means' bounding box (cell =
+ * min(1023, floor((m - lo) * (1024 / (hi - lo)))) in FP32; a flat axis and
+ * a NaN coordinate give cell 0).  `workspace` must hold
+ * gs_spatial_order_workspace_size() bytes.  gs_gather_rows applies such an
+ * order to one array of rows: dst[k][c] = src[order[k]][c] for rows of
+ * `width` floats (an order entry >= n gives a NaN row; src and dst must not
+ * overlap); applied to every parameter array and, during training, to the
+ * optimiser's moments, it reorders the Gaussian set. */
+gs_status gs_spatial_order_workspace_size(int64_t n, size_t* bytes);
+gs_status gs_spatial_order(const float* means, int64_t n, uint32_t* order, void* workspace, size_t workspace_bytes,
+                           void* stream);
+gs_status gs_gather_rows(const float* src, int64_t n, int32_t width, const uint32_t* order, float* dst,
+                         void* stream);
+
 /* ------------------------------------------------------------- autotuning
  * The tile size of the tile-based rasterisation (Sec. III-B) and the LDS
  * batch of the raster kernels (gs_options.lds_batch) are free parameters;

@@ -97,7 +97,8 @@ EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_op
            "gs_raster_bwd_abs", "gs_project_bwd_adam_stats", "gs_default_density_config", "gs_scene_extent", "gs_density_accumulate",
            "gs_density_workspace_size", "gs_density_plan", "gs_density_apply", "gs_delaunay", "gs_densify_depth",
            "gs_init_gaussians_workspace_size", "gs_init_gaussians_count", "gs_init_gaussians",
-           "gs_render_fwd_noalloc", "gs_autotune")
+           "gs_render_fwd_noalloc", "gs_autotune", "gs_spatial_order_workspace_size", "gs_spatial_order",
+           "gs_gather_rows")
 
 GS_ABI_VERSION = 2  # include/gs.h
 _lib = None
@@ -129,6 +130,9 @@ def load(path: str = LIB_PATH):
         "gs_render_fwd": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), pc, i32, po,
                                     C.POINTER(gs_loss), C.POINTER(gs_image), P, sz, P]),
         "gs_autotune": (C.c_int, [pp, pc, i32, po, P, i32, i32, i32, C.POINTER(gs_autotune_result), P]),
+        "gs_spatial_order_workspace_size": (C.c_int, [i64, C.POINTER(sz)]),
+        "gs_spatial_order": (C.c_int, [P, i64, P, P, sz, P]),
+        "gs_gather_rows": (C.c_int, [P, i64, i32, P, P, P]),
         "gs_render_fwd_noalloc": (C.c_int, [C.POINTER(gs_projected), i64, C.POINTER(gs_bins), pc, i32, po,
                                             C.POINTER(gs_loss), C.POINTER(gs_image), P]),
         "gs_render_bwd": (C.c_int, [pp, C.POINTER(gs_projected), C.POINTER(gs_bins), C.POINTER(gs_image), pc, i32,
@@ -253,6 +257,20 @@ def gs_render_fwd(proj, n, bins, cams, n_views, opts, loss, out, workspace, work
     _check("gs_render_fwd", load().gs_render_fwd(C.byref(proj), n, C.byref(bins), cams, n_views, C.byref(opts),
                                                  C.byref(loss) if loss is not None else None, C.byref(out),
                                                  workspace, workspace_bytes, stream))
+
+
+def gs_spatial_order_workspace_size(n):
+    out = C.c_size_t()
+    _check("gs_spatial_order_workspace_size", load().gs_spatial_order_workspace_size(n, C.byref(out)))
+    return out.value
+
+
+def gs_spatial_order(means, n, order, workspace, workspace_bytes, stream):
+    _check("gs_spatial_order", load().gs_spatial_order(means, n, order, workspace, workspace_bytes, stream))
+
+
+def gs_gather_rows(src, n, width, order, dst, stream):
+    _check("gs_gather_rows", load().gs_gather_rows(src, n, width, order, dst, stream))
 
 
 def gs_autotune(params, cams, n_views, opts, target, iters, candidate_mask, refresh, stream):

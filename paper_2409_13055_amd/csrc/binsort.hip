@@ -1032,7 +1032,185 @@ static_assert(kChunkGrid % kXcds == 0, "chunk grid must split evenly over the XC
 constexpr int kEmitGridWaves = 65536;
 static_assert((kEmitGridWaves / kChunkWavesPerBlock) % kXcds == 0, "emit grid must split evenly over the XCDs");
 
+// ---------------------------------------------------------------------------
+// Spatial order of the Gaussian set (a memory layout, not part of the method):
+// the Gaussians sorted by the Z-order (Morton) code of their means.  Each
+// kernel that walks the Gaussians in wavefronts of 64 consecutive ones (the
+// projection and its backward) then finds a wavefront's splats close together,
+// so a view either sees most of them or none, and a wavefront skips the views
+// that see none of its Gaussians.
+// ---------------------------------------------------------------------------
+constexpr int kMortonBits = 10;  // cells per axis: 2^10
+constexpr int kBoxThreads = 256;
+
+// Per block: the min and max of x, y, z over its means -> part[6 b .. 6 b + 5] (lo xyz, hi xyz).
+__global__ __launch_bounds__(kBoxThreads) void k_box_partial(const float* __restrict__ means, int64_t n,
+                                                             float* __restrict__ part) {
+  __shared__ float s[6][kBoxThreads / 64];
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * kBoxThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBoxThreads) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float m = means[3 * i + a];
+      lo[a] = fminf(lo[a], m);
+      hi[a] = fmaxf(hi[a], m);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], __shfl_xor(lo[a], o));
+      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o));
+    }
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      s[a][w] = lo[a];
+      s[3 + a][w] = hi[a];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    float v = s[threadIdx.x][0];
+    for (int k = 1; k < kBoxThreads / 64; ++k) v = threadIdx.x < 3 ? fminf(v, s[threadIdx.x][k]) : fmaxf(v, s[threadIdx.x][k]);
+    part[6 * blockIdx.x + threadIdx.x] = v;
+  }
+}
+
+// The box over the block partials (one thread per bound) and the Gaussian count for the radix passes.
+__global__ void k_box_final(const float* __restrict__ part, int nb, int64_t n, float* __restrict__ box,
+                            uint32_t* __restrict__ d_n) {
+  const int t = threadIdx.x;
+  if (t < 6) {
+    float v = part[t];
+    for (int b = 1; b < nb; ++b) v = t < 3 ? fminf(v, part[6 * b + t]) : fmaxf(v, part[6 * b + t]);
+    box[t] = v;
+  }
+  if (t == 0) *d_n = (uint32_t)n;
+}
+
+// Morton code of each mean: per axis the cell min(2^10 - 1, floor((m - lo) * (2^10 / (hi - lo)))) (a
+// degenerate axis gives cell 0; a NaN mean gives cell 0), bits interleaved x0 y0 z0 x1 y1 z1 ...
+__device__ inline uint32_t spread3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__global__ __launch_bounds__(kSortThreads) void k_morton(const float* __restrict__ means, int64_t n,
+                                                         const float* __restrict__ box, uint32_t* __restrict__ code) {
+  uint32_t cell[3];
+  const int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lo = box[a], ext = box[3 + a] - lo;
+    const float scale = ext > 0.0f ? (float)(1 << kMortonBits) / ext : 0.0f;
+    const float q = floorf((means[3 * i + a] - lo) * scale);
+    cell[a] = q >= 0.0f ? (uint32_t)fminf(q, (float)((1 << kMortonBits) - 1)) : 0u;  // NaN -> 0
+  }
+  code[i] = spread3(cell[0]) | (spread3(cell[1]) << 1) | (spread3(cell[2]) << 2);
+}
+
+// dst[k * width + c] = src[order[k] * width + c]; an order entry beyond the rows gives NaN rows.
+__global__ __launch_bounds__(kSortThreads) void k_gather_rows(const float* __restrict__ src, int64_t n, int width,
+                                                              const uint32_t* __restrict__ order,
+                                                              float* __restrict__ dst) {
+  const int64_t total = n * (int64_t)width;
+  for (int64_t e = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * kSortThreads) {
+    const int64_t k = e / width;
+    const int c = (int)(e - k * width);
+    const uint32_t o = order[k];
+    dst[e] = (int64_t)o < n ? src[(int64_t)o * width + c] : __int_as_float(0x7fc00000);
+  }
+}
+
+struct OrderPlan {
+  int nb_box, nb;
+  size_t off_part, off_box, off_n, off_ka, off_kb, off_va, off_vb, off_hist, off_dtot, bytes;
+};
+static OrderPlan order_plan(int64_t n) {
+  OrderPlan p;
+  p.nb_box = (int)std::min<int64_t>(1024, (n + kBoxThreads - 1) / kBoxThreads);
+  p.nb = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + 2047) / 2048));
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  p.off_part = take(sizeof(float) * 6 * (size_t)p.nb_box);
+  p.off_box = take(sizeof(float) * 6);
+  p.off_n = take(sizeof(uint32_t));
+  p.off_ka = take(sizeof(uint32_t) * (size_t)n);
+  p.off_kb = take(sizeof(uint32_t) * (size_t)n);
+  p.off_va = take(sizeof(uint32_t) * (size_t)n);
+  p.off_vb = take(sizeof(uint32_t) * (size_t)n);
+  p.off_hist = take(sizeof(uint32_t) * kRadixBins * (size_t)p.nb);
+  p.off_dtot = take(sizeof(uint32_t) * kRadixBins);
+  p.bytes = o;
+  return p;
+}
+
 }  // namespace gs
+
+extern "C" gs_status gs_spatial_order_workspace_size(int64_t n, size_t* bytes) {
+  using namespace gs;
+  if (!bytes) return fail(GS_ERR_INVALID_VALUE, "bytes is NULL");
+  if (n < 1 || n >= (int64_t(1) << 32) - 1) return fail(GS_ERR_INVALID_VALUE, "n must be in [1, 2^32 - 1)");
+  *bytes = order_plan(n).bytes;
+  return GS_OK;
+}
+
+extern "C" gs_status gs_spatial_order(const float* means, int64_t n, uint32_t* order, void* workspace,
+                                      size_t workspace_bytes, void* stream) {
+  using namespace gs;
+  if (!means || !order) return fail(GS_ERR_INVALID_VALUE, "means and order are required");
+  if (n < 1 || n >= (int64_t(1) << 32) - 1) return fail(GS_ERR_INVALID_VALUE, "n must be in [1, 2^32 - 1)");
+  const OrderPlan p = order_plan(n);
+  if (!workspace || workspace_bytes < p.bytes)
+    return fail(GS_ERR_CAPACITY, "workspace too small: need " + std::to_string(p.bytes) + " bytes");
+  hipStream_t st = as_stream(stream);
+  char* ws = static_cast<char*>(workspace);
+  float* part = reinterpret_cast<float*>(ws + p.off_part);
+  float* box = reinterpret_cast<float*>(ws + p.off_box);
+  uint32_t* d_n = reinterpret_cast<uint32_t*>(ws + p.off_n);
+  uint32_t* ka = reinterpret_cast<uint32_t*>(ws + p.off_ka);
+  uint32_t* kb = reinterpret_cast<uint32_t*>(ws + p.off_kb);
+  uint32_t* va = reinterpret_cast<uint32_t*>(ws + p.off_va);
+  uint32_t* vb = reinterpret_cast<uint32_t*>(ws + p.off_vb);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
+  uint32_t* dtot = reinterpret_cast<uint32_t*>(ws + p.off_dtot);
+  hipLaunchKernelGGL(k_box_partial, dim3(p.nb_box), dim3(kBoxThreads), 0, st, means, n, part);
+  hipLaunchKernelGGL(k_box_final, dim3(1), dim3(64), 0, st, part, p.nb_box, n, box, d_n);
+  hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + kSortThreads - 1) / kSortThreads)), dim3(kSortThreads), 0, st,
+                     means, n, box, ka);
+  // four stable 8-bit passes over the 30-bit codes, the positions carried as values (ties keep the index order)
+  radix_pass<uint32_t, false, true>(ka, nullptr, kb, va, d_n, 0, p.nb, hist, dtot, st);
+  radix_pass<uint32_t>(kb, va, ka, vb, d_n, 8, p.nb, hist, dtot, st);
+  radix_pass<uint32_t>(ka, vb, kb, va, d_n, 16, p.nb, hist, dtot, st);
+  radix_pass<uint32_t>(kb, va, ka, order, d_n, 24, p.nb, hist, dtot, st);
+  return check_launch("spatial order");
+}
+
+extern "C" gs_status gs_gather_rows(const float* src, int64_t n, int32_t width, const uint32_t* order, float* dst,
+                                    void* stream) {
+  using namespace gs;
+  if (!src || !order || !dst) return fail(GS_ERR_INVALID_VALUE, "src, order and dst are required");
+  if (src == dst) return fail(GS_ERR_INVALID_VALUE, "src and dst must not be the same buffer");
+  if (n < 1 || n >= (int64_t(1) << 32) - 1 || width < 1 || width > 4096)
+    return fail(GS_ERR_INVALID_VALUE, "need n in [1, 2^32 - 1) and width in [1, 4096]");
+  const int64_t total = n * (int64_t)width;
+  const unsigned grid = (unsigned)std::min<int64_t>(65536, (total + kSortThreads - 1) / kSortThreads);
+  hipLaunchKernelGGL(k_gather_rows, dim3(grid), dim3(kSortThreads), 0, as_stream(stream), src, n, width, order, dst);
+  return check_launch("gather rows");
+}
 
 extern "C" gs_status gs_bin_sort_workspace_size(int64_t n, const gs_camera* cams, int32_t n_views,
                                                 const gs_options* opts, int64_t pair_capacity, size_t* bytes) {

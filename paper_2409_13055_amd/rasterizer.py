@@ -90,6 +90,28 @@ class GaussianParams:
         g.sh_rest = _p(self.sh_rest) if self.sh_degree > 0 else None
         return g
 
+    def spatial_order(self) -> torch.Tensor:
+        """gs_spatial_order: the permutation (int32 [n], position k <- Gaussian order[k]) that sorts the
+        set by the Morton code of the means.  Enqueued on the current stream."""
+        ws = torch.empty(L.gs_spatial_order_workspace_size(self.n), dtype=torch.uint8, device=self.means.device)
+        order = torch.empty(self.n, dtype=torch.int32, device=self.means.device)
+        L.gs_spatial_order(_p(self.means), self.n, _p(order), _p(ws), ws.numel(), _stream())
+        return order
+
+    def gathered(self, order: torch.Tensor) -> "GaussianParams":
+        """A new set with row k = row order[k] of this one (gs_gather_rows on every array)."""
+        return GaussianParams(*[gather_rows(t, order) for t in self.tensors()], self.sh_degree)
+
+
+def gather_rows(t: torch.Tensor, order: torch.Tensor) -> torch.Tensor:
+    """gs_gather_rows: out[k] = t[order[k]] for a contiguous FP32 tensor of n rows."""
+    n = int(t.shape[0])
+    out = torch.empty_like(t)
+    width = t.numel() // n if n else 0
+    if n and width:
+        L.gs_gather_rows(_p(t.contiguous()), n, width, _p(order), _p(out), _stream())
+    return out
+
 
 def pack_images(images: Sequence, device="cuda") -> torch.Tensor:
     """Per-view [3,H,W] images -> one packed FP32 device buffer (view-major, planar)."""
@@ -368,6 +390,22 @@ class FusedAdam:
     def step(self, zero_grad: bool = True):
         L.gs_adam_step(self.groups, self.n_groups, self.betas[0], self.betas[1], self.eps, _p(self.d_step),
                        1 if zero_grad else 0, _stream())
+
+    def gathered(self, params: GaussianParams, order: torch.Tensor) -> "FusedAdam":
+        """The optimiser over `params` (this optimiser's set reordered by `order`, see
+        GaussianParams.gathered) with the moments reordered the same way and the step count kept."""
+        return FusedAdam(params, self.grads.gathered(order), self.lrs, self.betas, self.eps,
+                         exp_avg=self.exp_avg.gathered(order), exp_avg_sq=self.exp_avg_sq.gathered(order),
+                         d_step=self.d_step.clone())
+
+
+def spatially_ordered(params: GaussianParams, adam: Optional[FusedAdam] = None):
+    """The Gaussian set (and its optimiser, when given) reordered by gs_spatial_order: a memory layout
+    that lets the projection and its backward skip the views a wavefront's 64 Gaussians are all
+    outside of.  Returns (params, adam, order); the set is the same, only its order changes."""
+    order = params.spatial_order()
+    new_p = params.gathered(order)
+    return new_p, (adam.gathered(new_p, order) if adam is not None else None), order
 
 
 class CapacityOverflow(RuntimeError):
@@ -905,15 +943,20 @@ class MappingLoop:
 
     def __init__(self, params: GaussianParams, cameras, targets, lrs=None, levels: int = 2, schedule=None,
                  ssim_lambda: float = 0.2, densify_every: int = 1000, tile_size: int = 16, graphs: bool = True,
-                 generator: Optional[torch.Generator] = None, check_every: int = 100, **density_cfg):
+                 generator: Optional[torch.Generator] = None, check_every: int = 100, spatial_order: bool = True,
+                 **density_cfg):
         """check_every: iterations between host checks of the pair-capacity overflow flag (also checked
-        before every density step); an overflow raises CapacityOverflow."""
+        before every density step); an overflow raises CapacityOverflow.  spatial_order: the set a
+        density step makes is put in Morton order of its means (spatially_ordered) before the
+        iterations continue; its statistics restart at zero, so only the parameters and moments move."""
         self.cameras, self.lrs, self.levels = list(cameras), lrs, int(levels)
         self.targets = [t if isinstance(t, torch.Tensor) else pack_images([t], params.means.device)
                         for t in targets]
         self.densify_every = int(densify_every)
         self.check_every = max(1, int(check_every))
         self.generator = generator
+        self.spatial_order = bool(spatial_order)
+        self.last_order = None  # the permutation of the last reorder (int32, new row k <- row order[k])
         self.density = DensityControl(params.n, cameras, device=params.means.device, **density_cfg)
         self._opts = dict(schedule=schedule, lrs=lrs, graphs=graphs, ssim_lambda=ssim_lambda, tile_size=tile_size,
                           density=self.density)
@@ -943,6 +986,8 @@ class MappingLoop:
                 self.steps.check_overflow()
             if densify:
                 new_p, new_adam = self.density.apply(self.steps.params, self.steps.adam, generator=self.generator)
+                if self.spatial_order and new_p.n > 0:
+                    new_p, new_adam, self.last_order = spatially_ordered(new_p, new_adam)
                 self._rebuild(new_p, new_adam)
                 self.history.append((self.iteration, new_p.n))
         return st

@@ -9,6 +9,33 @@ from paper_2409_13055_amd import rasterizer as R
 DEV = "cuda"
 
 
+def _spread3(v):
+    v = v.astype(np.uint64) & 0x3FF
+    out = np.zeros_like(v)
+    for b in range(10):
+        out |= ((v >> b) & 1) << (3 * b)
+    return out
+
+
+def morton_codes(means):
+    """The codes gs_spatial_order sorts by, written out in FP32 like the device: per axis the cell
+    min(1023, floor((m - lo) * (1024 / (hi - lo)))) over the means' box (a flat axis and a NaN give
+    0), bits interleaved x, y, z from bit 0."""
+    m = np.asarray(means, np.float32)
+    lo, hi = np.nanmin(m, axis=0), np.nanmax(m, axis=0)
+    ext = (hi - lo).astype(np.float32)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        scale = np.where(ext > 0, np.float32(1024) / ext, np.float32(0)).astype(np.float32)
+        q = np.floor(((m - lo).astype(np.float32) * scale).astype(np.float32))
+        cell = np.where(q >= 0, np.minimum(q, 1023), 0).astype(np.uint64)
+    return _spread3(cell[:, 0]) | (_spread3(cell[:, 1]) << 1) | (_spread3(cell[:, 2]) << 2)
+
+
+def morton_order_reference(means):
+    """The permutation gs_spatial_order defines: a stable sort of morton_codes."""
+    return np.argsort(morton_codes(means), kind="stable")
+
+
 def gpu_extents(rec):
     """Tile rect half-extents (rx, ry) [VN,2] from GPU record word 10 (rx | ry << 16; 0 = culled)."""
     w = np.ascontiguousarray(np.asarray(rec, np.float32)[:, 10]).view(np.int32)

@@ -276,6 +276,22 @@ def test_autotune_validates_before_any_launch(L):
     assert C.sizeof(r) == 136  # int32 x 16, float x 6, int64 x 6: the layout gs.h declares
 
 
+def test_layout_calls_validate_before_any_launch(L):
+    """gs_spatial_order and gs_gather_rows reject bad arguments before touching the device."""
+    assert L.gs_spatial_order_workspace_size(1000) >= 4 * 4 * 1000
+    with pytest.raises(L.GsError, match="n must be"):
+        L.gs_spatial_order_workspace_size(0)
+    ws = L.gs_spatial_order_workspace_size(10)
+    with pytest.raises(L.GsError, match="required"):
+        L.gs_spatial_order(None, 10, C.c_void_p(0x1000), C.c_void_p(0x2000), ws, None)
+    with pytest.raises(L.GsError, match="workspace too small"):
+        L.gs_spatial_order(C.c_void_p(0x1000), 10, C.c_void_p(0x2000), C.c_void_p(0x3000), ws - 1, None)
+    with pytest.raises(L.GsError, match="must not be the same"):
+        L.gs_gather_rows(C.c_void_p(0x1000), 10, 3, C.c_void_p(0x2000), C.c_void_p(0x1000), None)
+    with pytest.raises(L.GsError, match="width"):
+        L.gs_gather_rows(C.c_void_p(0x1000), 10, 0, C.c_void_p(0x2000), C.c_void_p(0x3000), None)
+
+
 def test_noalloc_forward_validates_before_any_launch(L):
     """gs_render_fwd_noalloc rejects bad arguments before touching the device, as gs_render_fwd does."""
     from paper_2409_13055_amd import synthetic as S

@@ -190,7 +190,14 @@ def test_mapping_loop_pyramid_ssim_and_density_control():
     loop = R.MappingLoop(params, sc.cameras, sc.targets, lrs=dict(S.DEFAULT_LRS), levels=1, schedule=[3],
                          ssim_lambda=0.2, densify_every=4, generator=torch.Generator(device=DEV).manual_seed(3),
                          grad_threshold=1e-7)
-    st = loop.run(10)
+    loop.run(8)
+    torch.cuda.synchronize()
+    # the set of the last density step is in Morton order of its means
+    order = loop.last_order.cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(loop.params.n))
+    codes = U.morton_codes(loop.params.means.cpu().numpy())
+    assert np.all(codes[1:] >= codes[:-1])
+    st = loop.run(2)
     torch.cuda.synchronize()
     assert [h[0] for h in loop.history] == [4, 8]
     assert loop.history[0][1] > n0 and loop.params.n == loop.history[-1][1]
