@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 2
+#define GS_ABI_VERSION 3
 #define GS_MAX_VIEWS 32
 #define GS_MAX_SH_DEGREE 3
 /* floats per projected record, see gs_projected */
@@ -120,12 +120,17 @@ typedef struct gs_options {
   float radius_sigmas;   /* radius = ceil(radius_sigmas*sqrt(lambda_max)) (3) */
   float frustum_guard;   /* Jacobian uses x/z clamped to +-guard*(W/2)/fx (1.3) */
   float bg[3];           /* background colour (0,0,0) */
-  uint32_t flags;        /* reserved, must be 0 */
+  uint32_t flags;        /* GS_OPT_* bits below; other bits must be 0 (0) */
   int32_t lds_batch;     /* splat records each lane of a raster workgroup
                             stages into LDS per batch: 1 or 2 (1); the
                             batch is lds_batch x the workgroup's threads.
                             Every output is the same for either value. */
 } gs_options;
+
+/* gs_options.flags: the bins are window lists (see gs_bins) instead of tile
+ * lists.  gs_bin_sort then stops after the window lists, and every raster
+ * call takes each tile's entries from its window's list. */
+#define GS_OPT_WINDOW_LISTS 1u
 
 void gs_default_options(gs_options* opts);
 
@@ -163,14 +168,36 @@ typedef struct gs_projected {
   uint32_t* vis_count;
 } gs_projected;
 
-/* Tile bins.  keys [capacity] (may be NULL: not written), ids [capacity],
- * ranges [total_tiles][2].  After gs_bin_sort the first M entries of ids
- * hold v*N+i of every (pair, tile) incidence ordered by (global tile,
- * FP32 bit pattern of the depth, v*N+i); keys[p] = (tile << 32) | depth bits;
- * ranges[t] = [first, last+1) of tile t, (0,0) for an empty tile.
- * d_num_pairs (device int64) receives M; d_overflow (device int32) receives
- * 1 when M > capacity, in which case keys/ids/ranges are undefined and the
- * caller must grow the buffers and call again (0 otherwise). */
+/* Bins, in one of two forms chosen by GS_OPT_WINDOW_LISTS.
+ *
+ * Tile lists (the flag clear).  keys [capacity] (may be NULL: not written),
+ * ids [capacity], ranges [total_tiles][2].  After gs_bin_sort the first M
+ * entries of ids hold v*N+i of every (pair, tile) incidence ordered by
+ * (global tile, FP32 bit pattern of the depth, v*N+i); keys[p] =
+ * (tile << 32) | depth bits; ranges[t] = [first, last+1) of tile t, (0,0) for
+ * an empty tile.  d_overflow receives 1 when M > capacity.
+ *
+ * Window lists (the flag set).  A binning window is a block of 8 x 8 tiles of
+ * one view: window (wx, wy) of view v has global index win_off(v) +
+ * wy * WX(v) + wx, WX(v) = ceil(TX(v) / 8), windows numbered view by view
+ * (gs_total_windows gives their count W).  items [capacity][2] (8-byte
+ * aligned) holds, window after window, one item per (pair, window) whose
+ * tile rect meets the window: (v*N+i, lx0 | lx1 << 4 | ly0 << 8 | ly1 << 12),
+ * the rect clipped to the window in the window's tile coordinates,
+ * [lx0, lx1) x [ly0, ly1) inside [0, 8]^2.  Within a window the items are
+ * ordered by (FP32 bit pattern of the depth, v*N+i).  win_ranges [2][W]:
+ * win_ranges[w] = first item of window w, win_ranges[W + w] = one past its
+ * last ((0, 0) for an empty window).  The tile list of tile (tx, ty) is then
+ * the items of its window (tx / 8, ty / 8) whose clipped rect covers
+ * (tx mod 8, ty mod 8), in window order: the same entries in the same order
+ * as the tile-list form.  d_num_items (device int64, may be NULL) receives
+ * the item count E; d_overflow receives 1 when E > capacity.  ids, keys and
+ * ranges are not used.
+ *
+ * Both forms: d_num_pairs (device int64) receives M, the number of
+ * (pair, tile) incidences.  On overflow the lists are undefined, every range
+ * is empty (a raster call then renders the background), and the caller must
+ * grow the buffers and call again (d_overflow 0 otherwise). */
 typedef struct gs_bins {
   uint64_t* keys;
   uint32_t* ids;
@@ -178,6 +205,9 @@ typedef struct gs_bins {
   int64_t capacity;
   int64_t* d_num_pairs;
   int32_t* d_overflow;
+  uint32_t* items;
+  uint32_t* win_ranges;
+  int64_t* d_num_items;
 } gs_bins;
 
 /* Rendered views.  rgb [sum_v 3*H_v*W_v]: view v at 3*pix_off(v), planar
@@ -225,8 +255,11 @@ typedef struct gs_grads {
 /* Total tiles / pixels of a set of views at a tile size (host only). */
 gs_status gs_total_tiles(const gs_camera* cams, int32_t n_views, int32_t tile_size, int64_t* out);
 gs_status gs_total_pixels(const gs_camera* cams, int32_t n_views, int64_t* out);
-/* Workspace bytes of gs_bin_sort for n Gaussians, these views and a pair
- * capacity. */
+/* Binning windows (8 x 8 tiles of one view) of a set of views at a tile size. */
+gs_status gs_total_windows(const gs_camera* cams, int32_t n_views, int32_t tile_size, int64_t* out);
+/* Workspace bytes of gs_bin_sort for n Gaussians, these views and the
+ * capacity of the bins (gs_bins.capacity: incidences for tile lists, items
+ * for window lists). */
 gs_status gs_bin_sort_workspace_size(int64_t n, const gs_camera* cams, int32_t n_views, const gs_options* opts,
                                      int64_t pair_capacity, size_t* bytes);
 /* Workspace bytes of gs_render_fwd (per-tile loss partials) and
@@ -257,8 +290,11 @@ gs_status gs_project(const gs_params* params, const gs_camera* cams, int32_t n_v
  * read from proj->vis / proj->vis_count as gs_project wrote them, which must
  * be for the same n, cameras and n_views (their ids number the views of that
  * call; a sub-batch of views is projected by a call of its own); proj->rec is
- * read for the depths of bins->keys.  `workspace` must hold
- * gs_bin_sort_workspace_size() bytes for the same arguments. */
+ * read for the depths of bins->keys.  With GS_OPT_WINDOW_LISTS the call
+ * writes the window lists instead (every pair listed once per window its
+ * rect meets, then a stable sort on the window index) and no tile list.
+ * `workspace` must hold gs_bin_sort_workspace_size() bytes for the same
+ * arguments. */
 gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n_views,
                       const gs_options* opts, const gs_bins* bins, void* workspace, size_t workspace_bytes,
                       void* stream);

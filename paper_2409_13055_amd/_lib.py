@@ -53,7 +53,7 @@ class gs_projected(C.Structure):
 
 class gs_bins(C.Structure):
     _fields_ = [("keys", P), ("ids", P), ("ranges", P), ("capacity", C.c_int64), ("d_num_pairs", P),
-                ("d_overflow", P)]
+                ("d_overflow", P), ("items", P), ("win_ranges", P), ("d_num_items", P)]
 
 
 class gs_image(C.Structure):
@@ -90,7 +90,7 @@ class gs_autotune_result(C.Structure):
 
 
 EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_options", "gs_total_tiles",
-           "gs_total_pixels", "gs_bin_sort_workspace_size", "gs_render_fwd_workspace_size",
+           "gs_total_pixels", "gs_total_windows", "gs_bin_sort_workspace_size", "gs_render_fwd_workspace_size",
            "gs_render_bwd_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_raster_bwd", "gs_project_bwd", "gs_render_stats", "gs_adam_step", "gs_project_bwd_adam",
            "gs_photometric_loss_workspace_size", "gs_photometric_loss", "gs_pyramid_camera", "gs_pyramid_reduce",
@@ -100,7 +100,8 @@ EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_op
            "gs_render_fwd_noalloc", "gs_autotune", "gs_spatial_order_workspace_size", "gs_spatial_order",
            "gs_gather_rows")
 
-GS_ABI_VERSION = 2  # include/gs.h
+GS_ABI_VERSION = 3  # include/gs.h
+GS_OPT_WINDOW_LISTS = 1  # gs_options.flags
 _lib = None
 
 
@@ -122,6 +123,7 @@ def load(path: str = LIB_PATH):
         "gs_default_options": (None, [po]),
         "gs_total_tiles": (C.c_int, [pc, i32, i32, C.POINTER(i64)]),
         "gs_total_pixels": (C.c_int, [pc, i32, C.POINTER(i64)]),
+        "gs_total_windows": (C.c_int, [pc, i32, i32, C.POINTER(i64)]),
         "gs_bin_sort_workspace_size": (C.c_int, [i64, pc, i32, po, i64, C.POINTER(sz)]),
         "gs_render_fwd_workspace_size": (C.c_int, [pc, i32, po, C.POINTER(sz)]),
         "gs_render_bwd_workspace_size": (C.c_int, [i64, i32, C.POINTER(sz)]),
@@ -215,6 +217,12 @@ def make_cameras(cams) -> C.Array:
 def gs_total_tiles(cams, n_views, tile_size) -> int:
     out = C.c_int64(0)
     _check("gs_total_tiles", load().gs_total_tiles(cams, n_views, tile_size, C.byref(out)))
+    return out.value
+
+
+def gs_total_windows(cams, n_views, tile_size) -> int:
+    out = C.c_int64()
+    _check("gs_total_windows", load().gs_total_windows(cams, n_views, tile_size, C.byref(out)))
     return out.value
 
 

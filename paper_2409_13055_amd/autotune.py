@@ -4,9 +4,10 @@ gs_autotune times one iteration of the actual problem (projection, bin/sort,
 forward with the L1 term, raster backward, projection backward) for every
 candidate pair of tile size (8, 16, 32) and LDS batch of the raster kernels
 (one or two splat records per lane) on the current stream and keeps the
-fastest.  The library caches the result per (Gaussian-count bucket,
-resolution multiset, SH degree, checkpoint, candidates) for the life of the
-process.  Tile size changes which tiles a splat is binned into, so parity is
+fastest, with the bins in the form the rasteriser will use (window lists by
+default).  The library caches the result per (Gaussian-count bucket,
+resolution multiset, SH degree, checkpoint, option flags, candidates) for the
+life of the process.  Tile size changes which tiles a splat is binned into, so parity is
 always checked at the chosen size; the LDS batch changes no output.  This
 module only marshals the arguments.
 """
@@ -22,12 +23,14 @@ _BATCHES = (1, 2)
 
 
 def autotune_tile(params: R.GaussianParams, cameras, target: torch.Tensor, checkpoint=False, candidates=_TILES,
-                  batches=_BATCHES, iters=3, refresh=False):
+                  batches=_BATCHES, iters=3, refresh=False, lists="window"):
     """Returns {"best": tile, "lds_batch": b, "ms_fwd_bwd": {"tile/batch": ms}, "pairs": {tile: M},
     "from_cache": bool} (ms -1 for a candidate that did not fit in device memory)."""
     L.load()
     cams = L.make_cameras(list(cameras))
     opts = L.default_options(checkpoint=int(checkpoint))
+    if lists == "window":
+        opts.flags |= L.GS_OPT_WINDOW_LISTS
     mask = sum(1 << _TILES.index(int(t)) for t in candidates) | \
         sum(1 << (3 + _BATCHES.index(int(b))) for b in batches)
     torch.cuda.synchronize()

@@ -62,7 +62,7 @@ gs_status validate_opts(const gs_options* o) {
     return fail(GS_ERR_INVALID_VALUE, "frustum_guard must be > 0");
   for (int k = 0; k < 3; ++k)
     if (!finite(o->bg[k])) return fail(GS_ERR_INVALID_VALUE, "bg must be finite");
-  if (o->flags != 0) return fail(GS_ERR_INVALID_VALUE, "flags must be 0");
+  if ((o->flags & ~GS_OPT_WINDOW_LISTS) != 0) return fail(GS_ERR_INVALID_VALUE, "unknown bits in flags");
   if (o->lds_batch != 1 && o->lds_batch != 2) return fail(GS_ERR_UNSUPPORTED, "lds_batch must be 1 or 2");
   return GS_OK;
 }
@@ -157,6 +157,16 @@ gs_status gs_total_tiles(const gs_camera* cams, int32_t n_views, int32_t tile_si
   if (tile_size != 8 && tile_size != 16 && tile_size != 32)
     return gs::fail(GS_ERR_UNSUPPORTED, "tile_size must be 8, 16 or 32");
   *out = gs::make_view_table(cams, n_views, tile_size).total_tiles;
+  return GS_OK;
+}
+
+gs_status gs_total_windows(const gs_camera* cams, int32_t n_views, int32_t tile_size, int64_t* out) {
+  gs_status s = gs::validate_cams(cams, n_views);
+  if (s != GS_OK) return s;
+  if (!out) return gs::fail(GS_ERR_INVALID_VALUE, "out is NULL");
+  if (tile_size != 8 && tile_size != 16 && tile_size != 32)
+    return gs::fail(GS_ERR_UNSUPPORTED, "tile_size must be 8, 16 or 32");
+  *out = gs::make_view_table(cams, n_views, tile_size).total_windows;
   return GS_OK;
 }
 

@@ -47,6 +47,7 @@ std::vector<int64_t> cache_key(const gs_params* p, const gs_camera* cams, int32_
   key.push_back((int64_t)std::floor(std::log2((double)std::max<int64_t>(p->n, 1))));
   key.push_back(p->sh_degree);
   key.push_back(o->checkpoint);
+  key.push_back((int64_t)o->flags);
   key.push_back(mask);
   std::vector<int64_t> res;
   for (int v = 0; v < n_views; ++v) res.push_back((int64_t)cams[v].width << 32 | (int64_t)cams[v].height);
@@ -74,7 +75,8 @@ gs_status time_candidate(const gs_params* params, const gs_camera* cams, int32_t
   const int K = (params->sh_degree + 1) * (params->sh_degree + 1);
   DeviceBuffers buf;
   void *rec, *tt, *vis, *vcnt, *ranges, *np, *ovf, *rgb, *tfin = nullptr, *ncon = nullptr, *wsf, *lout, *g2;
-  void *gm, *gs_, *gq, *go, *gdc, *grest = nullptr, *ids = nullptr, *wss = nullptr;
+  void *gm, *gs_, *gq, *go, *gdc, *grest = nullptr, *ids = nullptr, *wss = nullptr, *wr = nullptr, *ni = nullptr;
+  const bool win = (o.flags & GS_OPT_WINDOW_LISTS) != 0;
   size_t fwd_bytes = 0;
   gs_status s = gs_render_fwd_workspace_size(cams, n_views, &o, &fwd_bytes);
   if (s != GS_OK) return s;
@@ -88,7 +90,9 @@ gs_status time_candidate(const gs_params* params, const gs_camera* cams, int32_t
   A(&vcnt, sizeof(uint32_t) * S);
   A(&ranges, sizeof(uint32_t) * 2 * vt.total_tiles);
   A(&np, sizeof(int64_t));
+  A(&ni, sizeof(int64_t));
   A(&ovf, sizeof(int32_t));
+  if (win) A(&wr, sizeof(uint32_t) * 2 * (size_t)std::max(vt.total_windows, 1));
   A(&rgb, sizeof(float) * 3 * Px);
   if (!o.checkpoint) {
     A(&tfin, sizeof(float) * Px);
@@ -111,7 +115,7 @@ gs_status time_candidate(const gs_params* params, const gs_camera* cams, int32_t
   const gs_projected proj{static_cast<float*>(rec), static_cast<int32_t*>(tt), static_cast<uint32_t*>(vis),
                           static_cast<uint32_t*>(vcnt)};
   gs_bins bins{nullptr, nullptr, static_cast<uint32_t*>(ranges), 0, static_cast<int64_t*>(np),
-               static_cast<int32_t*>(ovf)};
+               static_cast<int32_t*>(ovf), nullptr, static_cast<uint32_t*>(wr), static_cast<int64_t*>(ni)};
   const gs_image img{static_cast<float*>(rgb), static_cast<float*>(tfin), static_cast<int32_t*>(ncon)};
   gs_loss loss{};
   loss.kind = GS_LOSS_L1;
@@ -119,35 +123,39 @@ gs_status time_candidate(const gs_params* params, const gs_camera* cams, int32_t
   loss.loss_out = static_cast<float*>(lout);
   const gs_grads grads{static_cast<float*>(gm), static_cast<float*>(gs_), static_cast<float*>(gq),
                        static_cast<float*>(go), static_cast<float*>(gdc), static_cast<float*>(grest)};
-  // pair count: a sort with capacity 0 reports it
+  // pair (and window item) count: a sort with capacity 0 reports it
   size_t ws_bytes = 0;
   if ((s = gs_bin_sort_workspace_size(n, cams, n_views, &o, 0, &ws_bytes)) != GS_OK) return s;
   A(&wss, ws_bytes);
-  A(&ids, sizeof(uint32_t));
+  A(&ids, sizeof(uint32_t) * 2);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
     return GS_OK;
   }
   if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("gs_autotune: hipMalloc: ") + hipGetErrorString(e));
   bins.ids = static_cast<uint32_t*>(ids);
+  bins.items = static_cast<uint32_t*>(ids);
   if ((s = gs_project(params, cams, n_views, &o, &proj, st)) != GS_OK) return s;
   if ((s = gs_bin_sort(&proj, n, cams, n_views, &o, &bins, wss, ws_bytes, st)) != GS_OK) return s;
-  int64_t m = 0;
+  int64_t m = 0, items = 0;
   e = hipMemcpyAsync(&m, np, sizeof m, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&items, ni, sizeof items, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("gs_autotune: ") + hipGetErrorString(e));
   *pairs = m;
-  const int64_t cap = (int64_t)std::ceil((double)m * 1.25) + 1024;
+  // the capacity bounds the incidences (tile lists) or the window items (window lists)
+  const int64_t cap = (int64_t)std::ceil((double)(win ? items : m) * 1.25) + 1024;
   if (cap >= (int64_t(1) << 32) - 1) return GS_OK;  // beyond the 32-bit pair index space: skipped
   if ((s = gs_bin_sort_workspace_size(n, cams, n_views, &o, cap, &ws_bytes)) != GS_OK) return s;
   A(&wss, ws_bytes);
-  A(&ids, sizeof(uint32_t) * (size_t)cap);
+  A(&ids, (win ? sizeof(uint2) : sizeof(uint32_t)) * (size_t)cap);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
     return GS_OK;
   }
   if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("gs_autotune: hipMalloc: ") + hipGetErrorString(e));
-  bins.ids = static_cast<uint32_t*>(ids);
+  bins.ids = win ? nullptr : static_cast<uint32_t*>(ids);
+  bins.items = win ? static_cast<uint32_t*>(ids) : nullptr;
   bins.capacity = cap;
   auto iteration = [&]() -> gs_status {
     gs_status r;

@@ -473,7 +473,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_step_counts(uint64_t* __r
                                                                    uint32_t* __restrict__ d_m,
                                                                    int64_t* __restrict__ d_pairs,
                                                                    int32_t* __restrict__ d_overflow,
-                                                                   uint64_t capacity) {
+                                                                   int64_t* __restrict__ d_items,
+                                                                   uint64_t capacity, int items_bound) {
   __shared__ uint64_t s_w[kScanThreads / 64];
   const uint32_t nsteps = (*d_k + kStep - 1) / kStep;
   uint64_t carry_w = 0, carry_t = 0;
@@ -503,10 +504,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_step_counts(uint64_t* __r
     carry_t += tt;
   }
   if (threadIdx.x == 0) {
-    const bool over = carry_t > capacity;
+    // the capacity bounds the incidences (tile lists) or the items (window lists)
+    const bool over = (items_bound ? carry_w : carry_t) > capacity;
     *d_pairs = (int64_t)carry_t;
+    if (d_items) *d_items = (int64_t)carry_w;
     *d_overflow = over ? 1 : 0;
-    // every item holds at least one incidence, so the item count fits too
+    // with tile lists every item holds at least one incidence, so the item count fits too
     *d_m = over ? 0u : (uint32_t)carry_t;
     *d_e = over ? 0u : (uint32_t)carry_w;
   }
@@ -1235,8 +1238,13 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   if ((s = validate_opts(opts)) != GS_OK) return s;
   if (!proj || !proj->rec || !proj->vis || !proj->vis_count) return fail(GS_ERR_INVALID_VALUE, "proj is incomplete");
   if (reinterpret_cast<uintptr_t>(proj->vis) % 16 != 0) return fail(GS_ERR_INVALID_VALUE, "vis must be 16-byte aligned");
-  if (!bins || !bins->ids || !bins->ranges || !bins->d_num_pairs || !bins->d_overflow)
-    return fail(GS_ERR_INVALID_VALUE, "bins is incomplete");
+  const bool win_lists = (opts->flags & GS_OPT_WINDOW_LISTS) != 0;
+  if (!bins || !bins->d_num_pairs || !bins->d_overflow) return fail(GS_ERR_INVALID_VALUE, "bins is incomplete");
+  if (win_lists ? (!bins->items || !bins->win_ranges) : (!bins->ids || !bins->ranges))
+    return fail(GS_ERR_INVALID_VALUE, win_lists ? "window lists need bins->items and bins->win_ranges"
+                                                : "tile lists need bins->ids and bins->ranges");
+  if (win_lists && reinterpret_cast<uintptr_t>(bins->items) % 8 != 0)
+    return fail(GS_ERR_INVALID_VALUE, "bins->items must be 8-byte aligned");
   if (n < 1 || (int64_t)n_views * n >= (int64_t(1) << 32) - 1) return fail(GS_ERR_INVALID_VALUE, "bad n");
   if (bins->capacity < 0 || bins->capacity >= (int64_t(1) << 32) - 1)
     return fail(GS_ERR_INVALID_VALUE, "bins->capacity must be in [0, 2^32 - 1)");
@@ -1287,15 +1295,31 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   radix_pass<uint32_t, true>(bkey, bval, nullptr, ent, d_k, 24, p.nb_vn, hist, dtot, st, entc);
   hipLaunchKernelGGL(k_step_counts, dim3(p.grid_steps), dim3(kSortThreads), 0, st, ent, d_k, step_win, step_tiles);
   hipLaunchKernelGGL(k_scan_step_counts, dim3(1), dim3(kScanThreads), 0, st, step_win, step_tiles, d_k, d_e, d_m,
-                     bins->d_num_pairs, bins->d_overflow, p.cap);
+                     bins->d_num_pairs, bins->d_overflow, bins->d_num_items, p.cap, win_lists ? 1 : 0);
   // 4. (window, item) pairs in depth order, stably sorted on the window index
   hipLaunchKernelGGL(k_window_items, dim3(p.grid_steps), dim3(kSortThreads), 0, st, ent, d_k, d_e, step_win, vt,
                      (uint32_t)n, wkey[0], witem[0]);
+  // (window lists: the last pass writes the caller's items)
+  uint2* items_out = win_lists ? reinterpret_cast<uint2*>(bins->items) : nullptr;
   for (int k = 0; k < p.win_passes; ++k)
-    radix_pass<uint2>(wkey[k % 2], witem[k % 2], wkey[(k + 1) % 2], witem[(k + 1) % 2], d_e, kRadixBits * k,
+    radix_pass<uint2>(wkey[k % 2], witem[k % 2], wkey[(k + 1) % 2],
+                      (items_out && k + 1 == p.win_passes) ? items_out : witem[(k + 1) % 2], d_e, kRadixBits * k,
                       p.nb_items, hist, dtot, st);
   const uint32_t* skey = wkey[p.win_passes % 2];
-  const uint2* srec = witem[p.win_passes % 2];
+  const uint2* srec = items_out ? items_out : witem[p.win_passes % 2];
+  if (win_lists) {
+    // 5'. the window runs into the caller's win_ranges (begins, then ends); no tile list
+    uint32_t* beg = bins->win_ranges;
+    uint32_t* end = bins->win_ranges + W;
+    if (p.win_passes == 1) {
+      hipLaunchKernelGGL(k_window_table, dim3(1), dim3(kScanThreads), 0, st, dtot, W, beg, end, cfirst, d_nchunks);
+    } else {
+      const unsigned fill_grid = (unsigned)std::min<int64_t>(4096, (2 * W + 255) / 256);
+      hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, beg, (uint64_t)2 * W, 0u);
+      hipLaunchKernelGGL(k_window_bounds, dim3(p.nb_items), dim3(kSortThreads), 0, st, skey, d_e, beg, end);
+    }
+    return check_launch("bin/sort");
+  }
   // 5. window runs and their chunks
   if (p.win_passes == 1) {
     hipLaunchKernelGGL(k_window_table, dim3(1), dim3(kScanThreads), 0, st, dtot, W, wbeg, wend, cfirst, d_nchunks);

@@ -128,6 +128,7 @@ struct PixMap {
   static constexpr int RS = SUBH / PPL;                      // row stride between a lane's pixels
   int v, x, y0, W, H, pix_off, tile;
   int tx0, ty0;  // top-left pixel of the tile
+  int tcx, tcy;  // the tile's column and row in its view's grid
   int wx0, wy0;  // top-left pixel of this wave's block
   __device__ PixMap(const ViewTable& vt, int gt) {
     tile = gt;
@@ -139,6 +140,8 @@ struct PixMap {
     const int lt = gt - g.tile_off;
     const int tx = lt % g.TX, ty = lt / g.TX;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    tcx = tx;
+    tcy = ty;
     tx0 = tx * TILE;
     ty0 = ty * TILE;
     wx0 = tx0 + (w % WX) * SUBW;
@@ -190,16 +193,69 @@ __device__ __forceinline__ CullConic cull_conic(float ca, float cb, float cc, fl
   return k;
 }
 
-// One splat record loaded into registers ahead of its batch (prefetch).
+// The bins as the raster kernels read them: tile lists (ids, ranges) or
+// window lists (items, win_ranges), as gs_bins documents them.
+struct ListArgs {
+  const uint32_t* ids;
+  const uint2* ranges;
+  const uint2* items;
+  const uint32_t* win_ranges;
+};
+
+// A tile's run of list positions [s, e): of its own list, or (WIN) of its
+// binning window's list, whose items it takes where their clipped rect covers
+// the tile's position (lx, ly) in the window.  The window list is in the
+// order of every tile's list, so the covering items are the tile's list.
+struct TileRun {
+  int s, e;
+  uint32_t lx, ly;
+};
+template <bool WIN, class PM>
+__device__ __forceinline__ TileRun tile_run(const ListArgs& la, const ViewTable& vt, const PM& pm) {
+  TileRun tr;
+  if constexpr (WIN) {
+    const ViewGeom& g = vt.v[pm.v];
+    const int w = g.win_off + (pm.tcy >> kWinShift) * g.WX + (pm.tcx >> kWinShift);
+    tr.s = (int)la.win_ranges[w];
+    tr.e = (int)la.win_ranges[vt.total_windows + w];
+    tr.lx = (uint32_t)(pm.tcx & (kWinSide - 1));
+    tr.ly = (uint32_t)(pm.tcy & (kWinSide - 1));
+  } else {
+    const uint2 rg = la.ranges[pm.tile];
+    tr.s = (int)rg.x;
+    tr.e = (int)rg.y;
+    tr.lx = tr.ly = 0u;
+  }
+  return tr;
+}
+
+// Whether a window item's clipped rect (lx0 | lx1 << 4 | ly0 << 8 | ly1 << 12, half-open, lx0 < lx1 and
+// ly0 < ly1) covers window tile (lx, ly): one unsigned comparison per axis.
+__device__ __forceinline__ bool item_covers(uint32_t code, uint32_t lx, uint32_t ly) {
+  const uint32_t x0 = code & 15u, x1 = (code >> 4) & 15u, y0 = (code >> 8) & 15u, y1 = (code >> 12) & 15u;
+  return (lx - x0) < (x1 - x0) && (ly - y0) < (y1 - y0);
+}
+
+// One splat record loaded into registers ahead of its batch (prefetch): list
+// position idx of the tile's run; `valid` when it is an entry of the tile.
 struct SplatLoader {
   float4 a, b, c;  // record words 0-3, 4-7, 8-11
   uint32_t id;
   bool valid;
-  __device__ __forceinline__ void fetch(const float* __restrict__ rec, const uint32_t* __restrict__ ids, int idx,
-                                        int lo, int hi) {
-    valid = idx >= lo && idx < hi;
+  template <bool WIN>
+  __device__ __forceinline__ void fetch(const float* __restrict__ rec, const ListArgs& la, const TileRun& tr,
+                                        int idx) {
+    valid = idx >= tr.s && idx < tr.e;
     if (valid) {
-      id = ids[idx];
+      if constexpr (WIN) {
+        const uint2 it = la.items[idx];
+        id = it.x;
+        valid = item_covers(it.y, tr.lx, tr.ly);
+      } else {
+        id = la.ids[idx];
+      }
+    }
+    if (valid) {
       const float4* r = reinterpret_cast<const float4*>(rec + (size_t)id * GS_REC_FLOATS);
       a = r[0];
       b = r[1];
@@ -282,7 +338,9 @@ struct BlockBoxes {
 // LDS of one batch of RPL records per lane (RPL x NT entries): what the pixel
 // loop reads per entry, and per wavefront the ordered list of the batch entries
 // its pixel block can see.  Entry r NT + t of the batch is record r of thread t.
-template <class PM, int RPL>
+// RANK: also each valid entry's rank among the batch's valid entries (its
+// position in the tile's list relative to the batch's first entry of the tile).
+template <class PM, int RPL, bool RANK = false>
 struct BatchLds {
   static constexpr int NB = RPL * PM::NT;
   float4 a[NB];  // (mean x, mean y, a'/2, b') for the conic (a, b, c), ' = times log2(e)
@@ -291,6 +349,8 @@ struct BatchLds {
   uint32_t id[NB];
   uint16_t list[PM::WAVES][NB];
   int cnt[RPL][PM::WAVES][PM::WAVES];  // [record][staging wave][listing wave]
+  uint16_t rank[RANK ? NB : 1];
+  int vcnt[RANK ? RPL : 1][PM::WAVES];  // valid entries per [record][staging wave]
 };
 
 // Stages the batch held by `ld` (RPL entries per thread): entry data into LDS,
@@ -298,13 +358,21 @@ struct BatchLds {
 // wavefront's list built in entry order (ballots, then the staging waves'
 // counts in order, record by record).  Ends with a barrier; returns the
 // calling wave's count.
-template <class PM, int RPL>
+template <class PM, int RPL, bool RANK = false>
 __device__ __forceinline__ int stage_batch(const SplatLoader (&ld)[RPL], const BlockBoxes<PM>& bx, float alpha_min,
-                                           BatchLds<PM, RPL>& L, bool with_id) {
+                                           BatchLds<PM, RPL, RANK>& L, bool with_id, int* n_valid = nullptr) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   int mask[RPL];
   uint64_t bal[RPL][PM::WAVES];
+  uint64_t vb[RANK ? RPL : 1];
+  if constexpr (RANK) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      vb[r] = __ballot(ld[r].valid);
+      if (lane == 0) L.vcnt[r][w] = (int)__popcll(vb[r]);
+    }
+  }
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
     const int slot = r * PM::NT + t;
@@ -326,6 +394,23 @@ __device__ __forceinline__ int stage_batch(const SplatLoader (&ld)[RPL], const B
     }
   }
   __syncthreads();
+  if constexpr (RANK) {
+    // slot r NT + t is list position (valid slots of earlier records and earlier waves) + (lanes below)
+    int before = 0, total = 0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      int here = before;
+#pragma unroll
+      for (int w2 = 0; w2 < PM::WAVES; ++w2) {
+        const int c = L.vcnt[r][w2];
+        here += w2 < w ? c : 0;
+        before += c;
+      }
+      if (ld[r].valid) L.rank[r * PM::NT + t] = (uint16_t)(here + (int)__popcll(vb[r] & lt));
+    }
+    total = before;
+    *n_valid = total;
+  }
   int mine = 0;
 #pragma unroll
   for (int q = 0; q < PM::WAVES; ++q) {
@@ -354,16 +439,17 @@ __device__ __forceinline__ int stage_batch(const SplatLoader (&ld)[RPL], const B
 // NaN and fails the range test, so no separate flag is tested.
 // STATE: the pixel state (T_final, n_contrib) is written (not under the checkpoint flag).
 // (six wavefronts per SIMD: measured faster than five, despite a few bytes of spill outside the loop)
-// RPL: splat records each lane stages per LDS batch.
-template <int TILE, bool STATE, int RPL>
+// RPL: splat records each lane stages per LDS batch.  WIN: the bins are window lists.
+template <int TILE, bool STATE, int RPL, bool WIN>
 __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_render_fwd(
-    ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
-    RasterConsts rc, float* __restrict__ img, float* __restrict__ tfin, int32_t* __restrict__ ncon,
-    const float* __restrict__ target, float* __restrict__ tile_loss) {
+    ViewTable vt, const float* __restrict__ rec, ListArgs la, RasterConsts rc, float* __restrict__ img,
+    float* __restrict__ tfin, int32_t* __restrict__ ncon, const float* __restrict__ target,
+    float* __restrict__ tile_loss) {
   using PM = PixMap<TILE, FwdShape<TILE>>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
   constexpr int NB = RPL * NT;  // entries per batch
-  __shared__ BatchLds<PM, RPL> L;
+  constexpr bool RANK = WIN && STATE;  // list positions of window-list entries (for n_contrib)
+  __shared__ BatchLds<PM, RPL, RANK> L;
   __shared__ float s_loss[PM::WAVES];
   const PM pm(vt, blockIdx.x);
   const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
@@ -378,21 +464,23 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_wave
     last[p] = 0;
     fy[p] = pm.inside(p) ? (float)pm.row(p) : INFINITY;
   }
-  const uint2 rg = ranges[blockIdx.x];
-  const int s = (int)rg.x, e = (int)rg.y;
+  const TileRun tr = tile_run<WIN>(la, vt, pm);
+  const int s = tr.s, e = tr.e;
   const float fx = (float)pm.x;
+  int vbase = 0;  // RANK: the tile's entries in earlier batches
   SplatLoader ld[RPL];
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) ld[r].fetch(rec, ids, s + r * NT + (int)threadIdx.x, s, e);
+  for (int r = 0; r < RPL; ++r) ld[r].template fetch<WIN>(rec, la, tr, s + r * NT + (int)threadIdx.x);
   for (int base = s; base < e; base += NB) {
     int alive = 0;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) alive |= fy[p] != INFINITY ? 1 : 0;
     if (__syncthreads_count(alive) == 0) break;
-    const int n = stage_batch<PM, RPL>(ld, boxes, rc.alpha_min, L, false);
+    int n_valid = 0;
+    const int n = stage_batch<PM, RPL, RANK>(ld, boxes, rc.alpha_min, L, false, &n_valid);
 #pragma unroll
     for (int r = 0; r < RPL; ++r)  // next batch, in flight during this one
-      ld[r].fetch(rec, ids, base + NB + r * NT + (int)threadIdx.x, s, e);
+      ld[r].template fetch<WIN>(rec, la, tr, base + NB + r * NT + (int)threadIdx.x);
     // a wavefront whose pixels have all stopped only keeps the block's barriers
     // (wave-uniform: kept in a scalar register, so the walk's loop control is scalar)
     const int cnt = __builtin_amdgcn_readfirstlane(__ballot(alive) != 0ull ? n : 0);
@@ -420,9 +508,10 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_wave
         C[p][1] = fmaf(Cv.x, wgt, C[p][1]);
         C[p][2] = fmaf(Cv.y, wgt, C[p][2]);
         T[p] = blend ? test : T[p];
-        if (STATE) last[p] = blend ? base - s + j + 1 : last[p];
+        if (STATE) last[p] = blend ? (RANK ? vbase + (int)L.rank[j] : base - s + j) + 1 : last[p];
       }
     }
+    vbase += n_valid;
   }
   float lsum = 0.0f;
 #pragma unroll
@@ -572,13 +661,13 @@ __device__ int abs_role(int lane) {
 // scalar D_k = dL/dC . S_k, updated by the entry's dL/dC . c_k.
 // With ABS the kernel also adds the homodirectional view-space gradient of
 // each (view, Gaussian) pair into abs2d [V*N][2].
-template <int TILE, bool ABS, int RPL>
+template <int TILE, bool ABS, int RPL, bool WIN>
 // (five wavefronts per SIMD: 96 registers, no spill; measured 10% faster than four)
 __global__ __launch_bounds__(BwdShape<TILE>::THREADS)
 __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_render_bwd(
-    ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
-    RasterConsts rc, const float* __restrict__ img, int loss_kind, const float* __restrict__ target,
-    const float* __restrict__ dl_dimage, float* __restrict__ grad2d, float* __restrict__ abs2d) {
+    ViewTable vt, const float* __restrict__ rec, ListArgs la, RasterConsts rc, const float* __restrict__ img,
+    int loss_kind, const float* __restrict__ target, const float* __restrict__ dl_dimage,
+    float* __restrict__ grad2d, float* __restrict__ abs2d) {
   using PM = PixMap<TILE, BwdShape<TILE>>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
   constexpr int NB = RPL * NT;  // entries per batch
@@ -586,8 +675,8 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
   const PM pm(vt, blockIdx.x);
   const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
   const BlockBoxes<PM> boxes(pm);
-  const uint2 rg = ranges[blockIdx.x];
-  const int s = (int)rg.x, e = (int)rg.y;
+  const TileRun tr = tile_run<WIN>(la, vt, pm);
+  const int s = tr.s, e = tr.e;
   const float fx = (float)pm.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const LaneRole role = wave_roles(lane);
@@ -622,7 +711,7 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
   float amx = 0.0f, amy = 0.0f;  // ABS: the lane's sums of |dL_p/dmean| for the current entry
   SplatLoader ld[RPL];
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) ld[r].fetch(rec, ids, s + r * NT + (int)threadIdx.x, s, e);
+  for (int r = 0; r < RPL; ++r) ld[r].template fetch<WIN>(rec, la, tr, s + r * NT + (int)threadIdx.x);
   for (int base = s; base < e; base += NB) {
     int alive = 0;
 #pragma unroll
@@ -631,7 +720,7 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
     const int n = stage_batch<PM, RPL>(ld, boxes, rc.alpha_min, L, true);
 #pragma unroll
     for (int r = 0; r < RPL; ++r)  // next batch, in flight during this one
-      ld[r].fetch(rec, ids, base + NB + r * NT + (int)threadIdx.x, s, e);
+      ld[r].template fetch<WIN>(rec, la, tr, base + NB + r * NT + (int)threadIdx.x);
     // (wave-uniform: kept in a scalar register, so the walk's loop control is scalar)
     const int cnt = __builtin_amdgcn_readfirstlane(__ballot(alive) != 0ull ? n : 0);
     for (int k = 0; k < cnt; ++k) {
@@ -706,14 +795,14 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
 // the entry that would take T below t_min, inclusive), the entries blended,
 // and n_contrib; summed over the image into out[0..2] (one 64-bit atomic per
 // wavefront and count).
-template <int TILE>
+template <int TILE, bool WIN>
 __global__ __launch_bounds__(FwdShape<TILE>::THREADS) void k_render_stats(
-    ViewTable vt, const float* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
-    RasterConsts rc, unsigned long long* __restrict__ out) {
+    ViewTable vt, const float* __restrict__ rec, ListArgs la, RasterConsts rc, unsigned long long* __restrict__ out) {
   using PM = PixMap<TILE, FwdShape<TILE>>;
   constexpr int PPL = PM::PPL, NT = PM::NT;
-  __shared__ float4 s_a[NT];  // (mean x, mean y, -a'/2, -b'), ' = times log2(e)
-  __shared__ float2 s_b[NT];  // (-c'/2, opacity)
+  __shared__ float4 s_a[NT];  // (mean x, mean y, a'/2, b'), ' = times log2(e)
+  __shared__ float2 s_b[NT];  // (c'/2, opacity)
+  __shared__ int s_wc[PM::WAVES];  // WIN: the tile's entries per wavefront of the batch
   const PM pm(vt, blockIdx.x);
   const float amax = __builtin_canonicalizef(rc.alpha_max);  // canonical once: fminf needs no per-use quieting
   float T[PPL], fy[PPL];
@@ -726,22 +815,38 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) void k_render_stats(
     done[p] = !pm.inside(p);
     fy[p] = (float)pm.row(p);
   }
-  const uint2 rg = ranges[blockIdx.x];
-  const int s = (int)rg.x, e = (int)rg.y;
+  const TileRun tr = tile_run<WIN>(la, vt, pm);
+  const int s = tr.s, e = tr.e;
   const float fx = (float)pm.x;
+  int vbase = 0;  // the tile's entries in earlier batches
   SplatLoader ld;
   for (int base = s; base < e; base += NT) {
     int alive = 0;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) alive |= done[p] ? 0 : 1;
     if (__syncthreads_count(alive) == 0) break;
-    ld.fetch(rec, ids, base + (int)threadIdx.x, s, e);
+    ld.template fetch<WIN>(rec, la, tr, base + (int)threadIdx.x);
+    int slot = (int)threadIdx.x, cnt = min(NT, e - base);
+    if constexpr (WIN) {
+      // the batch's entries of the tile, packed in list order
+      const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+      const uint64_t b = __ballot(ld.valid);
+      if (lane == 0) s_wc[w] = (int)__popcll(b);
+      __syncthreads();
+      int before = 0;
+      cnt = 0;
+#pragma unroll
+      for (int q = 0; q < PM::WAVES; ++q) {
+        before += q < w ? s_wc[q] : 0;
+        cnt += s_wc[q];
+      }
+      slot = before + (int)__popcll(b & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+    }
     if (ld.valid) {
-      s_a[threadIdx.x] = make_float4(ld.a.x, ld.a.y, (0.5f * kLog2e) * ld.a.z, kLog2e * ld.a.w);
-      s_b[threadIdx.x] = make_float2((0.5f * kLog2e) * ld.b.x, ld.b.y);
+      s_a[slot] = make_float4(ld.a.x, ld.a.y, (0.5f * kLog2e) * ld.a.z, kLog2e * ld.a.w);
+      s_b[slot] = make_float2((0.5f * kLog2e) * ld.b.x, ld.b.y);
     }
     __syncthreads();
-    const int cnt = min(NT, e - base);
     for (int j = 0; j < cnt; ++j) {
       const float4 cu = s_a[j];
       const float2 geo = s_b[j];
@@ -762,10 +867,11 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) void k_render_stats(
         }
         T[p] = test;
         ++blended[p];
-        last[p] = base - s + j + 1;
+        last[p] = (WIN ? vbase : base - s) + j + 1;
       }
     }
     __syncthreads();
+    vbase += cnt;
   }
   unsigned long long c0 = 0, c1 = 0, c2 = 0;
 #pragma unroll
@@ -805,11 +911,23 @@ static gs_status validate_raster_common(const gs_projected* proj, const gs_bins*
   if ((s = validate_cams(cams, n_views)) != GS_OK) return s;
   if ((s = validate_opts(opts)) != GS_OK) return s;
   if (!proj || !proj->rec) return fail(GS_ERR_INVALID_VALUE, "proj->rec is NULL");
-  if (!bins || !bins->ids || !bins->ranges) return fail(GS_ERR_INVALID_VALUE, "bins->ids/ranges is NULL");
+  if (!bins) return fail(GS_ERR_INVALID_VALUE, "bins is NULL");
   if (reinterpret_cast<uintptr_t>(proj->rec) % 16 != 0) return fail(GS_ERR_INVALID_VALUE, "rec must be 16-byte aligned");
-  if (reinterpret_cast<uintptr_t>(bins->ranges) % 8 != 0)
-    return fail(GS_ERR_INVALID_VALUE, "ranges must be 8-byte aligned");
+  if (opts->flags & GS_OPT_WINDOW_LISTS) {
+    if (!bins->items || !bins->win_ranges) return fail(GS_ERR_INVALID_VALUE, "bins->items/win_ranges is NULL");
+    if (reinterpret_cast<uintptr_t>(bins->items) % 8 != 0)
+      return fail(GS_ERR_INVALID_VALUE, "items must be 8-byte aligned");
+  } else {
+    if (!bins->ids || !bins->ranges) return fail(GS_ERR_INVALID_VALUE, "bins->ids/ranges is NULL");
+    if (reinterpret_cast<uintptr_t>(bins->ranges) % 8 != 0)
+      return fail(GS_ERR_INVALID_VALUE, "ranges must be 8-byte aligned");
+  }
   return GS_OK;
+}
+
+static ListArgs list_args(const gs_bins* bins) {
+  return ListArgs{bins->ids, reinterpret_cast<const uint2*>(bins->ranges), reinterpret_cast<const uint2*>(bins->items),
+                  bins->win_ranges};
 }
 
 }  // namespace gs
@@ -846,16 +964,24 @@ static gs_status render_fwd_impl(const gs_projected* proj, int64_t n, const gs_b
   float* tf = opts->checkpoint ? nullptr : out->t_final;
   int32_t* nc = opts->checkpoint ? nullptr : out->n_contrib;
   const dim3 grid((unsigned)vt.total_tiles);
-  const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
+  const ListArgs la = list_args(bins);
+  const bool win = (opts->flags & GS_OPT_WINDOW_LISTS) != 0;
   (void)n;
-#define GS_LAUNCH_FWD_R(TILE_, NT_, RPL_)                                                                      \
-  do {                                                                                                        \
-    if (tf)                                                                                                   \
-      hipLaunchKernelGGL((k_render_fwd<TILE_, true, RPL_>), grid, dim3(NT_), 0, st, vt, proj->rec, bins->ids, \
-                         rg, rc, out->rgb, tf, nc, tgt, tile_loss);                                          \
-    else                                                                                                      \
-      hipLaunchKernelGGL((k_render_fwd<TILE_, false, RPL_>), grid, dim3(NT_), 0, st, vt, proj->rec, bins->ids,\
-                         rg, rc, out->rgb, tf, nc, tgt, tile_loss);                                          \
+#define GS_LAUNCH_FWD_W(TILE_, NT_, RPL_, WIN_)                                                                 \
+  do {                                                                                                         \
+    if (tf)                                                                                                    \
+      hipLaunchKernelGGL((k_render_fwd<TILE_, true, RPL_, WIN_>), grid, dim3(NT_), 0, st, vt, proj->rec, la, rc, \
+                         out->rgb, tf, nc, tgt, tile_loss);                                                   \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_render_fwd<TILE_, false, RPL_, WIN_>), grid, dim3(NT_), 0, st, vt, proj->rec, la,    \
+                         rc, out->rgb, tf, nc, tgt, tile_loss);                                               \
+  } while (0)
+#define GS_LAUNCH_FWD_R(TILE_, NT_, RPL_)           \
+  do {                                             \
+    if (win)                                       \
+      GS_LAUNCH_FWD_W(TILE_, NT_, RPL_, true);     \
+    else                                           \
+      GS_LAUNCH_FWD_W(TILE_, NT_, RPL_, false);    \
   } while (0)
 #define GS_LAUNCH_FWD(TILE_, NT_)                  \
   do {                                            \
@@ -869,6 +995,7 @@ static gs_status render_fwd_impl(const gs_projected* proj, int64_t n, const gs_b
     case 16: GS_LAUNCH_FWD(16, FwdShape<16>::THREADS); break;
     default: GS_LAUNCH_FWD(32, FwdShape<32>::THREADS); break;
   }
+#undef GS_LAUNCH_FWD_W
 #undef GS_LAUNCH_FWD_R
 #undef GS_LAUNCH_FWD
   if (want_loss) hipLaunchKernelGGL(k_loss_reduce, dim3(n_views), dim3(256), 0, st, vt, tile_loss, loss->loss_out);
@@ -978,10 +1105,18 @@ static void launch_raster_bwd(const ViewTable& vt, const gs_projected* proj, con
                               const gs_options* opts, const gs_loss* loss, float* g2, float* a2, hipStream_t st) {
   const RasterConsts rc = consts_of(opts);
   const dim3 grid((unsigned)vt.total_tiles);
-  const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
-#define GS_BWD_R(TILE, ABS, RPL)                                                                              \
-  hipLaunchKernelGGL((k_render_bwd<TILE, ABS, RPL>), grid, dim3(BwdShape<TILE>::THREADS), 0, st, vt, proj->rec, \
-                     bins->ids, rg, rc, img->rgb, (int)loss->kind, loss->target, loss->dl_dimage, g2, a2)
+  const ListArgs la = list_args(bins);
+  const bool win = (opts->flags & GS_OPT_WINDOW_LISTS) != 0;
+#define GS_BWD_W(TILE, ABS, RPL, WIN)                                                                        \
+  hipLaunchKernelGGL((k_render_bwd<TILE, ABS, RPL, WIN>), grid, dim3(BwdShape<TILE>::THREADS), 0, st, vt,     \
+                     proj->rec, la, rc, img->rgb, (int)loss->kind, loss->target, loss->dl_dimage, g2, a2)
+#define GS_BWD_R(TILE, ABS, RPL)      \
+  do {                                \
+    if (win)                          \
+      GS_BWD_W(TILE, ABS, RPL, true); \
+    else                              \
+      GS_BWD_W(TILE, ABS, RPL, false);\
+  } while (0)
 #define GS_BWD(TILE, ABS)          \
   do {                             \
     if (opts->lds_batch == 2)      \
@@ -1002,6 +1137,7 @@ static void launch_raster_bwd(const ViewTable& vt, const gs_projected* proj, con
       default: GS_BWD(32, false); break;
     }
   }
+#undef GS_BWD_W
 #undef GS_BWD_R
 #undef GS_BWD
 }
@@ -1086,20 +1222,22 @@ extern "C" gs_status gs_render_stats(const gs_projected* proj, int64_t n, const 
   unsigned long long* out = reinterpret_cast<unsigned long long*>(d_counts);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, out, 3);
   const dim3 grid((unsigned)vt.total_tiles);
-  const uint2* rg = reinterpret_cast<const uint2*>(bins->ranges);
+  const ListArgs la = list_args(bins);
+  const bool win = (opts->flags & GS_OPT_WINDOW_LISTS) != 0;
+#define GS_STATS(TILE)                                                                                          \
+  do {                                                                                                          \
+    if (win)                                                                                                    \
+      hipLaunchKernelGGL((k_render_stats<TILE, true>), grid, dim3(FwdShape<TILE>::THREADS), 0, st, vt, proj->rec, \
+                         la, rc, out);                                                                          \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_render_stats<TILE, false>), grid, dim3(FwdShape<TILE>::THREADS), 0, st, vt,          \
+                         proj->rec, la, rc, out);                                                               \
+  } while (0)
   switch (opts->tile_size) {
-    case 8:
-      hipLaunchKernelGGL(k_render_stats<8>, grid, dim3(FwdShape<8>::THREADS), 0, st, vt, proj->rec, bins->ids, rg, rc,
-                         out);
-      break;
-    case 16:
-      hipLaunchKernelGGL(k_render_stats<16>, grid, dim3(FwdShape<16>::THREADS), 0, st, vt, proj->rec, bins->ids, rg,
-                         rc, out);
-      break;
-    default:
-      hipLaunchKernelGGL(k_render_stats<32>, grid, dim3(FwdShape<32>::THREADS), 0, st, vt, proj->rec, bins->ids, rg,
-                         rc, out);
-      break;
+    case 8: GS_STATS(8); break;
+    case 16: GS_STATS(16); break;
+    default: GS_STATS(32); break;
   }
+#undef GS_STATS
   return check_launch("render stats");
 }

@@ -130,18 +130,27 @@ def unpack_images(flat: torch.Tensor, cameras, channels=3) -> List[torch.Tensor]
 
 
 class Frame:
-    """Buffers of one rendered batch: projected records, bins, image."""
+    """Buffers of one rendered batch: projected records, bins, image.  The bins are tile lists
+    (ids, ranges) or window lists (items, win_ranges), as the rasteriser's `lists` says."""
 
     def __init__(self, rast: "Rasterizer", capacity: int):
         dev = rast.device
         VN = rast.n * rast.n_views
+        self.windowed = rast.lists == "window"
         self.rec = torch.empty(VN * L.GS_REC_FLOATS, dtype=torch.float32, device=dev)
         self.tiles = torch.empty(VN, dtype=torch.int32, device=dev)
         n_seg = rast.n_views * ((rast.n + 63) // 64)  # visible pairs by (view, 64 Gaussians), see gs_projected
         self.vis = torch.empty(n_seg * 64 * 4, dtype=torch.int32, device=dev)
         self.vis_count = torch.empty(n_seg, dtype=torch.int32, device=dev)
-        self.ranges = torch.empty(2 * rast.total_tiles, dtype=torch.int32, device=dev)
+        # the ranges start empty, so a raster call before any sort reads no list
+        if self.windowed:
+            self.ranges = None
+            self.win_ranges = torch.zeros(2 * max(1, rast.total_windows), dtype=torch.int32, device=dev)
+        else:
+            self.ranges = torch.zeros(2 * rast.total_tiles, dtype=torch.int32, device=dev)
+            self.win_ranges = None
         self.d_num_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.d_num_items = torch.zeros(1, dtype=torch.int64, device=dev)
         self.d_overflow = torch.zeros(1, dtype=torch.int32, device=dev)
         self.rgb = torch.empty(3 * rast.total_pixels, dtype=torch.float32, device=dev)
         if rast.checkpoint:
@@ -153,10 +162,17 @@ class Frame:
         self.set_capacity(capacity, rast.want_keys)
 
     def set_capacity(self, capacity: int, want_keys: bool):
+        """Buffers for `capacity` list entries: incidences of the tile lists, or items of the window
+        lists (8 bytes each: the pair and its clipped rect)."""
         dev = self.rec.device
         self.capacity = int(capacity)
-        self.ids = torch.empty(max(1, self.capacity), dtype=torch.int32, device=dev)
-        self.keys = torch.empty(max(1, self.capacity), dtype=torch.int64, device=dev) if want_keys else None
+        if self.windowed:
+            self.ids = self.keys = None
+            self.items = torch.empty(max(1, self.capacity), dtype=torch.int64, device=dev)
+        else:
+            self.items = None
+            self.ids = torch.empty(max(1, self.capacity), dtype=torch.int32, device=dev)
+            self.keys = torch.empty(max(1, self.capacity), dtype=torch.int64, device=dev) if want_keys else None
 
     def c_proj(self) -> L.gs_projected:
         return L.gs_projected(_p(self.rec), _p(self.tiles), _p(self.vis), _p(self.vis_count))
@@ -164,20 +180,34 @@ class Frame:
     def c_bins(self) -> L.gs_bins:
         b = L.gs_bins()
         b.keys, b.ids, b.ranges = _p(self.keys), _p(self.ids), _p(self.ranges)
+        b.items, b.win_ranges, b.d_num_items = _p(self.items), _p(self.win_ranges), _p(self.d_num_items)
         b.capacity = self.capacity
         b.d_num_pairs, b.d_overflow = _p(self.d_num_pairs), _p(self.d_overflow)
         return b
+
+    def list_entries(self) -> int:
+        """The entries the bins hold after gs_bin_sort (syncs): window items or tile incidences."""
+        return int((self.d_num_items if self.windowed else self.d_num_pairs).item())
 
     def c_image(self) -> L.gs_image:
         return L.gs_image(_p(self.rgb), _p(self.t_final), _p(self.n_contrib))
 
 
 class Rasterizer:
-    """The four rasteriser calls of libgs for a fixed set of keyframe cameras."""
+    """The four rasteriser calls of libgs for a fixed set of keyframe cameras.  lists: the form of
+    the bins, "window" (gs_bin_sort writes each 8 x 8-tile window's list and the raster kernels take
+    a tile's entries from it; the default, it skips writing the tile lists) or "tile" (the tile
+    lists and ranges, which `want_keys` extends with the sort keys)."""
 
     def __init__(self, cameras, n: int, sh_degree: int, tile_size: int = 16, checkpoint: bool = False,
-                 device="cuda", want_keys: bool = False, growth: float = 1.25, **opt_overrides):
+                 device="cuda", want_keys: bool = False, growth: float = 1.25, lists: str = "window",
+                 **opt_overrides):
         L.load()
+        if lists not in ("window", "tile"):
+            raise ValueError(f"lists must be 'window' or 'tile', not {lists!r}")
+        if want_keys and lists != "tile":
+            raise ValueError("the sort keys come with tile lists (lists='tile')")
+        self.lists = lists
         self.cameras = list(cameras)
         self.n_views = len(self.cameras)
         self.n = int(n)
@@ -187,8 +217,11 @@ class Rasterizer:
         self.want_keys = want_keys
         self.growth = growth
         self.opts = L.default_options(tile_size=int(tile_size), checkpoint=int(checkpoint), **opt_overrides)
+        if lists == "window":
+            self.opts.flags |= L.GS_OPT_WINDOW_LISTS
         self.cams = L.make_cameras(self.cameras)
         self.total_tiles = L.gs_total_tiles(self.cams, self.n_views, self.opts.tile_size)
+        self.total_windows = L.gs_total_windows(self.cams, self.n_views, self.opts.tile_size)
         self.total_pixels = L.gs_total_pixels(self.cams, self.n_views)
         self.capacity = 0
         self.ws_sort = None
@@ -206,7 +239,8 @@ class Rasterizer:
             self.ws_sort_bytes = need
 
     def reserve(self, capacity: int):
-        """Set the pair capacity used by new frames (and grow the sort workspace)."""
+        """Set the list capacity used by new frames (tile incidences or window items; and grow the sort
+        workspace)."""
         self.capacity = int(capacity)
         self._ensure_sort_ws(self.capacity)
 
@@ -299,7 +333,7 @@ class Rasterizer:
         """After bin_sort: if the pairs overflowed, grow the capacity and sort again (syncs)."""
         if int(fr.d_overflow.item()) == 0:
             return False
-        m = int(fr.d_num_pairs.item())
+        m = fr.list_entries()
         self.reserve(int(math.ceil(m * self.growth)) + 1024)
         self.bin_sort(fr)
         assert int(fr.d_overflow.item()) == 0
@@ -564,7 +598,8 @@ class MappingStep:
         (synchronises with the host); the flag is cleared."""
         if int(self.overflow_seen.item()) != 0:
             self.overflow_seen.zero_()
-            raise CapacityOverflow(f"the (tile, Gaussian) pair count exceeded the capacity {self.rast.capacity}: "
+            raise CapacityOverflow(f"the list entries (tile incidences or window items) exceeded the capacity "
+                                   f"{self.rast.capacity}: "
                                    f"those iterations rendered empty tiles and stepped Adam on zero gradients; "
                                    f"size() again (and capture()) before continuing")
 

@@ -9,15 +9,17 @@ by HBM.
 
 Per-unit figures (P_n = 11 + 3K raw floats per Gaussian, K = (D+1)^2):
   project     N*4*P_n + V*N*4 [tiles_touched] + Nv*(48 + 16) [visible records and entries] + S*4 [segment counts]
-  bin_sort    S*4 [segment counts] + Nv*16 [visible-pair entries] + M*4 [ids] + T*8 [ranges]
-  render_fwd  Nv*36 + M*4 + Px*(12 + 12 [target] + 8 [T_final, n_contrib unless checkpoint])
-  raster_bwd  Px*(12 [image] + 12 [target]) + Nv*36 [records] + M*4 + Nv*36 [gradients]
+  bin_sort    S*4 [segment counts] + Nv*16 [visible-pair entries] + L [the lists]
+  render_fwd  Nv*36 + L + Px*(12 + 12 [target] + 8 [T_final, n_contrib unless checkpoint])
+  raster_bwd  Px*(12 [image] + 12 [target]) + Nv*36 [records] + L + Nv*36 [gradients]
   project_bwd N*(4*P_n + 8*P_n) + V*N*(36 + 16)
   render_bwd  raster_bwd + project_bwd
   adam        N*P_n*32  (read p, g, m, v; write p, m, v, g := 0)
   project_bwd_adam  N*P_n*24 (read p, m, v; write p, m, v) + V*N*52
 with N Gaussians, V views, Nv visible (view, Gaussian) pairs, S = V*ceil(N/64)
-projection segments, M tile incidences, Px pixels and T tiles.
+projection segments, Px pixels, and L the bytes of the bins: M*4 [ids] + T*8
+[ranges] for tile lists (M incidences, T tiles), E*8 [items] + W*8 [window
+ranges] for window lists (E items, W windows).
 """
 from __future__ import annotations
 
@@ -49,20 +51,23 @@ def counts(step, sc):
     n, V = step.params.n, step.rast.n_views
     K = (step.params.sh_degree + 1) ** 2
     pn = 11 + 3 * K
+    win = bool(getattr(fr, "windowed", False))
     return dict(N=n, V=V, Pn=pn, M=int(fr.d_num_pairs.item()), Nv=int(torch.count_nonzero(fr.tiles).item()),
-                Px=step.rast.total_pixels, T=step.rast.total_tiles, ckpt=step.rast.checkpoint)
+                Px=step.rast.total_pixels, T=step.rast.total_tiles, ckpt=step.rast.checkpoint, windowed=win,
+                E=int(fr.d_num_items.item()) if win else 0, W=step.rast.total_windows if win else 0)
 
 
 def algorithmic_bytes(c):
     N, V, Pn, M, Nv, Px, T = c["N"], c["V"], c["Pn"], c["M"], c["Nv"], c["Px"], c["T"]
     S = V * ((N + 63) // 64)
     saved = 0 if c["ckpt"] else 8
-    raster_bwd = Px * 24 + Nv * 36 + M * 4 + Nv * 36
+    lists = c["E"] * 8 + c["W"] * 8 if c.get("windowed") else M * 4 + T * 8
+    raster_bwd = Px * 24 + Nv * 36 + lists + Nv * 36
     project_bwd = N * 12 * Pn + V * N * 52
     return {
         "project": N * 4 * Pn + V * N * 4 + Nv * (48 + 16) + S * 4,
-        "bin_sort": S * 4 + Nv * 16 + M * 4 + T * 8,
-        "render_fwd": Nv * 36 + M * 4 + Px * (24 + saved),
+        "bin_sort": S * 4 + Nv * 16 + lists,
+        "render_fwd": Nv * 36 + lists + Px * (24 + saved),
         "raster_bwd": raster_bwd,
         "project_bwd": project_bwd,
         "render_bwd": raster_bwd + project_bwd,

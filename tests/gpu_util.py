@@ -48,14 +48,74 @@ def gpu_rec_to_oracle(rec):
     return np.concatenate([rec[:, 0:2], rec[:, 9:10], rec[:, 2:9]], axis=1).astype(np.float64)
 
 
+def window_tile_lists(items, win_ranges, cams, tile):
+    """The tile lists (ids, ranges) that window lists stand for, as gs_bins defines them: tile
+    (tx, ty) takes, in window order, the items of its window whose clipped rect covers
+    (tx mod 8, ty mod 8).  Also checks every item's clipped rect is a non-empty part of its window."""
+    items = np.asarray(items, np.uint32).reshape(-1, 2)
+    wr = np.asarray(win_ranges, np.uint32).reshape(2, -1)
+    lists, t_off, w_off = [], 0, 0
+    for c in cams:
+        TX, TY = -(-c.width // tile), -(-c.height // tile)
+        WX, WY = -(-TX // 8), -(-TY // 8)
+        per_tile = [None] * (TX * TY)
+        for wy in range(WY):
+            for wx in range(WX):
+                w = w_off + wy * WX + wx
+                b, e = int(wr[0, w]), int(wr[1, w])
+                assert b <= e
+                code = items[b:e, 1]
+                x0, x1, y0, y1 = code & 15, (code >> 4) & 15, (code >> 8) & 15, (code >> 12) & 15
+                assert np.all((x0 < x1) & (x1 <= 8) & (y0 < y1) & (y1 <= 8) & (code >> 16 == 0))
+                assert np.all(x1 <= TX - 8 * wx) and np.all(y1 <= TY - 8 * wy)
+                for ly in range(min(8, TY - 8 * wy)):
+                    for lx in range(min(8, TX - 8 * wx)):
+                        sel = (x0 <= lx) & (lx < x1) & (y0 <= ly) & (ly < y1)
+                        per_tile[(8 * wy + ly) * TX + 8 * wx + lx] = items[b:e, 0][sel]
+        lists += per_tile
+        t_off += TX * TY
+        w_off += WX * WY
+    assert w_off == wr.shape[1]
+    lens = np.array([len(x) for x in lists], np.int64)
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    ranges = np.stack([starts, starts + lens], 1)
+    ranges[lens == 0] = 0
+    ids = np.concatenate(lists) if lists else np.zeros(0, np.uint32)
+    return ids.astype(np.uint32), ranges.astype(np.uint32)
+
+
+def window_tile_list(items, win_ranges, cams, tile, t):
+    """The tile list of global tile t that window lists stand for (see window_tile_lists)."""
+    items = np.asarray(items, np.uint32).reshape(-1, 2)
+    wr = np.asarray(win_ranges, np.uint32).reshape(2, -1)
+    t_off = w_off = 0
+    for c in cams:
+        TX, TY = -(-c.width // tile), -(-c.height // tile)
+        WX, WY = -(-TX // 8), -(-TY // 8)
+        if t < t_off + TX * TY:
+            ty, tx = divmod(t - t_off, TX)
+            w = w_off + (ty // 8) * WX + tx // 8
+            b, e = int(wr[0, w]), int(wr[1, w])
+            code = items[b:e, 1]
+            lx, ly = tx % 8, ty % 8
+            sel = ((code & 15) <= lx) & (lx < ((code >> 4) & 15)) & (((code >> 8) & 15) <= ly) & \
+                (ly < ((code >> 12) & 15))
+            return items[b:e, 0][sel]
+        t_off += TX * TY
+        w_off += WX * WY
+    raise IndexError(t)
+
+
 def run_gpu(sc, tile=16, checkpoint=False, backward=True, want_keys=True, capacity=None, cams=None,
-            external_dl=None, lds_batch=1, with_abs=False):
+            external_dl=None, lds_batch=1, with_abs=False, lists="window"):
     """Forward (+ L1 backward) of `sc` on the GPU; returns numpy outputs.  with_abs: also the raster
-    backward with the homodirectional gradient (gs_raster_bwd_abs) into out["abs2d"]."""
+    backward with the homodirectional gradient (gs_raster_bwd_abs) into out["abs2d"].  lists: the form
+    of the bins; window lists are returned as they are ("items", "win_ranges") and as the tile lists
+    they stand for ("ids", "ranges"); the sort keys (want_keys) come with tile lists only."""
     cams = sc.cameras if cams is None else cams
     params = R.GaussianParams.from_scene(sc, DEV)
     rast = R.Rasterizer(cams, params.n, params.sh_degree, tile_size=tile, checkpoint=checkpoint, device=DEV,
-                        want_keys=want_keys, lds_batch=lds_batch)
+                        want_keys=want_keys and lists == "tile", lds_batch=lds_batch, lists=lists)
     if capacity is not None:
         rast.reserve(capacity)
     target = R.pack_images(sc.targets, DEV) if sc.targets is not None else None
@@ -89,9 +149,17 @@ def run_gpu(sc, tile=16, checkpoint=False, backward=True, want_keys=True, capaci
     rec = fr.rec.view(-1, 12).cpu().numpy()
     rec[out["tiles"] == 0] = 0.0  # culled pairs' rows are unwritten: read them as zero (extents 0)
     out["rec"] = rec
-    out["ids"] = fr.ids[:m].cpu().numpy().view(np.uint32)
-    out["keys"] = fr.keys[:m].cpu().numpy().view(np.uint64) if fr.keys is not None else None
-    out["ranges"] = fr.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    if fr.windowed:
+        n_items = int(fr.d_num_items.item())
+        out["items"] = fr.items[:n_items].cpu().numpy().view(np.uint32).reshape(-1, 2)
+        out["win_ranges"] = fr.win_ranges.cpu().numpy().view(np.uint32).reshape(2, -1)
+        out["ids"], out["ranges"] = window_tile_lists(out["items"], out["win_ranges"], cams, tile)
+        assert out["ids"].shape[0] == m
+        out["keys"] = None
+    else:
+        out["ids"] = fr.ids[:m].cpu().numpy().view(np.uint32)
+        out["keys"] = fr.keys[:m].cpu().numpy().view(np.uint64) if fr.keys is not None else None
+        out["ranges"] = fr.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
     out["image"] = fr.rgb.cpu().numpy().astype(np.float64)
     if fr.t_final is not None:
         out["t_final"] = fr.t_final.cpu().numpy().astype(np.float64)

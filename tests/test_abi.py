@@ -40,7 +40,7 @@ def test_defaults_and_queries(L):
     from paper_2409_13055_amd import synthetic as S
     o = L.default_options()
     assert o.tile_size == 16 and o.checkpoint == 0 and o.flags == 0 and o.lds_batch == 1
-    assert L.load().gs_abi_version() == L.GS_ABI_VERSION == 2
+    assert L.load().gs_abi_version() == L.GS_ABI_VERSION == 3
     assert abs(o.alpha_min - 1 / 255) < 1e-9 and abs(o.alpha_max - 0.99) < 1e-7 and abs(o.t_min - 1e-4) < 1e-10
     assert abs(o.near_plane - 0.2) < 1e-7 and abs(o.eps2d - 0.3) < 1e-7 and o.radius_sigmas == 3.0
     cams = [S.pinhole(1200, 680, 600.0), S.pinhole(640, 480, 525.0), S.pinhole(100, 75, 90.0)]
@@ -49,6 +49,11 @@ def test_defaults_and_queries(L):
         exp = sum(((c.width + B - 1) // B) * ((c.height + B - 1) // B) for c in cams)
         assert L.gs_total_tiles(cc, 3, B) == exp
     assert L.gs_total_pixels(cc, 3) == sum(c.width * c.height for c in cams)
+    for B in (8, 16, 32):  # binning windows: 8 x 8 tiles of one view
+        exp = sum(-(-((c.width + B - 1) // B) // 8) * -(-((c.height + B - 1) // B) // 8) for c in cams)
+        assert L.gs_total_windows(cc, 3, B) == exp
+    assert L.gs_total_windows(L.make_cameras([S.pinhole(1, 1, 1.0)]), 1, 32) == 1
+    assert C.sizeof(L.gs_bins) == 9 * 8  # seven pointers and the int64 capacity, as gs.h lays them out
     assert L.gs_render_bwd_workspace_size(1000, 3) >= 1000 * 3 * 9 * 4
     assert L.gs_render_fwd_workspace_size(cc, 3, o) >= 4 * L.gs_total_tiles(cc, 3, 16)
     a = L.gs_bin_sort_workspace_size(1000, cc, 3, o, 10_000)
@@ -93,6 +98,29 @@ def test_invalid_arguments_are_rejected_before_any_launch(L):
     out.vis, out.vis_count = C.c_void_p(0x3008), C.c_void_p(0x4000)
     with pytest.raises(L.GsError, match="vis must be 16-byte aligned"):
         L.gs_bin_sort(out, 10, cc, 1, o, L.gs_bins(), None, 0, None)
+    # the two forms of the bins need their own buffers; unknown option bits are rejected
+    out.vis = C.c_void_p(0x3000)
+    bins = L.gs_bins()
+    bins.d_num_pairs, bins.d_overflow = C.c_void_p(0x5000), C.c_void_p(0x5100)
+    bins.items, bins.win_ranges = C.c_void_p(0x6000), C.c_void_p(0x7000)
+    with pytest.raises(L.GsError, match="tile lists need"):
+        L.gs_bin_sort(out, 10, cc, 1, o, bins, None, 0, None)
+    ow = L.default_options()
+    ow.flags = L.GS_OPT_WINDOW_LISTS
+    bins.items = C.c_void_p(0x6004)
+    with pytest.raises(L.GsError, match="8-byte aligned"):
+        L.gs_bin_sort(out, 10, cc, 1, ow, bins, None, 0, None)
+    bins.items, bins.win_ranges = C.c_void_p(0x6000), None
+    with pytest.raises(L.GsError, match="window lists need"):
+        L.gs_bin_sort(out, 10, cc, 1, ow, bins, None, 0, None)
+    with pytest.raises(L.GsError, match="items/win_ranges"):
+        L.gs_render_fwd(out, 10, bins, cc, 1, ow, None, L.gs_image(), None, 0, None)
+    bins.win_ranges = C.c_void_p(0x7000)
+    with pytest.raises(L.GsError, match="CAPACITY"):  # a workspace is still required
+        L.gs_bin_sort(out, 10, cc, 1, ow, bins, None, 0, None)
+    ow.flags = 2
+    with pytest.raises(L.GsError, match="flags"):
+        L.gs_bin_sort(out, 10, cc, 1, ow, bins, None, 0, None)
     groups = (L.gs_adam_group * 1)()
     groups[0].numel = 4
     with pytest.raises(L.GsError, match="NULL"):

@@ -91,7 +91,7 @@ def test_full_size_sampled_parity(workload, tile):
     sc = S.make_config(workload)
     ckpt = sc.checkpoint
     print(f"[fullsize] workload {workload} tile {tile}", flush=True)
-    g = U.run_gpu(sc, tile=tile, checkpoint=ckpt, want_keys=False)
+    g = U.run_gpu(sc, tile=tile, checkpoint=ckpt, want_keys=False, lists="tile")
     cams = sc.cameras
     opts = O.Options(tile=tile)
     rng = np.random.default_rng(workload * 100 + tile)

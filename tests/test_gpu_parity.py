@@ -273,7 +273,7 @@ def _hand_lists(recs):
     from paper_2409_13055_amd import rasterizer as R
     cam = S.pinhole(8, 8, 10.0)
     n = len(recs)
-    rast = R.Rasterizer([cam], n, 0, tile_size=8, device="cuda")
+    rast = R.Rasterizer([cam], n, 0, tile_size=8, device="cuda", lists="tile")
     rast.reserve(n)
     fr = rast.new_frame()
     rec = np.zeros((n, 12), np.float32)
@@ -390,22 +390,27 @@ def test_empty_and_degenerate_inputs():
     assert g0["m"] == 0
 
 
-def test_capacity_overflow_is_reported_and_recovers():
+@pytest.mark.parametrize("lists", ["tile", "window"])
+def test_capacity_overflow_is_reported_and_recovers(lists):
+    """A capacity below the list entries (incidences, or window items) raises the overflow flag, leaves
+    every tile empty (the forward renders the background) and is grown to fit by fit_capacity."""
     import torch as T
     from paper_2409_13055_amd import rasterizer as R
     sc = small_scene(seed=5, n=800)
     params = R.GaussianParams.from_scene(sc, "cuda")
-    rast = R.Rasterizer(sc.cameras, params.n, params.sh_degree, device="cuda")
+    rast = R.Rasterizer(sc.cameras, params.n, params.sh_degree, device="cuda", lists=lists)
     rast.reserve(100)
     fr = rast.new_frame()
     rast.project(params, fr)
     rast.bin_sort(fr)
+    rast.render_fwd(fr)
     T.cuda.synchronize()
     assert int(fr.d_overflow.item()) == 1
-    m = int(fr.d_num_pairs.item())
-    assert m > 100
+    assert bool((fr.rgb == 0.0).all())
+    m, entries = int(fr.d_num_pairs.item()), fr.list_entries()
+    assert entries > 100 and m >= entries
     assert rast.fit_capacity(fr)
-    assert int(fr.d_num_pairs.item()) == m and int(fr.d_overflow.item()) == 0
+    assert int(fr.d_num_pairs.item()) == m and fr.list_entries() == entries and int(fr.d_overflow.item()) == 0
 
 
 def test_invalid_arguments_raise():
@@ -523,3 +528,101 @@ def test_autotune_times_every_tile_and_parity_holds_at_its_choice():
     _, dl = O.l1_loss(g["image"], sc.targets, sc.cameras)
     U.compare_grad2d(g["grad2d"], O.render_backward(sc.cameras, opts, orec, g["ids"], g["ranges"], dl),
                      msg=f"autotuned tile {tile}")
+
+
+# --- window lists (GS_OPT_WINDOW_LISTS): the bins as each 8 x 8-tile window's list ----------------------
+
+def _windows_scene(multi_pass):
+    if multi_pass:
+        # 2 views of 150 x 85 tiles at tile 8: 418 windows, so the window sort takes two 8-bit passes
+        cams = [S.pinhole(1200, 680, 900.0), S.pinhole(1200, 680, 800.0, *S.look_at((0.3, -0.1, -0.5),
+                                                                                  (0.0, 0.0, 3.0)))]
+        return S.make_scene(61, 6000, 1, cams, "box", log_scale_mu=-2.6, log_scale_sigma=0.7, logit_sigma=1.5)
+    return small_scene(seed=62, n=3000)
+
+
+@pytest.mark.parametrize("tile,multi_pass", [(8, False), (16, False), (32, False), (8, True)])
+def test_window_lists_stand_for_the_tile_lists(tile, multi_pass):
+    """The window-list form against the tile-list form on the same scene: the tile lists the window lists
+    stand for equal the tile lists bit for bit (and so the oracle's binning, which the tile form matches);
+    images, final transmittance, contributor counts, losses and work counts equal; gradients equal up to
+    the order of the FP32 atomics."""
+    sc = _windows_scene(multi_pass)
+    a = U.run_gpu(sc, tile=tile, lists="tile", with_abs=True)
+    b = U.run_gpu(sc, tile=tile, lists="window", with_abs=True)
+    assert a["m"] == b["m"] > 0
+    n_win = b["win_ranges"].shape[1]
+    assert (n_win > 256) == multi_pass
+    assert b["items"].shape[0] == int(b["win_ranges"][1].max())
+    for k in ("ids", "ranges", "image", "t_final", "n_contrib", "loss"):
+        np.testing.assert_array_equal(b[k], a[k], err_msg=k)
+    for k in ("grad2d", "abs2d"):
+        assert U.rel_l2(b[k], a[k]) <= 1e-5, k
+    # the image-space gradients differ only in the order of their FP32 atomics (above); the chain to the
+    # parameters sums views and cancels (the rotation gradients most), which can amplify that tenfold
+    for k in a["grads"]:
+        assert U.rel_l2(b["grads"][k], a["grads"][k]) <= 1e-4, k
+    assert a["rast"].render_stats(a["frame"]) == b["rast"].render_stats(b["frame"])
+    check_bins(sc, b, tile)
+
+
+def _hand_window_frames(recs0, recs1, lds_batch):
+    """One 16 x 8 view at tile 8: two tiles in one binning window.  Tile 0's list is recs0 and tile 1's is
+    recs1 (records as (opacity, rgb, depth) with a zero conic: alpha = opacity at every pixel), as tile
+    lists and as one window list that interleaves them; returns {form: (rasteriser, frame)}."""
+    import torch as T
+    from paper_2409_13055_amd import rasterizer as R
+    cam = S.pinhole(16, 8, 10.0)
+    recs = list(recs0) + list(recs1)
+    n, n0 = len(recs), len(recs0)
+    rec = np.zeros((n, 12), np.float32)
+    for i, (op, rgb, depth) in enumerate(recs):
+        rec[i, 0:2] = (3.5 if i < n0 else 11.5, 3.5)
+        rec[i, 5] = op
+        rec[i, 6:9] = rgb
+        rec[i, 9] = depth
+    code0, code1 = 0 | 1 << 4 | 0 << 8 | 1 << 12, 1 | 2 << 4 | 0 << 8 | 1 << 12
+    items = []
+    for k in range(max(n0, n - n0)):
+        if k < n0:
+            items.append((k, code0))
+        if k < n - n0:
+            items.append((n0 + k, code1))
+    out = {}
+    for form in ("tile", "window"):
+        rast = R.Rasterizer([cam], n, 0, tile_size=8, device="cuda", lists=form, lds_batch=lds_batch)
+        rast.reserve(n)
+        fr = rast.new_frame()
+        fr.rec.copy_(T.as_tensor(rec.reshape(-1)))
+        if form == "tile":
+            fr.ids[:n].copy_(T.arange(n, dtype=T.int32))
+            fr.ranges.copy_(T.tensor([0, n0, n0, n], dtype=T.int32))
+        else:
+            it = np.array(items, np.uint32).reshape(-1)
+            fr.items[:n].copy_(T.as_tensor(it.view(np.int64)))
+            fr.win_ranges.copy_(T.tensor([0, n], dtype=T.int32))
+            fr.d_num_items.fill_(n)
+        fr.d_num_pairs.fill_(n)
+        rast.render_fwd(fr)
+        out[form] = (rast, fr)
+    T.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("lds_batch", [1, 2])
+@pytest.mark.parametrize("k_skip", [0, 5, 70, 150])
+def test_window_list_positions_are_tile_list_positions(k_skip, lds_batch):
+    """n_contrib counts positions in the tile's own list when the entries come from a window list that
+    interleaves another tile's: one blending entry behind k_skip transparent ones gives k_skip + 1 at every
+    pixel of tile 0, also when the entries span several LDS batches (64 or 128 entries at tile 8); the
+    image, transmittance and work counts equal those of the tile lists."""
+    recs0 = [(0.002, (1, 1, 1), 1.0 + 0.01 * i) for i in range(k_skip)] + [(0.5, (0.2, 0.4, 0.8), 3.0)] + \
+            [(0.003, (1, 1, 1), 5.0 + 0.01 * i) for i in range(3)]
+    recs1 = [(0.004, (0.5, 0.5, 0.5), 1.0 + 0.01 * i) for i in range(k_skip + 9)] + [(0.6, (0.9, 0.1, 0.1), 4.0)]
+    fr = _hand_window_frames(recs0, recs1, lds_batch)
+    (ra, fa), (rb, fb) = fr["tile"], fr["window"]
+    nc = fb.n_contrib.cpu().numpy().reshape(8, 16)
+    assert np.all(nc[:, :8] == k_skip + 1) and np.all(nc[:, 8:] == k_skip + 10)
+    assert torch.equal(fa.n_contrib, fb.n_contrib) and torch.equal(fa.t_final, fb.t_final)
+    assert torch.equal(fa.rgb, fb.rgb)
+    assert ra.render_stats(fa) == rb.render_stats(fb)

@@ -96,16 +96,19 @@ def test_fused_l1_gradients_match_fd_on_200_gaussians_100k():
     fd_compare(sc, g["grads"], gidx, 1e-3, "100k SH3, 200 Gaussians")
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("lists", ["window", "tile"])
+def test_graph_replays_match_eager(lists):
     sc = S.make_config(3, n=40_000, res_div=4)
     params = R.GaussianParams.from_scene(sc, "cuda")
-    step = R.MappingStep(params, sc.cameras, sc.targets, tile_size=16, with_adam=False)
+    step = R.MappingStep(params, sc.cameras, sc.targets, tile_size=16, with_adam=False, lists=lists)
     step.size()
     step.run()
     torch.cuda.synchronize()
+    fr = step.frame
+    lists_of = (lambda: (fr.items[:int(fr.d_num_items.item())], fr.win_ranges)) if fr.windowed else \
+        (lambda: (fr.ids[:int(fr.d_num_pairs.item())], fr.ranges))
     ref_img = step.frame.rgb.clone()
-    ref_ids = step.frame.ids.clone()
-    ref_ranges = step.frame.ranges.clone()
+    ref_ids, ref_ranges = (t.clone() for t in lists_of())
     ref_loss = step.loss.clone()
     ref_grads = [t.clone() for t in step.grads.tensors()]
     for t in step.grads.tensors():
@@ -120,8 +123,9 @@ def test_graph_replays_match_eager():
         _ = (x * x).sum().item()
         torch.cuda.synchronize()
         assert torch.equal(step.frame.rgb, ref_img), r
-        assert torch.equal(step.frame.ids, ref_ids), r
-        assert torch.equal(step.frame.ranges, ref_ranges), r
+        ids, ranges = lists_of()
+        assert torch.equal(ids, ref_ids), r
+        assert torch.equal(ranges, ref_ranges), r
         assert torch.equal(step.loss, ref_loss), r
         # gradients accumulate: capture warm-up + r replays
         for a, b in zip(step.grads.tensors(), ref_grads):
