@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--layout", default="morton", choices=["morton", "generated"],
                     help="order of the Gaussian set in memory: Morton order of the means (gs_spatial_order, the "
                          "layout the mapping loop keeps) or the order the scene generator drew them in")
+    ap.add_argument("--lists", default="window", choices=["window", "tile"],
+                    help="form of the bins: each 8 x 8-tile window's list (the default) or every tile's list")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--configs", default="1,2,3,4",
                     help="comma-separated other workloads (1-4) timed after the main one ('' for none)")
@@ -94,19 +96,20 @@ def main():
     tune = None
     if tile == 0:
         tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint,
-                               batches=(1, 2) if lds_batch == 0 else (lds_batch,))
+                               batches=(1, 2) if lds_batch == 0 else (lds_batch,), lists=args.lists)
         tile, lds_batch = tune["best"], tune["lds_batch"]
         log(f"[bench] autotune: {tune}")
     elif lds_batch == 0:
         lds_batch = 1
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
+    lists = args.lists
     step = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                         with_adam=with_adam, lds_batch=lds_batch)
+                         with_adam=with_adam, lds_batch=lds_batch, lists=lists)
     step.size()
     torch.cuda.synchronize()
-    log(f"[bench] pairs M={int(step.frame.d_num_pairs.item())} capacity={step.rast.capacity} "
-        f"tile {tile} lds_batch {lds_batch}")
+    log(f"[bench] pairs M={int(step.frame.d_num_pairs.item())} list entries {step.frame.list_entries()} "
+        f"capacity={step.rast.capacity} tile {tile} lds_batch {lds_batch} lists {lists}")
 
     if args.profile_steps > 0:
         for _ in range(args.profile_steps):
@@ -161,7 +164,7 @@ def main():
         # the same iteration on the set in the order it was generated in
         init_g = [t.detach().cpu() for t in params_gen.tensors()]
         st_g = R.MappingStep(params_gen, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                             with_adam=with_adam, lds_batch=lds_batch)
+                             with_adam=with_adam, lds_batch=lds_batch, lists=lists)
         st_g.size()
         if use_graph:
             st_g.capture()
@@ -174,6 +177,23 @@ def main():
             f"stages {g_stages}")
         del st_g, init_g
     del params_gen
+
+    lists_info = {"form": lists}
+    if lists == "window":
+        # the same iteration with the bins as tile lists (the sort writes every tile's list)
+        st_t = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
+                             with_adam=with_adam, lds_batch=lds_batch, lists="tile")
+        st_t.size()
+        if use_graph:
+            st_t.capture()
+        reset(st_t)
+        ms_t = time_graph(st_t.replay if use_graph else st_t.run, args.steps, args.warmup)
+        t_stages, _ = stage_breakdown(st_t, args.steps)
+        lists_info.update(items=step.frame.list_entries(), windows=step.rast.total_windows,
+                          tile_lists={"ms_per_step": round(ms_t, 4), "value": round(mpix / (ms_t * 1e-3), 2),
+                                      "speedup_of_window_lists": round(ms_t / ms, 4), "stages_ms": t_stages})
+        log(f"[bench] tile lists: {ms_t:.3f} ms/step ({ms_t / ms:.3f}x the window-list step), stages {t_stages}")
+        del st_t
 
     # The same iteration issued eagerly (no graph), for comparison.
     eager_ms = None
@@ -200,7 +220,7 @@ def main():
     per_view = None
     if not args.no_per_view:
         pv = R.PerViewMappingStep(params, sc.cameras, sc.targets, lrs=lrs, tile_size=tile,
-                                  checkpoint=sc.checkpoint, with_adam=with_adam, lds_batch=lds_batch)
+                                  checkpoint=sc.checkpoint, with_adam=with_adam, lds_batch=lds_batch, lists=lists)
         pv.size()
         reset(pv)
         ms_pv_eager = time_graph(pv.run, args.steps, args.warmup)
@@ -223,7 +243,7 @@ def main():
         # and the loss call on its own
         lam = 0.2
         st = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                           with_adam=with_adam, ssim_lambda=lam, lds_batch=lds_batch)
+                           with_adam=with_adam, ssim_lambda=lam, lds_batch=lds_batch, lists=lists)
         st.size()
         if use_graph:
             st.capture()
@@ -284,7 +304,7 @@ def main():
         log(f"[bench] pyramid reduce (all views, level 0 -> 1): {ms_r:.4f} ms ({gbs:.0f} GB/s alg)")
         for lv in (1, 2):
             st = R.MappingStep(params, pyr.cameras[lv], pyr.images[lv], lrs=lrs, tile_size=tile,
-                               checkpoint=sc.checkpoint, with_adam=with_adam, lds_batch=lds_batch)
+                               checkpoint=sc.checkpoint, with_adam=with_adam, lds_batch=lds_batch, lists=lists)
             st.size()
             if use_graph:
                 st.capture()
@@ -314,7 +334,7 @@ def main():
         # (plan, apply) on the statistics those iterations gathered
         dc = R.DensityControl(params.n, sc.cameras, device=dev)
         st = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                           with_adam=with_adam, density=dc, lds_batch=lds_batch)
+                           with_adam=with_adam, density=dc, lds_batch=lds_batch, lists=lists)
         st.size()
         if use_graph:
             st.capture()
@@ -431,8 +451,9 @@ def main():
         "config": {"workload": sc.name, "gaussians": sc.n, "views": sc.n_views, "pixels_per_step": sc.total_pixels,
                    "sh_degree": sc.sh_degree, "work": sc.work, "checkpoint": sc.checkpoint, "tile": tile,
                    "lds_batch": lds_batch, "graph": use_graph, "pairs": int(step.frame.d_num_pairs.item()),
-                   "layout": args.layout},
+                   "layout": args.layout, "lists": lists},
         "layout": layout,
+        "lists": lists_info,
         "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "peak_hbm_bytes": peak_hbm,
         "per_view": per_view,
@@ -515,13 +536,13 @@ def bench_config(idx, args):
         target = None
     else:
         target = R.pack_images(sc.targets, dev)
-        tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint)
+        tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint, lists=args.lists)
         tile, lds_batch = tune["best"], tune["lds_batch"]
     lrs = sc.lrs or dict(S.DEFAULT_LRS)
     mpix = sc.total_pixels * 1e-6
     if sc.work == "fwd":
         rast = R.Rasterizer(sc.cameras, params.n, params.sh_degree, tile_size=tile, checkpoint=sc.checkpoint,
-                            device=dev, lds_batch=lds_batch)
+                            device=dev, lds_batch=lds_batch, lists=args.lists)
         fr = rast.forward(params)
 
         def run_eager():
@@ -544,7 +565,7 @@ def bench_config(idx, args):
         stages = ("project", "bin_sort", "render_fwd")
     else:
         step = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                             with_adam="adam" in sc.work, lds_batch=lds_batch)
+                             with_adam="adam" in sc.work, lds_batch=lds_batch, lists=args.lists)
         step.size()
         step.capture()
         ms = time_graph(step.replay, args.steps, args.warmup)
@@ -559,6 +580,7 @@ def bench_config(idx, args):
     gbs = alg / (ms * 1e-3) / 1e9
     out = {"workload": sc.name, "work": sc.work, "gaussians": sc.n, "views": sc.n_views,
            "pixels_per_step": sc.total_pixels, "tile": tile, "lds_batch": lds_batch, "layout": args.layout,
+           "lists": args.lists,
            "pairs": c["M"],
            "ms_per_step": round(ms, 4),
            "value": round(mpix / (ms * 1e-3), 2), "unit": "Mpix*iter/s", "step_alg_bytes": alg,
@@ -586,7 +608,8 @@ def bench_config(idx, args):
         log(f"[bench]   oracle: {dt:.2f} s ({out['cpu_oracle']['value']} Mpix*iter/s)")
     if sc.n_views > 1 and sc.work != "fwd" and not args.no_per_view:
         pv = R.PerViewMappingStep(params, sc.cameras, sc.targets, lrs=lrs, tile_size=tile,
-                                  checkpoint=sc.checkpoint, with_adam="adam" in sc.work, lds_batch=lds_batch)
+                                  checkpoint=sc.checkpoint, with_adam="adam" in sc.work, lds_batch=lds_batch,
+                                  lists=args.lists)
         pv.size()
         ms_eager = time_graph(pv.run, args.steps, args.warmup)
         pv.capture()
