@@ -248,9 +248,10 @@ struct SplatLoader {
     valid = idx >= tr.s && idx < tr.e;
     if (valid) {
       if constexpr (WIN) {
-        const uint2 it = la.items[idx];
-        id = it.x;
-        valid = item_covers(it.y, tr.lx, tr.ly);
+        // one 8-byte load (pair and clipped rect together), then the cover test
+        const unsigned long long it = reinterpret_cast<const unsigned long long*>(la.items)[idx];
+        id = (uint32_t)it;
+        valid = item_covers((uint32_t)(it >> 32), tr.lx, tr.ly);
       } else {
         id = la.ids[idx];
       }
@@ -497,7 +498,7 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_wave
         if (!q_in_range(q, Bv.z)) continue;
         // the rest is branch-free: a pixel that does not blend gets weight 0, which adds exactly nothing
         const float oG = Bv.y * __builtin_amdgcn_exp2f(-q);
-        const float alpha = oG <= amax ? oG : amax;  // min(alpha_max, oG), also for NaN
+        const float alpha = fminf(oG, amax);  // one v_min (NaN, not reachable here, would give alpha_max)
         const float test = T[p] * (1.0f - alpha);
         const bool keep = alpha >= rc.alpha_min;
         const bool stop = keep && test < rc.t_min;
@@ -514,6 +515,13 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_wave
     vbase += n_valid;
   }
   float lsum = 0.0f;
+  float tg[PPL][3];  // the target's pixels, all loads in flight before the stores
+  if (target) {
+#pragma unroll
+    for (int p = 0; p < PPL; ++p)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tg[p][c] = target[pm.inside(p) ? pm.chan(p, c) : 0];
+  }
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
     if (!pm.inside(p)) continue;
@@ -521,7 +529,7 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_wave
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       img[pm.chan(p, c)] = out[c];
-      if (target) lsum += fabsf(out[c] - target[pm.chan(p, c)]);
+      if (target) lsum += fabsf(out[c] - tg[p][c]);
     }
     if (STATE) {
       tfin[pm.pix(p)] = T[p];
@@ -685,27 +693,34 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
   // a pixel that has stopped gets row coordinate +inf (see k_render_fwd)
   float T[PPL], Dp[PPL], dl[PPL][3], fy[PPL];
   const float wv = 1.0f / (3.0f * (float)pm.W * (float)pm.H);
+  {
+    // every pixel's image and target (or dL/dimage) loads first, all in flight together (a pixel
+    // outside the image reads element 0 and discards it)
+    const bool l1 = loss_kind == GS_LOSS_L1;
+    const float* __restrict__ second = l1 ? target : dl_dimage;
+    float col[PPL][3], aux[PPL][3];
 #pragma unroll
-  for (int p = 0; p < PPL; ++p) {
-    fy[p] = pm.inside(p) ? (float)pm.row(p) : INFINITY;
-    T[p] = 1.0f;
-    float col[3];
+    for (int p = 0; p < PPL; ++p)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float d = 0.0f;
-      col[c] = 0.0f;
-      if (pm.inside(p)) {
-        col[c] = img[pm.chan(p, c)];
-        if (loss_kind == GS_LOSS_L1) {
-          const float r = col[c] - target[pm.chan(p, c)];
-          d = r > 0.0f ? wv : (r < 0.0f ? -wv : 0.0f);
-        } else {
-          d = dl_dimage[pm.chan(p, c)];
-        }
+      for (int c = 0; c < 3; ++c) {
+        const int at = pm.inside(p) ? pm.chan(p, c) : 0;
+        col[p][c] = img[at];
+        aux[p][c] = second[at];
       }
-      dl[p][c] = d;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const bool in = pm.inside(p);
+      fy[p] = in ? (float)pm.row(p) : INFINITY;
+      T[p] = 1.0f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float r = col[p][c] - aux[p][c];
+        const float d = l1 ? (r > 0.0f ? wv : (r < 0.0f ? -wv : 0.0f)) : aux[p][c];
+        dl[p][c] = in ? d : 0.0f;
+        col[p][c] = in ? col[p][c] : 0.0f;
+      }
+      Dp[p] = fmaf(dl[p][2], col[p][2], fmaf(dl[p][1], col[p][1], dl[p][0] * col[p][0]));
     }
-    Dp[p] = fmaf(dl[p][2], col[2], fmaf(dl[p][1], col[1], dl[p][0] * col[0]));
   }
   Acc6 acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   float amx = 0.0f, amy = 0.0f;  // ABS: the lane's sums of |dL_p/dmean| for the current entry
@@ -744,7 +759,7 @@ __attribute__((amdgpu_waves_per_eu(BwdShape<TILE>::PPL == 8 ? 4 : 5))) void k_re
         // gradient, which add exactly nothing (every factor is finite: 1 - alpha >= 1 - alpha_max)
         const float oG = Bv.y * __builtin_amdgcn_exp2f(-q);
         const bool below = oG <= amax;
-        const float alpha = below ? oG : amax;  // min(alpha_max, oG), also for NaN
+        const float alpha = fminf(oG, amax);  // one v_min, independent of the compare
         const float om = 1.0f - alpha;
         const float test = T[p] * om;
         const bool keep = alpha >= rc.alpha_min;
@@ -858,7 +873,7 @@ __global__ __launch_bounds__(FwdShape<TILE>::THREADS) void k_render_stats(
         const float q = splat_q(rt, geo.x, fy[p] - cu.y);
         if (q < 0.0f) continue;  // power > 0
         const float oG = geo.y * __builtin_amdgcn_exp2f(-q);
-        const float alpha = oG <= amax ? oG : amax;  // min(alpha_max, oG), also for NaN
+        const float alpha = fminf(oG, amax);  // one v_min (NaN, not reachable here, would give alpha_max)
         if (!(alpha >= rc.alpha_min)) continue;
         const float test = T[p] * (1.0f - alpha);
         if (test < rc.t_min) {
