@@ -397,7 +397,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
         const uint32_t kk = s_keys[i];
         const uint32_t d = (kk >> shift) & (kRadixBins - 1);
         const uint32_t g = s_glob[d] + (i - s_start[d]);
-        if constexpr (!GATHER) kout[g] = kk;
+        if constexpr (!GATHER) {
+          if (kout) kout[g] = kk;  // (no key output: the pass's keys are not needed after it)
+        }
         if constexpr (GATHER) {
           const Words4 v = s_vals[i];
           vout[g] = make_uint4(v.x, v.y, v.z, v.w);
@@ -1301,8 +1303,9 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
                      (uint32_t)n, wkey[0], witem[0]);
   // (window lists: the last pass writes the caller's items)
   uint2* items_out = win_lists ? reinterpret_cast<uint2*>(bins->items) : nullptr;
+  // (with a single pass the window runs come from its digit totals, so its keys are not written)
   for (int k = 0; k < p.win_passes; ++k)
-    radix_pass<uint2>(wkey[k % 2], witem[k % 2], wkey[(k + 1) % 2],
+    radix_pass<uint2>(wkey[k % 2], witem[k % 2], p.win_passes == 1 ? nullptr : wkey[(k + 1) % 2],
                       (items_out && k + 1 == p.win_passes) ? items_out : witem[(k + 1) % 2], d_e, kRadixBits * k,
                       p.nb_items, hist, dtot, st);
   const uint32_t* skey = wkey[p.win_passes % 2];
