@@ -44,8 +44,9 @@ def parse():
     ap.add_argument("--layout", default="morton", choices=["morton", "generated"],
                     help="order of the Gaussian set in memory: Morton order of the means (gs_spatial_order, the "
                          "layout the mapping loop keeps) or the order the scene generator drew them in")
-    ap.add_argument("--lists", default="window", choices=["window", "tile"],
-                    help="form of the bins: each 8 x 8-tile window's list (the default) or every tile's list")
+    ap.add_argument("--lists", default="auto", choices=["auto", "window", "tile"],
+                    help="form of the bins: each 8 x 8-tile window's list or every tile's list (auto: autotuned "
+                         "with the tile, or window lists at a fixed tile)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--configs", default="1,2,3,4",
                     help="comma-separated other workloads (1-4) timed after the main one ('' for none)")
@@ -97,13 +98,14 @@ def main():
     if tile == 0:
         tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint,
                                batches=(1, 2) if lds_batch == 0 else (lds_batch,), lists=args.lists)
-        tile, lds_batch = tune["best"], tune["lds_batch"]
+        tile, lds_batch, lists = tune["best"], tune["lds_batch"], tune["lists"]
         log(f"[bench] autotune: {tune}")
     elif lds_batch == 0:
         lds_batch = 1
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
-    lists = args.lists
+    if tune is None:
+        lists = "window" if args.lists == "auto" else args.lists
     step = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
                          with_adam=with_adam, lds_batch=lds_batch, lists=lists)
     step.size()
@@ -184,9 +186,12 @@ def main():
 
     lists_info = {"form": lists}
     if lists == "window":
-        # the same iteration with the bins as tile lists (the sort writes every tile's list)
+        lists_info.update(items=step.frame.list_entries(), windows=step.rast.total_windows)
+    other = "tile" if lists == "window" else "window"
+    if True:
+        # the same iteration with the bins in the other form
         st_t = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                             with_adam=with_adam, lds_batch=lds_batch, lists="tile")
+                             with_adam=with_adam, lds_batch=lds_batch, lists=other)
         st_t.size()
         if use_graph:
             st_t.capture()
@@ -196,10 +201,9 @@ def main():
         for _ in range(args.warmup):
             st_t.run()
         t_stages, _ = stage_breakdown(st_t, args.steps)
-        lists_info.update(items=step.frame.list_entries(), windows=step.rast.total_windows,
-                          tile_lists={"ms_per_step": round(ms_t, 4), "value": round(mpix / (ms_t * 1e-3), 2),
-                                      "speedup_of_window_lists": round(ms_t / ms, 4), "stages_ms": t_stages})
-        log(f"[bench] tile lists: {ms_t:.3f} ms/step ({ms_t / ms:.3f}x the window-list step), stages {t_stages}")
+        lists_info[f"{other}_lists"] = {"ms_per_step": round(ms_t, 4), "value": round(mpix / (ms_t * 1e-3), 2),
+                                        "ratio_to_chosen": round(ms_t / ms, 4), "stages_ms": t_stages}
+        log(f"[bench] {other} lists: {ms_t:.3f} ms/step ({ms_t / ms:.3f}x the {lists}-list step), stages {t_stages}")
         del st_t
 
     # The same iteration issued eagerly (no graph), for comparison.
@@ -540,16 +544,19 @@ def bench_config(idx, args):
     tune = None
     if sc.work == "fwd":
         tile, lds_batch = 16, 1  # the forward-only workload names 16 x 16 tiles
+        # (the autotuner times forward and backward; this workload's forward alone, 1 k Gaussians whose
+        # tiles walk their whole lists, is faster with tile lists)
+        lists = "tile" if args.lists == "auto" else args.lists
         target = None
     else:
         target = R.pack_images(sc.targets, dev)
         tune = A.autotune_tile(params, sc.cameras, target, checkpoint=sc.checkpoint, lists=args.lists)
-        tile, lds_batch = tune["best"], tune["lds_batch"]
+        tile, lds_batch, lists = tune["best"], tune["lds_batch"], tune["lists"]
     lrs = sc.lrs or dict(S.DEFAULT_LRS)
     mpix = sc.total_pixels * 1e-6
     if sc.work == "fwd":
         rast = R.Rasterizer(sc.cameras, params.n, params.sh_degree, tile_size=tile, checkpoint=sc.checkpoint,
-                            device=dev, lds_batch=lds_batch, lists=args.lists)
+                            device=dev, lds_batch=lds_batch, lists=lists)
         fr = rast.forward(params)
 
         def run_eager():
@@ -572,7 +579,7 @@ def bench_config(idx, args):
         stages = ("project", "bin_sort", "render_fwd")
     else:
         step = R.MappingStep(params, sc.cameras, target, lrs=lrs, tile_size=tile, checkpoint=sc.checkpoint,
-                             with_adam="adam" in sc.work, lds_batch=lds_batch, lists=args.lists)
+                             with_adam="adam" in sc.work, lds_batch=lds_batch, lists=lists)
         step.size()
         step.capture()
         ms = time_graph(step.replay, args.steps, args.warmup)
@@ -587,7 +594,7 @@ def bench_config(idx, args):
     gbs = alg / (ms * 1e-3) / 1e9
     out = {"workload": sc.name, "work": sc.work, "gaussians": sc.n, "views": sc.n_views,
            "pixels_per_step": sc.total_pixels, "tile": tile, "lds_batch": lds_batch, "layout": args.layout,
-           "lists": args.lists,
+           "lists": lists,
            "pairs": c["M"],
            "ms_per_step": round(ms, 4),
            "value": round(mpix / (ms * 1e-3), 2), "unit": "Mpix*iter/s", "step_alg_bytes": alg,
@@ -616,7 +623,7 @@ def bench_config(idx, args):
     if sc.n_views > 1 and sc.work != "fwd" and not args.no_per_view:
         pv = R.PerViewMappingStep(params, sc.cameras, sc.targets, lrs=lrs, tile_size=tile,
                                   checkpoint=sc.checkpoint, with_adam="adam" in sc.work, lds_batch=lds_batch,
-                                  lists=args.lists)
+                                  lists=lists)
         pv.size()
         ms_eager = time_graph(pv.run, args.steps, args.warmup)
         pv.capture()

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 3
+#define GS_ABI_VERSION 4
 #define GS_MAX_VIEWS 32
 #define GS_MAX_SH_DEGREE 3
 /* floats per projected record, see gs_projected */
@@ -457,31 +457,39 @@ gs_status gs_gather_rows(const float* src, int64_t n, int32_t width, const uint3
                          void* stream);
 
 /* ------------------------------------------------------------- autotuning
- * The tile size of the tile-based rasterisation (Sec. III-B) and the LDS
- * batch of the raster kernels (gs_options.lds_batch) are free parameters;
- * gs_autotune picks both by timing the actual problem: for each candidate
- * pair (bits 0-2 of candidate_mask: tile 8, 16, 32; bits 3-4: LDS batch 1,
- * 2; a group with no bit set means all of it) one warm-up and `iters` timed
- * iterations of gs_project, gs_bin_sort, gs_render_fwd with the L1 term
- * against `target` (rgb layout of gs_image, device), gs_raster_bwd and
- * gs_project_bwd on `stream`, at opts with tile_size and lds_batch replaced.
- * Host-side and synchronising, NOT for graph capture; the only call that
- * allocates device memory (its own buffers per tile size, all freed before it
- * returns).  A candidate that does not fit in device memory or whose pair
+ * The tile size of the tile-based rasterisation (Sec. III-B), the LDS batch
+ * of the raster kernels (gs_options.lds_batch) and the form of the bins
+ * (GS_OPT_WINDOW_LISTS) are free parameters: every form gives the same
+ * images, and which is fastest depends on the problem (window lists save
+ * the sort its tile lists but make a tile scan its window's list, which
+ * pays where pixels stop early and costs where tiles walk their whole
+ * lists).  gs_autotune picks all three by timing the actual problem: for
+ * each candidate (bits 0-2 of candidate_mask: tile 8, 16, 32; bits 3-4: LDS
+ * batch 1, 2; bits 5-6: tile lists, window lists; a group with no bit set
+ * means all of it) one warm-up and `iters` timed iterations of gs_project,
+ * gs_bin_sort, gs_render_fwd with the L1 term against `target` (rgb layout
+ * of gs_image, device), gs_raster_bwd and gs_project_bwd on `stream`, at
+ * opts with tile_size, lds_batch and the bins flag replaced.  Host-side and
+ * synchronising, NOT for graph capture; the only call that allocates device
+ * memory (its own buffers per tile size and form, all freed before it
+ * returns).  A candidate that does not fit in device memory or whose list
  * count exceeds the 32-bit index space is skipped (ms -1); GS_ERR_CAPACITY
  * when none fits.  Results are cached for the life of the process by
  * (floor(log2 n), the multiset of view resolutions, sh_degree, checkpoint,
- * candidate mask); refresh != 0 times again.  The parameters are not
- * modified. */
+ * the other option flags, candidate mask); refresh != 0 times again.  The
+ * parameters are not modified. */
+#define GS_AUTOTUNE_MAX_CANDIDATES 12
 typedef struct gs_autotune_result {
   int32_t tile_size;     /* the fastest candidate's tile size */
-  int32_t lds_batch;     /* and its LDS batch */
+  int32_t lds_batch;     /* its LDS batch */
+  int32_t window_lists;  /* 1: its bins are window lists (set GS_OPT_WINDOW_LISTS), 0: tile lists */
   int32_t from_cache;    /* 1: taken from the cache, nothing timed */
   int32_t n_candidates;  /* candidates timed, in the order of the arrays */
-  int32_t cand_tile[6];
-  int32_t cand_batch[6];
-  float ms[6];           /* mean milliseconds of one iteration at each (-1: skipped) */
-  int64_t pairs[6];      /* (tile, Gaussian) incidences at each (-1: not reached) */
+  int32_t cand_tile[GS_AUTOTUNE_MAX_CANDIDATES];
+  int32_t cand_batch[GS_AUTOTUNE_MAX_CANDIDATES];
+  int32_t cand_window[GS_AUTOTUNE_MAX_CANDIDATES];
+  float ms[GS_AUTOTUNE_MAX_CANDIDATES];      /* mean milliseconds of one iteration at each (-1: skipped) */
+  int64_t pairs[GS_AUTOTUNE_MAX_CANDIDATES]; /* (tile, Gaussian) incidences at each (-1: not reached) */
 } gs_autotune_result;
 
 gs_status gs_autotune(const gs_params* params, const gs_camera* cams, int32_t n_views, const gs_options* opts,

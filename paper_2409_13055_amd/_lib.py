@@ -83,10 +83,15 @@ class gs_adam_group(C.Structure):
                 ("lr", C.c_float), ("reserved", C.c_int32)]
 
 
+GS_AUTOTUNE_MAX_CANDIDATES = 12  # include/gs.h
+
+
 class gs_autotune_result(C.Structure):
-    _fields_ = [("tile_size", C.c_int32), ("lds_batch", C.c_int32), ("from_cache", C.c_int32),
-                ("n_candidates", C.c_int32), ("cand_tile", C.c_int32 * 6), ("cand_batch", C.c_int32 * 6),
-                ("ms", C.c_float * 6), ("pairs", C.c_int64 * 6)]
+    _K = GS_AUTOTUNE_MAX_CANDIDATES
+    _fields_ = [("tile_size", C.c_int32), ("lds_batch", C.c_int32), ("window_lists", C.c_int32),
+                ("from_cache", C.c_int32), ("n_candidates", C.c_int32), ("cand_tile", C.c_int32 * _K),
+                ("cand_batch", C.c_int32 * _K), ("cand_window", C.c_int32 * _K), ("ms", C.c_float * _K),
+                ("pairs", C.c_int64 * _K)]
 
 
 EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_options", "gs_total_tiles",
@@ -100,7 +105,7 @@ EXPORTS = ("gs_status_string", "gs_last_error", "gs_abi_version", "gs_default_op
            "gs_render_fwd_noalloc", "gs_autotune", "gs_spatial_order_workspace_size", "gs_spatial_order",
            "gs_gather_rows")
 
-GS_ABI_VERSION = 3  # include/gs.h
+GS_ABI_VERSION = 4  # include/gs.h
 GS_OPT_WINDOW_LISTS = 1  # gs_options.flags
 _lib = None
 

@@ -38,6 +38,8 @@ struct DeviceBuffers {
   }
 };
 
+static_assert(GS_AUTOTUNE_MAX_CANDIDATES >= 3 * 2 * 2, "three tile sizes x two LDS batches x two bins forms");
+
 std::mutex g_cache_mu;
 std::map<std::vector<int64_t>, gs_autotune_result> g_cache;
 
@@ -47,7 +49,7 @@ std::vector<int64_t> cache_key(const gs_params* p, const gs_camera* cams, int32_
   key.push_back((int64_t)std::floor(std::log2((double)std::max<int64_t>(p->n, 1))));
   key.push_back(p->sh_degree);
   key.push_back(o->checkpoint);
-  key.push_back((int64_t)o->flags);
+  key.push_back((int64_t)(o->flags & ~GS_OPT_WINDOW_LISTS));  // the bins form is a candidate
   key.push_back(mask);
   std::vector<int64_t> res;
   for (int v = 0; v < n_views; ++v) res.push_back((int64_t)cams[v].width << 32 | (int64_t)cams[v].height);
@@ -207,11 +209,13 @@ extern "C" gs_status gs_autotune(const gs_params* params, const gs_camera* cams,
   if (!target) return fail(GS_ERR_INVALID_VALUE, "gs_autotune times the L1 iteration: target is required");
   if (!out) return fail(GS_ERR_INVALID_VALUE, "out is NULL");
   if (iters < 1 || iters > 1000) return fail(GS_ERR_INVALID_VALUE, "iters must be in [1, 1000]");
-  if (candidate_mask < 0 || candidate_mask > 31)
-    return fail(GS_ERR_INVALID_VALUE, "candidate_mask uses bits 0-2 (tiles 8, 16, 32) and 3-4 (LDS batch 1, 2)");
+  if (candidate_mask < 0 || candidate_mask > 127)
+    return fail(GS_ERR_INVALID_VALUE,
+                "candidate_mask uses bits 0-2 (tiles 8, 16, 32), 3-4 (LDS batch 1, 2) and 5-6 (tile, window lists)");
   const int32_t tmask = (candidate_mask & 7) == 0 ? 7 : (candidate_mask & 7);
   const int32_t bmask = ((candidate_mask >> 3) & 3) == 0 ? 3 : ((candidate_mask >> 3) & 3);
-  const int32_t mask = tmask | (bmask << 3);
+  const int32_t lmask = ((candidate_mask >> 5) & 3) == 0 ? 3 : ((candidate_mask >> 5) & 3);
+  const int32_t mask = tmask | (bmask << 3) | (lmask << 5);
   if ((int64_t)n_views * params->n >= (int64_t(1) << 32) - 1) return fail(GS_ERR_INVALID_VALUE, "bad n");
   const std::vector<int64_t> key = cache_key(params, cams, n_views, opts, mask);
   if (!refresh) {
@@ -234,20 +238,27 @@ extern "C" gs_status gs_autotune(const gs_params* params, const gs_camera* cams,
   float best = 0.0f;
   for (int k = 0; k < 3; ++k) {
     if (!((tmask >> k) & 1)) continue;
-    const int c = r.n_candidates;
-    r.n_candidates += n_b;
-    for (int b = 0; b < n_b; ++b) {
-      r.cand_tile[c + b] = tiles[k];
-      r.cand_batch[c + b] = batches[b];
-    }
-    if ((s = time_candidate(params, cams, n_views, opts, tiles[k], batches, n_b, target, iters, st, &r.ms[c],
-                            &r.pairs[c])) != GS_OK)
-      return s;
-    for (int b = 0; b < n_b; ++b) {
-      if (r.ms[c + b] > 0.0f && (r.tile_size == 0 || r.ms[c + b] < best)) {
-        best = r.ms[c + b];
-        r.tile_size = tiles[k];
-        r.lds_batch = batches[b];
+    for (int f = 0; f < 2; ++f) {
+      if (!((lmask >> f) & 1)) continue;
+      gs_options of = *opts;
+      of.flags = f ? (of.flags | GS_OPT_WINDOW_LISTS) : (of.flags & ~GS_OPT_WINDOW_LISTS);
+      const int c = r.n_candidates;
+      r.n_candidates += n_b;
+      for (int b = 0; b < n_b; ++b) {
+        r.cand_tile[c + b] = tiles[k];
+        r.cand_batch[c + b] = batches[b];
+        r.cand_window[c + b] = f;
+      }
+      if ((s = time_candidate(params, cams, n_views, &of, tiles[k], batches, n_b, target, iters, st, &r.ms[c],
+                              &r.pairs[c])) != GS_OK)
+        return s;
+      for (int b = 0; b < n_b; ++b) {
+        if (r.ms[c + b] > 0.0f && (r.tile_size == 0 || r.ms[c + b] < best)) {
+          best = r.ms[c + b];
+          r.tile_size = tiles[k];
+          r.lds_batch = batches[b];
+          r.window_lists = f;
+        }
       }
     }
   }

@@ -40,7 +40,7 @@ def test_defaults_and_queries(L):
     from paper_2409_13055_amd import synthetic as S
     o = L.default_options()
     assert o.tile_size == 16 and o.checkpoint == 0 and o.flags == 0 and o.lds_batch == 1
-    assert L.load().gs_abi_version() == L.GS_ABI_VERSION == 3
+    assert L.load().gs_abi_version() == L.GS_ABI_VERSION == 4
     assert abs(o.alpha_min - 1 / 255) < 1e-9 and abs(o.alpha_max - 0.99) < 1e-7 and abs(o.t_min - 1e-4) < 1e-10
     assert abs(o.near_plane - 0.2) < 1e-7 and abs(o.eps2d - 0.3) < 1e-7 and o.radius_sigmas == 3.0
     cams = [S.pinhole(1200, 680, 600.0), S.pinhole(640, 480, 525.0), S.pinhole(100, 75, 90.0)]
@@ -280,6 +280,10 @@ def _incircle_exact(a, b, c, d):
             + m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]))
 
 
+def gs_offset(struct, field):
+    return getattr(type(struct), field).offset
+
+
 def test_autotune_validates_before_any_launch(L):
     """gs_autotune (host-side, synchronising) rejects bad arguments before touching the device."""
     from paper_2409_13055_amd import synthetic as S
@@ -294,14 +298,16 @@ def test_autotune_validates_before_any_launch(L):
         L.gs_autotune(params, cc, 1, o, None, 3, 0, 0, None)
     with pytest.raises(L.GsError, match="iters"):
         L.gs_autotune(params, cc, 1, o, C.c_void_p(0x6000), 0, 0, 0, None)
-    for mask in (32, -1):
+    for mask in (128, -1):
         with pytest.raises(L.GsError, match="candidate_mask"):
             L.gs_autotune(params, cc, 1, o, C.c_void_p(0x6000), 3, mask, 0, None)
     params.sh_degree = 4
     with pytest.raises(L.GsError, match="sh_degree"):
         L.gs_autotune(params, cc, 1, o, C.c_void_p(0x6000), 3, 0, 0, None)
     r = L.gs_autotune_result()
-    assert C.sizeof(r) == 136  # int32 x 16, float x 6, int64 x 6: the layout gs.h declares
+    # int32 x (5 + 3 x 12), float x 12, then int64 x 12 at the next 8-byte boundary: the layout gs.h declares
+    assert L.GS_AUTOTUNE_MAX_CANDIDATES == 12
+    assert C.sizeof(r) == 216 + 8 * 12 and gs_offset(r, "pairs") == 216
 
 
 def test_layout_calls_validate_before_any_launch(L):

@@ -499,8 +499,9 @@ def test_render_stats_counts_match_oracle():
 
 
 def test_autotune_times_every_tile_and_parity_holds_at_its_choice():
-    """gs_autotune (through the C ABI) times tiles 8, 16 and 32 on the actual problem, picks the fastest,
-    leaves the parameters untouched and caches the choice; the chosen tile passes the parity checks."""
+    """gs_autotune (through the C ABI) times tiles 8, 16 and 32, LDS batches 1 and 2 and both forms of the
+    bins on the actual problem, picks the fastest, leaves the parameters untouched and caches the choice;
+    the chosen configuration passes the parity checks."""
     from paper_2409_13055_amd import autotune as A
     from paper_2409_13055_amd import rasterizer as R
     sc = small_scene(seed=17, n=3000)
@@ -510,18 +511,20 @@ def test_autotune_times_every_tile_and_parity_holds_at_its_choice():
     res = A.autotune_tile(params, sc.cameras, target, refresh=True)
     ms, pairs = res["ms_fwd_bwd"], res["pairs"]
     assert not res["from_cache"] and all(v > 0 for v in ms.values()), res
-    assert set(ms) == {f"{t}/{b}" for t in (8, 16, 32) for b in (1, 2)}, res
-    assert f"{res['best']}/{res['lds_batch']}" == min(ms, key=ms.get)
+    assert set(ms) == {f"{t}/{b}/{f}" for t in (8, 16, 32) for b in (1, 2) for f in ("tile", "window")}, res
+    assert f"{res['best']}/{res['lds_batch']}/{res['lists']}" == min(ms, key=ms.get)
     assert pairs[8] >= pairs[16] >= pairs[32] > 0  # a finer grid lists a splat in at least as many tiles
     for a, b in zip(before, params.tensors()):
         assert torch.equal(a, b)
     again = A.autotune_tile(params, sc.cameras, target)
-    assert again["from_cache"] and (again["best"], again["lds_batch"]) == (res["best"], res["lds_batch"])
-    only = A.autotune_tile(params, sc.cameras, target, candidates=(16,), batches=(2,), refresh=True)
-    assert set(only["ms_fwd_bwd"]) == {"16/2"} and (only["best"], only["lds_batch"]) == (16, 2)
+    assert again["from_cache"] and (again["best"], again["lds_batch"], again["lists"]) == \
+        (res["best"], res["lds_batch"], res["lists"])
+    only = A.autotune_tile(params, sc.cameras, target, candidates=(16,), batches=(2,), refresh=True, lists="window")
+    assert set(only["ms_fwd_bwd"]) == {"16/2/window"} and (only["best"], only["lds_batch"], only["lists"]) == \
+        (16, 2, "window")
     tile = res["best"]
     opts = O.Options(tile=tile)
-    g = U.run_gpu(sc, tile=tile, lds_batch=res["lds_batch"])
+    g = U.run_gpu(sc, tile=tile, lds_batch=res["lds_batch"], lists=res["lists"])
     check_bins(sc, g, tile)
     check_image_pinned(sc, g, opts)
     orec = U.gpu_rec_to_oracle(g["rec"])
