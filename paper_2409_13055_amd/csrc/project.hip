@@ -616,6 +616,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
   const int nb = (int)min<int64_t>(T, a.n - i0);
   const int width[kParamGroups] = {3, 3, 4, 1, 3, 3 * (K - 1)};
   const int off[kParamGroups] = {0, 3, 6, 10, 11, 14};
+  // Each group's range of the block as float4 (it starts 16-byte aligned: i0 is a multiple of 256),
+  // four chunks per thread at a time with all their loads in flight before any update or store;
+  // the last block's remainder one by one.
 #pragma unroll
   for (int grp = 0; grp < kParamGroups; ++grp) {
     const int w = width[grp];
@@ -625,21 +628,31 @@ __global__ __launch_bounds__(kBwdThreads) void k_project_bwd(ProjectArgs a, CamT
     float* __restrict__ M = ap.m[grp] + i0 * w;
     float* __restrict__ V = ap.v[grp] + i0 * w;
     const float step_size = ap.lr[grp] * k1;
-    // float4 over the block's range (it starts 16-byte aligned: i0 is a multiple of 256), the last
-    // block's remainder one by one
     const int cnt = nb * w, n4 = (((reinterpret_cast<uintptr_t>(P) | reinterpret_cast<uintptr_t>(M) |
                                     reinterpret_cast<uintptr_t>(V)) & 15) == 0) ? cnt / 4 : 0;
-    for (int q = t; q < n4; q += T) {
-      float4 pv = reinterpret_cast<float4*>(P)[q], mv = reinterpret_cast<float4*>(M)[q];
-      float4 vv = reinterpret_cast<float4*>(V)[q];
-      const float4 gv = reinterpret_cast<const float4*>(G)[q];
-      adam_update(pv.x, gv.x, mv.x, vv.x, ap.c, step_size, k2);
-      adam_update(pv.y, gv.y, mv.y, vv.y, ap.c, step_size, k2);
-      adam_update(pv.z, gv.z, mv.z, vv.z, ap.c, step_size, k2);
-      adam_update(pv.w, gv.w, mv.w, vv.w, ap.c, step_size, k2);
-      reinterpret_cast<float4*>(P)[q] = pv;
-      reinterpret_cast<float4*>(M)[q] = mv;
-      reinterpret_cast<float4*>(V)[q] = vv;
+    constexpr int U = 4;
+    for (int q0 = t; q0 < n4; q0 += U * T) {
+      float4 pv[U], mv[U], vv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = min(q0 + u * T, n4 - 1);  // clamped: every load in bounds, the extra ones unused
+        pv[u] = reinterpret_cast<const float4*>(P)[q];
+        mv[u] = reinterpret_cast<const float4*>(M)[q];
+        vv[u] = reinterpret_cast<const float4*>(V)[q];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * T;
+        if (q >= n4) break;
+        const float4 gv = reinterpret_cast<const float4*>(G)[q];
+        adam_update(pv[u].x, gv.x, mv[u].x, vv[u].x, ap.c, step_size, k2);
+        adam_update(pv[u].y, gv.y, mv[u].y, vv[u].y, ap.c, step_size, k2);
+        adam_update(pv[u].z, gv.z, mv[u].z, vv[u].z, ap.c, step_size, k2);
+        adam_update(pv[u].w, gv.w, mv[u].w, vv[u].w, ap.c, step_size, k2);
+        reinterpret_cast<float4*>(P)[q] = pv[u];
+        reinterpret_cast<float4*>(M)[q] = mv[u];
+        reinterpret_cast<float4*>(V)[q] = vv[u];
+      }
     }
     for (int e = 4 * n4 + t; e < cnt; e += T) {
       float pv = P[e], mv = M[e], vv = V[e];
