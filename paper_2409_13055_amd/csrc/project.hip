@@ -295,11 +295,14 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a, CamTable cams, f
     uint32_t flags = 0;
     const float fmx = ok ? (float)p.mx : 0.f, fmy = ok ? (float)p.my : 0.f;
     if (ok) {
+      // the integer extents from FP32 square roots of FP64 arguments: they differ from FP64 roots only
+      // where a root lies within a few 1e-7 of an integer (the FP32 rounding of the argument and of
+      // the root), a boundary case of the extents either way
       const real mid = 0.5 * (p.a + p.c);
-      const real lam = mid + sqrt(fmax(mid * mid - (p.a * p.c - p.b * p.b), 0.0));
-      const real r = fmin(ceil((real)a.radius_sigmas * sqrt(lam)), (real)kMaxExtent);
-      const int rx = (int)fmin(r, ceil(sqrt(thr * p.a)) + 1.0);
-      const int ry = (int)fmin(r, ceil(sqrt(thr * p.c)) + 1.0);
+      const float lam = (float)mid + sqrtf((float)fmax(mid * mid - (p.a * p.c - p.b * p.b), 0.0));
+      const float r = fminf(ceilf(a.radius_sigmas * sqrtf(lam)), (float)kMaxExtent);
+      const int rx = (int)fminf(r, ceilf(sqrtf((float)(thr * p.a))) + 1.0f);
+      const int ry = (int)fminf(r, ceilf(sqrtf((float)(thr * p.c))) + 1.0f);
       const int TX = (cam.W + B - 1) / B, TY = (cam.H + B - 1) / B;
       tile_rect(fmx, fmy, rx, ry, B, TX, TY, x0, y0, x1, y1);
       tiles = (x1 - x0) * (y1 - y0);
