@@ -314,8 +314,16 @@ def main():
                    "reduce_hbm_frac": round(gbs / 8000.0, 4), "levels": {}}
         log(f"[bench] pyramid reduce (all views, level 0 -> 1): {ms_r:.4f} ms ({gbs:.0f} GB/s alg)")
         for lv in (1, 2):
-            st = R.MappingStep(params, pyr.cameras[lv], pyr.images[lv], lrs=lrs, tile_size=tile,
-                               checkpoint=sc.checkpoint, with_adam=with_adam, lds_batch=lds_batch, lists=lists)
+            # a coarse level is a different problem (a quarter or a sixteenth of the pixels, the same
+            # Gaussians): with the tile size left to the autotuner, each level gets its own choice
+            t_lv, b_lv, f_lv, tune_lv = tile, lds_batch, lists, None
+            if args.tile == 0:
+                tune_lv = A.autotune_tile(params, pyr.cameras[lv], pyr.images[lv], checkpoint=sc.checkpoint,
+                                          batches=(1, 2) if args.lds_batch == 0 else (args.lds_batch,),
+                                          lists=args.lists, iters=2)
+                t_lv, b_lv, f_lv = tune_lv["best"], tune_lv["lds_batch"], tune_lv["lists"]
+            st = R.MappingStep(params, pyr.cameras[lv], pyr.images[lv], lrs=lrs, tile_size=t_lv,
+                               checkpoint=sc.checkpoint, with_adam=with_adam, lds_batch=b_lv, lists=f_lv)
             st.size()
             if use_graph:
                 st.capture()
@@ -333,8 +341,12 @@ def main():
             pxl = sum(c.width * c.height for c in pyr.cameras[lv])
             pyramid["levels"][str(lv)] = {"ms_per_step": round(ms_lv, 4), "pixels_per_step": pxl,
                                           "value": round(pxl * 1e-6 / (ms_lv * 1e-3), 2),
-                                          "speedup_vs_level0": round(ms / ms_lv, 3)}
-            log(f"[bench] level {lv}: {ms_lv:.3f} ms/step ({ms / ms_lv:.2f}x faster than level 0)")
+                                          "speedup_vs_level0": round(ms / ms_lv, 3),
+                                          "tile": t_lv, "lds_batch": b_lv, "lists": f_lv}
+            if tune_lv is not None:
+                pyramid["levels"][str(lv)]["autotune_ms"] = tune_lv["ms_fwd_bwd"]
+            log(f"[bench] level {lv}: {ms_lv:.3f} ms/step ({ms / ms_lv:.2f}x faster than level 0; "
+                f"tile {t_lv}, batch {b_lv}, {f_lv} lists)")
             del st
         del pyr
 

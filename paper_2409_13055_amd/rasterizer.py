@@ -764,9 +764,12 @@ class PyramidMappingStep:
 
     def __init__(self, params: GaussianParams, cameras, targets, levels: int = 2, schedule=None, lrs=None,
                  graphs: bool = True, adam: Optional[FusedAdam] = None, pyramid: Optional["ImagePyramid"] = None,
-                 iteration: int = 0, **step_opts):
+                 iteration: int = 0, autotune: bool = False, **step_opts):
         """`adam`, `pyramid`, `iteration`: an optimiser state, a built pyramid of these targets and a
-        position in the schedule to continue from (after density control changed the set)."""
+        position in the schedule to continue from (after density control changed the set).
+        autotune: each batch of per-view levels takes the tile size, LDS batch and bins form that
+        gs_autotune picks for it (coarse levels favour other settings than full resolution), in
+        place of those in step_opts."""
         self.params = params
         self.pyramid = pyramid if pyramid is not None else ImagePyramid(cameras, targets, levels,
                                                                         device=params.means.device)
@@ -778,6 +781,8 @@ class PyramidMappingStep:
         self.lrs = lrs
         self.graphs = graphs
         self.step_opts = step_opts
+        self.autotune = bool(autotune)
+        self.tuned: Dict[tuple, dict] = {}  # per level batch: what the autotuner chose
         self.adam = adam if adam is not None else FusedAdam(params, params.zeros_like(), lrs)
         self.steps: Dict[tuple, MappingStep] = {}
         self._ran_at_capture = set()  # keys whose newest iteration capture() already ran
@@ -798,7 +803,13 @@ class PyramidMappingStep:
         st = self.steps.get(key)
         if st is None:
             cams, tgt = self.pyramid.batch(key)
-            st = MappingStep(self.params, cams, tgt, lrs=self.lrs, adam=self.adam, **self.step_opts)
+            opts = dict(self.step_opts)
+            if self.autotune:
+                from .autotune import autotune_tile  # (the autotuner's binding imports this module)
+                tune = autotune_tile(self.params, cams, tgt, checkpoint=bool(opts.get("checkpoint", False)), iters=2)
+                opts.update(tile_size=tune["best"], lds_batch=tune["lds_batch"], lists=tune["lists"])
+                self.tuned[key] = tune
+            st = MappingStep(self.params, cams, tgt, lrs=self.lrs, adam=self.adam, **opts)
             st.size()
             if self.graphs:
                 st.capture()  # runs one iteration eagerly, then records one
@@ -979,11 +990,13 @@ class MappingLoop:
     def __init__(self, params: GaussianParams, cameras, targets, lrs=None, levels: int = 2, schedule=None,
                  ssim_lambda: float = 0.2, densify_every: int = 1000, tile_size: int = 16, graphs: bool = True,
                  generator: Optional[torch.Generator] = None, check_every: int = 100, spatial_order: bool = True,
-                 **density_cfg):
+                 autotune: bool = False, **density_cfg):
         """check_every: iterations between host checks of the pair-capacity overflow flag (also checked
         before every density step); an overflow raises CapacityOverflow.  spatial_order: the set a
         density step makes is put in Morton order of its means (spatially_ordered) before the
-        iterations continue; its statistics restart at zero, so only the parameters and moments move."""
+        iterations continue; its statistics restart at zero, so only the parameters and moments move.
+        autotune: every per-view level batch is autotuned (PyramidMappingStep), again after each
+        density step since the set, and with it the best setting, has changed."""
         self.cameras, self.lrs, self.levels = list(cameras), lrs, int(levels)
         self.targets = [t if isinstance(t, torch.Tensor) else pack_images([t], params.means.device)
                         for t in targets]
@@ -994,7 +1007,7 @@ class MappingLoop:
         self.last_order = None  # the permutation of the last reorder (int32, new row k <- row order[k])
         self.density = DensityControl(params.n, cameras, device=params.means.device, **density_cfg)
         self._opts = dict(schedule=schedule, lrs=lrs, graphs=graphs, ssim_lambda=ssim_lambda, tile_size=tile_size,
-                          density=self.density)
+                          density=self.density, autotune=autotune)
         self.steps = PyramidMappingStep(params, self.cameras, torch.cat(self.targets), levels=self.levels,
                                         **self._opts)
         self.kf_iters = [0] * len(self.cameras)  # iterations each keyframe has trained

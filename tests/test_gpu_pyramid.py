@@ -109,6 +109,27 @@ def test_level_step_renders_the_level_camera_against_the_reduced_target():
         np.testing.assert_allclose(st.loss.cpu().numpy(), O.l1_loss_per_view(img, tgt, lc), rtol=1e-5)
 
 
+def test_autotuned_levels_take_their_own_settings_and_match_the_oracle():
+    sc = small_scene(5)
+    params = R.GaussianParams.from_scene(sc, DEV)
+    ps = R.PyramidMappingStep(params, sc.cameras, sc.targets, levels=2, lrs=ZERO_LRS, autotune=True)
+    for level in (2, 1, 0):
+        st = ps.run_levels([level] * 3)
+        torch.cuda.synchronize()
+        tune = ps.tuned[(level,) * 3]
+        assert tune["best"] in (8, 16, 32) and tune["lds_batch"] in (1, 2)
+        assert tune["lists"] in ("window", "tile") and len(tune["ms_fwd_bwd"]) == 12
+        assert st.rast.opts.tile_size == tune["best"] and st.rast.lists == tune["lists"]
+        lc = [O.pyramid_camera(c, level) for c in sc.cameras]
+        ref = O.forward(O.Params.from_scene(sc), lc, O.Options(tile=tune["best"]))
+        img = st.frame.rgb.cpu().numpy().astype(np.float64)
+        ok = np.concatenate([np.tile(ref["pix_flags"][off:off + c.width * c.height] == 0, 3) for off, c in
+                             zip(np.cumsum([0] + [c.width * c.height for c in lc])[:-1], lc)])
+        assert ok.mean() > 0.99
+        assert np.abs(img - ref["image"])[ok].max() <= 1e-4, level
+    assert len(ps.tuned) == 3
+
+
 def test_mixed_level_batch_matches_uniform_batches():
     sc = small_scene(7)
     params = R.GaussianParams.from_scene(sc, DEV)
