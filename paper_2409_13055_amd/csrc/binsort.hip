@@ -248,18 +248,34 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
   hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// One block per digit: exclusive scan of that digit's per-block counts.
+// One block per digit: exclusive scan of that digit's per-block counts.  A
+// thread takes kDigitScanItems consecutive counts per round, all loaded before
+// any is used, so up to kSortThreads * kDigitScanItems blocks (every plan's
+// count) take one round: one load round trip to counts the histogram kernel
+// has just written from every XCD, instead of one per 256 blocks.
+constexpr int kDigitScanItems = 16;
+constexpr int kMaxRadixBlocks = 4096;  // radix blocks per pass, at most (the plans' cap)
+static_assert(kSortThreads * kDigitScanItems >= kMaxRadixBlocks, "a digit's scan takes one round");
 __global__ __launch_bounds__(kSortThreads) void k_radix_scan_digit(uint32_t* __restrict__ hist, int nb,
                                                                    uint32_t* __restrict__ digit_total) {
   __shared__ uint32_t s_w[4];
   uint32_t* h = hist + (size_t)blockIdx.x * nb;
   uint32_t carry = 0;
-  for (int base = 0; base < nb; base += kSortThreads) {
-    const int i = base + threadIdx.x;
-    const uint32_t v = i < nb ? h[i] : 0;
+  for (int base = 0; base < nb; base += kSortThreads * kDigitScanItems) {
+    const int i0 = base + (int)threadIdx.x * kDigitScanItems;
+    uint32_t v[kDigitScanItems], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kDigitScanItems; ++k) {
+      v[k] = i0 + k < nb ? h[i0 + k] : 0u;
+      sum += v[k];
+    }
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<uint32_t>(v, s_w, tot);
-    if (i < nb) h[i] = carry + ex;
+    uint32_t run = carry + block_exclusive_scan<uint32_t>(sum, s_w, tot);
+#pragma unroll
+    for (int k = 0; k < kDigitScanItems; ++k) {
+      if (i0 + k < nb) h[i0 + k] = run;
+      run += v[k];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
@@ -974,10 +990,10 @@ static SortPlan make_plan(int64_t n, int32_t n_views, int64_t total_tiles, int64
   SortPlan p;
   p.vn = (uint64_t)n * (uint64_t)n_views;
   p.cap = (uint64_t)capacity;
-  p.nb_vn = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.vn + 2047) / 2048));
+  p.nb_vn = (int)std::min<uint64_t>(kMaxRadixBlocks, std::max<uint64_t>(1, (p.vn + 2047) / 2048));
   p.n_seg = (uint32_t)((uint64_t)n_views * (((uint64_t)n + 63) / 64));
   p.nb_seg = (int)((p.n_seg + kSortThreads - 1) / kSortThreads);
-  p.nb_items = (int)std::min<uint64_t>(4096, std::max<uint64_t>(1, (p.cap + 2047) / 2048));
+  p.nb_items = (int)std::min<uint64_t>(kMaxRadixBlocks, std::max<uint64_t>(1, (p.cap + 2047) / 2048));
   p.n_steps = (int)((p.vn + kStep - 1) / kStep);
   p.grid_steps = std::min(p.n_steps, 4096);
   int bits = 1;
@@ -1143,7 +1159,7 @@ struct OrderPlan {
 static OrderPlan order_plan(int64_t n) {
   OrderPlan p;
   p.nb_box = (int)std::min<int64_t>(1024, (n + kBoxThreads - 1) / kBoxThreads);
-  p.nb = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + 2047) / 2048));
+  p.nb = (int)std::min<int64_t>(kMaxRadixBlocks, std::max<int64_t>(1, (n + 2047) / 2048));
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
