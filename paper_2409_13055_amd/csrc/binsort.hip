@@ -483,8 +483,13 @@ __global__ __launch_bounds__(kSortThreads) void k_step_counts(const uint4* __res
 
 // Exclusive scans of the per-step item and incidence counts in place (one
 // block).  M -> d_num_pairs and the overflow flag; the clamped counts for the
-// rest of the call are zero on overflow, which makes its kernels no-ops.
-__global__ __launch_bounds__(kScanThreads) void k_scan_step_counts(uint64_t* __restrict__ step_win,
+// rest of the call are zero on overflow, which makes its kernels no-ops.  A
+// thread takes kStepScanItems consecutive steps of both arrays per round (8192
+// steps, 16.7 M pairs, per round): at 1024 threads the 64-bit values had
+// exceeded the 128 registers a thread may hold and spilled to scratch.
+constexpr int kStepScanThreads = 512;
+constexpr int kStepScanItems = 16;
+__global__ __launch_bounds__(kStepScanThreads) void k_scan_step_counts(uint64_t* __restrict__ step_win,
                                                                    uint64_t* __restrict__ step_tiles,
                                                                    const uint32_t* __restrict__ d_k,
                                                                    uint32_t* __restrict__ d_e,
@@ -493,24 +498,24 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_step_counts(uint64_t* __r
                                                                    int32_t* __restrict__ d_overflow,
                                                                    int64_t* __restrict__ d_items,
                                                                    uint64_t capacity, int items_bound) {
-  __shared__ uint64_t s_w[kScanThreads / 64];
+  __shared__ uint64_t s_w[kStepScanThreads / 64];
   const uint32_t nsteps = (*d_k + kStep - 1) / kStep;
   uint64_t carry_w = 0, carry_t = 0;
-  for (uint32_t base = 0; base < nsteps; base += kScanThreads * kScanItems) {
-    const uint32_t i0 = base + threadIdx.x * kScanItems;
-    uint64_t vw[kScanItems], vtl[kScanItems], sw = 0, stl = 0;
+  for (uint32_t base = 0; base < nsteps; base += kStepScanThreads * kStepScanItems) {
+    const uint32_t i0 = base + threadIdx.x * kStepScanItems;
+    uint64_t vw[kStepScanItems], vtl[kStepScanItems], sw = 0, stl = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int k = 0; k < kStepScanItems; ++k) {
       vw[k] = i0 + k < nsteps ? step_win[i0 + k] : 0;
       vtl[k] = i0 + k < nsteps ? step_tiles[i0 + k] : 0;
       sw += vw[k];
       stl += vtl[k];
     }
     uint64_t tw, tt;
-    uint64_t rw = carry_w + block_exclusive_scan<uint64_t, kScanThreads>(sw, s_w, tw);
-    uint64_t rt = carry_t + block_exclusive_scan<uint64_t, kScanThreads>(stl, s_w, tt);
+    uint64_t rw = carry_w + block_exclusive_scan<uint64_t, kStepScanThreads>(sw, s_w, tw);
+    uint64_t rt = carry_t + block_exclusive_scan<uint64_t, kStepScanThreads>(stl, s_w, tt);
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int k = 0; k < kStepScanItems; ++k) {
       if (i0 + k < nsteps) {
         step_win[i0 + k] = rw;
         step_tiles[i0 + k] = rt;
@@ -1312,7 +1317,7 @@ extern "C" gs_status gs_bin_sort(const gs_projected* proj, int64_t n, const gs_c
   //    overflow check
   radix_pass<uint32_t, true>(bkey, bval, nullptr, ent, d_k, 24, p.nb_vn, hist, dtot, st, entc);
   hipLaunchKernelGGL(k_step_counts, dim3(p.grid_steps), dim3(kSortThreads), 0, st, ent, d_k, step_win, step_tiles);
-  hipLaunchKernelGGL(k_scan_step_counts, dim3(1), dim3(kScanThreads), 0, st, step_win, step_tiles, d_k, d_e, d_m,
+  hipLaunchKernelGGL(k_scan_step_counts, dim3(1), dim3(kStepScanThreads), 0, st, step_win, step_tiles, d_k, d_e, d_m,
                      bins->d_num_pairs, bins->d_overflow, bins->d_num_items, p.cap, win_lists ? 1 : 0);
   // 4. (window, item) pairs in depth order, stably sorted on the window index
   hipLaunchKernelGGL(k_window_items, dim3(p.grid_steps), dim3(kSortThreads), 0, st, ent, d_k, d_e, step_win, vt,
