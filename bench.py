@@ -70,8 +70,9 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU design is data-parallel over keyframes, see the design notes)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(several GPUs would each take a share of the keyframes and all-reduce the parameter "
+              f"gradients before the Adam step)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2409_13055_amd import synthetic as S
