@@ -211,6 +211,35 @@ def test_mapping_loop_pyramid_ssim_and_density_control():
         assert torch.isfinite(t).all()
 
 
+def test_mapping_loop_autotunes_every_level_batch_again_after_a_density_step():
+    """MappingLoop(autotune=True): each per-view level batch renders with the tile size and bins
+    form the autotuner chose for it, and the batches are tuned again on the set a density step
+    makes.  The bins form and the LDS batch change no output, so the first iteration's loss equals
+    that of an untuned loop at the chosen tile size (the tile size itself does change the image:
+    a tile lists a splat over its whole rect, cut at the radius)."""
+    sc = small_scene(12)
+    kw = dict(lrs=dict(S.DEFAULT_LRS), levels=1, schedule=[2], densify_every=3, grad_threshold=1e-7)
+    tuned = R.MappingLoop(R.GaussianParams.from_scene(sc, DEV), sc.cameras, sc.targets, autotune=True,
+                          generator=torch.Generator(device=DEV).manual_seed(5), **kw)
+    a = tuned.run(1)
+    assert set(tuned.steps.tuned) == {(1, 1)}
+    first = tuned.steps.tuned[(1, 1)]
+    assert a.rast.opts.tile_size == first["best"] and a.rast.lists == first["lists"]
+    plain = R.MappingLoop(R.GaussianParams.from_scene(sc, DEV), sc.cameras, sc.targets, tile_size=first["best"],
+                          generator=torch.Generator(device=DEV).manual_seed(5), **kw)
+    b = plain.run(1)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(a.loss.cpu().numpy(), b.loss.cpu().numpy(), rtol=1e-6)
+    st = tuned.run(4)  # a density step after the third iteration, then two at full resolution
+    torch.cuda.synchronize()
+    assert [h[0] for h in tuned.history] == [3]
+    assert set(tuned.steps.tuned) == {(0, 0)}  # the rebuilt steps: only the batch run since
+    tune = tuned.steps.tuned[(0, 0)]
+    assert st.rast.opts.tile_size == tune["best"] and st.rast.lists == tune["lists"]
+    assert tune["best"] in (8, 16, 32) and len(tune["ms_fwd_bwd"]) == 12
+    assert np.isfinite(st.loss.cpu().numpy()).all() and float(st.loss.sum()) > 0
+
+
 def test_density_step_edge_cases():
     """No Gaussian selected (nothing split or cloned, eps empty) and every Gaussian pruned
     (an empty new set, no launch)."""
