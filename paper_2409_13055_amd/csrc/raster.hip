@@ -439,10 +439,12 @@ __device__ __forceinline__ int stage_batch(const SplatLoader (&ld)[RPL], const B
 // A pixel that has stopped gets row coordinate +inf: its q is then +inf or
 // NaN and fails the range test, so no separate flag is tested.
 // STATE: the pixel state (T_final, n_contrib) is written (not under the checkpoint flag).
-// (six wavefronts per SIMD: measured faster than five, despite a few bytes of spill outside the loop)
+// (six wavefronts per SIMD: measured faster than five, despite a few bytes of spill outside the loop;
+// at tile 32 with two records per lane the batch's LDS leaves room for four)
 // RPL: splat records each lane stages per LDS batch.  WIN: the bins are window lists.
 template <int TILE, bool STATE, int RPL, bool WIN>
-__global__ __launch_bounds__(FwdShape<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_render_fwd(
+__global__ __launch_bounds__(FwdShape<TILE>::THREADS)
+__attribute__((amdgpu_waves_per_eu(TILE == 32 && RPL == 2 ? 4 : 6))) void k_render_fwd(
     ViewTable vt, const float* __restrict__ rec, ListArgs la, RasterConsts rc, float* __restrict__ img,
     float* __restrict__ tfin, int32_t* __restrict__ ncon, const float* __restrict__ target,
     float* __restrict__ tile_loss) {
