@@ -144,43 +144,42 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_partials(uint64_t* __rest
 }
 
 // Block b copies segments [b kSortThreads, (b + 1) kSortThreads), whose
-// entries are the output positions [partial[b], partial[b] + total): thread t
-// takes positions t, t + kSortThreads, ... of that run, finding each one's
-// segment by a binary search over the block's exclusive count prefixes in LDS,
-// so consecutive lanes store to consecutive positions; kCopyBatch loads are in
-// flight before their stores.
+// entries are the output positions [partial[b], partial[b] + total): wavefront
+// w takes the block's segments [64 w, 64 w + 64), kCopyBatch at a time, one
+// lane per entry of a segment, so each segment is one contiguous load and one
+// contiguous store; the kCopyBatch segments' loads are in flight before any
+// of their stores.
 __global__ __launch_bounds__(kSortThreads) void k_compact_segments(const uint4* __restrict__ seg_ent,
                                                                    const uint32_t* __restrict__ seg_count,
                                                                    uint32_t n_seg,
                                                                    const uint64_t* __restrict__ partial,
                                                                    uint32_t* __restrict__ a_key,
                                                                    uint4* __restrict__ entc) {
-  static_assert(kSortThreads == 256, "the binary search covers 256 prefixes");
   __shared__ uint32_t s_w[kSortThreads / 64];
   __shared__ uint32_t s_loc[kSortThreads];
+  __shared__ uint32_t s_cnt[kSortThreads];
   const uint32_t sg0 = blockIdx.x * kSortThreads;
-  const uint32_t c = sg0 + threadIdx.x < n_seg ? seg_count[sg0 + threadIdx.x] : 0u;
+  const uint32_t c = sg0 + threadIdx.x < n_seg ? seg_count[sg0 + threadIdx.x] : 0u;  // 0 past the last segment
   uint32_t tot;
   s_loc[threadIdx.x] = block_exclusive_scan<uint32_t>(c, s_w, tot);  // at most 256 * 64
-  const uint32_t base = (uint32_t)partial[blockIdx.x];                 // < n_views * n < 2^32
+  s_cnt[threadIdx.x] = c;
+  const uint32_t base = (uint32_t)partial[blockIdx.x];  // < n_views * n < 2^32
   __syncthreads();
-  for (uint32_t i0 = threadIdx.x; i0 < tot; i0 += kSortThreads * kCopyBatch) {
+  const uint32_t lane = threadIdx.x & 63;
+  const int q_begin = (int)(threadIdx.x >> 6) * 64;
+  for (int q0 = q_begin; q0 < q_begin + 64; q0 += kCopyBatch) {
     Words4 e[kCopyBatch];
 #pragma unroll
     for (int k = 0; k < kCopyBatch; ++k) {
-      const uint32_t i = min(i0 + (uint32_t)k * kSortThreads, tot - 1);  // clamped: every load is in bounds
-      uint32_t q = 0;  // the last segment whose prefix is <= i: i lies inside it
-#pragma unroll
-      for (int b = 7; b >= 0; --b)
-        if (s_loc[q + (1u << b)] <= i) q += 1u << b;
-      const uint4 g = seg_ent[(size_t)(sg0 + q) * 64 + (i - s_loc[q])];
-      e[k] = Words4{g.x, g.y, g.z, g.w};
+      if (lane < s_cnt[q0 + k]) {
+        const uint4 g = seg_ent[(size_t)(sg0 + q0 + k) * 64 + lane];
+        e[k] = Words4{g.x, g.y, g.z, g.w};
+      }
     }
 #pragma unroll
     for (int k = 0; k < kCopyBatch; ++k) {
-      const uint32_t i = i0 + (uint32_t)k * kSortThreads;
-      if (i < tot) {
-        const uint32_t pos = base + i;
+      if (lane < s_cnt[q0 + k]) {
+        const uint32_t pos = base + s_loc[q0 + k] + lane;
         a_key[pos] = e[k].w;
         entc[pos] = make_uint4(e[k].x, e[k].y, e[k].z, e[k].w);
       }
